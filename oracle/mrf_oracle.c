@@ -1,0 +1,547 @@
+/*
+ * FP64 CPU oracle for ray-MRF loopy sum-product belief propagation
+ * (MRFMap, Shankar & Michael, arXiv 2006.03512).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU
+ * baseline leg of the benchmark load this file's library.  It shares no code,
+ * header, table or constant generator with the HIP library; it is written from
+ * the paper's equations in the paper's order, with plain sequential loops in
+ * double precision and OpenMP only across independent rays or voxels (every
+ * output has exactly one writer and every sum runs in fixed CSR order, so the
+ * result does not depend on the thread count).
+ *
+ * Pieces, each with the passage it follows:
+ *   or_trace_count / or_trace_emit  -- the ray of each depth pixel clipped to
+ *       the grid and truncated 3 sigma past the measurement (Sec. IV-B), walked
+ *       voxel by voxel with the 3D-DDA of Amanatides and Woo (Sec. IV-A).
+ *   or_incidence                    -- voxel -> ray incidence: the rays that
+ *       share a voxel (Sec. III-A, Fig. "graphical model"), a stable counting
+ *       sort of edges by voxel.
+ *   or_potentials                   -- log of the forward sensor model
+ *       nu(d_i) = N(Z; d_i, sigma(d_i)) (Eq. noise), sigma from a 64-bin
+ *       depth-indexed table.
+ *   or_infer                        -- flooding schedule of K sweeps; each
+ *       sweep sends variable->factor messages (Eq. node_to_factor, including
+ *       the prior factor, Eq. prior_potential) and then the ray-factor ->
+ *       variable messages of Eqs. pos and neg, in the log domain with the
+ *       division-free form of the second sum of Eq. neg (supplement, Sec. II-C,
+ *       the sum over j > i of the product over k < j, k != i).  Marginals are
+ *       the normalised product of all incoming factor messages (Sec. III-B).
+ *   or_backward                     -- reverse-mode derivative of the K
+ *       unrolled sweeps (not in the paper: a project extension), written from
+ *       the chain rule on the forward steps above.
+ *
+ * Messages to a binary variable are carried as log-odds
+ *   lambda = log mu(o=1) - log mu(o=0)      (voxel -> ray, per edge)
+ *   ell    = log mu(o=1) - log mu(o=0)      (ray -> voxel, per edge)
+ * which makes every incoming message normalised (supplement, Sec. II-A):
+ *   mu(o=1) = sigmoid(lambda), mu(o=0) = sigmoid(-lambda).
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* ------------------------------------------------------------------ */
+/* scalar helpers                                                      */
+/* ------------------------------------------------------------------ */
+
+/* log(exp(a) + exp(b)) with log(0 + 0) = -inf */
+static double or_lse(double a, double b)
+{
+    double hi = a > b ? a : b;
+    double lo = a > b ? b : a;
+    if (hi == -INFINITY) return -INFINITY;
+    return hi + log1p(exp(lo - hi));
+}
+
+/* log(1 + exp(x)) */
+static double or_softplus(double x)
+{
+    return (x > 0.0 ? x : 0.0) + log1p(exp(-fabs(x)));
+}
+
+/* ------------------------------------------------------------------ */
+/* rays and 3D-DDA                                                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t width, height;
+    double fx, fy, cx, cy;
+    int32_t nx, ny, nz;
+    double h;
+    double origin[3];
+    double z_min, z_max;
+    double trunc_nsigma, trunc_c0, trunc_c2, trunc_min;
+    double table_dmax;
+    int32_t min_ray_voxels;
+} or_cfg;
+
+typedef struct {
+    double c[3], w[3];
+    double Z, ts, te;
+} or_ray;
+
+/* The ray of pixel (u, v) of frame f: origin = camera centre, direction =
+ * R (x_n, y_n, 1) so the ray parameter is z-depth.  Returns 0 when the pixel
+ * carries no usable measurement or the ray misses the grid. */
+static int or_make_ray(const or_cfg* g, const float* depth, const double* T,
+                       int v, int u, or_ray* r)
+{
+    double Z = (double)depth[(int64_t)v * g->width + u];
+    if (!isfinite(Z) || Z < g->z_min || Z > g->z_max) return 0;
+    double xn = ((double)u - g->cx) / g->fx;
+    double yn = ((double)v - g->cy) / g->fy;
+    const int n[3] = {g->nx, g->ny, g->nz};
+    double ts = 0.0, texit = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        r->c[a] = T[4 * a + 3];
+        double wa = T[4 * a + 0] * xn;
+        wa = wa + T[4 * a + 1] * yn;
+        wa = wa + T[4 * a + 2];
+        r->w[a] = wa;
+        double lo = g->origin[a];
+        double hi = g->origin[a] + (double)n[a] * g->h;
+        if (wa != 0.0) {
+            double t0 = (lo - r->c[a]) / wa;
+            double t1 = (hi - r->c[a]) / wa;
+            double tmin = t0 < t1 ? t0 : t1;
+            double tmax = t0 < t1 ? t1 : t0;
+            if (tmin > ts) ts = tmin;
+            if (tmax < texit) texit = tmax;
+        } else if (r->c[a] < lo || r->c[a] >= hi) {
+            return 0;
+        }
+    }
+    /* the surface must lie inside the grid */
+    if (Z >= texit) return 0;
+    double sig = g->trunc_c2 * Z;
+    sig = sig * Z;
+    sig = g->trunc_c0 + sig;
+    if (sig < g->trunc_min) sig = g->trunc_min;
+    double te = Z + g->trunc_nsigma * sig;
+    if (te > texit) te = texit;
+    if (te <= ts) return 0;
+    r->Z = Z;
+    r->ts = ts;
+    r->te = te;
+    return 1;
+}
+
+static double or_face(const or_cfg* g, int a, int idx)
+{
+    return g->origin[a] + (double)idx * g->h;
+}
+
+typedef void (*or_emit_fn)(void* ud, int64_t k, int32_t id, double tin, double tout);
+
+/* Amanatides-Woo walk from t_s to t_e; calls emit for every voxel crossed
+ * with a chord of positive length.  Ties between axes step the lowest axis
+ * first.  Returns the number of voxels emitted. */
+static int64_t or_walk(const or_cfg* g, const or_ray* r, or_emit_fn emit, void* ud)
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    int idx[3];
+    double tmax[3];
+    for (int a = 0; a < 3; ++a) {
+        double p = r->c[a] + r->ts * r->w[a];
+        double q = floor((p - g->origin[a]) / g->h);
+        if (q < 0.0) q = 0.0;
+        if (q > (double)(n[a] - 1)) q = (double)(n[a] - 1);
+        idx[a] = (int)q;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (r->w[a] > 0.0)
+            tmax[a] = (or_face(g, a, idx[a] + 1) - r->c[a]) / r->w[a];
+        else if (r->w[a] < 0.0)
+            tmax[a] = (or_face(g, a, idx[a]) - r->c[a]) / r->w[a];
+        else
+            tmax[a] = INFINITY;
+    }
+    double tin = r->ts;
+    int64_t k = 0;
+    for (;;) {
+        int a = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
+        double tm = tmax[a];
+        double tout = tm < r->te ? tm : r->te;
+        if (tout > tin) {
+            int32_t id = idx[0] + g->nx * (idx[1] + g->ny * idx[2]);
+            if (emit) emit(ud, k, id, tin, tout);
+            ++k;
+        }
+        if (tm >= r->te) break;
+        if (tm > tin) tin = tm;
+        idx[a] += r->w[a] > 0.0 ? 1 : -1;
+        if (idx[a] < 0 || idx[a] >= n[a]) break;
+        if (r->w[a] > 0.0)
+            tmax[a] = (or_face(g, a, idx[a] + 1) - r->c[a]) / r->w[a];
+        else
+            tmax[a] = (or_face(g, a, idx[a]) - r->c[a]) / r->w[a];
+    }
+    return k;
+}
+
+/* Per-ray voxel counts for every pixel of every frame, in the order
+ * r = (f H + v) W + u.  Rays shorter than min_ray_voxels get 0. */
+void or_trace_count(const or_cfg* g, int32_t n_frames, const float* depth,
+                    const double* T_wc, int64_t* counts)
+{
+    const int64_t HW = (int64_t)g->width * g->height;
+    const int64_t R = HW * n_frames;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t f = r / HW, pix = r % HW;
+        int v = (int)(pix / g->width), u = (int)(pix % g->width);
+        or_ray ray;
+        int64_t m = 0;
+        if (or_make_ray(g, depth + f * HW, T_wc + 16 * f, v, u, &ray))
+            m = or_walk(g, &ray, NULL, NULL);
+        counts[r] = m >= g->min_ray_voxels ? m : 0;
+    }
+}
+
+typedef struct {
+    int32_t* col;
+    double *tin, *tout, *delta;
+    int32_t* bin;
+    int64_t base;
+    double Z, dbin;
+} or_emit_ud;
+
+static void or_emit(void* p, int64_t k, int32_t id, double tin, double tout)
+{
+    or_emit_ud* e = (or_emit_ud*)p;
+    int64_t at = e->base + k;
+    double d = (tin + tout) * 0.5;          /* depth of the voxel: chord midpoint */
+    double q = floor(d / e->dbin);
+    if (q < 0.0) q = 0.0;
+    if (q > 63.0) q = 63.0;
+    e->col[at] = id;
+    e->tin[at] = tin;
+    e->tout[at] = tout;
+    e->delta[at] = e->Z - d;
+    e->bin[at] = (int32_t)q;
+}
+
+/* Edges of every kept ray at row_ptr[r] .. row_ptr[r+1]: voxel id, chord
+ * entry/exit, measurement minus voxel depth, and sigma-table bin. */
+void or_trace_emit(const or_cfg* g, int32_t n_frames, const float* depth,
+                   const double* T_wc, const int64_t* row_ptr, int32_t* col,
+                   double* tin, double* tout, double* delta, int32_t* bin)
+{
+    const int64_t HW = (int64_t)g->width * g->height;
+    const int64_t R = HW * n_frames;
+    const double dbin = g->table_dmax / 64.0;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < R; ++r) {
+        if (row_ptr[r + 1] == row_ptr[r]) continue;
+        int64_t f = r / HW, pix = r % HW;
+        int v = (int)(pix / g->width), u = (int)(pix % g->width);
+        or_ray ray;
+        or_make_ray(g, depth + f * HW, T_wc + 16 * f, v, u, &ray);
+        or_emit_ud ud = {col, tin, tout, delta, bin, row_ptr[r], ray.Z, dbin};
+        or_walk(g, &ray, or_emit, &ud);
+    }
+}
+
+/* Stable counting sort of edges by voxel: vptr[V+1], vedge[E] with edge ids
+ * ascending inside every voxel. */
+void or_incidence(const int32_t* col, int64_t E, int64_t V, int64_t* vptr, int64_t* vedge)
+{
+    memset(vptr, 0, sizeof(int64_t) * (size_t)(V + 1));
+    for (int64_t e = 0; e < E; ++e) vptr[col[e] + 1] += 1;
+    for (int64_t v = 0; v < V; ++v) vptr[v + 1] += vptr[v];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(V > 0 ? V : 1));
+    memcpy(fill, vptr, sizeof(int64_t) * (size_t)V);
+    for (int64_t e = 0; e < E; ++e) vedge[fill[col[e]]++] = e;
+    free(fill);
+}
+
+/* g_e = log N(Z; d_e, sigma_b) = -(delta/sigma)^2/2 - log sigma - log(2 pi)/2 */
+void or_potentials(const double* delta, const int32_t* bin, int64_t E,
+                   const double* sigma, double* g)
+{
+    const double half_log_2pi = 0.5 * log(2.0 * M_PI);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < E; ++e) {
+        double s = sigma[bin[e]];
+        double x = delta[e] / s;
+        g[e] = -0.5 * x * x - log(s) - half_log_2pi;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* message passing                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Variable -> factor messages (Eq. node_to_factor): the voxel's prior factor
+ * times every other ray factor's message.  In log-odds: theta_v plus the sum
+ * of ell over the voxel's other edges, taken as (theta + sum before) + sum
+ * after, never as a difference. */
+static void or_voxel_phase(const int64_t* vptr, const int64_t* vedge, int64_t V,
+                           const double* base, const double* ell, double* lam)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t v = 0; v < V; ++v) {
+        int64_t s = vptr[v], e = vptr[v + 1];
+        double after = 0.0;
+        for (int64_t j = e - 1; j >= s; --j) {   /* suffix sums, parked in lam */
+            lam[vedge[j]] = after;
+            after += ell[vedge[j]];
+        }
+        double before = 0.0;
+        for (int64_t j = s; j < e; ++j) {
+            double b0 = base ? base[v] : 0.0;
+            lam[vedge[j]] = (b0 + before) + lam[vedge[j]];
+            before += ell[vedge[j]];
+        }
+    }
+}
+
+/* Ray-factor -> variable messages for one ray (Eqs. pos and neg).
+ *
+ * With a_k = mu(o_k=0), b_k = mu(o_k=1), nu_k = exp(g_k) and 1-based i:
+ *   m1_i = sum_{j<i} b_j nu_j prod_{k<j} a_k  +  nu_i prod_{k<i} a_k
+ *   m0_i = sum_{j<i} b_j nu_j prod_{k<j} a_k  +  sum_{j>i} b_j nu_j prod_{k<j,k!=i} a_k
+ * In logs, with P_i = sum_{k<i} log a_k (visibility up to voxel i):
+ *   first term   F_i = LSE_{j<i} (log b_j + g_j + P_j)       (Eq. depth_message summed)
+ *   second sum   P_i + T_i with T_i = log sum_{j>i} b_j nu_j prod_{i<k<j} a_k,
+ *                T_i = LSE(log b_{i+1} + g_{i+1}, log a_{i+1} + T_{i+1}), T_N = -inf
+ *   ell_i = LSE(F_i, g_i + P_i) - LSE(F_i, P_i + T_i).
+ * Scratch arrays hold n doubles each. */
+static void or_ray_messages(int64_t n, const double* lam, const double* g, double* ell,
+                            double* la, double* lb, double* P, double* F, double* T)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        la[i] = -or_softplus(lam[i]);    /* log mu(o=0) = log sigmoid(-lambda) */
+        lb[i] = -or_softplus(-lam[i]);   /* log mu(o=1) = log sigmoid(lambda)  */
+    }
+    double acc = 0.0, f = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        P[i] = acc;
+        F[i] = f;
+        f = or_lse(f, lb[i] + g[i] + P[i]);
+        acc += la[i];
+    }
+    T[n - 1] = -INFINITY;
+    for (int64_t i = n - 2; i >= 0; --i)
+        T[i] = or_lse(lb[i + 1] + g[i + 1], la[i + 1] + T[i + 1]);
+    for (int64_t i = 0; i < n; ++i) {
+        double m1 = or_lse(F[i], g[i] + P[i]);
+        double m0 = or_lse(F[i], P[i] + T[i]);
+        ell[i] = m1 - m0;
+    }
+}
+
+static int64_t or_max_len(const int64_t* row_ptr, int64_t R)
+{
+    int64_t m = 1;
+    for (int64_t r = 0; r < R; ++r)
+        if (row_ptr[r + 1] - row_ptr[r] > m) m = row_ptr[r + 1] - row_ptr[r];
+    return m;
+}
+
+static void or_ray_phase(const int64_t* row_ptr, int64_t R, const double* lam,
+                         const double* g, double* ell)
+{
+    int64_t mx = or_max_len(row_ptr, R);
+#pragma omp parallel
+    {
+        double* scratch = (double*)malloc(sizeof(double) * 5 * (size_t)mx);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < R; ++r) {
+            int64_t s = row_ptr[r], n = row_ptr[r + 1] - s;
+            if (n == 0) continue;
+            or_ray_messages(n, lam + s, g + s, ell + s, scratch, scratch + mx,
+                            scratch + 2 * mx, scratch + 3 * mx, scratch + 4 * mx);
+        }
+        free(scratch);
+    }
+}
+
+/* Belief of every voxel: L_v = theta_v + sum of all incoming ray messages. */
+static void or_beliefs(const int64_t* vptr, const int64_t* vedge, int64_t V,
+                       const double* theta, const double* ell, double* L)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t v = 0; v < V; ++v) {
+        double s = theta[v];
+        for (int64_t j = vptr[v]; j < vptr[v + 1]; ++j) s += ell[vedge[j]];
+        L[v] = s;
+    }
+}
+
+/* K sweeps of the flooding schedule starting from uniform ray messages
+ * (ell = 0).  lam_hist (K*E, optional) keeps lambda of every sweep for the
+ * reverse pass; ell_out (E) and lam_out (E) hold the last sweep's messages;
+ * L (V) the marginal log-odds. */
+void or_infer(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
+              int64_t V, int64_t E, const double* theta, const double* g, int32_t K,
+              double* lam_hist, double* lam_out, double* ell_out, double* L)
+{
+    double* ell = ell_out;
+    memset(ell, 0, sizeof(double) * (size_t)E);
+    for (int32_t k = 0; k < K; ++k) {
+        or_voxel_phase(vptr, vedge, V, theta, ell, lam_out);
+        if (lam_hist) memcpy(lam_hist + (int64_t)k * E, lam_out, sizeof(double) * (size_t)E);
+        or_ray_phase(row_ptr, R, lam_out, g, ell);
+    }
+    or_beliefs(vptr, vedge, V, theta, ell, L);
+}
+
+/* ------------------------------------------------------------------ */
+/* reverse mode (project extension)                                    */
+/* ------------------------------------------------------------------ */
+
+/* Adjoint of or_ray_messages for one ray: given d loss / d ell_i, returns
+ * d loss / d lambda_i and adds d loss / d g_i into gbar.  Follows the forward
+ * recurrences backwards:
+ *   ell_i = M1_i - M0_i, M1_i = LSE(F_i, A_i), M0_i = LSE(F_i, B_i),
+ *   A_i = g_i + P_i, B_i = P_i + T_i,
+ *   F_{i+1} = LSE(F_i, W_i), W_i = log b_i + g_i + P_i,
+ *   T_i = LSE(c_{i+1}, log a_{i+1} + T_{i+1}), c_j = log b_j + g_j,
+ *   P_{i+1} = P_i + log a_i,
+ *   d log a / d lambda = -b,  d log b / d lambda = a. */
+static void or_ray_adjoint(int64_t n, const double* lam, const double* g, const double* ellbar,
+                           double* lambar, double* gbar, double* w)
+{
+    double *la = w, *lb = w + n, *P = w + 2 * n, *F = w + 3 * n, *T = w + 4 * n;
+    double *M1 = w + 5 * n, *M0 = w + 6 * n, *Pb = w + 7 * n, *lab = w + 8 * n, *lbb = w + 9 * n;
+    double *Fb = w + 10 * n, *Tb = w + 11 * n;
+    for (int64_t i = 0; i < n; ++i) {
+        la[i] = -or_softplus(lam[i]);
+        lb[i] = -or_softplus(-lam[i]);
+    }
+    double acc = 0.0, f = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        P[i] = acc;
+        F[i] = f;
+        f = or_lse(f, lb[i] + g[i] + P[i]);
+        acc += la[i];
+    }
+    T[n - 1] = -INFINITY;
+    for (int64_t i = n - 2; i >= 0; --i)
+        T[i] = or_lse(lb[i + 1] + g[i + 1], la[i + 1] + T[i + 1]);
+    for (int64_t i = 0; i < n; ++i) {
+        M1[i] = or_lse(F[i], g[i] + P[i]);
+        M0[i] = or_lse(F[i], P[i] + T[i]);
+        Pb[i] = lab[i] = lbb[i] = 0.0;
+    }
+    /* direct partials of ell_i */
+    for (int64_t i = 0; i < n; ++i) {
+        double eb = ellbar[i];
+        Fb[i] = eb * (exp(F[i] - M1[i]) - exp(F[i] - M0[i]));
+        double Ab = eb * exp(g[i] + P[i] - M1[i]);
+        double Bb = -eb * exp(P[i] + T[i] - M0[i]);
+        gbar[i] += Ab;
+        Pb[i] += Ab + Bb;
+        Tb[i] = Bb;
+    }
+    /* T runs right-to-left, so its adjoint runs left-to-right */
+    for (int64_t i = 0; i + 1 < n; ++i) {
+        double cj = lb[i + 1] + g[i + 1];
+        double wc = exp(cj - T[i]);
+        double wt = exp(la[i + 1] + T[i + 1] - T[i]);
+        lbb[i + 1] += Tb[i] * wc;
+        gbar[i + 1] += Tb[i] * wc;
+        lab[i + 1] += Tb[i] * wt;
+        Tb[i + 1] += Tb[i] * wt;
+    }
+    /* F runs left-to-right, so its adjoint runs right-to-left */
+    for (int64_t i = n - 1; i >= 1; --i) {
+        /* F_i = LSE(F_{i-1}, W_{i-1}) */
+        double Wm = lb[i - 1] + g[i - 1] + P[i - 1];
+        double wf = exp(F[i - 1] - F[i]);
+        double ww = exp(Wm - F[i]);
+        Fb[i - 1] += Fb[i] * wf;
+        lbb[i - 1] += Fb[i] * ww;
+        gbar[i - 1] += Fb[i] * ww;
+        Pb[i - 1] += Fb[i] * ww;
+    }
+    /* P_i = sum_{k<i} log a_k */
+    double suf = 0.0;
+    for (int64_t k = n - 1; k >= 0; --k) {
+        lab[k] += suf;
+        suf += Pb[k];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double a = exp(la[i]), b = exp(lb[i]);
+        lambar[i] = -b * lab[i] + a * lbb[i];
+    }
+}
+
+/* Reverse pass over K sweeps.  Inputs: the forward's lambda of every sweep
+ * (lam_hist, K*E), g (E), and Lbar = d loss / d L (V).  Outputs:
+ * d loss / d theta (V), d loss / d g accumulated over sweeps (gbar, E), and
+ * d loss / d sigma_b (64) through g_e = log N(Z; d_e, sigma_b):
+ *   d g / d sigma = delta^2 / sigma^3 - 1 / sigma. */
+void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
+                 int64_t V, int64_t E, const double* g, int32_t K, const double* lam_hist,
+                 const double* Lbar, const double* delta, const int32_t* bin,
+                 const double* sigma, double* theta_bar, double* gbar, double* sigma_bar)
+{
+    double* ellbar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    double* lambar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    memset(gbar, 0, sizeof(double) * (size_t)E);
+    for (int64_t v = 0; v < V; ++v) {
+        theta_bar[v] = Lbar[v];
+        for (int64_t j = vptr[v]; j < vptr[v + 1]; ++j) ellbar[vedge[j]] = Lbar[v];
+    }
+    int64_t mx = or_max_len(row_ptr, R);
+    for (int32_t k = K - 1; k >= 0; --k) {
+        const double* lam = lam_hist + (int64_t)k * E;
+#pragma omp parallel
+        {
+            double* w = (double*)malloc(sizeof(double) * 12 * (size_t)mx);
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t r = 0; r < R; ++r) {
+                int64_t s = row_ptr[r], n = row_ptr[r + 1] - s;
+                if (n == 0) continue;
+                or_ray_adjoint(n, lam + s, g + s, ellbar + s, lambar + s, gbar + s, w);
+            }
+            free(w);
+        }
+        /* lambda_e = theta_v + sum_{e' in v, e' != e} ell_e' */
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t v = 0; v < V; ++v) {
+            double tot = 0.0;
+            for (int64_t j = vptr[v]; j < vptr[v + 1]; ++j) tot += lambar[vedge[j]];
+            theta_bar[v] += tot;
+        }
+        if (k > 0) or_voxel_phase(vptr, vedge, V, NULL, lambar, ellbar);
+    }
+    for (int b = 0; b < 64; ++b) sigma_bar[b] = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        double s = sigma[bin[e]];
+        sigma_bar[bin[e]] += gbar[e] * (delta[e] * delta[e] / (s * s * s) - 1.0 / s);
+    }
+    free(ellbar);
+    free(lambar);
+}
+
+/* ------------------------------------------------------------------ */
+/* small exports for tests                                             */
+/* ------------------------------------------------------------------ */
+
+/* Messages of a single ray factor, exposed for the brute-force checks. */
+void or_single_ray(int64_t n, const double* lam, const double* g, double* ell)
+{
+    double* s = (double*)malloc(sizeof(double) * 5 * (size_t)n);
+    or_ray_messages(n, lam, g, ell, s, s + n, s + 2 * n, s + 3 * n, s + 4 * n);
+    free(s);
+}
+
+void or_single_ray_adjoint(int64_t n, const double* lam, const double* g, const double* ellbar,
+                           double* lambar, double* gbar)
+{
+    double* w = (double*)malloc(sizeof(double) * 12 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) gbar[i] = 0.0;
+    or_ray_adjoint(n, lam, g, ellbar, lambar, gbar, w);
+    free(w);
+}
+
+int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n) { omp_set_num_threads(n); }
