@@ -1,0 +1,177 @@
+/*
+ * mrf.h -- C ABI of the MI355X ray-MRF belief-propagation library (libmrf.so).
+ *
+ * The library infers per-voxel occupancy marginals from depth images with the
+ * ray Markov random field of MRFMap (Shankar & Michael, arXiv 2006.03512):
+ * binary occupancy o_v per voxel with a Bernoulli prior factor
+ * (Sec. III-A, Eq. prior_potential), one ray depth potential per depth pixel
+ * that rewards the first occupied voxel along the ray with the forward sensor
+ * model nu(d) = N(Z; d, sigma(d)) (Eqs. depth_potential, noise), and loopy
+ * sum-product belief propagation (Sec. III-B) with the linear-time ray
+ * messages of Eqs. pos and neg.  A reverse pass (not in the paper) gives the
+ * gradient of any loss of the marginal log-odds with respect to the per-voxel
+ * prior log-odds and the 64-bin sigma table.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns MRF_OK (0) or a negative MRF_E* code; no C++ exception
+ *   crosses this boundary.  mrf_strerror() names a code; mrf_last_error()
+ *   gives the message of the last failure on the calling thread.
+ * - All array arguments are DEVICE pointers (hipMalloc'ed or torch CUDA
+ *   tensors on the current device) unless stated otherwise.  The caller owns
+ *   them and keeps them valid until the call's work on `stream` completes.
+ *   The context owns everything it allocates; mrf_destroy frees it.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Calls enqueue work asynchronously on it; the only host synchronisation is
+ *   inside mrf_build (it reads the edge count back to size its buffers).
+ * - A context is not thread-safe: use one context per host thread.
+ * - Ray r of scene s is global ray ray_base(s) + (f H + v) W + u (frame f,
+ *   pixel row v, column u).  Voxel (i, j, k) of scene s is global voxel
+ *   voxel_base(s) + i + nx (j + ny k).  Scenes are concatenated in call order.
+ * - Edge = one (ray, voxel) incidence, numbered by ray then by distance along
+ *   the ray (the order the 3D-DDA visits voxels).
+ */
+#ifndef MRF_H
+#define MRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MRF_OK = 0,
+    MRF_EINVAL = -1,   /* bad argument: null pointer, bad shape or parameter */
+    MRF_ENOMEM = -2,   /* device allocation failed */
+    MRF_EHIP = -3,     /* a HIP runtime call failed */
+    MRF_ESTATE = -4,   /* call out of order (e.g. backward without checkpoints) */
+    MRF_ERANGE = -5    /* a size exceeds an index type (E >= 2^32, ray > 2048 voxels) */
+};
+
+typedef struct mrf_ctx mrf_ctx;
+
+/* Pinhole camera: pixel (u, v) looks along R ((u - cx)/fx, (v - cy)/fy, 1),
+ * so the ray parameter is z-depth (Sec. III: one distance per ray). */
+typedef struct {
+    int32_t width, height;
+    double fx, fy, cx, cy;
+} mrf_intrinsics;
+
+/* Dense voxel grid: voxel (i, j, k) covers [o + i h, o + (i+1) h) x ... */
+typedef struct {
+    int32_t nx, ny, nz, reserved;
+    double voxel;
+    double origin[3];
+} mrf_grid;
+
+/* One scene: n_frames depth images of one camera model into one grid. */
+typedef struct {
+    int32_t n_frames, reserved;
+    const float* depth;     /* device, n_frames*H*W z-depth [m]; 0 or NaN = no return */
+    const double* T_wc;     /* device, n_frames*16 row-major camera->world (OpenCV axes) */
+    mrf_intrinsics K;
+    mrf_grid grid;
+} mrf_scene;
+
+/* Graph construction parameters (Sec. IV-B: rays stop 3 sigma past the
+ * measured depth).  A pixel is used iff z_min <= Z <= z_max and Z lies inside
+ * the grid; its ray is walked from the grid entry to
+ * min(Z + trunc_nsigma * sigma_tr(Z), grid exit) with
+ * sigma_tr(Z) = max(trunc_c0 + trunc_c2 Z^2, trunc_min), frozen at build so
+ * the incidence never depends on learnable parameters.  Rays that cross fewer
+ * than min_ray_voxels voxels (>= 2, since a one-voxel ray factor forces its
+ * voxel occupied with infinite log-odds) are dropped.  The sigma table has 64
+ * bins of width table_dmax/64 indexed by the voxel's depth. */
+typedef struct {
+    double z_min, z_max;
+    double trunc_nsigma, trunc_c0, trunc_c2, trunc_min;
+    double table_dmax;
+    int32_t min_ray_voxels;
+    int32_t keep_chords;    /* nonzero: keep f64 chord entry/exit per edge for export */
+} mrf_build_params;
+
+typedef struct {
+    int64_t n_scenes, n_rays, n_edges, n_voxels;
+    int64_t n_kept_rays, n_touched_voxels, max_ray_len, max_voxel_degree;
+    int64_t ray_len_hist[16];       /* rays with length in [2^i, 2^(i+1)) */
+    int64_t voxel_degree_hist[24];  /* touched voxels with degree in [2^i, 2^(i+1)) */
+    double fwd_bytes_per_sweep;     /* algorithmic HBM bytes of one forward sweep */
+    int32_t sweeps_done, have_checkpoints;
+} mrf_stats_t;
+
+/* Create an empty context on the current HIP device.  *out receives it. */
+int mrf_create(mrf_ctx** out);
+
+/* Build (or rebuild, reusing buffers when they are large enough) the ray MRF
+ * of n_scenes scenes: 3D-DDA traversal of every kept ray (Amanatides-Woo, the
+ * traversal named in Sec. IV-A), ray->voxel CSR in edge order, voxel->ray CSR
+ * by a stable device radix sort (edges ascending inside a voxel), per-edge
+ * voxel depth (chord midpoint) and sigma-table bin.  Depth and pose arrays
+ * must stay valid until the call returns.  Errors: MRF_EINVAL (bad shapes,
+ * min_ray_voxels < 2, more than 65535 frames), MRF_ERANGE (total edges >= 2^32
+ * or a ray longer than 2048 voxels), MRF_ENOMEM, MRF_EHIP. */
+int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
+              const mrf_build_params* params, void* stream);
+
+/* Run `sweeps` flooding sweeps of loopy sum-product BP (Sec. III-B/C, IV-A)
+ * from uniform ray messages.  One sweep sends every voxel->ray message
+ * (Eq. node_to_factor: the prior times every other ray's message) and then
+ * every ray->voxel message (Eqs. pos and neg, computed in the log domain
+ * with prefix products of mu(o=0) and the division-free suffix form of
+ * Eq. neg).  prior_logit: V floats, log(gamma_v / (1 - gamma_v)) per voxel
+ * (copied).  sigma_table: 64 floats > 0, the learnt depth-indexed Gaussian
+ * sigma of Eq. noise (copied).  keep_checkpoints != 0 stores every sweep's
+ * ray messages (sweeps * E floats) for mrf_backward.  Errors: MRF_ESTATE
+ * before mrf_build, MRF_EINVAL for sweeps < 1, MRF_ENOMEM. */
+int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
+              int32_t sweeps, int32_t keep_checkpoints, void* stream);
+
+/* Marginals of the last mrf_infer (Sec. III-B: normalised product of all
+ * factor messages into the voxel): logit_v = theta_v + sum of ray messages,
+ * p_v = sigmoid(logit_v).  Either output may be NULL.  V floats each.
+ * Errors: MRF_ESTATE before mrf_infer. */
+int mrf_marginals(mrf_ctx* ctx, float* p, float* logit, void* stream);
+
+/* Reverse pass through the K sweeps of the last mrf_infer (which must have
+ * kept checkpoints).  dloss_dlogit: V floats, the gradient with respect to
+ * the marginal log-odds (for BCE with logits: (p - y) / V).  Outputs
+ * dprior_logit (V floats) and dsigma_table (64 floats); either may be NULL.
+ * Deterministic: no floating-point atomics.  Errors: MRF_ESTATE. */
+int mrf_backward(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
+                 float* dsigma_table, void* stream);
+
+/* Sizes and histograms of the built graph (host struct). */
+int mrf_stats(const mrf_ctx* ctx, mrf_stats_t* out);
+
+/* Copy the incidence out in canonical edge order (for parity checks):
+ * row_ptr (R+1 int64), col (E int32 voxel ids), t_in / t_out (E f64 chord
+ * entry/exit z-depths; only if built with keep_chords, else must be NULL),
+ * vptr (V+1 int64), vedge (E uint32 edge ids).  Any pointer may be NULL. */
+int mrf_export_incidence(const mrf_ctx* ctx, int64_t* row_ptr, int32_t* col,
+                         double* t_in, double* t_out, int64_t* vptr, uint32_t* vedge,
+                         void* stream);
+
+/* Copy per-edge data out in canonical edge order: delta = Z - d (f32),
+ * bin (u8), g = log nu (f32), lam = last voxel->ray log-odds, ell = last
+ * ray->voxel log-odds (f32).  Any pointer may be NULL. */
+int mrf_export_edges(const mrf_ctx* ctx, float* delta, uint8_t* bin, float* g,
+                     float* lam, float* ell, void* stream);
+
+/* Execution schedule of the sweeps:
+ *   MRF_SCHED_PLAIN  one kernel launch per phase per ray class, per frame
+ *                    for the ray phase, fixed segments, no graph;
+ *   MRF_SCHED_GRAPH  all sweeps captured once into a hipGraph and replayed
+ *                    (default), with tuned launch shapes. */
+enum { MRF_SCHED_PLAIN = 0, MRF_SCHED_GRAPH = 1 };
+int mrf_set_schedule(mrf_ctx* ctx, int32_t schedule);
+
+void mrf_destroy(mrf_ctx* ctx);
+const char* mrf_strerror(int code);
+const char* mrf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRF_H */

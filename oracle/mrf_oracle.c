@@ -103,6 +103,7 @@ static int or_make_ray(const or_cfg* g, const float* depth, const double* T,
         wa = wa + T[4 * a + 1] * yn;
         wa = wa + T[4 * a + 2];
         r->w[a] = wa;
+        if (!isfinite(wa) || !isfinite(r->c[a])) return 0;   /* unusable pose */
         double lo = g->origin[a];
         double hi = g->origin[a] + (double)n[a] * g->h;
         if (wa != 0.0) {

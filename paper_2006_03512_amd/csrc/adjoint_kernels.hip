@@ -1,0 +1,307 @@
+// Reverse-mode derivative of the unrolled sweeps on gfx950 (a project
+// extension; the paper's BP has no gradients).
+//
+// Ray adjoint: for one ray, given d/d ell_i, the chain rule through
+//   ell_i = M1_i - M0_i, M1_i = LSE(S_i, A_i), M0_i = LSE(S_i, B_i),
+//   A_i = g_i + P_i, B_i = P_i + Q_i, S_{i+1} = LSE(S_i, W_i),
+//   W_i = log mu_i(1) + g_i + P_i, Q_{i-1} = LSE(c_i, log mu_i(0) + Q_i),
+//   c_i = log mu_i(1) + g_i, P_{i+1} = P_i + log mu_i(0)
+// gives two linear recurrences with weights in [0, 1] (softmax weights of
+// the LSEs), run as affine group scans:
+//   Tb_i = Bbar_i + rho_{i-1} Tb_{i-1}      forward,  rho_{i-1} = exp(log mu_i(0) + Q_i - Q_{i-1})
+//   Fb_i = Sbar_i + r_i Fb_{i+1}            backward, r_i = exp(S_i - S_{i+1})
+// and a suffix sum for the prefix sums P.  d log mu(0)/d lam = -mu(1),
+// d log mu(1)/d lam = mu(0).
+//
+// Sigma-table gradient: d g_e / d sigma_b = delta_e^2 / sigma_b^3 - 1 / sigma_b,
+// reduced per bin deterministically: fixed-order double sums over runs of
+// equal bins inside 64-edge chunks, then 128-bit fixed-point integer
+// accumulation (order-independent, hence bit-reproducible).
+#include <hip/hip_runtime.h>
+
+#include "dev_common.hpp"
+#include "mrf_internal.hpp"
+
+namespace mrf {
+
+static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <int G, int IPL>
+__global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ rays, int64_t n,
+                                                 const int64_t* __restrict__ row_ptr, const float* __restrict__ lam,
+                                                 const float* __restrict__ g, const float* __restrict__ ellbar,
+                                                 float* __restrict__ lambar, float* __restrict__ gsum, int first)
+{
+    const int64_t gid = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
+    if (gid >= n) return;
+    const int l = glane<G>();
+    const uint32_t r = rays[gid];
+    const int64_t s = row_ptr[r];
+    const int m = (int)(row_ptr[r + 1] - s);
+
+    float al[IPL], be[IPL], gg[IPL], eb[IPL], P[IPL], S[IPL], Q[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = k * G + l;
+        if (i < m) {
+            const float x = lam[s + i];
+            const float sp = softplus(x);
+            al[k] = -sp;
+            be[k] = x - sp;
+            gg[k] = g[s + i];
+            eb[k] = ellbar[s + i];
+        } else {
+            al[k] = 0.0f;
+            be[k] = MRF_NINF;
+            gg[k] = 0.0f;
+            eb[k] = 0.0f;
+        }
+    }
+    // ---- forward recomputation (same scans as the ray phase)
+    float cp = 0.0f;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const float incl = gscan_add<G>(al[k]) + cp;
+        const float up = gshfl_up<G>(incl, 1);
+        P[k] = l == 0 ? cp : up;
+        cp = gbcast<G>(incl, G - 1);
+    }
+    float cs = MRF_NINF;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const float incl = lse(cs, gscan_lse<G>(be[k] + gg[k] + P[k]));
+        const float up = gshfl_up<G>(incl, 1);
+        S[k] = l == 0 ? cs : up;
+        cs = gbcast<G>(incl, G - 1);
+    }
+    LMap cq{0.0f, MRF_NINF};
+#pragma unroll
+    for (int k = IPL - 1; k >= 0; --k) {
+        LMap mp{al[k], be[k] + gg[k]};
+        LMap incl = lmap_compose(grscan_lmap<G>(mp), cq);
+        const float dn = gshfl_down<G>(incl.c, 1);
+        Q[k] = l == G - 1 ? cq.c : dn;
+        cq.a = gbcast<G>(incl.a, 0);
+        cq.c = gbcast<G>(incl.c, 0);
+    }
+    // ---- direct partials of ell_i = M1_i - M0_i
+    float Fb[IPL], Bb[IPL], gb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const float A = gg[k] + P[k];
+        const float B = P[k] + Q[k];
+        const float m1 = lse(S[k], A);
+        const float m0 = lse(S[k], B);
+        const bool ok = (k * G + l) < m;
+        const float e = ok ? eb[k] : 0.0f;
+        // exp(-inf - finite) = 0 covers S_0 = -inf and Q_{N-1} = -inf
+        Fb[k] = ok ? e * (__expf(S[k] - m1) - __expf(S[k] - m0)) : 0.0f;
+        const float Ab = ok ? e * __expf(A - m1) : 0.0f;
+        Bb[k] = ok ? -e * __expf(B - m0) : 0.0f;
+        gb[k] = Ab;
+        Pb[k] = Ab + Bb[k];
+        lab[k] = 0.0f;
+        lbb[k] = 0.0f;
+    }
+    // ---- Q adjoint: forward affine scan Tb_i = Bb_i + rho_{i-1} Tb_{i-1}
+    {
+        AMap carry{1.0f, 0.0f};
+        float qcarry = MRF_NINF;   // Q of the previous chunk's last element
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            const int i = k * G + l;
+            const float qup = gshfl_up<G>(Q[k], 1);
+            const float qprev = l == 0 ? qcarry : qup;   // Q_{i-1}
+            float rho = 0.0f, kap = 0.0f;
+            if (i >= 1 && i < m) {
+                rho = __expf(al[k] + Q[k] - qprev);
+                kap = __expf(be[k] + gg[k] - qprev);
+            }
+            AMap mp{rho, Bb[k]};
+            AMap incl = amap_then(carry, gscan_amap<G>(mp));
+            const float up = gshfl_up<G>(incl.b, 1);
+            const float tprev = l == 0 ? carry.b : up;   // Tb_{i-1}
+            if (i >= 1 && i < m) {
+                const float tk = tprev * kap;
+                lbb[k] += tk;
+                gb[k] += tk;
+                lab[k] += tprev * rho;
+            }
+            carry.m = gbcast<G>(incl.m, G - 1);
+            carry.b = gbcast<G>(incl.b, G - 1);
+            qcarry = gbcast<G>(Q[k], G - 1);
+        }
+    }
+    // ---- S adjoint: backward affine scan Fb_i = Sbar_i + r_i Fb_{i+1}
+    {
+        AMap carry{1.0f, 0.0f};
+        float scarry = MRF_NINF;   // S of the next chunk's first element
+#pragma unroll
+        for (int k = IPL - 1; k >= 0; --k) {
+            const int i = k * G + l;
+            const float sdn = gshfl_down<G>(S[k], 1);
+            const float snext = l == G - 1 ? scarry : sdn;   // S_{i+1}
+            float rr = 0.0f, ww = 0.0f;
+            if (i + 1 < m) {
+                rr = __expf(S[k] - snext);
+                ww = __expf(be[k] + gg[k] + P[k] - snext);
+            }
+            AMap mp{rr, Fb[k]};
+            AMap incl = amap_then(carry, grscan_amap<G>(mp));
+            const float dn = gshfl_down<G>(incl.b, 1);
+            const float fnext = l == G - 1 ? carry.b : dn;   // Fb_{i+1}
+            if (i + 1 < m) {
+                const float wb = fnext * ww;
+                lbb[k] += wb;
+                gb[k] += wb;
+                Pb[k] += wb;
+            }
+            carry.m = gbcast<G>(incl.m, 0);
+            carry.b = gbcast<G>(incl.b, 0);
+            scarry = gbcast<G>(S[k], 0);
+        }
+    }
+    // ---- P adjoint: d/d log mu_k(0) += sum_{i>k} Pbar_i, then d/d lambda
+    {
+        float sc = 0.0f;
+#pragma unroll
+        for (int k = IPL - 1; k >= 0; --k) {
+            const float incl = grscan_add<G>(Pb[k]) + sc;
+            const float dn = gshfl_down<G>(incl, 1);
+            const float suf = l == G - 1 ? sc : dn;
+            sc = gbcast<G>(incl, 0);
+            const int i = k * G + l;
+            if (i < m) {
+                const float lb = lab[k] + suf;
+                const float a = __expf(al[k]), b = __expf(be[k]);
+                lambar[s + i] = -b * lb + a * lbb[k];
+                gsum[s + i] = first ? gb[k] : gsum[s + i] + gb[k];
+            }
+        }
+    }
+}
+
+template <int G, int IPL>
+static void launch_adj_class(const mrf_ctx* c, int k, const float* lam, const float* ellbar, float* lambar,
+                             float* gsum, int first, hipStream_t s)
+{
+    const int64_t n = c->ray_cnt[k];
+    if (n <= 0) return;
+    hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
+                       (const uint32_t*)c->b_ray_list[k].p, n, (const int64_t*)c->b_rowptr.p, lam,
+                       (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+}
+
+hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
+                              bool first, hipStream_t s)
+{
+    launch_adj_class<16, 1>(c, 0, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 1>(c, 1, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 4>(c, 2, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 16>(c, 3, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 32>(c, 4, lam, ellbar, lambar, gsum, first, s);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ sigma table
+
+constexpr int SG_BLOCKS = 1024;
+
+__device__ __forceinline__ void fx_add(unsigned long long* lo, long long* hi, double v)
+{
+    // v as a signed 128-bit fixed-point number with 64 fractional bits
+    const double fl = floor(v);
+    const double fr = v - fl;                                   // [0, 1), exact
+    const unsigned long long l = (unsigned long long)(fr * 18446744073709551616.0);
+    const long long h = (long long)fl;
+    const unsigned long long old = atomicAdd(lo, l);
+    const long long carry = (old + l < old) ? 1 : 0;
+    atomicAdd((unsigned long long*)hi, (unsigned long long)(h + carry));
+}
+
+__global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gsum, const float* __restrict__ delta,
+                                                    const uint8_t* __restrict__ bin, int64_t E,
+                                                    const float* __restrict__ sigma, unsigned long long* __restrict__ glo,
+                                                    long long* __restrict__ ghi)
+{
+    __shared__ unsigned long long slo[kBins];
+    __shared__ long long shi[kBins];
+    __shared__ double inv[kBins], inv3[kBins];
+    if (threadIdx.x < kBins) {
+        slo[threadIdx.x] = 0;
+        shi[threadIdx.x] = 0;
+        const double sg = (double)sigma[threadIdx.x];
+        inv[threadIdx.x] = 1.0 / sg;
+        inv3[threadIdx.x] = 1.0 / (sg * sg * sg);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t nchunks = (E + 63) / 64;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (int64_t ch = wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+        const int64_t e = ch * 64 + lane;
+        const bool valid = e < E;
+        const int b = valid ? (int)bin[e] : -1;
+        double x = 0.0;
+        if (valid) {
+            const double d = (double)delta[e];
+            x = (double)gsum[e] * (d * d * inv3[b] - inv[b]);
+        }
+        // segmented inclusive sum over runs of equal bins (fixed tree order)
+        const int bup = __shfl_up(b, 1, 64);
+        int f = (lane == 0 || bup != b) ? 1 : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double y = __shfl_up(x, d, 64);
+            const int gflag = __shfl_up(f, d, 64);
+            if (lane >= d) {
+                if (!f) x = y + x;
+                f |= gflag;
+            }
+        }
+        const int bdn = __shfl_down(b, 1, 64);
+        const bool tail = valid && (lane == 63 || bdn != b || e + 1 >= E);
+        if (tail) fx_add(&slo[b], &shi[b], x);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins) {
+        const unsigned long long l = slo[threadIdx.x];
+        const long long h = shi[threadIdx.x];
+        const unsigned long long old = atomicAdd(&glo[threadIdx.x], l);
+        const long long carry = (old + l < old) ? 1 : 0;
+        atomicAdd((unsigned long long*)&ghi[threadIdx.x], (unsigned long long)(h + carry));
+    }
+}
+
+__global__ void sigma_zero_k(unsigned long long* glo, long long* ghi)
+{
+    if (threadIdx.x < kBins) {
+        glo[threadIdx.x] = 0;
+        ghi[threadIdx.x] = 0;
+    }
+}
+
+__global__ void sigma_final_k(const unsigned long long* glo, const long long* ghi, float* out)
+{
+    if (threadIdx.x < kBins)
+        out[threadIdx.x] = (float)((double)ghi[threadIdx.x] + (double)glo[threadIdx.x] * 5.421010862427522e-20);
+}
+
+hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s)
+{
+    unsigned long long* glo = (unsigned long long*)c->b_sigpart.p;
+    long long* ghi = (long long*)(glo + kBins);
+    hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(64), 0, s, glo, ghi);
+    if (c->E > 0) {
+        int64_t blocks = (c->E + 255) / 256;
+        if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
+        hipLaunchKernelGGL(sigma_grad_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_gsum.p,
+                           (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p, c->E,
+                           (const float*)c->b_sigma.p, glo, ghi);
+    }
+    hipLaunchKernelGGL(sigma_final_k, dim3(1), dim3(64), 0, s, (const unsigned long long*)glo, (const long long*)ghi,
+                       dsigma);
+    return hipGetLastError();
+}
+
+}  // namespace mrf

@@ -1,0 +1,473 @@
+// C ABI of libmrf (declared in include/mrf.h): context lifetime, graph
+// construction, the sweep schedule (eager launches or one captured hipGraph),
+// marginals, the reverse pass, stats and exports.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mrf_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (!g_err.empty() && e == hipErrorInvalidConfiguration) m = g_err;
+    g_err = m;
+    return e == hipErrorOutOfMemory ? MRF_ENOMEM : MRF_EHIP;
+}
+
+#define HCK(expr, what)                                  \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+void drop_graph(mrf_ctx* c)
+{
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_K = c->g_ckpt = -1;
+}
+
+int bits_for(int64_t maxval)
+{
+    int b = 1;
+    while (b < 63 && (int64_t(1) << b) <= maxval) ++b;
+    return b;
+}
+
+}  // namespace
+
+namespace mrf {
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+hipError_t ensure(DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.p && b.cap >= bytes) return hipSuccess;
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        hipGetLastError();
+        return e;
+    }
+    b.cap = bytes;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------ sweeps
+
+static float* ckpt_slot(mrf_ctx* c, int k)   // ell after sweep k+1 (k = 0..K-1)
+{
+    return (float*)c->b_ckpt.p + (size_t)k * (size_t)c->E;
+}
+
+// Everything mrf_infer enqueues after the parameter copies; capturable.
+static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipStream_t s)
+{
+    hipError_t e;
+    const float* theta = (const float*)c->b_theta.p;
+    float* lam = (float*)c->b_lam.p;
+    if ((e = launch_potentials(c, s)) != hipSuccess) return e;
+    const float* prev = nullptr;   // ell of the previous sweep; nullptr = uniform (0)
+    for (int k = 0; k < K; ++k) {
+        float* out = keep ? ckpt_slot(c, k) : (float*)c->b_ell.p;
+        if ((e = launch_voxel_phase(c, theta, prev, lam, nullptr, 0, plain, s)) != hipSuccess) return e;
+        if ((e = launch_ray_phase(c, lam, out, plain, s)) != hipSuccess) return e;
+        prev = out;
+    }
+    if ((e = launch_copy((float*)c->b_L.p, theta, c->V, s)) != hipSuccess) return e;
+    return launch_voxel_phase(c, theta, prev, nullptr, (float*)c->b_L.p, 1, plain, s);
+}
+
+static const float* final_ell(const mrf_ctx* c)
+{
+    if (!c->inferred) return nullptr;
+    return c->have_ckpt ? (const float*)c->b_ckpt.p + (size_t)(c->K - 1) * (size_t)c->E : (const float*)c->b_ell.p;
+}
+
+}  // namespace mrf
+
+using namespace mrf;
+
+extern "C" {
+
+const char* mrf_strerror(int code)
+{
+    switch (code) {
+        case MRF_OK: return "ok";
+        case MRF_EINVAL: return "invalid argument";
+        case MRF_ENOMEM: return "out of device memory";
+        case MRF_EHIP: return "HIP runtime error";
+        case MRF_ESTATE: return "call out of order";
+        case MRF_ERANGE: return "size exceeds an index type";
+        default: return "unknown error";
+    }
+}
+
+const char* mrf_last_error(void) { return g_err.c_str(); }
+
+int mrf_create(mrf_ctx** out)
+{
+    if (!out) return fail(MRF_EINVAL, "mrf_create: out is NULL");
+    *out = nullptr;
+    mrf_ctx* c = new (std::nothrow) mrf_ctx();
+    if (!c) return fail(MRF_ENOMEM, "mrf_create: host allocation failed");
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "mrf_create");
+        mrf_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return MRF_OK;
+}
+
+static void free_buf(DevBuf& b)
+{
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+void mrf_destroy(mrf_ctx* c)
+{
+    if (!c) return;
+    drop_graph(c);
+    DevBuf* all[] = {&c->b_scenes, &c->b_frames, &c->b_counts, &c->b_rowptr, &c->b_col, &c->b_delta,
+                     &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
+                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_ckpt,
+                     &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
+                     &c->b_misc, &c->b_frame_list};
+    for (DevBuf* b : all) free_buf(*b);
+    for (auto& b : c->b_ray_list) free_buf(b);
+    for (auto& b : c->b_vox_list) free_buf(b);
+    for (auto& b : c->b_hub) free_buf(b);
+    if (c->ev_in) hipEventDestroy(c->ev_in);
+    if (c->ev_out) hipEventDestroy(c->ev_out);
+    if (c->aux) hipStreamDestroy(c->aux);
+    delete c;
+}
+
+int mrf_set_schedule(mrf_ctx* c, int32_t schedule)
+{
+    if (!c || (schedule != MRF_SCHED_PLAIN && schedule != MRF_SCHED_GRAPH))
+        return fail(MRF_EINVAL, "mrf_set_schedule: bad context or schedule");
+    c->schedule = schedule;
+    return MRF_OK;
+}
+
+int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p, void* stream)
+{
+    if (!c || !scenes || !p || n_scenes < 1) return fail(MRF_EINVAL, "mrf_build: null argument or no scenes");
+    if (p->min_ray_voxels < 2) return fail(MRF_EINVAL, "mrf_build: min_ray_voxels must be >= 2");
+    if (!(p->table_dmax > 0.0) || !(p->z_max >= p->z_min) || !(p->trunc_nsigma >= 0.0))
+        return fail(MRF_EINVAL, "mrf_build: bad depth window, truncation or table range");
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_build: hipSetDevice");
+    drop_graph(c);
+    c->built = c->inferred = c->have_ckpt = 0;
+
+    c->scenes_h.clear();
+    c->frames_h.clear();
+    c->n_scenes = n_scenes;
+    int64_t R = 0, V = 0;
+    int max_hw = 0;
+    for (int i = 0; i < n_scenes; ++i) {
+        const mrf_scene& sc = scenes[i];
+        if (sc.n_frames < 1 || !sc.depth || !sc.T_wc) return fail(MRF_EINVAL, "mrf_build: scene without frames");
+        if (sc.K.width < 1 || sc.K.height < 1 || sc.K.fx == 0.0 || sc.K.fy == 0.0)
+            return fail(MRF_EINVAL, "mrf_build: bad intrinsics");
+        if (sc.grid.nx < 1 || sc.grid.ny < 1 || sc.grid.nz < 1 || !(sc.grid.voxel > 0.0))
+            return fail(MRF_EINVAL, "mrf_build: bad grid");
+        SceneDev d{};
+        d.W = sc.K.width;
+        d.H = sc.K.height;
+        d.fx = sc.K.fx;
+        d.fy = sc.K.fy;
+        d.cx = sc.K.cx;
+        d.cy = sc.K.cy;
+        d.n[0] = sc.grid.nx;
+        d.n[1] = sc.grid.ny;
+        d.n[2] = sc.grid.nz;
+        d.h = sc.grid.voxel;
+        for (int a = 0; a < 3; ++a) d.o[a] = sc.grid.origin[a];
+        d.voxel_base = V;
+        d.ray_base = R;
+        const int64_t hw = (int64_t)d.W * d.H;
+        if (hw > (int64_t(1) << 30)) return fail(MRF_ERANGE, "mrf_build: image too large");
+        if (hw > max_hw) max_hw = (int)hw;
+        for (int f = 0; f < sc.n_frames; ++f) {
+            FrameDev fr{};
+            fr.depth = sc.depth + (size_t)f * hw;
+            fr.T = sc.T_wc + (size_t)f * 16;
+            fr.scene = i;
+            fr.ray_base = R + (int64_t)f * hw;
+            c->frames_h.push_back(fr);
+        }
+        R += hw * sc.n_frames;
+        V += (int64_t)sc.grid.nx * sc.grid.ny * sc.grid.nz;
+        c->scenes_h.push_back(d);
+    }
+    if (c->frames_h.size() > 65535) return fail(MRF_EINVAL, "mrf_build: more than 65535 frames");
+    if (V >= (int64_t(1) << 31) || R >= (int64_t(1) << 32))
+        return fail(MRF_ERANGE, "mrf_build: too many voxels (>= 2^31) or rays (>= 2^32)");
+    c->R = R;
+    c->V = V;
+    c->n_frames = (int)c->frames_h.size();
+    c->max_hw = max_hw;
+    c->bp.z_min = p->z_min;
+    c->bp.z_max = p->z_max;
+    c->bp.nsig = p->trunc_nsigma;
+    c->bp.c0 = p->trunc_c0;
+    c->bp.c2 = p->trunc_c2;
+    c->bp.smin = p->trunc_min;
+    c->bp.dmax = p->table_dmax;
+    c->bp.min_vox = p->min_ray_voxels;
+    c->keep_chords = p->keep_chords ? 1 : 0;
+
+    HCK(ensure(c->b_scenes, sizeof(SceneDev) * c->scenes_h.size()), "mrf_build: alloc");
+    HCK(ensure(c->b_frames, sizeof(FrameDev) * c->frames_h.size()), "mrf_build: alloc");
+    HCK(hipMemcpyAsync(c->b_scenes.p, c->scenes_h.data(), sizeof(SceneDev) * c->scenes_h.size(),
+                       hipMemcpyHostToDevice, s),
+        "mrf_build: upload");
+    HCK(hipMemcpyAsync(c->b_frames.p, c->frames_h.data(), sizeof(FrameDev) * c->frames_h.size(),
+                       hipMemcpyHostToDevice, s),
+        "mrf_build: upload");
+    HCK(ensure(c->b_counts, sizeof(int32_t) * (size_t)R), "mrf_build: alloc counts");
+    HCK(ensure(c->b_rowptr, sizeof(int64_t) * (size_t)(R + 1)), "mrf_build: alloc row_ptr");
+    const size_t sbytes = scan_tmp_bytes(R + 1);
+    HCK(ensure(c->b_misc, sbytes), "mrf_build: alloc scan");
+    HCK(launch_trace_count(c, s), "mrf_build: trace count");
+    HCK(scan_exclusive_i32((const int32_t*)c->b_counts.p, (int64_t*)c->b_rowptr.p, R, c->b_misc.p, sbytes, s),
+        "mrf_build: scan");
+    int64_t E = 0;
+    HCK(hipMemcpyAsync(&E, (int64_t*)c->b_rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+        "mrf_build: read E");
+    HCK(hipStreamSynchronize(s), "mrf_build: sync");
+    if (E >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_build: 2^32 or more edges");
+    c->E = E;
+
+    const size_t e4 = sizeof(float) * (size_t)(E > 0 ? E : 1);
+    HCK(ensure(c->b_col, e4), "mrf_build: alloc col");
+    HCK(ensure(c->b_delta, e4), "mrf_build: alloc delta");
+    HCK(ensure(c->b_bin, (size_t)(E > 0 ? E : 1)), "mrf_build: alloc bin");
+    HCK(ensure(c->b_g, e4), "mrf_build: alloc g");
+    HCK(ensure(c->b_lam, e4), "mrf_build: alloc lam");
+    HCK(ensure(c->b_ell, e4), "mrf_build: alloc ell");
+    HCK(ensure(c->b_vedge, e4), "mrf_build: alloc vedge");
+    HCK(ensure(c->b_ellbar, e4), "mrf_build: alloc ellbar");
+    HCK(ensure(c->b_lambar, e4), "mrf_build: alloc lambar");
+    HCK(ensure(c->b_gsum, e4), "mrf_build: alloc gsum");
+    if (c->keep_chords) {
+        HCK(ensure(c->b_tin, 2 * e4), "mrf_build: alloc t_in");
+        HCK(ensure(c->b_tout, 2 * e4), "mrf_build: alloc t_out");
+    }
+    HCK(ensure(c->b_vptr, sizeof(int64_t) * (size_t)(V + 1)), "mrf_build: alloc vptr");
+    const size_t vb = sizeof(float) * (size_t)V;
+    HCK(ensure(c->b_theta, vb), "mrf_build: alloc theta");
+    HCK(ensure(c->b_L, vb), "mrf_build: alloc L");
+    HCK(ensure(c->b_thetabar, vb), "mrf_build: alloc thetabar");
+    HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
+    HCK(ensure(c->b_sigpart, sizeof(double) * 4 * kBins), "mrf_build: alloc sigma partials");
+
+    HCK(launch_trace_emit(c, s), "mrf_build: trace emit");
+
+    // voxel -> ray incidence by a stable LSD radix sort of (voxel id, edge id);
+    // the message buffers are free during build and hold the sort's ping-pong
+    const int64_t nh = (int64_t)radix_hist_entries(E);
+    HCK(ensure(c->b_tmp64, sizeof(int64_t) * (size_t)(nh + 1) + sizeof(int32_t) * (size_t)nh),
+        "mrf_build: alloc sort tables");
+    int64_t* offs = (int64_t*)c->b_tmp64.p;
+    int32_t* hist = (int32_t*)(offs + nh + 1);
+    const size_t sb2 = scan_tmp_bytes(nh + 1);
+    HCK(ensure(c->b_misc, sb2 > sbytes ? sb2 : sbytes), "mrf_build: alloc scan");
+    HCK(radix_sort_pairs((const uint32_t*)c->b_col.p, (uint32_t*)c->b_lam.p, (uint32_t*)c->b_ell.p,
+                         (uint32_t*)c->b_ellbar.p, (uint32_t*)c->b_gsum.p, (uint32_t*)c->b_lambar.p,
+                         (uint32_t*)c->b_vedge.p, E, bits_for(V > 0 ? V - 1 : 0), hist, offs, c->b_misc.p,
+                         c->b_misc.cap, s),
+        "mrf_build: radix sort");
+    HCK(launch_vptr_from_sorted((const uint32_t*)c->b_lambar.p, E, V, (int64_t*)c->b_vptr.p, s),
+        "mrf_build: vptr");
+    {
+        hipError_t e = build_classes(c, s);
+        if (e == hipErrorInvalidConfiguration) return fail(MRF_ERANGE, "mrf_build: " + g_err);
+        HCK(e, "mrf_build: work lists");
+    }
+    HCK(hipStreamSynchronize(s), "mrf_build: sync");
+
+    mrf_stats_t& st = c->stats;
+    st.n_scenes = n_scenes;
+    st.n_rays = R;
+    st.n_edges = E;
+    st.n_voxels = V;
+    st.n_kept_rays = 0;
+    for (int k = 0; k < kRayClasses; ++k) st.n_kept_rays += c->ray_cnt[k];
+    st.n_touched_voxels = c->hub.n_hubs;
+    for (int k = 0; k < kVoxClasses; ++k) st.n_touched_voxels += c->vox_cnt[k];
+    // voxel phase: vedge 4 + gather ell 4 + scatter lam 4; ray phase: lam 4 + g 4 + ell 4;
+    // per touched voxel: theta 4 (+ vptr 8)
+    st.fwd_bytes_per_sweep = 24.0 * (double)E + 12.0 * (double)st.n_touched_voxels;
+    st.sweeps_done = 0;
+    st.have_checkpoints = 0;
+    c->built = 1;
+    return MRF_OK;
+}
+
+int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, int32_t sweeps,
+              int32_t keep_checkpoints, void* stream)
+{
+    if (!c || !prior_logit || !sigma_table) return fail(MRF_EINVAL, "mrf_infer: null argument");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_infer: call mrf_build first");
+    if (sweeps < 1) return fail(MRF_EINVAL, "mrf_infer: sweeps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_infer: hipSetDevice");
+    const int keep = keep_checkpoints ? 1 : 0;
+    if (keep) {
+        const size_t need = sizeof(float) * (size_t)sweeps * (size_t)(c->E > 0 ? c->E : 1);
+        if (c->b_ckpt.cap < need) {
+            drop_graph(c);   // the graph holds the old checkpoint addresses
+            HCK(ensure(c->b_ckpt, need), "mrf_infer: alloc checkpoints");
+        }
+    }
+    HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer: copy prior");
+    HCK(launch_copy((float*)c->b_sigma.p, sigma_table, kBins, s), "mrf_infer: copy sigma");
+    if (c->schedule == MRF_SCHED_PLAIN) {
+        HCK(enqueue_forward(c, sweeps, keep, true, s), "mrf_infer: sweeps");
+    } else {
+        if (!c->gexec || c->g_K != sweeps || c->g_ckpt != keep) {
+            drop_graph(c);
+            hipGraph_t g = nullptr;
+            HCK(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal), "mrf_infer: begin capture");
+            hipError_t e = enqueue_forward(c, sweeps, keep, false, c->aux);
+            hipError_t e2 = hipStreamEndCapture(c->aux, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            if (g) hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->gexec = nullptr;
+                return hip_fail(e, "mrf_infer: graph capture");
+            }
+            c->g_K = sweeps;
+            c->g_ckpt = keep;
+        }
+        HCK(hipEventRecord(c->ev_in, s), "mrf_infer: event");
+        HCK(hipStreamWaitEvent(c->aux, c->ev_in, 0), "mrf_infer: wait");
+        HCK(hipGraphLaunch(c->gexec, c->aux), "mrf_infer: graph launch");
+        HCK(hipEventRecord(c->ev_out, c->aux), "mrf_infer: event");
+        HCK(hipStreamWaitEvent(s, c->ev_out, 0), "mrf_infer: wait");
+    }
+    c->inferred = 1;
+    c->K = sweeps;
+    c->have_ckpt = keep;
+    c->stats.sweeps_done = sweeps;
+    c->stats.have_checkpoints = keep;
+    return MRF_OK;
+}
+
+int mrf_marginals(mrf_ctx* c, float* p, float* logit, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_marginals: null context");
+    if (!c->inferred) return fail(MRF_ESTATE, "mrf_marginals: call mrf_infer first");
+    hipStream_t s = (hipStream_t)stream;
+    if (p) HCK(launch_sigmoid((const float*)c->b_L.p, p, c->V, s), "mrf_marginals");
+    if (logit) HCK(launch_copy(logit, (const float*)c->b_L.p, c->V, s), "mrf_marginals");
+    return MRF_OK;
+}
+
+int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, void* stream)
+{
+    if (!c || !dlogit) return fail(MRF_EINVAL, "mrf_backward: null argument");
+    if (!c->inferred || !c->have_ckpt)
+        return fail(MRF_ESTATE, "mrf_backward: needs a preceding mrf_infer with keep_checkpoints");
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_backward: hipSetDevice");
+    const int K = c->K;
+    const int32_t* col = (const int32_t*)c->b_col.p;
+    const float* theta = (const float*)c->b_theta.p;
+    float* lam = (float*)c->b_lam.p;
+    float* ellbar = (float*)c->b_ellbar.p;
+    float* lambar = (float*)c->b_lambar.p;
+    float* gsum = (float*)c->b_gsum.p;
+    float* thetabar = (float*)c->b_thetabar.p;
+    // d loss / d ell^(K)_e = d loss / d L_v(e);  d loss / d theta starts at d loss / d L
+    HCK(launch_gather_voxel(col, dlogit, ellbar, c->E, s), "mrf_backward: seed");
+    HCK(launch_copy(thetabar, dlogit, c->V, s), "mrf_backward: seed");
+    for (int k = K - 1; k >= 0; --k) {
+        // lambda of sweep k from the checkpointed ell of sweep k-1 (0 before the first)
+        const float* prev = k > 0 ? ckpt_slot(c, k - 1) : nullptr;
+        HCK(launch_voxel_phase(c, theta, prev, lam, nullptr, 0, false, s), "mrf_backward: recompute");
+        HCK(launch_ray_adjoint(c, lam, ellbar, lambar, gsum, k == K - 1, s), "mrf_backward: ray adjoint");
+        HCK(launch_voxel_phase(c, nullptr, lambar, k > 0 ? ellbar : nullptr, thetabar, 2, false, s),
+            "mrf_backward: voxel adjoint");
+    }
+    if (dsigma) HCK(launch_sigma_grad(c, dsigma, s), "mrf_backward: sigma gradient");
+    if (dprior) HCK(launch_copy(dprior, thetabar, c->V, s), "mrf_backward: copy");
+    return MRF_OK;
+}
+
+int mrf_stats(const mrf_ctx* c, mrf_stats_t* out)
+{
+    if (!c || !out) return fail(MRF_EINVAL, "mrf_stats: null argument");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_stats: call mrf_build first");
+    *out = c->stats;
+    return MRF_OK;
+}
+
+int mrf_export_incidence(const mrf_ctx* c, int64_t* row_ptr, int32_t* col, double* t_in, double* t_out,
+                         int64_t* vptr, uint32_t* vedge, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_export_incidence: null context");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_export_incidence: call mrf_build first");
+    if ((t_in || t_out) && !c->keep_chords)
+        return fail(MRF_ESTATE, "mrf_export_incidence: chords were not kept (keep_chords = 0)");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t E = (size_t)c->E, R = (size_t)c->R, V = (size_t)c->V;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (row_ptr) HCK(hipMemcpyAsync(row_ptr, c->b_rowptr.p, 8 * (R + 1), k, s), "export");
+    if (col && E) HCK(hipMemcpyAsync(col, c->b_col.p, 4 * E, k, s), "export");
+    if (t_in && E) HCK(hipMemcpyAsync(t_in, c->b_tin.p, 8 * E, k, s), "export");
+    if (t_out && E) HCK(hipMemcpyAsync(t_out, c->b_tout.p, 8 * E, k, s), "export");
+    if (vptr) HCK(hipMemcpyAsync(vptr, c->b_vptr.p, 8 * (V + 1), k, s), "export");
+    if (vedge && E) HCK(hipMemcpyAsync(vedge, c->b_vedge.p, 4 * E, k, s), "export");
+    return MRF_OK;
+}
+
+int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, float* lam, float* ell, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_export_edges: null context");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_export_edges: call mrf_build first");
+    if ((g || lam || ell) && !c->inferred) return fail(MRF_ESTATE, "mrf_export_edges: call mrf_infer first");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t E = (size_t)c->E;
+    if (!E) return MRF_OK;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (delta) HCK(hipMemcpyAsync(delta, c->b_delta.p, 4 * E, k, s), "export");
+    if (bin) HCK(hipMemcpyAsync(bin, c->b_bin.p, E, k, s), "export");
+    if (g) HCK(hipMemcpyAsync(g, c->b_g.p, 4 * E, k, s), "export");
+    if (lam) HCK(hipMemcpyAsync(lam, c->b_lam.p, 4 * E, k, s), "export");
+    if (ell) HCK(hipMemcpyAsync(ell, final_ell(c), 4 * E, k, s), "export");
+    return MRF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,725 @@
+// Graph construction on gfx950: ray clipping and 3D-DDA traversal
+// (Amanatides-Woo, the traversal Sec. IV-A names; truncation 3 sigma past the
+// measurement, Sec. IV-B), device exclusive scans, a stable LSD radix sort
+// for the voxel->ray incidence, and the work lists of the message kernels.
+//
+// The traversal is FP64 and compiled with -ffp-contract=off: every rounding
+// step is an IEEE-754 operation on doubles in a fixed order, so the voxel
+// ids and chord end points are reproducible bit for bit by any FP64
+// implementation that performs the same operations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mrf_internal.hpp"
+
+namespace mrf {
+
+// ============================================================== traversal
+
+struct Ray {
+    double c[3], w[3];
+    double Z, ts, te;
+};
+
+// Ray of pixel (u, v): centre c, direction R (x_n, y_n, 1) (t is z-depth),
+// clipped to the grid box and truncated at Z + nsig * sigma_tr(Z).
+__device__ bool setup_ray(const SceneDev& sd, const BuildDev& bp, const double* T, float zf,
+                          int v, int u, Ray& r)
+{
+    const double Z = (double)zf;
+    if (!isfinite(Z) || Z < bp.z_min || Z > bp.z_max) return false;
+    const double xn = ((double)u - sd.cx) / sd.fx;
+    const double yn = ((double)v - sd.cy) / sd.fy;
+    double ts = 0.0, texit = __builtin_huge_val();
+    for (int a = 0; a < 3; ++a) {
+        r.c[a] = T[4 * a + 3];
+        double wa = T[4 * a + 0] * xn;
+        wa = wa + T[4 * a + 1] * yn;
+        wa = wa + T[4 * a + 2];
+        r.w[a] = wa;
+        if (!isfinite(wa) || !isfinite(r.c[a])) return false;   // unusable pose
+        const double lo = sd.o[a];
+        const double hi = sd.o[a] + (double)sd.n[a] * sd.h;
+        if (wa != 0.0) {
+            const double t0 = (lo - r.c[a]) / wa;
+            const double t1 = (hi - r.c[a]) / wa;
+            const double tmn = t0 < t1 ? t0 : t1;
+            const double tmx = t0 < t1 ? t1 : t0;
+            if (tmn > ts) ts = tmn;
+            if (tmx < texit) texit = tmx;
+        } else if (r.c[a] < lo || r.c[a] >= hi) {
+            return false;
+        }
+    }
+    if (Z >= texit) return false;   // surface outside the grid
+    double sig = bp.c2 * Z;
+    sig = sig * Z;
+    sig = bp.c0 + sig;
+    if (sig < bp.smin) sig = bp.smin;
+    double te = Z + bp.nsig * sig;
+    if (te > texit) te = texit;
+    if (te <= ts) return false;
+    r.Z = Z;
+    r.ts = ts;
+    r.te = te;
+    return true;
+}
+
+__device__ __forceinline__ double face(const SceneDev& sd, int a, int idx)
+{
+    return sd.o[a] + (double)idx * sd.h;
+}
+
+// Walk voxels from ts to te; emit(k, id, tin, tout) for each chord of
+// positive length; ties between axes step the lowest axis.  Returns count.
+template <class Emit>
+__device__ int walk(const SceneDev& sd, const Ray& r, Emit emit)
+{
+    int idx[3];
+    double tmax[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double p = r.c[a] + r.ts * r.w[a];
+        double q = floor((p - sd.o[a]) / sd.h);
+        if (q < 0.0) q = 0.0;
+        if (q > (double)(sd.n[a] - 1)) q = (double)(sd.n[a] - 1);
+        idx[a] = (int)q;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (r.w[a] > 0.0)
+            tmax[a] = (face(sd, a, idx[a] + 1) - r.c[a]) / r.w[a];
+        else if (r.w[a] < 0.0)
+            tmax[a] = (face(sd, a, idx[a]) - r.c[a]) / r.w[a];
+        else
+            tmax[a] = __builtin_huge_val();
+    }
+    double tin = r.ts;
+    int k = 0;
+    for (;;) {
+        const int a = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
+        const double tm = tmax[a];
+        const double tout = tm < r.te ? tm : r.te;
+        if (tout > tin) {
+            emit(k, idx[0] + sd.n[0] * (idx[1] + sd.n[1] * idx[2]), tin, tout);
+            ++k;
+        }
+        if (tm >= r.te) break;
+        if (tm > tin) tin = tm;
+        idx[a] += r.w[a] > 0.0 ? 1 : -1;
+        if (idx[a] < 0 || idx[a] >= sd.n[a]) break;
+        if (r.w[a] > 0.0)
+            tmax[a] = (face(sd, a, idx[a] + 1) - r.c[a]) / r.w[a];
+        else
+            tmax[a] = (face(sd, a, idx[a]) - r.c[a]) / r.w[a];
+    }
+    return k;
+}
+
+struct NoEmit {
+    __device__ void operator()(int, int, double, double) const {}
+};
+
+__global__ __launch_bounds__(256) void trace_count_k(const SceneDev* __restrict__ scenes,
+                                                     const FrameDev* __restrict__ frames,
+                                                     BuildDev bp, int32_t* __restrict__ counts)
+{
+    const FrameDev fr = frames[blockIdx.y];
+    const SceneDev& sd = scenes[fr.scene];
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= sd.W * sd.H) return;
+    const int v = pix / sd.W, u = pix - v * sd.W;
+    Ray r;
+    int m = 0;
+    if (setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, r)) m = walk(sd, r, NoEmit{});
+    counts[fr.ray_base + pix] = m >= bp.min_vox ? m : 0;
+}
+
+struct EdgeEmit {
+    int32_t* col;
+    float* delta;
+    uint8_t* bin;
+    double* tin;
+    double* tout;
+    int64_t base;
+    int32_t vbase;
+    double Z, dbin;
+    __device__ void operator()(int k, int id, double ti, double to) const
+    {
+        const int64_t e = base + k;
+        const double d = (ti + to) * 0.5;   // voxel depth: chord midpoint
+        double q = floor(d / dbin);
+        if (q < 0.0) q = 0.0;
+        if (q > 63.0) q = 63.0;
+        col[e] = vbase + id;
+        delta[e] = (float)(Z - d);
+        bin[e] = (uint8_t)q;
+        if (tin) {
+            tin[e] = ti;
+            tout[e] = to;
+        }
+    }
+};
+
+__global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__ scenes,
+                                                    const FrameDev* __restrict__ frames, BuildDev bp,
+                                                    const int64_t* __restrict__ row_ptr,
+                                                    int32_t* col, float* delta, uint8_t* bin,
+                                                    double* tin, double* tout)
+{
+    const FrameDev fr = frames[blockIdx.y];
+    const SceneDev& sd = scenes[fr.scene];
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= sd.W * sd.H) return;
+    const int64_t r = fr.ray_base + pix;
+    const int64_t base = row_ptr[r];
+    if (row_ptr[r + 1] == base) return;
+    const int v = pix / sd.W, u = pix - v * sd.W;
+    Ray ray;
+    setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
+    EdgeEmit em{col, delta, bin, tin, tout, base, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
+    walk(sd, ray, em);
+}
+
+hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s)
+{
+    dim3 grid((c->max_hw + 255) / 256, c->n_frames);
+    hipLaunchKernelGGL(trace_count_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
+                       (const FrameDev*)c->b_frames.p, c->bp, (int32_t*)c->b_counts.p);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s)
+{
+    dim3 grid((c->max_hw + 255) / 256, c->n_frames);
+    hipLaunchKernelGGL(trace_emit_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
+                       (const FrameDev*)c->b_frames.p, c->bp, (const int64_t*)c->b_rowptr.p,
+                       (int32_t*)c->b_col.p, (float*)c->b_delta.p, (uint8_t*)c->b_bin.p,
+                       c->keep_chords ? (double*)c->b_tin.p : nullptr,
+                       c->keep_chords ? (double*)c->b_tout.p : nullptr);
+    return hipGetLastError();
+}
+
+// ============================================================== scans
+
+constexpr int SC_T = 256, SC_IPT = 8, SC_TILE = SC_T * SC_IPT;
+
+struct LoadI32 {
+    const int32_t* p;
+    __device__ int64_t operator()(int64_t i) const { return p[i]; }
+};
+struct LoadI64 {
+    const int64_t* p;
+    __device__ int64_t operator()(int64_t i) const { return p[i]; }
+};
+struct LoadEqU8 {
+    const uint8_t* p;
+    uint8_t c;
+    __device__ int64_t operator()(int64_t i) const { return p[i] == c ? 1 : 0; }
+};
+
+__device__ int64_t block_excl_scan_i64(int64_t x, int64_t* total)
+{
+    __shared__ int64_t wsum[SC_T / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < SC_T / 64; ++i) {
+        if (i < w) off += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - x;
+}
+
+template <class Load>
+__global__ __launch_bounds__(SC_T) void scan_reduce_k(Load ld, int64_t n, int64_t* __restrict__ bsum)
+{
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+    int64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < SC_IPT; ++k) {
+        const int64_t i = base + k * SC_T + threadIdx.x;
+        if (i < n) acc += ld(i);
+    }
+    int64_t tot;
+    block_excl_scan_i64(acc, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <class Load>
+__global__ __launch_bounds__(SC_T) void scan_apply_k(Load ld, int64_t n, const int64_t* __restrict__ boff,
+                                                     int64_t* __restrict__ out)
+{
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_IPT;
+    int64_t v[SC_IPT];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SC_IPT; ++k) {
+        const int64_t i = base + k;
+        v[k] = i < n ? ld(i) : 0;
+        s += v[k];
+    }
+    int64_t tot;
+    int64_t ex = block_excl_scan_i64(s, &tot) + (boff ? boff[blockIdx.x] : 0);
+#pragma unroll
+    for (int k = 0; k < SC_IPT; ++k) {
+        const int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+        if (i == n - 1) out[n] = ex;
+    }
+}
+
+__global__ void zero_i64_k(int64_t* p) { *p = 0; }
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t scan_tmp_bytes(int64_t n)
+{
+    size_t words = 0;
+    int64_t m = n;
+    while (cdiv(m, SC_TILE) > 1) {
+        const int64_t nb = cdiv(m, SC_TILE);
+        words += 2 * nb + 1;
+        m = nb;
+    }
+    return (words + 8) * sizeof(int64_t);
+}
+
+template <class Load>
+static hipError_t scan_rec(Load ld, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s)
+{
+    if (n == 0) {
+        hipLaunchKernelGGL(zero_i64_k, dim3(1), dim3(1), 0, s, out);
+        return hipGetLastError();
+    }
+    const int64_t nb = cdiv(n, SC_TILE);
+    if (nb == 1) {
+        hipLaunchKernelGGL(scan_apply_k<Load>, dim3(1), dim3(SC_T), 0, s, ld, n,
+                           (const int64_t*)nullptr, out);
+        return hipGetLastError();
+    }
+    int64_t* bsum = tmp;
+    int64_t* boff = tmp + nb;
+    hipLaunchKernelGGL(scan_reduce_k<Load>, dim3((unsigned)nb), dim3(SC_T), 0, s, ld, n, bsum);
+    hipError_t e = scan_rec(LoadI64{bsum}, nb, boff, tmp + 2 * nb + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_apply_k<Load>, dim3((unsigned)nb), dim3(SC_T), 0, s, ld, n,
+                       (const int64_t*)boff, out);
+    return hipGetLastError();
+}
+
+hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t tmp_bytes,
+                              hipStream_t s)
+{
+    if (tmp_bytes < scan_tmp_bytes(n)) return hipErrorInvalidValue;
+    return scan_rec(LoadI32{in}, n, out, (int64_t*)tmp, s);
+}
+
+// ============================================================== radix sort
+
+constexpr int RS_T = 256, RS_IPT = 16, RS_TILE = RS_T * RS_IPT;
+
+size_t radix_hist_entries(int64_t n) { return (size_t)256 * (size_t)cdiv(n > 0 ? n : 1, RS_TILE); }
+
+__global__ __launch_bounds__(RS_T) void rs_hist_k(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                  int32_t* __restrict__ hist, int64_t nblocks)
+{
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t start = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t end = start + RS_TILE < n ? start + RS_TILE : n;
+    for (int64_t i = start + threadIdx.x; i < end; i += RS_T) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: items of a tile are ranked in index order among equal
+// digits (wave-level match by ballots, waves in order, rounds in order).
+__global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict__ keys_in,
+                                                     const uint32_t* __restrict__ vals_in, int64_t n,
+                                                     int shift, const int64_t* __restrict__ offs,
+                                                     int64_t nblocks, uint32_t* __restrict__ keys_out,
+                                                     uint32_t* __restrict__ vals_out)
+{
+    __shared__ int64_t boff[256];
+    __shared__ int32_t run[256];
+    __shared__ int32_t wcnt[RS_T / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    boff[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    run[tid] = 0;
+#pragma unroll
+    for (int q = 0; q < RS_T / 64; ++q) wcnt[q][tid] = 0;
+    __syncthreads();
+    const uint64_t below = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+    const int64_t start = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int64_t i = start + (int64_t)r * RS_T + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const int d = (key >> shift) & 255;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int pre = run[d];
+            for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+            const int64_t pos = boff[d] + pre + rank;
+            keys_out[pos] = key;
+            vals_out[pos] = vals_in ? vals_in[i] : (uint32_t)i;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int q = 0; q < RS_T / 64; ++q) {
+            add += wcnt[q][tid];
+            wcnt[q][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                            uint32_t* vals_b, uint32_t* keys_out, uint32_t* vals_out, int64_t n,
+                            int key_bits, int32_t* hist, int64_t* offs, void* tmp, size_t tmp_bytes,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int passes = key_bits <= 8 ? 1 : (key_bits + 7) / 8;
+    const int64_t nb = cdiv(n, RS_TILE);
+    const int64_t nh = 256 * nb;
+    if (tmp_bytes < scan_tmp_bytes(nh)) return hipErrorInvalidValue;
+    const uint32_t* sk = keys_in;
+    const uint32_t* sv = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t* dk = (p == passes - 1) ? keys_out : ((p & 1) ? keys_b : keys_a);
+        uint32_t* dv = (p == passes - 1) ? vals_out : ((p & 1) ? vals_b : vals_a);
+        hipLaunchKernelGGL(rs_hist_k, dim3((unsigned)nb), dim3(RS_T), 0, s, sk, n, 8 * p, hist, nb);
+        hipError_t e = scan_rec(LoadI32{hist}, nh, offs, (int64_t*)tmp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(rs_scatter_k, dim3((unsigned)nb), dim3(RS_T), 0, s, sk, sv, n, 8 * p,
+                           (const int64_t*)offs, nb, dk, dv);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        sk = dk;
+        sv = dv;
+    }
+    return hipSuccess;
+}
+
+// vptr[v] = first position whose key >= v (binary search), v in [0, V]
+__global__ void vptr_k(const uint32_t* __restrict__ keys, int64_t n, int64_t V, int64_t* __restrict__ vptr)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > V) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    vptr[v] = lo;
+}
+
+hipError_t launch_vptr_from_sorted(const uint32_t* sorted_keys, int64_t n, int64_t V, int64_t* vptr,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(vptr_k, dim3((unsigned)cdiv(V + 1, 256)), dim3(256), 0, s, sorted_keys, n, V, vptr);
+    return hipGetLastError();
+}
+
+// ============================================================== work lists
+
+__global__ void ray_class_k(const int32_t* __restrict__ counts, int64_t R, uint8_t* __restrict__ cls)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int n = counts[r];
+    uint8_t c = 255;
+    if (n > 0) {
+        c = kRayClasses;   // too long: reported as an error by the host
+        for (int k = 0; k < kRayClasses; ++k)
+            if (n <= kRayCap[k]) {
+                c = (uint8_t)k;
+                break;
+            }
+    }
+    cls[r] = c;
+}
+
+__global__ void vox_class_k(const int64_t* __restrict__ vptr, int64_t V, uint8_t* __restrict__ cls)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int64_t m = vptr[v + 1] - vptr[v];
+    uint8_t c = 255;
+    if (m > 0) {
+        c = kVoxClasses;   // hub
+        for (int k = 0; k < kVoxClasses; ++k)
+            if (m <= kVoxCap[k]) {
+                c = (uint8_t)k;
+                break;
+            }
+    }
+    cls[v] = c;
+}
+
+__global__ void compact_k(const uint8_t* __restrict__ cls, int64_t n, uint8_t c,
+                          const int64_t* __restrict__ pos, uint32_t* __restrict__ list)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cls[i] == c) list[pos[i]] = (uint32_t)i;
+}
+
+__global__ void hub_pieces_count_k(const uint32_t* __restrict__ hubs, uint32_t nh,
+                                   const int64_t* __restrict__ vptr, int32_t* __restrict__ npieces)
+{
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= nh) return;
+    const uint32_t v = hubs[h];
+    const int64_t m = vptr[v + 1] - vptr[v];
+    npieces[h] = (int32_t)((m + kPiece - 1) / kPiece);
+}
+
+__global__ void hub_pieces_fill_k(const uint32_t* __restrict__ hubs, uint32_t nh,
+                                  const int64_t* __restrict__ vptr, const int64_t* __restrict__ p0,
+                                  uint32_t* hub_piece0, uint32_t* piece_voxel, int64_t* piece_start,
+                                  uint32_t* piece_len)
+{
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h > nh) return;
+    hub_piece0[h] = (uint32_t)p0[h];
+    if (h == nh) return;
+    const uint32_t v = hubs[h];
+    const int64_t s = vptr[v], m = vptr[v + 1] - s;
+    uint32_t q = (uint32_t)p0[h];
+    for (int64_t off = 0; off < m; off += kPiece, ++q) {
+        piece_voxel[q] = v;
+        piece_start[q] = s + off;
+        piece_len[q] = (uint32_t)(m - off < kPiece ? m - off : kPiece);
+    }
+}
+
+}  // namespace mrf
+
+namespace mrf {
+
+// lower_bound of every frame's first ray id in every class list
+__global__ void frame_offsets_k(const uint32_t* const* __restrict__ lists, const int64_t* __restrict__ cnt,
+                                const int64_t* __restrict__ fbase, int32_t nf, int64_t* __restrict__ out)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (f > nf) return;
+    const uint32_t* L = lists[c];
+    int64_t lo = 0, hi = cnt[c];
+    const int64_t key = fbase[f];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)L[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    out[(int64_t)c * (nf + 1) + f] = lo;
+}
+
+// log2 histograms of ray lengths and voxel degrees (integer atomics only)
+__global__ void hist_k(const int32_t* __restrict__ counts, int64_t R, const int64_t* __restrict__ vptr,
+                       int64_t V, unsigned long long* __restrict__ h)
+{
+    __shared__ unsigned long long loc[16 + 24 + 2];
+    for (int i = threadIdx.x; i < 42; i += blockDim.x) loc[i] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < R) {
+        const int n = counts[i];
+        if (n > 0) {
+            const int b = min(15, 31 - __clz(n));
+            atomicAdd(&loc[b], 1ull);
+            atomicMax(&loc[40], (unsigned long long)n);
+        }
+    }
+    if (i < V) {
+        const int64_t m = vptr[i + 1] - vptr[i];
+        if (m > 0) {
+            const int b = min(23, 63 - __clzll(m));
+            atomicAdd(&loc[16 + b], 1ull);
+            atomicMax(&loc[41], (unsigned long long)m);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 42; k += blockDim.x) {
+        if (loc[k] == 0) continue;
+        if (k >= 40)
+            atomicMax(&h[k], loc[k]);
+        else
+            atomicAdd(&h[k], loc[k]);
+    }
+}
+
+static hipError_t partition(const uint8_t* cls, int64_t n, uint8_t c, int64_t* pos, void* tmp,
+                            size_t tmp_bytes, DevBuf& list, int64_t* count, hipStream_t s)
+{
+    if (tmp_bytes < scan_tmp_bytes(n)) return hipErrorInvalidValue;
+    hipError_t e = scan_rec(LoadEqU8{cls, c}, n, pos, (int64_t*)tmp, s);
+    if (e != hipSuccess) return e;
+    int64_t total = 0;
+    if ((e = hipMemcpyAsync(&total, pos + n, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    *count = total;
+    if ((e = ensure(list, (size_t)(total > 0 ? total : 1) * sizeof(uint32_t))) != hipSuccess) return e;
+    if (total > 0)
+        hipLaunchKernelGGL(compact_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, cls, n, c,
+                           (const int64_t*)pos, (uint32_t*)list.p);
+    return hipGetLastError();
+}
+
+hipError_t build_classes(mrf_ctx* c, hipStream_t s)
+{
+    hipError_t e;
+    const int64_t nmax = c->R > c->V ? c->R : c->V;
+    if ((e = ensure(c->b_cls, (size_t)(nmax + 1))) != hipSuccess) return e;
+    if ((e = ensure(c->b_tmp64, (size_t)(nmax + 2) * sizeof(int64_t))) != hipSuccess) return e;
+    const size_t sbytes = scan_tmp_bytes(nmax + 1);
+    if ((e = ensure(c->b_misc, sbytes)) != hipSuccess) return e;
+    uint8_t* cls = (uint8_t*)c->b_cls.p;
+    int64_t* pos = (int64_t*)c->b_tmp64.p;
+
+    // rays
+    if (c->R > 0)
+        hipLaunchKernelGGL(ray_class_k, dim3((unsigned)cdiv(c->R, 256)), dim3(256), 0, s,
+                           (const int32_t*)c->b_counts.p, c->R, cls);
+    for (int k = 0; k < kRayClasses; ++k)
+        if ((e = partition(cls, c->R, (uint8_t)k, pos, c->b_misc.p, sbytes, c->b_ray_list[k], &c->ray_cnt[k], s)) !=
+            hipSuccess)
+            return e;
+    {
+        DevBuf tmp;
+        int64_t too_long = 0;
+        e = partition(cls, c->R, (uint8_t)kRayClasses, pos, c->b_misc.p, sbytes, tmp, &too_long, s);
+        hipFree(tmp.p);
+        if (e != hipSuccess) return e;
+        if (too_long > 0) {
+            set_error("a ray crosses more than 2048 voxels");
+            return hipErrorInvalidConfiguration;
+        }
+    }
+    // voxels
+    if (c->V > 0)
+        hipLaunchKernelGGL(vox_class_k, dim3((unsigned)cdiv(c->V, 256)), dim3(256), 0, s,
+                           (const int64_t*)c->b_vptr.p, c->V, cls);
+    for (int k = 0; k < kVoxClasses; ++k)
+        if ((e = partition(cls, c->V, (uint8_t)k, pos, c->b_misc.p, sbytes, c->b_vox_list[k], &c->vox_cnt[k], s)) !=
+            hipSuccess)
+            return e;
+    int64_t nh = 0;
+    if ((e = partition(cls, c->V, (uint8_t)kVoxClasses, pos, c->b_misc.p, sbytes, c->b_hub[0], &nh, s)) != hipSuccess)
+        return e;
+    HubTables& H = c->hub;
+    H.n_hubs = (uint32_t)nh;
+    H.hub_voxel = (uint32_t*)c->b_hub[0].p;
+    if ((e = ensure(c->b_hub[1], (size_t)(nh + 1) * sizeof(uint32_t))) != hipSuccess) return e;
+    H.hub_piece0 = (uint32_t*)c->b_hub[1].p;
+    int64_t npieces = 0;
+    if (nh > 0) {
+        int32_t* np = (int32_t*)c->b_lambar.p;   // free during build
+        hipLaunchKernelGGL(hub_pieces_count_k, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, s, H.hub_voxel,
+                           (uint32_t)nh, (const int64_t*)c->b_vptr.p, np);
+        if ((e = scan_rec(LoadI32{np}, nh, pos, (int64_t*)c->b_misc.p, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(&npieces, pos + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    }
+    H.n_pieces = (uint32_t)npieces;
+    const size_t pn = (size_t)(npieces > 0 ? npieces : 1);
+    if ((e = ensure(c->b_hub[2], pn * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = ensure(c->b_hub[3], pn * sizeof(int64_t))) != hipSuccess) return e;
+    if ((e = ensure(c->b_hub[4], pn * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = ensure(c->b_hub[5], pn * sizeof(float))) != hipSuccess) return e;
+    if ((e = ensure(c->b_hub[6], pn * sizeof(float))) != hipSuccess) return e;
+    if ((e = ensure(c->b_hub[7], pn * sizeof(float))) != hipSuccess) return e;
+    H.piece_voxel = (uint32_t*)c->b_hub[2].p;
+    H.piece_start = (int64_t*)c->b_hub[3].p;
+    H.piece_len = (uint32_t*)c->b_hub[4].p;
+    H.piece_sum = (float*)c->b_hub[5].p;
+    H.piece_pre = (float*)c->b_hub[6].p;
+    H.piece_suf = (float*)c->b_hub[7].p;
+    if (nh > 0)
+        hipLaunchKernelGGL(hub_pieces_fill_k, dim3((unsigned)cdiv(nh + 1, 256)), dim3(256), 0, s, H.hub_voxel,
+                           (uint32_t)nh, (const int64_t*)c->b_vptr.p, (const int64_t*)pos, H.hub_piece0,
+                           H.piece_voxel, H.piece_start, H.piece_len);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // per-frame offsets of every ray class list (plain schedule)
+    {
+        const int nf = c->n_frames;
+        std::vector<int64_t> fbase(nf + 1);
+        for (int f = 0; f < nf; ++f) fbase[f] = c->frames_h[f].ray_base;
+        fbase[nf] = c->R;
+        std::vector<const uint32_t*> lists(kRayClasses);
+        for (int k = 0; k < kRayClasses; ++k) lists[k] = (const uint32_t*)c->b_ray_list[k].p;
+        // fbase (nf+1) | counts (classes) | offsets ((nf+1) * classes) | list pointers (classes)
+        const size_t need = sizeof(int64_t) * ((size_t)(nf + 1) * (kRayClasses + 1) + kRayClasses) +
+                            sizeof(void*) * kRayClasses;
+        if ((e = ensure(c->b_frame_list, need)) != hipSuccess) return e;
+        char* base = (char*)c->b_frame_list.p;
+        int64_t* d_fbase = (int64_t*)base;
+        int64_t* d_cnt = d_fbase + (nf + 1);
+        int64_t* d_out = d_cnt + kRayClasses;
+        const uint32_t** d_lists = (const uint32_t**)(d_out + (size_t)(nf + 1) * kRayClasses);
+        hipMemcpyAsync(d_fbase, fbase.data(), sizeof(int64_t) * (nf + 1), hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d_cnt, c->ray_cnt, sizeof(int64_t) * kRayClasses, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d_lists, lists.data(), sizeof(void*) * kRayClasses, hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(frame_offsets_k, dim3((unsigned)cdiv(nf + 1, 64), kRayClasses), dim3(64), 0, s,
+                           d_lists, (const int64_t*)d_cnt, (const int64_t*)d_fbase, nf, d_out);
+        c->frame_ray_off.assign((size_t)(nf + 1) * kRayClasses, 0);
+        if ((e = hipMemcpyAsync(c->frame_ray_off.data(), d_out, sizeof(int64_t) * (nf + 1) * kRayClasses,
+                                hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return e;
+        // the host arrays above are read by the copies: finish before they go away
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    }
+    // histograms
+    {
+        unsigned long long* d_h = (unsigned long long*)c->b_sigpart.p;
+        if ((e = ensure(c->b_sigpart, 64 * sizeof(double) * 4096)) != hipSuccess) return e;
+        d_h = (unsigned long long*)c->b_sigpart.p;
+        hipMemsetAsync(d_h, 0, 42 * sizeof(unsigned long long), s);
+        const int64_t nmx = c->R > c->V ? c->R : c->V;
+        if (nmx > 0)
+            hipLaunchKernelGGL(hist_k, dim3((unsigned)cdiv(nmx, 256)), dim3(256), 0, s,
+                               (const int32_t*)c->b_counts.p, c->R, (const int64_t*)c->b_vptr.p, c->V, d_h);
+        unsigned long long hh[42];
+        if ((e = hipMemcpyAsync(hh, d_h, sizeof(hh), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        for (int i = 0; i < 16; ++i) c->stats.ray_len_hist[i] = (int64_t)hh[i];
+        for (int i = 0; i < 24; ++i) c->stats.voxel_degree_hist[i] = (int64_t)hh[16 + i];
+        c->stats.max_ray_len = (int64_t)hh[40];
+        c->stats.max_voxel_degree = (int64_t)hh[41];
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mrf

@@ -1,0 +1,152 @@
+// Internal declarations of libmrf: device-side descriptors, the context, and
+// the host launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mrf.h"
+
+namespace mrf {
+
+// ---------------------------------------------------------------- limits
+constexpr int kBins = 64;
+constexpr int kMaxRayLen = 2048;      // longest ray factor a group can hold
+constexpr int kPiece = 1024;          // hub voxels are split into pieces of this many edges
+
+// Ray-length classes: (group lanes G, items per lane IPL), capacity G*IPL.
+constexpr int kRayClasses = 5;
+constexpr int kRayCap[kRayClasses] = {16, 64, 256, 1024, 2048};
+// Voxel-degree classes; degrees above the last capacity become hub pieces.
+constexpr int kVoxClasses = 4;
+constexpr int kVoxCap[kVoxClasses] = {16, 64, 256, 1024};
+
+struct SceneDev {
+    int32_t W, H;
+    double fx, fy, cx, cy;
+    int32_t n[3];
+    int32_t pad;
+    double h;
+    double o[3];
+    int64_t voxel_base;
+    int64_t ray_base;
+};
+
+struct FrameDev {
+    const float* depth;   // H*W
+    const double* T;      // 16
+    int32_t scene;
+    int32_t pad;
+    int64_t ray_base;     // global id of pixel (0, 0)
+};
+
+struct BuildDev {
+    double z_min, z_max, nsig, c0, c2, smin, dmax;
+    int32_t min_vox;
+    int32_t pad;
+};
+
+// Pieces of hub voxels (degree > kPiece).
+struct HubTables {
+    uint32_t n_hubs = 0, n_pieces = 0;
+    uint32_t* hub_voxel = nullptr;        // n_hubs
+    uint32_t* hub_piece0 = nullptr;       // n_hubs + 1
+    uint32_t* piece_voxel = nullptr;      // n_pieces
+    int64_t* piece_start = nullptr;       // n_pieces
+    uint32_t* piece_len = nullptr;        // n_pieces
+    float* piece_sum = nullptr;           // n_pieces
+    float* piece_pre = nullptr;           // n_pieces
+    float* piece_suf = nullptr;           // n_pieces
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace mrf
+
+struct mrf_ctx {
+    int device = 0;
+    hipStream_t aux = nullptr;    // internal stream used for graph capture/launch
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+
+    // graph description
+    int32_t n_scenes = 0;
+    int64_t R = 0, E = 0, V = 0;
+    int32_t n_frames = 0, max_hw = 0;
+    std::vector<mrf::SceneDev> scenes_h;
+    std::vector<mrf::FrameDev> frames_h;
+    std::vector<int32_t> frame_hw;
+    mrf::BuildDev bp{};
+    int keep_chords = 0;
+
+    // buffers (raw device pointers into `bufs`)
+    mrf::DevBuf b_scenes, b_frames, b_counts, b_rowptr, b_col, b_delta, b_bin, b_tin, b_tout,
+        b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_ckpt,
+        b_ellbar, b_lambar, b_gsum, b_tmp64, b_cls, b_sigpart, b_misc;
+    mrf::DevBuf b_ray_list[mrf::kRayClasses];
+    mrf::DevBuf b_vox_list[mrf::kVoxClasses];
+    mrf::DevBuf b_hub[8];
+    mrf::DevBuf b_frame_list;     // per-frame ray lists for the plain schedule
+
+    int64_t ray_cnt[mrf::kRayClasses] = {0};
+    int64_t vox_cnt[mrf::kVoxClasses] = {0};
+    std::vector<int64_t> frame_ray_off;   // plain schedule: rays of frame f at [off[f], off[f+1])
+    mrf::HubTables hub;
+
+    // stats
+    mrf_stats_t stats{};
+
+    // state
+    int built = 0, inferred = 0, K = 0, have_ckpt = 0;
+    int schedule = MRF_SCHED_GRAPH;
+
+    // graph cache
+    hipGraphExec_t gexec = nullptr;
+    int g_K = -1, g_ckpt = -1;
+};
+
+namespace mrf {
+
+void set_error(const std::string& msg);
+hipError_t ensure(DevBuf& b, size_t bytes);
+
+// every launcher returns hipSuccess or the first error
+// build_kernels.hip
+hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s);
+hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s);
+hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t tmp_bytes,
+                              hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
+                            uint32_t* keys_b, uint32_t* vals_b, uint32_t* keys_out,
+                            uint32_t* vals_out, int64_t n, int key_bits, int32_t* hist,
+                            int64_t* offs, void* tmp, size_t tmp_bytes, hipStream_t s);
+size_t radix_hist_entries(int64_t n);
+hipError_t launch_vptr_from_sorted(const uint32_t* sorted_keys, int64_t n, int64_t V, int64_t* vptr,
+                                   hipStream_t s);
+hipError_t build_classes(mrf_ctx* c, hipStream_t s);
+
+// sweep_kernels.hip
+hipError_t launch_potentials(mrf_ctx* c, hipStream_t s);
+hipError_t launch_fill(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_gather_voxel(const int32_t* col, const float* vox, float* edge, int64_t E,
+                               hipStream_t s);
+// voxel phase: out_e = (base_v + sum_{e'<e} in) + sum_{e'>e} in over the voxel's edges;
+// total_mode 0: none, 1: total[v] = base_v + sum, 2: total[v] += sum
+hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out,
+                              float* total, int total_mode, bool plain, hipStream_t s);
+hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain, hipStream_t s);
+hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
+
+// adjoint_kernels.hip
+hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar,
+                              float* gsum, bool first, hipStream_t s);
+hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s);
+
+}  // namespace mrf

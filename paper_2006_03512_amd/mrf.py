@@ -1,0 +1,200 @@
+"""Thin PyTorch face of libmrf: a ray-MRF context and its autograd function.
+
+Every step of the method runs in the HIP library; this module only moves
+scene arrays to the device, passes tensor addresses and the current stream
+through the C ABI, and wraps ``mrf_backward`` in ``torch.autograd.Function``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, ptr, stream_handle
+
+N_BINS = 64
+
+
+@dataclass
+class GraphStats:
+    n_scenes: int
+    n_rays: int
+    n_edges: int
+    n_voxels: int
+    n_kept_rays: int
+    n_touched_voxels: int
+    max_ray_len: int
+    max_voxel_degree: int
+    ray_len_hist: list
+    voxel_degree_hist: list
+    fwd_bytes_per_sweep: float
+
+
+class RayMRF:
+    """One library context on the current HIP device.
+
+    >>> m = RayMRF()
+    >>> m.build([scene])                       # 3D-DDA, CSR incidence, radix sort
+    >>> m.infer(theta, sigma, sweeps=10)       # loopy BP sweeps
+    >>> p, logit = m.marginals()
+    """
+
+    def __init__(self, device: int | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("RayMRF needs a HIP device (the library has no CPU path)")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._L = _lib.lib()
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self._L.mrf_create(C.byref(self._h)), "mrf_create")
+        self.n_voxels = 0
+        self.n_edges = 0
+        self.n_rays = 0
+        self.voxel_base = []
+        self._keep = []
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if self._h:
+            self._L.mrf_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ------------------------------------------------------------------
+    def build(self, scenes, keep_chords: bool = False, stream=None):
+        """Build the ray MRF of one scene or a list of scenes (batched)."""
+        if not isinstance(scenes, (list, tuple)):
+            scenes = [scenes]
+        p0 = scenes[0].params
+        arr = (_lib.SceneC * len(scenes))()
+        keep = []
+        vb = 0
+        self.voxel_base = []
+        for i, s in enumerate(scenes):
+            if s.params != p0:
+                raise ValueError("all scenes of a batch must share build parameters")
+            d = torch.from_numpy(np.ascontiguousarray(s.depth, np.float32)).to(self.device)
+            T = torch.from_numpy(np.ascontiguousarray(s.T_wc, np.float64).reshape(-1, 16)).to(self.device)
+            keep += [d, T]
+            sc = arr[i]
+            sc.n_frames = s.n_frames
+            sc.depth = d.data_ptr()
+            sc.T_wc = T.data_ptr()
+            sc.K = _lib.Intrinsics(s.intr.width, s.intr.height, s.intr.fx, s.intr.fy, s.intr.cx, s.intr.cy)
+            g = s.grid
+            sc.grid = _lib.Grid(g.nx, g.ny, g.nz, 0, g.voxel, (C.c_double * 3)(*g.origin))
+            self.voxel_base.append(vb)
+            vb += g.n_voxels
+        bp = _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
+                              p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0)
+        with torch.cuda.device(self.device):
+            check(self._L.mrf_build(self._h, arr, len(scenes), C.byref(bp), stream_handle(stream)),
+                  "mrf_build")
+        st = self.stats()
+        self.n_voxels, self.n_edges, self.n_rays = st.n_voxels, st.n_edges, st.n_rays
+        self.keep_chords = keep_chords
+        return st
+
+    def stats(self) -> GraphStats:
+        st = _lib.Stats()
+        check(self._L.mrf_stats(self._h, C.byref(st)), "mrf_stats")
+        return GraphStats(st.n_scenes, st.n_rays, st.n_edges, st.n_voxels, st.n_kept_rays,
+                          st.n_touched_voxels, st.max_ray_len, st.max_voxel_degree,
+                          list(st.ray_len_hist), list(st.voxel_degree_hist), st.fwd_bytes_per_sweep)
+
+    def set_schedule(self, schedule: str):
+        code = {"plain": _lib.MRF_SCHED_PLAIN, "graph": _lib.MRF_SCHED_GRAPH}[schedule]
+        check(self._L.mrf_set_schedule(self._h, code), "mrf_set_schedule")
+
+    # ------------------------------------------------------------------
+    def _vec(self, x, n, name):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+                and x.is_contiguous() and x.numel() == n):
+            raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} elements")
+        return x
+
+    def infer(self, prior_logit, sigma_table, sweeps: int, keep_checkpoints: bool = False, stream=None):
+        self._vec(prior_logit, self.n_voxels, "prior_logit")
+        self._vec(sigma_table, N_BINS, "sigma_table")
+        check(self._L.mrf_infer(self._h, ptr(prior_logit), ptr(sigma_table), int(sweeps),
+                                1 if keep_checkpoints else 0, stream_handle(stream)), "mrf_infer")
+
+    def marginals(self, stream=None):
+        p = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device)
+        logit = torch.empty_like(p)
+        check(self._L.mrf_marginals(self._h, ptr(p), ptr(logit), stream_handle(stream)), "mrf_marginals")
+        return p, logit
+
+    def backward(self, dloss_dlogit, want_prior=True, want_sigma=True, stream=None):
+        self._vec(dloss_dlogit, self.n_voxels, "dloss_dlogit")
+        dp = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device) if want_prior else None
+        ds = torch.empty(N_BINS, dtype=torch.float32, device=self.device) if want_sigma else None
+        check(self._L.mrf_backward(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), stream_handle(stream)),
+              "mrf_backward")
+        return dp, ds
+
+    # ------------------------------------------------------------------
+    def export_incidence(self, stream=None):
+        R, E, V = self.n_rays, self.n_edges, self.n_voxels
+        dev = self.device
+        out = {
+            "row_ptr": torch.empty(R + 1, dtype=torch.int64, device=dev),
+            "col": torch.empty(E, dtype=torch.int32, device=dev),
+            "vptr": torch.empty(V + 1, dtype=torch.int64, device=dev),
+            "vedge": torch.empty(E, dtype=torch.int32, device=dev),   # uint32 bits
+        }
+        if self.keep_chords:
+            out["t_in"] = torch.empty(E, dtype=torch.float64, device=dev)
+            out["t_out"] = torch.empty(E, dtype=torch.float64, device=dev)
+        check(self._L.mrf_export_incidence(self._h, ptr(out["row_ptr"]), ptr(out["col"]),
+                                           ptr(out.get("t_in")), ptr(out.get("t_out")),
+                                           ptr(out["vptr"]), ptr(out["vedge"]), stream_handle(stream)),
+              "mrf_export_incidence")
+        return out
+
+    def export_edges(self, with_messages: bool = True, stream=None):
+        E, dev = self.n_edges, self.device
+        out = {"delta": torch.empty(E, dtype=torch.float32, device=dev),
+               "bin": torch.empty(E, dtype=torch.uint8, device=dev)}
+        if with_messages:
+            for k in ("g", "lam", "ell"):
+                out[k] = torch.empty(E, dtype=torch.float32, device=dev)
+        check(self._L.mrf_export_edges(self._h, ptr(out["delta"]), ptr(out["bin"]), ptr(out.get("g")),
+                                       ptr(out.get("lam")), ptr(out.get("ell")), stream_handle(stream)),
+              "mrf_export_edges")
+        return out
+
+
+class MRFInfer(torch.autograd.Function):
+    """logit = MRFInfer.apply(mrf, prior_logit, sigma_table, sweeps)
+
+    Forward runs ``sweeps`` BP sweeps keeping per-sweep checkpoints and returns
+    the marginal log-odds; backward runs the library's reverse pass and
+    returns gradients for the prior log-odds and the 64-bin sigma table.
+    """
+
+    @staticmethod
+    def forward(ctx, mrf: RayMRF, prior_logit, sigma_table, sweeps: int):
+        mrf.infer(prior_logit.detach().contiguous(), sigma_table.detach().contiguous(), sweeps,
+                  keep_checkpoints=True)
+        _, logit = mrf.marginals()
+        ctx.mrf = mrf
+        return logit
+
+    @staticmethod
+    def backward(ctx, g):
+        dp, ds = ctx.mrf.backward(g.contiguous().float(), want_prior=ctx.needs_input_grad[1],
+                                  want_sigma=ctx.needs_input_grad[2])
+        return None, dp, ds, None
