@@ -166,6 +166,27 @@ int mrf_export_edges(const mrf_ctx* ctx, float* delta, uint8_t* bin, float* g,
 enum { MRF_SCHED_PLAIN = 0, MRF_SCHED_GRAPH = 1 };
 int mrf_set_schedule(mrf_ctx* ctx, int32_t schedule);
 
+/* Diagnostic timing of the sweep kernels (not part of the method).  Runs
+ * `reps` eager forward sweeps (voxel phase, then ray phase) on the messages
+ * of the last mrf_infer, and with include_backward != 0 also `reps` reverse
+ * sweeps, recording a HIP event pair around every kernel launch on `stream`
+ * (the stream the kernels run on).  Overwrites the context's message buffers
+ * (marginals of the last inference are kept; run mrf_infer again before
+ * mrf_backward).  Writes up to max_out entries, one per kernel that ran, and
+ * the count to *n_out.  bytes_per_launch is the kernel's algorithmic HBM
+ * traffic per launch (each per-edge and per-item array read or written once).
+ * Errors: MRF_ESTATE before mrf_infer. */
+typedef struct {
+    char name[40];
+    int32_t launches;
+    int32_t reserved;
+    double total_ms;
+    double bytes_per_launch;
+    int64_t edges_per_launch;
+} mrf_kernel_time_t;
+int mrf_profile_sweeps(mrf_ctx* ctx, int32_t reps, int32_t include_backward,
+                       mrf_kernel_time_t* out, int32_t max_out, int32_t* n_out, void* stream);
+
 void mrf_destroy(mrf_ctx* ctx);
 const char* mrf_strerror(int code);
 const char* mrf_last_error(void);

@@ -230,7 +230,8 @@ def single_ray_adjoint(lam, g, ellbar):
 
 def bce_logit_grad(L, y) -> np.ndarray:
     """d/dL of mean_v [softplus(L_v) - y_v L_v] (BCE with logits)."""
-    return (1.0 / (1.0 + np.exp(-np.asarray(L, np.float64))) - y) / L.shape[0]
+    L = np.asarray(L, np.float64)
+    return (np.exp(-np.logaddexp(0.0, -L)) - y) / L.shape[0]
 
 
 def bce_loss(L, y) -> float:

@@ -17,7 +17,7 @@ MRF_SCHED_PLAIN, MRF_SCHED_GRAPH = 0, 1
 
 SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backward", "mrf_stats",
            "mrf_export_incidence", "mrf_export_edges", "mrf_set_schedule", "mrf_destroy",
-           "mrf_strerror", "mrf_last_error"]
+           "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps"]
 
 
 class Intrinsics(C.Structure):
@@ -51,6 +51,12 @@ class Stats(C.Structure):
                 ("sweeps_done", C.c_int32), ("have_checkpoints", C.c_int32)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int32), ("reserved", C.c_int32),
+                ("total_ms", C.c_double), ("bytes_per_launch", C.c_double),
+                ("edges_per_launch", C.c_int64)]
+
+
 _lib = None
 
 
@@ -72,6 +78,7 @@ def lib() -> C.CDLL:
         L.mrf_export_incidence.argtypes = [P, P, P, P, P, P, P, P]
         L.mrf_export_edges.argtypes = [P, P, P, P, P, P, P]
         L.mrf_set_schedule.argtypes = [P, I32]
+        L.mrf_profile_sweeps.argtypes = [P, I32, I32, C.POINTER(KernelTime), I32, C.POINTER(I32), P]
         L.mrf_destroy.argtypes = [P]
         L.mrf_destroy.restype = None
         L.mrf_strerror.argtypes = [C.c_int]

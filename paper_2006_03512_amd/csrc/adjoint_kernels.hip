@@ -187,6 +187,7 @@ static void launch_adj_class(const mrf_ctx* c, int k, const float* lam, const fl
 {
     const int64_t n = c->ray_cnt[k];
     if (n <= 0) return;
+    ProfScope ps(c, KID_ADJ0 + k, s);
     hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
                        (const uint32_t*)c->b_ray_list[k].p, n, (const int64_t*)c->b_rowptr.p, lam,
                        (const float*)c->b_g.p, ellbar, lambar, gsum, first);
@@ -293,6 +294,7 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s)
     long long* ghi = (long long*)(glo + kBins);
     hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(64), 0, s, glo, ghi);
     if (c->E > 0) {
+        ProfScope ps(c, KID_SIGMA, s);
         int64_t blocks = (c->E + 255) / 256;
         if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
         hipLaunchKernelGGL(sigma_grad_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_gsum.p,

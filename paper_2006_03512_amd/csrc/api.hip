@@ -40,6 +40,23 @@ void drop_graph(mrf_ctx* c)
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->g_K = c->g_ckpt = -1;
+    c->g_key.clear();
+}
+
+// Everything a captured forward graph bakes in: launch shapes and addresses.
+std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
+{
+    std::vector<uint64_t> k = {(uint64_t)K, (uint64_t)keep, (uint64_t)c->E, (uint64_t)c->R, (uint64_t)c->V,
+                               c->hub.n_hubs, c->hub.n_pieces};
+    for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->ray_cnt[i]);
+    for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->vox_cnt[i]);
+    const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_delta, &c->b_bin, &c->b_g, &c->b_lam, &c->b_ell,
+                                 &c->b_vedge, &c->b_vptr, &c->b_theta, &c->b_L, &c->b_sigma, &c->b_ckpt};
+    for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
+    for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
+    for (const auto& b : c->b_vox_list) k.push_back((uint64_t)(uintptr_t)b.p);
+    for (const auto& b : c->b_hub) k.push_back((uint64_t)(uintptr_t)b.p);
+    return k;
 }
 
 int bits_for(int64_t maxval)
@@ -185,8 +202,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         return fail(MRF_EINVAL, "mrf_build: bad depth window, truncation or table range");
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_build: hipSetDevice");
-    drop_graph(c);
-    c->built = c->inferred = c->have_ckpt = 0;
+    c->built = c->inferred = c->have_ckpt = 0;   // a cached graph is revalidated by mrf_infer
 
     c->scenes_h.clear();
     c->frames_h.clear();
@@ -355,7 +371,8 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
     if (c->schedule == MRF_SCHED_PLAIN) {
         HCK(enqueue_forward(c, sweeps, keep, true, s), "mrf_infer: sweeps");
     } else {
-        if (!c->gexec || c->g_K != sweeps || c->g_ckpt != keep) {
+        std::vector<uint64_t> key = graph_key(c, sweeps, keep);
+        if (!c->gexec || key != c->g_key) {
             drop_graph(c);
             hipGraph_t g = nullptr;
             HCK(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal), "mrf_infer: begin capture");
@@ -370,6 +387,7 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
             }
             c->g_K = sweeps;
             c->g_ckpt = keep;
+            c->g_key = key;
         }
         HCK(hipEventRecord(c->ev_in, s), "mrf_infer: event");
         HCK(hipStreamWaitEvent(c->aux, c->ev_in, 0), "mrf_infer: wait");
@@ -467,6 +485,113 @@ int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, flo
     if (g) HCK(hipMemcpyAsync(g, c->b_g.p, 4 * E, k, s), "export");
     if (lam) HCK(hipMemcpyAsync(lam, c->b_lam.p, 4 * E, k, s), "export");
     if (ell) HCK(hipMemcpyAsync(ell, final_ell(c), 4 * E, k, s), "export");
+    return MRF_OK;
+}
+
+static const char* kid_name(int k)
+{
+    static const char* names[KID_COUNT] = {
+        "voxel_k<16,1>", "voxel_k<64,1>", "voxel_k<64,4>", "voxel_k<64,16>", "hub_sum_k", "hub_carry_k",
+        "hub_piece_k", "ray_k<16,1>", "ray_k<64,1>", "ray_k<64,4>", "ray_k<64,16>", "ray_k<64,32>",
+        "ray_adj_k<16,1>", "ray_adj_k<64,1>", "ray_adj_k<64,4>", "ray_adj_k<64,16>", "ray_adj_k<64,32>",
+        "potentials_k", "sigma_grad_k"};
+    return names[k];
+}
+
+// algorithmic bytes and edges of one launch of kernel k (steady-state sweep)
+static void kid_bytes(const mrf_ctx* c, int k, double* bytes, int64_t* edges)
+{
+    *bytes = 0.0;
+    *edges = 0;
+    if (k >= KID_VOX0 && k <= KID_VOX3) {
+        const int q = k - KID_VOX0;
+        // per edge: vedge 4 + gathered ell 4 + scattered lam 4; per voxel: list 4 + vptr 16 + theta 4
+        *edges = c->vox_cls_edges[q];
+        *bytes = 12.0 * (double)*edges + 24.0 * (double)c->vox_cnt[q];
+    } else if (k == KID_HUB_SUM) {
+        *edges = c->vox_cls_edges[kVoxClasses];
+        *bytes = 8.0 * (double)*edges + 16.0 * c->hub.n_pieces;
+    } else if (k == KID_HUB_PIECE) {
+        *edges = c->vox_cls_edges[kVoxClasses];
+        *bytes = 12.0 * (double)*edges + 32.0 * c->hub.n_pieces;
+    } else if (k == KID_HUB_CARRY) {
+        *bytes = 16.0 * c->hub.n_pieces + 12.0 * c->hub.n_hubs;
+    } else if (k >= KID_RAY0 && k <= KID_RAY4) {
+        const int q = k - KID_RAY0;
+        // per edge: lam 4 + g 4 + ell 4; per ray: list 4 + row_ptr 16
+        *edges = c->ray_cls_edges[q];
+        *bytes = 12.0 * (double)*edges + 20.0 * (double)c->ray_cnt[q];
+    } else if (k >= KID_ADJ0 && k <= KID_ADJ4) {
+        const int q = k - KID_ADJ0;
+        // per edge: lam 4 + g 4 + ellbar 4 + lambar 4 + gsum read 4 + write 4
+        *edges = c->ray_cls_edges[q];
+        *bytes = 24.0 * (double)*edges + 20.0 * (double)c->ray_cnt[q];
+    } else if (k == KID_POT) {
+        *edges = c->E;
+        *bytes = 9.0 * (double)c->E;
+    } else if (k == KID_SIGMA) {
+        *edges = c->E;
+        *bytes = 9.0 * (double)c->E;
+    }
+}
+
+int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_kernel_time_t* out, int32_t max_out,
+                       int32_t* n_out, void* stream)
+{
+    if (!c || !out || !n_out || reps < 1) return fail(MRF_EINVAL, "mrf_profile_sweeps: bad argument");
+    if (!c->inferred) return fail(MRF_ESTATE, "mrf_profile_sweeps: call mrf_infer first");
+    hipStream_t s = (hipStream_t)stream;
+    Profiler P;
+    c->prof = &P;
+    hipError_t e = hipSuccess;
+    const float* theta = (const float*)c->b_theta.p;
+    float* lam = (float*)c->b_lam.p;
+    float* ell = (float*)c->b_ellbar.p;   // scratch output: keeps the inference's messages
+    const float* ell_in = final_ell(c);
+    HCK(launch_copy(ell, ell_in, c->E, s), "mrf_profile_sweeps");
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = launch_voxel_phase(c, theta, ell, lam, nullptr, 0, false, s);
+        if (e == hipSuccess) e = launch_ray_phase(c, lam, ell, false, s);
+    }
+    if (include_backward) {
+        float* lambar = (float*)c->b_lambar.p;
+        float* gsum = (float*)c->b_gsum.p;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            e = launch_ray_adjoint(c, lam, ell, lambar, gsum, r == 0, s);
+            if (e == hipSuccess)
+                e = launch_voxel_phase(c, nullptr, lambar, ell, (float*)c->b_thetabar.p, 2, false, s);
+        }
+        if (e == hipSuccess) e = launch_sigma_grad(c, (float*)c->b_sigpart.p + 4 * kBins, s);
+    }
+    c->prof = nullptr;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        for (hipEvent_t ev : P.pool) hipEventDestroy(ev);
+        return hip_fail(e, "mrf_profile_sweeps");
+    }
+    double tot[KID_COUNT] = {0};
+    int cnt[KID_COUNT] = {0};
+    for (auto& rec : P.recs) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, P.pool[rec.second], P.pool[rec.second + 1]);
+        tot[rec.first] += ms;
+        cnt[rec.first] += 1;
+    }
+    for (hipEvent_t ev : P.pool) hipEventDestroy(ev);
+    int n = 0;
+    for (int k = 0; k < KID_COUNT; ++k) {
+        if (!cnt[k]) continue;
+        if (n < max_out) {
+            mrf_kernel_time_t& o = out[n];
+            memset(&o, 0, sizeof(o));
+            strncpy(o.name, kid_name(k), sizeof(o.name) - 1);
+            o.launches = cnt[k];
+            o.total_ms = tot[k];
+            kid_bytes(c, k, &o.bytes_per_launch, &o.edges_per_launch);
+        }
+        ++n;
+    }
+    *n_out = n < max_out ? n : max_out;
     return MRF_OK;
 }
 

@@ -579,6 +579,22 @@ __global__ void hist_k(const int32_t* __restrict__ counts, int64_t R, const int6
     }
 }
 
+// total edges of the items of one class list (integer atomics: exact)
+__global__ void class_edges_k(const uint32_t* __restrict__ list, int64_t n, const int64_t* __restrict__ ptr,
+                              unsigned long long* __restrict__ out)
+{
+    __shared__ unsigned long long acc;
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint32_t x = list[i];
+        atomicAdd(&acc, (unsigned long long)(ptr[x + 1] - ptr[x]));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && acc) atomicAdd(out, acc);
+}
+
 static hipError_t partition(const uint8_t* cls, int64_t n, uint8_t c, int64_t* pos, void* tmp,
                             size_t tmp_bytes, DevBuf& list, int64_t* count, hipStream_t s)
 {
@@ -700,6 +716,30 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
             return e;
         // the host arrays above are read by the copies: finish before they go away
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    }
+    // edges per work class (for the profiler's byte counts)
+    {
+        if ((e = ensure(c->b_sigpart, 64 * sizeof(double) * 4096)) != hipSuccess) return e;
+        unsigned long long* d = (unsigned long long*)c->b_sigpart.p + 64;
+        const int nc = kRayClasses + kVoxClasses + 1;
+        hipMemsetAsync(d, 0, nc * sizeof(unsigned long long), s);
+        for (int k = 0; k < kRayClasses; ++k)
+            if (c->ray_cnt[k] > 0)
+                hipLaunchKernelGGL(class_edges_k, dim3((unsigned)cdiv(c->ray_cnt[k], 256)), dim3(256), 0, s,
+                                   (const uint32_t*)c->b_ray_list[k].p, c->ray_cnt[k], (const int64_t*)c->b_rowptr.p,
+                                   d + k);
+        for (int k = 0; k <= kVoxClasses; ++k) {
+            const int64_t n = k < kVoxClasses ? c->vox_cnt[k] : (int64_t)c->hub.n_hubs;
+            const uint32_t* L = k < kVoxClasses ? (const uint32_t*)c->b_vox_list[k].p : c->hub.hub_voxel;
+            if (n > 0)
+                hipLaunchKernelGGL(class_edges_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, L, n,
+                                   (const int64_t*)c->b_vptr.p, d + kRayClasses + k);
+        }
+        unsigned long long hh[kRayClasses + kVoxClasses + 1];
+        if ((e = hipMemcpyAsync(hh, d, sizeof(hh), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        for (int k = 0; k < kRayClasses; ++k) c->ray_cls_edges[k] = (int64_t)hh[k];
+        for (int k = 0; k <= kVoxClasses; ++k) c->vox_cls_edges[k] = (int64_t)hh[kRayClasses + k];
     }
     // histograms
     {

@@ -67,6 +67,30 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Kernel launches that the profiler can time individually.
+enum KernelId {
+    KID_VOX0 = 0, KID_VOX1, KID_VOX2, KID_VOX3, KID_HUB_SUM, KID_HUB_CARRY, KID_HUB_PIECE,
+    KID_RAY0, KID_RAY1, KID_RAY2, KID_RAY3, KID_RAY4,
+    KID_ADJ0, KID_ADJ1, KID_ADJ2, KID_ADJ3, KID_ADJ4,
+    KID_POT, KID_SIGMA, KID_COUNT
+};
+
+// HIP events recorded around launches on the stream they run on.
+struct Profiler {
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> recs;   // (kernel id, index of its start event)
+    hipEvent_t next()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            hipEventCreate(&e);
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+
 }  // namespace mrf
 
 struct mrf_ctx {
@@ -95,6 +119,8 @@ struct mrf_ctx {
 
     int64_t ray_cnt[mrf::kRayClasses] = {0};
     int64_t vox_cnt[mrf::kVoxClasses] = {0};
+    int64_t ray_cls_edges[mrf::kRayClasses] = {0};
+    int64_t vox_cls_edges[mrf::kVoxClasses + 1] = {0};   // last entry: hub voxels
     std::vector<int64_t> frame_ray_off;   // plain schedule: rays of frame f at [off[f], off[f+1])
     mrf::HubTables hub;
 
@@ -108,11 +134,31 @@ struct mrf_ctx {
     // graph cache
     hipGraphExec_t gexec = nullptr;
     int g_K = -1, g_ckpt = -1;
+    std::vector<uint64_t> g_key;   // sizes and buffer addresses the captured graph depends on
+
+    mrf::Profiler* prof = nullptr;   // non-null while mrf_profile_sweeps records
 };
 
 namespace mrf {
 
 void set_error(const std::string& msg);
+
+// Records start/stop events around one launch when the context is profiling.
+struct ProfScope {
+    Profiler* p;
+    hipStream_t s;
+    ProfScope(const mrf_ctx* c, int kid, hipStream_t st) : p(c->prof), s(st)
+    {
+        if (p) {
+            p->recs.push_back({kid, p->used});
+            hipEventRecord(p->next(), s);
+        }
+    }
+    ~ProfScope()
+    {
+        if (p) hipEventRecord(p->next(), s);
+    }
+};
 hipError_t ensure(DevBuf& b, size_t bytes);
 
 // every launcher returns hipSuccess or the first error

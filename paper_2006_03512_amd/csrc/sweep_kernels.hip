@@ -111,6 +111,7 @@ hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s)
 hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 {
     if (c->E <= 0) return hipSuccess;
+    ProfScope ps(c, KID_POT, s);
     hipLaunchKernelGGL(potentials_k, dim3(grid_for(c->E)), dim3(256), 0, s, (const float*)c->b_delta.p,
                        (const uint8_t*)c->b_bin.p, c->E, (const float*)c->b_sigma.p, (float*)c->b_g.p);
     return hipGetLastError();
@@ -238,6 +239,7 @@ static void launch_voxel_class(const mrf_ctx* c, int k, const float* base, const
 {
     const int64_t n = c->vox_cnt[k];
     if (n <= 0) return;
+    ProfScope ps(c, KID_VOX0 + k, s);
     hipLaunchKernelGGL((voxel_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
                        (const uint32_t*)c->b_vox_list[k].p, n, (const int64_t*)c->b_vptr.p,
                        (const uint32_t*)c->b_vedge.p, base, in, out, total, mode);
@@ -253,9 +255,18 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, fl
     const HubTables& H = c->hub;
     if (H.n_pieces > 0) {
         const uint32_t* ve = (const uint32_t*)c->b_vedge.p;
-        hipLaunchKernelGGL(hub_sum_k, dim3(nblk(H.n_pieces, 4)), dim3(256), 0, s, H, ve, in);
-        hipLaunchKernelGGL(hub_carry_k, dim3(nblk(H.n_hubs, 64)), dim3(64), 0, s, H, base, total, total_mode);
-        if (out) hipLaunchKernelGGL(hub_piece_k, dim3(nblk(H.n_pieces, 4)), dim3(256), 0, s, H, ve, base, in, out);
+        {
+            ProfScope ps(c, KID_HUB_SUM, s);
+            hipLaunchKernelGGL(hub_sum_k, dim3(nblk(H.n_pieces, 4)), dim3(256), 0, s, H, ve, in);
+        }
+        {
+            ProfScope ps(c, KID_HUB_CARRY, s);
+            hipLaunchKernelGGL(hub_carry_k, dim3(nblk(H.n_hubs, 64)), dim3(64), 0, s, H, base, total, total_mode);
+        }
+        if (out) {
+            ProfScope ps(c, KID_HUB_PIECE, s);
+            hipLaunchKernelGGL(hub_piece_k, dim3(nblk(H.n_pieces, 4)), dim3(256), 0, s, H, ve, base, in, out);
+        }
     }
     return hipGetLastError();
 }
@@ -332,6 +343,7 @@ static void launch_ray_class(const mrf_ctx* c, int k, int64_t off, int64_t n, co
                              hipStream_t s)
 {
     if (n <= 0) return;
+    ProfScope ps(c, KID_RAY0 + k, s);
     hipLaunchKernelGGL((ray_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
                        (const uint32_t*)c->b_ray_list[k].p + off, n, (const int64_t*)c->b_rowptr.p, lam,
                        (const float*)c->b_g.p, ell);

@@ -73,8 +73,9 @@ class RayMRF:
         return self._h
 
     # ------------------------------------------------------------------
-    def build(self, scenes, keep_chords: bool = False, stream=None):
-        """Build the ray MRF of one scene or a list of scenes (batched)."""
+    def upload(self, scenes):
+        """Copy depth frames and poses of one scene or a batch of scenes to the
+        device; they stay resident for later (re)builds."""
         if not isinstance(scenes, (list, tuple)):
             scenes = [scenes]
         p0 = scenes[0].params
@@ -97,15 +98,27 @@ class RayMRF:
             sc.grid = _lib.Grid(g.nx, g.ny, g.nz, 0, g.voxel, (C.c_double * 3)(*g.origin))
             self.voxel_base.append(vb)
             vb += g.n_voxels
+        self._keep = keep
+        self._arr = arr
+        self._params = p0
+
+    def build_resident(self, keep_chords: bool = False, stream=None):
+        """(Re)build the ray MRF from the uploaded frames."""
+        p0 = self._params
         bp = _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
                               p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0)
         with torch.cuda.device(self.device):
-            check(self._L.mrf_build(self._h, arr, len(scenes), C.byref(bp), stream_handle(stream)),
-                  "mrf_build")
+            check(self._L.mrf_build(self._h, self._arr, len(self._arr), C.byref(bp),
+                                    stream_handle(stream)), "mrf_build")
         st = self.stats()
         self.n_voxels, self.n_edges, self.n_rays = st.n_voxels, st.n_edges, st.n_rays
         self.keep_chords = keep_chords
         return st
+
+    def build(self, scenes, keep_chords: bool = False, stream=None):
+        """Upload and build the ray MRF of one scene or a list of scenes (batched)."""
+        self.upload(scenes)
+        return self.build_resident(keep_chords, stream)
 
     def stats(self) -> GraphStats:
         st = _lib.Stats()
@@ -174,6 +187,22 @@ class RayMRF:
         check(self._L.mrf_export_edges(self._h, ptr(out["delta"]), ptr(out["bin"]), ptr(out.get("g")),
                                        ptr(out.get("lam")), ptr(out.get("ell")), stream_handle(stream)),
               "mrf_export_edges")
+        return out
+
+
+    def profile_sweeps(self, reps: int = 3, include_backward: bool = True, stream=None):
+        """Per-kernel HIP-event timings of `reps` eager sweeps (diagnostic)."""
+        arr = (_lib.KernelTime * 64)()
+        n = C.c_int32()
+        check(self._L.mrf_profile_sweeps(self._h, int(reps), 1 if include_backward else 0, arr, 64,
+                                         C.byref(n), stream_handle(stream)), "mrf_profile_sweeps")
+        out = []
+        for i in range(n.value):
+            k = arr[i]
+            out.append({"name": k.name.decode(), "launches": k.launches,
+                        "avg_ms": k.total_ms / max(k.launches, 1),
+                        "bytes_per_launch": k.bytes_per_launch,
+                        "edges_per_launch": k.edges_per_launch})
         return out
 
 

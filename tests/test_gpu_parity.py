@@ -70,6 +70,8 @@ def test_incidence_bit_exact(oracle, RayMRF, name):
 
 def test_incidence_multi_scene_bit_exact(oracle, RayMRF):
     scs = [S.make_c1(), S.make_fd(), S.random_scene(4)]
+    for s in scs[1:]:
+        s.params = scs[0].params          # one set of build parameters per batch
     G = oracle.build_graph(scs)
     m = _gpu(RayMRF, scs)
     inc = {k: v.cpu().numpy() for k, v in m.export_incidence().items()}
