@@ -37,6 +37,8 @@ WORKLOADS = {
     "c2": ("one 640x480 frame in a 5x5x3 m room, 100x100x60 grid at 0.05 m, 10 sweeps forward",
            10, False),
     "c1": ("one 64x48 frame, 64^3 grid at 0.05 m, 5 sweeps forward", 5, False),
+    "c5": ("8 independent rooms (grids 64^3 .. 400x400x150 at 0.05 .. 0.0125 m) batched in one "
+           "launch sequence, 10 sweeps forward + reverse pass; frame counts scaled by --c5-scale", 10, True),
 }
 
 
@@ -44,11 +46,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_scene(name, frames=None):
+def make_scene(name, frames=None, c5_scale=0.4):
+    """List of scenes of the workload (one scene except c5)."""
     from paper_2006_03512_amd import scenes
     if name in ("c3", "c4"):
-        return getattr(scenes, f"make_{name}")(n_frames=frames or 30)
-    return scenes.make(name)
+        return [getattr(scenes, f"make_{name}")(n_frames=frames or 30)]
+    if name == "c5":
+        return scenes.make_c5(frame_scale=c5_scale)
+    return [scenes.make(name)]
 
 
 def cpu_baseline(name, sc, sweeps, backward, row_frac):
@@ -94,6 +99,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=float, default=0.25, help="fraction of frame-0 rows the oracle runs on")
+    ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,15 +116,19 @@ def main():
     torch.cuda.set_device(0)
     desc, K, backward = WORKLOADS[args.workload]
     t = time.perf_counter()
-    sc = make_scene(args.workload, args.frames)
-    log(f"scene {args.workload}: {sc.n_frames} frames, grid {sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} "
+    scs = make_scene(args.workload, args.frames, args.c5_scale)
+    sc = scs[0]
+    for other in scs[1:]:
+        other.params, other.sigma_table = sc.params, sc.sigma_table
+    n_frames = sum(x.n_frames for x in scs)
+    log(f"scene {args.workload}: {len(scs)} scene(s), {n_frames} frames "
         f"({time.perf_counter() - t:.1f} s to generate)")
 
     m = RayMRF(0)
-    m.upload(sc)
-    theta = torch.from_numpy(sc.prior_logit()).cuda()
+    m.upload(scs)
+    theta = torch.from_numpy(np.concatenate([x.prior_logit() for x in scs])).cuda()
     sigma = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
-    y = torch.from_numpy(sc.occupancy()).cuda() if backward else None
+    y = torch.from_numpy(np.concatenate([x.occupancy() for x in scs])).cuda() if backward else None
 
     def step():
         m.build_resident()
@@ -195,11 +205,15 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f64 traversal)", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "frames": sc.n_frames,
-                   "grid": [sc.grid.nx, sc.grid.ny, sc.grid.nz], "voxel_m": sc.grid.voxel,
+        "config": {"workload": f"{args.workload}: {desc}", "scenes": len(scs), "frames": n_frames,
+                   "grid": [[x.grid.nx, x.grid.ny, x.grid.nz] for x in scs],
+                   "voxel_m": [x.grid.voxel for x in scs],
                    "sweeps": K, "rays": st.n_rays, "edges": E, "voxels": st.n_voxels,
+                   "edge_slots": st.n_slots, "tiles": st.n_tiles,
                    "touched_voxels": st.n_touched_voxels, "max_ray_len": st.max_ray_len,
-                   "max_voxel_degree": st.max_voxel_degree, "parallelism": "single GPU"},
+                   "max_voxel_degree": st.max_voxel_degree, "parallelism": "single GPU",
+                   "ray_len_log2_hist": st.ray_len_hist[:12],
+                   "voxel_degree_log2_hist": st.voxel_degree_hist[:20]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "breakdown_ms": {"build": round(build_ms, 2), "forward_graph": round(fwd_graph_ms, 2),

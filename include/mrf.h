@@ -98,6 +98,8 @@ typedef struct {
     int64_t voxel_degree_hist[24];  /* touched voxels with degree in [2^i, 2^(i+1)) */
     double fwd_bytes_per_sweep;     /* algorithmic HBM bytes of one forward sweep */
     int32_t sweeps_done, have_checkpoints;
+    int64_t n_slots;                /* edge slots in memory: edges plus tile padding */
+    int64_t n_tiles;                /* 4x4-pixel ray tiles */
 } mrf_stats_t;
 
 /* Create an empty context on the current HIP device.  *out receives it. */
@@ -144,10 +146,14 @@ int mrf_backward(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
 /* Sizes and histograms of the built graph (host struct). */
 int mrf_stats(const mrf_ctx* ctx, mrf_stats_t* out);
 
-/* Copy the incidence out in canonical edge order (for parity checks):
- * row_ptr (R+1 int64), col (E int32 voxel ids), t_in / t_out (E f64 chord
- * entry/exit z-depths; only if built with keep_chords, else must be NULL),
- * vptr (V+1 int64), vedge (E uint32 edge ids).  Any pointer may be NULL. */
+/* Copy the incidence out in canonical order (for parity checks): edge id
+ * = row_ptr[ray] + step along the ray, voxel id = linear id.  row_ptr (R+1
+ * int64), col (E int32 voxel ids), t_in / t_out (E f64 chord entry/exit
+ * z-depths; only if built with keep_chords, else must be NULL), vptr (V+1
+ * int64), vedge (E uint32 edge ids ascending inside each voxel).  Any pointer
+ * may be NULL.  The library stores edges in its own tiled order; producing
+ * the canonical vedge re-sorts on the device and allocates 20 E bytes of
+ * temporaries kept by the context. */
 int mrf_export_incidence(const mrf_ctx* ctx, int64_t* row_ptr, int32_t* col,
                          double* t_in, double* t_out, int64_t* vptr, uint32_t* vedge,
                          void* stream);

@@ -48,7 +48,8 @@ class Stats(C.Structure):
                 ("n_touched_voxels", C.c_int64), ("max_ray_len", C.c_int64),
                 ("max_voxel_degree", C.c_int64), ("ray_len_hist", C.c_int64 * 16),
                 ("voxel_degree_hist", C.c_int64 * 24), ("fwd_bytes_per_sweep", C.c_double),
-                ("sweeps_done", C.c_int32), ("have_checkpoints", C.c_int32)]
+                ("sweeps_done", C.c_int32), ("have_checkpoints", C.c_int32),
+                ("n_slots", C.c_int64), ("n_tiles", C.c_int64)]
 
 
 class KernelTime(C.Structure):

@@ -26,157 +26,167 @@ namespace mrf {
 
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Blocked like the forward ray kernel: lane l holds steps [l IPL, (l+1) IPL);
+// every recurrence runs sequentially inside the lane after one group scan of
+// the lane aggregates.
 template <int G, int IPL>
-__global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ rays, int64_t n,
-                                                 const int64_t* __restrict__ row_ptr, const float* __restrict__ lam,
-                                                 const float* __restrict__ g, const float* __restrict__ ellbar,
-                                                 float* __restrict__ lambar, float* __restrict__ gsum, int first)
+__global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                 const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
+                                                 const float* __restrict__ lam, const float* __restrict__ g,
+                                                 const float* __restrict__ ellbar, float* __restrict__ lambar,
+                                                 float* __restrict__ gsum, int first)
 {
-    const int64_t gid = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
-    if (gid >= n) return;
-    const int l = glane<G>();
-    const uint32_t r = rays[gid];
-    const int64_t s = row_ptr[r];
-    const int m = (int)(row_ptr[r + 1] - s);
+    static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
+    int64_t s;
+    int m;
+    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
+    const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
 
-    float al[IPL], be[IPL], gg[IPL], eb[IPL], P[IPL], S[IPL], Q[IPL];
+    float al[IPL], be[IPL], gg[IPL], P[IPL], S[IPL], Q[IPL];
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const int i = k * G + l;
+    for (int j = 0; j < IPL; ++j) {
+        const int i = i0 + j;
         if (i < m) {
-            const float x = lam[s + i];
+            const float x = lam[s + kTile * i];
             const float sp = softplus(x);
-            al[k] = -sp;
-            be[k] = x - sp;
-            gg[k] = g[s + i];
-            eb[k] = ellbar[s + i];
+            al[j] = -sp;
+            be[j] = x - sp;
+            gg[j] = g[s + kTile * i];
         } else {
-            al[k] = 0.0f;
-            be[k] = MRF_NINF;
-            gg[k] = 0.0f;
-            eb[k] = 0.0f;
+            al[j] = 0.0f;
+            be[j] = MRF_NINF;
+            gg[j] = 0.0f;
         }
     }
-    // ---- forward recomputation (same scans as the ray phase)
-    float cp = 0.0f;
+    // ---- forward recomputation (as in the ray phase)
+    {
+        float a = 0.0f;
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const float incl = gscan_add<G>(al[k]) + cp;
-        const float up = gshfl_up<G>(incl, 1);
-        P[k] = l == 0 ? cp : up;
-        cp = gbcast<G>(incl, G - 1);
-    }
-    float cs = MRF_NINF;
+        for (int j = 0; j < IPL; ++j) a += al[j];
+        float p = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const float incl = lse(cs, gscan_lse<G>(be[k] + gg[k] + P[k]));
-        const float up = gshfl_up<G>(incl, 1);
-        S[k] = l == 0 ? cs : up;
-        cs = gbcast<G>(incl, G - 1);
-    }
-    LMap cq{0.0f, MRF_NINF};
+        for (int j = 0; j < IPL; ++j) {
+            P[j] = p;
+            p += al[j];
+        }
+        float w = MRF_NINF;
 #pragma unroll
-    for (int k = IPL - 1; k >= 0; --k) {
-        LMap mp{al[k], be[k] + gg[k]};
-        LMap incl = lmap_compose(grscan_lmap<G>(mp), cq);
-        const float dn = gshfl_down<G>(incl.c, 1);
-        Q[k] = l == G - 1 ? cq.c : dn;
-        cq.a = gbcast<G>(incl.a, 0);
-        cq.c = gbcast<G>(incl.c, 0);
+        for (int j = 0; j < IPL; ++j) w = lse(w, be[j] + gg[j] + P[j]);
+        float sc = dexcl<G>(dscan<G, OpLse>(w), MRF_NINF);
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            S[j] = sc;
+            sc = lse(sc, be[j] + gg[j] + P[j]);
+        }
+        LMap lm = lmap_id();
+#pragma unroll
+        for (int j = IPL - 1; j >= 0; --j) lm = lmap_compose(LMap{al[j], be[j] + gg[j]}, lm);
+        const LMap right = drscan_lmap<G>(lm);
+        float q = drexcl<G>(right.c, MRF_NINF);
+#pragma unroll
+        for (int j = IPL - 1; j >= 0; --j) {
+            Q[j] = q;
+            q = lse(be[j] + gg[j], al[j] + q);
+        }
     }
     // ---- direct partials of ell_i = M1_i - M0_i
-    float Fb[IPL], Bb[IPL], gb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
+    float Fd[IPL], Bb[IPL], gb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const float A = gg[k] + P[k];
-        const float B = P[k] + Q[k];
-        const float m1 = lse(S[k], A);
-        const float m0 = lse(S[k], B);
-        const bool ok = (k * G + l) < m;
-        const float e = ok ? eb[k] : 0.0f;
+    for (int j = 0; j < IPL; ++j) {
+        const bool ok = i0 + j < m;
+        const float e = ok ? ellbar[s + kTile * (i0 + j)] : 0.0f;
+        const float A = gg[j] + P[j];
+        const float B = P[j] + Q[j];
+        const float m1 = lse(S[j], A);
+        const float m0 = lse(S[j], B);
         // exp(-inf - finite) = 0 covers S_0 = -inf and Q_{N-1} = -inf
-        Fb[k] = ok ? e * (__expf(S[k] - m1) - __expf(S[k] - m0)) : 0.0f;
+        Fd[j] = ok ? e * (__expf(S[j] - m1) - __expf(S[j] - m0)) : 0.0f;
         const float Ab = ok ? e * __expf(A - m1) : 0.0f;
-        Bb[k] = ok ? -e * __expf(B - m0) : 0.0f;
-        gb[k] = Ab;
-        Pb[k] = Ab + Bb[k];
-        lab[k] = 0.0f;
-        lbb[k] = 0.0f;
+        Bb[j] = ok ? -e * __expf(B - m0) : 0.0f;
+        gb[j] = Ab;
+        Pb[j] = Ab + Bb[j];
+        lab[j] = 0.0f;
+        lbb[j] = 0.0f;
     }
-    // ---- Q adjoint: forward affine scan Tb_i = Bb_i + rho_{i-1} Tb_{i-1}
+    // ---- Q adjoint: Tb_i = Bb_i + rho_{i-1} Tb_{i-1} (left to right)
     {
-        AMap carry{1.0f, 0.0f};
-        float qcarry = MRF_NINF;   // Q of the previous chunk's last element
+        const float qlast_prev_lane = dexcl<G>(Q[IPL - 1], MRF_NINF);
+        float rho[IPL], kap[IPL];
+        AMap lm = amap_id();
 #pragma unroll
-        for (int k = 0; k < IPL; ++k) {
-            const int i = k * G + l;
-            const float qup = gshfl_up<G>(Q[k], 1);
-            const float qprev = l == 0 ? qcarry : qup;   // Q_{i-1}
-            float rho = 0.0f, kap = 0.0f;
+        for (int j = 0; j < IPL; ++j) {
+            const int i = i0 + j;
+            const float qprev = j == 0 ? qlast_prev_lane : Q[j - 1];   // Q_{i-1}
+            rho[j] = 0.0f;
+            kap[j] = 0.0f;
             if (i >= 1 && i < m) {
-                rho = __expf(al[k] + Q[k] - qprev);
-                kap = __expf(be[k] + gg[k] - qprev);
+                rho[j] = __expf(al[j] + Q[j] - qprev);
+                kap[j] = __expf(be[j] + gg[j] - qprev);
             }
-            AMap mp{rho, Bb[k]};
-            AMap incl = amap_then(carry, gscan_amap<G>(mp));
-            const float up = gshfl_up<G>(incl.b, 1);
-            const float tprev = l == 0 ? carry.b : up;   // Tb_{i-1}
+            lm = amap_then(lm, AMap{rho[j], Bb[j]});
+        }
+        const AMap incl = dscan_amap<G>(lm);
+        float tb = dexcl<G>(incl.b, 0.0f);   // Tb_{i0-1}: every earlier lane's maps applied to 0
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            const int i = i0 + j;
             if (i >= 1 && i < m) {
-                const float tk = tprev * kap;
-                lbb[k] += tk;
-                gb[k] += tk;
-                lab[k] += tprev * rho;
+                const float tk = tb * kap[j];
+                lbb[j] += tk;
+                gb[j] += tk;
+                lab[j] += tb * rho[j];
             }
-            carry.m = gbcast<G>(incl.m, G - 1);
-            carry.b = gbcast<G>(incl.b, G - 1);
-            qcarry = gbcast<G>(Q[k], G - 1);
+            tb = rho[j] * tb + Bb[j];
         }
     }
-    // ---- S adjoint: backward affine scan Fb_i = Sbar_i + r_i Fb_{i+1}
+    // ---- S adjoint: Fb_i = Sbar_i + r_i Fb_{i+1} (right to left)
     {
-        AMap carry{1.0f, 0.0f};
-        float scarry = MRF_NINF;   // S of the next chunk's first element
+        const float sfirst_next_lane = drexcl<G>(S[0], MRF_NINF);
+        float rr[IPL], ww[IPL];
+        AMap lm = amap_id();
 #pragma unroll
-        for (int k = IPL - 1; k >= 0; --k) {
-            const int i = k * G + l;
-            const float sdn = gshfl_down<G>(S[k], 1);
-            const float snext = l == G - 1 ? scarry : sdn;   // S_{i+1}
-            float rr = 0.0f, ww = 0.0f;
+        for (int j = IPL - 1; j >= 0; --j) {
+            const int i = i0 + j;
+            const float snext = j == IPL - 1 ? sfirst_next_lane : S[j + 1];   // S_{i+1}
+            rr[j] = 0.0f;
+            ww[j] = 0.0f;
             if (i + 1 < m) {
-                rr = __expf(S[k] - snext);
-                ww = __expf(be[k] + gg[k] + P[k] - snext);
+                rr[j] = __expf(S[j] - snext);
+                ww[j] = __expf(be[j] + gg[j] + P[j] - snext);
             }
-            AMap mp{rr, Fb[k]};
-            AMap incl = amap_then(carry, grscan_amap<G>(mp));
-            const float dn = gshfl_down<G>(incl.b, 1);
-            const float fnext = l == G - 1 ? carry.b : dn;   // Fb_{i+1}
+            lm = amap_then(lm, AMap{rr[j], Fd[j]});
+        }
+        const AMap incl = drscan_amap<G>(lm);
+        float fb = drexcl<G>(incl.b, 0.0f);   // Fb_{i0+IPL}
+#pragma unroll
+        for (int j = IPL - 1; j >= 0; --j) {
+            const int i = i0 + j;
             if (i + 1 < m) {
-                const float wb = fnext * ww;
-                lbb[k] += wb;
-                gb[k] += wb;
-                Pb[k] += wb;
+                const float wb = fb * ww[j];
+                lbb[j] += wb;
+                gb[j] += wb;
+                Pb[j] += wb;
             }
-            carry.m = gbcast<G>(incl.m, 0);
-            carry.b = gbcast<G>(incl.b, 0);
-            scarry = gbcast<G>(S[k], 0);
+            fb = rr[j] * fb + Fd[j];
         }
     }
     // ---- P adjoint: d/d log mu_k(0) += sum_{i>k} Pbar_i, then d/d lambda
     {
-        float sc = 0.0f;
+        float a = 0.0f;
 #pragma unroll
-        for (int k = IPL - 1; k >= 0; --k) {
-            const float incl = grscan_add<G>(Pb[k]) + sc;
-            const float dn = gshfl_down<G>(incl, 1);
-            const float suf = l == G - 1 ? sc : dn;
-            sc = gbcast<G>(incl, 0);
-            const int i = k * G + l;
+        for (int j = 0; j < IPL; ++j) a += Pb[j];
+        float sc = drexcl<G>(drscan<G, OpAdd>(a), 0.0f);
+#pragma unroll
+        for (int j = IPL - 1; j >= 0; --j) {
+            const int i = i0 + j;
             if (i < m) {
-                const float lb = lab[k] + suf;
-                const float a = __expf(al[k]), b = __expf(be[k]);
-                lambar[s + i] = -b * lb + a * lbb[k];
-                gsum[s + i] = first ? gb[k] : gsum[s + i] + gb[k];
+                const float lb = lab[j] + sc;
+                const float aa = __expf(al[j]), bb = __expf(be[j]);
+                const int64_t at = s + kTile * i;
+                lambar[at] = -bb * lb + aa * lbb[j];
+                gsum[at] = first ? gb[j] : gsum[at] + gb[j];
             }
+            sc += Pb[j];
         }
     }
 }
@@ -188,9 +198,9 @@ static void launch_adj_class(const mrf_ctx* c, int k, const float* lam, const fl
     const int64_t n = c->ray_cnt[k];
     if (n <= 0) return;
     ProfScope ps(c, KID_ADJ0 + k, s);
-    hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
-                       (const uint32_t*)c->b_ray_list[k].p, n, (const int64_t*)c->b_rowptr.p, lam,
-                       (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+    hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+                       (const uint32_t*)c->b_ray_list[k].p, n, (const TileDev*)c->b_tiles.p,
+                       (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ellbar, lambar, gsum, first);
 }
 
 hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
@@ -198,9 +208,17 @@ hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar,
 {
     launch_adj_class<16, 1>(c, 0, lam, ellbar, lambar, gsum, first, s);
     launch_adj_class<64, 1>(c, 1, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 4>(c, 2, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 16>(c, 3, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 32>(c, 4, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 2>(c, 2, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 3>(c, 3, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 4>(c, 4, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 5>(c, 5, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 6>(c, 6, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 8>(c, 7, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 10>(c, 8, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 12>(c, 9, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 16>(c, 10, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 24>(c, 11, lam, ellbar, lambar, gsum, first, s);
+    launch_adj_class<64, 32>(c, 12, lam, ellbar, lambar, gsum, first, s);
     return hipGetLastError();
 }
 
@@ -241,8 +259,9 @@ __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gs
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     for (int64_t ch = wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
         const int64_t e = ch * 64 + lane;
-        const bool valid = e < E;
-        const int b = valid ? (int)bin[e] : -1;
+        const int braw = e < E ? (int)bin[e] : 255;
+        const bool valid = braw < kBins;   // padding slots carry bin 255
+        const int b = valid ? braw : -1;
         double x = 0.0;
         if (valid) {
             const double d = (double)delta[e];
@@ -293,12 +312,12 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s)
     unsigned long long* glo = (unsigned long long*)c->b_sigpart.p;
     long long* ghi = (long long*)(glo + kBins);
     hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(64), 0, s, glo, ghi);
-    if (c->E > 0) {
+    if (c->S > 0) {
         ProfScope ps(c, KID_SIGMA, s);
-        int64_t blocks = (c->E + 255) / 256;
+        int64_t blocks = (c->S + 255) / 256;
         if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
         hipLaunchKernelGGL(sigma_grad_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_gsum.p,
-                           (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p, c->E,
+                           (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p, c->S,
                            (const float*)c->b_sigma.p, glo, ghi);
     }
     hipLaunchKernelGGL(sigma_final_k, dim3(1), dim3(64), 0, s, (const unsigned long long*)glo, (const long long*)ghi,

@@ -47,15 +47,16 @@ void drop_graph(mrf_ctx* c)
 std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
 {
     std::vector<uint64_t> k = {(uint64_t)K, (uint64_t)keep, (uint64_t)c->E, (uint64_t)c->R, (uint64_t)c->V,
-                               c->hub.n_hubs, c->hub.n_pieces};
+                               (uint64_t)c->Vk, (uint64_t)c->S, (uint64_t)c->T};
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->ray_cnt[i]);
     for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->vox_cnt[i]);
     const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_delta, &c->b_bin, &c->b_g, &c->b_lam, &c->b_ell,
-                                 &c->b_vedge, &c->b_vptr, &c->b_theta, &c->b_L, &c->b_sigma, &c->b_ckpt};
+                                 &c->b_vedge, &c->b_vptr, &c->b_theta, &c->b_L, &c->b_sigma, &c->b_ckpt,
+                                 &c->b_tiles, &c->b_counts};
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
     for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
     for (const auto& b : c->b_vox_list) k.push_back((uint64_t)(uintptr_t)b.p);
-    for (const auto& b : c->b_hub) k.push_back((uint64_t)(uintptr_t)b.p);
+    for (const auto& b : c->b_vox_ext) k.push_back((uint64_t)(uintptr_t)b.p);
     return k;
 }
 
@@ -93,7 +94,7 @@ hipError_t ensure(DevBuf& b, size_t bytes)
 
 static float* ckpt_slot(mrf_ctx* c, int k)   // ell after sweep k+1 (k = 0..K-1)
 {
-    return (float*)c->b_ckpt.p + (size_t)k * (size_t)c->E;
+    return (float*)c->b_ckpt.p + (size_t)k * (size_t)c->S;
 }
 
 // Everything mrf_infer enqueues after the parameter copies; capturable.
@@ -117,7 +118,7 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
 static const float* final_ell(const mrf_ctx* c)
 {
     if (!c->inferred) return nullptr;
-    return c->have_ckpt ? (const float*)c->b_ckpt.p + (size_t)(c->K - 1) * (size_t)c->E : (const float*)c->b_ell.p;
+    return c->have_ckpt ? (const float*)c->b_ckpt.p + (size_t)(c->K - 1) * (size_t)c->S : (const float*)c->b_ell.p;
 }
 
 }  // namespace mrf
@@ -175,11 +176,11 @@ void mrf_destroy(mrf_ctx* c)
                      &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
                      &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_ckpt,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
-                     &c->b_misc, &c->b_frame_list};
+                     &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
     for (DevBuf* b : all) free_buf(*b);
     for (auto& b : c->b_ray_list) free_buf(b);
     for (auto& b : c->b_vox_list) free_buf(b);
-    for (auto& b : c->b_hub) free_buf(b);
+    for (auto& b : c->b_vox_ext) free_buf(b);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->aux) hipStreamDestroy(c->aux);
@@ -207,7 +208,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->scenes_h.clear();
     c->frames_h.clear();
     c->n_scenes = n_scenes;
-    int64_t R = 0, V = 0;
+    int64_t R = 0, V = 0, Vk = 0, Tn = 0;
     int max_hw = 0;
     for (int i = 0; i < n_scenes; ++i) {
         const mrf_scene& sc = scenes[i];
@@ -230,26 +231,35 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         for (int a = 0; a < 3; ++a) d.o[a] = sc.grid.origin[a];
         d.voxel_base = V;
         d.ray_base = R;
+        for (int a = 0; a < 3; ++a) d.nb[a] = (d.n[a] + kBrick - 1) / kBrick;
+        d.key_base = Vk;
+        Vk += (int64_t)d.nb[0] * d.nb[1] * d.nb[2] * kBrick * kBrick * kBrick;
         const int64_t hw = (int64_t)d.W * d.H;
         if (hw > (int64_t(1) << 30)) return fail(MRF_ERANGE, "mrf_build: image too large");
         if (hw > max_hw) max_hw = (int)hw;
+        const int ntx = (d.W + kTileW - 1) / kTileW, nty = (d.H + kTileW - 1) / kTileW;
         for (int f = 0; f < sc.n_frames; ++f) {
             FrameDev fr{};
             fr.depth = sc.depth + (size_t)f * hw;
             fr.T = sc.T_wc + (size_t)f * 16;
             fr.scene = i;
+            fr.ntx = ntx;
             fr.ray_base = R + (int64_t)f * hw;
+            fr.tile_base = Tn + (int64_t)f * ntx * nty;
             c->frames_h.push_back(fr);
         }
+        Tn += (int64_t)ntx * nty * sc.n_frames;
         R += hw * sc.n_frames;
         V += (int64_t)sc.grid.nx * sc.grid.ny * sc.grid.nz;
         c->scenes_h.push_back(d);
     }
     if (c->frames_h.size() > 65535) return fail(MRF_EINVAL, "mrf_build: more than 65535 frames");
-    if (V >= (int64_t(1) << 31) || R >= (int64_t(1) << 32))
-        return fail(MRF_ERANGE, "mrf_build: too many voxels (>= 2^31) or rays (>= 2^32)");
+    if (V >= (int64_t(1) << 31) || Vk >= (int64_t(1) << 32) - 1 || R >= (int64_t(1) << 31))
+        return fail(MRF_ERANGE, "mrf_build: too many voxels or rays (>= 2^31)");
     c->R = R;
     c->V = V;
+    c->Vk = Vk;
+    c->T = Tn;
     c->n_frames = (int)c->frames_h.size();
     c->max_hw = max_hw;
     c->bp.z_min = p->z_min;
@@ -281,13 +291,31 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(hipMemcpyAsync(&E, (int64_t*)c->b_rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s),
         "mrf_build: read E");
     HCK(hipStreamSynchronize(s), "mrf_build: sync");
-    if (E >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_build: 2^32 or more edges");
     c->E = E;
 
-    const size_t e4 = sizeof(float) * (size_t)(E > 0 ? E : 1);
+    // tiles of 4x4 rays, slot bases = exclusive scan of 16 * longest ray
+    const int64_t T = c->T;
+    HCK(ensure(c->b_tiles, sizeof(TileDev) * (size_t)T), "mrf_build: alloc tiles");
+    HCK(ensure(c->b_tbase, sizeof(int64_t) * (size_t)(T + 1)), "mrf_build: alloc tile bases");
+    HCK(ensure(c->b_tmp64, sizeof(int32_t) * (size_t)(T + 1)), "mrf_build: alloc");
+    const size_t tbytes = scan_tmp_bytes(T + 1);
+    HCK(ensure(c->b_misc, tbytes > sbytes ? tbytes : sbytes), "mrf_build: alloc scan");
+    HCK(launch_tiles(c, (int32_t*)c->b_tmp64.p, s), "mrf_build: tiles");
+    HCK(scan_exclusive_i32((const int32_t*)c->b_tmp64.p, (int64_t*)c->b_tbase.p, T, c->b_misc.p, c->b_misc.cap, s),
+        "mrf_build: tile scan");
+    HCK(launch_tile_bases(c, s), "mrf_build: tile bases");
+    int64_t S = 0;
+    HCK(hipMemcpyAsync(&S, (int64_t*)c->b_tbase.p + T, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+        "mrf_build: read S");
+    HCK(hipStreamSynchronize(s), "mrf_build: sync");
+    if (S >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_build: 2^32 or more edge slots");
+    c->S = S;
+
+    const size_t e1 = (size_t)(S > 0 ? S : 1);
+    const size_t e4 = sizeof(float) * e1;
     HCK(ensure(c->b_col, e4), "mrf_build: alloc col");
     HCK(ensure(c->b_delta, e4), "mrf_build: alloc delta");
-    HCK(ensure(c->b_bin, (size_t)(E > 0 ? E : 1)), "mrf_build: alloc bin");
+    HCK(ensure(c->b_bin, e1), "mrf_build: alloc bin");
     HCK(ensure(c->b_g, e4), "mrf_build: alloc g");
     HCK(ensure(c->b_lam, e4), "mrf_build: alloc lam");
     HCK(ensure(c->b_ell, e4), "mrf_build: alloc ell");
@@ -299,7 +327,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         HCK(ensure(c->b_tin, 2 * e4), "mrf_build: alloc t_in");
         HCK(ensure(c->b_tout, 2 * e4), "mrf_build: alloc t_out");
     }
-    HCK(ensure(c->b_vptr, sizeof(int64_t) * (size_t)(V + 1)), "mrf_build: alloc vptr");
+    HCK(ensure(c->b_vptr, sizeof(int64_t) * (size_t)(Vk + 1)), "mrf_build: alloc vptr");
     const size_t vb = sizeof(float) * (size_t)V;
     HCK(ensure(c->b_theta, vb), "mrf_build: alloc theta");
     HCK(ensure(c->b_L, vb), "mrf_build: alloc L");
@@ -307,23 +335,28 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
     HCK(ensure(c->b_sigpart, sizeof(double) * 4 * kBins), "mrf_build: alloc sigma partials");
 
+    // padding slots: no voxel (col -1), no bin (255), sort key past every voxel
+    HCK(hipMemsetAsync(c->b_col.p, 0xFF, e4, s), "mrf_build: init");
+    HCK(hipMemsetAsync(c->b_bin.p, 0xFF, e1, s), "mrf_build: init");
+    HCK(hipMemsetAsync(c->b_delta.p, 0, e4, s), "mrf_build: init");
+    HCK(launch_fill_u32((uint32_t*)c->b_g.p, (uint32_t)Vk, S, s), "mrf_build: init");
     HCK(launch_trace_emit(c, s), "mrf_build: trace emit");
 
-    // voxel -> ray incidence by a stable LSD radix sort of (voxel id, edge id);
-    // the message buffers are free during build and hold the sort's ping-pong
-    const int64_t nh = (int64_t)radix_hist_entries(E);
+    // voxel -> ray incidence by a stable LSD radix sort of (brick-major voxel key,
+    // slot); the emit pass left the keys in the potentials buffer, and the
+    // message buffers are free during build and hold the sort's ping-pong
+    const int64_t nh = (int64_t)radix_hist_entries(S);
     HCK(ensure(c->b_tmp64, sizeof(int64_t) * (size_t)(nh + 1) + sizeof(int32_t) * (size_t)nh),
         "mrf_build: alloc sort tables");
     int64_t* offs = (int64_t*)c->b_tmp64.p;
     int32_t* hist = (int32_t*)(offs + nh + 1);
     const size_t sb2 = scan_tmp_bytes(nh + 1);
-    HCK(ensure(c->b_misc, sb2 > sbytes ? sb2 : sbytes), "mrf_build: alloc scan");
-    HCK(radix_sort_pairs((const uint32_t*)c->b_col.p, (uint32_t*)c->b_lam.p, (uint32_t*)c->b_ell.p,
+    HCK(ensure(c->b_misc, sb2 > c->b_misc.cap ? sb2 : c->b_misc.cap), "mrf_build: alloc scan");
+    HCK(radix_sort_pairs((const uint32_t*)c->b_g.p, (uint32_t*)c->b_lam.p, (uint32_t*)c->b_ell.p,
                          (uint32_t*)c->b_ellbar.p, (uint32_t*)c->b_gsum.p, (uint32_t*)c->b_lambar.p,
-                         (uint32_t*)c->b_vedge.p, E, bits_for(V > 0 ? V - 1 : 0), hist, offs, c->b_misc.p,
-                         c->b_misc.cap, s),
+                         (uint32_t*)c->b_vedge.p, S, bits_for(Vk), hist, offs, c->b_misc.p, c->b_misc.cap, s),
         "mrf_build: radix sort");
-    HCK(launch_vptr_from_sorted((const uint32_t*)c->b_lambar.p, E, V, (int64_t*)c->b_vptr.p, s),
+    HCK(launch_vptr_from_sorted((const uint32_t*)c->b_lambar.p, S, Vk, (int64_t*)c->b_vptr.p, s),
         "mrf_build: vptr");
     {
         hipError_t e = build_classes(c, s);
@@ -338,12 +371,14 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     st.n_edges = E;
     st.n_voxels = V;
     st.n_kept_rays = 0;
-    for (int k = 0; k < kRayClasses; ++k) st.n_kept_rays += c->ray_cnt[k];
-    st.n_touched_voxels = c->hub.n_hubs;
+    for (int k = 0; k < kRayClasses; ++k) st.n_kept_rays += c->ray_cls_rays[k];
+    st.n_slots = S;
+    st.n_tiles = T;
+    st.n_touched_voxels = 0;
     for (int k = 0; k < kVoxClasses; ++k) st.n_touched_voxels += c->vox_cnt[k];
     // voxel phase: vedge 4 + gather ell 4 + scatter lam 4; ray phase: lam 4 + g 4 + ell 4;
-    // per touched voxel: theta 4 (+ vptr 8)
-    st.fwd_bytes_per_sweep = 24.0 * (double)E + 12.0 * (double)st.n_touched_voxels;
+    // per touched voxel: key 4 + id 4 + vptr 16 + theta 4; per kept ray: id 4 + row_ptr 16
+    st.fwd_bytes_per_sweep = 24.0 * (double)E + 28.0 * (double)st.n_touched_voxels + 20.0 * (double)st.n_kept_rays;
     st.sweeps_done = 0;
     st.have_checkpoints = 0;
     c->built = 1;
@@ -360,7 +395,7 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
     HCK(hipSetDevice(c->device), "mrf_infer: hipSetDevice");
     const int keep = keep_checkpoints ? 1 : 0;
     if (keep) {
-        const size_t need = sizeof(float) * (size_t)sweeps * (size_t)(c->E > 0 ? c->E : 1);
+        const size_t need = sizeof(float) * (size_t)sweeps * (size_t)(c->S > 0 ? c->S : 1);
         if (c->b_ckpt.cap < need) {
             drop_graph(c);   // the graph holds the old checkpoint addresses
             HCK(ensure(c->b_ckpt, need), "mrf_infer: alloc checkpoints");
@@ -429,7 +464,7 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
     float* gsum = (float*)c->b_gsum.p;
     float* thetabar = (float*)c->b_thetabar.p;
     // d loss / d ell^(K)_e = d loss / d L_v(e);  d loss / d theta starts at d loss / d L
-    HCK(launch_gather_voxel(col, dlogit, ellbar, c->E, s), "mrf_backward: seed");
+    HCK(launch_gather_voxel(col, dlogit, ellbar, c->S, s), "mrf_backward: seed");
     HCK(launch_copy(thetabar, dlogit, c->V, s), "mrf_backward: seed");
     for (int k = K - 1; k >= 0; --k) {
         // lambda of sweep k from the checkpointed ell of sweep k-1 (0 before the first)
@@ -460,14 +495,12 @@ int mrf_export_incidence(const mrf_ctx* c, int64_t* row_ptr, int32_t* col, doubl
     if ((t_in || t_out) && !c->keep_chords)
         return fail(MRF_ESTATE, "mrf_export_incidence: chords were not kept (keep_chords = 0)");
     hipStream_t s = (hipStream_t)stream;
-    const size_t E = (size_t)c->E, R = (size_t)c->R, V = (size_t)c->V;
-    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-    if (row_ptr) HCK(hipMemcpyAsync(row_ptr, c->b_rowptr.p, 8 * (R + 1), k, s), "export");
-    if (col && E) HCK(hipMemcpyAsync(col, c->b_col.p, 4 * E, k, s), "export");
-    if (t_in && E) HCK(hipMemcpyAsync(t_in, c->b_tin.p, 8 * E, k, s), "export");
-    if (t_out && E) HCK(hipMemcpyAsync(t_out, c->b_tout.p, 8 * E, k, s), "export");
-    if (vptr) HCK(hipMemcpyAsync(vptr, c->b_vptr.p, 8 * (V + 1), k, s), "export");
-    if (vedge && E) HCK(hipMemcpyAsync(vedge, c->b_vedge.p, 4 * E, k, s), "export");
+    if (row_ptr)
+        HCK(hipMemcpyAsync(row_ptr, c->b_rowptr.p, 8 * (size_t)(c->R + 1), hipMemcpyDeviceToDevice, s), "export");
+    if (col) HCK(export_canonical_edges(c, c->b_col.p, col, 4, s), "export");
+    if (t_in) HCK(export_canonical_edges(c, c->b_tin.p, t_in, 8, s), "export");
+    if (t_out) HCK(export_canonical_edges(c, c->b_tout.p, t_out, 8, s), "export");
+    if (vptr || vedge) HCK(export_canonical_incidence(c, vptr, vedge, s), "export");
     return MRF_OK;
 }
 
@@ -477,25 +510,33 @@ int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, flo
     if (!c->built) return fail(MRF_ESTATE, "mrf_export_edges: call mrf_build first");
     if ((g || lam || ell) && !c->inferred) return fail(MRF_ESTATE, "mrf_export_edges: call mrf_infer first");
     hipStream_t s = (hipStream_t)stream;
-    const size_t E = (size_t)c->E;
-    if (!E) return MRF_OK;
-    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-    if (delta) HCK(hipMemcpyAsync(delta, c->b_delta.p, 4 * E, k, s), "export");
-    if (bin) HCK(hipMemcpyAsync(bin, c->b_bin.p, E, k, s), "export");
-    if (g) HCK(hipMemcpyAsync(g, c->b_g.p, 4 * E, k, s), "export");
-    if (lam) HCK(hipMemcpyAsync(lam, c->b_lam.p, 4 * E, k, s), "export");
-    if (ell) HCK(hipMemcpyAsync(ell, final_ell(c), 4 * E, k, s), "export");
+    if (delta) HCK(export_canonical_edges(c, c->b_delta.p, delta, 4, s), "export");
+    if (bin) HCK(export_canonical_edges(c, c->b_bin.p, bin, 1, s), "export");
+    if (g) HCK(export_canonical_edges(c, c->b_g.p, g, 4, s), "export");
+    if (lam) HCK(export_canonical_edges(c, c->b_lam.p, lam, 4, s), "export");
+    if (ell) HCK(export_canonical_edges(c, final_ell(c), ell, 4, s), "export");
     return MRF_OK;
 }
 
-static const char* kid_name(int k)
+}  // extern "C"
+
+extern "C" {
+
+static std::string kid_name(int k)
 {
-    static const char* names[KID_COUNT] = {
-        "voxel_k<16,1>", "voxel_k<64,1>", "voxel_k<64,4>", "voxel_k<64,16>", "hub_sum_k", "hub_carry_k",
-        "hub_piece_k", "ray_k<16,1>", "ray_k<64,1>", "ray_k<64,4>", "ray_k<64,16>", "ray_k<64,32>",
-        "ray_adj_k<16,1>", "ray_adj_k<64,1>", "ray_adj_k<64,4>", "ray_adj_k<64,16>", "ray_adj_k<64,32>",
-        "potentials_k", "sigma_grad_k"};
-    return names[k];
+    static const int G[kRayClasses] = {16, 64, 64, 64, 64, 64, 64, 64, 64, 64, 64, 64, 64};
+    static const char* vox[kVoxClasses] = {"voxel_k<1,1>", "voxel_k<1,4>", "voxel_k<1,16>", "voxel_k<4,16>",
+                                           "voxel_k<16,16>", "voxel_chunked_k"};
+    if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) return vox[k - KID_VOX0];
+    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses)
+        return "ray_k<" + std::to_string(G[k - KID_RAY0]) + "," +
+               std::to_string(kRayCap[k - KID_RAY0] / G[k - KID_RAY0]) + ">";
+    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses)
+        return "ray_adj_k<" + std::to_string(G[k - KID_ADJ0]) + "," +
+               std::to_string(kRayCap[k - KID_ADJ0] / G[k - KID_ADJ0]) + ">";
+    if (k == KID_POT) return "potentials_k";
+    if (k == KID_SIGMA) return "sigma_grad_k";
+    return "?";
 }
 
 // algorithmic bytes and edges of one launch of kernel k (steady-state sweep)
@@ -503,35 +544,25 @@ static void kid_bytes(const mrf_ctx* c, int k, double* bytes, int64_t* edges)
 {
     *bytes = 0.0;
     *edges = 0;
-    if (k >= KID_VOX0 && k <= KID_VOX3) {
+    if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
         const int q = k - KID_VOX0;
-        // per edge: vedge 4 + gathered ell 4 + scattered lam 4; per voxel: list 4 + vptr 16 + theta 4
+        // per edge: vedge 4 + gathered ell 4 + scattered lam 4;
+        // per voxel: key 4 + linear id 4 + vptr 16 + theta 4
         *edges = c->vox_cls_edges[q];
-        *bytes = 12.0 * (double)*edges + 24.0 * (double)c->vox_cnt[q];
-    } else if (k == KID_HUB_SUM) {
-        *edges = c->vox_cls_edges[kVoxClasses];
-        *bytes = 8.0 * (double)*edges + 16.0 * c->hub.n_pieces;
-    } else if (k == KID_HUB_PIECE) {
-        *edges = c->vox_cls_edges[kVoxClasses];
-        *bytes = 12.0 * (double)*edges + 32.0 * c->hub.n_pieces;
-    } else if (k == KID_HUB_CARRY) {
-        *bytes = 16.0 * c->hub.n_pieces + 12.0 * c->hub.n_hubs;
-    } else if (k >= KID_RAY0 && k <= KID_RAY4) {
+        *bytes = 12.0 * (double)*edges + 28.0 * (double)c->vox_cnt[q];
+    } else if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) {
         const int q = k - KID_RAY0;
-        // per edge: lam 4 + g 4 + ell 4; per ray: list 4 + row_ptr 16
+        // per edge: lam 4 + g 4 + ell 4; per ray: count 4; per tile: descriptor 32
         *edges = c->ray_cls_edges[q];
-        *bytes = 12.0 * (double)*edges + 20.0 * (double)c->ray_cnt[q];
-    } else if (k >= KID_ADJ0 && k <= KID_ADJ4) {
+        *bytes = 12.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
+    } else if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses) {
         const int q = k - KID_ADJ0;
         // per edge: lam 4 + g 4 + ellbar 4 + lambar 4 + gsum read 4 + write 4
         *edges = c->ray_cls_edges[q];
-        *bytes = 24.0 * (double)*edges + 20.0 * (double)c->ray_cnt[q];
-    } else if (k == KID_POT) {
+        *bytes = 24.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
+    } else if (k == KID_POT || k == KID_SIGMA) {
         *edges = c->E;
-        *bytes = 9.0 * (double)c->E;
-    } else if (k == KID_SIGMA) {
-        *edges = c->E;
-        *bytes = 9.0 * (double)c->E;
+        *bytes = 9.0 * (double)c->S;
     }
 }
 
@@ -548,7 +579,7 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
     float* lam = (float*)c->b_lam.p;
     float* ell = (float*)c->b_ellbar.p;   // scratch output: keeps the inference's messages
     const float* ell_in = final_ell(c);
-    HCK(launch_copy(ell, ell_in, c->E, s), "mrf_profile_sweeps");
+    HCK(launch_copy(ell, ell_in, c->S, s), "mrf_profile_sweeps");
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
         e = launch_voxel_phase(c, theta, ell, lam, nullptr, 0, false, s);
         if (e == hipSuccess) e = launch_ray_phase(c, lam, ell, false, s);
@@ -584,7 +615,7 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
         if (n < max_out) {
             mrf_kernel_time_t& o = out[n];
             memset(&o, 0, sizeof(o));
-            strncpy(o.name, kid_name(k), sizeof(o.name) - 1);
+            strncpy(o.name, kid_name(k).c_str(), sizeof(o.name) - 1);
             o.launches = cnt[k];
             o.total_ms = tot[k];
             kid_bytes(c, k, &o.bytes_per_launch, &o.edges_per_launch);

@@ -136,23 +136,35 @@ __global__ __launch_bounds__(256) void trace_count_k(const SceneDev* __restrict_
     counts[fr.ray_base + pix] = m >= bp.min_vox ? m : 0;
 }
 
+// brick-major key of voxel (i, j, k) of a scene
+__device__ __forceinline__ uint32_t brick_key(const SceneDev& sd, int i, int j, int k)
+{
+    const int64_t brick = ((int64_t)(k >> 3) * sd.nb[1] + (j >> 3)) * sd.nb[0] + (i >> 3);
+    return (uint32_t)(sd.key_base + brick * 512 + ((k & 7) * 8 + (j & 7)) * 8 + (i & 7));
+}
+
 struct EdgeEmit {
     int32_t* col;
+    uint32_t* key;
     float* delta;
     uint8_t* bin;
     double* tin;
     double* tout;
+    const SceneDev* sd;
     int64_t base;
     int32_t vbase;
     double Z, dbin;
     __device__ void operator()(int k, int id, double ti, double to) const
     {
-        const int64_t e = base + k;
+        const int64_t e = base + (int64_t)kTile * k;   // step k of this ray's tile lane
         const double d = (ti + to) * 0.5;   // voxel depth: chord midpoint
         double q = floor(d / dbin);
         if (q < 0.0) q = 0.0;
         if (q > 63.0) q = 63.0;
         col[e] = vbase + id;
+        const int nxy = sd->n[0] * sd->n[1];
+        const int vk = id / nxy, rem = id - vk * nxy, vj = rem / sd->n[0], vi = rem - vj * sd->n[0];
+        key[e] = brick_key(*sd, vi, vj, vk);
         delta[e] = (float)(Z - d);
         bin[e] = (uint8_t)q;
         if (tin) {
@@ -164,8 +176,9 @@ struct EdgeEmit {
 
 __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__ scenes,
                                                     const FrameDev* __restrict__ frames, BuildDev bp,
-                                                    const int64_t* __restrict__ row_ptr,
-                                                    int32_t* col, float* delta, uint8_t* bin,
+                                                    const int32_t* __restrict__ counts,
+                                                    const int64_t* __restrict__ tbase,
+                                                    int32_t* col, uint32_t* key, float* delta, uint8_t* bin,
                                                     double* tin, double* tout)
 {
     const FrameDev fr = frames[blockIdx.y];
@@ -173,13 +186,52 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix >= sd.W * sd.H) return;
     const int64_t r = fr.ray_base + pix;
-    const int64_t base = row_ptr[r];
-    if (row_ptr[r + 1] == base) return;
+    if (counts[r] == 0) return;
     const int v = pix / sd.W, u = pix - v * sd.W;
+    const int64_t t = fr.tile_base + (int64_t)(v / kTileW) * fr.ntx + u / kTileW;
+    const int64_t slot0 = tbase[t] + (v % kTileW) * kTileW + (u % kTileW);
     Ray ray;
     setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
-    EdgeEmit em{col, delta, bin, tin, tout, base, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
+    EdgeEmit em{col, key, delta, bin, tin, tout, &sd, slot0, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
     walk(sd, ray, em);
+}
+
+// One thread per tile: its rays, extent inside the image and longest ray.
+__global__ void tile_init_k(const SceneDev* __restrict__ scenes, const FrameDev* __restrict__ frames,
+                            const int32_t* __restrict__ counts, TileDev* __restrict__ tiles,
+                            int32_t* __restrict__ slots16)
+{
+    const FrameDev fr = frames[blockIdx.y];
+    const SceneDev& sd = scenes[fr.scene];
+    const int nty = (sd.H + kTileW - 1) / kTileW;
+    const int lt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lt >= fr.ntx * nty) return;
+    const int ty = lt / fr.ntx, tx = lt - ty * fr.ntx;
+    TileDev td;
+    td.ray0 = (int32_t)(fr.ray_base + (int64_t)(ty * kTileW) * sd.W + tx * kTileW);
+    td.W = sd.W;
+    td.nu = min(kTileW, sd.W - tx * kTileW);
+    td.nv = min(kTileW, sd.H - ty * kTileW);
+    int len = 0;
+    for (int a = 0; a < td.nv; ++a)
+        for (int b = 0; b < td.nu; ++b) len = max(len, counts[td.ray0 + a * sd.W + b]);
+    td.len = len;
+    td.base = 0;
+    td.pad = 0;
+    tiles[fr.tile_base + lt] = td;
+    slots16[fr.tile_base + lt] = kTile * len;
+}
+
+__global__ void tile_base_k(TileDev* __restrict__ tiles, const int64_t* __restrict__ tbase, int64_t T)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) tiles[t].base = tbase[t];
+}
+
+__global__ void fill_u32_k(uint32_t* __restrict__ p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s)
@@ -190,12 +242,42 @@ hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s)
+{
+    int max_tiles = 0;
+    for (const auto& sd : c->scenes_h)
+        max_tiles = std::max(max_tiles, ((sd.W + kTileW - 1) / kTileW) * ((sd.H + kTileW - 1) / kTileW));
+    dim3 grid((max_tiles + 255) / 256, c->n_frames);
+    hipLaunchKernelGGL(tile_init_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
+                       (const FrameDev*)c->b_frames.p, (const int32_t*)c->b_counts.p, (TileDev*)c->b_tiles.p,
+                       slots16);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s)
+{
+    if (c->T > 0)
+        hipLaunchKernelGGL(tile_base_k, dim3((unsigned)((c->T + 255) / 256)), dim3(256), 0, s,
+                           (TileDev*)c->b_tiles.p, (const int64_t*)c->b_tbase.p, c->T);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(fill_u32_k, dim3((unsigned)b), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s)
 {
     dim3 grid((c->max_hw + 255) / 256, c->n_frames);
     hipLaunchKernelGGL(trace_emit_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
-                       (const FrameDev*)c->b_frames.p, c->bp, (const int64_t*)c->b_rowptr.p,
-                       (int32_t*)c->b_col.p, (float*)c->b_delta.p, (uint8_t*)c->b_bin.p,
+                       (const FrameDev*)c->b_frames.p, c->bp, (const int32_t*)c->b_counts.p,
+                       (const int64_t*)c->b_tbase.p,
+                       (int32_t*)c->b_col.p, (uint32_t*)c->b_g.p, (float*)c->b_delta.p, (uint8_t*)c->b_bin.p,
                        c->keep_chords ? (double*)c->b_tin.p : nullptr,
                        c->keep_chords ? (double*)c->b_tout.p : nullptr);
     return hipGetLastError();
@@ -451,11 +533,12 @@ hipError_t launch_vptr_from_sorted(const uint32_t* sorted_keys, int64_t n, int64
 
 // ============================================================== work lists
 
-__global__ void ray_class_k(const int32_t* __restrict__ counts, int64_t R, uint8_t* __restrict__ cls)
+// length class of every tile (255: no edges)
+__global__ void tile_class_k(const TileDev* __restrict__ tiles, int64_t T, uint8_t* __restrict__ cls)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const int n = counts[r];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int n = tiles[t].len;
     uint8_t c = 255;
     if (n > 0) {
         c = kRayClasses;   // too long: reported as an error by the host
@@ -465,24 +548,105 @@ __global__ void ray_class_k(const int32_t* __restrict__ counts, int64_t R, uint8
                 break;
             }
     }
-    cls[r] = c;
+    cls[t] = c;
 }
 
-__global__ void vox_class_k(const int64_t* __restrict__ vptr, int64_t V, uint8_t* __restrict__ cls)
+// degree class of every brick-major key (kVoxClasses: too large, 255: empty)
+__global__ void vox_class_k(const int64_t* __restrict__ vptr, int64_t Vk, uint8_t* __restrict__ cls)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
+    if (v >= Vk) return;
     const int64_t m = vptr[v + 1] - vptr[v];
     uint8_t c = 255;
     if (m > 0) {
-        c = kVoxClasses;   // hub
-        for (int k = 0; k < kVoxClasses; ++k)
+        c = kVoxClasses - 1;
+        for (int k = 0; k < kVoxClasses - 1; ++k)
             if (m <= kVoxCap[k]) {
                 c = (uint8_t)k;
                 break;
             }
+        if (m > (int64_t)kVoxChunk * kVoxMaxChunks) c = kVoxClasses;
     }
     cls[v] = c;
+}
+
+// linear voxel id of a brick-major key (keys of padding voxels never appear)
+__device__ uint32_t key_to_voxel(const SceneDev* __restrict__ scenes, int ns, uint32_t key)
+{
+    int sc = 0;
+    while (sc + 1 < ns && (int64_t)key >= scenes[sc + 1].key_base) ++sc;
+    const SceneDev& sd = scenes[sc];
+    const int64_t local = (int64_t)key - sd.key_base;
+    const int64_t brick = local >> 9;
+    const int l = (int)(local & 511);
+    const int bx = (int)(brick % sd.nb[0]);
+    const int by = (int)((brick / sd.nb[0]) % sd.nb[1]);
+    const int bz = (int)(brick / ((int64_t)sd.nb[0] * sd.nb[1]));
+    const int i = bx * 8 + (l & 7), j = by * 8 + ((l >> 3) & 7), k = bz * 8 + (l >> 6);
+    return (uint32_t)(sd.voxel_base + i + (int64_t)sd.n[0] * (j + (int64_t)sd.n[1] * k));
+}
+
+__global__ void keys_to_voxels_k(const SceneDev* __restrict__ scenes, int ns, const uint32_t* __restrict__ keys,
+                                 int64_t n, uint32_t* __restrict__ ext)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ext[i] = key_to_voxel(scenes, ns, keys[i]);
+}
+
+// brick-major key of a linear voxel id
+__device__ uint32_t voxel_to_key(const SceneDev* __restrict__ scenes, int ns, int64_t v)
+{
+    int sc = 0;
+    while (sc + 1 < ns && v >= scenes[sc + 1].voxel_base) ++sc;
+    const SceneDev& sd = scenes[sc];
+    const int64_t local = v - sd.voxel_base;
+    const int64_t nxy = (int64_t)sd.n[0] * sd.n[1];
+    const int k = (int)(local / nxy);
+    const int64_t rem = local - k * nxy;
+    const int j = (int)(rem / sd.n[0]), i = (int)(rem - (int64_t)j * sd.n[0]);
+    return brick_key(sd, i, j, k);
+}
+
+// canonical incidence: degree per linear voxel, then each voxel's edge list
+__global__ void canon_degree_k(const SceneDev* __restrict__ scenes, int ns, const int64_t* __restrict__ vptr,
+                               int64_t V, int32_t* __restrict__ deg)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const uint32_t k = voxel_to_key(scenes, ns, v);
+    deg[v] = (int32_t)(vptr[k + 1] - vptr[k]);
+}
+
+// first slot of ray r (its tile's base plus its lane)
+__device__ int64_t ray_slot0(const FrameDev* __restrict__ frames, int nf, const SceneDev* __restrict__ scenes,
+                             const int64_t* __restrict__ tbase, int64_t r)
+{
+    int lo = 0, hi = nf;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (frames[mid].ray_base <= r)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const FrameDev fr = frames[lo];
+    const int W = scenes[fr.scene].W;
+    const int64_t pix = r - fr.ray_base;
+    const int v = (int)(pix / W), u = (int)(pix - (int64_t)v * W);
+    return tbase[fr.tile_base + (int64_t)(v / kTileW) * fr.ntx + u / kTileW] + (v % kTileW) * kTileW + u % kTileW;
+}
+
+template <class T>
+__global__ void canon_edges_k(const FrameDev* __restrict__ frames, int nf, const SceneDev* __restrict__ scenes,
+                              const int64_t* __restrict__ tbase, const int64_t* __restrict__ row_ptr, int64_t R,
+                              const T* __restrict__ in, T* __restrict__ out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t d = row_ptr[r], m = row_ptr[r + 1] - d;
+    if (m == 0) return;
+    const int64_t s0 = ray_slot0(frames, nf, scenes, tbase, r);
+    for (int64_t k = 0; k < m; ++k) out[d + k] = in[s0 + kTile * k];
 }
 
 __global__ void compact_k(const uint8_t* __restrict__ cls, int64_t n, uint8_t c,
@@ -490,35 +654,6 @@ __global__ void compact_k(const uint8_t* __restrict__ cls, int64_t n, uint8_t c,
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && cls[i] == c) list[pos[i]] = (uint32_t)i;
-}
-
-__global__ void hub_pieces_count_k(const uint32_t* __restrict__ hubs, uint32_t nh,
-                                   const int64_t* __restrict__ vptr, int32_t* __restrict__ npieces)
-{
-    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= nh) return;
-    const uint32_t v = hubs[h];
-    const int64_t m = vptr[v + 1] - vptr[v];
-    npieces[h] = (int32_t)((m + kPiece - 1) / kPiece);
-}
-
-__global__ void hub_pieces_fill_k(const uint32_t* __restrict__ hubs, uint32_t nh,
-                                  const int64_t* __restrict__ vptr, const int64_t* __restrict__ p0,
-                                  uint32_t* hub_piece0, uint32_t* piece_voxel, int64_t* piece_start,
-                                  uint32_t* piece_len)
-{
-    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h > nh) return;
-    hub_piece0[h] = (uint32_t)p0[h];
-    if (h == nh) return;
-    const uint32_t v = hubs[h];
-    const int64_t s = vptr[v], m = vptr[v + 1] - s;
-    uint32_t q = (uint32_t)p0[h];
-    for (int64_t off = 0; off < m; off += kPiece, ++q) {
-        piece_voxel[q] = v;
-        piece_start[q] = s + off;
-        piece_len[q] = (uint32_t)(m - off < kPiece ? m - off : kPiece);
-    }
 }
 
 }  // namespace mrf
@@ -579,6 +714,34 @@ __global__ void hist_k(const int32_t* __restrict__ counts, int64_t R, const int6
     }
 }
 
+// total edges and rays of the tiles of one class list (integer atomics: exact)
+__global__ void tile_class_edges_k(const uint32_t* __restrict__ list, int64_t n, const TileDev* __restrict__ tiles,
+                                   const int32_t* __restrict__ counts, unsigned long long* __restrict__ out_e,
+                                   unsigned long long* __restrict__ out_r)
+{
+    __shared__ unsigned long long acc, accr;
+    if (threadIdx.x == 0) acc = accr = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const TileDev td = tiles[list[i]];
+        unsigned long long sum = 0, nr = 0;
+        for (int a = 0; a < td.nv; ++a)
+            for (int b = 0; b < td.nu; ++b) {
+                const int x = counts[td.ray0 + a * td.W + b];
+                sum += (unsigned long long)x;
+                nr += x > 0;
+            }
+        atomicAdd(&acc, sum);
+        atomicAdd(&accr, nr);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && acc) {
+        atomicAdd(out_e, acc);
+        atomicAdd(out_r, accr);
+    }
+}
+
 // total edges of the items of one class list (integer atomics: exact)
 __global__ void class_edges_k(const uint32_t* __restrict__ list, int64_t n, const int64_t* __restrict__ ptr,
                               unsigned long long* __restrict__ out)
@@ -615,7 +778,7 @@ static hipError_t partition(const uint8_t* cls, int64_t n, uint8_t c, int64_t* p
 hipError_t build_classes(mrf_ctx* c, hipStream_t s)
 {
     hipError_t e;
-    const int64_t nmax = c->R > c->V ? c->R : c->V;
+    const int64_t nmax = std::max(c->R, std::max(c->Vk, c->T));
     if ((e = ensure(c->b_cls, (size_t)(nmax + 1))) != hipSuccess) return e;
     if ((e = ensure(c->b_tmp64, (size_t)(nmax + 2) * sizeof(int64_t))) != hipSuccess) return e;
     const size_t sbytes = scan_tmp_bytes(nmax + 1);
@@ -623,18 +786,18 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
     uint8_t* cls = (uint8_t*)c->b_cls.p;
     int64_t* pos = (int64_t*)c->b_tmp64.p;
 
-    // rays
-    if (c->R > 0)
-        hipLaunchKernelGGL(ray_class_k, dim3((unsigned)cdiv(c->R, 256)), dim3(256), 0, s,
-                           (const int32_t*)c->b_counts.p, c->R, cls);
+    // tiles of rays, by their longest ray
+    if (c->T > 0)
+        hipLaunchKernelGGL(tile_class_k, dim3((unsigned)cdiv(c->T, 256)), dim3(256), 0, s,
+                           (const TileDev*)c->b_tiles.p, c->T, cls);
     for (int k = 0; k < kRayClasses; ++k)
-        if ((e = partition(cls, c->R, (uint8_t)k, pos, c->b_misc.p, sbytes, c->b_ray_list[k], &c->ray_cnt[k], s)) !=
+        if ((e = partition(cls, c->T, (uint8_t)k, pos, c->b_misc.p, sbytes, c->b_ray_list[k], &c->ray_cnt[k], s)) !=
             hipSuccess)
             return e;
     {
         DevBuf tmp;
         int64_t too_long = 0;
-        e = partition(cls, c->R, (uint8_t)kRayClasses, pos, c->b_misc.p, sbytes, tmp, &too_long, s);
+        e = partition(cls, c->T, (uint8_t)kRayClasses, pos, c->b_misc.p, sbytes, tmp, &too_long, s);
         hipFree(tmp.p);
         if (e != hipSuccess) return e;
         if (too_long > 0) {
@@ -642,58 +805,39 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
             return hipErrorInvalidConfiguration;
         }
     }
-    // voxels
-    if (c->V > 0)
-        hipLaunchKernelGGL(vox_class_k, dim3((unsigned)cdiv(c->V, 256)), dim3(256), 0, s,
-                           (const int64_t*)c->b_vptr.p, c->V, cls);
-    for (int k = 0; k < kVoxClasses; ++k)
-        if ((e = partition(cls, c->V, (uint8_t)k, pos, c->b_misc.p, sbytes, c->b_vox_list[k], &c->vox_cnt[k], s)) !=
+    // voxels, by brick-major key
+    if (c->Vk > 0)
+        hipLaunchKernelGGL(vox_class_k, dim3((unsigned)cdiv(c->Vk, 256)), dim3(256), 0, s,
+                           (const int64_t*)c->b_vptr.p, c->Vk, cls);
+    for (int k = 0; k < kVoxClasses; ++k) {
+        if ((e = partition(cls, c->Vk, (uint8_t)k, pos, c->b_misc.p, sbytes, c->b_vox_list[k], &c->vox_cnt[k], s)) !=
             hipSuccess)
             return e;
-    int64_t nh = 0;
-    if ((e = partition(cls, c->V, (uint8_t)kVoxClasses, pos, c->b_misc.p, sbytes, c->b_hub[0], &nh, s)) != hipSuccess)
-        return e;
-    HubTables& H = c->hub;
-    H.n_hubs = (uint32_t)nh;
-    H.hub_voxel = (uint32_t*)c->b_hub[0].p;
-    if ((e = ensure(c->b_hub[1], (size_t)(nh + 1) * sizeof(uint32_t))) != hipSuccess) return e;
-    H.hub_piece0 = (uint32_t*)c->b_hub[1].p;
-    int64_t npieces = 0;
-    if (nh > 0) {
-        int32_t* np = (int32_t*)c->b_lambar.p;   // free during build
-        hipLaunchKernelGGL(hub_pieces_count_k, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, s, H.hub_voxel,
-                           (uint32_t)nh, (const int64_t*)c->b_vptr.p, np);
-        if ((e = scan_rec(LoadI32{np}, nh, pos, (int64_t*)c->b_misc.p, s)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(&npieces, pos + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
-            return e;
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        const int64_t n = c->vox_cnt[k];
+        if ((e = ensure(c->b_vox_ext[k], (size_t)(n > 0 ? n : 1) * sizeof(uint32_t))) != hipSuccess) return e;
+        if (n > 0)
+            hipLaunchKernelGGL(keys_to_voxels_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s,
+                               (const SceneDev*)c->b_scenes.p, c->n_scenes, (const uint32_t*)c->b_vox_list[k].p, n,
+                               (uint32_t*)c->b_vox_ext[k].p);
     }
-    H.n_pieces = (uint32_t)npieces;
-    const size_t pn = (size_t)(npieces > 0 ? npieces : 1);
-    if ((e = ensure(c->b_hub[2], pn * sizeof(uint32_t))) != hipSuccess) return e;
-    if ((e = ensure(c->b_hub[3], pn * sizeof(int64_t))) != hipSuccess) return e;
-    if ((e = ensure(c->b_hub[4], pn * sizeof(uint32_t))) != hipSuccess) return e;
-    if ((e = ensure(c->b_hub[5], pn * sizeof(float))) != hipSuccess) return e;
-    if ((e = ensure(c->b_hub[6], pn * sizeof(float))) != hipSuccess) return e;
-    if ((e = ensure(c->b_hub[7], pn * sizeof(float))) != hipSuccess) return e;
-    H.piece_voxel = (uint32_t*)c->b_hub[2].p;
-    H.piece_start = (int64_t*)c->b_hub[3].p;
-    H.piece_len = (uint32_t*)c->b_hub[4].p;
-    H.piece_sum = (float*)c->b_hub[5].p;
-    H.piece_pre = (float*)c->b_hub[6].p;
-    H.piece_suf = (float*)c->b_hub[7].p;
-    if (nh > 0)
-        hipLaunchKernelGGL(hub_pieces_fill_k, dim3((unsigned)cdiv(nh + 1, 256)), dim3(256), 0, s, H.hub_voxel,
-                           (uint32_t)nh, (const int64_t*)c->b_vptr.p, (const int64_t*)pos, H.hub_piece0,
-                           H.piece_voxel, H.piece_start, H.piece_len);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        DevBuf tmp;
+        int64_t too_big = 0;
+        e = partition(cls, c->Vk, (uint8_t)kVoxClasses, pos, c->b_misc.p, sbytes, tmp, &too_big, s);
+        hipFree(tmp.p);
+        if (e != hipSuccess) return e;
+        if (too_big > 0) {
+            set_error("a voxel is crossed by more than 1048576 rays");
+            return hipErrorInvalidConfiguration;
+        }
+    }
 
     // per-frame offsets of every ray class list (plain schedule)
     {
         const int nf = c->n_frames;
         std::vector<int64_t> fbase(nf + 1);
-        for (int f = 0; f < nf; ++f) fbase[f] = c->frames_h[f].ray_base;
-        fbase[nf] = c->R;
+        for (int f = 0; f < nf; ++f) fbase[f] = c->frames_h[f].tile_base;
+        fbase[nf] = c->T;
         std::vector<const uint32_t*> lists(kRayClasses);
         for (int k = 0; k < kRayClasses; ++k) lists[k] = (const uint32_t*)c->b_ray_list[k].p;
         // fbase (nf+1) | counts (classes) | offsets ((nf+1) * classes) | list pointers (classes)
@@ -721,25 +865,26 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
     {
         if ((e = ensure(c->b_sigpart, 64 * sizeof(double) * 4096)) != hipSuccess) return e;
         unsigned long long* d = (unsigned long long*)c->b_sigpart.p + 64;
-        const int nc = kRayClasses + kVoxClasses + 1;
+        const int nc = 2 * kRayClasses + kVoxClasses;
         hipMemsetAsync(d, 0, nc * sizeof(unsigned long long), s);
         for (int k = 0; k < kRayClasses; ++k)
             if (c->ray_cnt[k] > 0)
-                hipLaunchKernelGGL(class_edges_k, dim3((unsigned)cdiv(c->ray_cnt[k], 256)), dim3(256), 0, s,
-                                   (const uint32_t*)c->b_ray_list[k].p, c->ray_cnt[k], (const int64_t*)c->b_rowptr.p,
-                                   d + k);
-        for (int k = 0; k <= kVoxClasses; ++k) {
-            const int64_t n = k < kVoxClasses ? c->vox_cnt[k] : (int64_t)c->hub.n_hubs;
-            const uint32_t* L = k < kVoxClasses ? (const uint32_t*)c->b_vox_list[k].p : c->hub.hub_voxel;
+                hipLaunchKernelGGL(tile_class_edges_k, dim3((unsigned)cdiv(c->ray_cnt[k], 256)), dim3(256), 0, s,
+                                   (const uint32_t*)c->b_ray_list[k].p, c->ray_cnt[k], (const TileDev*)c->b_tiles.p,
+                                   (const int32_t*)c->b_counts.p, d + k, d + kRayClasses + kVoxClasses + k);
+        for (int k = 0; k < kVoxClasses; ++k) {
+            const int64_t n = c->vox_cnt[k];
             if (n > 0)
-                hipLaunchKernelGGL(class_edges_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, L, n,
-                                   (const int64_t*)c->b_vptr.p, d + kRayClasses + k);
+                hipLaunchKernelGGL(class_edges_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s,
+                                   (const uint32_t*)c->b_vox_list[k].p, n, (const int64_t*)c->b_vptr.p,
+                                   d + kRayClasses + k);
         }
-        unsigned long long hh[kRayClasses + kVoxClasses + 1];
+        unsigned long long hh[2 * kRayClasses + kVoxClasses];
         if ((e = hipMemcpyAsync(hh, d, sizeof(hh), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
         for (int k = 0; k < kRayClasses; ++k) c->ray_cls_edges[k] = (int64_t)hh[k];
-        for (int k = 0; k <= kVoxClasses; ++k) c->vox_cls_edges[k] = (int64_t)hh[kRayClasses + k];
+        for (int k = 0; k < kVoxClasses; ++k) c->vox_cls_edges[k] = (int64_t)hh[kRayClasses + k];
+        for (int k = 0; k < kRayClasses; ++k) c->ray_cls_rays[k] = (int64_t)hh[kRayClasses + kVoxClasses + k];
     }
     // histograms
     {
@@ -747,10 +892,10 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
         if ((e = ensure(c->b_sigpart, 64 * sizeof(double) * 4096)) != hipSuccess) return e;
         d_h = (unsigned long long*)c->b_sigpart.p;
         hipMemsetAsync(d_h, 0, 42 * sizeof(unsigned long long), s);
-        const int64_t nmx = c->R > c->V ? c->R : c->V;
+        const int64_t nmx = c->R > c->Vk ? c->R : c->Vk;
         if (nmx > 0)
             hipLaunchKernelGGL(hist_k, dim3((unsigned)cdiv(nmx, 256)), dim3(256), 0, s,
-                               (const int32_t*)c->b_counts.p, c->R, (const int64_t*)c->b_vptr.p, c->V, d_h);
+                               (const int32_t*)c->b_counts.p, c->R, (const int64_t*)c->b_vptr.p, c->Vk, d_h);
         unsigned long long hh[42];
         if ((e = hipMemcpyAsync(hh, d_h, sizeof(hh), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
@@ -758,6 +903,78 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
         for (int i = 0; i < 24; ++i) c->stats.voxel_degree_hist[i] = (int64_t)hh[16 + i];
         c->stats.max_ray_len = (int64_t)hh[40];
         c->stats.max_voxel_degree = (int64_t)hh[41];
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mrf
+
+namespace mrf {
+
+hipError_t export_canonical_incidence(const mrf_ctx* c, int64_t* vptr, uint32_t* vedge, hipStream_t s)
+{
+    hipError_t e;
+    mrf_ctx* m = const_cast<mrf_ctx*>(c);
+    const SceneDev* sc = (const SceneDev*)c->b_scenes.p;
+    if (vptr) {
+        // canonical vptr: exclusive scan of the degree of every linear voxel id
+        if ((e = ensure(m->b_tmp64, sizeof(int32_t) * (size_t)(c->V + 1))) != hipSuccess) return e;
+        const size_t sb = scan_tmp_bytes(c->V + 1);
+        if ((e = ensure(m->b_misc, sb)) != hipSuccess) return e;
+        int32_t* deg = (int32_t*)c->b_tmp64.p;
+        if (c->V > 0)
+            hipLaunchKernelGGL(canon_degree_k, dim3((unsigned)cdiv(c->V, 256)), dim3(256), 0, s, sc, c->n_scenes,
+                               (const int64_t*)c->b_vptr.p, c->V, deg);
+        if ((e = scan_rec(LoadI32{deg}, c->V, vptr, (int64_t*)m->b_misc.p, s)) != hipSuccess) return e;
+    }
+    if (vedge && c->E > 0) {
+        // canonical vedge: stable radix sort of canonical edge ids by linear voxel id
+        // (O(E) temporaries: this export is a checking facility)
+        const size_t E = (size_t)c->E;
+        if ((e = ensure(m->b_export, 5 * E * sizeof(uint32_t))) != hipSuccess) return e;
+        uint32_t* keys = (uint32_t*)c->b_export.p;
+        uint32_t *ka = keys + E, *va = keys + 2 * E, *kb = keys + 3 * E, *vb = keys + 4 * E;
+        if ((e = export_canonical_edges(c, c->b_col.p, keys, 4, s)) != hipSuccess) return e;
+        const int64_t nh = (int64_t)radix_hist_entries(c->E);
+        if ((e = ensure(m->b_tmp64, sizeof(int64_t) * (size_t)(nh + 1) + sizeof(int32_t) * (size_t)nh)) != hipSuccess)
+            return e;
+        int64_t* offs = (int64_t*)c->b_tmp64.p;
+        int32_t* hist = (int32_t*)(offs + nh + 1);
+        const size_t sb2 = scan_tmp_bytes(nh + 1);
+        if ((e = ensure(m->b_misc, sb2)) != hipSuccess) return e;
+        int bits = 1;
+        while (bits < 31 && (int64_t(1) << bits) <= c->V - 1) ++bits;
+        const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+        uint32_t* kout = passes == 1 ? kb : keys;   // the first pass is the only reader of `keys`
+        if ((e = radix_sort_pairs(keys, ka, va, kb, vb, kout, vedge, c->E, bits, hist, offs, m->b_misc.p,
+                                  m->b_misc.cap, s)) != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t export_canonical_edges(const mrf_ctx* c, const void* in_slots, void* out, int elem_bytes, hipStream_t s)
+{
+    if (c->R <= 0 || c->E <= 0) return hipSuccess;
+    const dim3 g((unsigned)cdiv(c->R, 256)), b(256);
+    const FrameDev* fr = (const FrameDev*)c->b_frames.p;
+    const SceneDev* sc = (const SceneDev*)c->b_scenes.p;
+    const int64_t* tb = (const int64_t*)c->b_tbase.p;
+    const int64_t* rp = (const int64_t*)c->b_rowptr.p;
+    switch (elem_bytes) {
+        case 1:
+            hipLaunchKernelGGL(canon_edges_k<uint8_t>, g, b, 0, s, fr, c->n_frames, sc, tb, rp, c->R,
+                               (const uint8_t*)in_slots, (uint8_t*)out);
+            break;
+        case 4:
+            hipLaunchKernelGGL(canon_edges_k<uint32_t>, g, b, 0, s, fr, c->n_frames, sc, tb, rp, c->R,
+                               (const uint32_t*)in_slots, (uint32_t*)out);
+            break;
+        case 8:
+            hipLaunchKernelGGL(canon_edges_k<uint64_t>, g, b, 0, s, fr, c->n_frames, sc, tb, rp, c->R,
+                               (const uint64_t*)in_slots, (uint64_t*)out);
+            break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -169,3 +169,227 @@ __device__ __forceinline__ AMap grscan_amap(AMap x)
 }
 
 }  // namespace mrf
+
+// ---------------------------------------------------------------------------
+// DPP-based scans.  A wave64 is four rows of 16 lanes; row_shr:n moves data
+// to lane + n inside a row, row_shl:n to lane - n, wave_shr:1 / wave_shl:1
+// move it by one lane across the whole wave.  Lanes without a source keep
+// `old`.  Row results are combined across rows through readlane.
+// ---------------------------------------------------------------------------
+namespace mrf {
+
+enum : int {
+    DPP_ROW_SHL1 = 0x101, DPP_ROW_SHL2 = 0x102, DPP_ROW_SHL4 = 0x104, DPP_ROW_SHL8 = 0x108,
+    DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118,
+    DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float old, float src)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                 __builtin_bit_cast(int, src), CTRL, 0xF, 0xF,
+                                                                 false));
+}
+
+__device__ __forceinline__ float readlane(float x, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+
+struct OpAdd {
+    __device__ static float id() { return 0.0f; }
+    __device__ static float op(float a, float b) { return a + b; }
+};
+struct OpLse {
+    __device__ static float id() { return MRF_NINF; }
+    __device__ static float op(float a, float b) { return lse(a, b); }
+};
+
+// inclusive prefix: element i gets x_0 op ... op x_i over the group
+template <int G, class O>
+__device__ __forceinline__ float dscan(float x)
+{
+    static_assert(G == 16 || G == 64, "groups are rows or waves");
+    const float I = O::id();
+    x = O::op(dpp<DPP_ROW_SHR1>(I, x), x);
+    x = O::op(dpp<DPP_ROW_SHR2>(I, x), x);
+    x = O::op(dpp<DPP_ROW_SHR4>(I, x), x);
+    x = O::op(dpp<DPP_ROW_SHR8>(I, x), x);
+    if (G == 64) {
+        const float r0 = readlane(x, 15), r1 = readlane(x, 31), r2 = readlane(x, 47);
+        const float c2 = O::op(r0, r1);
+        const float c3 = O::op(c2, r2);
+        const int row = (threadIdx.x & 63) >> 4;
+        const float c = row == 1 ? r0 : (row == 2 ? c2 : c3);
+        if (row) x = O::op(c, x);
+    }
+    return x;
+}
+
+// inclusive suffix: element i gets x_i op ... op x_{G-1}
+template <int G, class O>
+__device__ __forceinline__ float drscan(float x)
+{
+    static_assert(G == 16 || G == 64, "groups are rows or waves");
+    const float I = O::id();
+    x = O::op(x, dpp<DPP_ROW_SHL1>(I, x));
+    x = O::op(x, dpp<DPP_ROW_SHL2>(I, x));
+    x = O::op(x, dpp<DPP_ROW_SHL4>(I, x));
+    x = O::op(x, dpp<DPP_ROW_SHL8>(I, x));
+    if (G == 64) {
+        const float t1 = readlane(x, 16), t2 = readlane(x, 32), t3 = readlane(x, 48);
+        const float c1 = O::op(t2, t3);
+        const float c0 = O::op(t1, c1);
+        const int row = (threadIdx.x & 63) >> 4;
+        const float c = row == 2 ? t3 : (row == 1 ? c1 : c0);
+        if (row != 3) x = O::op(x, c);
+    }
+    return x;
+}
+
+// exclusive from inclusive: element i gets incl_{i-1}; the first gets `first`
+template <int G>
+__device__ __forceinline__ float dexcl(float incl, float first)
+{
+    return G == 64 ? dpp<DPP_WAVE_SHR1>(first, incl) : dpp<DPP_ROW_SHR1>(first, incl);
+}
+
+// exclusive suffix from inclusive: element i gets incl_{i+1}; the last gets `last`
+template <int G>
+__device__ __forceinline__ float drexcl(float incl, float last)
+{
+    return G == 64 ? dpp<DPP_WAVE_SHL1>(last, incl) : dpp<DPP_ROW_SHL1>(last, incl);
+}
+
+// log-semiring maps x -> LSE(c, a + x): suffix composition (first o second)
+__device__ __forceinline__ LMap lmap_id() { return LMap{0.0f, MRF_NINF}; }
+
+template <int CTRL>
+__device__ __forceinline__ LMap dpp_lmap(LMap old, LMap src)
+{
+    return LMap{dpp<CTRL>(old.a, src.a), dpp<CTRL>(old.c, src.c)};
+}
+
+__device__ __forceinline__ LMap readlane_lmap(LMap x, int l) { return LMap{readlane(x.a, l), readlane(x.c, l)}; }
+
+template <int G>
+__device__ __forceinline__ LMap drscan_lmap(LMap x)
+{
+    const LMap I = lmap_id();
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL1>(I, x));
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL2>(I, x));
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL4>(I, x));
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL8>(I, x));
+    if (G == 64) {
+        const LMap t1 = readlane_lmap(x, 16), t2 = readlane_lmap(x, 32), t3 = readlane_lmap(x, 48);
+        const LMap c1 = lmap_compose(t2, t3);
+        const LMap c0 = lmap_compose(t1, c1);
+        const int row = (threadIdx.x & 63) >> 4;
+        const LMap c = row == 2 ? t3 : (row == 1 ? c1 : c0);
+        if (row != 3) x = lmap_compose(x, c);
+    }
+    return x;
+}
+
+// linear affine maps x -> m x + b
+__device__ __forceinline__ AMap amap_id() { return AMap{1.0f, 0.0f}; }
+
+template <int CTRL>
+__device__ __forceinline__ AMap dpp_amap(AMap old, AMap src)
+{
+    return AMap{dpp<CTRL>(old.m, src.m), dpp<CTRL>(old.b, src.b)};
+}
+
+__device__ __forceinline__ AMap readlane_amap(AMap x, int l) { return AMap{readlane(x.m, l), readlane(x.b, l)}; }
+
+// prefix: element i gets map_0 then ... then map_i
+template <int G>
+__device__ __forceinline__ AMap dscan_amap(AMap x)
+{
+    const AMap I = amap_id();
+    x = amap_then(dpp_amap<DPP_ROW_SHR1>(I, x), x);
+    x = amap_then(dpp_amap<DPP_ROW_SHR2>(I, x), x);
+    x = amap_then(dpp_amap<DPP_ROW_SHR4>(I, x), x);
+    x = amap_then(dpp_amap<DPP_ROW_SHR8>(I, x), x);
+    if (G == 64) {
+        const AMap r0 = readlane_amap(x, 15), r1 = readlane_amap(x, 31), r2 = readlane_amap(x, 47);
+        const AMap c2 = amap_then(r0, r1);
+        const AMap c3 = amap_then(c2, r2);
+        const int row = (threadIdx.x & 63) >> 4;
+        const AMap c = row == 1 ? r0 : (row == 2 ? c2 : c3);
+        if (row) x = amap_then(c, x);
+    }
+    return x;
+}
+
+// suffix: element i gets map_{G-1} then ... then map_i
+template <int G>
+__device__ __forceinline__ AMap drscan_amap(AMap x)
+{
+    const AMap I = amap_id();
+    x = amap_then(dpp_amap<DPP_ROW_SHL1>(I, x), x);
+    x = amap_then(dpp_amap<DPP_ROW_SHL2>(I, x), x);
+    x = amap_then(dpp_amap<DPP_ROW_SHL4>(I, x), x);
+    x = amap_then(dpp_amap<DPP_ROW_SHL8>(I, x), x);
+    if (G == 64) {
+        const AMap t1 = readlane_amap(x, 16), t2 = readlane_amap(x, 32), t3 = readlane_amap(x, 48);
+        const AMap c1 = amap_then(t3, t2);
+        const AMap c0 = amap_then(c1, t1);
+        const int row = (threadIdx.x & 63) >> 4;
+        const AMap c = row == 2 ? t3 : (row == 1 ? c1 : c0);
+        if (row != 3) x = amap_then(c, x);
+    }
+    return x;
+}
+
+// sum over a wave, result in every lane
+__device__ __forceinline__ float wave_sum(float x)
+{
+    x = dscan<64, OpAdd>(x);
+    return readlane(x, 63);
+}
+
+// Block index remapped so that each XCD (blocks are dealt to the 8 XCDs
+// round-robin) works on one contiguous range of logical blocks, keeping
+// neighbouring work items in the same L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nb)
+{
+    const unsigned q = nb >> 3, r = nb & 7, x = bid & 7, i = bid >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+}  // namespace mrf
+
+// Work item of the ray kernels: a 4x4-pixel tile of rays.  A 256-thread block
+// holds 16 rays of 16 lanes (G == 16) or 4 rays of one wave (G == 64, four
+// consecutive blocks per tile, kept on one XCD by the block remap).
+namespace mrf {
+
+template <int G>
+constexpr int tile_blocks()
+{
+    return 16 * G / 256;
+}
+
+// Slot of step 0 and length of this group's ray; false if the group has none.
+template <int G, class Tile>
+__device__ __forceinline__ bool tile_ray(const uint32_t* __restrict__ list, int64_t ntiles,
+                                         const Tile* __restrict__ tiles, const int32_t* __restrict__ counts,
+                                         int64_t& s0, int& m)
+{
+    constexpr int BPT = tile_blocks<G>();
+    constexpr int GPB = 256 / G;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t ti = lb / BPT;
+    if (ti >= ntiles) return false;
+    const int i = (int)(lb % BPT) * GPB + (int)(threadIdx.x / G);
+    const Tile td = tiles[list[ti]];
+    const int ux = i & 3, vy = i >> 2;
+    if (ux >= td.nu || vy >= td.nv) return false;
+    m = counts[td.ray0 + (int64_t)vy * td.W + ux];
+    s0 = td.base + i;
+    return m > 0;
+}
+
+}  // namespace mrf

@@ -15,14 +15,30 @@ namespace mrf {
 // ---------------------------------------------------------------- limits
 constexpr int kBins = 64;
 constexpr int kMaxRayLen = 2048;      // longest ray factor a group can hold
-constexpr int kPiece = 1024;          // hub voxels are split into pieces of this many edges
 
 // Ray-length classes: (group lanes G, items per lane IPL), capacity G*IPL.
-constexpr int kRayClasses = 5;
-constexpr int kRayCap[kRayClasses] = {16, 64, 256, 1024, 2048};
-// Voxel-degree classes; degrees above the last capacity become hub pieces.
-constexpr int kVoxClasses = 4;
-constexpr int kVoxCap[kVoxClasses] = {16, 64, 256, 1024};
+// Class 0 is G = 16, IPL = 1; the others are G = 64 with IPL = cap / 64.
+constexpr int kRayClasses = 13;
+constexpr int kRayCap[kRayClasses] = {16, 64, 128, 192, 256, 320, 384, 512, 640, 768, 1024, 1536, 2048};
+
+// Edges are stored in tiles of 4x4 pixels, step-major: slot of (ray lane i,
+// step k) = tile_base + 16 k + i.  Rays of one camera reach a voxel after the
+// same number of 3D-DDA steps, so the edges a voxel receives from one tile
+// share a 64-byte line.
+constexpr int kTileW = 4;
+constexpr int kTile = kTileW * kTileW;
+
+// Voxel work classes by degree: (waves per voxel NW, items per lane IPL);
+// each wave owns 64*IPL consecutive edges of the voxel.  Above the last
+// class a 1024-thread block walks 256-edge chunks twice.
+constexpr int kVoxClasses = 6;
+constexpr int kVoxCap[kVoxClasses - 1] = {64, 256, 1024, 4096, 16384};
+constexpr int kVoxChunk = 256;
+constexpr int kVoxMaxChunks = 4096;   // degree limit 1048576
+
+// Voxels are keyed brick-major (8^3 bricks) for the voxel -> ray incidence so
+// that one brick's voxels, which share most of their rays, are adjacent.
+constexpr int kBrick = 8;
 
 struct SceneDev {
     int32_t W, H;
@@ -33,33 +49,34 @@ struct SceneDev {
     double o[3];
     int64_t voxel_base;
     int64_t ray_base;
+    int32_t nb[3];        // bricks per axis
+    int32_t pad2;
+    int64_t key_base;     // first brick-major key of this scene
 };
 
 struct FrameDev {
     const float* depth;   // H*W
     const double* T;      // 16
     int32_t scene;
-    int32_t pad;
+    int32_t ntx;          // tiles per image row
     int64_t ray_base;     // global id of pixel (0, 0)
+    int64_t tile_base;    // global id of the frame's first tile
+};
+
+// One 4x4-pixel tile: its slots are [base, base + 16 len).
+struct TileDev {
+    int64_t base;
+    int32_t ray0;         // global ray id of the tile's top-left pixel
+    int32_t W;            // image width (ray id stride between tile rows)
+    int32_t nu, nv;       // pixels of the tile inside the image
+    int32_t len;          // longest ray of the tile (steps)
+    int32_t pad;
 };
 
 struct BuildDev {
     double z_min, z_max, nsig, c0, c2, smin, dmax;
     int32_t min_vox;
     int32_t pad;
-};
-
-// Pieces of hub voxels (degree > kPiece).
-struct HubTables {
-    uint32_t n_hubs = 0, n_pieces = 0;
-    uint32_t* hub_voxel = nullptr;        // n_hubs
-    uint32_t* hub_piece0 = nullptr;       // n_hubs + 1
-    uint32_t* piece_voxel = nullptr;      // n_pieces
-    int64_t* piece_start = nullptr;       // n_pieces
-    uint32_t* piece_len = nullptr;        // n_pieces
-    float* piece_sum = nullptr;           // n_pieces
-    float* piece_pre = nullptr;           // n_pieces
-    float* piece_suf = nullptr;           // n_pieces
 };
 
 struct DevBuf {
@@ -69,10 +86,9 @@ struct DevBuf {
 
 // Kernel launches that the profiler can time individually.
 enum KernelId {
-    KID_VOX0 = 0, KID_VOX1, KID_VOX2, KID_VOX3, KID_HUB_SUM, KID_HUB_CARRY, KID_HUB_PIECE,
-    KID_RAY0, KID_RAY1, KID_RAY2, KID_RAY3, KID_RAY4,
-    KID_ADJ0, KID_ADJ1, KID_ADJ2, KID_ADJ3, KID_ADJ4,
-    KID_POT, KID_SIGMA, KID_COUNT
+    KID_VOX0 = 0,
+    KID_RAY0 = KID_VOX0 + kVoxClasses, KID_ADJ0 = KID_RAY0 + kRayClasses,
+    KID_POT = KID_ADJ0 + kRayClasses, KID_SIGMA, KID_COUNT
 };
 
 // HIP events recorded around launches on the stream they run on.
@@ -101,6 +117,9 @@ struct mrf_ctx {
     // graph description
     int32_t n_scenes = 0;
     int64_t R = 0, E = 0, V = 0;
+    int64_t S = 0;                        // edge slots (E plus tile padding)
+    int64_t T = 0;                        // tiles
+    int64_t Vk = 0;                       // brick-major key space (>= V, padded bricks)
     int32_t n_frames = 0, max_hw = 0;
     std::vector<mrf::SceneDev> scenes_h;
     std::vector<mrf::FrameDev> frames_h;
@@ -112,17 +131,19 @@ struct mrf_ctx {
     mrf::DevBuf b_scenes, b_frames, b_counts, b_rowptr, b_col, b_delta, b_bin, b_tin, b_tout,
         b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_ckpt,
         b_ellbar, b_lambar, b_gsum, b_tmp64, b_cls, b_sigpart, b_misc;
-    mrf::DevBuf b_ray_list[mrf::kRayClasses];
-    mrf::DevBuf b_vox_list[mrf::kVoxClasses];
-    mrf::DevBuf b_hub[8];
+    mrf::DevBuf b_tiles, b_tbase;
+    mrf::DevBuf b_export;     // temporaries of the canonical incidence export
+    mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
+    mrf::DevBuf b_vox_list[mrf::kVoxClasses];     // brick-major keys
+    mrf::DevBuf b_vox_ext[mrf::kVoxClasses];      // matching linear voxel ids
     mrf::DevBuf b_frame_list;     // per-frame ray lists for the plain schedule
 
-    int64_t ray_cnt[mrf::kRayClasses] = {0};
+    int64_t ray_cnt[mrf::kRayClasses] = {0};       // tiles per class
     int64_t vox_cnt[mrf::kVoxClasses] = {0};
     int64_t ray_cls_edges[mrf::kRayClasses] = {0};
-    int64_t vox_cls_edges[mrf::kVoxClasses + 1] = {0};   // last entry: hub voxels
-    std::vector<int64_t> frame_ray_off;   // plain schedule: rays of frame f at [off[f], off[f+1])
-    mrf::HubTables hub;
+    int64_t vox_cls_edges[mrf::kVoxClasses] = {0};
+    std::vector<int64_t> frame_ray_off;   // plain schedule: tiles of frame f at [off[f], off[f+1])
+    int64_t ray_cls_rays[mrf::kRayClasses] = {0};
 
     // stats
     mrf_stats_t stats{};
@@ -176,6 +197,13 @@ size_t radix_hist_entries(int64_t n);
 hipError_t launch_vptr_from_sorted(const uint32_t* sorted_keys, int64_t n, int64_t V, int64_t* vptr,
                                    hipStream_t s);
 hipError_t build_classes(mrf_ctx* c, hipStream_t s);
+// canonical (linear voxel id, edge id = row_ptr[ray] + step) incidence
+hipError_t export_canonical_incidence(const mrf_ctx* c, int64_t* vptr, uint32_t* vedge, hipStream_t s);
+// per-edge array from slot order to canonical edge order
+hipError_t export_canonical_edges(const mrf_ctx* c, const void* in_slots, void* out, int elem_bytes, hipStream_t s);
+hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s);
+hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
 // sweep_kernels.hip
 hipError_t launch_potentials(mrf_ctx* c, hipStream_t s);

@@ -46,7 +46,10 @@ __global__ void gather_voxel_k(const int32_t* __restrict__ col, const float* __r
                                float* __restrict__ edge, int64_t E)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x)
-        edge[i] = vox[col[i]];
+    {
+        const int32_t v = col[i];
+        if (v >= 0) edge[i] = vox[v];   // padding slots carry col = -1
+    }
 }
 
 __global__ void sigmoid_k(const float* __restrict__ L, float* __restrict__ p, int64_t n)
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ de
     __syncthreads();
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
         const int b = bin[e];
+        if (b >= kBins) continue;   // padding slot
         const float x = delta[e] * inv[b];
         g[e] = -0.5f * x * x - cst[b];
     }
@@ -110,29 +114,46 @@ hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s)
 
 hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 {
-    if (c->E <= 0) return hipSuccess;
+    if (c->S <= 0) return hipSuccess;
     ProfScope ps(c, KID_POT, s);
-    hipLaunchKernelGGL(potentials_k, dim3(grid_for(c->E)), dim3(256), 0, s, (const float*)c->b_delta.p,
-                       (const uint8_t*)c->b_bin.p, c->E, (const float*)c->b_sigma.p, (float*)c->b_g.p);
+    hipLaunchKernelGGL(potentials_k, dim3(grid_for(c->S)), dim3(256), 0, s, (const float*)c->b_delta.p,
+                       (const uint8_t*)c->b_bin.p, c->S, (const float*)c->b_sigma.p, (float*)c->b_g.p);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ voxel phase
 
-// One voxel segment [s, s+m) of the voxel->ray CSR held by a group of G lanes,
-// IPL striped items per lane.  pre0 / suf0 are the sums of the segment's
-// edges before / after this piece (0 unless a hub is split).
-template <int G, int IPL>
-__device__ __forceinline__ float voxel_segment(int64_t s, int m, const uint32_t* __restrict__ vedge,
-                                               const float* __restrict__ in, float* __restrict__ out, float b0,
-                                               float pre0, float suf0)
+constexpr int VIPL = kVoxChunk / 64;   // items per lane in a 256-edge chunk
+
+// Sum of chunk c of the segment [s, s+m) (every lane gets it).
+__device__ __forceinline__ float vox_chunk_sum(int64_t s, int m, int c, const uint32_t* __restrict__ vedge,
+                                               const float* __restrict__ in)
 {
-    const int l = glane<G>();
-    float x[IPL];
-    uint32_t e[IPL];
+    const int l = threadIdx.x & 63;
+    float acc = 0.0f;
+    if (in) {
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const int i = k * G + l;
+        for (int k = 0; k < VIPL; ++k) {
+            const int i = c * kVoxChunk + k * 64 + l;
+            if (i < m) acc += in[vedge[s + i]];
+        }
+    }
+    return wave_sum(acc);
+}
+
+// Chunk c of the segment: out_e = (b0 + sum of earlier edges) + sum of later
+// edges, with pre0 / suf0 the sums of the chunks before / after this one.
+// Returns pre0 + the chunk's sum.
+__device__ __forceinline__ float vox_chunk(int64_t s, int m, int c, const uint32_t* __restrict__ vedge,
+                                           const float* __restrict__ in, float* __restrict__ out, float b0,
+                                           float pre0, float suf0)
+{
+    const int l = threadIdx.x & 63;
+    float x[VIPL];
+    uint32_t e[VIPL];
+#pragma unroll
+    for (int k = 0; k < VIPL; ++k) {
+        const int i = c * kVoxChunk + k * 64 + l;
         e[k] = 0;
         x[k] = 0.0f;
         if (i < m) {
@@ -140,43 +161,96 @@ __device__ __forceinline__ float voxel_segment(int64_t s, int m, const uint32_t*
             if (in) x[k] = in[e[k]];
         }
     }
-    float pre[IPL];
+    float pre[VIPL];
     float carry = pre0;
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const float incl = gscan_add<G>(x[k]) + carry;
-        const float up = gshfl_up<G>(incl, 1);
-        pre[k] = l == 0 ? carry : up;
-        carry = gbcast<G>(incl, G - 1);
+    for (int k = 0; k < VIPL; ++k) {
+        const float incl = dscan<64, OpAdd>(x[k]) + carry;
+        pre[k] = dexcl<64>(incl, carry);
+        carry = readlane(incl, 63);
     }
     if (out) {
         float sc = suf0;
 #pragma unroll
-        for (int k = IPL - 1; k >= 0; --k) {
-            const float incl = grscan_add<G>(x[k]) + sc;
-            const float dn = gshfl_down<G>(incl, 1);
-            const float suf = l == G - 1 ? sc : dn;
-            sc = gbcast<G>(incl, 0);
-            if (k * G + l < m) out[e[k]] = (b0 + pre[k]) + suf;
+        for (int k = VIPL - 1; k >= 0; --k) {
+            const float incl = drscan<64, OpAdd>(x[k]) + sc;
+            const float suf = drexcl<64>(incl, sc);
+            sc = readlane(incl, 0);
+            if (c * kVoxChunk + k * 64 + l < m) out[e[k]] = (b0 + pre[k]) + suf;
         }
     }
-    return carry;   // pre0 + sum of this piece
+    return carry;
 }
 
-template <int G, int IPL>
-__global__ __launch_bounds__(256) void voxel_k(const uint32_t* __restrict__ vox, int64_t n,
-                                               const int64_t* __restrict__ vptr, const uint32_t* __restrict__ vedge,
-                                               const float* __restrict__ base, const float* __restrict__ in,
-                                               float* __restrict__ out, float* __restrict__ total, int total_mode)
+// One voxel's edge list [s, s+m) held by NW waves, each owning 64*IPL
+// consecutive edges (striped over its lanes) gathered once into registers.
+// Waves exchange their sums through LDS for the carries.  NW == 1 packs four
+// voxels per 256-thread block.  Voxels arrive in brick-major order and blocks
+// are remapped so each XCD takes a contiguous range of them.
+template <int NW, int IPL>
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ext, int64_t n, const int64_t* __restrict__ vptr,
+    const uint32_t* __restrict__ vedge, const float* __restrict__ base, const float* __restrict__ in,
+    float* __restrict__ out, float* __restrict__ total, int total_mode)
 {
-    const int64_t gid = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
-    if (gid >= n) return;
-    const uint32_t v = vox[gid];
-    const int64_t s = vptr[v];
-    const int m = (int)(vptr[v + 1] - s);
+    constexpr int SPAN = 64 * IPL;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t vi = NW == 1 ? lb * 4 + wv : lb;
+    const int part = NW == 1 ? 0 : wv;
+    if (vi >= n) return;   // whole waves (NW == 1) or whole blocks (NW > 1)
+    const uint32_t key = keys[vi], v = ext[vi];
+    const int64_t s = vptr[key];
+    const int m = (int)(vptr[key + 1] - s);
     const float b0 = base ? base[v] : 0.0f;
-    const float tot = voxel_segment<G, IPL>(s, m, vedge, in, out, b0, 0.0f, 0.0f);
-    if (total_mode && glane<G>() == 0) {
+
+    float x[IPL];
+    uint32_t e[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = part * SPAN + k * 64 + l;
+        e[k] = 0;
+        x[k] = 0.0f;
+        if (i < m) {
+            e[k] = vedge[s + i];
+            if (in) x[k] = in[e[k]];
+        }
+    }
+    float pre0 = 0.0f, suf0 = 0.0f, tot = 0.0f;
+    if (NW > 1) {
+        __shared__ float wsum[NW > 1 ? NW : 1];
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) a += x[k];
+        a = wave_sum(a);
+        if (l == 0) wsum[wv] = a;
+        __syncthreads();
+        for (int q = 0; q < NW; ++q) {
+            if (q < wv) pre0 += wsum[q];
+            tot += wsum[q];
+        }
+        for (int q = NW - 1; q > wv; --q) suf0 += wsum[q];
+    }
+    float pre[IPL];
+    float carry = pre0;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const float incl = dscan<64, OpAdd>(x[k]) + carry;
+        pre[k] = dexcl<64>(incl, carry);
+        carry = readlane(incl, 63);
+    }
+    if (NW == 1) tot = carry;
+    if (out) {
+        float sc = suf0;
+#pragma unroll
+        for (int k = IPL - 1; k >= 0; --k) {
+            const float incl = drscan<64, OpAdd>(x[k]) + sc;
+            const float suf = drexcl<64>(incl, sc);
+            sc = readlane(incl, 0);
+            if (part * SPAN + k * 64 + l < m) out[e[k]] = (b0 + pre[k]) + suf;
+        }
+    }
+    if (total_mode && l == 0 && part == 0) {
         if (total_mode == 1)
             total[v] = b0 + tot;
         else
@@ -184,157 +258,169 @@ __global__ __launch_bounds__(256) void voxel_k(const uint32_t* __restrict__ vox,
     }
 }
 
-// hub pieces: sums, per-hub carries (sequential, fixed order), final pass
-__global__ __launch_bounds__(256) void hub_sum_k(HubTables H, const uint32_t* __restrict__ vedge,
-                                                 const float* __restrict__ in)
+// One 1024-thread block per voxel of degree above the largest single-pass
+// class: chunk sums into LDS, exclusive prefix / suffix of the chunk sums by
+// wave 0 in fixed order, then every wave revisits its chunks with both carries.
+__global__ __launch_bounds__(1024) void voxel_chunked_k(const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ ext, int64_t n,
+                                                        const int64_t* __restrict__ vptr,
+                                                        const uint32_t* __restrict__ vedge,
+                                                        const float* __restrict__ base, const float* __restrict__ in,
+                                                        float* __restrict__ out, float* __restrict__ total,
+                                                        int total_mode)
 {
-    const int64_t p = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 64;
-    if (p >= H.n_pieces) return;
-    const int l = threadIdx.x & 63;
-    const int64_t s = H.piece_start[p];
-    const int m = (int)H.piece_len[p];
-    float acc = 0.0f;
-    for (int i = l; i < m; i += 64) acc += in ? in[vedge[s + i]] : 0.0f;
-    acc = greduce_add<64>(acc);
-    if (l == 0) H.piece_sum[p] = acc;
-}
-
-__global__ void hub_carry_k(HubTables H, const float* __restrict__ base, float* __restrict__ total, int total_mode)
-{
-    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= H.n_hubs) return;
-    const uint32_t p0 = H.hub_piece0[h], p1 = H.hub_piece0[h + 1];
-    float run = 0.0f;
-    for (uint32_t p = p0; p < p1; ++p) {
-        H.piece_pre[p] = run;
-        run += H.piece_sum[p];
-    }
-    float suf = 0.0f;
-    for (uint32_t p = p1; p-- > p0;) {
-        H.piece_suf[p] = suf;
-        suf += H.piece_sum[p];
-    }
-    const uint32_t v = H.hub_voxel[h];
-    if (total_mode == 1)
-        total[v] = (base ? base[v] : 0.0f) + run;
-    else if (total_mode == 2)
-        total[v] += run;
-}
-
-__global__ __launch_bounds__(256) void hub_piece_k(HubTables H, const uint32_t* __restrict__ vedge,
-                                                   const float* __restrict__ base, const float* __restrict__ in,
-                                                   float* __restrict__ out)
-{
-    const int64_t p = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 64;
-    if (p >= H.n_pieces) return;
-    const uint32_t v = H.piece_voxel[p];
+    __shared__ float csum[kVoxMaxChunks];
+    __shared__ float cpre[kVoxMaxChunks];
+    __shared__ float csuf[kVoxMaxChunks];
+    __shared__ float stot;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= n) return;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint32_t key = keys[b], v = ext[b];
+    const int64_t s = vptr[key];
+    const int m = (int)(vptr[key + 1] - s);
     const float b0 = base ? base[v] : 0.0f;
-    voxel_segment<64, kPiece / 64>(H.piece_start[p], (int)H.piece_len[p], vedge, in, out, b0, H.piece_pre[p],
-                                   H.piece_suf[p]);
+    const int nch = (m + kVoxChunk - 1) / kVoxChunk;   // <= kVoxMaxChunks (checked at build)
+    for (int c = wv; c < nch; c += 16) {
+        const float cs = vox_chunk_sum(s, m, c, vedge, in);
+        if (l == 0) csum[c] = cs;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        float carry = 0.0f;
+        for (int c0 = 0; c0 < nch; c0 += 64) {
+            const float x = c0 + l < nch ? csum[c0 + l] : 0.0f;
+            const float incl = dscan<64, OpAdd>(x) + carry;
+            if (c0 + l < nch) cpre[c0 + l] = dexcl<64>(incl, carry);
+            carry = readlane(incl, 63);
+        }
+        if (l == 0) stot = carry;
+        float sc = 0.0f;
+        for (int c0 = ((nch - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
+            const float x = c0 + l < nch ? csum[c0 + l] : 0.0f;
+            const float incl = drscan<64, OpAdd>(x) + sc;
+            if (c0 + l < nch) csuf[c0 + l] = drexcl<64>(incl, sc);
+            sc = readlane(incl, 0);
+        }
+    }
+    __syncthreads();
+    if (out)
+        for (int c = wv; c < nch; c += 16) vox_chunk(s, m, c, vedge, in, out, b0, cpre[c], csuf[c]);
+    if (total_mode && threadIdx.x == 0) {
+        if (total_mode == 1)
+            total[v] = b0 + stot;
+        else
+            total[v] += stot;
+    }
 }
 
-template <int G, int IPL>
-static void launch_voxel_class(const mrf_ctx* c, int k, const float* base, const float* in, float* out,
-                               float* total, int mode, hipStream_t s)
+template <int NW, int IPL>
+static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float* in, float* out, float* total,
+                               int mode, hipStream_t s)
 {
     const int64_t n = c->vox_cnt[k];
     if (n <= 0) return;
     ProfScope ps(c, KID_VOX0 + k, s);
-    hipLaunchKernelGGL((voxel_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
-                       (const uint32_t*)c->b_vox_list[k].p, n, (const int64_t*)c->b_vptr.p,
-                       (const uint32_t*)c->b_vedge.p, base, in, out, total, mode);
+    const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
+    hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
+                       (const uint32_t*)c->b_vox_list[k].p, (const uint32_t*)c->b_vox_ext[k].p, n,
+                       (const int64_t*)c->b_vptr.p, (const uint32_t*)c->b_vedge.p, base, in, out, total, mode);
 }
 
 hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out, float* total,
                               int total_mode, bool /*plain*/, hipStream_t s)
 {
-    launch_voxel_class<16, 1>(c, 0, base, in, out, total, total_mode, s);
-    launch_voxel_class<64, 1>(c, 1, base, in, out, total, total_mode, s);
-    launch_voxel_class<64, 4>(c, 2, base, in, out, total, total_mode, s);
-    launch_voxel_class<64, 16>(c, 3, base, in, out, total, total_mode, s);
-    const HubTables& H = c->hub;
-    if (H.n_pieces > 0) {
-        const uint32_t* ve = (const uint32_t*)c->b_vedge.p;
-        {
-            ProfScope ps(c, KID_HUB_SUM, s);
-            hipLaunchKernelGGL(hub_sum_k, dim3(nblk(H.n_pieces, 4)), dim3(256), 0, s, H, ve, in);
-        }
-        {
-            ProfScope ps(c, KID_HUB_CARRY, s);
-            hipLaunchKernelGGL(hub_carry_k, dim3(nblk(H.n_hubs, 64)), dim3(64), 0, s, H, base, total, total_mode);
-        }
-        if (out) {
-            ProfScope ps(c, KID_HUB_PIECE, s);
-            hipLaunchKernelGGL(hub_piece_k, dim3(nblk(H.n_pieces, 4)), dim3(256), 0, s, H, ve, base, in, out);
-        }
+    launch_voxel_class<1, 1>(c, 0, base, in, out, total, total_mode, s);
+    launch_voxel_class<1, 4>(c, 1, base, in, out, total, total_mode, s);
+    launch_voxel_class<1, 16>(c, 2, base, in, out, total, total_mode, s);
+    launch_voxel_class<4, 16>(c, 3, base, in, out, total, total_mode, s);
+    launch_voxel_class<16, 16>(c, 4, base, in, out, total, total_mode, s);
+    const int kc = kVoxClasses - 1;
+    if (c->vox_cnt[kc] > 0) {
+        ProfScope ps(c, KID_VOX0 + kc, s);
+        hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, s,
+                           (const uint32_t*)c->b_vox_list[kc].p, (const uint32_t*)c->b_vox_ext[kc].p,
+                           c->vox_cnt[kc], (const int64_t*)c->b_vptr.p, (const uint32_t*)c->b_vedge.p, base, in,
+                           out, total, total_mode);
     }
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ ray phase
 
+// One group of G lanes per ray, blocked: lane l holds steps [l IPL, (l+1) IPL).
+// Each scan runs sequentially inside a lane and once across lanes on the
+// lane aggregates.
 template <int G, int IPL>
-__global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ rays, int64_t n,
-                                             const int64_t* __restrict__ row_ptr, const float* __restrict__ lam,
-                                             const float* __restrict__ g, float* __restrict__ ell)
+__global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                             const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
+                                             const float* __restrict__ lam, const float* __restrict__ g,
+                                             float* __restrict__ ell)
 {
-    const int64_t gid = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
-    if (gid >= n) return;
-    const int l = glane<G>();
-    const uint32_t r = rays[gid];
-    const int64_t s = row_ptr[r];
-    const int m = (int)(row_ptr[r + 1] - s);
+    static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
+    int64_t s;
+    int m;
+    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
+    const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
 
-    float al[IPL], be[IPL], gg[IPL], P[IPL], S[IPL];
+    float al[IPL], be[IPL], gg[IPL];
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const int i = k * G + l;
+    for (int j = 0; j < IPL; ++j) {
+        const int i = i0 + j;
         if (i < m) {
-            const float x = lam[s + i];
+            const float x = lam[s + kTile * i];
             const float sp = softplus(x);
-            al[k] = -sp;          // log mu(o=0)
-            be[k] = x - sp;       // log mu(o=1)
-            gg[k] = g[s + i];
+            al[j] = -sp;          // log mu(o=0)
+            be[j] = x - sp;       // log mu(o=1)
+            gg[j] = g[s + kTile * i];
         } else {                  // neutral padding
-            al[k] = 0.0f;
-            be[k] = MRF_NINF;
-            gg[k] = 0.0f;
+            al[j] = 0.0f;
+            be[j] = MRF_NINF;
+            gg[j] = 0.0f;
         }
     }
-    // P: exclusive prefix sum of log mu(0)
-    float cp = 0.0f;
+    // P_i = sum_{k<i} log mu_k(0)
+    float P[IPL];
+    {
+        float a = 0.0f;
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const float incl = gscan_add<G>(al[k]) + cp;
-        const float up = gshfl_up<G>(incl, 1);
-        P[k] = l == 0 ? cp : up;
-        cp = gbcast<G>(incl, G - 1);
+        for (int j = 0; j < IPL; ++j) a += al[j];
+        float p = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            P[j] = p;
+            p += al[j];
+        }
     }
-    // S: exclusive prefix LSE of W_j = log mu_j(1) + g_j + P_j
-    float cs = MRF_NINF;
+    // S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)
+    float S[IPL];
+    {
+        float w = MRF_NINF;
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const float incl = lse(cs, gscan_lse<G>(be[k] + gg[k] + P[k]));
-        const float up = gshfl_up<G>(incl, 1);
-        S[k] = l == 0 ? cs : up;
-        cs = gbcast<G>(incl, G - 1);
+        for (int j = 0; j < IPL; ++j) w = lse(w, be[j] + gg[j] + P[j]);
+        float sc = dexcl<G>(dscan<G, OpLse>(w), MRF_NINF);
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            S[j] = sc;
+            sc = lse(sc, be[j] + gg[j] + P[j]);
+        }
     }
-    // Q: exclusive suffix composition of x -> LSE(c_j, a_j + x), then ell
-    LMap cq{0.0f, MRF_NINF};
+    // Q_i = LSE(c_{i+1}, log mu_{i+1}(0) + Q_{i+1}): compose the lane's maps,
+    // scan the lane maps from the right, then walk the lane backwards
+    LMap lm = lmap_id();
 #pragma unroll
-    for (int k = IPL - 1; k >= 0; --k) {
-        LMap mp{al[k], be[k] + gg[k]};
-        LMap incl = lmap_compose(grscan_lmap<G>(mp), cq);
-        const float dn = gshfl_down<G>(incl.c, 1);
-        const float Q = l == G - 1 ? cq.c : dn;
-        cq.a = gbcast<G>(incl.a, 0);
-        cq.c = gbcast<G>(incl.c, 0);
-        const int i = k * G + l;
+    for (int j = IPL - 1; j >= 0; --j) lm = lmap_compose(LMap{al[j], be[j] + gg[j]}, lm);
+    const LMap right = drscan_lmap<G>(lm);
+    float Q = drexcl<G>(right.c, MRF_NINF);
+#pragma unroll
+    for (int j = IPL - 1; j >= 0; --j) {
+        const int i = i0 + j;
         if (i < m) {
-            const float m1 = lse(S[k], gg[k] + P[k]);
-            const float m0 = lse(S[k], P[k] + Q);
-            ell[s + i] = m1 - m0;
+            const float m1 = lse(S[j], gg[j] + P[j]);
+            const float m0 = lse(S[j], P[j] + Q);
+            ell[s + kTile * i] = m1 - m0;
         }
+        Q = lse(be[j] + gg[j], al[j] + Q);
     }
 }
 
@@ -344,9 +430,9 @@ static void launch_ray_class(const mrf_ctx* c, int k, int64_t off, int64_t n, co
 {
     if (n <= 0) return;
     ProfScope ps(c, KID_RAY0 + k, s);
-    hipLaunchKernelGGL((ray_k<G, IPL>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
-                       (const uint32_t*)c->b_ray_list[k].p + off, n, (const int64_t*)c->b_rowptr.p, lam,
-                       (const float*)c->b_g.p, ell);
+    hipLaunchKernelGGL((ray_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+                       (const uint32_t*)c->b_ray_list[k].p + off, n, (const TileDev*)c->b_tiles.p,
+                       (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ell);
 }
 
 static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt, const float* lam, float* ell,
@@ -354,9 +440,17 @@ static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt
 {
     launch_ray_class<16, 1>(c, 0, off[0], cnt[0], lam, ell, s);
     launch_ray_class<64, 1>(c, 1, off[1], cnt[1], lam, ell, s);
-    launch_ray_class<64, 4>(c, 2, off[2], cnt[2], lam, ell, s);
-    launch_ray_class<64, 16>(c, 3, off[3], cnt[3], lam, ell, s);
-    launch_ray_class<64, 32>(c, 4, off[4], cnt[4], lam, ell, s);
+    launch_ray_class<64, 2>(c, 2, off[2], cnt[2], lam, ell, s);
+    launch_ray_class<64, 3>(c, 3, off[3], cnt[3], lam, ell, s);
+    launch_ray_class<64, 4>(c, 4, off[4], cnt[4], lam, ell, s);
+    launch_ray_class<64, 5>(c, 5, off[5], cnt[5], lam, ell, s);
+    launch_ray_class<64, 6>(c, 6, off[6], cnt[6], lam, ell, s);
+    launch_ray_class<64, 8>(c, 7, off[7], cnt[7], lam, ell, s);
+    launch_ray_class<64, 10>(c, 8, off[8], cnt[8], lam, ell, s);
+    launch_ray_class<64, 12>(c, 9, off[9], cnt[9], lam, ell, s);
+    launch_ray_class<64, 16>(c, 10, off[10], cnt[10], lam, ell, s);
+    launch_ray_class<64, 24>(c, 11, off[11], cnt[11], lam, ell, s);
+    launch_ray_class<64, 32>(c, 12, off[12], cnt[12], lam, ell, s);
 }
 
 hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain, hipStream_t s)

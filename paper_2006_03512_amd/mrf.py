@@ -31,6 +31,8 @@ class GraphStats:
     ray_len_hist: list
     voxel_degree_hist: list
     fwd_bytes_per_sweep: float
+    n_slots: int
+    n_tiles: int
 
 
 class RayMRF:
@@ -125,7 +127,8 @@ class RayMRF:
         check(self._L.mrf_stats(self._h, C.byref(st)), "mrf_stats")
         return GraphStats(st.n_scenes, st.n_rays, st.n_edges, st.n_voxels, st.n_kept_rays,
                           st.n_touched_voxels, st.max_ray_len, st.max_voxel_degree,
-                          list(st.ray_len_hist), list(st.voxel_degree_hist), st.fwd_bytes_per_sweep)
+                          list(st.ray_len_hist), list(st.voxel_degree_hist), st.fwd_bytes_per_sweep,
+                          st.n_slots, st.n_tiles)
 
     def set_schedule(self, schedule: str):
         code = {"plain": _lib.MRF_SCHED_PLAIN, "graph": _lib.MRF_SCHED_GRAPH}[schedule]

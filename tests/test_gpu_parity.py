@@ -66,6 +66,14 @@ def test_incidence_bit_exact(oracle, RayMRF, name):
     np.testing.assert_array_equal(inc["vedge"].view(np.uint32).astype(np.int64), G.vedge)
     np.testing.assert_array_equal(edg["bin"].astype(np.int32), G.bin)
     np.testing.assert_array_equal(edg["delta"], G.delta.astype(np.float32))
+    st = m.stats()
+    deg = np.diff(G.vptr)
+    lens = np.diff(G.row_ptr)
+    assert st.n_edges == G.n_edges and st.n_rays == G.n_rays
+    assert st.n_touched_voxels == int((deg > 0).sum())
+    assert st.n_kept_rays == int((lens > 0).sum())
+    assert st.max_ray_len == int(lens.max()) and st.max_voxel_degree == int(deg.max())
+    assert st.n_slots >= st.n_edges
 
 
 def test_incidence_multi_scene_bit_exact(oracle, RayMRF):
