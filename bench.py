@@ -42,6 +42,26 @@ WORKLOADS = {
 }
 
 
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script
+# (FETCH_SIZE, then WRITE_SIZE; each run also times one plain copy through
+# --calib-copy-mib, which calibrates the counter: FETCH_SIZE read 0.5 x the bytes
+# the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid only while the
+# kernel sources hash to `csrc_sha256`; otherwise traffic is reported as null.
+TRAFFIC = None
+
+
+def csrc_sha256():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2006_03512_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -100,6 +120,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=float, default=0.25, help="fraction of frame-0 rows the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="time one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,6 +136,14 @@ def main():
     from paper_2006_03512_amd.mrf import RayMRF
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+        del src, dst
     desc, K, backward = WORKLOADS[args.workload]
     t = time.perf_counter()
     scs = make_scene(args.workload, args.frames, args.c5_scale)
@@ -184,10 +214,14 @@ def main():
     dom = max(prof, key=lambda k: k["avg_ms"] * k["launches"] / args.profile_reps)
     ach = dom["bytes_per_launch"] / (dom["avg_ms"] / 1e3) / 1e9
     sweep_ms = sum(k["avg_ms"] * k["launches"] for k in prof
-                   if k["name"].startswith(("voxel", "hub", "ray_k"))) / args.profile_reps
+                   if k["name"].startswith(("voxel", "ray_k", "ray_lds_k"))) / args.profile_reps
     fwd_bytes = st.fwd_bytes_per_sweep
+    traffic = None
+    if (TRAFFIC is not None and TRAFFIC["workload"] == args.workload and TRAFFIC["kernel"] == dom["name"]
+            and args.frames is None and TRAFFIC["csrc_sha256"] == csrc_sha256()):
+        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom["name"],
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
                 "kernel_avg_ms": round(dom["avg_ms"], 4),
                 "bytes_per_launch": dom["bytes_per_launch"],
                 "sweep_ms": round(sweep_ms, 3),

@@ -26,38 +26,17 @@ namespace mrf {
 
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// Blocked like the forward ray kernel: lane l holds steps [l IPL, (l+1) IPL);
-// every recurrence runs sequentially inside the lane after one group scan of
-// the lane aggregates.
+// Reverse pass of one ray, blocked like the forward ray kernel: lane l holds
+// steps [i0, i0 + IPL) with i0 = l IPL; al / be / gg are base-2 log mu(0),
+// log mu(1) and g of those steps (neutral padding beyond m), eb the incoming
+// d/d ell.  Outputs d/d lambda and d/d g per step.  Every recurrence runs
+// sequentially inside the lane after one group scan of the lane aggregates.
 template <int G, int IPL>
-__global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ list, int64_t ntiles,
-                                                 const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
-                                                 const float* __restrict__ lam, const float* __restrict__ g,
-                                                 const float* __restrict__ ellbar, float* __restrict__ lambar,
-                                                 float* __restrict__ gsum, int first)
+__device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float (&be)[IPL], const float (&gg)[IPL],
+                                             const float (&eb)[IPL], int m, int i0, float (&lamb)[IPL],
+                                             float (&gb)[IPL])
 {
-    static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
-    int64_t s;
-    int m;
-    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
-    const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
-
-    float al[IPL], be[IPL], gg[IPL], P[IPL], S[IPL], Q[IPL];
-#pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        const int i = i0 + j;
-        if (i < m) {
-            const float x = lam[s + kTile * i];
-            const float sp = softplus(x);
-            al[j] = -sp;
-            be[j] = x - sp;
-            gg[j] = g[s + kTile * i];
-        } else {
-            al[j] = 0.0f;
-            be[j] = MRF_NINF;
-            gg[j] = 0.0f;
-        }
-    }
+    float P[IPL], S[IPL], Q[IPL];
     // ---- forward recomputation (as in the ray phase)
     {
         float a = 0.0f;
@@ -89,20 +68,20 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
             q = lse(be[j] + gg[j], al[j] + q);
         }
     }
-    // ---- direct partials of ell_i = M1_i - M0_i
-    float Fd[IPL], Bb[IPL], gb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
+    // ---- direct partials of ell_i = M1_i - M0_i (softmax weights are base-free)
+    float Fd[IPL], Bb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const bool ok = i0 + j < m;
-        const float e = ok ? ellbar[s + kTile * (i0 + j)] : 0.0f;
+        const float e = ok ? eb[j] : 0.0f;
         const float A = gg[j] + P[j];
         const float B = P[j] + Q[j];
         const float m1 = lse(S[j], A);
         const float m0 = lse(S[j], B);
-        // exp(-inf - finite) = 0 covers S_0 = -inf and Q_{N-1} = -inf
-        Fd[j] = ok ? e * (__expf(S[j] - m1) - __expf(S[j] - m0)) : 0.0f;
-        const float Ab = ok ? e * __expf(A - m1) : 0.0f;
-        Bb[j] = ok ? -e * __expf(B - m0) : 0.0f;
+        // 2^(-inf - finite) = 0 covers S_0 = -inf and Q_{N-1} = -inf
+        Fd[j] = ok ? e * (ex2(S[j] - m1) - ex2(S[j] - m0)) : 0.0f;
+        const float Ab = ok ? e * ex2(A - m1) : 0.0f;
+        Bb[j] = ok ? -e * ex2(B - m0) : 0.0f;
         gb[j] = Ab;
         Pb[j] = Ab + Bb[j];
         lab[j] = 0.0f;
@@ -120,8 +99,8 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
             rho[j] = 0.0f;
             kap[j] = 0.0f;
             if (i >= 1 && i < m) {
-                rho[j] = __expf(al[j] + Q[j] - qprev);
-                kap[j] = __expf(be[j] + gg[j] - qprev);
+                rho[j] = ex2(al[j] + Q[j] - qprev);
+                kap[j] = ex2(be[j] + gg[j] - qprev);
             }
             lm = amap_then(lm, AMap{rho[j], Bb[j]});
         }
@@ -151,8 +130,8 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
             rr[j] = 0.0f;
             ww[j] = 0.0f;
             if (i + 1 < m) {
-                rr[j] = __expf(S[j] - snext);
-                ww[j] = __expf(be[j] + gg[j] + P[j] - snext);
+                rr[j] = ex2(S[j] - snext);
+                ww[j] = ex2(be[j] + gg[j] + P[j] - snext);
             }
             lm = amap_then(lm, AMap{rr[j], Fd[j]});
         }
@@ -178,34 +157,147 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
         float sc = drexcl<G>(drscan<G, OpAdd>(a), 0.0f);
 #pragma unroll
         for (int j = IPL - 1; j >= 0; --j) {
-            const int i = i0 + j;
-            if (i < m) {
-                const float lb = lab[j] + sc;
-                const float aa = __expf(al[j]), bb = __expf(be[j]);
-                const int64_t at = s + kTile * i;
-                lambar[at] = -bb * lb + aa * lbb[j];
-                gsum[at] = first ? gb[j] : gsum[at] + gb[j];
-            }
+            const float lb = lab[j] + sc;
+            lamb[j] = -ex2(be[j]) * lb + ex2(al[j]) * lbb[j];   // d log mu(0)/d lam = -mu(1), d log mu(1)/d lam = mu(0)
             sc += Pb[j];
         }
     }
 }
 
+// base-2 log mu(0), log mu(1), g of one step (neutral padding when out of range)
+__device__ __forceinline__ void load_step(float lam, float g, bool ok, float& al, float& be, float& gg)
+{
+    if (ok) {
+        const float x = lam * kLog2e;
+        const float sp = softplus(x);
+        al = -sp;
+        be = x - sp;
+        gg = g * kLog2e;
+    } else {
+        al = 0.0f;
+        be = MRF_NINF;
+        gg = 0.0f;
+    }
+}
+
+template <int G, int IPL>
+__global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                 const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
+                                                 const float* __restrict__ lam, const float* __restrict__ g,
+                                                 const float* __restrict__ ellbar, float* __restrict__ lambar,
+                                                 float* __restrict__ gsum, int first)
+{
+    static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
+    int64_t s;
+    int m;
+    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
+    const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
+    float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        const int i = i0 + j;
+        const bool ok = i < m;
+        load_step(ok ? lam[s + kTile * i] : 0.0f, ok ? g[s + kTile * i] : 0.0f, ok, al[j], be[j], gg[j]);
+        eb[j] = ok ? ellbar[s + kTile * i] : 0.0f;
+    }
+    ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        const int i = i0 + j;
+        if (i < m) {
+            const int64_t at = s + kTile * i;
+            lambar[at] = lamb[j];
+            gsum[at] = first ? gb[j] : gsum[at] + gb[j];
+        }
+    }
+}
+
+// Tile-staged reverse pass (rays of at most 64*IPL steps, one 1024-thread
+// block per tile): lambda and g, then ell-bar, pass through padded LDS rows
+// with coalesced loads; each wave writes its column of lambda-bar and g-bar
+// (zeros past its ray), and the block stores lambda-bar and accumulates the
+// g-bar sum coalesced.
+template <int IPL>
+__global__ __launch_bounds__(1024) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                      const TileDev* __restrict__ tiles,
+                                                      const int32_t* __restrict__ counts, const float* __restrict__ lam,
+                                                      const float* __restrict__ g, const float* __restrict__ ellbar,
+                                                      float* __restrict__ lambar, float* __restrict__ gsum, int first)
+{
+    constexpr int R = kTile + 1;
+    __shared__ float sa[R * 64 * IPL];
+    __shared__ float sb[R * 64 * IPL];
+    const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
+    if (ti >= ntiles) return;   // whole block
+    const TileDev td = tiles[list[ti]];
+    const int nf = kTile * td.len;
+    for (int idx = threadIdx.x; idx < nf; idx += 1024) {
+        const int at = (idx >> 4) * R + (idx & 15);
+        sa[at] = lam[td.base + idx];
+        sb[at] = g[td.base + idx];
+    }
+    __syncthreads();
+    const int i = threadIdx.x >> 6;
+    const int i0 = (threadIdx.x & 63) * IPL;
+    int m = 0;
+    if ((i & 3) < td.nu && (i >> 2) < td.nv) m = counts[td.ray0 + (int64_t)(i >> 2) * td.W + (i & 3)];
+    float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        const int k = i0 + j;
+        const bool ok = k < m;
+        load_step(ok ? sa[k * R + i] : 0.0f, ok ? sb[k * R + i] : 0.0f, ok, al[j], be[j], gg[j]);
+    }
+    __syncthreads();   // every wave has its lambda: reuse sa for ell-bar
+    for (int idx = threadIdx.x; idx < nf; idx += 1024) sa[(idx >> 4) * R + (idx & 15)] = ellbar[td.base + idx];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        const int k = i0 + j;
+        eb[j] = k < m ? sa[k * R + i] : 0.0f;
+    }
+    if (m > 0) ray_adj_body<64, IPL>(al, be, gg, eb, m, i0, lamb, gb);   // m is uniform per wave
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        const int k = i0 + j;
+        if (k < td.len) {   // own column only; zeros past the ray
+            sa[k * R + i] = k < m ? lamb[j] : 0.0f;
+            sb[k * R + i] = k < m ? gb[j] : 0.0f;
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nf; idx += 1024) {
+        const int at = (idx >> 4) * R + (idx & 15);
+        const int64_t o = td.base + idx;
+        lambar[o] = sa[at];
+        gsum[o] = first ? sb[at] : gsum[o] + sb[at];
+    }
+}
+
 template <int G, int IPL>
 static void launch_adj_class(const mrf_ctx* c, int k, const float* lam, const float* ellbar, float* lambar,
-                             float* gsum, int first, hipStream_t s)
+                             float* gsum, int first, hipStream_t s0)
 {
     const int64_t n = c->ray_cnt[k];
     if (n <= 0) return;
+    const hipStream_t s = class_stream(c, k, s0);
     ProfScope ps(c, KID_ADJ0 + k, s);
-    hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
-                       (const uint32_t*)c->b_ray_list[k].p, n, (const TileDev*)c->b_tiles.p,
-                       (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+    if constexpr (G == 64 && IPL <= 8) {
+        hipLaunchKernelGGL((ray_adj_lds_k<IPL>), dim3((unsigned)n), dim3(1024), 0, s,
+                           (const uint32_t*)c->b_ray_list[k].p, n, (const TileDev*)c->b_tiles.p,
+                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+    } else {
+        hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+                           (const uint32_t*)c->b_ray_list[k].p, n, (const TileDev*)c->b_tiles.p,
+                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+    }
 }
 
 hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
                               bool first, hipStream_t s)
 {
+    hipError_t e;
+    if ((e = fork_streams(c, s)) != hipSuccess) return e;
     launch_adj_class<16, 1>(c, 0, lam, ellbar, lambar, gsum, first, s);
     launch_adj_class<64, 1>(c, 1, lam, ellbar, lambar, gsum, first, s);
     launch_adj_class<64, 2>(c, 2, lam, ellbar, lambar, gsum, first, s);
@@ -219,7 +311,8 @@ hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar,
     launch_adj_class<64, 16>(c, 10, lam, ellbar, lambar, gsum, first, s);
     launch_adj_class<64, 24>(c, 11, lam, ellbar, lambar, gsum, first, s);
     launch_adj_class<64, 32>(c, 12, lam, ellbar, lambar, gsum, first, s);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return join_streams(c, s);
 }
 
 // ------------------------------------------------------------ sigma table

@@ -73,6 +73,25 @@ namespace mrf {
 
 void set_error(const std::string& msg) { g_err = msg; }
 
+hipError_t fork_streams(mrf_ctx* c, hipStream_t s)
+{
+    if (!c->npar) return hipSuccess;
+    hipError_t e = hipEventRecord(c->par_fork, s);
+    for (int i = 0; i < c->npar && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->par[i], c->par_fork, 0);
+    return e;
+}
+
+hipError_t join_streams(mrf_ctx* c, hipStream_t s)
+{
+    if (!c->npar) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < c->npar && e == hipSuccess; ++i) {
+        e = hipEventRecord(c->par_join[i], c->par[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, c->par_join[i], 0);
+    }
+    return e;
+}
+
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
@@ -152,6 +171,11 @@ int mrf_create(mrf_ctx** out)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->par_fork, hipEventDisableTiming);
+    for (int i = 0; i < mrf_ctx::kPar && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&c->par[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->par_join[i], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         int rc = hip_fail(e, "mrf_create");
         mrf_destroy(c);
@@ -181,6 +205,11 @@ void mrf_destroy(mrf_ctx* c)
     for (auto& b : c->b_ray_list) free_buf(b);
     for (auto& b : c->b_vox_list) free_buf(b);
     for (auto& b : c->b_vox_ext) free_buf(b);
+    for (int i = 0; i < mrf_ctx::kPar; ++i) {
+        if (c->par_join[i]) hipEventDestroy(c->par_join[i]);
+        if (c->par[i]) hipStreamDestroy(c->par[i]);
+    }
+    if (c->par_fork) hipEventDestroy(c->par_fork);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->aux) hipStreamDestroy(c->aux);
@@ -209,7 +238,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->frames_h.clear();
     c->n_scenes = n_scenes;
     int64_t R = 0, V = 0, Vk = 0, Tn = 0;
-    int max_hw = 0;
+    int max_hw = 0, max_tpf = 0;
     for (int i = 0; i < n_scenes; ++i) {
         const mrf_scene& sc = scenes[i];
         if (sc.n_frames < 1 || !sc.depth || !sc.T_wc) return fail(MRF_EINVAL, "mrf_build: scene without frames");
@@ -238,6 +267,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         if (hw > (int64_t(1) << 30)) return fail(MRF_ERANGE, "mrf_build: image too large");
         if (hw > max_hw) max_hw = (int)hw;
         const int ntx = (d.W + kTileW - 1) / kTileW, nty = (d.H + kTileW - 1) / kTileW;
+        if (ntx * nty > max_tpf) max_tpf = ntx * nty;
         for (int f = 0; f < sc.n_frames; ++f) {
             FrameDev fr{};
             fr.depth = sc.depth + (size_t)f * hw;
@@ -262,6 +292,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->T = Tn;
     c->n_frames = (int)c->frames_h.size();
     c->max_hw = max_hw;
+    c->max_tpf = max_tpf;
     c->bp.z_min = p->z_min;
     c->bp.z_max = p->z_max;
     c->bp.nsig = p->trunc_nsigma;
@@ -411,7 +442,9 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
             drop_graph(c);
             hipGraph_t g = nullptr;
             HCK(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal), "mrf_infer: begin capture");
+            c->npar = mrf_ctx::kPar;   // class launches of a phase become parallel graph branches
             hipError_t e = enqueue_forward(c, sweeps, keep, false, c->aux);
+            c->npar = 0;
             hipError_t e2 = hipStreamEndCapture(c->aux, &g);
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
@@ -528,12 +561,14 @@ static std::string kid_name(int k)
     static const char* vox[kVoxClasses] = {"voxel_k<1,1>", "voxel_k<1,4>", "voxel_k<1,16>", "voxel_k<4,16>",
                                            "voxel_k<16,16>", "voxel_chunked_k"};
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) return vox[k - KID_VOX0];
-    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses)
-        return "ray_k<" + std::to_string(G[k - KID_RAY0]) + "," +
-               std::to_string(kRayCap[k - KID_RAY0] / G[k - KID_RAY0]) + ">";
-    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses)
-        return "ray_adj_k<" + std::to_string(G[k - KID_ADJ0]) + "," +
-               std::to_string(kRayCap[k - KID_ADJ0] / G[k - KID_ADJ0]) + ">";
+    // classes of 64-lane rays with at most 8 steps per lane use the LDS-staged kernels
+    auto ray_name = [&](const char* direct, const char* lds, int q) {
+        const int ipl = kRayCap[q] / G[q];
+        if (G[q] == 64 && ipl <= 8) return std::string(lds) + "<" + std::to_string(ipl) + ">";
+        return std::string(direct) + "<" + std::to_string(G[q]) + "," + std::to_string(ipl) + ">";
+    };
+    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) return ray_name("ray_k", "ray_lds_k", k - KID_RAY0);
+    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses) return ray_name("ray_adj_k", "ray_adj_lds_k", k - KID_ADJ0);
     if (k == KID_POT) return "potentials_k";
     if (k == KID_SIGMA) return "sigma_grad_k";
     return "?";

@@ -174,6 +174,9 @@ struct EdgeEmit {
     }
 };
 
+// Threads are grouped by tile: the 16 lanes 16t..16t+15 of a block trace the 16 pixels
+// of tile t, so at every traversal step they write one whole 64-byte line of each
+// per-slot array (a row-major pixel order would write 16-byte pieces of 16 lines).
 __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__ scenes,
                                                     const FrameDev* __restrict__ frames, BuildDev bp,
                                                     const int32_t* __restrict__ counts,
@@ -183,13 +186,17 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
 {
     const FrameDev fr = frames[blockIdx.y];
     const SceneDev& sd = scenes[fr.scene];
-    const int pix = blockIdx.x * 256 + threadIdx.x;
-    if (pix >= sd.W * sd.H) return;
+    const int nty = (sd.H + kTileW - 1) / kTileW;
+    const int lt = blockIdx.x * (256 / kTile) + (int)threadIdx.x / kTile;
+    if (lt >= fr.ntx * nty) return;
+    const int ty = lt / fr.ntx, tx = lt - ty * fr.ntx;
+    const int q = (int)threadIdx.x % kTile;
+    const int v = ty * kTileW + q / kTileW, u = tx * kTileW + q % kTileW;
+    if (v >= sd.H || u >= sd.W) return;
+    const int pix = v * sd.W + u;
     const int64_t r = fr.ray_base + pix;
     if (counts[r] == 0) return;
-    const int v = pix / sd.W, u = pix - v * sd.W;
-    const int64_t t = fr.tile_base + (int64_t)(v / kTileW) * fr.ntx + u / kTileW;
-    const int64_t slot0 = tbase[t] + (v % kTileW) * kTileW + (u % kTileW);
+    const int64_t slot0 = tbase[fr.tile_base + lt] + q;
     Ray ray;
     setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
     EdgeEmit em{col, key, delta, bin, tin, tout, &sd, slot0, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
@@ -273,7 +280,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
 
 hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s)
 {
-    dim3 grid((c->max_hw + 255) / 256, c->n_frames);
+    dim3 grid((unsigned)((c->max_tpf + 256 / kTile - 1) / (256 / kTile)), c->n_frames);
     hipLaunchKernelGGL(trace_emit_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
                        (const FrameDev*)c->b_frames.p, c->bp, (const int32_t*)c->b_counts.p,
                        (const int64_t*)c->b_tbase.p,

@@ -9,19 +9,29 @@
 
 namespace mrf {
 
-// log(exp(a) + exp(b)); log(0 + 0) = -inf.  Never forms inf - inf.
+// The message kernels work with base-2 logarithms: the hardware's v_exp_f32
+// and v_log_f32 compute 2^x and log2 x directly.  Every softmax weight
+// exp(x - y) equals 2^(x2 - y2) for the base-2 versions x2 = x log2(e), so only
+// inputs and outputs change scale.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
+
+// log2(2^a + 2^b); log2(0 + 0) = -inf.  Never forms inf - inf; no branch.
 __device__ __forceinline__ float lse(float a, float b)
 {
     const float hi = fmaxf(a, b);
     const float lo = fminf(a, b);
-    if (hi == MRF_NINF) return MRF_NINF;
-    return hi + __logf(1.0f + __expf(lo - hi));
+    const float d = hi == MRF_NINF ? MRF_NINF : lo - hi;
+    return hi + lg2(1.0f + ex2(d));
 }
 
-// log(1 + exp(x))
+// log2(1 + 2^x)
 __device__ __forceinline__ float softplus(float x)
 {
-    return fmaxf(x, 0.0f) + __logf(1.0f + __expf(-fabsf(x)));
+    return fmaxf(x, 0.0f) + lg2(1.0f + ex2(-fabsf(x)));
 }
 
 // x -> LSE(c, a + x): one voxel's step of the suffix recurrence of the second

@@ -316,10 +316,11 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const uint32_t* __restri
 
 template <int NW, int IPL>
 static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float* in, float* out, float* total,
-                               int mode, hipStream_t s)
+                               int mode, hipStream_t s0)
 {
     const int64_t n = c->vox_cnt[k];
     if (n <= 0) return;
+    const hipStream_t s = class_stream(c, k, s0);
     ProfScope ps(c, KID_VOX0 + k, s);
     const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
     hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
@@ -330,6 +331,8 @@ static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float
 hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out, float* total,
                               int total_mode, bool /*plain*/, hipStream_t s)
 {
+    hipError_t e;
+    if ((e = fork_streams(c, s)) != hipSuccess) return e;
     launch_voxel_class<1, 1>(c, 0, base, in, out, total, total_mode, s);
     launch_voxel_class<1, 4>(c, 1, base, in, out, total, total_mode, s);
     launch_voxel_class<1, 16>(c, 2, base, in, out, total, total_mode, s);
@@ -337,20 +340,22 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, fl
     launch_voxel_class<16, 16>(c, 4, base, in, out, total, total_mode, s);
     const int kc = kVoxClasses - 1;
     if (c->vox_cnt[kc] > 0) {
-        ProfScope ps(c, KID_VOX0 + kc, s);
-        hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, s,
+        const hipStream_t sc = class_stream(c, kc, s);
+        ProfScope ps(c, KID_VOX0 + kc, sc);
+        hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, sc,
                            (const uint32_t*)c->b_vox_list[kc].p, (const uint32_t*)c->b_vox_ext[kc].p,
                            c->vox_cnt[kc], (const int64_t*)c->b_vptr.p, (const uint32_t*)c->b_vedge.p, base, in,
                            out, total, total_mode);
     }
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return join_streams(c, s);
 }
 
 // ------------------------------------------------------------ ray phase
 
 // One group of G lanes per ray, blocked: lane l holds steps [l IPL, (l+1) IPL).
 // Each scan runs sequentially inside a lane and once across lanes on the
-// lane aggregates.
+// lane aggregates.  Logarithms are base 2 inside the kernel.
 template <int G, int IPL>
 __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                              const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
@@ -368,11 +373,11 @@ __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, 
     for (int j = 0; j < IPL; ++j) {
         const int i = i0 + j;
         if (i < m) {
-            const float x = lam[s + kTile * i];
+            const float x = lam[s + kTile * i] * kLog2e;
             const float sp = softplus(x);
-            al[j] = -sp;          // log mu(o=0)
-            be[j] = x - sp;       // log mu(o=1)
-            gg[j] = g[s + kTile * i];
+            al[j] = -sp;          // log2 mu(o=0)
+            be[j] = x - sp;       // log2 mu(o=1)
+            gg[j] = g[s + kTile * i] * kLog2e;
         } else {                  // neutral padding
             al[j] = 0.0f;
             be[j] = MRF_NINF;
@@ -418,21 +423,119 @@ __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, 
         if (i < m) {
             const float m1 = lse(S[j], gg[j] + P[j]);
             const float m0 = lse(S[j], P[j] + Q);
-            ell[s + kTile * i] = m1 - m0;
+            ell[s + kTile * i] = (m1 - m0) * kLn2;
         }
         Q = lse(be[j] + gg[j], al[j] + Q);
     }
 }
 
+// Tile-staged variant for rays of at most 64*IPL steps: one 1024-thread block
+// per tile.  The block copies the tile's lambda and g (16 rays x len steps,
+// contiguous) into LDS with coalesced loads, each of the 16 waves runs the
+// blocked scans of its own ray reading its LDS column, writes ell back into
+// that column, and the block stores the tile coalesced.  Rows of 16 floats
+// are padded to 17 so that a wave's column reads spread over the banks.
+constexpr int kLdsRow = kTile + 1;
+
+template <int IPL>
+__global__ __launch_bounds__(1024) void ray_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                  const TileDev* __restrict__ tiles,
+                                                  const int32_t* __restrict__ counts, const float* __restrict__ lam,
+                                                  const float* __restrict__ g, float* __restrict__ ell)
+{
+    __shared__ float sl[kLdsRow * 64 * IPL];
+    __shared__ float sg[kLdsRow * 64 * IPL];
+    const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
+    if (ti >= ntiles) return;   // whole block
+    const TileDev td = tiles[list[ti]];
+    const int nf = kTile * td.len;
+    for (int idx = threadIdx.x; idx < nf; idx += 1024) {
+        const int at = (idx >> 4) * kLdsRow + (idx & 15);
+        sl[at] = lam[td.base + idx];
+        sg[at] = g[td.base + idx];
+    }
+    __syncthreads();
+    const int i = threadIdx.x >> 6;   // this wave's ray: lane i of the tile
+    const int i0 = (threadIdx.x & 63) * IPL;
+    int m = 0;
+    if ((i & 3) < td.nu && (i >> 2) < td.nv) m = counts[td.ray0 + (int64_t)(i >> 2) * td.W + (i & 3)];
+    if (m > 0) {   // uniform per wave
+        float al[IPL], be[IPL], gg[IPL];
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            const int k = i0 + j;
+            if (k < m) {
+                const float x = sl[k * kLdsRow + i] * kLog2e;
+                const float sp = softplus(x);
+                al[j] = -sp;
+                be[j] = x - sp;
+                gg[j] = sg[k * kLdsRow + i] * kLog2e;
+            } else {
+                al[j] = 0.0f;
+                be[j] = MRF_NINF;
+                gg[j] = 0.0f;
+            }
+        }
+        float P[IPL];
+        {
+            float a = 0.0f;
+#pragma unroll
+            for (int j = 0; j < IPL; ++j) a += al[j];
+            float p = dexcl<64>(dscan<64, OpAdd>(a), 0.0f);
+#pragma unroll
+            for (int j = 0; j < IPL; ++j) {
+                P[j] = p;
+                p += al[j];
+            }
+        }
+        float S[IPL];
+        {
+            float w = MRF_NINF;
+#pragma unroll
+            for (int j = 0; j < IPL; ++j) w = lse(w, be[j] + gg[j] + P[j]);
+            float sc = dexcl<64>(dscan<64, OpLse>(w), MRF_NINF);
+#pragma unroll
+            for (int j = 0; j < IPL; ++j) {
+                S[j] = sc;
+                sc = lse(sc, be[j] + gg[j] + P[j]);
+            }
+        }
+        LMap lm = lmap_id();
+#pragma unroll
+        for (int j = IPL - 1; j >= 0; --j) lm = lmap_compose(LMap{al[j], be[j] + gg[j]}, lm);
+        const LMap right = drscan_lmap<64>(lm);
+        float Q = drexcl<64>(right.c, MRF_NINF);
+#pragma unroll
+        for (int j = IPL - 1; j >= 0; --j) {
+            const int k = i0 + j;
+            if (k < m) {
+                const float m1 = lse(S[j], gg[j] + P[j]);
+                const float m0 = lse(S[j], P[j] + Q);
+                sl[k * kLdsRow + i] = (m1 - m0) * kLn2;   // own column only
+            }
+            Q = lse(be[j] + gg[j], al[j] + Q);
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nf; idx += 1024) ell[td.base + idx] = sl[(idx >> 4) * kLdsRow + (idx & 15)];
+}
+
 template <int G, int IPL>
 static void launch_ray_class(const mrf_ctx* c, int k, int64_t off, int64_t n, const float* lam, float* ell,
-                             hipStream_t s)
+                             hipStream_t s0)
 {
     if (n <= 0) return;
+    const hipStream_t s = class_stream(c, k, s0);
     ProfScope ps(c, KID_RAY0 + k, s);
-    hipLaunchKernelGGL((ray_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
-                       (const uint32_t*)c->b_ray_list[k].p + off, n, (const TileDev*)c->b_tiles.p,
-                       (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ell);
+    if constexpr (G == 64 && IPL <= 8) {
+        hipLaunchKernelGGL((ray_lds_k<IPL>), dim3((unsigned)n), dim3(1024), 0, s,
+                           (const uint32_t*)c->b_ray_list[k].p + off, n, (const TileDev*)c->b_tiles.p,
+                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ell);
+    } else {
+        hipLaunchKernelGGL((ray_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+                           (const uint32_t*)c->b_ray_list[k].p + off, n, (const TileDev*)c->b_tiles.p,
+                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ell);
+    }
 }
 
 static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt, const float* lam, float* ell,
@@ -457,8 +560,12 @@ hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain
 {
     int64_t off[kRayClasses] = {0}, cnt[kRayClasses];
     if (!plain) {
+        hipError_t e;
         for (int k = 0; k < kRayClasses; ++k) cnt[k] = c->ray_cnt[k];
+        if ((e = fork_streams(c, s)) != hipSuccess) return e;
         ray_classes(c, off, cnt, lam, ell, s);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = join_streams(c, s)) != hipSuccess) return e;
     } else {
         // one launch per frame (per class): the plain per-frame schedule
         const int nf = c->n_frames;
