@@ -124,7 +124,8 @@ int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
  * Eq. neg).  prior_logit: V floats, log(gamma_v / (1 - gamma_v)) per voxel
  * (copied).  sigma_table: 64 floats > 0, the learnt depth-indexed Gaussian
  * sigma of Eq. noise (copied).  keep_checkpoints != 0 stores every sweep's
- * ray messages (sweeps * E floats) for mrf_backward.  Errors: MRF_ESTATE
+ * voxel->ray messages (sweeps * E floats, the input of each ray phase) for
+ * mrf_backward.  Errors: MRF_ESTATE
  * before mrf_build, MRF_EINVAL for sweeps < 1, MRF_ENOMEM. */
 int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
               int32_t sweeps, int32_t keep_checkpoints, void* stream);

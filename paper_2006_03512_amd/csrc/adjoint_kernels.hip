@@ -19,8 +19,11 @@
 // accumulation (order-independent, hence bit-reproducible).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "dev_common.hpp"
 #include "mrf_internal.hpp"
+#include "tile_lds.hpp"
 
 namespace mrf {
 
@@ -39,28 +42,28 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
     float P[IPL], S[IPL], Q[IPL];
     // ---- forward recomputation (as in the ray phase)
     {
+        float cw[IPL];
         float a = 0.0f;
 #pragma unroll
-        for (int j = 0; j < IPL; ++j) a += al[j];
-        float p = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
+        for (int j = 0; j < IPL; ++j) {
+            cw[j] = be[j] + gg[j] + a;
+            a += al[j];
+        }
+        const float Cl = lse_items<IPL>(cw);
+        const float p0 = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
+        float p = p0;
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
             P[j] = p;
             p += al[j];
         }
-        float w = MRF_NINF;
-#pragma unroll
-        for (int j = 0; j < IPL; ++j) w = lse(w, be[j] + gg[j] + P[j]);
-        float sc = dexcl<G>(dscan<G, OpLse>(w), MRF_NINF);
+        float sc = dexcl<G>(dscan<G, OpLse>(p0 + Cl), MRF_NINF);
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
             S[j] = sc;
             sc = lse(sc, be[j] + gg[j] + P[j]);
         }
-        LMap lm = lmap_id();
-#pragma unroll
-        for (int j = IPL - 1; j >= 0; --j) lm = lmap_compose(LMap{al[j], be[j] + gg[j]}, lm);
-        const LMap right = drscan_lmap<G>(lm);
+        const LMap right = drscan_lmap<G>(LMap{a, Cl});
         float q = drexcl<G>(right.c, MRF_NINF);
 #pragma unroll
         for (int j = IPL - 1; j >= 0; --j) {
@@ -68,7 +71,8 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
             q = lse(be[j] + gg[j], al[j] + q);
         }
     }
-    // ---- direct partials of ell_i = M1_i - M0_i (softmax weights are base-free)
+    // ---- direct partials of ell_i = M1_i - M0_i: d M1 / d (S, A) and
+    // d M0 / d (S, B) are the softmax weights of the two LSEs
     float Fd[IPL], Bb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
@@ -78,7 +82,6 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
         const float B = P[j] + Q[j];
         const float m1 = lse(S[j], A);
         const float m0 = lse(S[j], B);
-        // 2^(-inf - finite) = 0 covers S_0 = -inf and Q_{N-1} = -inf
         Fd[j] = ok ? e * (ex2(S[j] - m1) - ex2(S[j] - m0)) : 0.0f;
         const float Ab = ok ? e * ex2(A - m1) : 0.0f;
         Bb[j] = ok ? -e * ex2(B - m0) : 0.0f;
@@ -164,22 +167,6 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
     }
 }
 
-// base-2 log mu(0), log mu(1), g of one step (neutral padding when out of range)
-__device__ __forceinline__ void load_step(float lam, float g, bool ok, float& al, float& be, float& gg)
-{
-    if (ok) {
-        const float x = lam * kLog2e;
-        const float sp = softplus(x);
-        al = -sp;
-        be = x - sp;
-        gg = g * kLog2e;
-    } else {
-        al = 0.0f;
-        be = MRF_NINF;
-        gg = 0.0f;
-    }
-}
-
 template <int G, int IPL>
 __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                  const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
@@ -212,85 +199,103 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
     }
 }
 
-// Tile-staged reverse pass (rays of at most 64*IPL steps, one 1024-thread
-// block per tile): lambda and g, then ell-bar, pass through padded LDS rows
-// with coalesced loads; each wave writes its column of lambda-bar and g-bar
-// (zeros past its ray), and the block stores lambda-bar and accumulates the
-// g-bar sum coalesced.
-template <int IPL>
-__global__ __launch_bounds__(1024) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
-                                                      const TileDev* __restrict__ tiles,
-                                                      const int32_t* __restrict__ counts, const float* __restrict__ lam,
-                                                      const float* __restrict__ g, const float* __restrict__ ellbar,
-                                                      float* __restrict__ lambar, float* __restrict__ gsum, int first)
+// Tile-staged reverse pass for tiles of at most G*IPL steps (one block of 16
+// groups per tile): lambda and g, then ell-bar, pass through LDS with
+// coalesced loads; each group writes its column of lambda-bar and g-bar (zeros
+// past its ray), and the block stores lambda-bar and accumulates the g-bar sum
+// coalesced.
+template <int G, int IPL>
+__global__ __launch_bounds__(kTile * G) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                           const TileDev* __restrict__ tiles,
+                                                           const int32_t* __restrict__ counts,
+                                                           const float* __restrict__ lam, const float* __restrict__ g,
+                                                           const float* __restrict__ ellbar,
+                                                           float* __restrict__ lambar, float* __restrict__ gsum,
+                                                           int first)
 {
-    constexpr int R = kTile + 1;
-    __shared__ float sa[R * 64 * IPL];
-    __shared__ float sb[R * 64 * IPL];
+    constexpr int NT = kTile * G;
+    __shared__ float sa[kTile * G * IPL];
+    __shared__ float sb[kTile * G * IPL];
     const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
     if (ti >= ntiles) return;   // whole block
     const TileDev td = tiles[list[ti]];
-    const int nf = kTile * td.len;
-    for (int idx = threadIdx.x; idx < nf; idx += 1024) {
-        const int at = (idx >> 4) * R + (idx & 15);
+    const int nf = kTile * td.len;   // td.len <= G * IPL by class
+    for (int idx = threadIdx.x; idx < nf; idx += NT) {
+        const int at = lds_at<IPL>(idx >> 4, idx & 15);
         sa[at] = lam[td.base + idx];
         sb[at] = g[td.base + idx];
     }
     __syncthreads();
-    const int i = threadIdx.x >> 6;
-    const int i0 = (threadIdx.x & 63) * IPL;
-    int m = 0;
-    if ((i & 3) < td.nu && (i >> 2) < td.nv) m = counts[td.ray0 + (int64_t)(i >> 2) * td.W + (i & 3)];
+    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
+    const int i0 = ((int)threadIdx.x % G) * IPL;
+    const int m = tile_ray_len(td, counts, i);
     float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int k = i0 + j;
         const bool ok = k < m;
-        load_step(ok ? sa[k * R + i] : 0.0f, ok ? sb[k * R + i] : 0.0f, ok, al[j], be[j], gg[j]);
+        const int at = lds_at<IPL>(k, i);
+        load_step(ok ? sa[at] : 0.0f, ok ? sb[at] : 0.0f, ok, al[j], be[j], gg[j]);
     }
-    __syncthreads();   // every wave has its lambda: reuse sa for ell-bar
-    for (int idx = threadIdx.x; idx < nf; idx += 1024) sa[(idx >> 4) * R + (idx & 15)] = ellbar[td.base + idx];
+    __syncthreads();   // every group has its lambda: reuse sa for ell-bar
+    for (int idx = threadIdx.x; idx < nf; idx += NT) sa[lds_at<IPL>(idx >> 4, idx & 15)] = ellbar[td.base + idx];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int k = i0 + j;
-        eb[j] = k < m ? sa[k * R + i] : 0.0f;
+        eb[j] = k < m ? sa[lds_at<IPL>(k, i)] : 0.0f;
     }
-    if (m > 0) ray_adj_body<64, IPL>(al, be, gg, eb, m, i0, lamb, gb);   // m is uniform per wave
+    if (__ballot(m > 0)) {   // skip waves whose rays are all empty; empty rays give zeros
+        ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) lamb[j] = gb[j] = 0.0f;
+    }
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int k = i0 + j;
         if (k < td.len) {   // own column only; zeros past the ray
-            sa[k * R + i] = k < m ? lamb[j] : 0.0f;
-            sb[k * R + i] = k < m ? gb[j] : 0.0f;
+            const int at = lds_at<IPL>(k, i);
+            sa[at] = k < m ? lamb[j] : 0.0f;
+            sb[at] = k < m ? gb[j] : 0.0f;
         }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nf; idx += 1024) {
-        const int at = (idx >> 4) * R + (idx & 15);
+    for (int idx = threadIdx.x; idx < nf; idx += NT) {
+        const int at = lds_at<IPL>(idx >> 4, idx & 15);
         const int64_t o = td.base + idx;
         lambar[o] = sa[at];
         gsum[o] = first ? sb[at] : gsum[o] + sb[at];
     }
 }
 
-template <int G, int IPL>
-static void launch_adj_class(const mrf_ctx* c, int k, const float* lam, const float* ellbar, float* lambar,
-                             float* gsum, int first, hipStream_t s0)
+template <int Q>
+static void launch_adj_class(const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
+                             int first, hipStream_t s0)
 {
-    const int64_t n = c->ray_cnt[k];
+    const int64_t n = c->ray_cnt[Q];
     if (n <= 0) return;
-    const hipStream_t s = class_stream(c, k, s0);
-    ProfScope ps(c, KID_ADJ0 + k, s);
-    if constexpr (G == 64 && IPL <= 8) {
-        hipLaunchKernelGGL((ray_adj_lds_k<IPL>), dim3((unsigned)n), dim3(1024), 0, s,
-                           (const uint32_t*)c->b_ray_list[k].p, n, (const TileDev*)c->b_tiles.p,
-                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+    constexpr int CAP = kRayCap[Q];
+    constexpr int G = ray_class_group(Q, true);
+    const hipStream_t s = class_stream(c, Q, s0);
+    ProfScope ps(c, KID_ADJ0 + Q, s);
+    const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p;
+    if constexpr (ray_class_lds(Q)) {
+        hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
+                           (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                           (const float*)c->b_g.p, ellbar, lambar, gsum, first);
     } else {
-        hipLaunchKernelGGL((ray_adj_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
-                           (const uint32_t*)c->b_ray_list[k].p, n, (const TileDev*)c->b_tiles.p,
-                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+        hipLaunchKernelGGL((ray_adj_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s, list,
+                           n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                           (const float*)c->b_g.p, ellbar, lambar, gsum, first);
     }
+}
+
+template <int... Q>
+static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const float* lam, const float* ellbar,
+                        float* lambar, float* gsum, int first, hipStream_t s)
+{
+    (launch_adj_class<Q>(c, lam, ellbar, lambar, gsum, first, s), ...);
 }
 
 hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
@@ -298,19 +303,7 @@ hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar,
 {
     hipError_t e;
     if ((e = fork_streams(c, s)) != hipSuccess) return e;
-    launch_adj_class<16, 1>(c, 0, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 1>(c, 1, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 2>(c, 2, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 3>(c, 3, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 4>(c, 4, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 5>(c, 5, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 6>(c, 6, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 8>(c, 7, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 10>(c, 8, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 12>(c, 9, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 16>(c, 10, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 24>(c, 11, lam, ellbar, lambar, gsum, first, s);
-    launch_adj_class<64, 32>(c, 12, lam, ellbar, lambar, gsum, first, s);
+    adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, lam, ellbar, lambar, gsum, first ? 1 : 0, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return join_streams(c, s);
 }

@@ -111,7 +111,9 @@ hipError_t ensure(DevBuf& b, size_t bytes)
 
 // ------------------------------------------------------------ sweeps
 
-static float* ckpt_slot(mrf_ctx* c, int k)   // ell after sweep k+1 (k = 0..K-1)
+// voxel->ray messages (lambda) that sweep k+1 feeds to the ray phase (k = 0..K-1): the
+// reverse pass needs exactly these, so it never recomputes a voxel phase
+static float* ckpt_slot(const mrf_ctx* c, int k)
 {
     return (float*)c->b_ckpt.p + (size_t)k * (size_t)c->S;
 }
@@ -121,23 +123,25 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
 {
     hipError_t e;
     const float* theta = (const float*)c->b_theta.p;
-    float* lam = (float*)c->b_lam.p;
+    float* ell = (float*)c->b_ell.p;
     if ((e = launch_potentials(c, s)) != hipSuccess) return e;
     const float* prev = nullptr;   // ell of the previous sweep; nullptr = uniform (0)
     for (int k = 0; k < K; ++k) {
-        float* out = keep ? ckpt_slot(c, k) : (float*)c->b_ell.p;
+        float* lam = keep ? ckpt_slot(c, k) : (float*)c->b_lam.p;
         if ((e = launch_voxel_phase(c, theta, prev, lam, nullptr, 0, plain, s)) != hipSuccess) return e;
-        if ((e = launch_ray_phase(c, lam, out, plain, s)) != hipSuccess) return e;
-        prev = out;
+        if ((e = launch_ray_phase(c, lam, ell, plain, s)) != hipSuccess) return e;
+        prev = ell;
     }
     if ((e = launch_copy((float*)c->b_L.p, theta, c->V, s)) != hipSuccess) return e;
     return launch_voxel_phase(c, theta, prev, nullptr, (float*)c->b_L.p, 1, plain, s);
 }
 
-static const float* final_ell(const mrf_ctx* c)
+static const float* final_ell(const mrf_ctx* c) { return c->inferred ? (const float*)c->b_ell.p : nullptr; }
+
+static const float* final_lam(const mrf_ctx* c)
 {
     if (!c->inferred) return nullptr;
-    return c->have_ckpt ? (const float*)c->b_ckpt.p + (size_t)(c->K - 1) * (size_t)c->S : (const float*)c->b_ell.p;
+    return c->have_ckpt ? ckpt_slot(c, c->K - 1) : (const float*)c->b_lam.p;
 }
 
 }  // namespace mrf
@@ -490,8 +494,6 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
     HCK(hipSetDevice(c->device), "mrf_backward: hipSetDevice");
     const int K = c->K;
     const int32_t* col = (const int32_t*)c->b_col.p;
-    const float* theta = (const float*)c->b_theta.p;
-    float* lam = (float*)c->b_lam.p;
     float* ellbar = (float*)c->b_ellbar.p;
     float* lambar = (float*)c->b_lambar.p;
     float* gsum = (float*)c->b_gsum.p;
@@ -499,14 +501,15 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
     // d loss / d ell^(K)_e = d loss / d L_v(e);  d loss / d theta starts at d loss / d L
     HCK(launch_gather_voxel(col, dlogit, ellbar, c->S, s), "mrf_backward: seed");
     HCK(launch_copy(thetabar, dlogit, c->V, s), "mrf_backward: seed");
-    for (int k = K - 1; k >= 0; --k) {
-        // lambda of sweep k from the checkpointed ell of sweep k-1 (0 before the first)
-        const float* prev = k > 0 ? ckpt_slot(c, k - 1) : nullptr;
-        HCK(launch_voxel_phase(c, theta, prev, lam, nullptr, 0, false, s), "mrf_backward: recompute");
-        HCK(launch_ray_adjoint(c, lam, ellbar, lambar, gsum, k == K - 1, s), "mrf_backward: ray adjoint");
-        HCK(launch_voxel_phase(c, nullptr, lambar, k > 0 ? ellbar : nullptr, thetabar, 2, false, s),
-            "mrf_backward: voxel adjoint");
+    // class launches of a phase run on the side streams (fork/join by events)
+    c->npar = mrf_ctx::kPar;
+    hipError_t e = hipSuccess;
+    for (int k = K - 1; k >= 0 && e == hipSuccess; --k) {
+        e = launch_ray_adjoint(c, ckpt_slot(c, k), ellbar, lambar, gsum, k == K - 1, s);
+        if (e == hipSuccess) e = launch_voxel_phase(c, nullptr, lambar, k > 0 ? ellbar : nullptr, thetabar, 2, false, s);
     }
+    c->npar = 0;
+    HCK(e, "mrf_backward: sweeps");
     if (dsigma) HCK(launch_sigma_grad(c, dsigma, s), "mrf_backward: sigma gradient");
     if (dprior) HCK(launch_copy(dprior, thetabar, c->V, s), "mrf_backward: copy");
     return MRF_OK;
@@ -546,7 +549,7 @@ int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, flo
     if (delta) HCK(export_canonical_edges(c, c->b_delta.p, delta, 4, s), "export");
     if (bin) HCK(export_canonical_edges(c, c->b_bin.p, bin, 1, s), "export");
     if (g) HCK(export_canonical_edges(c, c->b_g.p, g, 4, s), "export");
-    if (lam) HCK(export_canonical_edges(c, c->b_lam.p, lam, 4, s), "export");
+    if (lam) HCK(export_canonical_edges(c, final_lam(c), lam, 4, s), "export");
     if (ell) HCK(export_canonical_edges(c, final_ell(c), ell, 4, s), "export");
     return MRF_OK;
 }
@@ -557,18 +560,17 @@ extern "C" {
 
 static std::string kid_name(int k)
 {
-    static const int G[kRayClasses] = {16, 64, 64, 64, 64, 64, 64, 64, 64, 64, 64, 64, 64};
     static const char* vox[kVoxClasses] = {"voxel_k<1,1>", "voxel_k<1,4>", "voxel_k<1,16>", "voxel_k<4,16>",
                                            "voxel_k<16,16>", "voxel_chunked_k"};
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) return vox[k - KID_VOX0];
-    // classes of 64-lane rays with at most 8 steps per lane use the LDS-staged kernels
-    auto ray_name = [&](const char* direct, const char* lds, int q) {
-        const int ipl = kRayCap[q] / G[q];
-        if (G[q] == 64 && ipl <= 8) return std::string(lds) + "<" + std::to_string(ipl) + ">";
-        return std::string(direct) + "<" + std::to_string(G[q]) + "," + std::to_string(ipl) + ">";
+    auto ray_name = [](const char* direct, const char* lds, int q, bool adj) {
+        const int G = ray_class_group(q, adj);
+        return std::string(ray_class_lds(q) ? lds : direct) + "<" + std::to_string(G) + "," +
+               std::to_string(kRayCap[q] / G) + ">";
     };
-    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) return ray_name("ray_k", "ray_lds_k", k - KID_RAY0);
-    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses) return ray_name("ray_adj_k", "ray_adj_lds_k", k - KID_ADJ0);
+    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) return ray_name("ray_k", "ray_lds_k", k - KID_RAY0, false);
+    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses)
+        return ray_name("ray_adj_k", "ray_adj_lds_k", k - KID_ADJ0, true);
     if (k == KID_POT) return "potentials_k";
     if (k == KID_SIGMA) return "sigma_grad_k";
     return "?";

@@ -28,6 +28,20 @@ __device__ __forceinline__ float lse(float a, float b)
     return hi + lg2(1.0f + ex2(d));
 }
 
+// log2 sum_j 2^x_j of a lane's items: maximum first, then one exp2 per item
+template <int N>
+__device__ __forceinline__ float lse_items(const float (&x)[N])
+{
+    float mx = MRF_NINF;
+#pragma unroll
+    for (int j = 0; j < N; ++j) mx = fmaxf(mx, x[j]);
+    if (mx == MRF_NINF) return MRF_NINF;
+    float sm = 0.0f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) sm += ex2(x[j] - mx);
+    return mx + lg2(sm);
+}
+
 // log2(1 + 2^x)
 __device__ __forceinline__ float softplus(float x)
 {
@@ -181,10 +195,11 @@ __device__ __forceinline__ AMap grscan_amap(AMap x)
 }  // namespace mrf
 
 // ---------------------------------------------------------------------------
-// DPP-based scans.  A wave64 is four rows of 16 lanes; row_shr:n moves data
-// to lane + n inside a row, row_shl:n to lane - n, wave_shr:1 / wave_shl:1
-// move it by one lane across the whole wave.  Lanes without a source keep
-// `old`.  Row results are combined across rows through readlane.
+// DPP-based scans over groups of G = 16, 32 or 64 consecutive lanes.  A wave64
+// is four rows of 16 lanes; row_shr:n moves data to lane + n inside a row,
+// row_shl:n to lane - n, wave_shr:1 / wave_shl:1 move it by one lane across the
+// whole wave.  Lanes without a source keep `old`.  Row results are combined
+// across the rows of a group through readlane.
 // ---------------------------------------------------------------------------
 namespace mrf {
 
@@ -220,12 +235,17 @@ struct OpLse {
 template <int G, class O>
 __device__ __forceinline__ float dscan(float x)
 {
-    static_assert(G == 16 || G == 64, "groups are rows or waves");
+    static_assert(G == 16 || G == 32 || G == 64, "groups are rows, half-waves or waves");
     const float I = O::id();
     x = O::op(dpp<DPP_ROW_SHR1>(I, x), x);
     x = O::op(dpp<DPP_ROW_SHR2>(I, x), x);
     x = O::op(dpp<DPP_ROW_SHR4>(I, x), x);
     x = O::op(dpp<DPP_ROW_SHR8>(I, x), x);
+    if (G == 32) {
+        const float r0 = readlane(x, 15), r2 = readlane(x, 47);
+        const int row = (threadIdx.x & 63) >> 4;
+        if (row & 1) x = O::op(row == 1 ? r0 : r2, x);
+    }
     if (G == 64) {
         const float r0 = readlane(x, 15), r1 = readlane(x, 31), r2 = readlane(x, 47);
         const float c2 = O::op(r0, r1);
@@ -241,12 +261,17 @@ __device__ __forceinline__ float dscan(float x)
 template <int G, class O>
 __device__ __forceinline__ float drscan(float x)
 {
-    static_assert(G == 16 || G == 64, "groups are rows or waves");
+    static_assert(G == 16 || G == 32 || G == 64, "groups are rows, half-waves or waves");
     const float I = O::id();
     x = O::op(x, dpp<DPP_ROW_SHL1>(I, x));
     x = O::op(x, dpp<DPP_ROW_SHL2>(I, x));
     x = O::op(x, dpp<DPP_ROW_SHL4>(I, x));
     x = O::op(x, dpp<DPP_ROW_SHL8>(I, x));
+    if (G == 32) {
+        const float t1 = readlane(x, 16), t3 = readlane(x, 48);
+        const int row = (threadIdx.x & 63) >> 4;
+        if (!(row & 1)) x = O::op(x, row == 0 ? t1 : t3);
+    }
     if (G == 64) {
         const float t1 = readlane(x, 16), t2 = readlane(x, 32), t3 = readlane(x, 48);
         const float c1 = O::op(t2, t3);
@@ -262,6 +287,10 @@ __device__ __forceinline__ float drscan(float x)
 template <int G>
 __device__ __forceinline__ float dexcl(float incl, float first)
 {
+    if (G == 32) {
+        const float y = dpp<DPP_WAVE_SHR1>(first, incl);
+        return (threadIdx.x & 31) == 0 ? first : y;
+    }
     return G == 64 ? dpp<DPP_WAVE_SHR1>(first, incl) : dpp<DPP_ROW_SHR1>(first, incl);
 }
 
@@ -269,6 +298,10 @@ __device__ __forceinline__ float dexcl(float incl, float first)
 template <int G>
 __device__ __forceinline__ float drexcl(float incl, float last)
 {
+    if (G == 32) {
+        const float y = dpp<DPP_WAVE_SHL1>(last, incl);
+        return (threadIdx.x & 31) == 31 ? last : y;
+    }
     return G == 64 ? dpp<DPP_WAVE_SHL1>(last, incl) : dpp<DPP_ROW_SHL1>(last, incl);
 }
 
@@ -291,6 +324,11 @@ __device__ __forceinline__ LMap drscan_lmap(LMap x)
     x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL2>(I, x));
     x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL4>(I, x));
     x = lmap_compose(x, dpp_lmap<DPP_ROW_SHL8>(I, x));
+    if (G == 32) {
+        const LMap t1 = readlane_lmap(x, 16), t3 = readlane_lmap(x, 48);
+        const int row = (threadIdx.x & 63) >> 4;
+        if (!(row & 1)) x = lmap_compose(x, row == 0 ? t1 : t3);
+    }
     if (G == 64) {
         const LMap t1 = readlane_lmap(x, 16), t2 = readlane_lmap(x, 32), t3 = readlane_lmap(x, 48);
         const LMap c1 = lmap_compose(t2, t3);
@@ -322,6 +360,11 @@ __device__ __forceinline__ AMap dscan_amap(AMap x)
     x = amap_then(dpp_amap<DPP_ROW_SHR2>(I, x), x);
     x = amap_then(dpp_amap<DPP_ROW_SHR4>(I, x), x);
     x = amap_then(dpp_amap<DPP_ROW_SHR8>(I, x), x);
+    if (G == 32) {
+        const AMap r0 = readlane_amap(x, 15), r2 = readlane_amap(x, 47);
+        const int row = (threadIdx.x & 63) >> 4;
+        if (row & 1) x = amap_then(row == 1 ? r0 : r2, x);
+    }
     if (G == 64) {
         const AMap r0 = readlane_amap(x, 15), r1 = readlane_amap(x, 31), r2 = readlane_amap(x, 47);
         const AMap c2 = amap_then(r0, r1);
@@ -342,6 +385,11 @@ __device__ __forceinline__ AMap drscan_amap(AMap x)
     x = amap_then(dpp_amap<DPP_ROW_SHL2>(I, x), x);
     x = amap_then(dpp_amap<DPP_ROW_SHL4>(I, x), x);
     x = amap_then(dpp_amap<DPP_ROW_SHL8>(I, x), x);
+    if (G == 32) {
+        const AMap t1 = readlane_amap(x, 16), t3 = readlane_amap(x, 48);
+        const int row = (threadIdx.x & 63) >> 4;
+        if (!(row & 1)) x = amap_then(row == 0 ? t1 : t3, x);
+    }
     if (G == 64) {
         const AMap t1 = readlane_amap(x, 16), t2 = readlane_amap(x, 32), t3 = readlane_amap(x, 48);
         const AMap c1 = amap_then(t3, t2);

@@ -16,10 +16,39 @@ namespace mrf {
 constexpr int kBins = 64;
 constexpr int kMaxRayLen = 2048;      // longest ray factor a group can hold
 
-// Ray-length classes: (group lanes G, items per lane IPL), capacity G*IPL.
-// Class 0 is G = 16, IPL = 1; the others are G = 64 with IPL = cap / 64.
+// Ray-length classes by tile length (longest ray of the tile), capacity cap.
+// A ray is held by a group of G lanes (16, 32 or 64), each holding IPL = cap / G
+// consecutive steps.  Class 0 (cap 16) is G = 16 reading the tile directly;
+// classes up to kLdsMaxCap stage the tile through LDS with G from kRayG (ray
+// phase) or kAdjG (reverse pass); longer classes are G = 64, direct.
 constexpr int kRayClasses = 13;
 constexpr int kRayCap[kRayClasses] = {16, 64, 128, 192, 256, 320, 384, 512, 640, 768, 1024, 1536, 2048};
+constexpr int kLdsMaxCap = 512;
+#ifndef MRF_RAY_GROUPS
+#define MRF_RAY_GROUPS 16, 16, 16, 16, 32, 32, 32, 64, 64, 64, 64, 64, 64
+#endif
+#ifndef MRF_ADJ_GROUPS
+#define MRF_ADJ_GROUPS 16, 16, 32, 64, 32, 64, 64, 64, 64, 64, 64, 64, 64
+#endif
+constexpr int kRayG[kRayClasses] = {MRF_RAY_GROUPS};
+constexpr int kAdjG[kRayClasses] = {MRF_ADJ_GROUPS};
+
+constexpr bool ray_class_lds(int q) { return q > 0 && kRayCap[q] <= kLdsMaxCap; }
+// lanes per ray of class q in the ray phase (adj = false) or the reverse pass
+constexpr int ray_class_group(int q, bool adj)
+{
+    return q == 0 ? 16 : (ray_class_lds(q) ? (adj ? kAdjG[q] : kRayG[q]) : 64);
+}
+constexpr bool ray_groups_valid()
+{
+    for (int q = 0; q < kRayClasses; ++q)
+        for (int a = 0; a < 2; ++a) {
+            const int G = ray_class_group(q, a == 1);
+            if ((G != 16 && G != 32 && G != 64) || kRayCap[q] % G != 0) return false;
+        }
+    return true;
+}
+static_assert(ray_groups_valid(), "ray class groups must be 16, 32 or 64 lanes dividing the class capacity");
 
 // Edges are stored in tiles of 4x4 pixels, step-major: slot of (ray lane i,
 // step k) = tile_base + 16 k + i.  Rays of one camera reach a voxel after the

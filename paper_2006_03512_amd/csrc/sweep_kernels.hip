@@ -21,8 +21,11 @@
 // division-free form (sum over j > i of the product over k < j, k != i).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "dev_common.hpp"
 #include "mrf_internal.hpp"
+#include "tile_lds.hpp"
 
 namespace mrf {
 
@@ -353,9 +356,62 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, fl
 
 // ------------------------------------------------------------ ray phase
 
-// One group of G lanes per ray, blocked: lane l holds steps [l IPL, (l+1) IPL).
-// Each scan runs sequentially inside a lane and once across lanes on the
-// lane aggregates.  Logarithms are base 2 inside the kernel.
+// Messages of one ray held by a group of G lanes, blocked: lane l holds steps
+// [i0, i0 + IPL), i0 = l IPL, as base-2 log mu(0), log mu(1) and g, with
+// neutral padding past the ray's m steps.  Each scan runs sequentially inside
+// a lane and once across the group on the lane aggregates.  put(j, ell)
+// receives the natural-log message of every step i0 + j < m.
+template <int G, int IPL, class Put>
+__device__ __forceinline__ void ray_body(const float (&al)[IPL], const float (&be)[IPL], const float (&gg)[IPL],
+                                         int m, int i0, Put&& put)
+{
+    // lane aggregate Cl = LSE_j (c_j + lp_j), c_j = log mu_j(1) + g_j, lp_j the
+    // lane-local prefix of log mu(0): the lane's share of the S scan is p0 + Cl
+    // and its composed Q map is (sum of log mu(0), Cl)
+    float cw[IPL];
+    float a = 0.0f;
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        cw[j] = be[j] + gg[j] + a;
+        a += al[j];
+    }
+    const float Cl = lse_items<IPL>(cw);
+    // P_i = sum_{k<i} log mu_k(0)
+    const float p0 = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
+    float P[IPL];
+    float p = p0;
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        P[j] = p;
+        p += al[j];
+    }
+    // S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)
+    float S[IPL];
+    {
+        float sc = dexcl<G>(dscan<G, OpLse>(p0 + Cl), MRF_NINF);
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            S[j] = sc;
+            sc = lse(sc, be[j] + gg[j] + P[j]);
+        }
+    }
+    // Q_i = LSE(c_{i+1}, log mu_{i+1}(0) + Q_{i+1}): scan the lane maps from
+    // the right, then walk the lane backwards
+    const LMap right = drscan_lmap<G>(LMap{a, Cl});
+    float Q = drexcl<G>(right.c, MRF_NINF);
+#pragma unroll
+    for (int j = IPL - 1; j >= 0; --j) {
+        if (i0 + j < m) {
+            const float m1 = lse(S[j], gg[j] + P[j]);
+            const float m0 = lse(S[j], P[j] + Q);
+            put(j, (m1 - m0) * kLn2);
+        }
+        Q = lse(be[j] + gg[j], al[j] + Q);
+    }
+}
+
+// Direct variant: each group reads its ray's steps from global memory (one
+// 64-byte row per step holds the 16 rays of the tile).
 template <int G, int IPL>
 __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                              const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
@@ -367,193 +423,92 @@ __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, 
     int m;
     if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
     const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
-
     float al[IPL], be[IPL], gg[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int i = i0 + j;
-        if (i < m) {
-            const float x = lam[s + kTile * i] * kLog2e;
-            const float sp = softplus(x);
-            al[j] = -sp;          // log2 mu(o=0)
-            be[j] = x - sp;       // log2 mu(o=1)
-            gg[j] = g[s + kTile * i] * kLog2e;
-        } else {                  // neutral padding
-            al[j] = 0.0f;
-            be[j] = MRF_NINF;
-            gg[j] = 0.0f;
-        }
+        const bool ok = i < m;
+        load_step(ok ? lam[s + kTile * i] : 0.0f, ok ? g[s + kTile * i] : 0.0f, ok, al[j], be[j], gg[j]);
     }
-    // P_i = sum_{k<i} log mu_k(0)
-    float P[IPL];
-    {
-        float a = 0.0f;
-#pragma unroll
-        for (int j = 0; j < IPL; ++j) a += al[j];
-        float p = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
-#pragma unroll
-        for (int j = 0; j < IPL; ++j) {
-            P[j] = p;
-            p += al[j];
-        }
-    }
-    // S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)
-    float S[IPL];
-    {
-        float w = MRF_NINF;
-#pragma unroll
-        for (int j = 0; j < IPL; ++j) w = lse(w, be[j] + gg[j] + P[j]);
-        float sc = dexcl<G>(dscan<G, OpLse>(w), MRF_NINF);
-#pragma unroll
-        for (int j = 0; j < IPL; ++j) {
-            S[j] = sc;
-            sc = lse(sc, be[j] + gg[j] + P[j]);
-        }
-    }
-    // Q_i = LSE(c_{i+1}, log mu_{i+1}(0) + Q_{i+1}): compose the lane's maps,
-    // scan the lane maps from the right, then walk the lane backwards
-    LMap lm = lmap_id();
-#pragma unroll
-    for (int j = IPL - 1; j >= 0; --j) lm = lmap_compose(LMap{al[j], be[j] + gg[j]}, lm);
-    const LMap right = drscan_lmap<G>(lm);
-    float Q = drexcl<G>(right.c, MRF_NINF);
-#pragma unroll
-    for (int j = IPL - 1; j >= 0; --j) {
-        const int i = i0 + j;
-        if (i < m) {
-            const float m1 = lse(S[j], gg[j] + P[j]);
-            const float m0 = lse(S[j], P[j] + Q);
-            ell[s + kTile * i] = (m1 - m0) * kLn2;
-        }
-        Q = lse(be[j] + gg[j], al[j] + Q);
-    }
+    ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, float v) { ell[s + kTile * (i0 + j)] = v; });
 }
 
-// Tile-staged variant for rays of at most 64*IPL steps: one 1024-thread block
+// Tile-staged variant for tiles of at most G*IPL steps: one block of 16 groups
 // per tile.  The block copies the tile's lambda and g (16 rays x len steps,
-// contiguous) into LDS with coalesced loads, each of the 16 waves runs the
-// blocked scans of its own ray reading its LDS column, writes ell back into
-// that column, and the block stores the tile coalesced.  Rows of 16 floats
-// are padded to 17 so that a wave's column reads spread over the banks.
-constexpr int kLdsRow = kTile + 1;
-
-template <int IPL>
-__global__ __launch_bounds__(1024) void ray_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
-                                                  const TileDev* __restrict__ tiles,
-                                                  const int32_t* __restrict__ counts, const float* __restrict__ lam,
-                                                  const float* __restrict__ g, float* __restrict__ ell)
+// contiguous) into LDS with coalesced loads, every group runs the scans of its
+// own ray on its LDS column and writes ell back into that column, and the
+// block stores the tile coalesced.  Padding slots past a ray receive its
+// staged lambda, which nothing reads.
+template <int G, int IPL>
+__global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                       const TileDev* __restrict__ tiles,
+                                                       const int32_t* __restrict__ counts,
+                                                       const float* __restrict__ lam, const float* __restrict__ g,
+                                                       float* __restrict__ ell)
 {
-    __shared__ float sl[kLdsRow * 64 * IPL];
-    __shared__ float sg[kLdsRow * 64 * IPL];
+    constexpr int NT = kTile * G;
+    __shared__ float sl[kTile * G * IPL];
+    __shared__ float sg[kTile * G * IPL];
     const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
     if (ti >= ntiles) return;   // whole block
     const TileDev td = tiles[list[ti]];
-    const int nf = kTile * td.len;
-    for (int idx = threadIdx.x; idx < nf; idx += 1024) {
-        const int at = (idx >> 4) * kLdsRow + (idx & 15);
+    const int nf = kTile * td.len;   // td.len <= G * IPL by class
+    for (int idx = threadIdx.x; idx < nf; idx += NT) {
+        const int at = lds_at<IPL>(idx >> 4, idx & 15);
         sl[at] = lam[td.base + idx];
         sg[at] = g[td.base + idx];
     }
     __syncthreads();
-    const int i = threadIdx.x >> 6;   // this wave's ray: lane i of the tile
-    const int i0 = (threadIdx.x & 63) * IPL;
-    int m = 0;
-    if ((i & 3) < td.nu && (i >> 2) < td.nv) m = counts[td.ray0 + (int64_t)(i >> 2) * td.W + (i & 3)];
-    if (m > 0) {   // uniform per wave
+    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
+    const int i0 = ((int)threadIdx.x % G) * IPL;
+    const int m = tile_ray_len(td, counts, i);
+    if (__ballot(m > 0)) {   // skip waves whose rays are all empty
         float al[IPL], be[IPL], gg[IPL];
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
             const int k = i0 + j;
-            if (k < m) {
-                const float x = sl[k * kLdsRow + i] * kLog2e;
-                const float sp = softplus(x);
-                al[j] = -sp;
-                be[j] = x - sp;
-                gg[j] = sg[k * kLdsRow + i] * kLog2e;
-            } else {
-                al[j] = 0.0f;
-                be[j] = MRF_NINF;
-                gg[j] = 0.0f;
-            }
+            const bool ok = k < m;
+            const int at = lds_at<IPL>(k, i);
+            load_step(ok ? sl[at] : 0.0f, ok ? sg[at] : 0.0f, ok, al[j], be[j], gg[j]);
         }
-        float P[IPL];
-        {
-            float a = 0.0f;
-#pragma unroll
-            for (int j = 0; j < IPL; ++j) a += al[j];
-            float p = dexcl<64>(dscan<64, OpAdd>(a), 0.0f);
-#pragma unroll
-            for (int j = 0; j < IPL; ++j) {
-                P[j] = p;
-                p += al[j];
-            }
-        }
-        float S[IPL];
-        {
-            float w = MRF_NINF;
-#pragma unroll
-            for (int j = 0; j < IPL; ++j) w = lse(w, be[j] + gg[j] + P[j]);
-            float sc = dexcl<64>(dscan<64, OpLse>(w), MRF_NINF);
-#pragma unroll
-            for (int j = 0; j < IPL; ++j) {
-                S[j] = sc;
-                sc = lse(sc, be[j] + gg[j] + P[j]);
-            }
-        }
-        LMap lm = lmap_id();
-#pragma unroll
-        for (int j = IPL - 1; j >= 0; --j) lm = lmap_compose(LMap{al[j], be[j] + gg[j]}, lm);
-        const LMap right = drscan_lmap<64>(lm);
-        float Q = drexcl<64>(right.c, MRF_NINF);
-#pragma unroll
-        for (int j = IPL - 1; j >= 0; --j) {
-            const int k = i0 + j;
-            if (k < m) {
-                const float m1 = lse(S[j], gg[j] + P[j]);
-                const float m0 = lse(S[j], P[j] + Q);
-                sl[k * kLdsRow + i] = (m1 - m0) * kLn2;   // own column only
-            }
-            Q = lse(be[j] + gg[j], al[j] + Q);
-        }
+        ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, float v) { sl[lds_at<IPL>(i0 + j, i)] = v; });
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nf; idx += 1024) ell[td.base + idx] = sl[(idx >> 4) * kLdsRow + (idx & 15)];
+    for (int idx = threadIdx.x; idx < nf; idx += NT) ell[td.base + idx] = sl[lds_at<IPL>(idx >> 4, idx & 15)];
 }
 
-template <int G, int IPL>
-static void launch_ray_class(const mrf_ctx* c, int k, int64_t off, int64_t n, const float* lam, float* ell,
+template <int Q>
+static void launch_ray_class(const mrf_ctx* c, int64_t off, int64_t n, const float* lam, float* ell,
                              hipStream_t s0)
 {
     if (n <= 0) return;
-    const hipStream_t s = class_stream(c, k, s0);
-    ProfScope ps(c, KID_RAY0 + k, s);
-    if constexpr (G == 64 && IPL <= 8) {
-        hipLaunchKernelGGL((ray_lds_k<IPL>), dim3((unsigned)n), dim3(1024), 0, s,
-                           (const uint32_t*)c->b_ray_list[k].p + off, n, (const TileDev*)c->b_tiles.p,
-                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ell);
+    constexpr int CAP = kRayCap[Q];
+    constexpr int G = ray_class_group(Q, false);
+    const hipStream_t s = class_stream(c, Q, s0);
+    ProfScope ps(c, KID_RAY0 + Q, s);
+    const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p + off;
+    if constexpr (ray_class_lds(Q)) {
+        hipLaunchKernelGGL((ray_lds_k<G, CAP / G>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
+                           (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                           (const float*)c->b_g.p, ell);
     } else {
-        hipLaunchKernelGGL((ray_k<G, IPL>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
-                           (const uint32_t*)c->b_ray_list[k].p + off, n, (const TileDev*)c->b_tiles.p,
-                           (const int32_t*)c->b_counts.p, lam, (const float*)c->b_g.p, ell);
+        hipLaunchKernelGGL((ray_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s, list, n,
+                           (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                           (const float*)c->b_g.p, ell);
     }
+}
+
+template <int... Q>
+static void ray_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const int64_t* off, const int64_t* cnt,
+                        const float* lam, float* ell, hipStream_t s)
+{
+    (launch_ray_class<Q>(c, off[Q], cnt[Q], lam, ell, s), ...);
 }
 
 static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt, const float* lam, float* ell,
                         hipStream_t s)
 {
-    launch_ray_class<16, 1>(c, 0, off[0], cnt[0], lam, ell, s);
-    launch_ray_class<64, 1>(c, 1, off[1], cnt[1], lam, ell, s);
-    launch_ray_class<64, 2>(c, 2, off[2], cnt[2], lam, ell, s);
-    launch_ray_class<64, 3>(c, 3, off[3], cnt[3], lam, ell, s);
-    launch_ray_class<64, 4>(c, 4, off[4], cnt[4], lam, ell, s);
-    launch_ray_class<64, 5>(c, 5, off[5], cnt[5], lam, ell, s);
-    launch_ray_class<64, 6>(c, 6, off[6], cnt[6], lam, ell, s);
-    launch_ray_class<64, 8>(c, 7, off[7], cnt[7], lam, ell, s);
-    launch_ray_class<64, 10>(c, 8, off[8], cnt[8], lam, ell, s);
-    launch_ray_class<64, 12>(c, 9, off[9], cnt[9], lam, ell, s);
-    launch_ray_class<64, 16>(c, 10, off[10], cnt[10], lam, ell, s);
-    launch_ray_class<64, 24>(c, 11, off[11], cnt[11], lam, ell, s);
-    launch_ray_class<64, 32>(c, 12, off[12], cnt[12], lam, ell, s);
+    ray_classes(std::make_integer_sequence<int, kRayClasses>{}, c, off, cnt, lam, ell, s);
 }
 
 hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain, hipStream_t s)
