@@ -1,17 +1,17 @@
 // Reverse-mode derivative of the unrolled sweeps on gfx950 (a project
 // extension; the paper's BP has no gradients).
 //
-// Ray adjoint: for one ray, given d/d ell_i, the chain rule through
-//   ell_i = M1_i - M0_i, M1_i = LSE(S_i, A_i), M0_i = LSE(S_i, B_i),
-//   A_i = g_i + P_i, B_i = P_i + Q_i, S_{i+1} = LSE(S_i, W_i),
-//   W_i = log mu_i(1) + g_i + P_i, Q_{i-1} = LSE(c_i, log mu_i(0) + Q_i),
-//   c_i = log mu_i(1) + g_i, P_{i+1} = P_i + log mu_i(0)
+// Ray adjoint: for one ray, given d/d ell_i, the chain rule through the
+// P-free form of the ray phase (c_i = log mu_i(1) + g_i)
+//   ell_i = M1_i - M0_i,  M1_i = LSE(R_i, g_i),  M0_i = LSE(R_i, Q_i),
+//   R_{i+1} = U_i - log mu_i(0),  U_i = LSE(R_i, c_i),
+//   Q_{i-1} = LSE(c_i, log mu_i(0) + Q_i)
 // gives two linear recurrences with weights in [0, 1] (softmax weights of
 // the LSEs), run as affine group scans:
-//   Tb_i = Bbar_i + rho_{i-1} Tb_{i-1}      forward,  rho_{i-1} = exp(log mu_i(0) + Q_i - Q_{i-1})
-//   Fb_i = Sbar_i + r_i Fb_{i+1}            backward, r_i = exp(S_i - S_{i+1})
-// and a suffix sum for the prefix sums P.  d log mu(0)/d lam = -mu(1),
-// d log mu(1)/d lam = mu(0).
+//   Tb_i = Qbar_i + rho_i Tb_{i-1}      left to right,  rho_i = 2^(log mu_i(0) + Q_i - Q_{i-1})
+//   Rb_i = Rbar_i + r_i Rb_{i+1}        right to left,  r_i = 2^(R_i - U_i)
+// where Tb and Rb are the total derivatives with respect to Q_i and R_i.
+// d log mu(0)/d lam = -mu(1), d log mu(1)/d lam = mu(0).
 //
 // Sigma-table gradient: d g_e / d sigma_b = delta_e^2 / sigma_b^3 - 1 / sigma_b,
 // reduced per bin deterministically: fixed-order double sums over runs of
@@ -39,58 +39,49 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
                                              const float (&eb)[IPL], int m, int i0, float (&lamb)[IPL],
                                              float (&gb)[IPL])
 {
-    float P[IPL], S[IPL], Q[IPL];
+    float c[IPL], R[IPL], U[IPL], Q[IPL];
     // ---- forward recomputation (as in the ray phase)
     {
         float cw[IPL];
         float a = 0.0f;
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
-            cw[j] = be[j] + gg[j] + a;
+            c[j] = be[j] + gg[j];
+            cw[j] = c[j] + a;
             a += al[j];
         }
         const float Cl = lse_items<IPL>(cw);
-        const float p0 = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
-        float p = p0;
+        const LMap left = dscan_lmap<G>(LMap{-a, Cl - a});
+        float r = dexcl<G>(left.c, MRF_NINF);
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
-            P[j] = p;
-            p += al[j];
-        }
-        float sc = dexcl<G>(dscan<G, OpLse>(p0 + Cl), MRF_NINF);
-#pragma unroll
-        for (int j = 0; j < IPL; ++j) {
-            S[j] = sc;
-            sc = lse(sc, be[j] + gg[j] + P[j]);
+            R[j] = r;
+            U[j] = lse(r, c[j]);
+            r = U[j] - al[j];
         }
         const LMap right = drscan_lmap<G>(LMap{a, Cl});
         float q = drexcl<G>(right.c, MRF_NINF);
 #pragma unroll
         for (int j = IPL - 1; j >= 0; --j) {
             Q[j] = q;
-            q = lse(be[j] + gg[j], al[j] + q);
+            q = lse(c[j], al[j] + q);
         }
     }
-    // ---- direct partials of ell_i = M1_i - M0_i: d M1 / d (S, A) and
-    // d M0 / d (S, B) are the softmax weights of the two LSEs
-    float Fd[IPL], Bb[IPL], Pb[IPL], lab[IPL], lbb[IPL];
+    // ---- direct partials of ell_i = M1_i - M0_i (softmax weights)
+    float Fd[IPL], Bb[IPL], lab[IPL], lbb[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const bool ok = i0 + j < m;
         const float e = ok ? eb[j] : 0.0f;
-        const float A = gg[j] + P[j];
-        const float B = P[j] + Q[j];
-        const float m1 = lse(S[j], A);
-        const float m0 = lse(S[j], B);
-        Fd[j] = ok ? e * (ex2(S[j] - m1) - ex2(S[j] - m0)) : 0.0f;
-        const float Ab = ok ? e * ex2(A - m1) : 0.0f;
-        Bb[j] = ok ? -e * ex2(B - m0) : 0.0f;
-        gb[j] = Ab;
-        Pb[j] = Ab + Bb[j];
+        const float m1 = lse(R[j], gg[j]);
+        const float m0 = lse(R[j], Q[j]);
+        Fd[j] = ok ? e * (ex2(R[j] - m1) - ex2(R[j] - m0)) : 0.0f;
+        gb[j] = ok ? e * ex2(gg[j] - m1) : 0.0f;
+        Bb[j] = ok ? -e * ex2(Q[j] - m0) : 0.0f;
         lab[j] = 0.0f;
         lbb[j] = 0.0f;
     }
-    // ---- Q adjoint: Tb_i = Bb_i + rho_{i-1} Tb_{i-1} (left to right)
+    // ---- Q adjoint: Tb_i = Bb_i + rho_i Tb_{i-1} (left to right)
     {
         const float qlast_prev_lane = dexcl<G>(Q[IPL - 1], MRF_NINF);
         float rho[IPL], kap[IPL];
@@ -99,72 +90,47 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
         for (int j = 0; j < IPL; ++j) {
             const int i = i0 + j;
             const float qprev = j == 0 ? qlast_prev_lane : Q[j - 1];   // Q_{i-1}
-            rho[j] = 0.0f;
-            kap[j] = 0.0f;
-            if (i >= 1 && i < m) {
-                rho[j] = ex2(al[j] + Q[j] - qprev);
-                kap[j] = ex2(be[j] + gg[j] - qprev);
-            }
+            const bool v = i >= 1 && i < m;
+            rho[j] = v ? ex2(al[j] + Q[j] - qprev) : 0.0f;
+            kap[j] = v ? ex2(c[j] - qprev) : 0.0f;
             lm = amap_then(lm, AMap{rho[j], Bb[j]});
         }
         const AMap incl = dscan_amap<G>(lm);
         float tb = dexcl<G>(incl.b, 0.0f);   // Tb_{i0-1}: every earlier lane's maps applied to 0
 #pragma unroll
-        for (int j = 0; j < IPL; ++j) {
-            const int i = i0 + j;
-            if (i >= 1 && i < m) {
-                const float tk = tb * kap[j];
-                lbb[j] += tk;
-                gb[j] += tk;
-                lab[j] += tb * rho[j];
-            }
+        for (int j = 0; j < IPL; ++j) {   // rho = kap = 0 outside [1, m): no branch needed
+            const float tk = tb * kap[j];
+            lbb[j] += tk;
+            gb[j] += tk;
+            lab[j] += tb * rho[j];
             tb = rho[j] * tb + Bb[j];
         }
     }
-    // ---- S adjoint: Fb_i = Sbar_i + r_i Fb_{i+1} (right to left)
+    // ---- R adjoint: Rb_i = Fd_i + r_i Rb_{i+1} (right to left); R_{i+1}
+    // depends on c_i with weight w_i = 2^(c_i - U_i) and on log mu_i(0) with -1
     {
-        const float sfirst_next_lane = drexcl<G>(S[0], MRF_NINF);
         float rr[IPL], ww[IPL];
         AMap lm = amap_id();
 #pragma unroll
         for (int j = IPL - 1; j >= 0; --j) {
-            const int i = i0 + j;
-            const float snext = j == IPL - 1 ? sfirst_next_lane : S[j + 1];   // S_{i+1}
-            rr[j] = 0.0f;
-            ww[j] = 0.0f;
-            if (i + 1 < m) {
-                rr[j] = ex2(S[j] - snext);
-                ww[j] = ex2(be[j] + gg[j] + P[j] - snext);
-            }
+            rr[j] = ex2(R[j] - U[j]);
+            ww[j] = ex2(c[j] - U[j]);
             lm = amap_then(lm, AMap{rr[j], Fd[j]});
         }
         const AMap incl = drscan_amap<G>(lm);
-        float fb = drexcl<G>(incl.b, 0.0f);   // Fb_{i0+IPL}
+        float fb = drexcl<G>(incl.b, 0.0f);   // Rb_{i0+IPL}; 0 past the ray (R_m feeds nothing)
 #pragma unroll
         for (int j = IPL - 1; j >= 0; --j) {
-            const int i = i0 + j;
-            if (i + 1 < m) {
-                const float wb = fb * ww[j];
-                lbb[j] += wb;
-                gb[j] += wb;
-                Pb[j] += wb;
-            }
+            const float wb = fb * ww[j];
+            lbb[j] += wb;
+            gb[j] += wb;
+            lab[j] -= fb;
             fb = rr[j] * fb + Fd[j];
         }
     }
-    // ---- P adjoint: d/d log mu_k(0) += sum_{i>k} Pbar_i, then d/d lambda
-    {
-        float a = 0.0f;
 #pragma unroll
-        for (int j = 0; j < IPL; ++j) a += Pb[j];
-        float sc = drexcl<G>(drscan<G, OpAdd>(a), 0.0f);
-#pragma unroll
-        for (int j = IPL - 1; j >= 0; --j) {
-            const float lb = lab[j] + sc;
-            lamb[j] = -ex2(be[j]) * lb + ex2(al[j]) * lbb[j];   // d log mu(0)/d lam = -mu(1), d log mu(1)/d lam = mu(0)
-            sc += Pb[j];
-        }
-    }
+    for (int j = 0; j < IPL; ++j)   // d log mu(0)/d lam = -mu(1), d log mu(1)/d lam = mu(0)
+        lamb[j] = -ex2(be[j]) * lab[j] + ex2(al[j]) * lbb[j];
 }
 
 template <int G, int IPL>
@@ -219,32 +185,39 @@ __global__ __launch_bounds__(kTile * G) void ray_adj_lds_k(const uint32_t* __res
     const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
     if (ti >= ntiles) return;   // whole block
     const TileDev td = tiles[list[ti]];
-    const int nf = kTile * td.len;   // td.len <= G * IPL by class
-    for (int idx = threadIdx.x; idx < nf; idx += NT) {
-        const int at = lds_at<IPL>(idx >> 4, idx & 15);
-        sa[at] = lam[td.base + idx];
-        sb[at] = g[td.base + idx];
+    const int nf = kTile * td.len;   // 1 <= td.len <= G * IPL by class
+    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
+    const int gl = (int)threadIdx.x % G;
+    const int i0 = gl * IPL;
+    const int cb = lds_col(i0, gl, i);
+    const int m = tile_ray_len(td, counts, i);
+    float ve[IPL];   // ell-bar, fetched with lambda and g, staged after them
+    {
+        float vl[IPL], vg[IPL];
+        tile_fetch<G, IPL>(lam, td.base, nf, vl);
+        tile_fetch<G, IPL>(g, td.base, nf, vg);
+        tile_fetch<G, IPL>(ellbar, td.base, nf, ve);
+        tile_to_lds<G, IPL>(sa, nf, vl);
+        tile_to_lds<G, IPL>(sb, nf, vg);
     }
     __syncthreads();
-    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
-    const int i0 = ((int)threadIdx.x % G) * IPL;
-    const int m = tile_ray_len(td, counts, i);
     float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
 #pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        const int k = i0 + j;
-        const bool ok = k < m;
-        const int at = lds_at<IPL>(k, i);
-        load_step(ok ? sa[at] : 0.0f, ok ? sb[at] : 0.0f, ok, al[j], be[j], gg[j]);
-    }
+    for (int j = 0; j < IPL; ++j)   // column rows are inside the LDS tile even past the ray
+        load_step(sa[cb + kTile * j], sb[cb + kTile * j], i0 + j < m, al[j], be[j], gg[j]);
     __syncthreads();   // every group has its lambda: reuse sa for ell-bar
-    for (int idx = threadIdx.x; idx < nf; idx += NT) sa[lds_at<IPL>(idx >> 4, idx & 15)] = ellbar[td.base + idx];
+    tile_to_lds<G, IPL>(sa, nf, ve);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
-        const int k = i0 + j;
-        eb[j] = k < m ? sa[lds_at<IPL>(k, i)] : 0.0f;
+        const float v = sa[cb + kTile * j];
+        eb[j] = i0 + j < m ? v : 0.0f;
     }
+    // g-bar sums of earlier sweeps, fetched before the scans so that their
+    // latency hides behind them (unconditionally: a branch here would make
+    // the compiler wait for the loads at its end; unused on the first sweep)
+    float vs[IPL];
+    tile_fetch<G, IPL>(gsum, td.base, nf, vs);
     if (__ballot(m > 0)) {   // skip waves whose rays are all empty; empty rays give zeros
         ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
     } else {
@@ -252,20 +225,21 @@ __global__ __launch_bounds__(kTile * G) void ray_adj_lds_k(const uint32_t* __res
         for (int j = 0; j < IPL; ++j) lamb[j] = gb[j] = 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        const int k = i0 + j;
-        if (k < td.len) {   // own column only; zeros past the ray
-            const int at = lds_at<IPL>(k, i);
-            sa[at] = k < m ? lamb[j] : 0.0f;
-            sb[at] = k < m ? gb[j] : 0.0f;
-        }
+    for (int j = 0; j < IPL; ++j) {   // own column only; zeros past the ray
+        const bool ok = i0 + j < m;
+        sa[cb + kTile * j] = ok ? lamb[j] : 0.0f;
+        sb[cb + kTile * j] = ok ? gb[j] : 0.0f;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nf; idx += NT) {
-        const int at = lds_at<IPL>(idx >> 4, idx & 15);
-        const int64_t o = td.base + idx;
-        lambar[o] = sa[at];
-        gsum[o] = first ? sb[at] : gsum[o] + sb[at];
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+        const int idx = (int)threadIdx.x + r * NT;
+        if (idx < nf) {
+            const int at = lds_at<IPL>(idx >> 4, idx & (kTile - 1));
+            const int64_t o = td.base + idx;
+            lambar[o] = sa[at];
+            gsum[o] = first ? sb[at] : vs[r] + sb[at];
+        }
     }
 }
 

@@ -5,7 +5,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define MRF_NINF (-__builtin_huge_valf())
+// log 0 inside the message kernels: a finite -2^100 instead of -inf.  For every
+// genuine log-domain value x (|x| far below 2^76; log-odds of 1e9 are already
+// extreme) x + MRF_NINF rounds to MRF_NINF and 2^(MRF_NINF - x) is 0, so LSE
+// needs no special case for log 0.  The one visible difference: a ray of a
+// single voxel sends 2^100 ln 2 where the exact message is +inf.
+#define MRF_NINF (-0x1p100f)
 
 namespace mrf {
 
@@ -19,13 +24,18 @@ constexpr float kLn2 = 0.6931471805599453f;
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 
-// log2(2^a + 2^b); log2(0 + 0) = -inf.  Never forms inf - inf; no branch.
+// log2(2^a + 2^b) for finite a, b (log 0 is MRF_NINF)
 __device__ __forceinline__ float lse(float a, float b)
 {
-    const float hi = fmaxf(a, b);
-    const float lo = fminf(a, b);
-    const float d = hi == MRF_NINF ? MRF_NINF : lo - hi;
-    return hi + lg2(1.0f + ex2(d));
+    return fmaxf(a, b) + lg2(1.0f + ex2(-fabsf(a - b)));
+}
+
+// LSE(r, x) - LSE(r, y) as (max(r, x) - max(r, y)) + (softplus differences): a
+// common dominant r cancels exactly instead of through rounded sums
+__device__ __forceinline__ float lse_diff(float r, float x, float y)
+{
+    const float hx = fmaxf(r, x), hy = fmaxf(r, y);
+    return (hx - hy) + (lg2(1.0f + ex2(-fabsf(r - x))) - lg2(1.0f + ex2(-fabsf(r - y))));
 }
 
 // log2 sum_j 2^x_j of a lane's items: maximum first, then one exp2 per item
@@ -35,21 +45,14 @@ __device__ __forceinline__ float lse_items(const float (&x)[N])
     float mx = MRF_NINF;
 #pragma unroll
     for (int j = 0; j < N; ++j) mx = fmaxf(mx, x[j]);
-    if (mx == MRF_NINF) return MRF_NINF;
     float sm = 0.0f;
 #pragma unroll
     for (int j = 0; j < N; ++j) sm += ex2(x[j] - mx);
     return mx + lg2(sm);
 }
 
-// log2(1 + 2^x)
-__device__ __forceinline__ float softplus(float x)
-{
-    return fmaxf(x, 0.0f) + lg2(1.0f + ex2(-fabsf(x)));
-}
-
 // x -> LSE(c, a + x): one voxel's step of the suffix recurrence of the second
-// sum of Eq. neg.  Identity is (0, -inf).
+// sum of Eq. neg.  Identity is (0, log 0).
 struct LMap {
     float a, c;
 };
@@ -315,6 +318,31 @@ __device__ __forceinline__ LMap dpp_lmap(LMap old, LMap src)
 }
 
 __device__ __forceinline__ LMap readlane_lmap(LMap x, int l) { return LMap{readlane(x.a, l), readlane(x.c, l)}; }
+
+// prefix: element i gets map_i o ... o map_0 (maps applied left to right)
+template <int G>
+__device__ __forceinline__ LMap dscan_lmap(LMap x)
+{
+    const LMap I = lmap_id();
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHR1>(I, x));
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHR2>(I, x));
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHR4>(I, x));
+    x = lmap_compose(x, dpp_lmap<DPP_ROW_SHR8>(I, x));
+    if (G == 32) {
+        const LMap r0 = readlane_lmap(x, 15), r2 = readlane_lmap(x, 47);
+        const int row = (threadIdx.x & 63) >> 4;
+        if (row & 1) x = lmap_compose(x, row == 1 ? r0 : r2);
+    }
+    if (G == 64) {
+        const LMap r0 = readlane_lmap(x, 15), r1 = readlane_lmap(x, 31), r2 = readlane_lmap(x, 47);
+        const LMap c2 = lmap_compose(r1, r0);
+        const LMap c3 = lmap_compose(r2, c2);
+        const int row = (threadIdx.x & 63) >> 4;
+        const LMap c = row == 1 ? r0 : (row == 2 ? c2 : c3);
+        if (row) x = lmap_compose(x, c);
+    }
+    return x;
+}
 
 template <int G>
 __device__ __forceinline__ LMap drscan_lmap(LMap x)

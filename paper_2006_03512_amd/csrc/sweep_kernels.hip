@@ -10,15 +10,14 @@
 //
 // Voxel phase: one group of lanes per voxel's edge list (or per 1024-edge
 // piece of a hub voxel), exclusive prefix and suffix sums, never a
-// difference, so +-inf and large log-odds stay exact.
-// Ray phase: one group of lanes per ray, three group scans over the ray:
-//   P_i = sum_{k<i} log mu_k(0)                    prefix sum
-//   S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)      prefix log-sum-exp
+// difference, so large log-odds never cancel.
+// Ray phase: one group of lanes per ray.  With P_i = sum_{k<i} log mu_k(0),
+//   S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)
 //   Q_i = LSE(log mu_{i+1}(1) + g_{i+1}, log mu_{i+1}(0) + Q_{i+1})
-//                                                  suffix scan of maps
 //   ell_i = LSE(S_i, g_i + P_i) - LSE(S_i, P_i + Q_i)
-// which is Eq. pos over Eq. neg with the second sum of Eq. neg in its
-// division-free form (sum over j > i of the product over k < j, k != i).
+// is Eq. pos over Eq. neg with the second sum of Eq. neg in its division-free
+// form (sum over j > i of the product over k < j, k != i).  The kernels carry
+// R_i = S_i - P_i instead of S and P (see ray_body).
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -357,56 +356,49 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, fl
 // ------------------------------------------------------------ ray phase
 
 // Messages of one ray held by a group of G lanes, blocked: lane l holds steps
-// [i0, i0 + IPL), i0 = l IPL, as base-2 log mu(0), log mu(1) and g, with
-// neutral padding past the ray's m steps.  Each scan runs sequentially inside
-// a lane and once across the group on the lane aggregates.  put(j, ell)
-// receives the natural-log message of every step i0 + j < m.
+// [i0, i0 + IPL), i0 = l IPL, as base-2 log mu(0) (al), log mu(1) (be) and g,
+// with neutral padding past the ray's m steps.  With c_i = log mu_i(1) + g_i
+// the kernel carries P-free quantities (P_i, the log visibility up to voxel i,
+// can reach 1e6 and would leak its rounding into every message):
+//   R_i = S_i - P_i:  R_0 = log 0,  R_{i+1} = LSE(R_i, c_i) - log mu_i(0)
+//   Q_i:              Q_{m-1} = log 0,  Q_{i-1} = LSE(c_i, log mu_i(0) + Q_i)
+//   ell_i = LSE(R_i, g_i) - LSE(R_i, Q_i)
+// Both recurrences are maps x -> LSE(c, a + x), scanned once across the group
+// on the lane aggregates and walked sequentially inside the lane.
+// put(j, ok, ell) receives the natural-log message of step i0 + j (meaningful
+// when ok, i.e. i0 + j < m).
 template <int G, int IPL, class Put>
 __device__ __forceinline__ void ray_body(const float (&al)[IPL], const float (&be)[IPL], const float (&gg)[IPL],
                                          int m, int i0, Put&& put)
 {
-    // lane aggregate Cl = LSE_j (c_j + lp_j), c_j = log mu_j(1) + g_j, lp_j the
-    // lane-local prefix of log mu(0): the lane's share of the S scan is p0 + Cl
-    // and its composed Q map is (sum of log mu(0), Cl)
-    float cw[IPL];
+    // lane aggregate Cl = LSE_j (c_j + lp_j), lp_j the lane-local prefix of
+    // log mu(0), a the lane sum: the lane's R map is (-a, Cl - a) and its Q
+    // map (a, Cl)
+    float c[IPL], cw[IPL];
     float a = 0.0f;
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
-        cw[j] = be[j] + gg[j] + a;
+        c[j] = be[j] + gg[j];
+        cw[j] = c[j] + a;
         a += al[j];
     }
     const float Cl = lse_items<IPL>(cw);
-    // P_i = sum_{k<i} log mu_k(0)
-    const float p0 = dexcl<G>(dscan<G, OpAdd>(a), 0.0f);
-    float P[IPL];
-    float p = p0;
-#pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        P[j] = p;
-        p += al[j];
-    }
-    // S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)
-    float S[IPL];
+    float R[IPL];
     {
-        float sc = dexcl<G>(dscan<G, OpLse>(p0 + Cl), MRF_NINF);
+        const LMap left = dscan_lmap<G>(LMap{-a, Cl - a});
+        float r = dexcl<G>(left.c, MRF_NINF);
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
-            S[j] = sc;
-            sc = lse(sc, be[j] + gg[j] + P[j]);
+            R[j] = r;
+            r = lse(r, c[j]) - al[j];
         }
     }
-    // Q_i = LSE(c_{i+1}, log mu_{i+1}(0) + Q_{i+1}): scan the lane maps from
-    // the right, then walk the lane backwards
     const LMap right = drscan_lmap<G>(LMap{a, Cl});
     float Q = drexcl<G>(right.c, MRF_NINF);
 #pragma unroll
     for (int j = IPL - 1; j >= 0; --j) {
-        if (i0 + j < m) {
-            const float m1 = lse(S[j], gg[j] + P[j]);
-            const float m0 = lse(S[j], P[j] + Q);
-            put(j, (m1 - m0) * kLn2);
-        }
-        Q = lse(be[j] + gg[j], al[j] + Q);
+        put(j, i0 + j < m, lse_diff(R[j], gg[j], Q) * kLn2);
+        Q = lse(c[j], al[j] + Q);
     }
 }
 
@@ -430,15 +422,16 @@ __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, 
         const bool ok = i < m;
         load_step(ok ? lam[s + kTile * i] : 0.0f, ok ? g[s + kTile * i] : 0.0f, ok, al[j], be[j], gg[j]);
     }
-    ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, float v) { ell[s + kTile * (i0 + j)] = v; });
+    ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, bool ok, float v) {
+        if (ok) ell[s + kTile * (i0 + j)] = v;
+    });
 }
 
 // Tile-staged variant for tiles of at most G*IPL steps: one block of 16 groups
 // per tile.  The block copies the tile's lambda and g (16 rays x len steps,
 // contiguous) into LDS with coalesced loads, every group runs the scans of its
-// own ray on its LDS column and writes ell back into that column, and the
-// block stores the tile coalesced.  Padding slots past a ray receive its
-// staged lambda, which nothing reads.
+// own ray on its LDS column and writes ell back into that column (0 past the
+// ray), and the block stores the tile coalesced.
 template <int G, int IPL>
 __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                        const TileDev* __restrict__ tiles,
@@ -452,29 +445,33 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
     const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
     if (ti >= ntiles) return;   // whole block
     const TileDev td = tiles[list[ti]];
-    const int nf = kTile * td.len;   // td.len <= G * IPL by class
-    for (int idx = threadIdx.x; idx < nf; idx += NT) {
-        const int at = lds_at<IPL>(idx >> 4, idx & 15);
-        sl[at] = lam[td.base + idx];
-        sg[at] = g[td.base + idx];
+    const int nf = kTile * td.len;   // 1 <= td.len <= G * IPL by class
+    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
+    const int gl = (int)threadIdx.x % G;
+    const int i0 = gl * IPL;
+    const int cb = lds_col(i0, gl, i);
+    const int m = tile_ray_len(td, counts, i);
+    {
+        float vl[IPL], vg[IPL];
+        tile_fetch<G, IPL>(lam, td.base, nf, vl);
+        tile_fetch<G, IPL>(g, td.base, nf, vg);
+        tile_to_lds<G, IPL>(sl, nf, vl);
+        tile_to_lds<G, IPL>(sg, nf, vg);
     }
     __syncthreads();
-    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
-    const int i0 = ((int)threadIdx.x % G) * IPL;
-    const int m = tile_ray_len(td, counts, i);
     if (__ballot(m > 0)) {   // skip waves whose rays are all empty
         float al[IPL], be[IPL], gg[IPL];
 #pragma unroll
-        for (int j = 0; j < IPL; ++j) {
-            const int k = i0 + j;
-            const bool ok = k < m;
-            const int at = lds_at<IPL>(k, i);
-            load_step(ok ? sl[at] : 0.0f, ok ? sg[at] : 0.0f, ok, al[j], be[j], gg[j]);
-        }
-        ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, float v) { sl[lds_at<IPL>(i0 + j, i)] = v; });
+        for (int j = 0; j < IPL; ++j)   // column rows are inside the LDS tile even past the ray
+            load_step(sl[cb + kTile * j], sg[cb + kTile * j], i0 + j < m, al[j], be[j], gg[j]);
+        ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, bool ok, float v) { sl[cb + kTile * j] = ok ? v : 0.0f; });
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nf; idx += NT) ell[td.base + idx] = sl[lds_at<IPL>(idx >> 4, idx & 15)];
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+        const int idx = (int)threadIdx.x + r * NT;
+        if (idx < nf) ell[td.base + idx] = sl[lds_at<IPL>(idx >> 4, idx & (kTile - 1))];
+    }
 }
 
 template <int Q>

@@ -20,6 +20,39 @@ __device__ __forceinline__ int lds_at(int k, int i)
     return k * kTile + (i ^ ((k / IPL) & (kTile - 1)));
 }
 
+// lds_at<IPL>(i0 + j, i) for the steps [i0, i0 + IPL) of group lane gl
+// (i0 = gl IPL, so (i0 + j) / IPL = gl): the column base; step i0 + j is at
+// base + 16 j, an immediate offset.
+__device__ __forceinline__ int lds_col(int i0, int gl, int i)
+{
+    return i0 * kTile + (i ^ (gl & (kTile - 1)));
+}
+
+// A block of 16 G threads moves a tile's nf = 16 len floats (len <= G IPL) in
+// at most IPL rounds: thread t handles idx = t + r 16 G, r < IPL.  Loads go
+// through registers so that every round's load is issued before the first
+// wait; indices past nf are clamped to the tile's last float (len >= 1) and
+// their values dropped.
+template <int G, int IPL>
+__device__ __forceinline__ void tile_fetch(const float* __restrict__ src, int64_t base, int nf, float (&v)[IPL])
+{
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+        const int idx = min((int)threadIdx.x + r * kTile * G, nf - 1);
+        v[r] = src[base + idx];
+    }
+}
+
+template <int G, int IPL>
+__device__ __forceinline__ void tile_to_lds(float* __restrict__ lds, int nf, const float (&v)[IPL])
+{
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+        const int idx = (int)threadIdx.x + r * kTile * G;
+        if (idx < nf) lds[lds_at<IPL>(idx >> 4, idx & (kTile - 1))] = v[r];
+    }
+}
+
 // steps of tile lane i (0 for pixels outside the image)
 __device__ __forceinline__ int tile_ray_len(const TileDev& td, const int32_t* __restrict__ counts, int i)
 {
@@ -28,20 +61,19 @@ __device__ __forceinline__ int tile_ray_len(const TileDev& td, const int32_t* __
 }
 
 // base-2 log mu(0), log mu(1) and g of one step from lambda and g (natural
-// log); neutral padding (0, -inf, 0) when the step is past the ray
+// log); neutral padding (0, log 0, 0) when the step is past the ray.  With
+// x = lambda log2(e) and t = log2(1 + 2^-|x|): log mu(0) = -(max(x, 0) + t),
+// log mu(1) = -(max(-x, 0) + t), both free of cancellation (x - softplus(x)
+// would lose the small one to the rounding of x once |lambda| is large).  No
+// branch: past the ray the inputs may be any bits and are discarded by the
+// selects.
 __device__ __forceinline__ void load_step(float lam, float g, bool ok, float& al, float& be, float& gg)
 {
-    if (ok) {
-        const float x = lam * kLog2e;
-        const float sp = softplus(x);
-        al = -sp;
-        be = x - sp;
-        gg = g * kLog2e;
-    } else {
-        al = 0.0f;
-        be = MRF_NINF;
-        gg = 0.0f;
-    }
+    const float x = lam * kLog2e;
+    const float t = lg2(1.0f + ex2(-fabsf(x)));
+    al = ok ? -(fmaxf(x, 0.0f) + t) : 0.0f;
+    be = ok ? -(fmaxf(-x, 0.0f) + t) : MRF_NINF;
+    gg = ok ? g * kLog2e : 0.0f;
 }
 
 }  // namespace mrf
