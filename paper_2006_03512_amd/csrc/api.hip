@@ -370,11 +370,8 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
     HCK(ensure(c->b_sigpart, sizeof(double) * 4 * kBins), "mrf_build: alloc sigma partials");
 
-    // padding slots: no voxel (col -1), no bin (255), sort key past every voxel
-    HCK(hipMemsetAsync(c->b_col.p, 0xFF, e4, s), "mrf_build: init");
-    HCK(hipMemsetAsync(c->b_bin.p, 0xFF, e1, s), "mrf_build: init");
-    HCK(hipMemsetAsync(c->b_delta.p, 0, e4, s), "mrf_build: init");
-    HCK(launch_fill_u32((uint32_t*)c->b_g.p, (uint32_t)Vk, S, s), "mrf_build: init");
+    // every slot is written: edges by the traversal, the rest as padding (no voxel,
+    // no bin, sort key past every voxel)
     HCK(launch_trace_emit(c, s), "mrf_build: trace emit");
 
     // voxel -> ray incidence by a stable LSD radix sort of (brick-major voxel key,

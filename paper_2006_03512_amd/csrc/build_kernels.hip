@@ -177,10 +177,14 @@ struct EdgeEmit {
 // Threads are grouped by tile: the 16 lanes 16t..16t+15 of a block trace the 16 pixels
 // of tile t, so at every traversal step they write one whole 64-byte line of each
 // per-slot array (a row-major pixel order would write 16-byte pieces of 16 lines).
+// Each lane then marks its column's slots past its ray, up to the tile's length, as
+// padding (no voxel, no bin, sort key pad_key past every voxel); lanes of pixels
+// outside the image pad their whole column.
 __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__ scenes,
                                                     const FrameDev* __restrict__ frames, BuildDev bp,
                                                     const int32_t* __restrict__ counts,
                                                     const int64_t* __restrict__ tbase,
+                                                    const TileDev* __restrict__ tiles, uint32_t pad_key,
                                                     int32_t* col, uint32_t* key, float* delta, uint8_t* bin,
                                                     double* tin, double* tout)
 {
@@ -192,15 +196,27 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
     const int ty = lt / fr.ntx, tx = lt - ty * fr.ntx;
     const int q = (int)threadIdx.x % kTile;
     const int v = ty * kTileW + q / kTileW, u = tx * kTileW + q % kTileW;
-    if (v >= sd.H || u >= sd.W) return;
-    const int pix = v * sd.W + u;
-    const int64_t r = fr.ray_base + pix;
-    if (counts[r] == 0) return;
-    const int64_t slot0 = tbase[fr.tile_base + lt] + q;
-    Ray ray;
-    setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
-    EdgeEmit em{col, key, delta, bin, tin, tout, &sd, slot0, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
-    walk(sd, ray, em);
+    const int64_t t = fr.tile_base + lt;
+    const int64_t slot0 = tbase[t] + q;
+    const int len = tiles[t].len;
+    int m = 0;
+    if (v < sd.H && u < sd.W) {
+        const int pix = v * sd.W + u;
+        m = counts[fr.ray_base + pix];
+        if (m > 0) {
+            Ray ray;
+            setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
+            EdgeEmit em{col, key, delta, bin, tin, tout, &sd, slot0, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
+            walk(sd, ray, em);
+        }
+    }
+    for (int k = m; k < len; ++k) {
+        const int64_t e = slot0 + (int64_t)kTile * k;
+        col[e] = -1;
+        key[e] = pad_key;
+        delta[e] = 0.0f;
+        bin[e] = 255;
+    }
 }
 
 // One thread per tile: its rays, extent inside the image and longest ray.
@@ -283,7 +299,7 @@ hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s)
     dim3 grid((unsigned)((c->max_tpf + 256 / kTile - 1) / (256 / kTile)), c->n_frames);
     hipLaunchKernelGGL(trace_emit_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
                        (const FrameDev*)c->b_frames.p, c->bp, (const int32_t*)c->b_counts.p,
-                       (const int64_t*)c->b_tbase.p,
+                       (const int64_t*)c->b_tbase.p, (const TileDev*)c->b_tiles.p, (uint32_t)c->Vk,
                        (int32_t*)c->b_col.p, (uint32_t*)c->b_g.p, (float*)c->b_delta.p, (uint8_t*)c->b_bin.p,
                        c->keep_chords ? (double*)c->b_tin.p : nullptr,
                        c->keep_chords ? (double*)c->b_tout.p : nullptr);

@@ -28,7 +28,7 @@ constexpr int kLdsMaxCap = 512;
 #define MRF_RAY_GROUPS 16, 16, 16, 16, 32, 32, 32, 64, 64, 64, 64, 64, 64
 #endif
 #ifndef MRF_ADJ_GROUPS
-#define MRF_ADJ_GROUPS 16, 16, 32, 64, 32, 64, 64, 64, 64, 64, 64, 64, 64
+#define MRF_ADJ_GROUPS 16, 16, 16, 32, 32, 64, 64, 64, 64, 64, 64, 64, 64
 #endif
 constexpr int kRayG[kRayClasses] = {MRF_RAY_GROUPS};
 constexpr int kAdjG[kRayClasses] = {MRF_ADJ_GROUPS};

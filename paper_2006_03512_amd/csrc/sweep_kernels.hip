@@ -127,19 +127,39 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 
 constexpr int VIPL = kVoxChunk / 64;   // items per lane in a 256-edge chunk
 
+// Items base + 64 k + l (k < N, l the lane) of the edge list [s, s+m) of one
+// voxel: their slots into e and incoming messages into x (0 past m, or
+// everywhere when in is null).  Branchless, with item indices clamped to
+// m - 1 (m >= 1), so that every load is issued before the first wait.
+template <int N>
+__device__ __forceinline__ void vox_gather(int64_t s, int m, int base, const uint32_t* __restrict__ vedge,
+                                           const float* __restrict__ in, uint32_t (&e)[N], float (&x)[N])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < N; ++k) e[k] = vedge[s + min(base + k * 64 + l, m - 1)];
+    if (in) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) x[k] = in[e[k]];
+#pragma unroll
+        for (int k = 0; k < N; ++k) x[k] = base + k * 64 + l < m ? x[k] : 0.0f;
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) x[k] = 0.0f;
+    }
+}
+
 // Sum of chunk c of the segment [s, s+m) (every lane gets it).
 __device__ __forceinline__ float vox_chunk_sum(int64_t s, int m, int c, const uint32_t* __restrict__ vedge,
                                                const float* __restrict__ in)
 {
-    const int l = threadIdx.x & 63;
+    if (!in) return 0.0f;
+    float x[VIPL];
+    uint32_t e[VIPL];
+    vox_gather<VIPL>(s, m, c * kVoxChunk, vedge, in, e, x);
     float acc = 0.0f;
-    if (in) {
 #pragma unroll
-        for (int k = 0; k < VIPL; ++k) {
-            const int i = c * kVoxChunk + k * 64 + l;
-            if (i < m) acc += in[vedge[s + i]];
-        }
-    }
+    for (int k = 0; k < VIPL; ++k) acc += x[k];
     return wave_sum(acc);
 }
 
@@ -153,16 +173,7 @@ __device__ __forceinline__ float vox_chunk(int64_t s, int m, int c, const uint32
     const int l = threadIdx.x & 63;
     float x[VIPL];
     uint32_t e[VIPL];
-#pragma unroll
-    for (int k = 0; k < VIPL; ++k) {
-        const int i = c * kVoxChunk + k * 64 + l;
-        e[k] = 0;
-        x[k] = 0.0f;
-        if (i < m) {
-            e[k] = vedge[s + i];
-            if (in) x[k] = in[e[k]];
-        }
-    }
+    vox_gather<VIPL>(s, m, c * kVoxChunk, vedge, in, e, x);
     float pre[VIPL];
     float carry = pre0;
 #pragma unroll
@@ -208,16 +219,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
 
     float x[IPL];
     uint32_t e[IPL];
-#pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const int i = part * SPAN + k * 64 + l;
-        e[k] = 0;
-        x[k] = 0.0f;
-        if (i < m) {
-            e[k] = vedge[s + i];
-            if (in) x[k] = in[e[k]];
-        }
-    }
+    vox_gather<IPL>(s, m, part * SPAN, vedge, in, e, x);
     float pre0 = 0.0f, suf0 = 0.0f, tot = 0.0f;
     if (NW > 1) {
         __shared__ float wsum[NW > 1 ? NW : 1];
