@@ -284,7 +284,8 @@ hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar,
 
 // ------------------------------------------------------------ sigma table
 
-constexpr int SG_BLOCKS = 1024;
+constexpr int SG_BLOCKS = 8192;   // blocks of the sigma-table reduction (at most)
+constexpr int SG_U = 4;           // chunks per round
 
 __device__ __forceinline__ void fx_add(unsigned long long* lo, long long* hi, double v)
 {
@@ -317,31 +318,44 @@ __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gs
     const int lane = threadIdx.x & 63;
     const int64_t nchunks = (E + 63) / 64;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (int64_t ch = wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
-        const int64_t e = ch * 64 + lane;
-        const int braw = e < E ? (int)bin[e] : 255;
-        const bool valid = braw < kBins;   // padding slots carry bin 255
-        const int b = valid ? braw : -1;
-        double x = 0.0;
-        if (valid) {
-            const double d = (double)delta[e];
-            x = (double)gsum[e] * (d * d * inv3[b] - inv[b]);
-        }
-        // segmented inclusive sum over runs of equal bins (fixed tree order)
-        const int bup = __shfl_up(b, 1, 64);
-        int f = (lane == 0 || bup != b) ? 1 : 0;
+    // SG_U consecutive 64-slot chunks per round, their loads issued together
+    for (int64_t c0 = wave * SG_U; c0 < nchunks; c0 += (int64_t)gridDim.x * 4 * SG_U) {
+        int br[SG_U];
+        float dl[SG_U], gs[SG_U];
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double y = __shfl_up(x, d, 64);
-            const int gflag = __shfl_up(f, d, 64);
-            if (lane >= d) {
-                if (!f) x = y + x;
-                f |= gflag;
-            }
+        for (int u = 0; u < SG_U; ++u) {
+            const int64_t e = (c0 + u) * 64 + lane;
+            const int64_t ec = e < E ? e : E - 1;
+            br[u] = (int)bin[ec];
+            dl[u] = delta[ec];
+            gs[u] = gsum[ec];
         }
-        const int bdn = __shfl_down(b, 1, 64);
-        const bool tail = valid && (lane == 63 || bdn != b || e + 1 >= E);
-        if (tail) fx_add(&slo[b], &shi[b], x);
+#pragma unroll
+        for (int u = 0; u < SG_U; ++u) {
+            const int64_t e = (c0 + u) * 64 + lane;
+            const bool valid = e < E && br[u] < kBins;   // padding slots carry bin 255
+            const int b = valid ? br[u] : -1;
+            double x = 0.0;
+            if (valid) {
+                const double d = (double)dl[u];
+                x = (double)gs[u] * (d * d * inv3[b] - inv[b]);
+            }
+            // segmented inclusive sum over runs of equal bins (fixed tree order)
+            const int bup = __shfl_up(b, 1, 64);
+            int f = (lane == 0 || bup != b) ? 1 : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const double y = __shfl_up(x, d, 64);
+                const int gflag = __shfl_up(f, d, 64);
+                if (lane >= d) {
+                    if (!f) x = y + x;
+                    f |= gflag;
+                }
+            }
+            const int bdn = __shfl_down(b, 1, 64);
+            const bool tail = valid && (lane == 63 || bdn != b || e + 1 >= E);
+            if (tail) fx_add(&slo[b], &shi[b], x);
+        }
     }
     __syncthreads();
     if (threadIdx.x < kBins) {
@@ -374,7 +388,7 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s)
     hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(64), 0, s, glo, ghi);
     if (c->S > 0) {
         ProfScope ps(c, KID_SIGMA, s);
-        int64_t blocks = (c->S + 255) / 256;
+        int64_t blocks = (c->S + 256 * SG_U - 1) / (256 * SG_U);
         if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
         hipLaunchKernelGGL(sigma_grad_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_gsum.p,
                            (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p, c->S,

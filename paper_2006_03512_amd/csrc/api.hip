@@ -56,7 +56,7 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
     for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
     for (const auto& b : c->b_vox_list) k.push_back((uint64_t)(uintptr_t)b.p);
-    for (const auto& b : c->b_vox_ext) k.push_back((uint64_t)(uintptr_t)b.p);
+    for (const auto& b : c->b_vox_desc) k.push_back((uint64_t)(uintptr_t)b.p);
     return k;
 }
 
@@ -208,7 +208,7 @@ void mrf_destroy(mrf_ctx* c)
     for (DevBuf* b : all) free_buf(*b);
     for (auto& b : c->b_ray_list) free_buf(b);
     for (auto& b : c->b_vox_list) free_buf(b);
-    for (auto& b : c->b_vox_ext) free_buf(b);
+    for (auto& b : c->b_vox_desc) free_buf(b);
     for (int i = 0; i < mrf_ctx::kPar; ++i) {
         if (c->par_join[i]) hipEventDestroy(c->par_join[i]);
         if (c->par[i]) hipStreamDestroy(c->par[i]);

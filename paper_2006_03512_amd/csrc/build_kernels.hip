@@ -609,11 +609,17 @@ __device__ uint32_t key_to_voxel(const SceneDev* __restrict__ scenes, int ns, ui
     return (uint32_t)(sd.voxel_base + i + (int64_t)sd.n[0] * (j + (int64_t)sd.n[1] * k));
 }
 
-__global__ void keys_to_voxels_k(const SceneDev* __restrict__ scenes, int ns, const uint32_t* __restrict__ keys,
-                                 int64_t n, uint32_t* __restrict__ ext)
+__global__ void vox_desc_k(const SceneDev* __restrict__ scenes, int ns, const uint32_t* __restrict__ keys, int64_t n,
+                           const int64_t* __restrict__ vptr, VoxDev* __restrict__ desc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) ext[i] = key_to_voxel(scenes, ns, keys[i]);
+    if (i >= n) return;
+    const uint32_t key = keys[i];
+    VoxDev d;
+    d.start = vptr[key];
+    d.m = (int32_t)(vptr[key + 1] - d.start);
+    d.v = key_to_voxel(scenes, ns, key);
+    desc[i] = d;
 }
 
 // brick-major key of a linear voxel id
@@ -837,11 +843,11 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
             hipSuccess)
             return e;
         const int64_t n = c->vox_cnt[k];
-        if ((e = ensure(c->b_vox_ext[k], (size_t)(n > 0 ? n : 1) * sizeof(uint32_t))) != hipSuccess) return e;
+        if ((e = ensure(c->b_vox_desc[k], (size_t)(n > 0 ? n : 1) * sizeof(VoxDev))) != hipSuccess) return e;
         if (n > 0)
-            hipLaunchKernelGGL(keys_to_voxels_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s,
+            hipLaunchKernelGGL(vox_desc_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s,
                                (const SceneDev*)c->b_scenes.p, c->n_scenes, (const uint32_t*)c->b_vox_list[k].p, n,
-                               (uint32_t*)c->b_vox_ext[k].p);
+                               (const int64_t*)c->b_vptr.p, (VoxDev*)c->b_vox_desc[k].p);
     }
     {
         DevBuf tmp;

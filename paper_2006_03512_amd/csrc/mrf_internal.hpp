@@ -102,6 +102,14 @@ struct TileDev {
     int32_t pad;
 };
 
+// Work item of the voxel kernels: one voxel's edge list vedge[start, start + m)
+// and its linear id.
+struct VoxDev {
+    int64_t start;
+    int32_t m;
+    uint32_t v;
+};
+
 struct BuildDev {
     double z_min, z_max, nsig, c0, c2, smin, dmax;
     int32_t min_vox;
@@ -164,7 +172,7 @@ struct mrf_ctx {
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
     mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
     mrf::DevBuf b_vox_list[mrf::kVoxClasses];     // brick-major keys
-    mrf::DevBuf b_vox_ext[mrf::kVoxClasses];      // matching linear voxel ids
+    mrf::DevBuf b_vox_desc[mrf::kVoxClasses];     // matching VoxDev descriptors
     mrf::DevBuf b_frame_list;     // per-frame ray lists for the plain schedule
 
     int64_t ray_cnt[mrf::kRayClasses] = {0};       // tiles per class

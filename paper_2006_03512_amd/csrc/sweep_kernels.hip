@@ -202,9 +202,8 @@ __device__ __forceinline__ float vox_chunk(int64_t s, int m, int c, const uint32
 // are remapped so each XCD takes a contiguous range of them.
 template <int NW, int IPL>
 __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ext, int64_t n, const int64_t* __restrict__ vptr,
-    const uint32_t* __restrict__ vedge, const float* __restrict__ base, const float* __restrict__ in,
-    float* __restrict__ out, float* __restrict__ total, int total_mode)
+    const VoxDev* __restrict__ vd, int64_t n, const uint32_t* __restrict__ vedge, const float* __restrict__ base,
+    const float* __restrict__ in, float* __restrict__ out, float* __restrict__ total, int total_mode)
 {
     constexpr int SPAN = 64 * IPL;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -212,9 +211,10 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
     const int64_t vi = NW == 1 ? lb * 4 + wv : lb;
     const int part = NW == 1 ? 0 : wv;
     if (vi >= n) return;   // whole waves (NW == 1) or whole blocks (NW > 1)
-    const uint32_t key = keys[vi], v = ext[vi];
-    const int64_t s = vptr[key];
-    const int m = (int)(vptr[key + 1] - s);
+    const VoxDev d = vd[vi];
+    const uint32_t v = d.v;
+    const int64_t s = d.start;
+    const int m = d.m;
     const float b0 = base ? base[v] : 0.0f;
 
     float x[IPL];
@@ -265,9 +265,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
 // One 1024-thread block per voxel of degree above the largest single-pass
 // class: chunk sums into LDS, exclusive prefix / suffix of the chunk sums by
 // wave 0 in fixed order, then every wave revisits its chunks with both carries.
-__global__ __launch_bounds__(1024) void voxel_chunked_k(const uint32_t* __restrict__ keys,
-                                                        const uint32_t* __restrict__ ext, int64_t n,
-                                                        const int64_t* __restrict__ vptr,
+__global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict__ vd, int64_t n,
                                                         const uint32_t* __restrict__ vedge,
                                                         const float* __restrict__ base, const float* __restrict__ in,
                                                         float* __restrict__ out, float* __restrict__ total,
@@ -280,9 +278,10 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const uint32_t* __restri
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= n) return;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const uint32_t key = keys[b], v = ext[b];
-    const int64_t s = vptr[key];
-    const int m = (int)(vptr[key + 1] - s);
+    const VoxDev d = vd[b];
+    const uint32_t v = d.v;
+    const int64_t s = d.start;
+    const int m = d.m;
     const float b0 = base ? base[v] : 0.0f;
     const int nch = (m + kVoxChunk - 1) / kVoxChunk;   // <= kVoxMaxChunks (checked at build)
     for (int c = wv; c < nch; c += 16) {
@@ -328,8 +327,8 @@ static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float
     ProfScope ps(c, KID_VOX0 + k, s);
     const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
     hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
-                       (const uint32_t*)c->b_vox_list[k].p, (const uint32_t*)c->b_vox_ext[k].p, n,
-                       (const int64_t*)c->b_vptr.p, (const uint32_t*)c->b_vedge.p, base, in, out, total, mode);
+                       (const VoxDev*)c->b_vox_desc[k].p, n, (const uint32_t*)c->b_vedge.p, base, in, out, total,
+                       mode);
 }
 
 hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out, float* total,
@@ -347,9 +346,8 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, fl
         const hipStream_t sc = class_stream(c, kc, s);
         ProfScope ps(c, KID_VOX0 + kc, sc);
         hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, sc,
-                           (const uint32_t*)c->b_vox_list[kc].p, (const uint32_t*)c->b_vox_ext[kc].p,
-                           c->vox_cnt[kc], (const int64_t*)c->b_vptr.p, (const uint32_t*)c->b_vedge.p, base, in,
-                           out, total, total_mode);
+                           (const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p, base,
+                           in, out, total, total_mode);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return join_streams(c, s);
