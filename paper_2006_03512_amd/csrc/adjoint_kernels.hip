@@ -245,13 +245,12 @@ __global__ __launch_bounds__(kTile * G) void ray_adj_lds_k(const uint32_t* __res
 
 template <int Q>
 static void launch_adj_class(const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
-                             int first, hipStream_t s0)
+                             int first, hipStream_t s)
 {
     const int64_t n = c->ray_cnt[Q];
     if (n <= 0) return;
     constexpr int CAP = kRayCap[Q];
     constexpr int G = ray_class_group(Q, true);
-    const hipStream_t s = class_stream(c, Q, s0);
     ProfScope ps(c, KID_ADJ0 + Q, s);
     const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p;
     if constexpr (ray_class_lds(Q)) {
@@ -275,11 +274,8 @@ static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, cons
 hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
                               bool first, hipStream_t s)
 {
-    hipError_t e;
-    if ((e = fork_streams(c, s)) != hipSuccess) return e;
     adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, lam, ellbar, lambar, gsum, first ? 1 : 0, s);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return join_streams(c, s);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ sigma table

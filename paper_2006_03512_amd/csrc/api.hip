@@ -73,25 +73,6 @@ namespace mrf {
 
 void set_error(const std::string& msg) { g_err = msg; }
 
-hipError_t fork_streams(mrf_ctx* c, hipStream_t s)
-{
-    if (!c->npar) return hipSuccess;
-    hipError_t e = hipEventRecord(c->par_fork, s);
-    for (int i = 0; i < c->npar && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->par[i], c->par_fork, 0);
-    return e;
-}
-
-hipError_t join_streams(mrf_ctx* c, hipStream_t s)
-{
-    if (!c->npar) return hipSuccess;
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < c->npar && e == hipSuccess; ++i) {
-        e = hipEventRecord(c->par_join[i], c->par[i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, c->par_join[i], 0);
-    }
-    return e;
-}
-
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
@@ -175,11 +156,6 @@ int mrf_create(mrf_ctx** out)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->par_fork, hipEventDisableTiming);
-    for (int i = 0; i < mrf_ctx::kPar && e == hipSuccess; ++i) {
-        e = hipStreamCreateWithFlags(&c->par[i], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->par_join[i], hipEventDisableTiming);
-    }
     if (e != hipSuccess) {
         int rc = hip_fail(e, "mrf_create");
         mrf_destroy(c);
@@ -209,11 +185,6 @@ void mrf_destroy(mrf_ctx* c)
     for (auto& b : c->b_ray_list) free_buf(b);
     for (auto& b : c->b_vox_list) free_buf(b);
     for (auto& b : c->b_vox_desc) free_buf(b);
-    for (int i = 0; i < mrf_ctx::kPar; ++i) {
-        if (c->par_join[i]) hipEventDestroy(c->par_join[i]);
-        if (c->par[i]) hipStreamDestroy(c->par[i]);
-    }
-    if (c->par_fork) hipEventDestroy(c->par_fork);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->aux) hipStreamDestroy(c->aux);
@@ -443,9 +414,7 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
             drop_graph(c);
             hipGraph_t g = nullptr;
             HCK(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal), "mrf_infer: begin capture");
-            c->npar = mrf_ctx::kPar;   // class launches of a phase become parallel graph branches
             hipError_t e = enqueue_forward(c, sweeps, keep, false, c->aux);
-            c->npar = 0;
             hipError_t e2 = hipStreamEndCapture(c->aux, &g);
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
@@ -498,14 +467,11 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
     // d loss / d ell^(K)_e = d loss / d L_v(e);  d loss / d theta starts at d loss / d L
     HCK(launch_gather_voxel(col, dlogit, ellbar, c->S, s), "mrf_backward: seed");
     HCK(launch_copy(thetabar, dlogit, c->V, s), "mrf_backward: seed");
-    // class launches of a phase run on the side streams (fork/join by events)
-    c->npar = mrf_ctx::kPar;
     hipError_t e = hipSuccess;
     for (int k = K - 1; k >= 0 && e == hipSuccess; --k) {
         e = launch_ray_adjoint(c, ckpt_slot(c, k), ellbar, lambar, gsum, k == K - 1, s);
         if (e == hipSuccess) e = launch_voxel_phase(c, nullptr, lambar, k > 0 ? ellbar : nullptr, thetabar, 2, false, s);
     }
-    c->npar = 0;
     HCK(e, "mrf_backward: sweeps");
     if (dsigma) HCK(launch_sigma_grad(c, dsigma, s), "mrf_backward: sigma gradient");
     if (dprior) HCK(launch_copy(dprior, thetabar, c->V, s), "mrf_backward: copy");

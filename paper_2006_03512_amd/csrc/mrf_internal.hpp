@@ -195,29 +195,11 @@ struct mrf_ctx {
     std::vector<uint64_t> g_key;   // sizes and buffer addresses the captured graph depends on
 
     mrf::Profiler* prof = nullptr;   // non-null while mrf_profile_sweeps records
-
-    // Side streams: while a graph is captured, the independent class launches
-    // of one phase are spread over them (fork/join by events), so the graph
-    // runs them as parallel branches.  npar = 0 launches everything in order.
-    static constexpr int kPar = 4;
-    hipStream_t par[kPar] = {};
-    hipEvent_t par_fork = nullptr;
-    hipEvent_t par_join[kPar] = {};
-    int npar = 0;
 };
 
 namespace mrf {
 
 void set_error(const std::string& msg);
-
-// stream for the k-th independent launch of a phase
-inline hipStream_t class_stream(const mrf_ctx* c, int k, hipStream_t s)
-{
-    return c->npar ? c->par[k % c->npar] : s;
-}
-// make the side streams wait for `s` / make `s` wait for the side streams
-hipError_t fork_streams(mrf_ctx* c, hipStream_t s);
-hipError_t join_streams(mrf_ctx* c, hipStream_t s);
 
 // Records start/stop events around one launch when the context is profiling.
 struct ProfScope {

@@ -319,11 +319,10 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
 
 template <int NW, int IPL>
 static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float* in, float* out, float* total,
-                               int mode, hipStream_t s0)
+                               int mode, hipStream_t s)
 {
     const int64_t n = c->vox_cnt[k];
     if (n <= 0) return;
-    const hipStream_t s = class_stream(c, k, s0);
     ProfScope ps(c, KID_VOX0 + k, s);
     const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
     hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
@@ -334,8 +333,6 @@ static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float
 hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out, float* total,
                               int total_mode, bool /*plain*/, hipStream_t s)
 {
-    hipError_t e;
-    if ((e = fork_streams(c, s)) != hipSuccess) return e;
     launch_voxel_class<1, 1>(c, 0, base, in, out, total, total_mode, s);
     launch_voxel_class<1, 4>(c, 1, base, in, out, total, total_mode, s);
     launch_voxel_class<1, 16>(c, 2, base, in, out, total, total_mode, s);
@@ -343,14 +340,12 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, fl
     launch_voxel_class<16, 16>(c, 4, base, in, out, total, total_mode, s);
     const int kc = kVoxClasses - 1;
     if (c->vox_cnt[kc] > 0) {
-        const hipStream_t sc = class_stream(c, kc, s);
-        ProfScope ps(c, KID_VOX0 + kc, sc);
-        hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, sc,
+        ProfScope ps(c, KID_VOX0 + kc, s);
+        hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, s,
                            (const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p, base,
                            in, out, total, total_mode);
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return join_streams(c, s);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ ray phase
@@ -476,12 +471,11 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
 
 template <int Q>
 static void launch_ray_class(const mrf_ctx* c, int64_t off, int64_t n, const float* lam, float* ell,
-                             hipStream_t s0)
+                             hipStream_t s)
 {
     if (n <= 0) return;
     constexpr int CAP = kRayCap[Q];
     constexpr int G = ray_class_group(Q, false);
-    const hipStream_t s = class_stream(c, Q, s0);
     ProfScope ps(c, KID_RAY0 + Q, s);
     const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p + off;
     if constexpr (ray_class_lds(Q)) {
@@ -512,12 +506,8 @@ hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain
 {
     int64_t off[kRayClasses] = {0}, cnt[kRayClasses];
     if (!plain) {
-        hipError_t e;
         for (int k = 0; k < kRayClasses; ++k) cnt[k] = c->ray_cnt[k];
-        if ((e = fork_streams(c, s)) != hipSuccess) return e;
         ray_classes(c, off, cnt, lam, ell, s);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = join_streams(c, s)) != hipSuccess) return e;
     } else {
         // one launch per frame (per class): the plain per-frame schedule
         const int nf = c->n_frames;
