@@ -165,74 +165,91 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
     }
 }
 
-// Tile-staged reverse pass for tiles of at most G*IPL steps (one block of 16
-// groups per tile): lambda and g, then ell-bar, pass through LDS with
-// coalesced loads; each group writes its column of lambda-bar and g-bar (zeros
-// past its ray), and the block stores lambda-bar and accumulates the g-bar sum
-// coalesced.
-template <int G, int IPL>
-__global__ __launch_bounds__(kTile * G) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
-                                                           const TileDev* __restrict__ tiles,
-                                                           const int32_t* __restrict__ counts,
-                                                           const float* __restrict__ lam, const float* __restrict__ g,
-                                                           const float* __restrict__ ellbar,
-                                                           float* __restrict__ lambar, float* __restrict__ gsum,
-                                                           int first)
+// Tile-staged reverse pass for tiles of at most G*IPL steps: one block of
+// 16 / RPW groups per tile, each group walking RPW rays in turn.  lambda, g and
+// ell-bar pass through LDS with coalesced loads (RPW == 1 stages ell-bar after
+// the groups have read their lambda, which saves a third LDS array); each group
+// writes lambda-bar and g-bar into its rays' columns (zeros past the ray), and
+// the block stores lambda-bar and accumulates the g-bar sum coalesced.
+template <int G, int IPL, int RPW>
+__global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
+                                                                 const TileDev* __restrict__ tiles,
+                                                                 const int32_t* __restrict__ counts,
+                                                                 const float* __restrict__ lam,
+                                                                 const float* __restrict__ g,
+                                                                 const float* __restrict__ ellbar,
+                                                                 float* __restrict__ lambar, float* __restrict__ gsum,
+                                                                 int first)
 {
-    constexpr int NT = kTile * G;
-    __shared__ float sa[kTile * G * IPL];
-    __shared__ float sb[kTile * G * IPL];
+    constexpr int NT = kTile * G / RPW;   // threads
+    constexpr int NG = kTile / RPW;       // groups
+    constexpr int NR = IPL * RPW;         // staging rounds per thread
+    constexpr int CAP = G * IPL;
+    __shared__ float sa[kTile * CAP];
+    __shared__ float sb[kTile * CAP];
+    __shared__ float se[RPW > 1 ? kTile * CAP : 1];
     const int64_t ti = xcd_block(blockIdx.x, gridDim.x);
     if (ti >= ntiles) return;   // whole block
     const TileDev td = tiles[list[ti]];
     const int nf = kTile * td.len;   // 1 <= td.len <= G * IPL by class
-    const int i = (int)threadIdx.x / G;   // this group's ray: lane i of the tile
+    const int grp = (int)threadIdx.x / G;
     const int gl = (int)threadIdx.x % G;
     const int i0 = gl * IPL;
-    const int cb = lds_col(i0, gl, i);
-    const int m = tile_ray_len(td, counts, i);
-    float ve[IPL];   // ell-bar, fetched with lambda and g, staged after them
+    int mr[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) mr[r] = tile_ray_len(td, counts, grp + r * NG);
+    float ve[NR];   // ell-bar
     {
-        float vl[IPL], vg[IPL];
-        tile_fetch<G, IPL>(lam, td.base, nf, vl);
-        tile_fetch<G, IPL>(g, td.base, nf, vg);
-        tile_fetch<G, IPL>(ellbar, td.base, nf, ve);
-        tile_to_lds<G, IPL>(sa, nf, vl);
-        tile_to_lds<G, IPL>(sb, nf, vg);
+        float vl[NR], vg[NR];
+        tile_fetch<NT, NR>(lam, td.base, nf, vl);
+        tile_fetch<NT, NR>(g, td.base, nf, vg);
+        tile_fetch<NT, NR>(ellbar, td.base, nf, ve);
+        tile_to_lds<NT, NR, IPL>(sa, nf, vl);
+        tile_to_lds<NT, NR, IPL>(sb, nf, vg);
+        if (RPW > 1) tile_to_lds<NT, NR, IPL>(se, nf, ve);
     }
     __syncthreads();
-    float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
-#pragma unroll
-    for (int j = 0; j < IPL; ++j)   // column rows are inside the LDS tile even past the ray
-        load_step(sa[cb + kTile * j], sb[cb + kTile * j], i0 + j < m, al[j], be[j], gg[j]);
-    __syncthreads();   // every group has its lambda: reuse sa for ell-bar
-    tile_to_lds<G, IPL>(sa, nf, ve);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        const float v = sa[cb + kTile * j];
-        eb[j] = i0 + j < m ? v : 0.0f;
-    }
     // g-bar sums of earlier sweeps, fetched before the scans so that their
     // latency hides behind them (unconditionally: a branch here would make
     // the compiler wait for the loads at its end; unused on the first sweep)
-    float vs[IPL];
-    tile_fetch<G, IPL>(gsum, td.base, nf, vs);
-    if (__ballot(m > 0)) {   // skip waves whose rays are all empty; empty rays give zeros
-        ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
-    } else {
+    float vs[NR];
+    tile_fetch<NT, NR>(gsum, td.base, nf, vs);
 #pragma unroll
-        for (int j = 0; j < IPL; ++j) lamb[j] = gb[j] = 0.0f;
-    }
+    for (int r = 0; r < RPW; ++r) {
+        const int i = grp + r * NG;   // this group's ray: lane i of the tile
+        const int m = mr[r];
+        const int cb = lds_col(i0, gl, i);
+        float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
 #pragma unroll
-    for (int j = 0; j < IPL; ++j) {   // own column only; zeros past the ray
-        const bool ok = i0 + j < m;
-        sa[cb + kTile * j] = ok ? lamb[j] : 0.0f;
-        sb[cb + kTile * j] = ok ? gb[j] : 0.0f;
+        for (int j = 0; j < IPL; ++j)   // column rows are inside the LDS tile even past the ray
+            load_step(sa[cb + kTile * j], sb[cb + kTile * j], i0 + j < m, al[j], be[j], gg[j]);
+        if (RPW == 1) {
+            __syncthreads();   // every group has its lambda: reuse sa for ell-bar
+            tile_to_lds<NT, NR, IPL>(sa, nf, ve);
+            __syncthreads();
+        }
+        const float* sev = RPW > 1 ? se : sa;
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            const float v = sev[cb + kTile * j];
+            eb[j] = i0 + j < m ? v : 0.0f;
+        }
+        if (__ballot(m > 0)) {   // skip waves whose rays are all empty; empty rays give zeros
+            ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
+        } else {
+#pragma unroll
+            for (int j = 0; j < IPL; ++j) lamb[j] = gb[j] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {   // own column only; zeros past the ray
+            const bool ok = i0 + j < m;
+            sa[cb + kTile * j] = ok ? lamb[j] : 0.0f;
+            sb[cb + kTile * j] = ok ? gb[j] : 0.0f;
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < IPL; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int idx = (int)threadIdx.x + r * NT;
         if (idx < nf) {
             const int at = lds_at<IPL>(idx >> 4, idx & (kTile - 1));
@@ -254,7 +271,8 @@ static void launch_adj_class(const mrf_ctx* c, const float* lam, const float* el
     ProfScope ps(c, KID_ADJ0 + Q, s);
     const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p;
     if constexpr (ray_class_lds(Q)) {
-        hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
+        constexpr int RPW = kAdjRPW[Q];
+        hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G, RPW>), dim3((unsigned)n), dim3(kTile * G / RPW), 0, s, list, n,
                            (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
                            (const float*)c->b_g.p, ellbar, lambar, gsum, first);
     } else {

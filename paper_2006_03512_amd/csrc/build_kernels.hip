@@ -438,59 +438,92 @@ constexpr int RS_T = 256, RS_IPT = 16, RS_TILE = RS_T * RS_IPT;
 
 size_t radix_hist_entries(int64_t n) { return (size_t)256 * (size_t)cdiv(n > 0 ? n : 1, RS_TILE); }
 
+// Lanes of a wave holding digit d (of valid items): 8 ballots.
+__device__ __forceinline__ uint64_t rs_peers(int d, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// Digit counts of one tile of RS_TILE keys (LDS atomics); all loads of the
+// tile are issued first.
 __global__ __launch_bounds__(RS_T) void rs_hist_k(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                   int32_t* __restrict__ hist, int64_t nblocks)
 {
     __shared__ int32_t h[256];
     h[threadIdx.x] = 0;
-    __syncthreads();
     const int64_t start = (int64_t)blockIdx.x * RS_TILE;
-    const int64_t end = start + RS_TILE < n ? start + RS_TILE : n;
-    for (int64_t i = start + threadIdx.x; i < end; i += RS_T) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    uint32_t kr[RS_IPT];
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int64_t i = start + (int64_t)r * RS_T + threadIdx.x;
+        kr[r] = keys[i < n ? i : n - 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r)
+        if (start + (int64_t)r * RS_T + threadIdx.x < n) atomicAdd(&h[(kr[r] >> shift) & 255], 1);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: items of a tile are ranked in index order among equal
-// digits (wave-level match by ballots, waves in order, rounds in order).
+// Stable scatter of one tile of RS_TILE items.  Items are ranked in index order
+// among equal digits (wave ballots, waves in order, rounds in order) into an
+// LDS copy of the tile grouped by digit; the copy is then written out as
+// contiguous runs, one per digit, at the digit's global offset for this tile
+// (coalesced stores in place of scattered words).  offs is the exclusive scan
+// of the (digit, tile) counts in digit-major order, with the total at the end.
 __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict__ keys_in,
                                                      const uint32_t* __restrict__ vals_in, int64_t n,
                                                      int shift, const int64_t* __restrict__ offs,
                                                      int64_t nblocks, uint32_t* __restrict__ keys_out,
                                                      uint32_t* __restrict__ vals_out)
 {
+    __shared__ uint32_t lk[RS_TILE];
+    __shared__ uint32_t lv[RS_TILE];
     __shared__ int64_t boff[256];
+    __shared__ int32_t dstart[256];
     __shared__ int32_t run[256];
     __shared__ int32_t wcnt[RS_T / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    boff[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    const int64_t start = (int64_t)blockIdx.x * RS_TILE;
+    uint32_t kr[RS_IPT], vr[RS_IPT];
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int64_t i = start + (int64_t)r * RS_T + tid;
+        const int64_t ic = i < n ? i : n - 1;
+        kr[r] = keys_in[ic];
+        vr[r] = vals_in ? vals_in[ic] : (uint32_t)i;
+    }
+    const int64_t o0 = offs[(int64_t)tid * nblocks + blockIdx.x];
+    const int64_t cnt = offs[(int64_t)tid * nblocks + blockIdx.x + 1] - o0;
+    boff[tid] = o0;
     run[tid] = 0;
 #pragma unroll
     for (int q = 0; q < RS_T / 64; ++q) wcnt[q][tid] = 0;
-    __syncthreads();
+    int64_t total;
+    dstart[tid] = (int32_t)block_excl_scan_i64(cnt, &total);   // synchronises the block
     const uint64_t below = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-    const int64_t start = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_IPT; ++r) {
-        const int64_t i = start + (int64_t)r * RS_T + tid;
-        const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
+        const bool valid = start + (int64_t)r * RS_T + tid < n;
+        const uint32_t key = kr[r];
         const int d = (key >> shift) & 255;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
+        const uint64_t peers = rs_peers(d, valid);
         const int rank = __popcll(peers & below);
         if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
             int pre = run[d];
             for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-            const int64_t pos = boff[d] + pre + rank;
-            keys_out[pos] = key;
-            vals_out[pos] = vals_in ? vals_in[i] : (uint32_t)i;
+            const int lp = dstart[d] + pre + rank;
+            lk[lp] = key;
+            lv[lp] = vr[r];
         }
         __syncthreads();
         int add = 0;
@@ -501,6 +534,14 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
         }
         run[tid] += add;
         __syncthreads();
+    }
+    const int tn = (int)(n - start < RS_TILE ? n - start : RS_TILE);
+    for (int j = tid; j < tn; j += RS_T) {
+        const uint32_t key = lk[j];
+        const int d = (key >> shift) & 255;
+        const int64_t pos = boff[d] + (j - dstart[d]);
+        keys_out[pos] = key;
+        vals_out[pos] = lv[j];
     }
 }
 

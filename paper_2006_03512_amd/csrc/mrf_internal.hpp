@@ -30,8 +30,14 @@ constexpr int kLdsMaxCap = 512;
 #ifndef MRF_ADJ_GROUPS
 #define MRF_ADJ_GROUPS 16, 16, 16, 32, 32, 64, 64, 64, 64, 64, 64, 64, 64
 #endif
+#ifndef MRF_ADJ_RPW
+#define MRF_ADJ_RPW 1, 1, 1, 1, 1, 2, 2, 1, 1, 1, 1, 1, 1
+#endif
 constexpr int kRayG[kRayClasses] = {MRF_RAY_GROUPS};
 constexpr int kAdjG[kRayClasses] = {MRF_ADJ_GROUPS};
+// rays per lane group in the reverse pass of the LDS classes (1 or 2): with 2,
+// a tile's block has half the threads and every group walks two rays
+constexpr int kAdjRPW[kRayClasses] = {MRF_ADJ_RPW};
 
 constexpr bool ray_class_lds(int q) { return q > 0 && kRayCap[q] <= kLdsMaxCap; }
 // lanes per ray of class q in the ray phase (adj = false) or the reverse pass

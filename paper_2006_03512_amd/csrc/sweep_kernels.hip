@@ -448,10 +448,10 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
     const int m = tile_ray_len(td, counts, i);
     {
         float vl[IPL], vg[IPL];
-        tile_fetch<G, IPL>(lam, td.base, nf, vl);
-        tile_fetch<G, IPL>(g, td.base, nf, vg);
-        tile_to_lds<G, IPL>(sl, nf, vl);
-        tile_to_lds<G, IPL>(sg, nf, vg);
+        tile_fetch<NT, IPL>(lam, td.base, nf, vl);
+        tile_fetch<NT, IPL>(g, td.base, nf, vg);
+        tile_to_lds<NT, IPL, IPL>(sl, nf, vl);
+        tile_to_lds<NT, IPL, IPL>(sg, nf, vg);
     }
     __syncthreads();
     if (__ballot(m > 0)) {   // skip waves whose rays are all empty

@@ -28,27 +28,27 @@ __device__ __forceinline__ int lds_col(int i0, int gl, int i)
     return i0 * kTile + (i ^ (gl & (kTile - 1)));
 }
 
-// A block of 16 G threads moves a tile's nf = 16 len floats (len <= G IPL) in
-// at most IPL rounds: thread t handles idx = t + r 16 G, r < IPL.  Loads go
-// through registers so that every round's load is issued before the first
-// wait; indices past nf are clamped to the tile's last float (len >= 1) and
-// their values dropped.
-template <int G, int IPL>
-__device__ __forceinline__ void tile_fetch(const float* __restrict__ src, int64_t base, int nf, float (&v)[IPL])
+// A block of NT threads moves a tile's nf = 16 len floats (nf <= NT NR) in NR
+// rounds: thread t handles idx = t + r NT.  Loads go through registers so
+// that every round's load is issued before the first wait; indices past nf are
+// clamped to the tile's last float (len >= 1) and their values dropped.
+template <int NT, int NR>
+__device__ __forceinline__ void tile_fetch(const float* __restrict__ src, int64_t base, int nf, float (&v)[NR])
 {
 #pragma unroll
-    for (int r = 0; r < IPL; ++r) {
-        const int idx = min((int)threadIdx.x + r * kTile * G, nf - 1);
+    for (int r = 0; r < NR; ++r) {
+        const int idx = min((int)threadIdx.x + r * NT, nf - 1);
         v[r] = src[base + idx];
     }
 }
 
-template <int G, int IPL>
-__device__ __forceinline__ void tile_to_lds(float* __restrict__ lds, int nf, const float (&v)[IPL])
+// The fetched values into the LDS image of the tile (layout lds_at<IPL>).
+template <int NT, int NR, int IPL>
+__device__ __forceinline__ void tile_to_lds(float* __restrict__ lds, int nf, const float (&v)[NR])
 {
 #pragma unroll
-    for (int r = 0; r < IPL; ++r) {
-        const int idx = (int)threadIdx.x + r * kTile * G;
+    for (int r = 0; r < NR; ++r) {
+        const int idx = (int)threadIdx.x + r * NT;
         if (idx < nf) lds[lds_at<IPL>(idx >> 4, idx & (kTile - 1))] = v[r];
     }
 }
