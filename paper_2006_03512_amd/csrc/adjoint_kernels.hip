@@ -15,8 +15,8 @@
 //
 // Sigma-table gradient: d g_e / d sigma_b = delta_e^2 / sigma_b^3 - 1 / sigma_b,
 // reduced per bin deterministically: fixed-order double sums over runs of
-// equal bins inside 64-edge chunks, then 128-bit fixed-point integer
-// accumulation (order-independent, hence bit-reproducible).
+// equal bins within each lane's 16 consecutive slots, then 128-bit fixed-point
+// integer accumulation (order-independent, hence bit-reproducible).
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -298,8 +298,7 @@ hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar,
 
 // ------------------------------------------------------------ sigma table
 
-constexpr int SG_BLOCKS = 8192;   // blocks of the sigma-table reduction (at most)
-constexpr int SG_U = 4;           // chunks per round
+constexpr int SG_BLOCKS = 4096;   // blocks of the sigma-table reduction (at most)
 
 __device__ __forceinline__ void fx_add(unsigned long long* lo, long long* hi, double v)
 {
@@ -313,8 +312,14 @@ __device__ __forceinline__ void fx_add(unsigned long long* lo, long long* hi, do
     atomicAdd((unsigned long long*)hi, (unsigned long long)(h + carry));
 }
 
+// Every lane sums runs of equal bins over 16 consecutive slots in slot order
+// (double), and adds each run's sum to its bin in LDS as a 128-bit fixed-point
+// integer; each block then adds its 64 bins to the global accumulators.  The
+// partition of slots into lanes is fixed and integer sums do not depend on
+// order, so the result is bit-reproducible.  S is a multiple of 16 (16 slots
+// per tile step), so a lane's 16 slots are three 16-byte vector loads.
 __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gsum, const float* __restrict__ delta,
-                                                    const uint8_t* __restrict__ bin, int64_t E,
+                                                    const uint8_t* __restrict__ bin, int64_t S,
                                                     const float* __restrict__ sigma, unsigned long long* __restrict__ glo,
                                                     long long* __restrict__ ghi)
 {
@@ -329,47 +334,36 @@ __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gs
         inv3[threadIdx.x] = 1.0 / (sg * sg * sg);
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t nchunks = (E + 63) / 64;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    // SG_U consecutive 64-slot chunks per round, their loads issued together
-    for (int64_t c0 = wave * SG_U; c0 < nchunks; c0 += (int64_t)gridDim.x * 4 * SG_U) {
-        int br[SG_U];
-        float dl[SG_U], gs[SG_U];
+    const int64_t nch = S / 16;
+    for (int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < nch;
+         ch += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e0 = ch * 16;
+        float4 gv[4], dv[4];
 #pragma unroll
-        for (int u = 0; u < SG_U; ++u) {
-            const int64_t e = (c0 + u) * 64 + lane;
-            const int64_t ec = e < E ? e : E - 1;
-            br[u] = (int)bin[ec];
-            dl[u] = delta[ec];
-            gs[u] = gsum[ec];
+        for (int q = 0; q < 4; ++q) {
+            gv[q] = *(const float4*)(gsum + e0 + 4 * q);
+            dv[q] = *(const float4*)(delta + e0 + 4 * q);
         }
+        const uint4 bw = *(const uint4*)(bin + e0);
+        const uint32_t bwords[4] = {bw.x, bw.y, bw.z, bw.w};
+        int cur = -1;
+        double acc = 0.0;
 #pragma unroll
-        for (int u = 0; u < SG_U; ++u) {
-            const int64_t e = (c0 + u) * 64 + lane;
-            const bool valid = e < E && br[u] < kBins;   // padding slots carry bin 255
-            const int b = valid ? br[u] : -1;
-            double x = 0.0;
-            if (valid) {
-                const double d = (double)dl[u];
-                x = (double)gs[u] * (d * d * inv3[b] - inv[b]);
+        for (int j = 0; j < 16; ++j) {
+            const int b = (int)((bwords[j >> 2] >> (8 * (j & 3))) & 255u);
+            const float4 g4 = gv[j >> 2], d4 = dv[j >> 2];
+            const float gj = (j & 3) == 0 ? g4.x : (j & 3) == 1 ? g4.y : (j & 3) == 2 ? g4.z : g4.w;
+            const float dj = (j & 3) == 0 ? d4.x : (j & 3) == 1 ? d4.y : (j & 3) == 2 ? d4.z : d4.w;
+            if (b >= kBins) continue;   // padding slots carry bin 255
+            if (b != cur) {
+                if (cur >= 0) fx_add(&slo[cur], &shi[cur], acc);
+                cur = b;
+                acc = 0.0;
             }
-            // segmented inclusive sum over runs of equal bins (fixed tree order)
-            const int bup = __shfl_up(b, 1, 64);
-            int f = (lane == 0 || bup != b) ? 1 : 0;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const double y = __shfl_up(x, d, 64);
-                const int gflag = __shfl_up(f, d, 64);
-                if (lane >= d) {
-                    if (!f) x = y + x;
-                    f |= gflag;
-                }
-            }
-            const int bdn = __shfl_down(b, 1, 64);
-            const bool tail = valid && (lane == 63 || bdn != b || e + 1 >= E);
-            if (tail) fx_add(&slo[b], &shi[b], x);
+            const double d = (double)dj;
+            acc += (double)gj * (d * d * inv3[b] - inv[b]);
         }
+        if (cur >= 0) fx_add(&slo[cur], &shi[cur], acc);
     }
     __syncthreads();
     if (threadIdx.x < kBins) {
@@ -402,7 +396,7 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s)
     hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(64), 0, s, glo, ghi);
     if (c->S > 0) {
         ProfScope ps(c, KID_SIGMA, s);
-        int64_t blocks = (c->S + 256 * SG_U - 1) / (256 * SG_U);
+        int64_t blocks = (c->S / 16 + 255) / 256;
         if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
         hipLaunchKernelGGL(sigma_grad_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_gsum.p,
                            (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p, c->S,
