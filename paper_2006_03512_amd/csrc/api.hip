@@ -109,7 +109,10 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
     const float* prev = nullptr;   // ell of the previous sweep; nullptr = uniform (0)
     for (int k = 0; k < K; ++k) {
         float* lam = keep ? ckpt_slot(c, k) : (float*)c->b_lam.p;
-        if ((e = launch_voxel_phase(c, theta, prev, lam, nullptr, 0, plain, s)) != hipSuccess) return e;
+        // first sweep: every incoming message is 0, so lambda_e = theta_v(e), a gather by slot
+        if ((e = k == 0 ? launch_gather_voxel((const int32_t*)c->b_col.p, theta, lam, c->S, s)
+                        : launch_voxel_phase(c, theta, prev, lam, nullptr, 0, plain, s)) != hipSuccess)
+            return e;
         if ((e = launch_ray_phase(c, lam, ell, plain, s)) != hipSuccess) return e;
         prev = ell;
     }
@@ -523,9 +526,11 @@ extern "C" {
 
 static std::string kid_name(int k)
 {
-    static const char* vox[kVoxClasses] = {"voxel_k<1,1>", "voxel_k<1,4>", "voxel_k<1,16>", "voxel_k<4,16>",
-                                           "voxel_k<16,16>", "voxel_chunked_k"};
-    if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) return vox[k - KID_VOX0];
+    if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
+        const int q = k - KID_VOX0;
+        if (q == kVoxClasses - 1) return "voxel_chunked_k";
+        return "voxel_k<" + std::to_string(kVoxNW[q]) + "," + std::to_string(kVoxCap[q] / (64 * kVoxNW[q])) + ">";
+    }
     auto ray_name = [](const char* direct, const char* lds, int q, bool adj) {
         const int G = ray_class_group(q, adj);
         return std::string(ray_class_lds(q) ? lds : direct) + "<" + std::to_string(G) + "," +

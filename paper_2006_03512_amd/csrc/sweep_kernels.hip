@@ -317,27 +317,31 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
     }
 }
 
-template <int NW, int IPL>
-static void launch_voxel_class(mrf_ctx* c, int k, const float* base, const float* in, float* out, float* total,
-                               int mode, hipStream_t s)
+template <int K>
+static void launch_voxel_class(mrf_ctx* c, const float* base, const float* in, float* out, float* total, int mode,
+                               hipStream_t s)
 {
-    const int64_t n = c->vox_cnt[k];
+    const int64_t n = c->vox_cnt[K];
     if (n <= 0) return;
-    ProfScope ps(c, KID_VOX0 + k, s);
+    constexpr int NW = kVoxNW[K], IPL = kVoxCap[K] / (64 * NW);
+    ProfScope ps(c, KID_VOX0 + K, s);
     const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
     hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
-                       (const VoxDev*)c->b_vox_desc[k].p, n, (const uint32_t*)c->b_vedge.p, base, in, out, total,
+                       (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, out, total,
                        mode);
+}
+
+template <int... K>
+static void voxel_classes(std::integer_sequence<int, K...>, mrf_ctx* c, const float* base, const float* in,
+                          float* out, float* total, int mode, hipStream_t s)
+{
+    (launch_voxel_class<K>(c, base, in, out, total, mode, s), ...);
 }
 
 hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out, float* total,
                               int total_mode, bool /*plain*/, hipStream_t s)
 {
-    launch_voxel_class<1, 1>(c, 0, base, in, out, total, total_mode, s);
-    launch_voxel_class<1, 4>(c, 1, base, in, out, total, total_mode, s);
-    launch_voxel_class<1, 16>(c, 2, base, in, out, total, total_mode, s);
-    launch_voxel_class<4, 16>(c, 3, base, in, out, total, total_mode, s);
-    launch_voxel_class<16, 16>(c, 4, base, in, out, total, total_mode, s);
+    voxel_classes(std::make_integer_sequence<int, kVoxClasses - 1>{}, c, base, in, out, total, total_mode, s);
     const int kc = kVoxClasses - 1;
     if (c->vox_cnt[kc] > 0) {
         ProfScope ps(c, KID_VOX0 + kc, s);

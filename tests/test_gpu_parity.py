@@ -166,6 +166,35 @@ def test_messages_first_sweep(oracle, RayMRF):
     assert np.all(err <= bound), float((err / bound).max())
 
 
+def test_messages_extreme_prior_logodds(oracle, RayMRF):
+    """Priors of +-1e6 log-odds on a seeded third of the voxels (near-certain
+    occupancy or emptiness).  After one sweep (lambda = theta exactly) every
+    ray message matches the oracle: log mu(1) and log mu(0) of such voxels must
+    not lose their small member to rounding.  After three sweeps the marginals
+    still meet the 1e-4 bar (the messages then carry the FP32 rounding of sums
+    of 1e6-sized terms)."""
+    sc = S.make_fd()
+    G = oracle.build_graph(sc)
+    rng = np.random.default_rng(11)
+    th = sc.prior_logit().astype(np.float32).copy()
+    pick = rng.random(th.shape[0]) < 1.0 / 3.0
+    th[pick] = np.where(rng.random(int(pick.sum())) < 0.5, -1.0e6, 1.0e6).astype(np.float32)
+    sig = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
+    m = _gpu(RayMRF, sc, keep_chords=False)
+    ref1 = oracle.infer(G, th.astype(np.float64), sc.sigma_table, 1)
+    m.infer(torch.from_numpy(th).cuda(), sig, 1)
+    ell = m.export_edges()["ell"].cpu().numpy().astype(np.float64)
+    err = np.abs(ell - ref1.ell)
+    nz = np.diff(G.row_ptr) > 0   # as in test_messages_first_sweep: relative, plus the ray's g scale
+    bound = 2e-4 * (1.0 + np.abs(ref1.ell)) + 1e-6 * np.repeat(
+        np.maximum.reduceat(np.abs(ref1.g), G.row_ptr[:-1][nz]), np.diff(G.row_ptr)[nz])
+    assert np.all(err <= bound), float((err / bound).max())
+    ref3 = oracle.infer(G, th.astype(np.float64), sc.sigma_table, 3)
+    m.infer(torch.from_numpy(th).cuda(), sig, 3)
+    p, _ = m.marginals()
+    assert np.abs(p.cpu().numpy() - ref3.p).max() <= TOL_P
+
+
 def test_determinism(RayMRF):
     sc = S.make_c2()
     m = _gpu(RayMRF, sc, keep_chords=False)
