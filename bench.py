@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=float, default=0.25, help="fraction of frame-0 rows the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of timing the candidates after warmup")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="time one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -172,6 +174,13 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done (E = {m.n_edges})")
+    if not args.no_autotune:
+        if args.warmup == 0:
+            step()
+        tun = m.autotune(reps=2)
+        step()   # captures the graph with the chosen shapes
+        torch.cuda.synchronize()
+        log(f"autotuned: lanes {tun['fwd_lanes'][:8]} reverse {tun['adj_lanes'][:8]} x {tun['adj_rays'][:8]}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -257,6 +266,8 @@ def main():
         "forward_updates_per_s": {"batched_graph": E * K / (fwd_graph_ms / 1e3),
                                   "plain_per_frame": E * K / (fwd_plain_ms / 1e3)},
         "kernels": kernels,
+        "tuning": {k: v for k, v in m.tuning().items() if k in ("cap", "fwd_lanes", "adj_lanes", "adj_rays")},
+        "autotuned": not args.no_autotune,
     }
     if backward:
         line["fwd_bwd_edge_sweeps_per_s"] = E * K / ((fwd_graph_ms + bwd_ms) / 1e3)

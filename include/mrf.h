@@ -194,6 +194,40 @@ typedef struct {
 int mrf_profile_sweeps(mrf_ctx* ctx, int32_t reps, int32_t include_backward,
                        mrf_kernel_time_t* out, int32_t max_out, int32_t* n_out, void* stream);
 
+/* Launch shapes of the ray-length classes (the schedule the task calls the
+ * ray-segment length and waves per ray).  Rays are grouped in 4x4-pixel
+ * tiles and tiles in classes by their longest ray (cap[q] steps).  A class
+ * has fwd_candidates shapes for the ray phase (Eqs. pos and neg) and
+ * adj_candidates for the reverse pass; a shape is the lanes per ray (16, 32 or
+ * 64; steps per lane = cap / lanes) and, in the reverse pass, the rays a lane
+ * group walks in turn (1 or 2).  *_sel is the selected candidate, 0 the
+ * built-in default.  MRF_MAX_RAY_CLASSES bounds n_classes. */
+#define MRF_MAX_RAY_CLASSES 32
+typedef struct {
+    int32_t n_classes;
+    int32_t cap[MRF_MAX_RAY_CLASSES];
+    int32_t fwd_candidates[MRF_MAX_RAY_CLASSES], fwd_sel[MRF_MAX_RAY_CLASSES], fwd_lanes[MRF_MAX_RAY_CLASSES];
+    int32_t adj_candidates[MRF_MAX_RAY_CLASSES], adj_sel[MRF_MAX_RAY_CLASSES], adj_lanes[MRF_MAX_RAY_CLASSES];
+    int32_t adj_rays[MRF_MAX_RAY_CLASSES];
+} mrf_tuning_t;
+
+/* Current launch shapes (host struct).  Errors: MRF_EINVAL for NULL. */
+int mrf_get_tuning(const mrf_ctx* ctx, mrf_tuning_t* out);
+
+/* Select launch shapes: fwd_sel / adj_sel hold n_classes candidate indices
+ * (host arrays); NULL leaves that pass unchanged.  Every shape computes the
+ * same messages up to FP32 rounding order.  Errors: MRF_EINVAL for an index
+ * out of range (nothing changed). */
+int mrf_set_tuning(mrf_ctx* ctx, const int32_t* fwd_sel, const int32_t* adj_sel);
+
+/* Autotuner: time every candidate shape of every populated class on the
+ * built graph (one warm-up and reps timed launches per candidate, HIP events
+ * on `stream`) and select the fastest per class and pass.  Needs a preceding
+ * mrf_infer (it reads the last sweep's messages; it writes only buffers that
+ * mrf_backward initialises, so marginals and checkpoints are kept).
+ * Synchronises `stream`.  Errors: MRF_EINVAL (reps < 1), MRF_ESTATE, MRF_EHIP. */
+int mrf_autotune(mrf_ctx* ctx, int32_t reps, void* stream);
+
 void mrf_destroy(mrf_ctx* ctx);
 const char* mrf_strerror(int code);
 const char* mrf_last_error(void);

@@ -17,7 +17,9 @@ MRF_SCHED_PLAIN, MRF_SCHED_GRAPH = 0, 1
 
 SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backward", "mrf_stats",
            "mrf_export_incidence", "mrf_export_edges", "mrf_set_schedule", "mrf_destroy",
-           "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps"]
+           "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps", "mrf_get_tuning", "mrf_set_tuning",
+           "mrf_autotune"]
+MAX_RAY_CLASSES = 32
 
 
 class Intrinsics(C.Structure):
@@ -58,6 +60,14 @@ class KernelTime(C.Structure):
                 ("edges_per_launch", C.c_int64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("n_classes", C.c_int32), ("cap", C.c_int32 * MAX_RAY_CLASSES),
+                ("fwd_candidates", C.c_int32 * MAX_RAY_CLASSES), ("fwd_sel", C.c_int32 * MAX_RAY_CLASSES),
+                ("fwd_lanes", C.c_int32 * MAX_RAY_CLASSES), ("adj_candidates", C.c_int32 * MAX_RAY_CLASSES),
+                ("adj_sel", C.c_int32 * MAX_RAY_CLASSES), ("adj_lanes", C.c_int32 * MAX_RAY_CLASSES),
+                ("adj_rays", C.c_int32 * MAX_RAY_CLASSES)]
+
+
 _lib = None
 
 
@@ -80,6 +90,9 @@ def lib() -> C.CDLL:
         L.mrf_export_edges.argtypes = [P, P, P, P, P, P, P]
         L.mrf_set_schedule.argtypes = [P, I32]
         L.mrf_profile_sweeps.argtypes = [P, I32, I32, C.POINTER(KernelTime), I32, C.POINTER(I32), P]
+        L.mrf_get_tuning.argtypes = [P, C.POINTER(Tuning)]
+        L.mrf_set_tuning.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
+        L.mrf_autotune.argtypes = [P, I32, P]
         L.mrf_destroy.argtypes = [P]
         L.mrf_destroy.restype = None
         L.mrf_strerror.argtypes = [C.c_int]

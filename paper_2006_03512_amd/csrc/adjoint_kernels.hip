@@ -19,6 +19,7 @@
 // integer accumulation (order-independent, hence bit-reproducible).
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <utility>
 
 #include "dev_common.hpp"
@@ -260,39 +261,72 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
     }
 }
 
-template <int Q>
-static void launch_adj_class(const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
+template <int Q, int I>
+static void launch_adj_shape(const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
                              int first, hipStream_t s)
 {
-    const int64_t n = c->ray_cnt[Q];
-    if (n <= 0) return;
-    constexpr int CAP = kRayCap[Q];
-    constexpr int G = ray_class_group(Q, true);
-    ProfScope ps(c, KID_ADJ0 + Q, s);
-    const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p;
-    if constexpr (ray_class_lds(Q)) {
-        constexpr int RPW = kAdjRPW[Q];
-        hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G, RPW>), dim3((unsigned)n), dim3(kTile * G / RPW), 0, s, list, n,
-                           (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
-                           (const float*)c->b_g.p, ellbar, lambar, gsum, first);
-    } else {
-        hipLaunchKernelGGL((ray_adj_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s, list,
-                           n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
-                           (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+    constexpr int G = kAdjShapes[Q][I].g;
+    if constexpr (G != 0) {
+        constexpr int CAP = kRayCap[Q];
+        const int64_t n = c->ray_cnt[Q];
+        const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p;
+        if constexpr (ray_class_lds(Q)) {
+            constexpr int RPW = kAdjShapes[Q][I].rpw;
+            hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G, RPW>), dim3((unsigned)n), dim3(kTile * G / RPW), 0, s,
+                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                               (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+        } else {
+            hipLaunchKernelGGL((ray_adj_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                               (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+        }
     }
+}
+
+template <int Q, int... I>
+static void launch_adj_sel(int sel, const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar,
+                           float* gsum, int first, hipStream_t s, std::integer_sequence<int, I...>)
+{
+    ((sel == I ? launch_adj_shape<Q, I>(c, lam, ellbar, lambar, gsum, first, s) : void()), ...);
+}
+
+template <int Q>
+static void launch_adj_class(const mrf_ctx* c, int sel, const float* lam, const float* ellbar, float* lambar,
+                             float* gsum, int first, hipStream_t s)
+{
+    if (c->ray_cnt[Q] <= 0) return;
+    ProfScope ps(c, KID_ADJ0 + Q, s);
+    launch_adj_sel<Q>(sel, c, lam, ellbar, lambar, gsum, first, s, std::make_integer_sequence<int, kNShapes>{});
 }
 
 template <int... Q>
 static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const float* lam, const float* ellbar,
                         float* lambar, float* gsum, int first, hipStream_t s)
 {
-    (launch_adj_class<Q>(c, lam, ellbar, lambar, gsum, first, s), ...);
+    (launch_adj_class<Q>(c, c->adj_sel[Q], lam, ellbar, lambar, gsum, first, s), ...);
 }
 
 hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
                               bool first, hipStream_t s)
 {
     adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, lam, ellbar, lambar, gsum, first ? 1 : 0, s);
+    return hipGetLastError();
+}
+
+using AdjClassFn = void (*)(const mrf_ctx*, int, const float*, const float*, float*, float*, int, hipStream_t);
+template <int... Q>
+static constexpr std::array<AdjClassFn, kRayClasses> adj_class_fns(std::integer_sequence<int, Q...>)
+{
+    return {&launch_adj_class<Q>...};
+}
+
+hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, const float* ellbar,
+                                  float* lambar, float* gsum, int first, hipStream_t s)
+{
+    static constexpr std::array<AdjClassFn, kRayClasses> fns =
+        adj_class_fns(std::make_integer_sequence<int, kRayClasses>{});
+    if (q < 0 || q >= kRayClasses || sel < 0 || sel >= ray_shape_count(q, true)) return hipErrorInvalidValue;
+    fns[q](c, sel, lam, ellbar, lambar, gsum, first, s);
     return hipGetLastError();
 }
 

@@ -50,7 +50,8 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
                                (uint64_t)c->Vk, (uint64_t)c->S, (uint64_t)c->T};
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->ray_cnt[i]);
     for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->vox_cnt[i]);
-    const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_delta, &c->b_bin, &c->b_g, &c->b_lam, &c->b_ell,
+    for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->fwd_sel[i]);
+    const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_col, &c->b_delta, &c->b_bin, &c->b_g, &c->b_lam, &c->b_ell,
                                  &c->b_vedge, &c->b_vptr, &c->b_theta, &c->b_L, &c->b_sigma, &c->b_ckpt,
                                  &c->b_tiles, &c->b_counts};
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
@@ -524,21 +525,27 @@ int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, flo
 
 extern "C" {
 
-static std::string kid_name(int k)
+static std::string kid_name(const mrf_ctx* c, int k)
 {
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
         const int q = k - KID_VOX0;
         if (q == kVoxClasses - 1) return "voxel_chunked_k";
         return "voxel_k<" + std::to_string(kVoxNW[q]) + "," + std::to_string(kVoxCap[q] / (64 * kVoxNW[q])) + ">";
     }
-    auto ray_name = [](const char* direct, const char* lds, int q, bool adj) {
-        const int G = ray_class_group(q, adj);
-        return std::string(ray_class_lds(q) ? lds : direct) + "<" + std::to_string(G) + "," +
-               std::to_string(kRayCap[q] / G) + ">";
+    auto ray_name = [](const char* direct, const char* lds, int q, RayShape sh, bool adj) {
+        std::string n = std::string(ray_class_lds(q) ? lds : direct) + "<" + std::to_string(sh.g) + "," +
+                        std::to_string(kRayCap[q] / sh.g);
+        if (adj && ray_class_lds(q)) n += "," + std::to_string(sh.rpw);
+        return n + ">";
     };
-    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) return ray_name("ray_k", "ray_lds_k", k - KID_RAY0, false);
-    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses)
-        return ray_name("ray_adj_k", "ray_adj_lds_k", k - KID_ADJ0, true);
+    if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) {
+        const int q = k - KID_RAY0;
+        return ray_name("ray_k", "ray_lds_k", q, kFwdShapes[q][c->fwd_sel[q]], false);
+    }
+    if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses) {
+        const int q = k - KID_ADJ0;
+        return ray_name("ray_adj_k", "ray_adj_lds_k", q, kAdjShapes[q][c->adj_sel[q]], true);
+    }
     if (k == KID_POT) return "potentials_k";
     if (k == KID_SIGMA) return "sigma_grad_k";
     return "?";
@@ -620,7 +627,7 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
         if (n < max_out) {
             mrf_kernel_time_t& o = out[n];
             memset(&o, 0, sizeof(o));
-            strncpy(o.name, kid_name(k).c_str(), sizeof(o.name) - 1);
+            strncpy(o.name, kid_name(c, k).c_str(), sizeof(o.name) - 1);
             o.launches = cnt[k];
             o.total_ms = tot[k];
             kid_bytes(c, k, &o.bytes_per_launch, &o.edges_per_launch);
@@ -628,6 +635,92 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
         ++n;
     }
     *n_out = n < max_out ? n : max_out;
+    return MRF_OK;
+}
+
+
+int mrf_get_tuning(const mrf_ctx* c, mrf_tuning_t* out)
+{
+    if (!c || !out) return fail(MRF_EINVAL, "mrf_get_tuning: null argument");
+    memset(out, 0, sizeof(*out));
+    out->n_classes = kRayClasses;
+    for (int q = 0; q < kRayClasses; ++q) {
+        out->cap[q] = kRayCap[q];
+        out->fwd_candidates[q] = ray_shape_count(q, false);
+        out->fwd_sel[q] = c->fwd_sel[q];
+        out->fwd_lanes[q] = kFwdShapes[q][c->fwd_sel[q]].g;
+        out->adj_candidates[q] = ray_shape_count(q, true);
+        out->adj_sel[q] = c->adj_sel[q];
+        out->adj_lanes[q] = kAdjShapes[q][c->adj_sel[q]].g;
+        out->adj_rays[q] = kAdjShapes[q][c->adj_sel[q]].rpw;
+    }
+    return MRF_OK;
+}
+
+int mrf_set_tuning(mrf_ctx* c, const int32_t* fwd_sel, const int32_t* adj_sel)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_set_tuning: null context");
+    for (int q = 0; q < kRayClasses; ++q) {
+        if (fwd_sel && (fwd_sel[q] < 0 || fwd_sel[q] >= ray_shape_count(q, false)))
+            return fail(MRF_EINVAL, "mrf_set_tuning: ray-phase shape index out of range");
+        if (adj_sel && (adj_sel[q] < 0 || adj_sel[q] >= ray_shape_count(q, true)))
+            return fail(MRF_EINVAL, "mrf_set_tuning: reverse-pass shape index out of range");
+    }
+    for (int q = 0; q < kRayClasses; ++q) {
+        if (fwd_sel) c->fwd_sel[q] = fwd_sel[q];
+        if (adj_sel) c->adj_sel[q] = adj_sel[q];
+    }
+    return MRF_OK;   // a cached forward graph is revalidated by mrf_infer (its key holds the shapes)
+}
+
+int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
+{
+    if (!c || reps < 1) return fail(MRF_EINVAL, "mrf_autotune: bad argument");
+    if (!c->inferred) return fail(MRF_ESTATE, "mrf_autotune: call mrf_infer first");
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_autotune: hipSetDevice");
+    // inputs: the last sweep's messages; outputs go to buffers the reverse pass
+    // initialises before use, so the inference state stays untouched
+    const float* lam = final_lam(c);
+    const float* ell_in = final_ell(c);
+    float* ell_out = (float*)c->b_ellbar.p;
+    float* lambar = (float*)c->b_lambar.p;
+    float* gsum = (float*)c->b_gsum.p;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    HCK(hipEventCreate(&ev[0]), "mrf_autotune: event");
+    hipError_t e = hipEventCreate(&ev[1]);
+    for (int adj = 0; adj < 2 && e == hipSuccess; ++adj) {
+        for (int q = 0; q < kRayClasses && e == hipSuccess; ++q) {
+            const int ns = ray_shape_count(q, adj == 1);
+            if (c->ray_cnt[q] <= 0 || ns < 2) continue;
+            int best = 0;
+            float best_ms = 0.0f;
+            for (int i = 0; i < ns && e == hipSuccess; ++i) {
+                auto run = [&]() {
+                    return adj ? launch_adj_class_shape(c, q, i, lam, ell_in, lambar, gsum, 1, s)
+                               : launch_ray_class_shape(c, q, i, lam, ell_out, s);
+                };
+                e = run();   // warm-up
+                if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
+                if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (e == hipSuccess && (i == 0 || ms < best_ms)) {
+                    best = i;
+                    best_ms = ms;
+                }
+            }
+            if (adj)
+                c->adj_sel[q] = best;
+            else
+                c->fwd_sel[q] = best;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    if (ev[1]) hipEventDestroy(ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "mrf_autotune");
     return MRF_OK;
 }
 

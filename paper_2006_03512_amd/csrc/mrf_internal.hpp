@@ -18,43 +18,63 @@ constexpr int kMaxRayLen = 2048;      // longest ray factor a group can hold
 
 // Ray-length classes by tile length (longest ray of the tile), capacity cap.
 // A ray is held by a group of G lanes (16, 32 or 64), each holding IPL = cap / G
-// consecutive steps.  Class 0 (cap 16) is G = 16 reading the tile directly;
-// classes up to kLdsMaxCap stage the tile through LDS with G from kRayG (ray
-// phase) or kAdjG (reverse pass); longer classes are G = 64, direct.
+// consecutive steps; in the reverse pass a group may walk RPW = 2 rays in turn.
+// Class 0 (cap 16) is G = 16 reading the tile directly; classes up to
+// kLdsMaxCap stage the tile through LDS; longer classes are G = 64, direct.
 constexpr int kRayClasses = 13;
 constexpr int kRayCap[kRayClasses] = {16, 64, 128, 192, 256, 320, 384, 512, 640, 768, 1024, 1536, 2048};
 constexpr int kLdsMaxCap = 512;
-#ifndef MRF_RAY_GROUPS
-#define MRF_RAY_GROUPS 16, 16, 16, 16, 32, 32, 32, 64, 64, 64, 64, 64, 64
-#endif
-#ifndef MRF_ADJ_GROUPS
-#define MRF_ADJ_GROUPS 16, 16, 16, 32, 32, 64, 64, 64, 64, 64, 64, 64, 64
-#endif
-#ifndef MRF_ADJ_RPW
-#define MRF_ADJ_RPW 1, 1, 1, 1, 1, 2, 2, 1, 1, 1, 1, 1, 1
-#endif
-constexpr int kRayG[kRayClasses] = {MRF_RAY_GROUPS};
-constexpr int kAdjG[kRayClasses] = {MRF_ADJ_GROUPS};
-// rays per lane group in the reverse pass of the LDS classes (1 or 2): with 2,
-// a tile's block has half the threads and every group walks two rays
-constexpr int kAdjRPW[kRayClasses] = {MRF_ADJ_RPW};
-
 constexpr bool ray_class_lds(int q) { return q > 0 && kRayCap[q] <= kLdsMaxCap; }
-// lanes per ray of class q in the ray phase (adj = false) or the reverse pass
-constexpr int ray_class_group(int q, bool adj)
+
+// Candidate launch shapes of every class; the first is the default (fastest
+// on the 30-keyframe batch), mrf_autotune times them all on the built graph
+// and keeps the fastest per class.  A zero G ends a list.
+struct RayShape {
+    int g, rpw;
+};
+constexpr int kNShapes = 5;
+constexpr RayShape kFwdShapes[kRayClasses][kNShapes] = {
+    {{16, 1}},
+    {{16, 1}, {32, 1}, {64, 1}},
+    {{16, 1}, {32, 1}, {64, 1}},
+    {{16, 1}, {32, 1}, {64, 1}},
+    {{32, 1}, {16, 1}, {64, 1}},
+    {{32, 1}, {64, 1}, {16, 1}},
+    {{32, 1}, {64, 1}},
+    {{64, 1}, {32, 1}},
+    {{64, 1}}, {{64, 1}}, {{64, 1}}, {{64, 1}}, {{64, 1}},
+};
+constexpr RayShape kAdjShapes[kRayClasses][kNShapes] = {
+    {{16, 1}},
+    {{16, 1}, {32, 1}, {64, 1}},
+    {{16, 1}, {32, 1}, {64, 1}, {64, 2}},
+    {{32, 1}, {64, 1}, {16, 1}, {64, 2}},
+    {{32, 1}, {64, 1}, {64, 2}, {32, 2}},
+    {{64, 2}, {64, 1}, {32, 1}, {32, 2}},
+    {{64, 2}, {64, 1}, {32, 1}},
+    {{64, 1}, {64, 2}},
+    {{64, 1}}, {{64, 1}}, {{64, 1}}, {{64, 1}}, {{64, 1}},
+};
+constexpr int ray_shape_count(int q, bool adj)
 {
-    return q == 0 ? 16 : (ray_class_lds(q) ? (adj ? kAdjG[q] : kRayG[q]) : 64);
+    int n = 0;
+    while (n < kNShapes && (adj ? kAdjShapes[q][n].g : kFwdShapes[q][n].g) != 0) ++n;
+    return n;
 }
-constexpr bool ray_groups_valid()
+constexpr bool ray_shapes_valid()
 {
     for (int q = 0; q < kRayClasses; ++q)
-        for (int a = 0; a < 2; ++a) {
-            const int G = ray_class_group(q, a == 1);
-            if ((G != 16 && G != 32 && G != 64) || kRayCap[q] % G != 0) return false;
-        }
+        for (int a = 0; a < 2; ++a)
+            for (int i = 0; i < ray_shape_count(q, a == 1); ++i) {
+                const RayShape sh = a ? kAdjShapes[q][i] : kFwdShapes[q][i];
+                if ((sh.g != 16 && sh.g != 32 && sh.g != 64) || kRayCap[q] % sh.g != 0) return false;
+                if (sh.rpw != 1 && !(a == 1 && sh.rpw == 2 && ray_class_lds(q))) return false;
+                if (!ray_class_lds(q) && !(sh.g == 64 || kRayCap[q] == sh.g)) return false;   // direct kernels
+            }
     return true;
 }
-static_assert(ray_groups_valid(), "ray class groups must be 16, 32 or 64 lanes dividing the class capacity");
+static_assert(ray_shapes_valid(), "ray shapes: 16, 32 or 64 lanes dividing the capacity; 2 rays per group only "
+                                  "in reverse LDS classes; direct classes hold a ray in one group");
 
 // Edges are stored in tiles of 4x4 pixels, step-major: slot of (ray lane i,
 // step k) = tile_base + 16 k + i.  Rays of one camera reach a voxel after the
@@ -216,6 +236,10 @@ struct mrf_ctx {
     std::vector<uint64_t> g_key;   // sizes and buffer addresses the captured graph depends on
 
     mrf::Profiler* prof = nullptr;   // non-null while mrf_profile_sweeps records
+
+    // selected launch shape (index into kFwdShapes / kAdjShapes) of every ray class
+    int fwd_sel[mrf::kRayClasses] = {0};
+    int adj_sel[mrf::kRayClasses] = {0};
 };
 
 namespace mrf {
@@ -274,6 +298,10 @@ hipError_t launch_gather_voxel(const int32_t* col, const float* vox, float* edge
 hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out,
                               float* total, int total_mode, bool plain, hipStream_t s);
 hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain, hipStream_t s);
+// one class of the ray phase / reverse pass with launch shape `sel` (autotuner)
+hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, float* ell, hipStream_t s);
+hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, const float* ellbar,
+                                  float* lambar, float* gsum, int first, hipStream_t s);
 hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
 
 // adjoint_kernels.hip

@@ -20,6 +20,7 @@
 // R_i = S_i - P_i instead of S and P (see ray_body).
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <utility>
 
 #include "dev_common.hpp"
@@ -473,37 +474,69 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
     }
 }
 
+template <int Q, int I>
+static void launch_ray_shape(const mrf_ctx* c, int64_t off, int64_t n, const float* lam, float* ell, hipStream_t s)
+{
+    constexpr int G = kFwdShapes[Q][I].g;
+    if constexpr (G != 0) {
+        constexpr int CAP = kRayCap[Q];
+        const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p + off;
+        if constexpr (ray_class_lds(Q)) {
+            hipLaunchKernelGGL((ray_lds_k<G, CAP / G>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
+                               (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                               (const float*)c->b_g.p, ell);
+        } else {
+            hipLaunchKernelGGL((ray_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s, list,
+                               n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
+                               (const float*)c->b_g.p, ell);
+        }
+    }
+}
+
+template <int Q, int... I>
+static void launch_ray_sel(int sel, const mrf_ctx* c, int64_t off, int64_t n, const float* lam, float* ell,
+                           hipStream_t s, std::integer_sequence<int, I...>)
+{
+    ((sel == I ? launch_ray_shape<Q, I>(c, off, n, lam, ell, s) : void()), ...);
+}
+
+// class Q of the ray phase with launch shape sel, over n tiles of its list from off
 template <int Q>
-static void launch_ray_class(const mrf_ctx* c, int64_t off, int64_t n, const float* lam, float* ell,
+static void launch_ray_class(const mrf_ctx* c, int sel, int64_t off, int64_t n, const float* lam, float* ell,
                              hipStream_t s)
 {
     if (n <= 0) return;
-    constexpr int CAP = kRayCap[Q];
-    constexpr int G = ray_class_group(Q, false);
     ProfScope ps(c, KID_RAY0 + Q, s);
-    const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p + off;
-    if constexpr (ray_class_lds(Q)) {
-        hipLaunchKernelGGL((ray_lds_k<G, CAP / G>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
-                           (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
-                           (const float*)c->b_g.p, ell);
-    } else {
-        hipLaunchKernelGGL((ray_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s, list, n,
-                           (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
-                           (const float*)c->b_g.p, ell);
-    }
+    launch_ray_sel<Q>(sel, c, off, n, lam, ell, s, std::make_integer_sequence<int, kNShapes>{});
 }
 
 template <int... Q>
 static void ray_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const int64_t* off, const int64_t* cnt,
                         const float* lam, float* ell, hipStream_t s)
 {
-    (launch_ray_class<Q>(c, off[Q], cnt[Q], lam, ell, s), ...);
+    (launch_ray_class<Q>(c, c->fwd_sel[Q], off[Q], cnt[Q], lam, ell, s), ...);
 }
 
 static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt, const float* lam, float* ell,
                         hipStream_t s)
 {
     ray_classes(std::make_integer_sequence<int, kRayClasses>{}, c, off, cnt, lam, ell, s);
+}
+
+using RayClassFn = void (*)(const mrf_ctx*, int, int64_t, int64_t, const float*, float*, hipStream_t);
+template <int... Q>
+static constexpr std::array<RayClassFn, kRayClasses> ray_class_fns(std::integer_sequence<int, Q...>)
+{
+    return {&launch_ray_class<Q>...};
+}
+
+hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, float* ell, hipStream_t s)
+{
+    static constexpr std::array<RayClassFn, kRayClasses> fns =
+        ray_class_fns(std::make_integer_sequence<int, kRayClasses>{});
+    if (q < 0 || q >= kRayClasses || sel < 0 || sel >= ray_shape_count(q, false)) return hipErrorInvalidValue;
+    fns[q](c, sel, 0, c->ray_cnt[q], lam, ell, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain, hipStream_t s)

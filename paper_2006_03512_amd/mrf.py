@@ -209,6 +209,30 @@ class RayMRF:
         return out
 
 
+    # ------------------------------------------------------------------
+    def tuning(self) -> dict:
+        """Launch shapes of the ray-length classes (see mrf_get_tuning)."""
+        t = _lib.Tuning()
+        check(self._L.mrf_get_tuning(self._h, C.byref(t)), "mrf_get_tuning")
+        n = t.n_classes
+        return {k: list(getattr(t, k))[:n] for k in ("cap", "fwd_candidates", "fwd_sel", "fwd_lanes",
+                                                     "adj_candidates", "adj_sel", "adj_lanes", "adj_rays")}
+
+    def set_tuning(self, fwd_sel=None, adj_sel=None):
+        """Select a candidate launch shape per class (lists of indices; None keeps)."""
+        n = _lib.MAX_RAY_CLASSES
+
+        def arr(v):
+            return None if v is None else (C.c_int32 * n)(*[int(x) for x in v])
+        check(self._L.mrf_set_tuning(self._h, arr(fwd_sel), arr(adj_sel)), "mrf_set_tuning")
+
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        """Time every candidate shape on the built graph and keep the fastest
+        per class (needs a preceding infer); returns the resulting tuning."""
+        check(self._L.mrf_autotune(self._h, int(reps), stream_handle(stream)), "mrf_autotune")
+        return self.tuning()
+
+
 class MRFInfer(torch.autograd.Function):
     """logit = MRFInfer.apply(mrf, prior_logit, sigma_table, sweeps)
 

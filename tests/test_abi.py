@@ -40,6 +40,9 @@ def test_null_arguments_are_rejected():
     st = _lib.Stats()
     assert L.mrf_stats(None, C.byref(st)) == _lib.MRF_EINVAL
     assert L.mrf_set_schedule(None, 0) == _lib.MRF_EINVAL
+    assert L.mrf_get_tuning(None, None) == _lib.MRF_EINVAL
+    assert L.mrf_set_tuning(None, None, None) == _lib.MRF_EINVAL
+    assert L.mrf_autotune(None, 3, None) == _lib.MRF_EINVAL
     L.mrf_destroy(None)
     assert L.mrf_strerror(_lib.MRF_ESTATE) == b"call out of order"
     assert b"NULL" in L.mrf_last_error() or len(L.mrf_last_error()) > 0
@@ -53,3 +56,5 @@ def test_struct_layouts_match_header():
     assert C.sizeof(_lib.SceneC) == 8 + 16 + 40 + 48
     assert C.sizeof(_lib.BuildParams) == 7 * 8 + 8
     assert _lib.Stats.fwd_bytes_per_sweep.offset == 8 * (8 + 16 + 24)
+    assert C.sizeof(_lib.Tuning) == 4 * (1 + 8 * _lib.MAX_RAY_CLASSES)
+    assert _lib.Tuning.adj_rays.offset == 4 * (1 + 7 * _lib.MAX_RAY_CLASSES)
