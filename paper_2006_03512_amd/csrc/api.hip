@@ -530,6 +530,7 @@ static std::string kid_name(const mrf_ctx* c, int k)
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
         const int q = k - KID_VOX0;
         if (q == kVoxClasses - 1) return "voxel_chunked_k";
+        if (kVoxNW[q] == 0) return "voxel_small_k<" + std::to_string(kVoxCap[q]) + ">";
         return "voxel_k<" + std::to_string(kVoxNW[q]) + "," + std::to_string(kVoxCap[q] / (64 * kVoxNW[q])) + ">";
     }
     auto ray_name = [](const char* direct, const char* lds, int q, RayShape sh, bool adj) {

@@ -87,22 +87,30 @@ constexpr int kTile = kTileW * kTileW;
 // capacity / (64 NW)); each wave owns 64*IPL consecutive edges of the voxel.
 // Above the last class a 1024-thread block walks 256-edge chunks twice.
 #ifndef MRF_VOX_CAPS
-#define MRF_VOX_CAPS 64, 256, 1024, 4096, 16384
-#define MRF_VOX_NW 1, 1, 1, 4, 16
+#define MRF_VOX_CAPS 16, 32, 64, 256, 1024, 4096, 16384
+#define MRF_VOX_NW 0, 0, 1, 1, 1, 4, 16
 #endif
-constexpr int kVoxCap[] = {MRF_VOX_CAPS};   // degree capacity of each single-pass class
-constexpr int kVoxNW[] = {MRF_VOX_NW};      // waves per voxel of each single-pass class
+// Degree capacity of each single-pass class and its waves per voxel; NW = 0
+// packs 64 / cap voxels into a wave (cap = 16 or 32 lanes per voxel, one edge
+// per lane).
+constexpr int kVoxCap[] = {MRF_VOX_CAPS};
+constexpr int kVoxNW[] = {MRF_VOX_NW};
 constexpr int kVoxClasses = (int)(sizeof(kVoxCap) / sizeof(int)) + 1;   // + the chunked class
 static_assert(sizeof(kVoxNW) == sizeof(kVoxCap), "one wave count per voxel class");
 constexpr bool vox_classes_valid()
 {
     for (int k = 0; k + 1 < kVoxClasses; ++k) {
-        if (kVoxCap[k] % (64 * kVoxNW[k]) != 0 || kVoxCap[k] / (64 * kVoxNW[k]) > 32 || kVoxNW[k] > 16) return false;
+        if (kVoxNW[k] == 0) {
+            if (kVoxCap[k] != 16 && kVoxCap[k] != 32) return false;
+        } else if (kVoxCap[k] % (64 * kVoxNW[k]) != 0 || kVoxCap[k] / (64 * kVoxNW[k]) > 32 || kVoxNW[k] > 16) {
+            return false;
+        }
         if (k > 0 && kVoxCap[k] <= kVoxCap[k - 1]) return false;
     }
     return true;
 }
-static_assert(vox_classes_valid(), "voxel classes: increasing capacities of 64 NW IPL edges, IPL <= 32, NW <= 16");
+static_assert(vox_classes_valid(), "voxel classes: increasing capacities; 16 or 32 lanes per packed voxel, or "
+                                   "64 NW IPL edges with IPL <= 32, NW <= 16");
 constexpr int kVoxChunk = 256;
 constexpr int kVoxMaxChunks = 4096;   // degree limit 1048576
 

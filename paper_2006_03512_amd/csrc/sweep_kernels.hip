@@ -263,6 +263,45 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
     }
 }
 
+// Voxels of at most G edges (G = 16 or 32), 64 / G per wave and 256 / G per
+// block: lane l of a group holds edge l of its voxel, and the exclusive prefix
+// and suffix come from group scans.  Groups past the list take no edges.
+template <int G>
+__global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ vd, int64_t n,
+                                                     const uint32_t* __restrict__ vedge,
+                                                     const float* __restrict__ base, const float* __restrict__ in,
+                                                     float* __restrict__ out, float* __restrict__ total,
+                                                     int total_mode)
+{
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb * (256 / G) >= n) return;   // whole block
+    const int64_t vi = lb * (256 / G) + (int)threadIdx.x / G;
+    const int l = (int)threadIdx.x % G;
+    VoxDev d{0, 0, 0};
+    if (vi < n) d = vd[vi];
+    const int m = d.m;
+    uint32_t e = 0;
+    float x = 0.0f;
+    if (m > 0) {
+        e = vedge[d.start + min(l, m - 1)];
+        if (in) {
+            const float y = in[e];
+            x = l < m ? y : 0.0f;
+        }
+    }
+    const float b0 = (m > 0 && base) ? base[d.v] : 0.0f;
+    const float pre = dexcl<G>(dscan<G, OpAdd>(x), 0.0f);
+    const float sinc = drscan<G, OpAdd>(x);   // at group lane 0: the voxel's sum
+    const float suf = drexcl<G>(sinc, 0.0f);
+    if (out && l < m) out[e] = (b0 + pre) + suf;
+    if (total_mode && l == 0 && m > 0) {
+        if (total_mode == 1)
+            total[d.v] = b0 + sinc;
+        else
+            total[d.v] += sinc;
+    }
+}
+
 // One 1024-thread block per voxel of degree above the largest single-pass
 // class: chunk sums into LDS, exclusive prefix / suffix of the chunk sums by
 // wave 0 in fixed order, then every wave revisits its chunks with both carries.
@@ -324,12 +363,20 @@ static void launch_voxel_class(mrf_ctx* c, const float* base, const float* in, f
 {
     const int64_t n = c->vox_cnt[K];
     if (n <= 0) return;
-    constexpr int NW = kVoxNW[K], IPL = kVoxCap[K] / (64 * NW);
     ProfScope ps(c, KID_VOX0 + K, s);
-    const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
-    hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
-                       (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, out, total,
-                       mode);
+    constexpr int NW = kVoxNW[K];
+    if constexpr (NW == 0) {
+        constexpr int G = kVoxCap[K];
+        hipLaunchKernelGGL((voxel_small_k<G>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
+                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, out,
+                           total, mode);
+    } else {
+        constexpr int IPL = kVoxCap[K] / (64 * NW);
+        const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
+        hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
+                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, out,
+                           total, mode);
+    }
 }
 
 template <int... K>
