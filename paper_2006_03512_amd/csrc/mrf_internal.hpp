@@ -87,8 +87,8 @@ constexpr int kTile = kTileW * kTileW;
 // capacity / (64 NW)); each wave owns 64*IPL consecutive edges of the voxel.
 // Above the last class a 1024-thread block walks 256-edge chunks twice.
 #ifndef MRF_VOX_CAPS
-#define MRF_VOX_CAPS 16, 32, 64, 256, 1024, 4096, 16384
-#define MRF_VOX_NW 0, 0, 1, 1, 1, 4, 16
+#define MRF_VOX_CAPS 16, 32, 64, 256, 1024, 4096, 16384, 32768
+#define MRF_VOX_NW 0, 0, 1, 1, 1, 4, 16, 16
 #endif
 // Degree capacity of each single-pass class and its waves per voxel; NW = 0
 // packs 64 / cap voxels into a wave (cap = 16 or 32 lanes per voxel, one edge
