@@ -384,8 +384,10 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     st.n_touched_voxels = 0;
     for (int k = 0; k < kVoxClasses; ++k) st.n_touched_voxels += c->vox_cnt[k];
     // voxel phase: vedge 4 + gather ell 4 + scatter lam 4; ray phase: lam 4 + g 4 + ell 4;
-    // per touched voxel: key 4 + id 4 + vptr 16 + theta 4; per kept ray: id 4 + row_ptr 16
-    st.fwd_bytes_per_sweep = 24.0 * (double)E + 28.0 * (double)st.n_touched_voxels + 20.0 * (double)st.n_kept_rays;
+    // per touched voxel: descriptor 16 + theta 4; per kept ray: count 4; per tile: list 4 +
+    // descriptor 32
+    st.fwd_bytes_per_sweep =
+        24.0 * (double)E + 20.0 * (double)st.n_touched_voxels + 4.0 * (double)st.n_kept_rays + 36.0 * (double)c->T;
     st.sweeps_done = 0;
     st.have_checkpoints = 0;
     c->built = 1;
@@ -560,9 +562,9 @@ static void kid_bytes(const mrf_ctx* c, int k, double* bytes, int64_t* edges)
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
         const int q = k - KID_VOX0;
         // per edge: vedge 4 + gathered ell 4 + scattered lam 4;
-        // per voxel: key 4 + linear id 4 + vptr 16 + theta 4
+        // per voxel: descriptor 16 + theta 4
         *edges = c->vox_cls_edges[q];
-        *bytes = 12.0 * (double)*edges + 28.0 * (double)c->vox_cnt[q];
+        *bytes = 12.0 * (double)*edges + 20.0 * (double)c->vox_cnt[q];
     } else if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) {
         const int q = k - KID_RAY0;
         // per edge: lam 4 + g 4 + ell 4; per ray: count 4; per tile: descriptor 32

@@ -8,8 +8,8 @@
 // log 0 inside the message kernels: a finite -2^100 instead of -inf.  For every
 // genuine log-domain value x (|x| far below 2^76; log-odds of 1e9 are already
 // extreme) x + MRF_NINF rounds to MRF_NINF and 2^(MRF_NINF - x) is 0, so LSE
-// needs no special case for log 0.  The one visible difference: a ray of a
-// single voxel sends 2^100 ln 2 where the exact message is +inf.
+// needs no special case for log 0 and every message equals its -inf form (rays
+// have at least two voxels; a one-voxel ray would send 2^100 ln 2, not +inf).
 #define MRF_NINF (-0x1p100f)
 
 namespace mrf {
