@@ -118,14 +118,16 @@ int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
 
 /* Run `sweeps` flooding sweeps of loopy sum-product BP (Sec. III-B/C, IV-A)
  * from uniform ray messages.  One sweep sends every voxel->ray message
- * (Eq. node_to_factor: the prior times every other ray's message) and then
+ * (Eq. node_to_factor: the prior times every other ray's message, formed as
+ * the voxel's total log-odds less the receiving ray's own message) and then
  * every ray->voxel message (Eqs. pos and neg, computed in the log domain
  * with prefix products of mu(o=0) and the division-free suffix form of
  * Eq. neg).  prior_logit: V floats, log(gamma_v / (1 - gamma_v)) per voxel
  * (copied).  sigma_table: 64 floats > 0, the learnt depth-indexed Gaussian
- * sigma of Eq. noise (copied).  keep_checkpoints != 0 stores every sweep's
- * voxel->ray messages (sweeps * E floats, the input of each ray phase) for
- * mrf_backward.  Errors: MRF_ESTATE
+ * sigma of Eq. noise (copied).  keep_checkpoints != 0 stores, for
+ * mrf_backward, the ray->voxel messages of sweeps 1..K-1 ((sweeps - 1) * E
+ * floats) and the voxel totals of sweeps 2..K ((sweeps - 1) * V floats),
+ * which together give every sweep's voxel->ray messages.  Errors: MRF_ESTATE
  * before mrf_build, MRF_EINVAL for sweeps < 1, MRF_ENOMEM. */
 int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
               int32_t sweeps, int32_t keep_checkpoints, void* stream);

@@ -134,11 +134,15 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
         lamb[j] = -ex2(be[j]) * lab[j] + ex2(al[j]) * lbb[j];
 }
 
+// Inputs of both reverse-pass kernels per edge: lambda_e = lam.tot[col_e] -
+// lam.own_e (the forward messages of the sweep) and d/d ell_e = eb.tot[col_e] -
+// eb.own_e (the later sweep's d/d lambda summed over the voxel, less the
+// edge's own: the adjoint of the forward's total-minus-own).
 template <int G, int IPL>
 __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                  const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
-                                                 const float* __restrict__ lam, const float* __restrict__ g,
-                                                 const float* __restrict__ ellbar, float* __restrict__ lambar,
+                                                 const int32_t* __restrict__ col, ExclDev lam,
+                                                 const float* __restrict__ g, ExclDev eb, float* __restrict__ lambar,
                                                  float* __restrict__ gsum, int first)
 {
     static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
@@ -146,15 +150,30 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
     int m;
     if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
     const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
-    float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
+    int32_t cv[IPL];
+    float lo[IPL], eo[IPL], gv[IPL], lt[IPL], et[IPL];
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {   // indices clamped to the ray (m >= 1): loads issued before any wait
+        const int64_t at = s + kTile * (int64_t)min(i0 + j, m - 1);
+        cv[j] = col[at];
+        lo[j] = lam.own[at];
+        eo[j] = eb.own[at];
+        gv[j] = g[at];
+    }
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
-        const int i = i0 + j;
-        const bool ok = i < m;
-        load_step(ok ? lam[s + kTile * i] : 0.0f, ok ? g[s + kTile * i] : 0.0f, ok, al[j], be[j], gg[j]);
-        eb[j] = ok ? ellbar[s + kTile * i] : 0.0f;
+        const int cc = max(cv[j], 0);
+        lt[j] = lam.tot[cc];
+        et[j] = eb.tot[cc];
     }
-    ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
+    float al[IPL], be[IPL], gg[IPL], ebar[IPL], lamb[IPL], gb[IPL];
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+        const bool ok = i0 + j < m;
+        load_step(excl_value(cv[j], lt[j], lo[j], lam.has_own), gv[j], ok, al[j], be[j], gg[j]);
+        ebar[j] = ok ? excl_value(cv[j], et[j], eo[j], eb.has_own) : 0.0f;
+    }
+    ray_adj_body<G, IPL>(al, be, gg, ebar, m, i0, lamb, gb);
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int i = i0 + j;
@@ -167,18 +186,19 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
 }
 
 // Tile-staged reverse pass for tiles of at most G*IPL steps: one block of
-// 16 / RPW groups per tile, each group walking RPW rays in turn.  lambda, g and
-// ell-bar pass through LDS with coalesced loads (RPW == 1 stages ell-bar after
-// the groups have read their lambda, which saves a third LDS array); each group
-// writes lambda-bar and g-bar into its rays' columns (zeros past the ray), and
-// the block stores lambda-bar and accumulates the g-bar sum coalesced.
+// 16 / RPW groups per tile, each group walking RPW rays in turn.  The block
+// reads col, the two own terms and g with coalesced loads, gathers both voxel
+// totals, and stages lambda, g and ell-bar through LDS (RPW == 1 stages
+// ell-bar after the groups have read their lambda, which saves a third LDS
+// array); each group writes lambda-bar and g-bar into its rays' columns (zeros
+// past the ray), and the block stores lambda-bar and accumulates the g-bar sum
+// coalesced.
 template <int G, int IPL, int RPW>
 __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                                  const TileDev* __restrict__ tiles,
                                                                  const int32_t* __restrict__ counts,
-                                                                 const float* __restrict__ lam,
-                                                                 const float* __restrict__ g,
-                                                                 const float* __restrict__ ellbar,
+                                                                 const int32_t* __restrict__ col, ExclDev lam,
+                                                                 const float* __restrict__ g, ExclDev eb,
                                                                  float* __restrict__ lambar, float* __restrict__ gsum,
                                                                  int first)
 {
@@ -201,11 +221,24 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
     for (int r = 0; r < RPW; ++r) mr[r] = tile_ray_len(td, counts, grp + r * NG);
     float ve[NR];   // ell-bar
     {
-        float vl[NR], vg[NR];
-        tile_fetch<NT, NR>(lam, td.base, nf, vl);
+        int32_t vc[NR];
+        float vo[NR], vb[NR], vg[NR], vt[NR];
+        tile_fetch_i<NT, NR>(col, td.base, nf, vc);
+        tile_fetch<NT, NR>(lam.own, td.base, nf, vo);
+        tile_fetch<NT, NR>(eb.own, td.base, nf, vb);
         tile_fetch<NT, NR>(g, td.base, nf, vg);
-        tile_fetch<NT, NR>(ellbar, td.base, nf, ve);
-        tile_to_lds<NT, NR, IPL>(sa, nf, vl);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int cc = max(vc[r], 0);
+            vt[r] = lam.tot[cc];
+            ve[r] = eb.tot[cc];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            vt[r] = excl_value(vc[r], vt[r], vo[r], lam.has_own);
+            ve[r] = excl_value(vc[r], ve[r], vb[r], eb.has_own);
+        }
+        tile_to_lds<NT, NR, IPL>(sa, nf, vt);
         tile_to_lds<NT, NR, IPL>(sb, nf, vg);
         if (RPW > 1) tile_to_lds<NT, NR, IPL>(se, nf, ve);
     }
@@ -220,7 +253,7 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
         const int i = grp + r * NG;   // this group's ray: lane i of the tile
         const int m = mr[r];
         const int cb = lds_col(i0, gl, i);
-        float al[IPL], be[IPL], gg[IPL], eb[IPL], lamb[IPL], gb[IPL];
+        float al[IPL], be[IPL], gg[IPL], ebar[IPL], lamb[IPL], gb[IPL];
 #pragma unroll
         for (int j = 0; j < IPL; ++j)   // column rows are inside the LDS tile even past the ray
             load_step(sa[cb + kTile * j], sb[cb + kTile * j], i0 + j < m, al[j], be[j], gg[j]);
@@ -233,10 +266,10 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
 #pragma unroll
         for (int j = 0; j < IPL; ++j) {
             const float v = sev[cb + kTile * j];
-            eb[j] = i0 + j < m ? v : 0.0f;
+            ebar[j] = i0 + j < m ? v : 0.0f;
         }
         if (__ballot(m > 0)) {   // skip waves whose rays are all empty; empty rays give zeros
-            ray_adj_body<G, IPL>(al, be, gg, eb, m, i0, lamb, gb);
+            ray_adj_body<G, IPL>(al, be, gg, ebar, m, i0, lamb, gb);
         } else {
 #pragma unroll
             for (int j = 0; j < IPL; ++j) lamb[j] = gb[j] = 0.0f;
@@ -262,8 +295,8 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
 }
 
 template <int Q, int I>
-static void launch_adj_shape(const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
-                             int first, hipStream_t s)
+static void launch_adj_shape(const mrf_ctx* c, ExclDev lam, ExclDev eb, float* lambar, float* gsum, int first,
+                             hipStream_t s)
 {
     constexpr int G = kAdjShapes[Q][I].g;
     if constexpr (G != 0) {
@@ -273,60 +306,61 @@ static void launch_adj_shape(const mrf_ctx* c, const float* lam, const float* el
         if constexpr (ray_class_lds(Q)) {
             constexpr int RPW = kAdjShapes[Q][I].rpw;
             hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G, RPW>), dim3((unsigned)n), dim3(kTile * G / RPW), 0, s,
-                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
-                               (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
+                               (const int32_t*)c->b_col.p, lam, (const float*)c->b_g.p, eb, lambar, gsum, first);
         } else {
             hipLaunchKernelGGL((ray_adj_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
-                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p, lam,
-                               (const float*)c->b_g.p, ellbar, lambar, gsum, first);
+                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
+                               (const int32_t*)c->b_col.p, lam, (const float*)c->b_g.p, eb, lambar, gsum, first);
         }
     }
 }
 
 template <int Q, int... I>
-static void launch_adj_sel(int sel, const mrf_ctx* c, const float* lam, const float* ellbar, float* lambar,
-                           float* gsum, int first, hipStream_t s, std::integer_sequence<int, I...>)
+static void launch_adj_sel(int sel, const mrf_ctx* c, ExclDev lam, ExclDev eb, float* lambar, float* gsum, int first,
+                           hipStream_t s, std::integer_sequence<int, I...>)
 {
-    ((sel == I ? launch_adj_shape<Q, I>(c, lam, ellbar, lambar, gsum, first, s) : void()), ...);
+    ((sel == I ? launch_adj_shape<Q, I>(c, lam, eb, lambar, gsum, first, s) : void()), ...);
 }
 
 template <int Q>
-static void launch_adj_class(const mrf_ctx* c, int sel, const float* lam, const float* ellbar, float* lambar,
-                             float* gsum, int first, hipStream_t s)
+static void launch_adj_class(const mrf_ctx* c, int sel, ExclDev lam, ExclDev eb, float* lambar, float* gsum,
+                             int first, hipStream_t s)
 {
     if (c->ray_cnt[Q] <= 0) return;
     ProfScope ps(c, KID_ADJ0 + Q, s);
-    launch_adj_sel<Q>(sel, c, lam, ellbar, lambar, gsum, first, s, std::make_integer_sequence<int, kNShapes>{});
+    launch_adj_sel<Q>(sel, c, lam, eb, lambar, gsum, first, s, std::make_integer_sequence<int, kNShapes>{});
 }
 
 template <int... Q>
-static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const float* lam, const float* ellbar,
-                        float* lambar, float* gsum, int first, hipStream_t s)
+static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, ExclDev lam, ExclDev eb, float* lambar,
+                        float* gsum, int first, hipStream_t s)
 {
-    (launch_adj_class<Q>(c, c->adj_sel[Q], lam, ellbar, lambar, gsum, first, s), ...);
+    (launch_adj_class<Q>(c, c->adj_sel[Q], lam, eb, lambar, gsum, first, s), ...);
 }
 
-hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar, float* gsum,
-                              bool first, hipStream_t s)
+hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* lambar, float* gsum, bool first,
+                              hipStream_t s)
 {
-    adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, lam, ellbar, lambar, gsum, first ? 1 : 0, s);
+    adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, excl_dev(c, lam), excl_dev(c, ellbar), lambar,
+                gsum, first ? 1 : 0, s);
     return hipGetLastError();
 }
 
-using AdjClassFn = void (*)(const mrf_ctx*, int, const float*, const float*, float*, float*, int, hipStream_t);
+using AdjClassFn = void (*)(const mrf_ctx*, int, ExclDev, ExclDev, float*, float*, int, hipStream_t);
 template <int... Q>
 static constexpr std::array<AdjClassFn, kRayClasses> adj_class_fns(std::integer_sequence<int, Q...>)
 {
     return {&launch_adj_class<Q>...};
 }
 
-hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, const float* ellbar,
-                                  float* lambar, float* gsum, int first, hipStream_t s)
+hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam, ExclSrc ellbar, float* lambar,
+                                  float* gsum, int first, hipStream_t s)
 {
     static constexpr std::array<AdjClassFn, kRayClasses> fns =
         adj_class_fns(std::make_integer_sequence<int, kRayClasses>{});
     if (q < 0 || q >= kRayClasses || sel < 0 || sel >= ray_shape_count(q, true)) return hipErrorInvalidValue;
-    fns[q](c, sel, lam, ellbar, lambar, gsum, first, s);
+    fns[q](c, sel, excl_dev(c, lam), excl_dev(c, ellbar), lambar, gsum, first, s);
     return hipGetLastError();
 }
 

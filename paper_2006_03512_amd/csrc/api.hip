@@ -51,9 +51,9 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->ray_cnt[i]);
     for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->vox_cnt[i]);
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->fwd_sel[i]);
-    const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_col, &c->b_delta, &c->b_bin, &c->b_g, &c->b_lam, &c->b_ell,
-                                 &c->b_vedge, &c->b_vptr, &c->b_theta, &c->b_L, &c->b_sigma, &c->b_ckpt,
-                                 &c->b_tiles, &c->b_counts};
+    const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_col,   &c->b_delta, &c->b_bin,  &c->b_g,    &c->b_lam,
+                                 &c->b_ell,    &c->b_vedge, &c->b_vptr,  &c->b_theta, &c->b_L,   &c->b_sigma,
+                                 &c->b_ckpt,   &c->b_tsum,  &c->b_tbar,  &c->b_tiles, &c->b_counts};
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
     for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
     for (const auto& b : c->b_vox_list) k.push_back((uint64_t)(uintptr_t)b.p);
@@ -93,11 +93,27 @@ hipError_t ensure(DevBuf& b, size_t bytes)
 
 // ------------------------------------------------------------ sweeps
 
-// voxel->ray messages (lambda) that sweep k+1 feeds to the ray phase (k = 0..K-1): the
-// reverse pass needs exactly these, so it never recomputes a voxel phase
-static float* ckpt_slot(const mrf_ctx* c, int k)
+// ray->voxel messages of sweep k (1..K): the last in b_ell; with checkpoints
+// the earlier ones in b_ckpt (the reverse pass needs each), otherwise
+// alternating between b_lam and b_ell so that sweep K-1's survive
+static float* ell_slot(const mrf_ctx* c, int K, int k, bool keep)
 {
-    return (float*)c->b_ckpt.p + (size_t)k * (size_t)c->S;
+    if (k == K) return (float*)c->b_ell.p;
+    if (keep) return (float*)c->b_ckpt.p + (size_t)(k - 1) * (size_t)c->S;
+    return ((K - k) & 1) ? (float*)c->b_lam.p : (float*)c->b_ell.p;
+}
+
+// voxel totals that sweep k (2..K) reads: theta plus the ray messages of sweep k-1
+static float* tot_slot(const mrf_ctx* c, int k, bool keep)
+{
+    return (float*)c->b_tsum.p + (keep ? (size_t)(k - 2) * (size_t)c->V : 0);
+}
+
+// the voxel->ray messages of sweep k (1..K): lambda_e = tot[col_e] - own_e
+static ExclSrc lam_src(const mrf_ctx* c, int K, int k, bool keep)
+{
+    if (k == 1) return ExclSrc{(const float*)c->b_theta.p, nullptr};   // no incoming message yet
+    return ExclSrc{tot_slot(c, k, keep), ell_slot(c, K, k - 1, keep)};
 }
 
 // Everything mrf_infer enqueues after the parameter copies; capturable.
@@ -105,29 +121,22 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
 {
     hipError_t e;
     const float* theta = (const float*)c->b_theta.p;
-    float* ell = (float*)c->b_ell.p;
     if ((e = launch_potentials(c, s)) != hipSuccess) return e;
-    const float* prev = nullptr;   // ell of the previous sweep; nullptr = uniform (0)
-    for (int k = 0; k < K; ++k) {
-        float* lam = keep ? ckpt_slot(c, k) : (float*)c->b_lam.p;
-        // first sweep: every incoming message is 0, so lambda_e = theta_v(e), a gather by slot
-        if ((e = k == 0 ? launch_gather_voxel((const int32_t*)c->b_col.p, theta, lam, c->S, s)
-                        : launch_voxel_phase(c, theta, prev, lam, nullptr, 0, plain, s)) != hipSuccess)
+    for (int k = 1; k <= K; ++k) {
+        if (k > 1 && (e = launch_voxel_phase(c, theta, ell_slot(c, K, k - 1, keep), tot_slot(c, k, keep), nullptr,
+                                             s)) != hipSuccess)
             return e;
-        if ((e = launch_ray_phase(c, lam, ell, plain, s)) != hipSuccess) return e;
-        prev = ell;
+        if ((e = launch_ray_phase(c, lam_src(c, K, k, keep), ell_slot(c, K, k, keep), plain, s)) != hipSuccess)
+            return e;
     }
     if ((e = launch_copy((float*)c->b_L.p, theta, c->V, s)) != hipSuccess) return e;
-    return launch_voxel_phase(c, theta, prev, nullptr, (float*)c->b_L.p, 1, plain, s);
+    return launch_voxel_phase(c, theta, ell_slot(c, K, K, keep), (float*)c->b_L.p, nullptr, s);
 }
 
 static const float* final_ell(const mrf_ctx* c) { return c->inferred ? (const float*)c->b_ell.p : nullptr; }
 
-static const float* final_lam(const mrf_ctx* c)
-{
-    if (!c->inferred) return nullptr;
-    return c->have_ckpt ? ckpt_slot(c, c->K - 1) : (const float*)c->b_lam.p;
-}
+// the last sweep's voxel->ray messages
+static ExclSrc final_lam(const mrf_ctx* c) { return lam_src(c, c->K, c->K, c->have_ckpt != 0); }
 
 }  // namespace mrf
 
@@ -182,7 +191,7 @@ void mrf_destroy(mrf_ctx* c)
     drop_graph(c);
     DevBuf* all[] = {&c->b_scenes, &c->b_frames, &c->b_counts, &c->b_rowptr, &c->b_col, &c->b_delta,
                      &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
-                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_ckpt,
+                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_ckpt, &c->b_tsum, &c->b_tbar,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
     for (DevBuf* b : all) free_buf(*b);
@@ -342,6 +351,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_theta, vb), "mrf_build: alloc theta");
     HCK(ensure(c->b_L, vb), "mrf_build: alloc L");
     HCK(ensure(c->b_thetabar, vb), "mrf_build: alloc thetabar");
+    HCK(ensure(c->b_tbar, 2 * vb), "mrf_build: alloc voxel sums");
     HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
     HCK(ensure(c->b_sigpart, sizeof(double) * 4 * kBins), "mrf_build: alloc sigma partials");
 
@@ -383,11 +393,11 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     st.n_tiles = T;
     st.n_touched_voxels = 0;
     for (int k = 0; k < kVoxClasses; ++k) st.n_touched_voxels += c->vox_cnt[k];
-    // voxel phase: vedge 4 + gather ell 4 + scatter lam 4; ray phase: lam 4 + g 4 + ell 4;
-    // per touched voxel: descriptor 16 + theta 4; per kept ray: count 4; per tile: list 4 +
-    // descriptor 32
+    // voxel phase: vedge 4 + gathered ell 4 per edge, descriptor 16 + theta 4 + total 4 per
+    // touched voxel; ray phase: col 4 + own ell 4 + g 4 + ell 4 per edge, total 4 per touched
+    // voxel, count 4 per kept ray, list 4 + descriptor 32 per tile
     st.fwd_bytes_per_sweep =
-        24.0 * (double)E + 20.0 * (double)st.n_touched_voxels + 4.0 * (double)st.n_kept_rays + 36.0 * (double)c->T;
+        24.0 * (double)E + 28.0 * (double)st.n_touched_voxels + 4.0 * (double)st.n_kept_rays + 36.0 * (double)c->T;
     st.sweeps_done = 0;
     st.have_checkpoints = 0;
     c->built = 1;
@@ -403,11 +413,14 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_infer: hipSetDevice");
     const int keep = keep_checkpoints ? 1 : 0;
-    if (keep) {
-        const size_t need = sizeof(float) * (size_t)sweeps * (size_t)(c->S > 0 ? c->S : 1);
-        if (c->b_ckpt.cap < need) {
-            drop_graph(c);   // the graph holds the old checkpoint addresses
-            HCK(ensure(c->b_ckpt, need), "mrf_infer: alloc checkpoints");
+    {
+        // checkpoints: ell of sweeps 1..K-1 and the voxel totals of sweeps 2..K
+        const size_t need_ell = keep ? sizeof(float) * (size_t)(sweeps - 1) * (size_t)c->S : 0;
+        const size_t need_tot = sizeof(float) * (size_t)(keep && sweeps > 2 ? sweeps - 1 : 1) * (size_t)c->V;
+        if (c->b_ckpt.cap < need_ell || c->b_tsum.cap < need_tot) {
+            drop_graph(c);   // the graph holds the old addresses
+            HCK(ensure(c->b_ckpt, need_ell), "mrf_infer: alloc checkpoints");
+            HCK(ensure(c->b_tsum, need_tot), "mrf_infer: alloc voxel totals");
         }
     }
     HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer: copy prior");
@@ -465,18 +478,21 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_backward: hipSetDevice");
     const int K = c->K;
-    const int32_t* col = (const int32_t*)c->b_col.p;
-    float* ellbar = (float*)c->b_ellbar.p;
-    float* lambar = (float*)c->b_lambar.p;
     float* gsum = (float*)c->b_gsum.p;
     float* thetabar = (float*)c->b_thetabar.p;
-    // d loss / d ell^(K)_e = d loss / d L_v(e);  d loss / d theta starts at d loss / d L
-    HCK(launch_gather_voxel(col, dlogit, ellbar, c->S, s), "mrf_backward: seed");
+    float* tbar = (float*)c->b_tbar.p;
+    float* lbuf[2] = {(float*)c->b_lambar.p, (float*)c->b_ellbar.p};
+    // d loss / d theta starts at d loss / d L; d loss / d ell^(K)_e = d loss / d L_v(e)
     HCK(launch_copy(thetabar, dlogit, c->V, s), "mrf_backward: seed");
+    ExclSrc eb{dlogit, nullptr};
     hipError_t e = hipSuccess;
-    for (int k = K - 1; k >= 0 && e == hipSuccess; --k) {
-        e = launch_ray_adjoint(c, ckpt_slot(c, k), ellbar, lambar, gsum, k == K - 1, s);
-        if (e == hipSuccess) e = launch_voxel_phase(c, nullptr, lambar, k > 0 ? ellbar : nullptr, thetabar, 2, false, s);
+    for (int k = K; k >= 1 && e == hipSuccess; --k) {
+        // sweep k: d/d lambda^(k) from the ray adjoint, then its per-voxel sums, which
+        // give d/d theta and (less the edge's own) d/d ell^(k-1)
+        float* lb = lbuf[(K - k) & 1];
+        e = launch_ray_adjoint(c, lam_src(c, K, k, true), eb, lb, gsum, k == K, s);
+        if (e == hipSuccess) e = launch_voxel_phase(c, nullptr, lb, k > 1 ? tbar : nullptr, thetabar, s);
+        eb = ExclSrc{tbar, lb};
     }
     HCK(e, "mrf_backward: sweeps");
     if (dsigma) HCK(launch_sigma_grad(c, dsigma, s), "mrf_backward: sigma gradient");
@@ -518,7 +534,11 @@ int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, flo
     if (delta) HCK(export_canonical_edges(c, c->b_delta.p, delta, 4, s), "export");
     if (bin) HCK(export_canonical_edges(c, c->b_bin.p, bin, 1, s), "export");
     if (g) HCK(export_canonical_edges(c, c->b_g.p, g, 4, s), "export");
-    if (lam) HCK(export_canonical_edges(c, final_lam(c), lam, 4, s), "export");
+    if (lam) {   // materialised into a scratch edge array first
+        float* tmp = (float*)c->b_ellbar.p;
+        HCK(launch_excl(c, final_lam(c), tmp, s), "export");
+        HCK(export_canonical_edges(c, tmp, lam, 4, s), "export");
+    }
     if (ell) HCK(export_canonical_edges(c, final_ell(c), ell, 4, s), "export");
     return MRF_OK;
 }
@@ -561,20 +581,21 @@ static void kid_bytes(const mrf_ctx* c, int k, double* bytes, int64_t* edges)
     *edges = 0;
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
         const int q = k - KID_VOX0;
-        // per edge: vedge 4 + gathered ell 4 + scattered lam 4;
-        // per voxel: descriptor 16 + theta 4
+        // per edge: vedge 4 + gathered message 4; per voxel: descriptor 16 + base 4 + total 4
         *edges = c->vox_cls_edges[q];
-        *bytes = 12.0 * (double)*edges + 20.0 * (double)c->vox_cnt[q];
+        *bytes = 8.0 * (double)*edges + 24.0 * (double)c->vox_cnt[q];
     } else if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) {
         const int q = k - KID_RAY0;
-        // per edge: lam 4 + g 4 + ell 4; per ray: count 4; per tile: descriptor 32
+        // per edge: col 4 + own ell 4 + g 4 + ell 4 (voxel totals: counted once per voxel
+        // in the sweep figure); per ray: count 4; per tile: list 4 + descriptor 32
         *edges = c->ray_cls_edges[q];
-        *bytes = 12.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
+        *bytes = 16.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
     } else if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses) {
         const int q = k - KID_ADJ0;
-        // per edge: lam 4 + g 4 + ellbar 4 + lambar 4 + gsum read 4 + write 4
+        // per edge: col 4 + own ell 4 + g 4 + own lambar of the later sweep 4 + lambar 4 +
+        // gsum read 4 + write 4
         *edges = c->ray_cls_edges[q];
-        *bytes = 24.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
+        *bytes = 28.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
     } else if (k == KID_POT || k == KID_SIGMA) {
         *edges = c->E;
         *bytes = 9.0 * (double)c->S;
@@ -590,22 +611,24 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
     Profiler P;
     c->prof = &P;
     hipError_t e = hipSuccess;
+    // inputs: the last sweep's messages; outputs go to scratch buffers, so the
+    // inference state stays untouched
     const float* theta = (const float*)c->b_theta.p;
-    float* lam = (float*)c->b_lam.p;
-    float* ell = (float*)c->b_ellbar.p;   // scratch output: keeps the inference's messages
     const float* ell_in = final_ell(c);
-    HCK(launch_copy(ell, ell_in, c->S, s), "mrf_profile_sweeps");
+    float* vt = (float*)c->b_tbar.p;
+    float* ell = (float*)c->b_ellbar.p;
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
-        e = launch_voxel_phase(c, theta, ell, lam, nullptr, 0, false, s);
-        if (e == hipSuccess) e = launch_ray_phase(c, lam, ell, false, s);
+        e = launch_voxel_phase(c, theta, ell_in, vt, nullptr, s);
+        if (e == hipSuccess) e = launch_ray_phase(c, ExclSrc{vt, ell_in}, ell, false, s);
     }
     if (include_backward) {
         float* lambar = (float*)c->b_lambar.p;
         float* gsum = (float*)c->b_gsum.p;
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
-            e = launch_ray_adjoint(c, lam, ell, lambar, gsum, r == 0, s);
+            e = launch_ray_adjoint(c, ExclSrc{vt, ell_in}, ExclSrc{(const float*)c->b_L.p, ell}, lambar, gsum,
+                                   r == 0, s);
             if (e == hipSuccess)
-                e = launch_voxel_phase(c, nullptr, lambar, ell, (float*)c->b_thetabar.p, 2, false, s);
+                e = launch_voxel_phase(c, nullptr, lambar, vt + c->V, (float*)c->b_thetabar.p, s);
         }
         if (e == hipSuccess) e = launch_sigma_grad(c, (float*)c->b_sigpart.p + 4 * kBins, s);
     }
@@ -684,8 +707,8 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
     HCK(hipSetDevice(c->device), "mrf_autotune: hipSetDevice");
     // inputs: the last sweep's messages; outputs go to buffers the reverse pass
     // initialises before use, so the inference state stays untouched
-    const float* lam = final_lam(c);
-    const float* ell_in = final_ell(c);
+    const ExclSrc lam = final_lam(c);
+    const ExclSrc eb{(const float*)c->b_L.p, nullptr};
     float* ell_out = (float*)c->b_ellbar.p;
     float* lambar = (float*)c->b_lambar.p;
     float* gsum = (float*)c->b_gsum.p;
@@ -700,7 +723,7 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
             float best_ms = 0.0f;
             for (int i = 0; i < ns && e == hipSuccess; ++i) {
                 auto run = [&]() {
-                    return adj ? launch_adj_class_shape(c, q, i, lam, ell_in, lambar, gsum, 1, s)
+                    return adj ? launch_adj_class_shape(c, q, i, lam, eb, lambar, gsum, 1, s)
                                : launch_ray_class_shape(c, q, i, lam, ell_out, s);
                 };
                 e = run();   // warm-up

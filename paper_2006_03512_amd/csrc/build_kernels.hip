@@ -629,7 +629,7 @@ __global__ void vox_class_k(const int64_t* __restrict__ vptr, int64_t Vk, uint8_
                 c = (uint8_t)k;
                 break;
             }
-        if (m > (int64_t)kVoxChunk * kVoxMaxChunks) c = kVoxClasses;
+        if (m > 2147483647LL) c = kVoxClasses;
     }
     cls[v] = c;
 }
@@ -897,7 +897,7 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
         hipFree(tmp.p);
         if (e != hipSuccess) return e;
         if (too_big > 0) {
-            set_error("a voxel is crossed by more than 1048576 rays");
+            set_error("a voxel is crossed by more than 2^31 - 1 rays");
             return hipErrorInvalidConfiguration;
         }
     }

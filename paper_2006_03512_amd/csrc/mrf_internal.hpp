@@ -112,7 +112,6 @@ constexpr bool vox_classes_valid()
 static_assert(vox_classes_valid(), "voxel classes: increasing capacities; 16 or 32 lanes per packed voxel, or "
                                    "64 NW IPL edges with IPL <= 32, NW <= 16");
 constexpr int kVoxChunk = 256;
-constexpr int kVoxMaxChunks = 4096;   // degree limit 1048576
 
 // Voxels are keyed brick-major (8^3 bricks) for the voxel -> ray incidence so
 // that one brick's voxels, which share most of their rays, are adjacent.
@@ -149,6 +148,22 @@ struct TileDev {
     int32_t nu, nv;       // pixels of the tile inside the image
     int32_t len;          // longest ray of the tile (steps)
     int32_t pad;
+};
+
+// Per-edge voxel -> ray messages (forward) or d/d ell (reverse) in the form the
+// ray kernels read them: value_e = tot[col_e] - own_e, tot a per-voxel total
+// (linear voxel id) and own_e the edge's own term in it (own null: 0).
+struct ExclSrc {
+    const float* tot;
+    const float* own;
+};
+
+// The kernel-side form: own always points at a readable per-slot array (the
+// potentials g when absent), with has_own telling whether to use it.
+struct ExclDev {
+    const float* tot;
+    const float* own;
+    int has_own;
 };
 
 // Work item of the voxel kernels: one voxel's edge list vedge[start, start + m)
@@ -218,6 +233,8 @@ struct mrf_ctx {
         b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_ckpt,
         b_ellbar, b_lambar, b_gsum, b_tmp64, b_cls, b_sigpart, b_misc;
     mrf::DevBuf b_tiles, b_tbase;
+    mrf::DevBuf b_tsum;   // per-voxel totals of the sweeps (theta + incoming ray messages)
+    mrf::DevBuf b_tbar;   // per-voxel sums of d/d lambda in the reverse pass (2 V: one spare)
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
     mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
     mrf::DevBuf b_vox_list[mrf::kVoxClasses];     // brick-major keys
@@ -295,26 +312,31 @@ hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s);
 hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
+inline ExclDev excl_dev(const mrf_ctx* c, ExclSrc x)
+{
+    return ExclDev{x.tot, x.own ? x.own : (const float*)c->b_g.p, x.own ? 1 : 0};
+}
+
 // sweep_kernels.hip
 hipError_t launch_potentials(mrf_ctx* c, hipStream_t s);
 hipError_t launch_fill(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
-hipError_t launch_gather_voxel(const int32_t* col, const float* vox, float* edge, int64_t E,
-                               hipStream_t s);
-// voxel phase: out_e = (base_v + sum_{e'<e} in) + sum_{e'>e} in over the voxel's edges;
-// total_mode 0: none, 1: total[v] = base_v + sum, 2: total[v] += sum
-hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* out,
-                              float* total, int total_mode, bool plain, hipStream_t s);
-hipError_t launch_ray_phase(mrf_ctx* c, const float* lam, float* ell, bool plain, hipStream_t s);
+// voxel phase: per touched voxel v, sum_v = sum of in over its edges;
+// tout[v] = base[v] + sum_v (base null: 0) and / or tacc[v] += sum_v (each may be null)
+hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* tout, float* tacc,
+                              hipStream_t s);
+hipError_t launch_ray_phase(mrf_ctx* c, ExclSrc lam, float* ell, bool plain, hipStream_t s);
 // one class of the ray phase / reverse pass with launch shape `sel` (autotuner)
-hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, float* ell, hipStream_t s);
-hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, const float* lam, const float* ellbar,
-                                  float* lambar, float* gsum, int first, hipStream_t s);
+hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam, float* ell, hipStream_t s);
+hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam, ExclSrc ellbar, float* lambar,
+                                  float* gsum, int first, hipStream_t s);
+// out_e = tot[col_e] - own_e on every edge slot (0 on padding)
+hipError_t launch_excl(const mrf_ctx* c, ExclSrc x, float* out, hipStream_t s);
 hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
 
 // adjoint_kernels.hip
-hipError_t launch_ray_adjoint(mrf_ctx* c, const float* lam, const float* ellbar, float* lambar,
-                              float* gsum, bool first, hipStream_t s);
+hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* lambar, float* gsum, bool first,
+                              hipStream_t s);
 hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s);
 
 }  // namespace mrf

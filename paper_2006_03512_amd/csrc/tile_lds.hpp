@@ -42,6 +42,24 @@ __device__ __forceinline__ void tile_fetch(const float* __restrict__ src, int64_
     }
 }
 
+template <int NT, int NR>
+__device__ __forceinline__ void tile_fetch_i(const int32_t* __restrict__ src, int64_t base, int nf, int32_t (&v)[NR])
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int idx = min((int)threadIdx.x + r * NT, nf - 1);
+        v[r] = src[base + idx];
+    }
+}
+
+// Per-edge value tot[col] - own (the voxel's total less the edge's own term;
+// own absent when has_own is 0), 0 on padding slots (col < 0).  t is the
+// gathered tot[max(col, 0)]; selects, so stale bits on padding never propagate.
+__device__ __forceinline__ float excl_value(int32_t col, float t, float own, int has_own)
+{
+    return col >= 0 ? t - (has_own ? own : 0.0f) : 0.0f;
+}
+
 // The fetched values into the LDS image of the tile (layout lds_at<IPL>).
 template <int NT, int NR, int IPL>
 __device__ __forceinline__ void tile_to_lds(float* __restrict__ lds, int nf, const float (&v)[NR])
