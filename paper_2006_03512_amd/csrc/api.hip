@@ -367,8 +367,8 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         "mrf_build: alloc sort tables");
     int64_t* offs = (int64_t*)c->b_tmp64.p;
     int32_t* hist = (int32_t*)(offs + nh + 1);
-    const size_t sb2 = scan_tmp_bytes(nh + 1);
-    HCK(ensure(c->b_misc, sb2 > c->b_misc.cap ? sb2 : c->b_misc.cap), "mrf_build: alloc scan");
+    const size_t sb2 = radix_tmp_bytes(S);
+    HCK(ensure(c->b_misc, sb2 > c->b_misc.cap ? sb2 : c->b_misc.cap), "mrf_build: alloc sort scan");
     HCK(radix_sort_pairs((const uint32_t*)c->b_g.p, (uint32_t*)c->b_lam.p, (uint32_t*)c->b_ell.p,
                          (uint32_t*)c->b_ellbar.p, (uint32_t*)c->b_gsum.p, (uint32_t*)c->b_lambar.p,
                          (uint32_t*)c->b_vedge.p, S, bits_for(Vk), hist, offs, c->b_misc.p, c->b_misc.cap, s),
@@ -552,8 +552,10 @@ static std::string kid_name(const mrf_ctx* c, int k)
     if (k >= KID_VOX0 && k < KID_VOX0 + kVoxClasses) {
         const int q = k - KID_VOX0;
         if (q == kVoxClasses - 1) return "voxel_chunked_k";
-        if (kVoxNW[q] == 0) return "voxel_small_k<" + std::to_string(kVoxCap[q]) + ">";
-        return "voxel_k<" + std::to_string(kVoxNW[q]) + "," + std::to_string(kVoxCap[q] / (64 * kVoxNW[q])) + ">";
+        if (kVoxNW[q] == 0)
+            return "voxel_small_k<" + std::to_string(kVoxCap[q]) + "," + std::to_string(kVoxVPW[q]) + ">";
+        return "voxel_k<" + std::to_string(kVoxNW[q]) + "," + std::to_string(kVoxCap[q] / (64 * kVoxNW[q])) + "," +
+               std::to_string(kVoxVPW[q]) + ">";
     }
     auto ray_name = [](const char* direct, const char* lds, int q, RayShape sh, bool adj) {
         std::string n = std::string(ray_class_lds(q) ? lds : direct) + "<" + std::to_string(sh.g) + "," +

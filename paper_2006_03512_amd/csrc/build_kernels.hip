@@ -436,7 +436,15 @@ hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* 
 
 constexpr int RS_T = 256, RS_IPT = 16, RS_TILE = RS_T * RS_IPT;
 
+constexpr int RS_CB = 256;   // tiles per chunk of the digit-offset scan
+
 size_t radix_hist_entries(int64_t n) { return (size_t)256 * (size_t)cdiv(n > 0 ? n : 1, RS_TILE); }
+
+size_t radix_tmp_bytes(int64_t n)
+{
+    const int64_t nch = cdiv(cdiv(n > 0 ? n : 1, RS_TILE), RS_CB);
+    return sizeof(int64_t) * (size_t)(2 * 256 * nch + 256);
+}
 
 // Lanes of a wave holding digit d (of valid items): 8 ballots.
 __device__ __forceinline__ uint64_t rs_peers(int d, bool valid)
@@ -451,38 +459,116 @@ __device__ __forceinline__ uint64_t rs_peers(int d, bool valid)
     return peers;
 }
 
-// Digit counts of one tile of RS_TILE keys (LDS atomics); all loads of the
-// tile are issued first.
+// Digit counts of one tile of RS_TILE keys.  Thread t takes RS_IPT
+// consecutive keys (vector loads) and adds each run of equal digits with one
+// LDS atomic: keys in slot order come in runs (the rays of a tile cross the
+// same voxels at the same step), which would otherwise serialise the atomics
+// of a wave on a few addresses.  RS_TILE is a multiple of 16 and n of 4 is
+// not assumed: the tile's tail is read key by key.
 __global__ __launch_bounds__(RS_T) void rs_hist_k(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                   int32_t* __restrict__ hist, int64_t nblocks)
 {
+    static_assert(RS_IPT == 16, "four 16-byte loads per thread");
     __shared__ int32_t h[256];
     h[threadIdx.x] = 0;
-    const int64_t start = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t i0 = (int64_t)blockIdx.x * RS_TILE + (int64_t)threadIdx.x * RS_IPT;
     uint32_t kr[RS_IPT];
+    if (i0 + RS_IPT <= n) {
+        const uint4* p = (const uint4*)(keys + i0);   // keys and RS_IPT * 4 bytes: 16-byte aligned
 #pragma unroll
-    for (int r = 0; r < RS_IPT; ++r) {
-        const int64_t i = start + (int64_t)r * RS_T + threadIdx.x;
-        kr[r] = keys[i < n ? i : n - 1];
+        for (int q = 0; q < 4; ++q) {
+            const uint4 w = p[q];
+            kr[4 * q] = w.x;
+            kr[4 * q + 1] = w.y;
+            kr[4 * q + 2] = w.z;
+            kr[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RS_IPT; ++j) kr[j] = i0 + j < n ? keys[i0 + j] : 0u;
+    }
+    const int nv = (int)(n - i0 < RS_IPT ? (n - i0 > 0 ? n - i0 : 0) : RS_IPT);
+    __syncthreads();
+    if (nv > 0) {
+        int cur = (kr[0] >> shift) & 255, cnt = 1;
+#pragma unroll
+        for (int j = 1; j < RS_IPT; ++j) {
+            const int d = (kr[j] >> shift) & 255;
+            if (j < nv) {
+                if (d == cur) {
+                    ++cnt;
+                } else {
+                    atomicAdd(&h[cur], cnt);
+                    cur = d;
+                    cnt = 1;
+                }
+            }
+        }
+        atomicAdd(&h[cur], cnt);
     }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RS_IPT; ++r)
-        if (start + (int64_t)r * RS_T + threadIdx.x < n) atomicAdd(&h[(kr[r] >> shift) & 255], 1);
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// Digit offsets from the tile-major (tile, digit) counts, in three steps:
+// per-chunk column sums (coalesced rows), an exclusive scan of each digit's
+// chunk sums (one block per digit), and per-tile running sums inside each
+// chunk on top of the digit's base (the exclusive scan of the digit totals).
+__global__ __launch_bounds__(256) void rs_colsum_k(const int32_t* __restrict__ hist, int64_t nb,
+                                                   int64_t* __restrict__ csum)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * RS_CB;
+    const int64_t b1 = b0 + RS_CB < nb ? b0 + RS_CB : nb;
+    int64_t acc = 0;
+#pragma unroll 8
+    for (int64_t b = b0; b < b1; ++b) acc += hist[b * 256 + threadIdx.x];
+    csum[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+// block d: coff[c][d] = items of digit d in chunks < c; dtot[d] = all of them
+__global__ __launch_bounds__(256) void rs_colscan_k(const int64_t* __restrict__ csum, int64_t nch,
+                                                    int64_t* __restrict__ coff, int64_t* __restrict__ dtot)
+{
+    const int d = blockIdx.x;
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nch; c0 += 256) {
+        const int64_t c = c0 + threadIdx.x;
+        const int64_t x = c < nch ? csum[c * 256 + d] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan_i64(x, &tot);
+        if (c < nch) coff[c * 256 + d] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtot[d] = carry;
+}
+
+// offs[b][d]: output position of tile b's first item of digit d
+__global__ __launch_bounds__(256) void rs_offsets_k(const int32_t* __restrict__ hist, int64_t nb,
+                                                    const int64_t* __restrict__ coff,
+                                                    const int64_t* __restrict__ dtot, int64_t* __restrict__ offs)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * RS_CB;
+    const int64_t b1 = b0 + RS_CB < nb ? b0 + RS_CB : nb;
+    int64_t total;
+    const int64_t base = block_excl_scan_i64(dtot[threadIdx.x], &total);
+    int64_t run = base + coff[(int64_t)blockIdx.x * 256 + threadIdx.x];
+    for (int64_t b = b0; b < b1; ++b) {
+        offs[b * 256 + threadIdx.x] = run;
+        run += hist[b * 256 + threadIdx.x];
+    }
 }
 
 // Stable scatter of one tile of RS_TILE items.  Items are ranked in index order
 // among equal digits (wave ballots, waves in order, rounds in order) into an
 // LDS copy of the tile grouped by digit; the copy is then written out as
 // contiguous runs, one per digit, at the digit's global offset for this tile
-// (coalesced stores in place of scattered words).  offs is the exclusive scan
-// of the (digit, tile) counts in digit-major order, with the total at the end.
+// (coalesced stores in place of scattered words).  hist and offs hold the
+// tile's digit counts and output offsets (tile-major rows of 256).
 __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict__ keys_in,
                                                      const uint32_t* __restrict__ vals_in, int64_t n,
-                                                     int shift, const int64_t* __restrict__ offs,
-                                                     int64_t nblocks, uint32_t* __restrict__ keys_out,
+                                                     int shift, const int32_t* __restrict__ hist,
+                                                     const int64_t* __restrict__ offs,
+                                                     uint32_t* __restrict__ keys_out,
                                                      uint32_t* __restrict__ vals_out)
 {
     __shared__ uint32_t lk[RS_TILE];
@@ -501,8 +587,8 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
         kr[r] = keys_in[ic];
         vr[r] = vals_in ? vals_in[ic] : (uint32_t)i;
     }
-    const int64_t o0 = offs[(int64_t)tid * nblocks + blockIdx.x];
-    const int64_t cnt = offs[(int64_t)tid * nblocks + blockIdx.x + 1] - o0;
+    const int64_t o0 = offs[(int64_t)blockIdx.x * 256 + tid];
+    const int64_t cnt = hist[(int64_t)blockIdx.x * 256 + tid];
     boff[tid] = o0;
     run[tid] = 0;
 #pragma unroll
@@ -553,19 +639,27 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t*
     if (n == 0) return hipSuccess;
     const int passes = key_bits <= 8 ? 1 : (key_bits + 7) / 8;
     const int64_t nb = cdiv(n, RS_TILE);
-    const int64_t nh = 256 * nb;
-    if (tmp_bytes < scan_tmp_bytes(nh)) return hipErrorInvalidValue;
+    const int64_t nch = cdiv(nb, RS_CB);
+    if (tmp_bytes < radix_tmp_bytes(n)) return hipErrorInvalidValue;
+    for (const uint32_t* k : {keys_in, (const uint32_t*)keys_a, (const uint32_t*)keys_b})   // rs_hist_k's 16-byte loads
+        if ((uintptr_t)k % 16 != 0) return hipErrorInvalidValue;
+    int64_t* csum = (int64_t*)tmp;
+    int64_t* coff = csum + 256 * nch;
+    int64_t* dtot = coff + 256 * nch;
     const uint32_t* sk = keys_in;
     const uint32_t* sv = nullptr;
     for (int p = 0; p < passes; ++p) {
         uint32_t* dk = (p == passes - 1) ? keys_out : ((p & 1) ? keys_b : keys_a);
         uint32_t* dv = (p == passes - 1) ? vals_out : ((p & 1) ? vals_b : vals_a);
         hipLaunchKernelGGL(rs_hist_k, dim3((unsigned)nb), dim3(RS_T), 0, s, sk, n, 8 * p, hist, nb);
-        hipError_t e = scan_rec(LoadI32{hist}, nh, offs, (int64_t*)tmp, s);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(rs_colsum_k, dim3((unsigned)nch), dim3(256), 0, s, (const int32_t*)hist, nb, csum);
+        hipLaunchKernelGGL(rs_colscan_k, dim3(256), dim3(256), 0, s, (const int64_t*)csum, nch, coff, dtot);
+        hipLaunchKernelGGL(rs_offsets_k, dim3((unsigned)nch), dim3(256), 0, s, (const int32_t*)hist, nb,
+                           (const int64_t*)coff, (const int64_t*)dtot, offs);
         hipLaunchKernelGGL(rs_scatter_k, dim3((unsigned)nb), dim3(RS_T), 0, s, sk, sv, n, 8 * p,
-                           (const int64_t*)offs, nb, dk, dv);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+                           (const int32_t*)hist, (const int64_t*)offs, dk, dv);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
         sk = dk;
         sv = dv;
     }
@@ -1001,17 +1095,18 @@ hipError_t export_canonical_incidence(const mrf_ctx* c, int64_t* vptr, uint32_t*
         // canonical vedge: stable radix sort of canonical edge ids by linear voxel id
         // (O(E) temporaries: this export is a checking facility)
         const size_t E = (size_t)c->E;
-        if ((e = ensure(m->b_export, 5 * E * sizeof(uint32_t))) != hipSuccess) return e;
+        const size_t Ep = (E + 63) & ~(size_t)63;   // 256-byte aligned sub-arrays (vector loads)
+        if ((e = ensure(m->b_export, 5 * Ep * sizeof(uint32_t))) != hipSuccess) return e;
         uint32_t* keys = (uint32_t*)c->b_export.p;
-        uint32_t *ka = keys + E, *va = keys + 2 * E, *kb = keys + 3 * E, *vb = keys + 4 * E;
+        uint32_t *ka = keys + Ep, *va = keys + 2 * Ep, *kb = keys + 3 * Ep, *vb = keys + 4 * Ep;
         if ((e = export_canonical_edges(c, c->b_col.p, keys, 4, s)) != hipSuccess) return e;
         const int64_t nh = (int64_t)radix_hist_entries(c->E);
         if ((e = ensure(m->b_tmp64, sizeof(int64_t) * (size_t)(nh + 1) + sizeof(int32_t) * (size_t)nh)) != hipSuccess)
             return e;
         int64_t* offs = (int64_t*)c->b_tmp64.p;
         int32_t* hist = (int32_t*)(offs + nh + 1);
-        const size_t sb2 = scan_tmp_bytes(nh + 1);
-        if ((e = ensure(m->b_misc, sb2)) != hipSuccess) return e;
+        const size_t sb2 = radix_tmp_bytes(c->E);
+        if ((e = ensure(m->b_misc, sb2 > m->b_misc.cap ? sb2 : m->b_misc.cap)) != hipSuccess) return e;
         int bits = 1;
         while (bits < 31 && (int64_t(1) << bits) <= c->V - 1) ++bits;
         const int passes = bits <= 8 ? 1 : (bits + 7) / 8;

@@ -84,19 +84,25 @@ constexpr int kTileW = 4;
 constexpr int kTile = kTileW * kTileW;
 
 // Voxel work classes by degree: (waves per voxel NW, items per lane IPL =
-// capacity / (64 NW)); each wave owns 64*IPL consecutive edges of the voxel.
-// Above the last class a 1024-thread block walks 256-edge chunks twice.
+// capacity / (64 NW), voxels per wave VPW); each wave owns 64*IPL consecutive
+// edges of a voxel, and a one-wave class (NW = 1) walks VPW voxels per wave
+// (a packed class, NW = 0: VPW voxels per lane group) with every load issued
+// first.  Above the last class a 1024-thread block walks the voxel in
+// 1024-edge pieces.
 #ifndef MRF_VOX_CAPS
-#define MRF_VOX_CAPS 16, 32, 64, 256, 1024, 4096, 16384, 32768
-#define MRF_VOX_NW 0, 0, 1, 1, 1, 4, 16, 16
+#define MRF_VOX_CAPS 16, 32, 64, 128, 256, 1024, 4096, 16384, 32768
+#define MRF_VOX_NW 0, 0, 1, 1, 1, 1, 4, 16, 16
+#define MRF_VOX_VPW 4, 4, 8, 4, 4, 1, 1, 1, 1
 #endif
 // Degree capacity of each single-pass class and its waves per voxel; NW = 0
 // packs 64 / cap voxels into a wave (cap = 16 or 32 lanes per voxel, one edge
 // per lane).
 constexpr int kVoxCap[] = {MRF_VOX_CAPS};
 constexpr int kVoxNW[] = {MRF_VOX_NW};
+constexpr int kVoxVPW[] = {MRF_VOX_VPW};
 constexpr int kVoxClasses = (int)(sizeof(kVoxCap) / sizeof(int)) + 1;   // + the chunked class
-static_assert(sizeof(kVoxNW) == sizeof(kVoxCap), "one wave count per voxel class");
+static_assert(sizeof(kVoxNW) == sizeof(kVoxCap) && sizeof(kVoxVPW) == sizeof(kVoxCap),
+              "one wave count and one voxels-per-wave count per voxel class");
 constexpr bool vox_classes_valid()
 {
     for (int k = 0; k + 1 < kVoxClasses; ++k) {
@@ -105,13 +111,16 @@ constexpr bool vox_classes_valid()
         } else if (kVoxCap[k] % (64 * kVoxNW[k]) != 0 || kVoxCap[k] / (64 * kVoxNW[k]) > 32 || kVoxNW[k] > 16) {
             return false;
         }
+        if (kVoxVPW[k] < 1 || kVoxVPW[k] > 32 || (kVoxNW[k] > 1 && kVoxVPW[k] != 1)) return false;
+        if (kVoxNW[k] == 1 && kVoxVPW[k] * (kVoxCap[k] / 64) > 32) return false;
         if (k > 0 && kVoxCap[k] <= kVoxCap[k - 1]) return false;
     }
     return true;
 }
 static_assert(vox_classes_valid(), "voxel classes: increasing capacities; 16 or 32 lanes per packed voxel, or "
-                                   "64 NW IPL edges with IPL <= 32, NW <= 16");
-constexpr int kVoxChunk = 256;
+                                   "64 NW IPL edges with IPL <= 32, NW <= 16; several voxels per wave or "
+                                   "group only with NW <= 1, at most 32 items per lane in all");
+constexpr int kVoxChunk = 1024;   // piece of a hub voxel (16 items per lane)
 
 // Voxels are keyed brick-major (8^3 bricks) for the voxel -> ray incidence so
 // that one brick's voxels, which share most of their rays, are adjacent.
@@ -301,6 +310,7 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t*
                             uint32_t* vals_out, int64_t n, int key_bits, int32_t* hist,
                             int64_t* offs, void* tmp, size_t tmp_bytes, hipStream_t s);
 size_t radix_hist_entries(int64_t n);
+size_t radix_tmp_bytes(int64_t n);   // tmp bytes radix_sort_pairs needs for n items
 hipError_t launch_vptr_from_sorted(const uint32_t* sorted_keys, int64_t n, int64_t V, int64_t* vptr,
                                    hipStream_t s);
 hipError_t build_classes(mrf_ctx* c, hipStream_t s);

@@ -63,9 +63,12 @@ __global__ void sigmoid_k(const float* __restrict__ L, float* __restrict__ p, in
         p[i] = 1.0f / (1.0f + __expf(-L[i]));
 }
 
-// g_e = -(delta_e / sigma_b)^2 / 2 - log sigma_b - log(2 pi) / 2
+// g_e = -(delta_e / sigma_b)^2 / 2 - log sigma_b - log(2 pi) / 2.  One thread
+// per 16 consecutive slots (S is a multiple of 16: one tile step): 16-byte
+// loads of delta and bin, 16-byte stores of g; padding slots (bin 255) are
+// left as they are.
 __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ delta, const uint8_t* __restrict__ bin,
-                                                    int64_t E, const float* __restrict__ sigma, float* __restrict__ g)
+                                                    int64_t S, const float* __restrict__ sigma, float* __restrict__ g)
 {
     __shared__ float inv[kBins], cst[kBins];
     if (threadIdx.x < kBins) {
@@ -74,11 +77,33 @@ __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ de
         cst[threadIdx.x] = logf(s) + 0.91893853320467274f;
     }
     __syncthreads();
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
-        const int b = bin[e];
-        if (b >= kBins) continue;   // padding slot
-        const float x = delta[e] * inv[b];
-        g[e] = -0.5f * x * x - cst[b];
+    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (e0 >= S) return;
+    const uint4 bw = *(const uint4*)(bin + e0);
+    float4 dv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dv[q] = *(const float4*)(delta + e0 + 4 * q);
+    const uint32_t words[4] = {bw.x, bw.y, bw.z, bw.w};
+    bool all = true;
+    float out[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int b = (int)((words[j >> 2] >> (8 * (j & 3))) & 255u);
+        const float4 d4 = dv[j >> 2];
+        const float dj = (j & 3) == 0 ? d4.x : (j & 3) == 1 ? d4.y : (j & 3) == 2 ? d4.z : d4.w;
+        const int bb = b < kBins ? b : 0;
+        const float x = dj * inv[bb];
+        out[j] = -0.5f * x * x - cst[bb];
+        all = all && b < kBins;
+    }
+    if (all) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *(float4*)(g + e0 + 4 * q) = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (((words[j >> 2] >> (8 * (j & 3))) & 255u) < kBins) g[e0 + j] = out[j];
     }
 }
 
@@ -122,7 +147,7 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 {
     if (c->S <= 0) return hipSuccess;
     ProfScope ps(c, KID_POT, s);
-    hipLaunchKernelGGL(potentials_k, dim3(grid_for(c->S)), dim3(256), 0, s, (const float*)c->b_delta.p,
+    hipLaunchKernelGGL(potentials_k, dim3(nblk(c->S / 16, 256)), dim3(256), 0, s, (const float*)c->b_delta.p,
                        (const uint8_t*)c->b_bin.p, c->S, (const float*)c->b_sigma.p, (float*)c->b_g.p);
     return hipGetLastError();
 }
@@ -134,8 +159,6 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 // fixed order, written as tout[v] = base[v] + sum_v and/or added to tacc[v].
 // The voxel -> ray message of edge e is then tot[v(e)] - own_e, formed by the
 // ray kernels as they stage their tiles (no per-edge scatter here).
-
-constexpr int VIPL = kVoxChunk / 64;   // items per lane in a 256-edge chunk
 
 // Sum over items base + 64 k + l (k < N, l the lane) of the edge list
 // [s, s+m) of one voxel (0 past m).  Branchless, with item indices clamped to
@@ -166,58 +189,89 @@ __device__ __forceinline__ void vox_store(uint32_t v, float sum, const float* __
 
 // One voxel's edge list [s, s+m) summed by NW waves, each owning 64*IPL
 // consecutive edges (striped over its lanes); the wave sums meet in LDS and
-// are added in wave order.  NW == 1 packs four voxels per 256-thread block.
+// are added in wave order.  NW == 1: four waves per 256-thread block, each
+// summing VPW consecutive voxels of the list with all their loads issued
+// before the first wait (more bytes in flight per wave for low degrees).
 // Voxels arrive in brick-major order and blocks are remapped so each XCD
 // takes a contiguous range of them.
-template <int NW, int IPL>
+template <int NW, int IPL, int VPW>
 __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
     const VoxDev* __restrict__ vd, int64_t n, const uint32_t* __restrict__ vedge, const float* __restrict__ base,
     const float* __restrict__ in, float* __restrict__ tout, float* __restrict__ tacc)
 {
+    static_assert(NW == 1 || VPW == 1, "several voxels per wave only with one wave per voxel");
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t vi = NW == 1 ? lb * 4 + wv : lb;
-    const int part = NW == 1 ? 0 : wv;
-    if (vi >= n) return;   // whole waves (NW == 1) or whole blocks (NW > 1)
-    const VoxDev d = vd[vi];
-    float tot = wave_sum(vox_lane_sum<IPL>(d.start, d.m, part * 64 * IPL, vedge, in));
-    if (NW > 1) {
-        __shared__ float wsum[NW > 1 ? NW : 1];
+    if constexpr (NW == 1) {
+        const int64_t v0 = (lb * 4 + wv) * VPW;
+        if (v0 >= n) return;   // whole wave
+        VoxDev d[VPW];
+#pragma unroll
+        for (int u = 0; u < VPW; ++u) d[u] = vd[min(v0 + u, n - 1)];   // past the list: a repeat, not stored
+        uint32_t e[VPW][IPL];
+        float x[VPW][IPL];
+#pragma unroll
+        for (int u = 0; u < VPW; ++u)
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) e[u][k] = vedge[d[u].start + min(k * 64 + l, d[u].m - 1)];
+#pragma unroll
+        for (int u = 0; u < VPW; ++u)
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) x[u][k] = in[e[u][k]];
+#pragma unroll
+        for (int u = 0; u < VPW; ++u) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) a += k * 64 + l < d[u].m ? x[u][k] : 0.0f;
+            a = wave_sum(a);
+            if (l == 0 && v0 + u < n) vox_store(d[u].v, a, base, tout, tacc);
+        }
+    } else {
+        const int64_t vi = lb;
+        if (vi >= n) return;   // whole block
+        const VoxDev d = vd[vi];
+        float tot = wave_sum(vox_lane_sum<IPL>(d.start, d.m, wv * 64 * IPL, vedge, in));
+        __shared__ float wsum[NW];
         if (l == 0) wsum[wv] = tot;
         __syncthreads();
         tot = 0.0f;
         for (int q = 0; q < NW; ++q) tot += wsum[q];
+        if (threadIdx.x == 0) vox_store(d.v, tot, base, tout, tacc);
     }
-    if (l == 0 && part == 0) vox_store(d.v, tot, base, tout, tacc);
 }
 
-// Voxels of at most G edges (G = 16 or 32), 64 / G per wave and 256 / G per
-// block: lane l of a group holds edge l of its voxel and a group reduction
-// sums them.  Groups past the list take no edges.
-template <int G>
+// Voxels of at most G edges (G = 16 or 32): 64 / G lane groups per wave, 256
+// / G per block, each group summing VPG consecutive voxels of the list (lane
+// l holds edge l of each; group reductions), every load issued first.
+template <int G, int VPG>
 __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ vd, int64_t n,
                                                      const uint32_t* __restrict__ vedge,
                                                      const float* __restrict__ base, const float* __restrict__ in,
                                                      float* __restrict__ tout, float* __restrict__ tacc)
 {
+    constexpr int GPB = 256 / G;   // groups per block
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    if (lb * (256 / G) >= n) return;   // whole block
-    const int64_t vi = lb * (256 / G) + (int)threadIdx.x / G;
+    if (lb * GPB * VPG >= n) return;   // whole block
+    const int64_t v0 = (lb * GPB + (int)threadIdx.x / G) * VPG;
     const int l = (int)threadIdx.x % G;
-    VoxDev d{0, 0, 0};
-    if (vi < n) d = vd[vi];
-    const int m = d.m;
-    float x = 0.0f;
-    if (m > 0) {
-        const float y = in[vedge[d.start + min(l, m - 1)]];
-        x = l < m ? y : 0.0f;
+    VoxDev d[VPG];
+#pragma unroll
+    for (int u = 0; u < VPG; ++u) d[u] = vd[min(v0 + u, n - 1)];   // past the list: a repeat, not stored
+    uint32_t e[VPG];
+    float x[VPG];
+#pragma unroll
+    for (int u = 0; u < VPG; ++u) e[u] = vedge[d[u].start + min(l, d[u].m - 1)];
+#pragma unroll
+    for (int u = 0; u < VPG; ++u) x[u] = in[e[u]];
+#pragma unroll
+    for (int u = 0; u < VPG; ++u) {
+        const float sum = drscan<G, OpAdd>(l < d[u].m ? x[u] : 0.0f);   // at group lane 0: the voxel's sum
+        if (l == 0 && v0 + u < n) vox_store(d[u].v, sum, base, tout, tacc);
     }
-    const float sum = drscan<G, OpAdd>(x);   // at group lane 0: the voxel's sum
-    if (l == 0 && m > 0) vox_store(d.v, sum, base, tout, tacc);
 }
 
 // One 1024-thread block per voxel of degree above the largest single-pass
-// class: wave w sums chunks w, w + 16, ... of 256 edges in order, and the 16
+// class: wave w sums pieces w, w + 16, ... of 1024 edges in order, and the 16
 // wave sums are added in wave order.
 __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict__ vd, int64_t n,
                                                         const uint32_t* __restrict__ vedge,
@@ -231,7 +285,7 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
     const VoxDev d = vd[b];
     const int nch = (d.m + kVoxChunk - 1) / kVoxChunk;
     float a = 0.0f;
-    for (int c = wv; c < nch; c += 16) a += vox_lane_sum<VIPL>(d.start, d.m, c * kVoxChunk, vedge, in);
+    for (int c = wv; c < nch; c += 16) a += vox_lane_sum<kVoxChunk / 64>(d.start, d.m, c * kVoxChunk, vedge, in);
     a = wave_sum(a);
     if (l == 0) wsum[wv] = a;
     __syncthreads();
@@ -252,13 +306,15 @@ static void launch_voxel_class(mrf_ctx* c, const float* base, const float* in, f
     constexpr int NW = kVoxNW[K];
     if constexpr (NW == 0) {
         constexpr int G = kVoxCap[K];
-        hipLaunchKernelGGL((voxel_small_k<G>), dim3(nblk(n, 256 / G)), dim3(256), 0, s,
+        constexpr int VPG = kVoxVPW[K];
+        hipLaunchKernelGGL((voxel_small_k<G, VPG>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s,
                            (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, tout,
                            tacc);
     } else {
         constexpr int IPL = kVoxCap[K] / (64 * NW);
-        const unsigned blocks = NW == 1 ? nblk(n, 4) : (unsigned)n;
-        hipLaunchKernelGGL((voxel_k<NW, IPL>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
+        constexpr int VPW = kVoxVPW[K];
+        const unsigned blocks = NW == 1 ? nblk(n, 4 * VPW) : (unsigned)n;
+        hipLaunchKernelGGL((voxel_k<NW, IPL, VPW>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
                            (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, tout,
                            tacc);
     }
