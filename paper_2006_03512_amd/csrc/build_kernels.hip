@@ -434,7 +434,12 @@ hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* 
 
 // ============================================================== radix sort
 
-constexpr int RS_T = 256, RS_IPT = 16, RS_TILE = RS_T * RS_IPT;
+#ifndef MRF_RS_T
+#define MRF_RS_T 256
+#define MRF_RS_IPT 32
+#endif
+constexpr int RS_T = MRF_RS_T, RS_IPT = MRF_RS_IPT, RS_TILE = RS_T * RS_IPT;
+static_assert(RS_T == 256 && RS_IPT % 4 == 0, "radix tile shape: one thread per digit");
 
 constexpr int RS_CB = 256;   // tiles per chunk of the digit-offset scan
 
@@ -468,7 +473,6 @@ __device__ __forceinline__ uint64_t rs_peers(int d, bool valid)
 __global__ __launch_bounds__(RS_T) void rs_hist_k(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                   int32_t* __restrict__ hist, int64_t nblocks)
 {
-    static_assert(RS_IPT == 16, "four 16-byte loads per thread");
     __shared__ int32_t h[256];
     h[threadIdx.x] = 0;
     const int64_t i0 = (int64_t)blockIdx.x * RS_TILE + (int64_t)threadIdx.x * RS_IPT;
@@ -476,7 +480,7 @@ __global__ __launch_bounds__(RS_T) void rs_hist_k(const uint32_t* __restrict__ k
     if (i0 + RS_IPT <= n) {
         const uint4* p = (const uint4*)(keys + i0);   // keys and RS_IPT * 4 bytes: 16-byte aligned
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < RS_IPT / 4; ++q) {
             const uint4 w = p[q];
             kr[4 * q] = w.x;
             kr[4 * q + 1] = w.y;
@@ -558,12 +562,16 @@ __global__ __launch_bounds__(256) void rs_offsets_k(const int32_t* __restrict__ 
     }
 }
 
-// Stable scatter of one tile of RS_TILE items.  Items are ranked in index order
-// among equal digits (wave ballots, waves in order, rounds in order) into an
-// LDS copy of the tile grouped by digit; the copy is then written out as
-// contiguous runs, one per digit, at the digit's global offset for this tile
-// (coalesced stores in place of scattered words).  hist and offs hold the
-// tile's digit counts and output offsets (tile-major rows of 256).
+// Stable scatter of one tile of RS_TILE items.  Wave w owns items
+// [w RS_IPT 64, (w + 1) RS_IPT 64) of the tile, RS_IPT rounds of 64; equal
+// digits inside a round are matched with wave ballots.  A first walk counts
+// each wave's digits, the per-wave bases follow in digit-major, wave-minor
+// order (index order, hence stable), and a second walk places every item in
+// an LDS copy of the tile grouped by digit: two barriers in all.  The copy is
+// then written out as contiguous runs, one per digit, at the digit's global
+// offset for this tile (coalesced stores in place of scattered words).  hist
+// and offs hold the tile's digit counts and output offsets (tile-major rows
+// of 256).
 __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict__ keys_in,
                                                      const uint32_t* __restrict__ vals_in, int64_t n,
                                                      int shift, const int32_t* __restrict__ hist,
@@ -571,18 +579,20 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ keys_out,
                                                      uint32_t* __restrict__ vals_out)
 {
+    constexpr int NW = RS_T / 64;
+    constexpr int WI = RS_IPT * 64;   // items per wave
     __shared__ uint32_t lk[RS_TILE];
     __shared__ uint32_t lv[RS_TILE];
     __shared__ int64_t boff[256];
     __shared__ int32_t dstart[256];
-    __shared__ int32_t run[256];
-    __shared__ int32_t wcnt[RS_T / 64][256];
+    __shared__ int32_t wcnt[NW][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t start = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t wstart = start + (int64_t)w * WI;
     uint32_t kr[RS_IPT], vr[RS_IPT];
 #pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
-        const int64_t i = start + (int64_t)r * RS_T + tid;
+        const int64_t i = wstart + r * 64 + lane;
         const int64_t ic = i < n ? i : n - 1;
         kr[r] = keys_in[ic];
         vr[r] = vals_in ? vals_in[ic] : (uint32_t)i;
@@ -590,37 +600,52 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
     const int64_t o0 = offs[(int64_t)blockIdx.x * 256 + tid];
     const int64_t cnt = hist[(int64_t)blockIdx.x * 256 + tid];
     boff[tid] = o0;
-    run[tid] = 0;
 #pragma unroll
-    for (int q = 0; q < RS_T / 64; ++q) wcnt[q][tid] = 0;
+    for (int q = 0; q < NW; ++q) wcnt[q][tid] = 0;
     int64_t total;
     dstart[tid] = (int32_t)block_excl_scan_i64(cnt, &total);   // synchronises the block
     const uint64_t below = lane ? ((~0ull) >> (64 - lane)) : 0ull;
-    for (int r = 0; r < RS_IPT; ++r) {
-        const bool valid = start + (int64_t)r * RS_T + tid < n;
-        const uint32_t key = kr[r];
-        const int d = (key >> shift) & 255;
-        const uint64_t peers = rs_peers(d, valid);
-        const int rank = __popcll(peers & below);
-        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int pre = run[d];
-            for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-            const int lp = dstart[d] + pre + rank;
-            lk[lp] = key;
-            lv[lp] = vr[r];
-        }
-        __syncthreads();
-        int add = 0;
+    // walk 1: digit counts of this wave (the lowest lane of each digit adds;
+    // the digits of one round are distinct, so no two lanes share an address).
+    // Each item keeps its rank among equal digits of its round and their
+    // count, packed as rank | count << 8 (both <= 64).
+    int rc[RS_IPT];
 #pragma unroll
-        for (int q = 0; q < RS_T / 64; ++q) {
-            add += wcnt[q][tid];
-            wcnt[q][tid] = 0;
-        }
-        run[tid] += add;
-        __syncthreads();
+    for (int r = 0; r < RS_IPT; ++r) {
+        const bool valid = wstart + r * 64 + lane < n;
+        const int d = (kr[r] >> shift) & 255;
+        const uint64_t peers = rs_peers(d, valid);
+        const int rank = __popcll(peers & below), num = __popcll(peers);
+        rc[r] = rank | (num << 8);
+        if (valid && rank == 0) wcnt[w][d] += num;
     }
+    __syncthreads();
+    {   // thread = digit: wave bases inside the tile's LDS copy
+        int acc = dstart[tid];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int t = wcnt[q][tid];
+            wcnt[q][tid] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+    // walk 2: place the items; a round's lanes read their digit's base before
+    // the lowest lane of each digit advances it (LDS operations of a wave
+    // complete in order)
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r) {
+        const bool valid = wstart + r * 64 + lane < n;
+        const int d = (kr[r] >> shift) & 255;
+        const int rank = rc[r] & 255;
+        const int b = wcnt[w][d];
+        if (valid) {
+            lk[b + rank] = kr[r];
+            lv[b + rank] = vr[r];
+        }
+        if (valid && rank == 0) wcnt[w][d] = b + (rc[r] >> 8);
+    }
+    __syncthreads();
     const int tn = (int)(n - start < RS_TILE ? n - start : RS_TILE);
     for (int j = tid; j < tn; j += RS_T) {
         const uint32_t key = lk[j];
