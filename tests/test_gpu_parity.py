@@ -195,6 +195,44 @@ def test_messages_extreme_prior_logodds(oracle, RayMRF):
     assert np.abs(p.cpu().numpy() - ref3.p).max() <= TOL_P
 
 
+@pytest.mark.parametrize("keep", [False, True])
+def test_messages_last_sweep(oracle, RayMRF, keep):
+    """After K = 4 sweeps (with and without checkpoints, which keep the
+    messages in different buffers): every voxel->ray message is the prior plus
+    the other rays' messages of sweep K-1 (Eq. node_to_factor, summed in FP64
+    from the exported sweep-(K-1) messages), and every ray->voxel message is
+    the oracle's single-ray Eqs. pos / neg on the exported sweep-K inputs."""
+    _say(f"[last sweep] fd K=4 keep={keep}")
+    sc = S.make_fd()
+    G = oracle.build_graph(sc)
+    th = sc.prior_logit().astype(np.float32)
+    sig = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
+    m = _gpu(RayMRF, sc, keep_chords=False)
+    m.infer(torch.from_numpy(th).cuda(), sig, 3, keep_checkpoints=keep)
+    ell3 = m.export_edges()["ell"].cpu().numpy().astype(np.float64)
+    m.infer(torch.from_numpy(th).cuda(), sig, 4, keep_checkpoints=keep)
+    e = {k: v.cpu().numpy().astype(np.float64) for k, v in m.export_edges().items() if k in ("lam", "ell", "g")}
+    # voxel phase: lam_e = theta_v + sum over the voxel's other edges of ell3
+    tot = th.astype(np.float64).copy()
+    np.add.at(tot, G.col, ell3)
+    mag = np.abs(th).astype(np.float64)
+    np.add.at(mag, G.col, np.abs(ell3))
+    want = tot[G.col] - ell3
+    err = np.abs(e["lam"] - want)
+    bound = 1e-5 * mag[G.col] + 1e-6
+    assert np.all(err <= bound), float((err / bound).max())
+    # ray phase on the GPU's own inputs
+    worst = 0.0
+    for r in range(G.row_ptr.shape[0] - 1):
+        a, b = int(G.row_ptr[r]), int(G.row_ptr[r + 1])
+        if b == a:
+            continue
+        ref = oracle.single_ray(e["lam"][a:b], e["g"][a:b])
+        bnd = 2e-4 * (1.0 + np.abs(ref)) + 1e-6 * np.abs(e["g"][a:b]).max()
+        worst = max(worst, float((np.abs(e["ell"][a:b] - ref) / bnd).max()))
+    assert worst <= 1.0, worst
+
+
 def test_determinism(RayMRF):
     sc = S.make_c2()
     m = _gpu(RayMRF, sc, keep_chords=False)
