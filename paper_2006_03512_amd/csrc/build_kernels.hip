@@ -11,6 +11,7 @@
 
 #include <algorithm>
 
+#include "dev_common.hpp"
 #include "mrf_internal.hpp"
 
 namespace mrf {
@@ -569,7 +570,9 @@ __global__ __launch_bounds__(256) void rs_offsets_k(const int32_t* __restrict__ 
 // order (index order, hence stable), and a second walk places every item in
 // an LDS copy of the tile grouped by digit: two barriers in all.  The copy is
 // then written out as contiguous runs, one per digit, at the digit's global
-// offset for this tile (coalesced stores in place of scattered words).  hist
+// offset for this tile (coalesced stores in place of scattered words).  Tile
+// t's run of a digit ends where tile t+1's begins, so consecutive tiles run on
+// one XCD (block remap) and their shared lines merge in its L2.  hist
 // and offs hold the tile's digit counts and output offsets (tile-major rows
 // of 256).
 __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict__ keys_in,
@@ -587,7 +590,8 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
     __shared__ int32_t dstart[256];
     __shared__ int32_t wcnt[NW][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t start = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+    const int64_t start = tile * RS_TILE;
     const int64_t wstart = start + (int64_t)w * WI;
     uint32_t kr[RS_IPT], vr[RS_IPT];
 #pragma unroll
@@ -597,8 +601,8 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
         kr[r] = keys_in[ic];
         vr[r] = vals_in ? vals_in[ic] : (uint32_t)i;
     }
-    const int64_t o0 = offs[(int64_t)blockIdx.x * 256 + tid];
-    const int64_t cnt = hist[(int64_t)blockIdx.x * 256 + tid];
+    const int64_t o0 = offs[tile * 256 + tid];
+    const int64_t cnt = hist[tile * 256 + tid];
     boff[tid] = o0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) wcnt[q][tid] = 0;
