@@ -72,8 +72,9 @@ __device__ __forceinline__ double face(const SceneDev& sd, int a, int idx)
     return sd.o[a] + (double)idx * sd.h;
 }
 
-// Walk voxels from ts to te; emit(k, id, tin, tout) for each chord of
-// positive length; ties between axes step the lowest axis.  Returns count.
+// Walk voxels from ts to te; emit(k, i, j, kz, tin, tout) for each chord of
+// positive length (voxel (i, j, kz)); ties between axes step the lowest axis.
+// Returns count.
 template <class Emit>
 __device__ int walk(const SceneDev& sd, const Ray& r, Emit emit)
 {
@@ -103,7 +104,7 @@ __device__ int walk(const SceneDev& sd, const Ray& r, Emit emit)
         const double tm = tmax[a];
         const double tout = tm < r.te ? tm : r.te;
         if (tout > tin) {
-            emit(k, idx[0] + sd.n[0] * (idx[1] + sd.n[1] * idx[2]), tin, tout);
+            emit(k, idx[0], idx[1], idx[2], tin, tout);
             ++k;
         }
         if (tm >= r.te) break;
@@ -119,7 +120,7 @@ __device__ int walk(const SceneDev& sd, const Ray& r, Emit emit)
 }
 
 struct NoEmit {
-    __device__ void operator()(int, int, double, double) const {}
+    __device__ void operator()(int, int, int, int, double, double) const {}
 };
 
 __global__ __launch_bounds__(256) void trace_count_k(const SceneDev* __restrict__ scenes,
@@ -155,16 +156,14 @@ struct EdgeEmit {
     int64_t base;
     int32_t vbase;
     double Z, dbin;
-    __device__ void operator()(int k, int id, double ti, double to) const
+    __device__ void operator()(int k, int vi, int vj, int vk, double ti, double to) const
     {
         const int64_t e = base + (int64_t)kTile * k;   // step k of this ray's tile lane
         const double d = (ti + to) * 0.5;   // voxel depth: chord midpoint
         double q = floor(d / dbin);
         if (q < 0.0) q = 0.0;
         if (q > 63.0) q = 63.0;
-        col[e] = vbase + id;
-        const int nxy = sd->n[0] * sd->n[1];
-        const int vk = id / nxy, rem = id - vk * nxy, vj = rem / sd->n[0], vi = rem - vj * sd->n[0];
+        col[e] = vbase + vi + sd->n[0] * (vj + sd->n[1] * vk);
         key[e] = brick_key(*sd, vi, vj, vk);
         delta[e] = (float)(Z - d);
         bin[e] = (uint8_t)q;
@@ -437,7 +436,7 @@ hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* 
 
 #ifndef MRF_RS_T
 #define MRF_RS_T 256
-#define MRF_RS_IPT 32
+#define MRF_RS_IPT 16
 #endif
 constexpr int RS_T = MRF_RS_T, RS_IPT = MRF_RS_IPT, RS_TILE = RS_T * RS_IPT;
 static_assert(RS_T == 256 && RS_IPT % 4 == 0, "radix tile shape: one thread per digit");
