@@ -179,9 +179,9 @@ int mrf_set_schedule(mrf_ctx* ctx, int32_t schedule);
  * `reps` eager forward sweeps (voxel phase, then ray phase) on the messages
  * of the last mrf_infer, and with include_backward != 0 also `reps` reverse
  * sweeps, recording a HIP event pair around every kernel launch on `stream`
- * (the stream the kernels run on).  Overwrites the context's message buffers
- * (marginals of the last inference are kept; run mrf_infer again before
- * mrf_backward).  Writes up to max_out entries, one per kernel that ran, and
+ * (the stream the kernels run on).  Writes only scratch buffers that
+ * mrf_backward initialises, so the last inference (messages, checkpoints,
+ * marginals) is kept.  Writes up to max_out entries, one per kernel that ran, and
  * the count to *n_out.  bytes_per_launch is the kernel's algorithmic HBM
  * traffic per launch (each per-edge and per-item array read or written once).
  * Errors: MRF_ESTATE before mrf_infer. */
