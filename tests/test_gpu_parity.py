@@ -248,6 +248,30 @@ def test_determinism(RayMRF):
         np.testing.assert_array_equal(a, b)
 
 
+def test_diagnostics_keep_inference_state(RayMRF):
+    """Profiling and autotuning between mrf_infer and mrf_backward write only
+    scratch buffers: messages, marginals and gradients equal those of a run
+    without them, bit for bit."""
+    sc = S.make_fd()
+    m = _gpu(RayMRF, sc, keep_chords=False)
+    th = torch.from_numpy(sc.prior_logit()).cuda()
+    sig = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
+    res = []
+    for diag in (False, True):
+        m.infer(th, sig, 5, keep_checkpoints=True)
+        if diag:
+            t0 = m.tuning()
+            m.profile_sweeps(2, include_backward=True)
+            m.autotune(1)
+            m.set_tuning(t0["fwd_sel"], t0["adj_sel"])   # same shapes, same rounding
+        p, lg = m.marginals()
+        e = m.export_edges()
+        dp, ds = m.backward((p - 0.5) / p.numel())
+        res.append([x.cpu().numpy().copy() for x in (lg, e["lam"], e["ell"], dp, ds)])
+    for a, b in zip(*res):
+        np.testing.assert_array_equal(a, b)
+
+
 def _grad_check(g, ref):
     g = np.asarray(g, np.float64)
     ref = np.asarray(ref, np.float64)
