@@ -68,17 +68,19 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
             q = lse(c[j], al[j] + q);
         }
     }
-    // ---- direct partials of ell_i = M1_i - M0_i (softmax weights)
+    // ---- direct partials of ell_i = M1_i - M0_i: the softmax weights of the
+    // two LSEs (M1 and M0 themselves are not needed)
     float Fd[IPL], Bb[IPL], lab[IPL], lbb[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const bool ok = i0 + j < m;
         const float e = ok ? eb[j] : 0.0f;
-        const float m1 = lse(R[j], gg[j]);
-        const float m0 = lse(R[j], Q[j]);
-        Fd[j] = ok ? e * (ex2(R[j] - m1) - ex2(R[j] - m0)) : 0.0f;
-        gb[j] = ok ? e * ex2(gg[j] - m1) : 0.0f;
-        Bb[j] = ok ? -e * ex2(Q[j] - m0) : 0.0f;
+        float wr1, wg1, wr0, wq0;
+        lse_weights(R[j], gg[j], wr1, wg1);
+        lse_weights(R[j], Q[j], wr0, wq0);
+        Fd[j] = ok ? e * (wr1 - wr0) : 0.0f;
+        gb[j] = ok ? e * wg1 : 0.0f;
+        Bb[j] = ok ? -e * wq0 : 0.0f;
         lab[j] = 0.0f;
         lbb[j] = 0.0f;
     }

@@ -30,6 +30,19 @@ __device__ __forceinline__ float lse(float a, float b)
     return fmaxf(a, b) + lg2(1.0f + ex2(-fabsf(a - b)));
 }
 
+// Softmax weights (2^(a - L), 2^(b - L)) of L = LSE(a, b): with t = 2^-|a-b|
+// the larger is 1 / (1 + t) and the smaller t / (1 + t) (no subtraction; two
+// transcendental operations where L and two exponentials take four).
+__device__ __forceinline__ void lse_weights(float a, float b, float& wa, float& wb)
+{
+    const float t = ex2(-fabsf(a - b));
+    const float big = __builtin_amdgcn_rcpf(1.0f + t);
+    const float small = t * big;
+    const bool ge = a >= b;
+    wa = ge ? big : small;
+    wb = ge ? small : big;
+}
+
 // LSE(r, x) - LSE(r, y) as (max(r, x) - max(r, y)) + (softplus differences): a
 // common dominant r cancels exactly instead of through rounded sums
 __device__ __forceinline__ float lse_diff(float r, float x, float y)
