@@ -48,8 +48,8 @@ constexpr RayShape kAdjShapes[kRayClasses][kNShapes] = {
     {{16, 1}},
     {{16, 1}, {32, 1}, {64, 1}},
     {{16, 1}, {32, 1}, {64, 1}, {64, 2}},
-    {{32, 1}, {64, 1}, {16, 1}, {64, 2}},
-    {{32, 1}, {64, 1}, {64, 2}, {32, 2}},
+    {{16, 1}, {32, 1}, {64, 1}, {64, 2}},
+    {{32, 2}, {32, 1}, {64, 1}, {64, 2}},
     {{64, 2}, {64, 1}, {32, 1}, {32, 2}},
     {{64, 2}, {64, 1}, {32, 1}},
     {{64, 1}, {64, 2}},
