@@ -110,6 +110,25 @@ def cpu_baseline(name, sc, sweeps, backward, row_frac):
                       f"({E} edges), {what}, FP64, {dt:.1f} s"}
 
 
+def copy_bandwidth(nbytes: int, reps: int = 5) -> float:
+    """GB/s (bytes read + written) of torch's device-to-device copy, best of reps."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2.0 * n * 4 / (best / 1e3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +257,11 @@ def main():
                 "forward_sweep_frac": round(fwd_bytes / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     kernels = [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4), "launches": k["launches"],
                 "GBs": round(k["bytes_per_launch"] / max(k["avg_ms"], 1e-9) / 1e6, 1)} for k in prof]
+    # achievable HBM bandwidth on this part: a plain 2 GiB device copy (read + write), HIP events
+    copy_gbs = copy_bandwidth(2 << 30)
+    roofline["copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(ach / copy_gbs, 4)
+    log(f"device copy: {copy_gbs:.0f} GB/s; dominant kernel at {ach / copy_gbs:.1%} of it")
 
     cpu = None
     if not args.no_cpu_baseline:
