@@ -284,16 +284,8 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int idx = (int)threadIdx.x + r * NT;
-        if (idx < nf) {
-            const int at = lds_at<IPL>(idx >> 4, idx & (kTile - 1));
-            const int64_t o = td.base + idx;
-            lambar[o] = sa[at];
-            gsum[o] = first ? sb[at] : vs[r] + sb[at];
-        }
-    }
+    tile_store<NT, NR, IPL>(lambar, td.base, nf, [&](int, int at) { return sa[at]; });
+    tile_store<NT, NR, IPL>(gsum, td.base, nf, [&](int r, int at) { return first ? sb[at] : vs[r] + sb[at]; });
 }
 
 template <int Q, int I>

@@ -472,11 +472,7 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
         ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, bool ok, float v) { sl[cb + kTile * j] = ok ? v : 0.0f; });
     }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < IPL; ++r) {
-        const int idx = (int)threadIdx.x + r * NT;
-        if (idx < nf) ell[td.base + idx] = sl[lds_at<IPL>(idx >> 4, idx & (kTile - 1))];
-    }
+    tile_store<NT, IPL, IPL>(ell, td.base, nf, [&](int, int at) { return sl[at]; });
 }
 
 template <int Q, int I>

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dev_common.hpp"
 #include "mrf_internal.hpp"
 
@@ -29,26 +31,77 @@ __device__ __forceinline__ int lds_col(int i0, int gl, int i)
 }
 
 // A block of NT threads moves a tile's nf = 16 len floats (nf <= NT NR) in NR
-// rounds: thread t handles idx = t + r NT.  Loads go through registers so
-// that every round's load is issued before the first wait; indices past nf are
-// clamped to the tile's last float (len >= 1) and their values dropped.
+// rounds.  With NR a multiple of 4, thread t handles four consecutive floats per
+// group of rounds, idx = 4 (t + q NT) + b for round r = 4 q + b (16-byte loads
+// and stores); otherwise idx = t + r NT.  Loads go through registers so that
+// every round's load is issued before the first wait; indices past nf are
+// clamped to the tile's last floats and their values dropped.  The tile starts
+// 64-byte aligned (tile bases are multiples of 16 slots).
+template <int NT, int NR>
+__device__ __forceinline__ int tile_idx(int r)
+{
+    if constexpr (NR % 4 == 0)
+        return 4 * ((int)threadIdx.x + (r >> 2) * NT) + (r & 3);
+    else
+        return (int)threadIdx.x + r * NT;
+}
+
+template <int NT, int NR, class T>
+__device__ __forceinline__ void tile_fetch_t(const T* __restrict__ src, int64_t base, int nf, T (&v)[NR])
+{
+    static_assert(sizeof(T) == 4, "32-bit items");
+    if constexpr (NR % 4 == 0) {
+        using V4 = typename std::conditional<std::is_same<T, float>::value, float4, int4>::type;
+        const V4* p = (const V4*)(src + base);
+        const int n4 = nf >> 2;
+#pragma unroll
+        for (int q = 0; q < NR / 4; ++q) {
+            const V4 w = p[min((int)threadIdx.x + q * NT, n4 - 1)];
+            v[4 * q] = w.x;
+            v[4 * q + 1] = w.y;
+            v[4 * q + 2] = w.z;
+            v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = src[base + min((int)threadIdx.x + r * NT, nf - 1)];
+    }
+}
+
 template <int NT, int NR>
 __device__ __forceinline__ void tile_fetch(const float* __restrict__ src, int64_t base, int nf, float (&v)[NR])
 {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int idx = min((int)threadIdx.x + r * NT, nf - 1);
-        v[r] = src[base + idx];
-    }
+    tile_fetch_t<NT, NR, float>(src, base, nf, v);
 }
 
 template <int NT, int NR>
 __device__ __forceinline__ void tile_fetch_i(const int32_t* __restrict__ src, int64_t base, int nf, int32_t (&v)[NR])
 {
+    tile_fetch_t<NT, NR, int32_t>(src, base, nf, v);
+}
+
+// Values of the LDS image (layout lds_at<IPL>) to global memory, in the
+// mapping of tile_idx: 16-byte stores when NR is a multiple of 4.
+template <int NT, int NR, int IPL, class F>
+__device__ __forceinline__ void tile_store(float* __restrict__ dst, int64_t base, int nf, F val)
+{
+    if constexpr (NR % 4 == 0) {
+        float4* p = (float4*)(dst + base);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int idx = min((int)threadIdx.x + r * NT, nf - 1);
-        v[r] = src[base + idx];
+        for (int q = 0; q < NR / 4; ++q) {
+            const int i4 = (int)threadIdx.x + q * NT;
+            if (4 * i4 < nf) {
+                const int k = i4 >> 2, l0 = (i4 & 3) << 2;
+                p[i4] = make_float4(val(4 * q, lds_at<IPL>(k, l0)), val(4 * q + 1, lds_at<IPL>(k, l0 + 1)),
+                                    val(4 * q + 2, lds_at<IPL>(k, l0 + 2)), val(4 * q + 3, lds_at<IPL>(k, l0 + 3)));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int idx = (int)threadIdx.x + r * NT;
+            if (idx < nf) dst[base + idx] = val(r, lds_at<IPL>(idx >> 4, idx & (kTile - 1)));
+        }
     }
 }
 
@@ -66,7 +119,7 @@ __device__ __forceinline__ void tile_to_lds(float* __restrict__ lds, int nf, con
 {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int idx = (int)threadIdx.x + r * NT;
+        const int idx = tile_idx<NT, NR>(r);
         if (idx < nf) lds[lds_at<IPL>(idx >> 4, idx & (kTile - 1))] = v[r];
     }
 }
