@@ -47,7 +47,7 @@ WORKLOADS = {
 # --calib-copy-mib, which calibrates the counter: FETCH_SIZE read 0.5 x the bytes
 # the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid only while the
 # kernel sources hash to `csrc_sha256`; otherwise traffic is reported as null.
-TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "0bde893897ee75afcf395ea02664e1ec6860a52d49e111e12dc562f7a175aff7",
+TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "579dad19b5101dfb8d970405c656a1997f2a321855f6291e2a6fc7d61e840f13",
            "fetch_bytes": 1.252e+10, "write_bytes": 4.666e+09}
 
 

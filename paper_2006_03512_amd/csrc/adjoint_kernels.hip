@@ -72,15 +72,14 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
     // two LSEs (M1 and M0 themselves are not needed)
     float Fd[IPL], Bb[IPL], lab[IPL], lbb[IPL];
 #pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        const bool ok = i0 + j < m;
-        const float e = ok ? eb[j] : 0.0f;
+    for (int j = 0; j < IPL; ++j) {   // weights are finite, so e = 0 past the ray zeroes all three
+        const float e = i0 + j < m ? eb[j] : 0.0f;
         float wr1, wg1, wr0, wq0;
         lse_weights(R[j], gg[j], wr1, wg1);
         lse_weights(R[j], Q[j], wr0, wq0);
-        Fd[j] = ok ? e * (wr1 - wr0) : 0.0f;
-        gb[j] = ok ? e * wg1 : 0.0f;
-        Bb[j] = ok ? -e * wq0 : 0.0f;
+        Fd[j] = e * (wr1 - wr0);
+        gb[j] = e * wg1;
+        Bb[j] = -e * wq0;
         lab[j] = 0.0f;
         lbb[j] = 0.0f;
     }
