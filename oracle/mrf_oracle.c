@@ -18,8 +18,10 @@
  *       share a voxel (Sec. III-A, Fig. "graphical model"), a stable counting
  *       sort of edges by voxel.
  *   or_potentials                   -- log of the forward sensor model
- *       nu(d_i) = N(Z; d_i, sigma(d_i)) (Eq. noise), sigma from a 64-bin
- *       depth-indexed table.
+ *       nu(d_i) = N(Z; d_i + b(d_i), sigma(d_i)) (Eq. noise with the learnt
+ *       bias of Sec. IV-C: the bias at the traversed depth gives the predicted
+ *       mean measurement, the noise its spread), sigma and b from 64-bin
+ *       depth-indexed tables (b = 0 when no bias table is given).
  *   or_infer                        -- flooding schedule of K sweeps; each
  *       sweep sends variable->factor messages (Eq. node_to_factor, including
  *       the prior factor, Eq. prior_potential) and then the ray-factor ->
@@ -261,15 +263,17 @@ void or_incidence(const int32_t* col, int64_t E, int64_t V, int64_t* vptr, int64
     free(fill);
 }
 
-/* g_e = log N(Z; d_e, sigma_b) = -(delta/sigma)^2/2 - log sigma - log(2 pi)/2 */
+/* g_e = log N(Z; d_e + mu_b, sigma_b) = -((delta - mu_b)/sigma_b)^2/2 - log sigma_b
+ * - log(2 pi)/2 with delta = Z - d_e; bias (mu, 64 entries) may be NULL for mu = 0. */
 void or_potentials(const double* delta, const int32_t* bin, int64_t E,
-                   const double* sigma, double* g)
+                   const double* sigma, const double* bias, double* g)
 {
     const double half_log_2pi = 0.5 * log(2.0 * M_PI);
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < E; ++e) {
         double s = sigma[bin[e]];
-        double x = delta[e] / s;
+        double mu = bias ? bias[bin[e]] : 0.0;
+        double x = (delta[e] - mu) / s;
         g[e] = -0.5 * x * x - log(s) - half_log_2pi;
     }
 }
@@ -477,12 +481,15 @@ static void or_ray_adjoint(int64_t n, const double* lam, const double* g, const 
 /* Reverse pass over K sweeps.  Inputs: the forward's lambda of every sweep
  * (lam_hist, K*E), g (E), and Lbar = d loss / d L (V).  Outputs:
  * d loss / d theta (V), d loss / d g accumulated over sweeps (gbar, E), and
- * d loss / d sigma_b (64) through g_e = log N(Z; d_e, sigma_b):
- *   d g / d sigma = delta^2 / sigma^3 - 1 / sigma. */
+ * d loss / d sigma_b and d loss / d mu_b (64 each) through
+ * g_e = log N(Z; d_e + mu_b, sigma_b), with r = Z - d_e - mu_b:
+ *   d g / d sigma = r^2 / sigma^3 - 1 / sigma,   d g / d mu = r / sigma^2.
+ * bias may be NULL (mu = 0); bias_bar may be NULL (not wanted). */
 void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
                  int64_t V, int64_t E, const double* g, int32_t K, const double* lam_hist,
                  const double* Lbar, const double* delta, const int32_t* bin,
-                 const double* sigma, double* theta_bar, double* gbar, double* sigma_bar)
+                 const double* sigma, const double* bias, double* theta_bar, double* gbar,
+                 double* sigma_bar, double* bias_bar)
 {
     double* ellbar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
     double* lambar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
@@ -514,10 +521,15 @@ void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const i
         }
         if (k > 0) or_voxel_phase(vptr, vedge, V, NULL, lambar, ellbar);
     }
-    for (int b = 0; b < 64; ++b) sigma_bar[b] = 0.0;
+    for (int b = 0; b < 64; ++b) {
+        sigma_bar[b] = 0.0;
+        if (bias_bar) bias_bar[b] = 0.0;
+    }
     for (int64_t e = 0; e < E; ++e) {
         double s = sigma[bin[e]];
-        sigma_bar[bin[e]] += gbar[e] * (delta[e] * delta[e] / (s * s * s) - 1.0 / s);
+        double r = delta[e] - (bias ? bias[bin[e]] : 0.0);
+        sigma_bar[bin[e]] += gbar[e] * (r * r / (s * s * s) - 1.0 / s);
+        if (bias_bar) bias_bar[bin[e]] += gbar[e] * (r / (s * s));
     }
     free(ellbar);
     free(lambar);

@@ -52,9 +52,9 @@ def lib():
         _lib.or_trace_count.argtypes = [P, I32, P, P, P]
         _lib.or_trace_emit.argtypes = [P, I32, P, P, P, P, P, P, P, P]
         _lib.or_incidence.argtypes = [P, I64, I64, P, P]
-        _lib.or_potentials.argtypes = [P, P, I64, P, P]
+        _lib.or_potentials.argtypes = [P, P, I64, P, P, P]
         _lib.or_infer.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P]
-        _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, P, P]
+        _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, P, P, P, P]
         _lib.or_single_ray.argtypes = [I64, P, P, P]
         _lib.or_single_ray_adjoint.argtypes = [I64, P, P, P, P, P]
         _lib.or_num_threads.restype = C.c_int
@@ -163,12 +163,17 @@ def build_graph(scenes) -> Graph:
                  ray_base, voxel_base)
 
 
-def potentials(graph: Graph, sigma_edge_table) -> np.ndarray:
-    """g_e for one 64-entry table, or per-scene tables given as a (S, 64) array
-    together with the scene of every edge (handled by the caller)."""
-    sig = np.ascontiguousarray(sigma_edge_table, np.float64)
+def _bias(bias_table):
+    return None if bias_table is None else np.ascontiguousarray(bias_table, np.float64)
+
+
+def potentials(graph: Graph, sigma_table, bias_table=None) -> np.ndarray:
+    """g_e = log N(Z; d_e + mu_b, sigma_b) for 64-entry sigma and bias tables
+    (no bias table: mu = 0)."""
+    sig = np.ascontiguousarray(sigma_table, np.float64)
+    mu = _bias(bias_table)
     g = np.empty(graph.n_edges)
-    lib().or_potentials(_p(graph.delta), _p(graph.bin), graph.n_edges, _p(sig), _p(g))
+    lib().or_potentials(_p(graph.delta), _p(graph.bin), graph.n_edges, _p(sig), _p(mu), _p(g))
     return g
 
 
@@ -186,10 +191,10 @@ class Result:
 
 
 def infer(graph: Graph, theta, sigma_table, sweeps: int, keep_history: bool = False,
-          g: np.ndarray | None = None) -> Result:
+          g: np.ndarray | None = None, bias_table=None) -> Result:
     theta = np.ascontiguousarray(theta, np.float64)
     if g is None:
-        g = potentials(graph, sigma_table)
+        g = potentials(graph, sigma_table, bias_table)
     E, V = graph.n_edges, graph.n_voxels
     lam, ell, L = np.empty(E), np.empty(E), np.empty(V)
     hist = np.empty((sweeps, E)) if keep_history else None
@@ -198,17 +203,21 @@ def infer(graph: Graph, theta, sigma_table, sweeps: int, keep_history: bool = Fa
     return Result(L, lam, ell, g, hist)
 
 
-def backward(graph: Graph, res: Result, Lbar, sigma_table):
-    """(d loss/d theta (V), d loss/d sigma (64), d loss/d g (E))."""
+def backward(graph: Graph, res: Result, Lbar, sigma_table, bias_table=None, want_bias: bool = False):
+    """(d loss/d theta (V), d loss/d sigma (64), d loss/d g (E)), and with
+    want_bias also d loss/d mu (64) appended.  bias_table must be the one the
+    forward used."""
     assert res.lam_hist is not None, "forward must keep its history"
     Lbar = np.ascontiguousarray(Lbar, np.float64)
     sig = np.ascontiguousarray(sigma_table, np.float64)
+    mu = _bias(bias_table)
     E, V = graph.n_edges, graph.n_voxels
     tb, gb, sb = np.empty(V), np.empty(E), np.empty(64)
+    bb = np.empty(64) if want_bias else None
     lib().or_backward(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
                       _p(res.g), res.lam_hist.shape[0], _p(res.lam_hist), _p(Lbar),
-                      _p(graph.delta), _p(graph.bin), _p(sig), _p(tb), _p(gb), _p(sb))
-    return tb, sb, gb
+                      _p(graph.delta), _p(graph.bin), _p(sig), _p(mu), _p(tb), _p(gb), _p(sb), _p(bb))
+    return (tb, sb, gb, bb) if want_bias else (tb, sb, gb)
 
 
 def single_ray(lam, g) -> np.ndarray:

@@ -193,6 +193,16 @@ def sigma_table(kind: str, dmax: float) -> np.ndarray:
     raise ValueError(kind)
 
 
+def bias_table(sigma: np.ndarray, seed: int) -> np.ndarray:
+    """64-bin depth bias table (metres) for a learnt sensor model: a smooth
+    trend of a quarter sigma that changes sign over the range, plus a seeded
+    tenth-of-sigma wobble per bin, so every bin carries its own value."""
+    rng = np.random.default_rng(seed)
+    sigma = np.asarray(sigma, np.float64)
+    trend = np.cos(np.linspace(0.0, np.pi, N_BINS))
+    return sigma * (0.25 * trend + 0.1 * rng.standard_normal(N_BINS))
+
+
 # --------------------------------------------------------------------------
 # noise
 # --------------------------------------------------------------------------

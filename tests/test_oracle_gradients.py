@@ -115,3 +115,56 @@ def test_bce_gradient_directional_fd(oracle):
     lm = oracle.bce_loss(oracle.infer(G, th - h * d, sc.sigma_table, sc.sweeps).L, y)
     fd = (lp - lm) / (2 * h)
     assert abs(fd - tb @ d) <= 1e-5 * abs(tb @ d)
+
+
+@pytest.fixture(scope="module")
+def fd_bias_setup(oracle):
+    """The FD instance with a nonzero bias table (Sec. IV-C), loss = sum_v w_v p_v."""
+    sc = S.make_fd()
+    G = oracle.build_graph(sc)
+    th = sc.prior_logit().astype(np.float64)
+    sig = sc.sigma_table.copy()
+    mu = S.bias_table(sig, seed=36)
+    w = np.random.default_rng(37).normal(size=th.shape)
+
+    def loss(sigma, bias):
+        return float(w @ oracle.infer(G, th, sigma, sc.sweeps, bias_table=bias).p)
+
+    res = oracle.infer(G, th, sig, sc.sweeps, keep_history=True, bias_table=mu)
+    p = res.p
+    tb, sb, gb, bb = oracle.backward(G, res, w * p * (1 - p), sig, mu, want_bias=True)
+    return G, sig, mu, loss, tb, sb, bb
+
+
+def test_bias_gradient_fd(fd_bias_setup):
+    G, sig, mu, loss, tb, sb, bb = fd_bias_setup
+    used = np.unique(G.bin)
+    big = np.argsort(-np.abs(bb))[:4]
+    assert np.max(np.abs(bb)) > 1e-3
+    for b in list(used[::3]) + list(big):
+        h = 1e-6 * sig[b]
+        e = np.zeros(64)
+        e[b] = h
+        fd = (loss(sig, mu + e) - loss(sig, mu - e)) / (2 * h)
+        # floor: FD round-off on bins whose gradient is 1e5 times below the largest
+        assert abs(fd - bb[b]) <= 1e-5 * abs(bb[b]) + 1e-8 * np.max(np.abs(bb)), (b, fd, bb[b])
+    unused = np.setdiff1d(np.arange(64), used)
+    np.testing.assert_array_equal(bb[unused], 0.0)
+    d = np.random.default_rng(38).normal(size=64) * sig
+    h = 1e-6
+    fd = (loss(sig, mu + h * d) - loss(sig, mu - h * d)) / (2 * h)
+    assert abs(fd - bb @ d) <= 1e-6 * abs(bb @ d) + 1e-9
+
+
+def test_sigma_gradient_with_bias_fd(fd_bias_setup):
+    """The sigma gradient takes the residual about the biased mean."""
+    G, sig, mu, loss, tb, sb, bb = fd_bias_setup
+    d = np.random.default_rng(39).normal(size=64) * sig
+    h = 1e-6
+    fd = (loss(sig + h * d, mu) - loss(sig - h * d, mu)) / (2 * h)
+    assert abs(fd - sb @ d) <= 1e-6 * abs(sb @ d) + 1e-9
+    for b in np.argsort(-np.abs(sb))[:3]:
+        e = np.zeros(64)
+        e[b] = 1e-6 * sig[b]
+        fd = (loss(sig + e, mu) - loss(sig - e, mu)) / (2 * e[b])
+        assert abs(fd - sb[b]) <= 1e-5 * abs(sb[b]) + 1e-9 / sig[b] * 1e-3, (b, fd, sb[b])

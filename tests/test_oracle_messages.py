@@ -220,3 +220,37 @@ def test_potentials_match_gaussian_logpdf(oracle):
     G = oracle.graph_from_rays([list(range(E))], E, delta=delta, bins=bins)
     g = oracle.potentials(G, sig)
     np.testing.assert_allclose(g, norm.logpdf(delta, loc=0.0, scale=sig[bins]), rtol=1e-12)
+
+
+def test_potentials_with_bias_match_gaussian_logpdf(oracle):
+    """Sec. IV-C: the bias at depth d predicts the mean measurement d + mu(d);
+    nu is the normal density of Z around it.  Z and d drawn separately, so a
+    flipped sign of mu or of delta fails."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(16)
+    E = 500
+    d = rng.uniform(0.3, 6.0, E)
+    Z = d + rng.normal(0, 0.05, E)
+    bins = rng.integers(0, 64, E).astype(np.int32)
+    sig = rng.uniform(1e-3, 0.2, 64)
+    mu = rng.normal(0, 0.03, 64)
+    G = oracle.graph_from_rays([list(range(E))], E, delta=Z - d, bins=bins)
+    g = oracle.potentials(G, sig, mu)
+    np.testing.assert_allclose(g, norm.logpdf(Z, loc=d + mu[bins], scale=sig[bins]), rtol=1e-12)
+    np.testing.assert_array_equal(oracle.potentials(G, sig, np.zeros(64)), oracle.potentials(G, sig))
+
+
+def test_constant_bias_is_a_shift_of_the_measurement(oracle):
+    """A bias c in every bin predicts Z - c where an unbiased model predicts Z:
+    the whole inference equals the unbiased one on measurements lowered by c."""
+    import dataclasses
+    from paper_2006_03512_amd import scenes as S
+    sc = S.make_fd()
+    G = oracle.build_graph(sc)
+    c = 0.013
+    Gs = dataclasses.replace(G, delta=G.delta - c)
+    th = sc.prior_logit()
+    a = oracle.infer(G, th, sc.sigma_table, sc.sweeps, bias_table=np.full(64, c))
+    b = oracle.infer(Gs, th, sc.sigma_table, sc.sweeps)
+    np.testing.assert_allclose(a.g, b.g, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(a.L, b.L, rtol=1e-9, atol=1e-9)
