@@ -47,7 +47,7 @@ WORKLOADS = {
 # --calib-copy-mib, which calibrates the counter: FETCH_SIZE read 0.5 x the bytes
 # the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid only while the
 # kernel sources hash to `csrc_sha256`; otherwise traffic is reported as null.
-TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "579dad19b5101dfb8d970405c656a1997f2a321855f6291e2a6fc7d61e840f13",
+TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "aefa3df29eb0d248622cf40303c849bb44b5876eb1aaa6c9fdc171f723a6a8cd",
            "fetch_bytes": 1.252e+10, "write_bytes": 4.666e+09}
 
 
@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--frames", type=int, default=None, help="override the batch size (c3/c4)")
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=float, default=0.25, help="fraction of frame-0 rows the oracle runs on")
+    ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of frame-0 rows the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing the candidates after warmup")
@@ -236,6 +236,18 @@ def main():
         bwd_ms = timed(lambda: m.backward(gl))
     log(f"build {build_ms:.1f} ms, forward graph {fwd_graph_ms:.1f} ms, plain {fwd_plain_ms:.1f} ms, "
         f"backward {bwd_ms}")
+    # the same sweeps with a learnt depth-bias table in the sensor model, and the
+    # reverse pass that also returns its gradient
+    from paper_2006_03512_amd import scenes as S
+    bias = torch.from_numpy(S.bias_table(sc.sigma_table, 7).astype(np.float32)).cuda()
+    fwd_bias_ms = timed(lambda: m.infer(theta, sigma, K, bias_table=bias))
+    bwd_bias_ms = None
+    if backward:
+        m.infer(theta, sigma, K, keep_checkpoints=True, bias_table=bias)
+        p, _ = m.marginals()
+        gl = (p - y) / p.numel()
+        bwd_bias_ms = timed(lambda: m.backward(gl, want_bias=True))
+    log(f"with a bias table: forward graph {fwd_bias_ms:.1f} ms, backward {bwd_bias_ms}")
 
     # ---- roofline of the dominant kernel (HIP events around each launch)
     m.infer(theta, sigma, K)
@@ -286,7 +298,9 @@ def main():
         "cpu_baseline": cpu,
         "breakdown_ms": {"build": round(build_ms, 2), "forward_graph": round(fwd_graph_ms, 2),
                          "forward_plain_per_frame": round(fwd_plain_ms, 2),
-                         "backward": None if bwd_ms is None else round(bwd_ms, 2)},
+                         "backward": None if bwd_ms is None else round(bwd_ms, 2),
+                         "forward_graph_with_bias": round(fwd_bias_ms, 2),
+                         "backward_with_bias_grad": None if bwd_bias_ms is None else round(bwd_bias_ms, 2)},
         "forward_updates_per_s": {"batched_graph": E * K / (fwd_graph_ms / 1e3),
                                   "plain_per_frame": E * K / (fwd_plain_ms / 1e3)},
         "kernels": kernels,

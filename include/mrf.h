@@ -132,6 +132,17 @@ int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
 int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
               int32_t sweeps, int32_t keep_checkpoints, void* stream);
 
+/* mrf_infer with the learnt sensor bias of Sec. IV-C: the bias b(d) at a
+ * traversed depth d gives the predicted mean measurement d + b(d), so the
+ * forward sensor model of Eq. noise becomes nu = N(Z; d + b(d), sigma(d)).
+ * bias_table: 64 floats [m] on the same depth bins as sigma_table (device,
+ * copied), or NULL for b = 0, which is mrf_infer exactly.  The incidence
+ * (truncation of every ray 3 sigma past its measurement) is fixed at build
+ * and does not depend on either table.  Errors as mrf_infer. */
+int mrf_infer_sensor(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
+                     const float* bias_table, int32_t sweeps, int32_t keep_checkpoints,
+                     void* stream);
+
 /* Marginals of the last mrf_infer (Sec. III-B: normalised product of all
  * factor messages into the voxel): logit_v = theta_v + sum of ray messages,
  * p_v = sigmoid(logit_v).  Either output may be NULL.  V floats each.
@@ -145,6 +156,15 @@ int mrf_marginals(mrf_ctx* ctx, float* p, float* logit, void* stream);
  * Deterministic: no floating-point atomics.  Errors: MRF_ESTATE. */
 int mrf_backward(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
                  float* dsigma_table, void* stream);
+
+/* mrf_backward that also returns dbias_table (64 floats, device; may be
+ * NULL), the gradient with respect to the bias table of the last inference
+ * (zero table after plain mrf_infer).  With r = Z - d - b the residual about
+ * the predicted mean, d g / d b = r / sigma^2 and d g / d sigma = r^2 / sigma^3
+ * - 1 / sigma, g = log nu.  Deterministic like mrf_backward; dprior_logit and
+ * dsigma_table are bit-identical to mrf_backward's.  Errors: MRF_ESTATE. */
+int mrf_backward_sensor(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
+                        float* dsigma_table, float* dbias_table, void* stream);
 
 /* Sizes and histograms of the built graph (host struct). */
 int mrf_stats(const mrf_ctx* ctx, mrf_stats_t* out);

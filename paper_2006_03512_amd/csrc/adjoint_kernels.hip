@@ -373,26 +373,36 @@ __device__ __forceinline__ void fx_add(unsigned long long* lo, long long* hi, do
     atomicAdd((unsigned long long*)hi, (unsigned long long)(h + carry));
 }
 
-// Every lane sums runs of equal bins over 16 consecutive slots in slot order
-// (double), and adds each run's sum to its bin in LDS as a 128-bit fixed-point
-// integer; each block then adds its 64 bins to the global accumulators.  The
-// partition of slots into lanes is fixed and integer sums do not depend on
-// order, so the result is bit-reproducible.  S is a multiple of 16 (16 slots
-// per tile step), so a lane's 16 slots are three 16-byte vector loads.
+// d loss / d sigma_b and, with BIAS, d loss / d mu_b: sums over the slots of
+// bin b of gbar_e times d g / d sigma = r^2 / sigma^3 - 1 / sigma and
+// d g / d mu = r / sigma^2, r = delta_e - mu_b the residual about the
+// predicted mean.  Every lane sums runs of equal bins over 16 consecutive slots
+// in slot order (double), and adds each run's sum to its bin in LDS as a
+// 128-bit fixed-point integer; each block then adds its 64 bins to the global
+// accumulators.  The partition of slots into lanes is fixed and integer sums
+// do not depend on order, so the result is bit-reproducible.  S is a multiple
+// of 16 (16 slots per tile step), so a lane's 16 slots are three 16-byte
+// vector loads.
+template <bool BIAS>
 __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gsum, const float* __restrict__ delta,
                                                     const uint8_t* __restrict__ bin, int64_t S,
-                                                    const float* __restrict__ sigma, unsigned long long* __restrict__ glo,
-                                                    long long* __restrict__ ghi)
+                                                    const float* __restrict__ sigma, const float* __restrict__ bias,
+                                                    unsigned long long* __restrict__ glo, long long* __restrict__ ghi)
 {
-    __shared__ unsigned long long slo[kBins];
-    __shared__ long long shi[kBins];
-    __shared__ double inv[kBins], inv3[kBins];
+    constexpr int NT = BIAS ? 2 : 1;   // accumulated tables: sigma, then bias
+    __shared__ unsigned long long slo[NT * kBins];
+    __shared__ long long shi[NT * kBins];
+    __shared__ double inv[kBins], inv2[kBins], inv3[kBins], mu[kBins];
     if (threadIdx.x < kBins) {
-        slo[threadIdx.x] = 0;
-        shi[threadIdx.x] = 0;
+        for (int t = 0; t < NT; ++t) {
+            slo[t * kBins + threadIdx.x] = 0;
+            shi[t * kBins + threadIdx.x] = 0;
+        }
         const double sg = (double)sigma[threadIdx.x];
         inv[threadIdx.x] = 1.0 / sg;
+        inv2[threadIdx.x] = 1.0 / (sg * sg);
         inv3[threadIdx.x] = 1.0 / (sg * sg * sg);
+        mu[threadIdx.x] = (double)bias[threadIdx.x];
     }
     __syncthreads();
     const int64_t nch = S / 16;
@@ -408,7 +418,7 @@ __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gs
         const uint4 bw = *(const uint4*)(bin + e0);
         const uint32_t bwords[4] = {bw.x, bw.y, bw.z, bw.w};
         int cur = -1;
-        double acc = 0.0;
+        double acc = 0.0, accb = 0.0;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int b = (int)((bwords[j >> 2] >> (8 * (j & 3))) & 255u);
@@ -417,54 +427,70 @@ __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gs
             const float dj = (j & 3) == 0 ? d4.x : (j & 3) == 1 ? d4.y : (j & 3) == 2 ? d4.z : d4.w;
             if (b >= kBins) continue;   // padding slots carry bin 255
             if (b != cur) {
-                if (cur >= 0) fx_add(&slo[cur], &shi[cur], acc);
+                if (cur >= 0) {
+                    fx_add(&slo[cur], &shi[cur], acc);
+                    if (BIAS) fx_add(&slo[kBins + cur], &shi[kBins + cur], accb);
+                }
                 cur = b;
                 acc = 0.0;
+                accb = 0.0;
             }
-            const double d = (double)dj;
-            acc += (double)gj * (d * d * inv3[b] - inv[b]);
+            const double r = (double)dj - mu[b];
+            acc += (double)gj * (r * r * inv3[b] - inv[b]);
+            if (BIAS) accb += (double)gj * (r * inv2[b]);
         }
-        if (cur >= 0) fx_add(&slo[cur], &shi[cur], acc);
+        if (cur >= 0) {
+            fx_add(&slo[cur], &shi[cur], acc);
+            if (BIAS) fx_add(&slo[kBins + cur], &shi[kBins + cur], accb);
+        }
     }
     __syncthreads();
-    if (threadIdx.x < kBins) {
-        const unsigned long long l = slo[threadIdx.x];
-        const long long h = shi[threadIdx.x];
-        const unsigned long long old = atomicAdd(&glo[threadIdx.x], l);
+    for (int i = threadIdx.x; i < NT * kBins; i += blockDim.x) {
+        const unsigned long long l = slo[i];
+        const long long h = shi[i];
+        const unsigned long long old = atomicAdd(&glo[i], l);
         const long long carry = (old + l < old) ? 1 : 0;
-        atomicAdd((unsigned long long*)&ghi[threadIdx.x], (unsigned long long)(h + carry));
+        atomicAdd((unsigned long long*)&ghi[i], (unsigned long long)(h + carry));
     }
 }
 
+// accumulators of the sigma and bias tables: glo[2 kBins] then ghi[2 kBins]
 __global__ void sigma_zero_k(unsigned long long* glo, long long* ghi)
 {
-    if (threadIdx.x < kBins) {
+    if (threadIdx.x < 2 * kBins) {
         glo[threadIdx.x] = 0;
         ghi[threadIdx.x] = 0;
     }
 }
 
-__global__ void sigma_final_k(const unsigned long long* glo, const long long* ghi, float* out)
+__global__ void sigma_final_k(const unsigned long long* glo, const long long* ghi, float* out, float* out_bias)
 {
-    if (threadIdx.x < kBins)
-        out[threadIdx.x] = (float)((double)ghi[threadIdx.x] + (double)glo[threadIdx.x] * 5.421010862427522e-20);
+    const int i = threadIdx.x;
+    const auto fx = [&](int k) { return (float)((double)ghi[k] + (double)glo[k] * 5.421010862427522e-20); };
+    if (i < kBins && out) out[i] = fx(i);
+    if (i < kBins && out_bias) out_bias[i] = fx(kBins + i);
 }
 
-hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s)
+hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_t s)
 {
     unsigned long long* glo = (unsigned long long*)c->b_sigpart.p;
-    long long* ghi = (long long*)(glo + kBins);
-    hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(64), 0, s, glo, ghi);
+    long long* ghi = (long long*)(glo + 2 * kBins);
+    hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(2 * kBins), 0, s, glo, ghi);
     if (c->S > 0) {
         ProfScope ps(c, KID_SIGMA, s);
         int64_t blocks = (c->S / 16 + 255) / 256;
         if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
-        hipLaunchKernelGGL(sigma_grad_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_gsum.p,
-                           (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p, c->S,
-                           (const float*)c->b_sigma.p, glo, ghi);
+        if (dbias)
+            hipLaunchKernelGGL(sigma_grad_k<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const float*)c->b_gsum.p, (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p,
+                               c->S, (const float*)c->b_sigma.p, (const float*)c->b_bias.p, glo, ghi);
+        else
+            hipLaunchKernelGGL(sigma_grad_k<false>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const float*)c->b_gsum.p, (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p,
+                               c->S, (const float*)c->b_sigma.p, (const float*)c->b_bias.p, glo, ghi);
     }
     hipLaunchKernelGGL(sigma_final_k, dim3(1), dim3(64), 0, s, (const unsigned long long*)glo, (const long long*)ghi,
-                       dsigma);
+                       dsigma, dbias);
     return hipGetLastError();
 }
 

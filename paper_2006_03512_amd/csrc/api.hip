@@ -52,7 +52,7 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->vox_cnt[i]);
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->fwd_sel[i]);
     const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_col,   &c->b_delta, &c->b_bin,  &c->b_g,    &c->b_lam,
-                                 &c->b_ell,    &c->b_vedge, &c->b_vptr,  &c->b_theta, &c->b_L,   &c->b_sigma,
+                                 &c->b_ell,    &c->b_vedge, &c->b_vptr,  &c->b_theta, &c->b_L,   &c->b_sigma, &c->b_bias,
                                  &c->b_ckpt,   &c->b_tsum,  &c->b_tbar,  &c->b_tiles, &c->b_counts};
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
     for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
@@ -191,7 +191,7 @@ void mrf_destroy(mrf_ctx* c)
     drop_graph(c);
     DevBuf* all[] = {&c->b_scenes, &c->b_frames, &c->b_counts, &c->b_rowptr, &c->b_col, &c->b_delta,
                      &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
-                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_ckpt, &c->b_tsum, &c->b_tbar,
+                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias, &c->b_ckpt, &c->b_tsum, &c->b_tbar,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
     for (DevBuf* b : all) free_buf(*b);
@@ -353,7 +353,8 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_thetabar, vb), "mrf_build: alloc thetabar");
     HCK(ensure(c->b_tbar, 2 * vb), "mrf_build: alloc voxel sums");
     HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
-    HCK(ensure(c->b_sigpart, sizeof(double) * 4 * kBins), "mrf_build: alloc sigma partials");
+    HCK(ensure(c->b_bias, sizeof(float) * kBins), "mrf_build: alloc bias");
+    HCK(ensure(c->b_sigpart, kSigPartBytes + sizeof(float) * kBins), "mrf_build: alloc table partials");
 
     // every slot is written: edges by the traversal, the rest as padding (no voxel,
     // no bin, sort key past every voxel)
@@ -407,6 +408,12 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
 int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, int32_t sweeps,
               int32_t keep_checkpoints, void* stream)
 {
+    return mrf_infer_sensor(c, prior_logit, sigma_table, nullptr, sweeps, keep_checkpoints, stream);
+}
+
+int mrf_infer_sensor(mrf_ctx* c, const float* prior_logit, const float* sigma_table, const float* bias_table,
+                     int32_t sweeps, int32_t keep_checkpoints, void* stream)
+{
     if (!c || !prior_logit || !sigma_table) return fail(MRF_EINVAL, "mrf_infer: null argument");
     if (!c->built) return fail(MRF_ESTATE, "mrf_infer: call mrf_build first");
     if (sweeps < 1) return fail(MRF_EINVAL, "mrf_infer: sweeps must be >= 1");
@@ -425,6 +432,10 @@ int mrf_infer(mrf_ctx* c, const float* prior_logit, const float* sigma_table, in
     }
     HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer: copy prior");
     HCK(launch_copy((float*)c->b_sigma.p, sigma_table, kBins, s), "mrf_infer: copy sigma");
+    if (bias_table)
+        HCK(launch_copy((float*)c->b_bias.p, bias_table, kBins, s), "mrf_infer: copy bias");
+    else
+        HCK(launch_fill((float*)c->b_bias.p, 0.0f, kBins, s), "mrf_infer: zero bias");
     if (c->schedule == MRF_SCHED_PLAIN) {
         HCK(enqueue_forward(c, sweeps, keep, true, s), "mrf_infer: sweeps");
     } else {
@@ -472,6 +483,11 @@ int mrf_marginals(mrf_ctx* c, float* p, float* logit, void* stream)
 
 int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, void* stream)
 {
+    return mrf_backward_sensor(c, dlogit, dprior, dsigma, nullptr, stream);
+}
+
+int mrf_backward_sensor(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, float* dbias, void* stream)
+{
     if (!c || !dlogit) return fail(MRF_EINVAL, "mrf_backward: null argument");
     if (!c->inferred || !c->have_ckpt)
         return fail(MRF_ESTATE, "mrf_backward: needs a preceding mrf_infer with keep_checkpoints");
@@ -495,7 +511,7 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
         eb = ExclSrc{tbar, lb};
     }
     HCK(e, "mrf_backward: sweeps");
-    if (dsigma) HCK(launch_sigma_grad(c, dsigma, s), "mrf_backward: sigma gradient");
+    if (dsigma || dbias) HCK(launch_sigma_grad(c, dsigma, dbias, s), "mrf_backward: sensor-table gradients");
     if (dprior) HCK(launch_copy(dprior, thetabar, c->V, s), "mrf_backward: copy");
     return MRF_OK;
 }
@@ -572,7 +588,7 @@ static std::string kid_name(const mrf_ctx* c, int k)
         return ray_name("ray_adj_k", "ray_adj_lds_k", q, kAdjShapes[q][c->adj_sel[q]], true);
     }
     if (k == KID_POT) return "potentials_k";
-    if (k == KID_SIGMA) return "sigma_grad_k";
+    if (k == KID_SIGMA) return "sigma_grad_k<false>";   // the profile asks for no bias gradient
     return "?";
 }
 
@@ -632,7 +648,8 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
             if (e == hipSuccess)
                 e = launch_voxel_phase(c, nullptr, lambar, vt + c->V, (float*)c->b_thetabar.p, s);
         }
-        if (e == hipSuccess) e = launch_sigma_grad(c, (float*)c->b_sigpart.p + 4 * kBins, s);
+        if (e == hipSuccess)
+            e = launch_sigma_grad(c, (float*)((char*)c->b_sigpart.p + kSigPartBytes), nullptr, s);
     }
     c->prof = nullptr;
     if (e == hipSuccess) e = hipStreamSynchronize(s);

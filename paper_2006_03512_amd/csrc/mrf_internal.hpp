@@ -239,7 +239,7 @@ struct mrf_ctx {
 
     // buffers (raw device pointers into `bufs`)
     mrf::DevBuf b_scenes, b_frames, b_counts, b_rowptr, b_col, b_delta, b_bin, b_tin, b_tout,
-        b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_ckpt,
+        b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_bias, b_ckpt,
         b_ellbar, b_lambar, b_gsum, b_tmp64, b_cls, b_sigpart, b_misc;
     mrf::DevBuf b_tiles, b_tbase;
     mrf::DevBuf b_tsum;   // per-voxel totals of the sweeps (theta + incoming ray messages)
@@ -347,6 +347,10 @@ hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
 // adjoint_kernels.hip
 hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* lambar, float* gsum, bool first,
                               hipStream_t s);
-hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, hipStream_t s);
+// d loss / d sigma (64) and, when dbias is not null, d loss / d bias (64) from
+// the accumulated d loss / d g; b_sigpart holds the 2 x 2 x 64 fixed-point
+// accumulators (kSigPartBytes), scratch past them is free for callers.
+constexpr size_t kSigPartBytes = sizeof(double) * 4 * kBins;
+hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_t s);
 
 }  // namespace mrf

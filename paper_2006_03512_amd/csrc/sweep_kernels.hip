@@ -63,18 +63,22 @@ __global__ void sigmoid_k(const float* __restrict__ L, float* __restrict__ p, in
         p[i] = 1.0f / (1.0f + __expf(-L[i]));
 }
 
-// g_e = -(delta_e / sigma_b)^2 / 2 - log sigma_b - log(2 pi) / 2.  One thread
+// g_e = log N(Z; d_e + mu_b, sigma_b) = -((delta_e - mu_b) / sigma_b)^2 / 2 -
+// log sigma_b - log(2 pi) / 2, delta_e = Z - d_e, mu_b the learnt depth bias
+// (the predicted mean measurement at depth d is d + mu(d)).  One thread
 // per 16 consecutive slots (S is a multiple of 16: one tile step): 16-byte
 // loads of delta and bin, 16-byte stores of g; padding slots (bin 255) are
 // left as they are.
 __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ delta, const uint8_t* __restrict__ bin,
-                                                    int64_t S, const float* __restrict__ sigma, float* __restrict__ g)
+                                                    int64_t S, const float* __restrict__ sigma,
+                                                    const float* __restrict__ bias, float* __restrict__ g)
 {
-    __shared__ float inv[kBins], cst[kBins];
+    __shared__ float inv[kBins], cst[kBins], mu[kBins];
     if (threadIdx.x < kBins) {
         const float s = sigma[threadIdx.x];
         inv[threadIdx.x] = 1.0f / s;
         cst[threadIdx.x] = logf(s) + 0.91893853320467274f;
+        mu[threadIdx.x] = bias[threadIdx.x];
     }
     __syncthreads();
     const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ de
         const float4 d4 = dv[j >> 2];
         const float dj = (j & 3) == 0 ? d4.x : (j & 3) == 1 ? d4.y : (j & 3) == 2 ? d4.z : d4.w;
         const int bb = b < kBins ? b : 0;
-        const float x = dj * inv[bb];
+        const float x = (dj - mu[bb]) * inv[bb];   // residual about the predicted mean d + mu
         out[j] = -0.5f * x * x - cst[bb];
         all = all && b < kBins;
     }
@@ -148,7 +152,8 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
     if (c->S <= 0) return hipSuccess;
     ProfScope ps(c, KID_POT, s);
     hipLaunchKernelGGL(potentials_k, dim3(nblk(c->S / 16, 256)), dim3(256), 0, s, (const float*)c->b_delta.p,
-                       (const uint8_t*)c->b_bin.p, c->S, (const float*)c->b_sigma.p, (float*)c->b_g.p);
+                       (const uint8_t*)c->b_bin.p, c->S, (const float*)c->b_sigma.p,
+                       (const float*)c->b_bias.p, (float*)c->b_g.p);
     return hipGetLastError();
 }
 

@@ -141,11 +141,20 @@ class RayMRF:
             raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} elements")
         return x
 
-    def infer(self, prior_logit, sigma_table, sweeps: int, keep_checkpoints: bool = False, stream=None):
+    def infer(self, prior_logit, sigma_table, sweeps: int, keep_checkpoints: bool = False, stream=None,
+              bias_table=None):
+        """K sweeps; bias_table (64, metres) is the learnt depth bias of the
+        sensor model (None: zero bias, the plain ``mrf_infer``)."""
         self._vec(prior_logit, self.n_voxels, "prior_logit")
         self._vec(sigma_table, N_BINS, "sigma_table")
-        check(self._L.mrf_infer(self._h, ptr(prior_logit), ptr(sigma_table), int(sweeps),
-                                1 if keep_checkpoints else 0, stream_handle(stream)), "mrf_infer")
+        keep = 1 if keep_checkpoints else 0
+        if bias_table is None:
+            check(self._L.mrf_infer(self._h, ptr(prior_logit), ptr(sigma_table), int(sweeps), keep,
+                                    stream_handle(stream)), "mrf_infer")
+        else:
+            self._vec(bias_table, N_BINS, "bias_table")
+            check(self._L.mrf_infer_sensor(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
+                                           int(sweeps), keep, stream_handle(stream)), "mrf_infer_sensor")
 
     def marginals(self, stream=None):
         p = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device)
@@ -153,13 +162,20 @@ class RayMRF:
         check(self._L.mrf_marginals(self._h, ptr(p), ptr(logit), stream_handle(stream)), "mrf_marginals")
         return p, logit
 
-    def backward(self, dloss_dlogit, want_prior=True, want_sigma=True, stream=None):
+    def backward(self, dloss_dlogit, want_prior=True, want_sigma=True, stream=None, want_bias=False):
+        """(d loss/d prior, d loss/d sigma), with want_bias also d loss/d bias
+        appended; an output not wanted is None."""
         self._vec(dloss_dlogit, self.n_voxels, "dloss_dlogit")
         dp = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device) if want_prior else None
         ds = torch.empty(N_BINS, dtype=torch.float32, device=self.device) if want_sigma else None
-        check(self._L.mrf_backward(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), stream_handle(stream)),
-              "mrf_backward")
-        return dp, ds
+        if not want_bias:
+            check(self._L.mrf_backward(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), stream_handle(stream)),
+                  "mrf_backward")
+            return dp, ds
+        db = torch.empty(N_BINS, dtype=torch.float32, device=self.device)
+        check(self._L.mrf_backward_sensor(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), ptr(db),
+                                          stream_handle(stream)), "mrf_backward_sensor")
+        return dp, ds, db
 
     # ------------------------------------------------------------------
     def export_incidence(self, stream=None):
@@ -234,23 +250,27 @@ class RayMRF:
 
 
 class MRFInfer(torch.autograd.Function):
-    """logit = MRFInfer.apply(mrf, prior_logit, sigma_table, sweeps)
+    """logit = MRFInfer.apply(mrf, prior_logit, sigma_table, sweeps[, bias_table])
 
     Forward runs ``sweeps`` BP sweeps keeping per-sweep checkpoints and returns
     the marginal log-odds; backward runs the library's reverse pass and
-    returns gradients for the prior log-odds and the 64-bin sigma table.
+    returns gradients for the prior log-odds, the 64-bin sigma table and, when
+    given, the 64-bin depth-bias table of the sensor model.
     """
 
     @staticmethod
-    def forward(ctx, mrf: RayMRF, prior_logit, sigma_table, sweeps: int):
+    def forward(ctx, mrf: RayMRF, prior_logit, sigma_table, sweeps: int, bias_table=None):
         mrf.infer(prior_logit.detach().contiguous(), sigma_table.detach().contiguous(), sweeps,
-                  keep_checkpoints=True)
+                  keep_checkpoints=True,
+                  bias_table=None if bias_table is None else bias_table.detach().contiguous())
         _, logit = mrf.marginals()
         ctx.mrf = mrf
+        ctx.has_bias = bias_table is not None
         return logit
 
     @staticmethod
     def backward(ctx, g):
-        dp, ds = ctx.mrf.backward(g.contiguous().float(), want_prior=ctx.needs_input_grad[1],
-                                  want_sigma=ctx.needs_input_grad[2])
-        return None, dp, ds, None
+        want_bias = ctx.has_bias and ctx.needs_input_grad[4]
+        out = ctx.mrf.backward(g.contiguous().float(), want_prior=ctx.needs_input_grad[1],
+                               want_sigma=ctx.needs_input_grad[2], want_bias=want_bias)
+        return None, out[0], out[1], None, (out[2] if want_bias else None)
