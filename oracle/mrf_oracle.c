@@ -29,6 +29,10 @@
  *       division-free form of the second sum of Eq. neg (supplement, Sec. II-C,
  *       the sum over j > i of the product over k < j, k != i).  Marginals are
  *       the normalised product of all incoming factor messages (Sec. III-B).
+ *   or_accuracy                     -- the accuracy metric of a map
+ *       (Sec. III-D): visibility and generating-surface density along each
+ *       depth ray through voxels of constant occlusion density, the
+ *       measurement checked against the most likely surface.
  *   or_backward                     -- reverse-mode derivative of the K
  *       unrolled sweeps (not in the paper: a project extension), written from
  *       the chain rule on the forward steps above.
@@ -88,10 +92,11 @@ typedef struct {
 } or_ray;
 
 /* The ray of pixel (u, v) of frame f: origin = camera centre, direction =
- * R (x_n, y_n, 1) so the ray parameter is z-depth.  Returns 0 when the pixel
- * carries no usable measurement or the ray misses the grid. */
-static int or_make_ray(const or_cfg* g, const float* depth, const double* T,
-                       int v, int u, or_ray* r)
+ * R (x_n, y_n, 1) so the ray parameter is z-depth, clipped to the grid box:
+ * [*ts, *texit].  Returns 0 when the pixel carries no usable measurement or
+ * the ray misses the grid. */
+static int or_clip_ray(const or_cfg* g, const float* depth, const double* T,
+                       int v, int u, or_ray* r, double* ts_out, double* texit_out)
 {
     double Z = (double)depth[(int64_t)v * g->width + u];
     if (!isfinite(Z) || Z < g->z_min || Z > g->z_max) return 0;
@@ -119,6 +124,21 @@ static int or_make_ray(const or_cfg* g, const float* depth, const double* T,
             return 0;
         }
     }
+    r->Z = Z;
+    *ts_out = ts;
+    *texit_out = texit;
+    return 1;
+}
+
+/* The graph's ray of a pixel: the clipped ray, kept only when the surface
+ * lies inside the grid, walked from the grid entry to 3 sigma_tr past the
+ * measurement (Sec. IV-B) or the grid exit. */
+static int or_make_ray(const or_cfg* g, const float* depth, const double* T,
+                       int v, int u, or_ray* r)
+{
+    double ts, texit;
+    if (!or_clip_ray(g, depth, T, v, u, r, &ts, &texit)) return 0;
+    double Z = r->Z;
     /* the surface must lie inside the grid */
     if (Z >= texit) return 0;
     double sig = g->trunc_c2 * Z;
@@ -128,7 +148,6 @@ static int or_make_ray(const or_cfg* g, const float* depth, const double* T,
     double te = Z + g->trunc_nsigma * sig;
     if (te > texit) te = texit;
     if (te <= ts) return 0;
-    r->Z = Z;
     r->ts = ts;
     r->te = te;
     return 1;
@@ -533,6 +552,100 @@ void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const i
     }
     free(ellbar);
     free(lambar);
+}
+
+/* ------------------------------------------------------------------ */
+/* accuracy metric of a map (Sec. III-D)                               */
+/* ------------------------------------------------------------------ */
+
+/* Each voxel is a region of constant occlusion density alpha; a ray that
+ * crosses the voxel's side h is blocked with the voxel's occupancy
+ * probability p, so alpha = -ln(1 - p) / h = softplus(L) / h for log-odds L.
+ * Along the ray (Euclidean distance s) vis(s) = exp(-integral of alpha) and
+ * the density of the generating surface is omega(s) = alpha(s) vis(s); inside
+ * a voxel it decays, so its maximum over the ray is at the entry of the voxel
+ * maximising log alpha_n - sum_{i<n} alpha_i l_i (the first such voxel on
+ * ties). */
+typedef struct {
+    const double* L;
+    double inv_h, wn;
+    double acc;              /* sum of alpha_i l_i over the voxels walked */
+    double best, second;     /* largest and second largest log omega at an entry */
+    double btin, btout;      /* chord of the best voxel (z-depth) */
+} or_metric_ud;
+
+static void or_metric_emit(void* p, int64_t k, int32_t id, double tin, double tout)
+{
+    (void)k;
+    or_metric_ud* m = (or_metric_ud*)p;
+    double alpha = or_softplus(m->L[id]) * m->inv_h;
+    double lw = log(alpha) - m->acc;
+    if (lw > m->best) {
+        m->second = m->best;
+        m->best = lw;
+        m->btin = tin;
+        m->btout = tout;
+    } else if (lw > m->second) {
+        m->second = lw;
+    }
+    m->acc += alpha * ((tout - tin) * m->wn);
+}
+
+/* Accuracy of every depth ray of one scene against the map L (V log-odds,
+ * scene-local ids).  A ray is walked over the whole grid (no truncation; the
+ * surface may lie beyond it).  When the visibility at the grid exit is at
+ * least vis_min the map has not blocked the ray enough and the ray counts as
+ * accurate iff its measurement lies beyond the exit (Z > exit z-depth);
+ * otherwise iff the measurement lies inside the chord of the voxel where the
+ * most likely generating surface is.  Per ray (r = (f H + v) W + u):
+ *   code   1 accurate, 0 not, -1 not evaluated (no usable measurement, or the
+ *          ray misses the grid);
+ *   tin, tout  chord of the chosen voxel, or (exit, +inf) for the beyond rule;
+ *   lvis   log visibility at the grid exit;
+ *   margin distance of the decision from a tie: the smaller of (best - second
+ *          best log omega) and |lvis - log vis_min| (+inf when neither exists). */
+void or_accuracy(const or_cfg* g, int32_t n_frames, const float* depth, const double* T_wc,
+                 const double* L, double vis_min, int8_t* code, double* tin, double* tout,
+                 double* lvis, double* margin)
+{
+    const int64_t HW = (int64_t)g->width * g->height;
+    const int64_t R = HW * n_frames;
+    const double lvmin = log(vis_min);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t f = r / HW, pix = r % HW;
+        int v = (int)(pix / g->width), u = (int)(pix % g->width);
+        or_ray ray;
+        double ts, texit;
+        code[r] = -1;
+        tin[r] = tout[r] = lvis[r] = margin[r] = NAN;
+        if (!or_clip_ray(g, depth + f * HW, T_wc + 16 * f, v, u, &ray, &ts, &texit)) continue;
+        if (!(ts < texit)) continue;
+        ray.ts = ts;
+        ray.te = texit;
+        or_metric_ud m;
+        m.L = L;
+        m.inv_h = 1.0 / g->h;
+        m.wn = sqrt(ray.w[0] * ray.w[0] + ray.w[1] * ray.w[1] + ray.w[2] * ray.w[2]);
+        m.acc = 0.0;
+        m.best = m.second = -INFINITY;
+        m.btin = m.btout = NAN;
+        or_walk(g, &ray, or_metric_emit, &m);
+        double lv = -m.acc;
+        double gap = m.best > -INFINITY && m.second > -INFINITY ? m.best - m.second : INFINITY;
+        double vgap = fabs(lv - lvmin);
+        lvis[r] = lv;
+        margin[r] = gap < vgap ? gap : vgap;
+        if (lv >= lvmin) {
+            code[r] = ray.Z > texit ? 1 : 0;
+            tin[r] = texit;
+            tout[r] = INFINITY;
+        } else {
+            code[r] = (m.btin <= ray.Z && ray.Z < m.btout) ? 1 : 0;
+            tin[r] = m.btin;
+            tout[r] = m.btout;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */

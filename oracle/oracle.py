@@ -56,6 +56,7 @@ def lib():
         _lib.or_infer.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P]
         _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, P, P, P, P]
         _lib.or_single_ray.argtypes = [I64, P, P, P]
+        _lib.or_accuracy.argtypes = [P, I32, P, P, P, C.c_double, P, P, P, P, P]
         _lib.or_single_ray_adjoint.argtypes = [I64, P, P, P, P, P]
         _lib.or_num_threads.restype = C.c_int
         _lib.or_set_threads.argtypes = [C.c_int]
@@ -235,6 +236,26 @@ def single_ray_adjoint(lam, g, ellbar):
     lb, gb = np.empty_like(lam), np.empty_like(lam)
     lib().or_single_ray_adjoint(lam.shape[0], _p(lam), _p(g), _p(eb), _p(lb), _p(gb))
     return lb, gb
+
+
+def accuracy(scene, L, vis_min: float = 0.5) -> dict:
+    """Sec. III-D accuracy of every depth ray of one scene against the map L
+    (log-odds of the scene's V voxels): per ray code (1 accurate, 0 not, -1
+    not evaluated), the chosen voxel's chord t_in/t_out (z-depth; (exit, inf)
+    when the surface is taken to lie beyond the map), log visibility at the
+    grid exit and the decision's margin from a tie."""
+    cfg = _cfg(scene)
+    depth = np.ascontiguousarray(scene.depth, np.float32)
+    T = np.ascontiguousarray(scene.T_wc, np.float64)
+    Lm = np.ascontiguousarray(L, np.float64)
+    assert Lm.shape == (scene.grid.n_voxels,)
+    R = depth.size
+    out = {"code": np.empty(R, np.int8), "t_in": np.empty(R), "t_out": np.empty(R),
+           "lvis": np.empty(R), "margin": np.empty(R)}
+    lib().or_accuracy(C.byref(cfg), scene.n_frames, _p(depth), _p(T), _p(Lm), float(vis_min),
+                      _p(out["code"]), _p(out["t_in"]), _p(out["t_out"]), _p(out["lvis"]),
+                      _p(out["margin"]))
+    return out
 
 
 def bce_logit_grad(L, y) -> np.ndarray:
