@@ -77,16 +77,16 @@ def make_scene(name, frames=None, c5_scale=0.4):
     return [scenes.make(name)]
 
 
-def cpu_baseline(name, sc, sweeps, backward, row_frac):
-    """The FP64 oracle on a bounded sample of the same workload: the first
-    frame of the batch, restricted to a band of its pixel rows (the other
+def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=2):
+    """The FP64 oracle on a bounded sample of the same workload: the first nf
+    frames of the batch, restricted to a band of their pixel rows (the other
     pixels carry no measurement)."""
     import numpy as np
 
     from oracle import oracle
     from paper_2006_03512_amd import scenes as S
 
-    nf = 1
+    nf = max(1, min(nf, sc.n_frames))
     depth = sc.depth[:nf].copy()
     H = depth.shape[1]
     keep = max(1, int(round(H * row_frac)))
@@ -106,7 +106,7 @@ def cpu_baseline(name, sc, sweeps, backward, row_frac):
     E = G.n_edges
     what = "build + %d sweeps%s" % (sweeps, " + reverse pass" if backward else "")
     return {"value": E * sweeps / dt, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"rows {r0}..{r0 + keep - 1} of frame 0 of the {sc.n_frames}-frame {name} batch "
+            "sample": f"rows {r0}..{r0 + keep - 1} of frames 0..{nf - 1} of the {sc.n_frames}-frame {name} batch "
                       f"({E} edges), {what}, FP64, {dt:.1f} s"}
 
 
@@ -138,7 +138,8 @@ def main():
     ap.add_argument("--frames", type=int, default=None, help="override the batch size (c3/c4)")
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of frame-0 rows the oracle runs on")
+    ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of the sampled frames' rows the oracle runs on")
+    ap.add_argument("--cpu-frames", type=int, default=2, help="frames of the batch the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing the candidates after warmup")
@@ -248,6 +249,12 @@ def main():
         gl = (p - y) / p.numel()
         bwd_bias_ms = timed(lambda: m.backward(gl, want_bias=True))
     log(f"with a bias table: forward graph {fwd_bias_ms:.1f} ms, backward {bwd_bias_ms}")
+    # the accuracy metric of the inferred map over every pixel of the batch
+    m.infer(theta, sigma, K)
+    acc_ms = timed(lambda: m.accuracy())
+    acc = m.accuracy()
+    acc_counts = acc["counts"].cpu().numpy().sum(0).tolist()
+    log(f"accuracy metric: {acc_ms:.1f} ms, {acc_counts[1]} of {acc_counts[0]} rays accurate")
 
     # ---- roofline of the dominant kernel (HIP events around each launch)
     m.infer(theta, sigma, K)
@@ -278,7 +285,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(args.workload, sc, K, backward, args.cpu_rows)
+        cpu = cpu_baseline(args.workload, sc, K, backward, args.cpu_rows, args.cpu_frames)
         log(f"cpu baseline: {cpu['value']:.3e} {UNIT} on {cpu['cores']} threads")
 
     line = {
@@ -300,7 +307,10 @@ def main():
                          "forward_plain_per_frame": round(fwd_plain_ms, 2),
                          "backward": None if bwd_ms is None else round(bwd_ms, 2),
                          "forward_graph_with_bias": round(fwd_bias_ms, 2),
-                         "backward_with_bias_grad": None if bwd_bias_ms is None else round(bwd_bias_ms, 2)},
+                         "backward_with_bias_grad": None if bwd_bias_ms is None else round(bwd_bias_ms, 2),
+                         "accuracy_metric": round(acc_ms, 2)},
+        "map_accuracy": {"evaluated_rays": acc_counts[0], "accurate_rays": acc_counts[1],
+                         "fraction": acc_counts[1] / max(acc_counts[0], 1), "vis_min": 0.5},
         "forward_updates_per_s": {"batched_graph": E * K / (fwd_graph_ms / 1e3),
                                   "plain_per_frame": E * K / (fwd_plain_ms / 1e3)},
         "kernels": kernels,

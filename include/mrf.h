@@ -166,6 +166,32 @@ int mrf_backward(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
 int mrf_backward_sensor(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
                         float* dsigma_table, float* dbias_table, void* stream);
 
+/* The accuracy metric of Sec. III-D for a map: every pixel of the scenes of
+ * the last mrf_build with a usable measurement (z_min <= Z <= z_max) whose ray
+ * meets the grid is walked through the whole grid (3D-DDA, no truncation).
+ * A voxel is a region of constant occlusion density alpha = -ln(1 - p) / h
+ * (= softplus(logit) / h: crossing one voxel side blocks the ray with the
+ * voxel's occupancy probability p); along the ray vis(s) = exp(-integral of
+ * alpha ds) and the generating surface has density omega = alpha vis, largest
+ * at the entry of the voxel maximising alpha_n vis_n (the first on ties).
+ * The ray is accurate iff its measurement lies in that voxel's chord, or, when
+ * the visibility at the grid exit is still at least vis_min (the map does not
+ * block the ray enough), iff the measurement lies beyond the exit.  All of it
+ * in FP64.
+ *   logit: V floats, the map's log-odds (NULL: the last mrf_infer's marginals).
+ *   vis_min: in (0, 1] (0.5: the surface is more likely beyond the map).
+ *   ray_code: R int8 (ray id as in mrf_build: frame-major, then row-major
+ *     pixels), 1 accurate, 0 not, -1 not evaluated; may be NULL.
+ *   surface_depth: R doubles, z-depth of the chosen voxel's entry, +inf for a
+ *     surface beyond the map, NaN if not evaluated; may be NULL.
+ *   counts: 2 int64 per scene (evaluated rays, accurate rays); may be NULL.
+ * Reads the depth images and poses passed to mrf_build, which must still be
+ * valid.  Allocates 16 V bytes of scratch in the context on first use.
+ * Errors: MRF_ESTATE (before mrf_build, or logit NULL before mrf_infer),
+ * MRF_EINVAL (vis_min out of range). */
+int mrf_accuracy(mrf_ctx* ctx, const float* logit, double vis_min, int8_t* ray_code,
+                 double* surface_depth, int64_t* counts, void* stream);
+
 /* Sizes and histograms of the built graph (host struct). */
 int mrf_stats(const mrf_ctx* ctx, mrf_stats_t* out);
 

@@ -191,7 +191,7 @@ void mrf_destroy(mrf_ctx* c)
     drop_graph(c);
     DevBuf* all[] = {&c->b_scenes, &c->b_frames, &c->b_counts, &c->b_rowptr, &c->b_col, &c->b_delta,
                      &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
-                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias, &c->b_ckpt, &c->b_tsum, &c->b_tbar,
+                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias, &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
     for (DevBuf* b : all) free_buf(*b);
@@ -513,6 +513,23 @@ int mrf_backward_sensor(mrf_ctx* c, const float* dlogit, float* dprior, float* d
     HCK(e, "mrf_backward: sweeps");
     if (dsigma || dbias) HCK(launch_sigma_grad(c, dsigma, dbias, s), "mrf_backward: sensor-table gradients");
     if (dprior) HCK(launch_copy(dprior, thetabar, c->V, s), "mrf_backward: copy");
+    return MRF_OK;
+}
+
+int mrf_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* ray_code, double* surface_depth,
+                 int64_t* counts, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_accuracy: null context");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_accuracy: call mrf_build first");
+    if (!(vis_min > 0.0 && vis_min <= 1.0)) return fail(MRF_EINVAL, "mrf_accuracy: vis_min must lie in (0, 1]");
+    if (!logit) {
+        if (!c->inferred) return fail(MRF_ESTATE, "mrf_accuracy: no map given and no mrf_infer yet");
+        logit = (const float*)c->b_L.p;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_accuracy: hipSetDevice");
+    HCK(ensure(c->b_metric, 2 * sizeof(double) * (size_t)c->V), "mrf_accuracy: alloc");
+    HCK(launch_accuracy(c, logit, vis_min, ray_code, surface_depth, counts, s), "mrf_accuracy");
     return MRF_OK;
 }
 

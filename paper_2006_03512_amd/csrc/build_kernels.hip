@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "dev_common.hpp"
 #include "mrf_internal.hpp"
@@ -24,9 +25,10 @@ struct Ray {
 };
 
 // Ray of pixel (u, v): centre c, direction R (x_n, y_n, 1) (t is z-depth),
-// clipped to the grid box and truncated at Z + nsig * sigma_tr(Z).
-__device__ bool setup_ray(const SceneDev& sd, const BuildDev& bp, const double* T, float zf,
-                          int v, int u, Ray& r)
+// clipped to the grid box: [ts, texit].  False when the pixel has no usable
+// measurement or the ray misses the grid.
+__device__ bool clip_ray(const SceneDev& sd, const BuildDev& bp, const double* T, float zf, int v, int u,
+                         Ray& r, double& ts_out, double& texit_out)
 {
     const double Z = (double)zf;
     if (!isfinite(Z) || Z < bp.z_min || Z > bp.z_max) return false;
@@ -53,6 +55,20 @@ __device__ bool setup_ray(const SceneDev& sd, const BuildDev& bp, const double* 
             return false;
         }
     }
+    r.Z = Z;
+    ts_out = ts;
+    texit_out = texit;
+    return true;
+}
+
+// The graph's ray: the clipped ray of a surface inside the grid, walked to
+// Z + nsig * sigma_tr(Z) or the grid exit.
+__device__ bool setup_ray(const SceneDev& sd, const BuildDev& bp, const double* T, float zf,
+                          int v, int u, Ray& r)
+{
+    double ts, texit;
+    if (!clip_ray(sd, bp, T, zf, v, u, r, ts, texit)) return false;
+    const double Z = r.Z;
     if (Z >= texit) return false;   // surface outside the grid
     double sig = bp.c2 * Z;
     sig = sig * Z;
@@ -61,7 +77,6 @@ __device__ bool setup_ray(const SceneDev& sd, const BuildDev& bp, const double* 
     double te = Z + bp.nsig * sig;
     if (te > texit) te = texit;
     if (te <= ts) return false;
-    r.Z = Z;
     r.ts = ts;
     r.te = te;
     return true;
@@ -76,7 +91,7 @@ __device__ __forceinline__ double face(const SceneDev& sd, int a, int idx)
 // positive length (voxel (i, j, kz)); ties between axes step the lowest axis.
 // Returns count.
 template <class Emit>
-__device__ int walk(const SceneDev& sd, const Ray& r, Emit emit)
+__device__ int walk(const SceneDev& sd, const Ray& r, Emit&& emit)
 {
     int idx[3];
     double tmax[3];
@@ -1169,6 +1184,135 @@ hipError_t export_canonical_edges(const mrf_ctx* c, const void* in_slots, void* 
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+
+// ============================================================== accuracy metric
+
+// Sec. III-D: a voxel is a region of constant occlusion density alpha, chosen
+// so that crossing one voxel side h blocks a ray with the voxel's occupancy
+// probability: alpha = -ln(1 - p) / h = softplus(L) / h for log-odds L.  Per
+// voxel of one scene, FP64: alpha and log alpha.
+__global__ void metric_alpha_k(const float* __restrict__ logit, int64_t n, double inv_h,
+                               double* __restrict__ alpha, double* __restrict__ lalpha)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = (double)logit[i];
+        const double sp = (x > 0.0 ? x : 0.0) + log1p(exp(-fabs(x)));
+        const double a = sp * inv_h;
+        alpha[i] = a;
+        lalpha[i] = log(a);
+    }
+}
+
+// Along a ray (Euclidean length s) vis(s) = exp(-integral of alpha) and the
+// density of the generating surface omega(s) = alpha(s) vis(s) decays inside
+// a voxel, so its maximum is at the entry of the voxel maximising
+// log alpha_n - sum_{i<n} alpha_i l_i (the first on ties).
+struct MetricEmit {
+    const double* alpha;
+    const double* lalpha;
+    int64_t vb;              // the scene's first global voxel id
+    int32_t nx, ny;
+    double wn;               // |w|: Euclidean length per unit of z-depth
+    double acc = 0.0;        // sum of alpha_i l_i so far
+    double best = -__builtin_huge_val();
+    double btin = 0.0, btout = 0.0;
+
+    __device__ void operator()(int, int i, int j, int kz, double tin, double tout)
+    {
+        const int64_t v = vb + (int64_t)(i + nx * (j + ny * kz));
+        const double a = alpha[v];
+        const double lw = lalpha[v] - acc;
+        if (lw > best) {
+            best = lw;
+            btin = tin;
+            btout = tout;
+        }
+        acc += a * ((tout - tin) * wn);
+    }
+};
+
+// One thread per pixel of one frame (blockIdx.y): the ray clipped to the grid
+// box and walked to the grid exit.  Exit visibility of at least vis_min (log:
+// lvmin) means the map leaves the ray visible, and the ray is accurate iff its
+// measurement lies beyond the exit; otherwise iff the measurement lies inside
+// the chord [t_in, t_out) of the voxel of the most likely surface.  code: 1
+// accurate, 0 not, -1 not evaluated; surf: z-depth of the chosen voxel's
+// entry, +inf when the surface is taken to lie beyond the map, NaN when not
+// evaluated.  Per-scene counts (evaluated, accurate) by block counts and one
+// atomic per block.
+__global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ scenes,
+                                                  const FrameDev* __restrict__ frames, BuildDev bp,
+                                                  const double* __restrict__ alpha,
+                                                  const double* __restrict__ lalpha, double lvmin,
+                                                  int8_t* __restrict__ code, double* __restrict__ surf,
+                                                  unsigned long long* __restrict__ counts)
+{
+    const FrameDev fr = frames[blockIdx.y];
+    const SceneDev& sd = scenes[fr.scene];
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    int ev = 0, ok = 0;
+    if (pix < sd.W * sd.H) {
+        const int v = pix / sd.W, u = pix - v * sd.W;
+        Ray r;
+        double ts, texit;
+        int8_t cd = -1;
+        double sf = __builtin_nan("");
+        if (clip_ray(sd, bp, fr.T, fr.depth[pix], v, u, r, ts, texit) && ts < texit) {
+            r.ts = ts;
+            r.te = texit;
+            MetricEmit m;
+            m.alpha = alpha;
+            m.lalpha = lalpha;
+            m.vb = sd.voxel_base;
+            m.nx = sd.n[0];
+            m.ny = sd.n[1];
+            m.wn = sqrt(r.w[0] * r.w[0] + r.w[1] * r.w[1] + r.w[2] * r.w[2]);
+            walk(sd, r, m);
+            if (-m.acc >= lvmin) {
+                cd = r.Z > texit ? 1 : 0;
+                sf = __builtin_huge_val();
+            } else {
+                cd = (m.btin <= r.Z && r.Z < m.btout) ? 1 : 0;
+                sf = m.btin;
+            }
+            ev = 1;
+            ok = cd;
+        }
+        const int64_t gr = fr.ray_base + pix;
+        if (code) code[gr] = cd;
+        if (surf) surf[gr] = sf;
+    }
+    const int nev = __syncthreads_count(ev);
+    const int nok = __syncthreads_count(ok);
+    if (counts && threadIdx.x == 0 && nev > 0) {
+        atomicAdd(&counts[2 * fr.scene], (unsigned long long)nev);
+        atomicAdd(&counts[2 * fr.scene + 1], (unsigned long long)nok);
+    }
+}
+
+hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
+                           int64_t* counts, hipStream_t s)
+{
+    double* alpha = (double*)c->b_metric.p;
+    double* lalpha = alpha + c->V;
+    for (const SceneDev& sd : c->scenes_h) {
+        const int64_t n = (int64_t)sd.n[0] * sd.n[1] * sd.n[2];
+        int64_t b = (n + 255) / 256;
+        if (b > 65536) b = 65536;
+        hipLaunchKernelGGL(metric_alpha_k, dim3((unsigned)b), dim3(256), 0, s, logit + sd.voxel_base, n, 1.0 / sd.h,
+                           alpha + sd.voxel_base, lalpha + sd.voxel_base);
+    }
+    if (counts) {
+        hipError_t e = launch_fill_u32((uint32_t*)counts, 0u, 4 * (int64_t)c->n_scenes, s);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((c->max_hw + 255) / 256, c->n_frames);
+    hipLaunchKernelGGL(accuracy_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
+                       (const FrameDev*)c->b_frames.p, c->bp, (const double*)alpha, (const double*)lalpha,
+                       std::log(vis_min), code, surf, (unsigned long long*)counts);
     return hipGetLastError();
 }
 

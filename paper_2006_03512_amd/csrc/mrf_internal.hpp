@@ -243,6 +243,7 @@ struct mrf_ctx {
         b_ellbar, b_lambar, b_gsum, b_tmp64, b_cls, b_sigpart, b_misc;
     mrf::DevBuf b_tiles, b_tbase;
     mrf::DevBuf b_tsum;   // per-voxel totals of the sweeps (theta + incoming ray messages)
+    mrf::DevBuf b_metric; // accuracy metric: per-voxel alpha and log alpha (2 V doubles)
     mrf::DevBuf b_tbar;   // per-voxel sums of d/d lambda in the reverse pass (2 V: one spare)
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
     mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
@@ -352,5 +353,10 @@ hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* la
 // accumulators (kSigPartBytes), scratch past them is free for callers.
 constexpr size_t kSigPartBytes = sizeof(double) * 4 * kBins;
 hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_t s);
+// Accuracy metric (Sec. III-D) of the map `logit` over every pixel of the built
+// scenes; counts: 2 per scene (evaluated, accurate), zeroed here.  Needs
+// b_metric of 2 V doubles.
+hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
+                           int64_t* counts, hipStream_t s);
 
 }  // namespace mrf

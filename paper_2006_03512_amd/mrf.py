@@ -103,6 +103,7 @@ class RayMRF:
         self._keep = keep
         self._arr = arr
         self._params = p0
+        self._frames_built = False   # the context still points at the previous upload's frames
 
     def build_resident(self, keep_chords: bool = False, stream=None):
         """(Re)build the ray MRF from the uploaded frames."""
@@ -115,6 +116,7 @@ class RayMRF:
         st = self.stats()
         self.n_voxels, self.n_edges, self.n_rays = st.n_voxels, st.n_edges, st.n_rays
         self.keep_chords = keep_chords
+        self._frames_built = True
         return st
 
     def build(self, scenes, keep_chords: bool = False, stream=None):
@@ -176,6 +178,26 @@ class RayMRF:
         check(self._L.mrf_backward_sensor(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), ptr(db),
                                           stream_handle(stream)), "mrf_backward_sensor")
         return dp, ds, db
+
+    def accuracy(self, logit=None, vis_min: float = 0.5, stream=None) -> dict:
+        """Accuracy metric of a map (Sec. III-D) over every pixel of the built
+        scenes: per-ray ``code`` (int8: 1 accurate, 0 not, -1 not evaluated),
+        ``surface_depth`` (float64 z-depth of the most likely generating
+        surface, inf beyond the map), per-scene ``counts`` (evaluated, accurate)
+        and ``accuracy`` (accurate / evaluated per scene).  logit: the map's V
+        log-odds; None uses the last inference's marginals."""
+        if not getattr(self, "_frames_built", False):
+            raise RuntimeError("accuracy() needs a build of the uploaded frames")
+        if logit is not None:
+            self._vec(logit, self.n_voxels, "logit")
+        code = torch.empty(self.n_rays, dtype=torch.int8, device=self.device)
+        surf = torch.empty(self.n_rays, dtype=torch.float64, device=self.device)
+        counts = torch.empty((len(self._arr), 2), dtype=torch.int64, device=self.device)
+        check(self._L.mrf_accuracy(self._h, ptr(logit), float(vis_min), ptr(code), ptr(surf), ptr(counts),
+                                   stream_handle(stream)), "mrf_accuracy")
+        c = counts.cpu()
+        acc = [float(a) / float(n) if n > 0 else float("nan") for n, a in c.tolist()]
+        return {"code": code, "surface_depth": surf, "counts": counts, "accuracy": acc}
 
     # ------------------------------------------------------------------
     def export_incidence(self, stream=None):
