@@ -198,39 +198,41 @@ def test_messages_extreme_prior_logodds(oracle, RayMRF):
 @pytest.mark.parametrize("keep", [False, True])
 def test_messages_last_sweep(oracle, RayMRF, keep):
     """After K = 4 sweeps (with and without checkpoints, which keep the
-    messages in different buffers): every voxel->ray message is the prior plus
-    the other rays' messages of sweep K-1 (Eq. node_to_factor, summed in FP64
-    from the exported sweep-(K-1) messages), and every ray->voxel message is
-    the oracle's single-ray Eqs. pos / neg on the exported sweep-K inputs."""
+    messages in different buffers) every message matches the oracle's own
+    sweep-4 messages: voxel->ray messages (Eq. node_to_factor) within 1e-5 of
+    the magnitude of the terms they sum (theta and the voxel's sweep-3 ray
+    messages), and ray->voxel messages (Eqs. pos / neg) within the bound used
+    after one sweep (2e-4 relative plus 1e-6 of the ray's largest |g|).  Independently of the oracle, every voxel->ray message
+    is the prior plus the other rays' exported sweep-3 messages, summed in FP64."""
     _say(f"[last sweep] fd K=4 keep={keep}")
     sc = S.make_fd()
     G = oracle.build_graph(sc)
     th = sc.prior_logit().astype(np.float32)
+    th64 = th.astype(np.float64)
     sig = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
     m = _gpu(RayMRF, sc, keep_chords=False)
     m.infer(torch.from_numpy(th).cuda(), sig, 3, keep_checkpoints=keep)
     ell3 = m.export_edges()["ell"].cpu().numpy().astype(np.float64)
     m.infer(torch.from_numpy(th).cuda(), sig, 4, keep_checkpoints=keep)
     e = {k: v.cpu().numpy().astype(np.float64) for k, v in m.export_edges().items() if k in ("lam", "ell", "g")}
-    # voxel phase: lam_e = theta_v + sum over the voxel's other edges of ell3
-    tot = th.astype(np.float64).copy()
+    ref3 = oracle.infer(G, th64, sc.sigma_table, 3)
+    ref4 = oracle.infer(G, th64, sc.sigma_table, 4)
+    # voxel phase against the oracle
+    mag = np.abs(th64).copy()
+    np.add.at(mag, G.col, np.abs(ref3.ell))
+    r_lam = float((np.abs(e["lam"] - ref4.lam) / (1e-5 * mag[G.col] + 1e-6)).max())
+    # ray phase against the oracle
+    nz = np.diff(G.row_ptr) > 0
+    gmax = np.repeat(np.maximum.reduceat(np.abs(ref4.g), G.row_ptr[:-1][nz]), np.diff(G.row_ptr)[nz])
+    r_ell = float((np.abs(e["ell"] - ref4.ell) / (2e-4 * (1.0 + np.abs(ref4.ell)) + 1e-6 * gmax)).max())
+    # voxel phase as a property of the exported messages: lam_e = theta_v + sum of the others' ell3
+    tot = th64.copy()
     np.add.at(tot, G.col, ell3)
-    mag = np.abs(th).astype(np.float64)
-    np.add.at(mag, G.col, np.abs(ell3))
-    want = tot[G.col] - ell3
-    err = np.abs(e["lam"] - want)
-    bound = 1e-5 * mag[G.col] + 1e-6
-    assert np.all(err <= bound), float((err / bound).max())
-    # ray phase on the GPU's own inputs
-    worst = 0.0
-    for r in range(G.row_ptr.shape[0] - 1):
-        a, b = int(G.row_ptr[r]), int(G.row_ptr[r + 1])
-        if b == a:
-            continue
-        ref = oracle.single_ray(e["lam"][a:b], e["g"][a:b])
-        bnd = 2e-4 * (1.0 + np.abs(ref)) + 1e-6 * np.abs(e["g"][a:b]).max()
-        worst = max(worst, float((np.abs(e["ell"][a:b] - ref) / bnd).max()))
-    assert worst <= 1.0, worst
+    mag3 = np.abs(th64).copy()
+    np.add.at(mag3, G.col, np.abs(ell3))
+    r_own = float((np.abs(e["lam"] - (tot[G.col] - ell3)) / (1e-5 * mag3[G.col] + 1e-6)).max())
+    _say(f"  worst error / bound: lam {r_lam:.3f}, ell {r_ell:.3f}, lam from exported ell3 {r_own:.3f}")
+    assert r_lam <= 1.0 and r_ell <= 1.0 and r_own <= 1.0
 
 
 def test_determinism(RayMRF):
