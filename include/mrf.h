@@ -10,7 +10,9 @@
  * sum-product belief propagation (Sec. III-B) with the linear-time ray
  * messages of Eqs. pos and neg.  A reverse pass (not in the paper) gives the
  * gradient of any loss of the marginal log-odds with respect to the per-voxel
- * prior log-odds and the 64-bin sigma table.
+ * prior log-odds and the 64-bin sigma table (and the 64-bin depth-bias table of
+ * the sensor model, Sec. IV-C).  mrf_accuracy evaluates a map with the
+ * accuracy metric of Sec. III-D.
  *
  * Conventions shared by every call
  * --------------------------------
