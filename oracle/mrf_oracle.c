@@ -84,6 +84,7 @@ typedef struct {
     double trunc_nsigma, trunc_c0, trunc_c2, trunc_min;
     double table_dmax;
     int32_t min_ray_voxels;
+    const uint8_t* bricks;   /* allocated 8^3 bricks (or_brick_mask), NULL: dense grid */
 } or_cfg;
 
 typedef struct {
@@ -158,11 +159,64 @@ static double or_face(const or_cfg* g, int a, int idx)
     return g->origin[a] + (double)idx * g->h;
 }
 
+/* Sparse bricks (Sec. IV-B): storage exists only in 8^3-voxel bricks
+ * allocated around the reprojected depth points, and rays skip the rest.
+ * A brick is allocated when the measured surface point c + Z w of a pixel
+ * with a usable measurement (any frame) lies in a voxel of the grid whose
+ * brick is within `radius` bricks of it along every axis.  mask: one byte per
+ * brick, brick (bi, bj, bk) at bi + nbx (bj + nby bk), nb = ceil(n / 8). */
+void or_brick_mask(const or_cfg* g, int32_t n_frames, const float* depth, const double* T_wc,
+                   int32_t radius, uint8_t* mask)
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    int nb[3];
+    for (int a = 0; a < 3; ++a) nb[a] = (n[a] + 7) / 8;
+    memset(mask, 0, (size_t)nb[0] * nb[1] * nb[2]);
+    const int64_t HW = (int64_t)g->width * g->height;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const double* T = T_wc + 16 * f;
+        for (int64_t pix = 0; pix < HW; ++pix) {
+            int v = (int)(pix / g->width), u = (int)(pix % g->width);
+            double Z = (double)depth[f * HW + pix];
+            if (!isfinite(Z) || Z < g->z_min || Z > g->z_max) continue;
+            double xn = ((double)u - g->cx) / g->fx;
+            double yn = ((double)v - g->cy) / g->fy;
+            int b[3], ok = 1;
+            for (int a = 0; a < 3 && ok; ++a) {
+                double wa = T[4 * a + 0] * xn;
+                wa = wa + T[4 * a + 1] * yn;
+                wa = wa + T[4 * a + 2];
+                double pa = T[4 * a + 3] + Z * wa;
+                double q = floor((pa - g->origin[a]) / g->h);
+                if (!(q >= 0.0 && q < (double)n[a])) ok = 0;
+                else b[a] = (int)q / 8;
+            }
+            if (!ok) continue;
+            for (int dk = -radius; dk <= radius; ++dk)
+                for (int dj = -radius; dj <= radius; ++dj)
+                    for (int di = -radius; di <= radius; ++di) {
+                        int bi = b[0] + di, bj = b[1] + dj, bk = b[2] + dk;
+                        if (bi < 0 || bj < 0 || bk < 0 || bi >= nb[0] || bj >= nb[1] || bk >= nb[2]) continue;
+                        mask[bi + (int64_t)nb[0] * (bj + (int64_t)nb[1] * bk)] = 1;
+                    }
+        }
+    }
+}
+
+/* whether the voxel idx lies in an allocated brick (always, for a dense grid) */
+static int or_allocated(const or_cfg* g, const int idx[3])
+{
+    if (!g->bricks) return 1;
+    const int nbx = (g->nx + 7) / 8, nby = (g->ny + 7) / 8;
+    return g->bricks[idx[0] / 8 + (int64_t)nbx * (idx[1] / 8 + (int64_t)nby * (idx[2] / 8))];
+}
+
 typedef void (*or_emit_fn)(void* ud, int64_t k, int32_t id, double tin, double tout);
 
 /* Amanatides-Woo walk from t_s to t_e; calls emit for every voxel crossed
- * with a chord of positive length.  Ties between axes step the lowest axis
- * first.  Returns the number of voxels emitted. */
+ * with a chord of positive length (in an allocated brick, when the grid is
+ * sparse).  Ties between axes step the lowest axis first.  Returns the number
+ * of voxels emitted. */
 static int64_t or_walk(const or_cfg* g, const or_ray* r, or_emit_fn emit, void* ud)
 {
     const int n[3] = {g->nx, g->ny, g->nz};
@@ -189,7 +243,7 @@ static int64_t or_walk(const or_cfg* g, const or_ray* r, or_emit_fn emit, void* 
         int a = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
         double tm = tmax[a];
         double tout = tm < r->te ? tm : r->te;
-        if (tout > tin) {
+        if (tout > tin && or_allocated(g, idx)) {
             int32_t id = idx[0] + g->nx * (idx[1] + g->ny * idx[2]);
             if (emit) emit(ud, k, id, tin, tout);
             ++k;
@@ -611,6 +665,8 @@ void or_accuracy(const or_cfg* g, int32_t n_frames, const float* depth, const do
     const int64_t HW = (int64_t)g->width * g->height;
     const int64_t R = HW * n_frames;
     const double lvmin = log(vis_min);
+    or_cfg dense = *g;          /* the metric walks the whole grid */
+    dense.bricks = NULL;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t r = 0; r < R; ++r) {
         int64_t f = r / HW, pix = r % HW;
@@ -630,7 +686,7 @@ void or_accuracy(const or_cfg* g, int32_t n_frames, const float* depth, const do
         m.acc = 0.0;
         m.best = m.second = -INFINITY;
         m.btin = m.btout = NAN;
-        or_walk(g, &ray, or_metric_emit, &m);
+        or_walk(&dense, &ray, or_metric_emit, &m);
         double lv = -m.acc;
         double gap = m.best > -INFINITY && m.second > -INFINITY ? m.best - m.second : INFINITY;
         double vgap = fabs(lv - lvmin);

@@ -37,7 +37,8 @@ class _Cfg(C.Structure):
                 ("z_min", C.c_double), ("z_max", C.c_double),
                 ("trunc_nsigma", C.c_double), ("trunc_c0", C.c_double),
                 ("trunc_c2", C.c_double), ("trunc_min", C.c_double),
-                ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32)]
+                ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32),
+                ("bricks", C.c_void_p)]
 
 
 _lib = None
@@ -50,6 +51,7 @@ def lib():
         P = C.c_void_p
         I64, I32 = C.c_int64, C.c_int32
         _lib.or_trace_count.argtypes = [P, I32, P, P, P]
+        _lib.or_brick_mask.argtypes = [P, I32, P, P, I32, P]
         _lib.or_trace_emit.argtypes = [P, I32, P, P, P, P, P, P, P, P]
         _lib.or_incidence.argtypes = [P, I64, I64, P, P]
         _lib.or_potentials.argtypes = [P, P, I64, P, P, P]
@@ -117,10 +119,25 @@ class Graph:
         return int(self.row_ptr.shape[0] - 1)
 
 
+def brick_mask(scene) -> np.ndarray:
+    """Allocated 8^3 bricks of a sparse grid (uint8, bi + nbx (bj + nby bk))."""
+    g = scene.grid
+    nb = [(n + 7) // 8 for n in (g.nx, g.ny, g.nz)]
+    mask = np.zeros(nb[0] * nb[1] * nb[2], np.uint8)
+    depth = np.ascontiguousarray(scene.depth, np.float32)
+    T = np.ascontiguousarray(scene.T_wc, np.float64)
+    lib().or_brick_mask(C.byref(_cfg(scene)), scene.n_frames, _p(depth), _p(T),
+                        int(scene.params.brick_radius), _p(mask))
+    return mask
+
+
 def trace_scene(scene):
-    """(counts, row_ptr, col, t_in, t_out, delta, bin) of one scene."""
+    """(counts, row_ptr, col, t_in, t_out, delta, bin) of one scene (only voxels
+    of allocated bricks when its build parameters ask for a sparse grid)."""
     L = lib()
     cfg = _cfg(scene)
+    mask = brick_mask(scene) if scene.params.sparse_bricks else None
+    cfg.bricks = _p(mask)
     depth = np.ascontiguousarray(scene.depth, np.float32)
     T = np.ascontiguousarray(scene.T_wc, np.float64)
     R = depth.size

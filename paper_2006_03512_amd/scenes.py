@@ -74,6 +74,8 @@ class BuildParams:
     trunc_min: float = 0.0
     table_dmax: float = 8.0
     min_ray_voxels: int = 2
+    sparse_bricks: int = 0      # 1: only 8^3 bricks around the measured points carry voxels
+    brick_radius: int = 1       # bricks allocated around each measured point's brick
 
 
 @dataclass

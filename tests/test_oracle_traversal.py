@@ -1,6 +1,8 @@
 """Pins of the oracle's ray clipping and 3D-DDA walk (Sec. IV-A/IV-B) against
 a brute-force intersection of each ray segment with every half-open voxel box,
 and of its incidence against its definition."""
+import dataclasses
+import itertools
 import math
 
 import numpy as np
@@ -184,3 +186,75 @@ def test_thread_count_does_not_change_results(oracle):
         oracle.set_threads(n)
     b = oracle.infer(G, th, sc.sigma_table, 5)
     np.testing.assert_array_equal(a.L, b.L)
+
+
+def _np_brick_mask(sc, radius):
+    """Allocated bricks written here from the definition: the brick of every
+    measured surface point inside the grid, dilated by radius bricks."""
+    g = sc.grid
+    n = np.array([g.nx, g.ny, g.nz])
+    nb = (n + 7) // 8
+    mask = np.zeros(tuple(nb[::-1]), bool)          # [bk, bj, bi]
+    F, H, W = sc.depth.shape
+    u, v = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    xn = (u - sc.intr.cx) / sc.intr.fx
+    yn = (v - sc.intr.cy) / sc.intr.fy
+    p = sc.params
+    for f in range(F):
+        Z = sc.depth[f].astype(np.float64)
+        ok = np.isfinite(Z) & (Z >= p.z_min) & (Z <= p.z_max)
+        T = sc.T_wc[f]
+        q = []
+        for a in range(3):
+            w = (T[a, 0] * xn + T[a, 1] * yn) + T[a, 2]
+            pa = T[a, 3] + Z * w
+            qa = np.floor((pa - g.origin[a]) / g.voxel)
+            ok &= (qa >= 0) & (qa < n[a])
+            q.append(qa)
+        b = np.stack([qa[ok].astype(int) // 8 for qa in q], 1)
+        for d in itertools.product(range(-radius, radius + 1), repeat=3):
+            c = b + np.array(d)
+            c = c[np.all((c >= 0) & (c < nb), 1)]
+            mask[c[:, 2], c[:, 1], c[:, 0]] = True
+    return mask.reshape(-1).astype(np.uint8)
+
+
+@pytest.mark.parametrize("name,radius", [("c1", 0), ("c1", 1), ("fd", 1), ("c2", 0)])
+def test_sparse_bricks_are_the_dense_rays_restricted_to_allocated_bricks(oracle, name, radius):
+    """Sec. IV-B: a sparse grid keeps of every dense ray exactly the voxels in
+    allocated bricks (same chords), dropping rays left shorter than
+    min_ray_voxels; the allocation is the dilated bricks of the measured points."""
+    sc = S.random_scene(int(name[4:])) if name.startswith("rand") else S.make(name)
+    dense = oracle.build_graph(sc)
+    sp = dataclasses.replace(sc, params=dataclasses.replace(sc.params, sparse_bricks=1, brick_radius=radius))
+    mask = _np_brick_mask(sc, radius)
+    np.testing.assert_array_equal(oracle.brick_mask(sp), mask)
+    assert 0 < mask.sum() < mask.size
+    G = oracle.build_graph(sp)
+    g = sc.grid
+    i = G.col % g.nx
+    j = (G.col // g.nx) % g.ny
+    k = G.col // (g.nx * g.ny)
+    nbx, nby = (g.nx + 7) // 8, (g.ny + 7) // 8
+    di, dj, dk = dense.col % g.nx, (dense.col // g.nx) % g.ny, dense.col // (g.nx * g.ny)
+    keep = mask[di // 8 + nbx * (dj // 8 + nby * (dk // 8))] == 1
+    ray = np.repeat(np.arange(dense.n_rays), np.diff(dense.row_ptr))
+    cnt = np.bincount(ray[keep], minlength=dense.n_rays)
+    cnt[cnt < sc.params.min_ray_voxels] = 0
+    np.testing.assert_array_equal(np.diff(G.row_ptr), cnt)
+    sel = keep & (cnt[ray] > 0)
+    np.testing.assert_array_equal(G.col, dense.col[sel])
+    np.testing.assert_array_equal(G.t_in.view(np.int64), dense.t_in[sel].view(np.int64))
+    np.testing.assert_array_equal(G.t_out.view(np.int64), dense.t_out[sel].view(np.int64))
+    np.testing.assert_array_equal(G.delta, dense.delta[sel])
+    np.testing.assert_array_equal(G.bin, dense.bin[sel])
+    assert mask[i // 8 + nbx * (j // 8 + nby * (k // 8))].all()
+    assert G.n_edges < dense.n_edges
+
+
+def test_sparse_bricks_with_a_radius_covering_the_grid_are_dense(oracle):
+    sc = S.make_fd()
+    sp = dataclasses.replace(sc, params=dataclasses.replace(sc.params, sparse_bricks=1, brick_radius=64))
+    a, b = oracle.build_graph(sc), oracle.build_graph(sp)
+    np.testing.assert_array_equal(a.row_ptr, b.row_ptr)
+    np.testing.assert_array_equal(a.col, b.col)
