@@ -77,37 +77,52 @@ def make_scene(name, frames=None, c5_scale=0.4):
     return [scenes.make(name)]
 
 
-def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=2):
+def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=2, single_rows=30):
     """The FP64 oracle on a bounded sample of the same workload: the first nf
     frames of the batch, restricted to a band of their pixel rows (the other
-    pixels carry no measurement)."""
+    pixels carry no measurement), on every thread; then on one thread over a
+    band of single_rows rows of frame 0."""
     import numpy as np
 
     from oracle import oracle
     from paper_2006_03512_amd import scenes as S
 
-    nf = max(1, min(nf, sc.n_frames))
-    depth = sc.depth[:nf].copy()
-    H = depth.shape[1]
-    keep = max(1, int(round(H * row_frac)))
-    r0 = (H - keep) // 2
-    depth[:, :r0] = 0.0
-    depth[:, r0 + keep:] = 0.0
-    sub = S.Scene(sc.name, depth, sc.T_wc[:nf].copy(), sc.intr, sc.grid, sc.solids,
-                  sc.params, sc.sigma_table, sc.prior, sc.sweeps)
-    t0 = time.perf_counter()
-    G = oracle.build_graph(sub)
-    th = sub.prior_logit().astype(np.float64)
-    res = oracle.infer(G, th, sub.sigma_table, sweeps, keep_history=backward)
-    if backward:
-        y = sub.occupancy().astype(np.float64)
-        oracle.backward(G, res, oracle.bce_logit_grad(res.L, y), sub.sigma_table)
-    dt = time.perf_counter() - t0
-    E = G.n_edges
+    def band(frames, rows):
+        depth = sc.depth[:frames].copy()
+        H = depth.shape[1]
+        keep = max(1, min(H, rows))
+        r0 = (H - keep) // 2
+        depth[:, :r0] = 0.0
+        depth[:, r0 + keep:] = 0.0
+        sub = S.Scene(sc.name, depth, sc.T_wc[:frames].copy(), sc.intr, sc.grid, sc.solids,
+                      sc.params, sc.sigma_table, sc.prior, sc.sweeps)
+        return sub, f"rows {r0}..{r0 + keep - 1} of frames 0..{frames - 1}"
+
+    def run(sub):
+        y = sub.occupancy().astype(np.float64) if backward else None   # labels: not timed
+        t0 = time.perf_counter()
+        G = oracle.build_graph(sub)
+        th = sub.prior_logit().astype(np.float64)
+        res = oracle.infer(G, th, sub.sigma_table, sweeps, keep_history=backward)
+        if backward:
+            oracle.backward(G, res, oracle.bce_logit_grad(res.L, y), sub.sigma_table)
+        return G.n_edges, time.perf_counter() - t0
+
     what = "build + %d sweeps%s" % (sweeps, " + reverse pass" if backward else "")
-    return {"value": E * sweeps / dt, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"rows {r0}..{r0 + keep - 1} of frames 0..{nf - 1} of the {sc.n_frames}-frame {name} batch "
-                      f"({E} edges), {what}, FP64, {dt:.1f} s"}
+    nf = max(1, min(nf, sc.n_frames))
+    sub, where = band(nf, int(round(sc.depth.shape[1] * row_frac)))
+    E, dt = run(sub)
+    threads = oracle.num_threads()
+    sub1, where1 = band(1, single_rows)
+    oracle.set_threads(1)
+    try:
+        E1, dt1 = run(sub1)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": E * sweeps / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{where} of the {sc.n_frames}-frame {name} batch ({E} edges), {what}, FP64, {dt:.1f} s",
+            "single_thread": {"value": E1 * sweeps / dt1, "unit": UNIT, "cores": 1,
+                              "sample": f"{where1} ({E1} edges), {what}, FP64, {dt1:.1f} s"}}
 
 
 def copy_bandwidth(nbytes: int, reps: int = 5) -> float:

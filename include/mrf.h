@@ -84,13 +84,23 @@ typedef struct {
  * the incidence never depends on learnable parameters.  Rays that cross fewer
  * than min_ray_voxels voxels (>= 2, since a one-voxel ray factor forces its
  * voxel occupied with infinite log-odds) are dropped.  The sigma table has 64
- * bins of width table_dmax/64 indexed by the voxel's depth. */
+ * bins of width table_dmax/64 indexed by the voxel's depth.
+ * Sparse grid (Sec. IV-B: storage only in 8^3-voxel bricks allocated around
+ * the reprojected depth points, rays skip the rest): with sparse_bricks != 0
+ * a brick (voxels [8b, 8b + 8) per axis from the grid origin) is allocated
+ * iff the measured point c + Z w of a usable pixel of any frame of the scene
+ * lies in a grid voxel whose brick is within brick_radius bricks of it on
+ * every axis; a ray then keeps only its voxels in allocated bricks (same
+ * chords), and min_ray_voxels applies to those.  Voxels of other bricks take
+ * part in no ray factor and keep their prior. */
 typedef struct {
     double z_min, z_max;
     double trunc_nsigma, trunc_c0, trunc_c2, trunc_min;
     double table_dmax;
     int32_t min_ray_voxels;
     int32_t keep_chords;    /* nonzero: keep f64 chord entry/exit per edge for export */
+    int32_t sparse_bricks;  /* nonzero: sparse grid (Sec. IV-B), see below; 0: dense */
+    int32_t brick_radius;   /* sparse grid: bricks allocated around a point's brick, 0..64 */
 } mrf_build_params;
 
 typedef struct {

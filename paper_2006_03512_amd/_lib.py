@@ -41,7 +41,7 @@ class BuildParams(C.Structure):
     _fields_ = [("z_min", C.c_double), ("z_max", C.c_double), ("trunc_nsigma", C.c_double),
                 ("trunc_c0", C.c_double), ("trunc_c2", C.c_double), ("trunc_min", C.c_double),
                 ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32),
-                ("keep_chords", C.c_int32)]
+                ("keep_chords", C.c_int32), ("sparse_bricks", C.c_int32), ("brick_radius", C.c_int32)]
 
 
 class Stats(C.Structure):

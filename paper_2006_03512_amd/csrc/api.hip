@@ -191,7 +191,7 @@ void mrf_destroy(mrf_ctx* c)
     drop_graph(c);
     DevBuf* all[] = {&c->b_scenes, &c->b_frames, &c->b_counts, &c->b_rowptr, &c->b_col, &c->b_delta,
                      &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
-                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias, &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric,
+                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias, &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric, &c->b_bricks,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
     for (DevBuf* b : all) free_buf(*b);
@@ -225,7 +225,9 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->scenes_h.clear();
     c->frames_h.clear();
     c->n_scenes = n_scenes;
-    int64_t R = 0, V = 0, Vk = 0, Tn = 0;
+    int64_t R = 0, V = 0, Vk = 0, Tn = 0, NB = 0;
+    if (p->sparse_bricks && (p->brick_radius < 0 || p->brick_radius > 64))
+        return fail(MRF_EINVAL, "mrf_build: brick_radius must lie in [0, 64]");
     int max_hw = 0, max_tpf = 0;
     for (int i = 0; i < n_scenes; ++i) {
         const mrf_scene& sc = scenes[i];
@@ -251,6 +253,8 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         for (int a = 0; a < 3; ++a) d.nb[a] = (d.n[a] + kBrick - 1) / kBrick;
         d.key_base = Vk;
         Vk += (int64_t)d.nb[0] * d.nb[1] * d.nb[2] * kBrick * kBrick * kBrick;
+        d.brick_off = NB;
+        NB += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
         const int64_t hw = (int64_t)d.W * d.H;
         if (hw > (int64_t(1) << 30)) return fail(MRF_ERANGE, "mrf_build: image too large");
         if (hw > max_hw) max_hw = (int)hw;
@@ -289,6 +293,9 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->bp.smin = p->trunc_min;
     c->bp.dmax = p->table_dmax;
     c->bp.min_vox = p->min_ray_voxels;
+    c->bp.radius = p->sparse_bricks ? p->brick_radius : 0;
+    c->bp.bricks = nullptr;
+    c->n_bricks = NB;
     c->keep_chords = p->keep_chords ? 1 : 0;
 
     HCK(ensure(c->b_scenes, sizeof(SceneDev) * c->scenes_h.size()), "mrf_build: alloc");
@@ -303,6 +310,11 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_rowptr, sizeof(int64_t) * (size_t)(R + 1)), "mrf_build: alloc row_ptr");
     const size_t sbytes = scan_tmp_bytes(R + 1);
     HCK(ensure(c->b_misc, sbytes), "mrf_build: alloc scan");
+    if (p->sparse_bricks) {
+        HCK(ensure(c->b_bricks, (size_t)((NB + 3) / 4) * 4), "mrf_build: alloc brick mask");
+        c->bp.bricks = (const uint8_t*)c->b_bricks.p;
+        HCK(launch_brick_mask(c, s), "mrf_build: brick mask");
+    }
     HCK(launch_trace_count(c, s), "mrf_build: trace count");
     HCK(scan_exclusive_i32((const int32_t*)c->b_counts.p, (int64_t*)c->b_rowptr.p, R, c->b_misc.p, sbytes, s),
         "mrf_build: scan");

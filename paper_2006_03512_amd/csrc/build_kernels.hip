@@ -88,10 +88,10 @@ __device__ __forceinline__ double face(const SceneDev& sd, int a, int idx)
 }
 
 // Walk voxels from ts to te; emit(k, i, j, kz, tin, tout) for each chord of
-// positive length (voxel (i, j, kz)); ties between axes step the lowest axis.
-// Returns count.
+// positive length (voxel (i, j, kz)) in an allocated brick (every brick when
+// bricks is null); ties between axes step the lowest axis.  Returns count.
 template <class Emit>
-__device__ int walk(const SceneDev& sd, const Ray& r, Emit&& emit)
+__device__ int walk(const SceneDev& sd, const Ray& r, const uint8_t* bricks, Emit&& emit)
 {
     int idx[3];
     double tmax[3];
@@ -118,7 +118,7 @@ __device__ int walk(const SceneDev& sd, const Ray& r, Emit&& emit)
         const int a = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
         const double tm = tmax[a];
         const double tout = tm < r.te ? tm : r.te;
-        if (tout > tin) {
+        if (tout > tin && (!bricks || bricks[(idx[0] >> 3) + sd.nb[0] * ((idx[1] >> 3) + sd.nb[1] * (idx[2] >> 3))])) {
             emit(k, idx[0], idx[1], idx[2], tin, tout);
             ++k;
         }
@@ -132,6 +132,53 @@ __device__ int walk(const SceneDev& sd, const Ray& r, Emit&& emit)
             tmax[a] = (face(sd, a, idx[a]) - r.c[a]) / r.w[a];
     }
     return k;
+}
+
+__device__ __forceinline__ const uint8_t* scene_bricks(const BuildDev& bp, const SceneDev& sd)
+{
+    return bp.bricks ? bp.bricks + sd.brick_off : nullptr;
+}
+
+// Sparse grid (Sec. IV-B: bricks are allocated around the reprojected depth
+// points): one thread per pixel of one frame (blockIdx.y).  The measured
+// surface point c + Z w of a usable measurement marks every brick within
+// bp.radius bricks (per axis) of the brick of its voxel; points outside the
+// grid mark nothing.  Bytes are only ever set to 1, so the mask does not
+// depend on the order of the stores.
+__global__ __launch_bounds__(256) void brick_mark_k(const SceneDev* __restrict__ scenes,
+                                                    const FrameDev* __restrict__ frames, BuildDev bp,
+                                                    uint8_t* __restrict__ bricks)
+{
+    const FrameDev fr = frames[blockIdx.y];
+    const SceneDev& sd = scenes[fr.scene];
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= sd.W * sd.H) return;
+    const int v = pix / sd.W, u = pix - v * sd.W;
+    const double Z = (double)fr.depth[pix];
+    if (!isfinite(Z) || Z < bp.z_min || Z > bp.z_max) return;
+    const double xn = ((double)u - sd.cx) / sd.fx;
+    const double yn = ((double)v - sd.cy) / sd.fy;
+    const double* T = fr.T;
+    int b[3];
+    for (int a = 0; a < 3; ++a) {
+        double wa = T[4 * a + 0] * xn;
+        wa = wa + T[4 * a + 1] * yn;
+        wa = wa + T[4 * a + 2];
+        const double pa = T[4 * a + 3] + Z * wa;
+        const double q = floor((pa - sd.o[a]) / sd.h);
+        if (!(q >= 0.0 && q < (double)sd.n[a])) return;
+        b[a] = (int)q / kBrick;
+    }
+    const int r = bp.radius;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = max(b[a] - r, 0);
+        hi[a] = min(b[a] + r, sd.nb[a] - 1);
+    }
+    uint8_t* m = bricks + sd.brick_off;
+    for (int bk = lo[2]; bk <= hi[2]; ++bk)
+        for (int bj = lo[1]; bj <= hi[1]; ++bj)
+            for (int bi = lo[0]; bi <= hi[0]; ++bi) m[bi + (int64_t)sd.nb[0] * (bj + (int64_t)sd.nb[1] * bk)] = 1;
 }
 
 struct NoEmit {
@@ -149,7 +196,7 @@ __global__ __launch_bounds__(256) void trace_count_k(const SceneDev* __restrict_
     const int v = pix / sd.W, u = pix - v * sd.W;
     Ray r;
     int m = 0;
-    if (setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, r)) m = walk(sd, r, NoEmit{});
+    if (setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, r)) m = walk(sd, r, scene_bricks(bp, sd), NoEmit{});
     counts[fr.ray_base + pix] = m >= bp.min_vox ? m : 0;
 }
 
@@ -222,7 +269,7 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
             Ray ray;
             setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
             EdgeEmit em{col, key, delta, bin, tin, tout, &sd, slot0, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
-            walk(sd, ray, em);
+            walk(sd, ray, scene_bricks(bp, sd), em);
         }
     }
     for (int k = m; k < len; ++k) {
@@ -270,6 +317,16 @@ __global__ void fill_u32_k(uint32_t* __restrict__ p, uint32_t v, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+hipError_t launch_brick_mask(mrf_ctx* c, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32((uint32_t*)c->b_bricks.p, 0u, (c->n_bricks + 3) / 4, s);
+    if (e != hipSuccess) return e;
+    dim3 grid((c->max_hw + 255) / 256, c->n_frames);
+    hipLaunchKernelGGL(brick_mark_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
+                       (const FrameDev*)c->b_frames.p, c->bp, (uint8_t*)c->b_bricks.p);
+    return hipGetLastError();
 }
 
 hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s)
@@ -1270,7 +1327,7 @@ __global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ s
             m.nx = sd.n[0];
             m.ny = sd.n[1];
             m.wn = sqrt(r.w[0] * r.w[0] + r.w[1] * r.w[1] + r.w[2] * r.w[2]);
-            walk(sd, r, m);
+            walk(sd, r, nullptr, m);   // the metric walks the whole grid
             if (-m.acc >= lvmin) {
                 cd = r.Z > texit ? 1 : 0;
                 sf = __builtin_huge_val();

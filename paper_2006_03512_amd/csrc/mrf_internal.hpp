@@ -138,6 +138,7 @@ struct SceneDev {
     int32_t nb[3];        // bricks per axis
     int32_t pad2;
     int64_t key_base;     // first brick-major key of this scene
+    int64_t brick_off;    // the scene's first byte in the brick allocation mask
 };
 
 struct FrameDev {
@@ -186,7 +187,8 @@ struct VoxDev {
 struct BuildDev {
     double z_min, z_max, nsig, c0, c2, smin, dmax;
     int32_t min_vox;
-    int32_t pad;
+    int32_t radius;            // sparse grid: bricks allocated around a measured point's brick
+    const uint8_t* bricks;     // sparse grid: allocation mask (SceneDev::brick_off); null: dense
 };
 
 struct DevBuf {
@@ -244,6 +246,8 @@ struct mrf_ctx {
     mrf::DevBuf b_tiles, b_tbase;
     mrf::DevBuf b_tsum;   // per-voxel totals of the sweeps (theta + incoming ray messages)
     mrf::DevBuf b_metric; // accuracy metric: per-voxel alpha and log alpha (2 V doubles)
+    mrf::DevBuf b_bricks; // sparse grid: one byte per 8^3 brick of every scene
+    int64_t n_bricks = 0;
     mrf::DevBuf b_tbar;   // per-voxel sums of d/d lambda in the reverse pass (2 V: one spare)
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
     mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
@@ -356,6 +360,9 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_
 // Accuracy metric (Sec. III-D) of the map `logit` over every pixel of the built
 // scenes; counts: 2 per scene (evaluated, accurate), zeroed here.  Needs
 // b_metric of 2 V doubles.
+// Sparse grid (Sec. IV-B): zero the allocation mask and mark the bricks around
+// every measured point (c->bp.bricks, c->bp.radius).
+hipError_t launch_brick_mask(mrf_ctx* c, hipStream_t s);
 hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
                            int64_t* counts, hipStream_t s);
 
