@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of the sampled frames' rows the oracle runs on")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames of the batch the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
+    ap.add_argument("--sparse-bricks", type=int, default=-1,
+                    help="brick radius of a sparse grid (bricks around the measured points); -1: dense")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing the candidates after warmup")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -186,6 +188,9 @@ def main():
     t = time.perf_counter()
     scs = make_scene(args.workload, args.frames, args.c5_scale)
     sc = scs[0]
+    if args.sparse_bricks >= 0:   # sparse grid: bricks around the measured points only
+        import dataclasses
+        sc.params = dataclasses.replace(sc.params, sparse_bricks=1, brick_radius=args.sparse_bricks)
     for other in scs[1:]:
         other.params, other.sigma_table = sc.params, sc.sigma_table
     n_frames = sum(x.n_frames for x in scs)
@@ -314,6 +319,8 @@ def main():
                    "edge_slots": st.n_slots, "tiles": st.n_tiles,
                    "touched_voxels": st.n_touched_voxels, "max_ray_len": st.max_ray_len,
                    "max_voxel_degree": st.max_voxel_degree, "parallelism": "single GPU",
+                   "grid_storage": ("dense" if args.sparse_bricks < 0
+                                    else f"sparse bricks, radius {args.sparse_bricks}"),
                    "ray_len_log2_hist": st.ray_len_hist[:12],
                    "voxel_degree_log2_hist": st.voxel_degree_hist[:20]},
         "roofline": roofline,
