@@ -118,10 +118,14 @@ def test_accuracy_column_cases(RayMRF):
     empty = np.full(16, -30.0, np.float32)
     cases = [(front, 0.85, 1, 0.8), (front, 1.35, 0, 0.8), (thin, 1.35, 1, 1.3), (thin, 0.85, 0, 1.3),
              (empty, 2.5, 1, math.inf), (empty, 1.0, 0, math.inf)]
+    zero = np.full(16, -1000.0, np.float32)        # alpha = 0 exactly: exit visibility 1
+    cases += [(zero, 2.5, 1, math.inf, 1.0), (zero, 1.0, 0, math.inf, 1.0)]
     m = RayMRF()
-    for L, Z, want, depth in cases:
+    for case in cases:
+        L, Z, want, depth = case[:4]
+        vis_min = case[4] if len(case) > 4 else 0.5
         m.build(column(Z), keep_chords=False)
-        out = m.accuracy(torch.from_numpy(L).cuda())
+        out = m.accuracy(torch.from_numpy(L).cuda(), vis_min=vis_min)
         assert int(out["code"][0]) == want, (Z, want)
         assert float(out["surface_depth"][0]) == pytest.approx(depth, abs=1e-12)
         assert out["counts"].cpu().numpy().tolist() == [[1, want]]

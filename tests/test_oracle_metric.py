@@ -73,6 +73,15 @@ def test_map_that_leaves_the_ray_visible(oracle):
     assert a["code"][0] == 0 and a["t_out"][0] == math.inf
 
 
+def test_map_of_zero_density_with_vis_min_one(oracle):
+    """Log-odds of -1000 give alpha = softplus(-1000) / h = 0 exactly: the exit
+    visibility is exactly 1, so even vis_min = 1 applies the beyond-the-map rule."""
+    L = np.full(16, -1000.0)
+    for Z, want in ((2.5, 1), (1.0, 0)):
+        a = oracle.accuracy(_column_scene(Z), L, vis_min=1.0)
+        assert a["code"][0] == want and a["lvis"][0] == 0.0 and a["t_out"][0] == math.inf
+
+
 def test_uniform_map_closed_form(oracle):
     """Constant occupancy: omega only decreases along the ray, so the surface
     is at the grid entry, and vis at the exit is exp(-alpha |w| (t_exit - t_s))."""
