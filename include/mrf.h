@@ -254,8 +254,8 @@ typedef struct {
 int mrf_profile_sweeps(mrf_ctx* ctx, int32_t reps, int32_t include_backward,
                        mrf_kernel_time_t* out, int32_t max_out, int32_t* n_out, void* stream);
 
-/* Launch shapes of the ray-length classes (the schedule the task calls the
- * ray-segment length and waves per ray).  Rays are grouped in 4x4-pixel
+/* Launch shapes of the ray-length classes (the ray-segment length and the
+ * lanes per ray the ray kernels use).  Rays are grouped in 4x4-pixel
  * tiles and tiles in classes by their longest ray (cap[q] steps).  A class
  * has fwd_candidates shapes for the ray phase (Eqs. pos and neg) and
  * adj_candidates for the reverse pass; a shape is the lanes per ray (16, 32 or
