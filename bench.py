@@ -47,7 +47,7 @@ WORKLOADS = {
 # --calib-copy-mib, which calibrates the counter: FETCH_SIZE read 0.5 x the bytes
 # the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid only while the
 # kernel sources hash to `csrc_sha256`; otherwise traffic is reported as null.
-TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "37ef3bf1e0848c3eb2849f218683a8e8a02fae68937c9000eededdc9ad0a166b",
+TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "3bca698af0262b25fe9f23bec48e52f2f93cecc1c72cb67beaf3a87d6977d634",
            "fetch_bytes": 1.252e+10, "write_bytes": 4.666e+09}
 
 

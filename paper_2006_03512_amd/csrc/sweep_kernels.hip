@@ -65,10 +65,14 @@ __global__ void sigmoid_k(const float* __restrict__ L, float* __restrict__ p, in
 
 // g_e = log N(Z; d_e + mu_b, sigma_b) = -((delta_e - mu_b) / sigma_b)^2 / 2 -
 // log sigma_b - log(2 pi) / 2, delta_e = Z - d_e, mu_b the learnt depth bias
-// (the predicted mean measurement at depth d is d + mu(d)).  One thread
-// per 16 consecutive slots (S is a multiple of 16: one tile step): 16-byte
-// loads of delta and bin, 16-byte stores of g; padding slots (bin 255) are
-// left as they are.
+// (the predicted mean measurement at depth d is d + mu(d)).  A lane takes 4
+// consecutive slots and consecutive lanes consecutive groups, so every load
+// (4 bins, 4 deltas) and store (4 g) instruction of a wave covers one
+// contiguous run; S is a multiple of 16, so a group lies wholly inside or
+// outside [0, S).  Grid-stride, so each block builds its tables once.
+// Padding slots (bin 255) are left as they are.
+constexpr int kPotGroups = 4;   // potentials: groups of 4 slots in flight per lane
+
 __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ delta, const uint8_t* __restrict__ bin,
                                                     int64_t S, const float* __restrict__ sigma,
                                                     const float* __restrict__ bias, float* __restrict__ g)
@@ -81,33 +85,42 @@ __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ de
         mu[threadIdx.x] = bias[threadIdx.x];
     }
     __syncthreads();
-    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
-    if (e0 >= S) return;
-    const uint4 bw = *(const uint4*)(bin + e0);
-    float4 dv[4];
+    const int64_t ng = S / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x * kPotGroups + threadIdx.x; g0 < ng;
+         g0 += stride * kPotGroups) {
+        uint32_t bw[kPotGroups];
+        float4 dv[kPotGroups];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dv[q] = *(const float4*)(delta + e0 + 4 * q);
-    const uint32_t words[4] = {bw.x, bw.y, bw.z, bw.w};
-    bool all = true;
-    float out[16];
+        for (int u = 0; u < kPotGroups; ++u) {
+            const int64_t gi = g0 + (int64_t)u * blockDim.x;
+            const int64_t at = gi < ng ? gi : ng - 1;
+            bw[u] = ((const uint32_t*)bin)[at];
+            dv[u] = ((const float4*)delta)[at];
+        }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int b = (int)((words[j >> 2] >> (8 * (j & 3))) & 255u);
-        const float4 d4 = dv[j >> 2];
-        const float dj = (j & 3) == 0 ? d4.x : (j & 3) == 1 ? d4.y : (j & 3) == 2 ? d4.z : d4.w;
-        const int bb = b < kBins ? b : 0;
-        const float x = (dj - mu[bb]) * inv[bb];   // residual about the predicted mean d + mu
-        out[j] = -0.5f * x * x - cst[bb];
-        all = all && b < kBins;
-    }
-    if (all) {
+        for (int u = 0; u < kPotGroups; ++u) {
+            const int64_t gi = g0 + (int64_t)u * blockDim.x;
+            if (gi >= ng) break;
+            float out[4];
+            bool all = true;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *(float4*)(g + e0 + 4 * q) = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
-    } else {
+            for (int j = 0; j < 4; ++j) {
+                const int b = (int)((bw[u] >> (8 * j)) & 255u);
+                const float dj = j == 0 ? dv[u].x : j == 1 ? dv[u].y : j == 2 ? dv[u].z : dv[u].w;
+                const int bb = b < kBins ? b : 0;
+                const float x = (dj - mu[bb]) * inv[bb];   // residual about the predicted mean d + mu
+                out[j] = -0.5f * x * x - cst[bb];
+                all = all && b < kBins;
+            }
+            if (all) {
+                ((float4*)g)[gi] = make_float4(out[0], out[1], out[2], out[3]);
+            } else {
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (((words[j >> 2] >> (8 * (j & 3))) & 255u) < kBins) g[e0 + j] = out[j];
+                for (int j = 0; j < 4; ++j)
+                    if (((bw[u] >> (8 * j)) & 255u) < kBins) g[4 * gi + j] = out[j];
+            }
+        }
     }
 }
 
@@ -151,7 +164,9 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 {
     if (c->S <= 0) return hipSuccess;
     ProfScope ps(c, KID_POT, s);
-    hipLaunchKernelGGL(potentials_k, dim3(nblk(c->S / 16, 256)), dim3(256), 0, s, (const float*)c->b_delta.p,
+    int64_t blocks = nblk(c->S / 4, 256 * kPotGroups);
+    if (blocks > 4096) blocks = 4096;   // grid-stride over at most 16 blocks per CU
+    hipLaunchKernelGGL(potentials_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_delta.p,
                        (const uint8_t*)c->b_bin.p, c->S, (const float*)c->b_sigma.p,
                        (const float*)c->b_bias.p, (float*)c->b_g.p);
     return hipGetLastError();
