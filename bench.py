@@ -275,6 +275,14 @@ def main():
     acc = m.accuracy()
     acc_counts = acc["counts"].cpu().numpy().sum(0).tolist()
     log(f"accuracy metric: {acc_ms:.1f} ms, {acc_counts[1]} of {acc_counts[0]} rays accurate")
+    # the same metric after 1..9 sweeps: flooding BP can cycle, and the map's quality
+    # then depends on the phase the stated K lands in
+    acc_by_k = {}
+    for k in range(1, 10):
+        m.infer(theta, sigma, k)
+        c = m.accuracy()["counts"].cpu().numpy().sum(0)
+        acc_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
+    log(f"accurate fraction by sweeps: {acc_by_k}")
 
     # ---- roofline of the dominant kernel (HIP events around each launch)
     m.infer(theta, sigma, K)
@@ -332,7 +340,8 @@ def main():
                          "backward_with_bias_grad": None if bwd_bias_ms is None else round(bwd_bias_ms, 2),
                          "accuracy_metric": round(acc_ms, 2)},
         "map_accuracy": {"evaluated_rays": acc_counts[0], "accurate_rays": acc_counts[1],
-                         "fraction": acc_counts[1] / max(acc_counts[0], 1), "vis_min": 0.5},
+                         "fraction": acc_counts[1] / max(acc_counts[0], 1), "vis_min": 0.5,
+                         "fraction_by_sweeps": acc_by_k},
         "forward_updates_per_s": {"batched_graph": E * K / (fwd_graph_ms / 1e3),
                                   "plain_per_frame": E * K / (fwd_plain_ms / 1e3)},
         "kernels": kernels,
