@@ -14,6 +14,9 @@
  *   or_trace_count / or_trace_emit  -- the ray of each depth pixel clipped to
  *       the grid and truncated 3 sigma past the measurement (Sec. IV-B), walked
  *       voxel by voxel with the 3D-DDA of Amanatides and Woo (Sec. IV-A).
+ *   or_brick_mask                   -- sparse grid (Sec. IV-B): the 8^3 bricks
+ *       allocated around the reprojected depth points; with a mask, the walk
+ *       emits only voxels of allocated bricks.
  *   or_incidence                    -- voxel -> ray incidence: the rays that
  *       share a voxel (Sec. III-A, Fig. "graphical model"), a stable counting
  *       sort of edges by voxel.
