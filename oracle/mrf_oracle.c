@@ -36,6 +36,9 @@
  *       (Sec. III-D): visibility and generating-surface density along each
  *       depth ray through voxels of constant occlusion density, the
  *       measurement checked against the most likely surface.
+ *   or_infer_keyframe_avg           -- the same sweeps with the paper's
+ *       memory approximation (Sec. IV-A): one length-weighted average message
+ *       per keyframe and voxel.
  *   or_backward                     -- reverse-mode derivative of the K
  *       unrolled sweeps (not in the paper: a project extension), written from
  *       the chain rule on the forward steps above.
@@ -471,6 +474,85 @@ void or_infer(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int6
         or_ray_phase(row_ptr, R, lam_out, g, ell);
     }
     or_beliefs(vptr, vedge, V, theta, ell, L);
+}
+
+/* Per-keyframe averaged messages (Sec. IV-A): storing every incoming message
+ * of a voxel is avoided by assuming that the rays of one keyframe crossing a
+ * voxel send the same message, their average weighted by the length each ray
+ * travels in the voxel.  Read here as: each keyframe f contributes ONE message
+ * m_f,v = sum w_e ell_e / sum w_e (over its edges e in voxel v) to the voxel's
+ * belief, and the voxel -> ray message of an edge of keyframe f is the prior
+ * plus the averages of the OTHER keyframes (the receiving ray's keyframe is
+ * excluded as a whole).  key: keyframe of every edge, non-decreasing along
+ * every voxel's edge list (edge ids are keyframe-major); w: weight per edge.
+ * Sums over keyframes are taken as (theta + before) + after, never as a
+ * difference.  Returns 0, or -1 when key is not grouped per voxel. */
+static int or_voxel_phase_kf(const int64_t* vptr, const int64_t* vedge, int64_t V, const double* theta,
+                             const double* ell, const int32_t* key, const double* w, double* lam, double* L)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : bad)
+    for (int64_t v = 0; v < V; ++v) {
+        int64_t s = vptr[v], e = vptr[v + 1];
+        /* run averages, parked per edge in lam as the run's mean, then replaced */
+        double after = 0.0;
+        for (int64_t j = s; j < e;) {
+            int32_t f = key[vedge[j]];
+            double sw = 0.0, sm = 0.0;
+            int64_t q = j;
+            for (; q < e && key[vedge[q]] == f; ++q) {
+                sw += w[vedge[q]];
+                sm += w[vedge[q]] * ell[vedge[q]];
+            }
+            if (q < e && key[vedge[q]] < f) bad = 1;
+            for (int64_t r = j; r < q; ++r) lam[vedge[r]] = sm / sw;
+            j = q;
+        }
+        /* suffix sums over the runs after each run */
+        for (int64_t j = e - 1; j >= s;) {
+            int32_t f = key[vedge[j]];
+            double m = lam[vedge[j]];
+            int64_t q = j;
+            for (; q >= s && key[vedge[q]] == f; --q) lam[vedge[q]] = after;
+            after += m;
+            j = q;
+        }
+        /* (theta + runs before) + runs after */
+        double before = 0.0;
+        for (int64_t j = s; j < e;) {
+            int32_t f = key[vedge[j]];
+            int64_t q = j;
+            double m = 0.0, sw = 0.0;
+            for (; q < e && key[vedge[q]] == f; ++q) {
+                sw += w[vedge[q]];
+                m += w[vedge[q]] * ell[vedge[q]];
+            }
+            for (int64_t r = j; r < q; ++r) lam[vedge[r]] = (theta[v] + before) + lam[vedge[r]];
+            before += m / sw;
+            j = q;
+        }
+        if (L) L[v] = theta[v] + before;
+    }
+    return bad ? -1 : 0;
+}
+
+/* K sweeps of the flooding schedule with per-keyframe averaged messages;
+ * ell = 0 initially, so the first sweep's lambda is theta.  Outputs as
+ * or_infer: the last sweep's lambda and ell (E) and the beliefs L (V): the
+ * prior plus one averaged message per keyframe.  Returns 0 or -1 (key). */
+int or_infer_keyframe_avg(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
+                          int64_t V, int64_t E, const double* theta, const double* g, int32_t K,
+                          const int32_t* key, const double* w, double* lam_out, double* ell_out, double* L)
+{
+    memset(ell_out, 0, sizeof(double) * (size_t)E);
+    for (int32_t k = 0; k < K; ++k) {
+        if (or_voxel_phase_kf(vptr, vedge, V, theta, ell_out, key, w, lam_out, NULL)) return -1;
+        or_ray_phase(row_ptr, R, lam_out, g, ell_out);
+    }
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    int rc = or_voxel_phase_kf(vptr, vedge, V, theta, ell_out, key, w, tmp, L);
+    free(tmp);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */

@@ -58,6 +58,8 @@ def lib():
         _lib.or_infer.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P]
         _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, P, P, P, P]
         _lib.or_single_ray.argtypes = [I64, P, P, P]
+        _lib.or_infer_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P, P]
+        _lib.or_infer_keyframe_avg.restype = C.c_int
         _lib.or_accuracy.argtypes = [P, I32, P, P, P, C.c_double, P, P, P, P, P]
         _lib.or_single_ray_adjoint.argtypes = [I64, P, P, P, P, P]
         _lib.or_num_threads.restype = C.c_int
@@ -219,6 +221,45 @@ def infer(graph: Graph, theta, sigma_table, sweeps: int, keep_history: bool = Fa
     lib().or_infer(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
                    _p(theta), _p(g), int(sweeps), _p(hist), _p(lam), _p(ell), _p(L))
     return Result(L, lam, ell, g, hist)
+
+
+def edge_keyframes_and_lengths(graph: Graph, scenes):
+    """Keyframe of every edge (frames numbered across the batch's scenes) and
+    the length the edge's ray travels in its voxel, (t_out - t_in) |w| with
+    w = R (x_n, y_n, 1) the ray direction of its pixel."""
+    if not isinstance(scenes, (list, tuple)):
+        scenes = [scenes]
+    ray = np.repeat(np.arange(graph.n_rays), np.diff(graph.row_ptr))
+    key = np.empty(graph.n_edges, np.int32)
+    wn_ray = np.empty(graph.n_rays)
+    f0 = 0
+    for s, rb in zip(scenes, graph.ray_base):
+        F, H, W = s.depth.shape
+        u, v = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+        d = np.stack([(u - s.intr.cx) / s.intr.fx, (v - s.intr.cy) / s.intr.fy, np.ones((H, W))], -1).reshape(-1, 3)
+        for f in range(F):
+            wn_ray[rb + f * H * W: rb + (f + 1) * H * W] = np.linalg.norm(d @ s.T_wc[f][:3, :3].T, axis=1)
+        sel = (ray >= rb) & (ray < rb + F * H * W)
+        key[sel] = f0 + (ray[sel] - rb) // (H * W)
+        f0 += F
+    return key, (graph.t_out - graph.t_in) * wn_ray[ray]
+
+
+def infer_keyframe_average(graph: Graph, theta, sigma_table, sweeps: int, key, weight,
+                           bias_table=None) -> Result:
+    """K sweeps with one length-weighted average message per keyframe and
+    voxel (Sec. IV-A); key and weight per edge (edge_keyframes_and_lengths)."""
+    theta = np.ascontiguousarray(theta, np.float64)
+    g = potentials(graph, sigma_table, bias_table)
+    E, V = graph.n_edges, graph.n_voxels
+    key = np.ascontiguousarray(key, np.int32)
+    weight = np.ascontiguousarray(weight, np.float64)
+    lam, ell, L = np.empty(E), np.empty(E), np.empty(V)
+    rc = lib().or_infer_keyframe_avg(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
+                                     _p(theta), _p(g), int(sweeps), _p(key), _p(weight), _p(lam), _p(ell), _p(L))
+    if rc != 0:
+        raise ValueError("keyframes must be grouped along every voxel's edge list")
+    return Result(L, lam, ell, g, None)
 
 
 def backward(graph: Graph, res: Result, Lbar, sigma_table, bias_table=None, want_bias: bool = False):
