@@ -116,3 +116,30 @@ def test_sparse_radius_out_of_range(RayMRF):
     with pytest.raises(_lib.MRFError) as ei:
         m.build(_sparse(S.make_fd(), 65))
     assert ei.value.code == _lib.MRF_EINVAL
+
+
+def test_sparse_grid_with_bias_table_and_metric(oracle, RayMRF):
+    """The three extensions together on fd: a sparse grid, a learnt bias table,
+    and the accuracy metric (which walks the whole grid) of the oracle's map."""
+    sc = _sparse(S.make_fd(), 1)
+    G = oracle.build_graph(sc)
+    sig32 = sc.sigma_table.astype(np.float32)
+    mu32 = S.bias_table(sc.sigma_table, 90).astype(np.float32)
+    th = sc.prior_logit()
+    ref = oracle.infer(G, th.astype(np.float64), sig32.astype(np.float64), sc.sweeps,
+                       bias_table=mu32.astype(np.float64))
+    m = RayMRF()
+    m.build(sc, keep_chords=False)
+    m.infer(torch.from_numpy(th).cuda(), torch.from_numpy(sig32).cuda(), sc.sweeps,
+            bias_table=torch.from_numpy(mu32).cuda())
+    p, _ = m.marginals()
+    assert np.abs(p.cpu().numpy() - ref.p).max() <= TOL_P
+    L32 = ref.L.astype(np.float32)
+    a = oracle.accuracy(sc, L32.astype(np.float64))
+    out = m.accuracy(torch.from_numpy(L32).cuda())
+    code = out["code"].cpu().numpy()
+    ev = a["code"] >= 0
+    clear = ev & (a["margin"] > 1e-9)
+    np.testing.assert_array_equal(code >= 0, ev)
+    np.testing.assert_array_equal(code[clear], a["code"][clear])
+    assert int(out["counts"].cpu().numpy()[0, 0]) == int(ev.sum())
