@@ -138,7 +138,7 @@ int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
  * (copied).  sigma_table: 64 floats > 0, the learnt depth-indexed Gaussian
  * sigma of Eq. noise (copied).  keep_checkpoints != 0 stores, for
  * mrf_backward, the ray->voxel messages of sweeps 1..K-1 ((sweeps - 1) * E
- * floats) and the voxel totals of sweeps 2..K ((sweeps - 1) * V floats),
+ * floats) and the voxel totals of sweeps 2..K ((sweeps - 1) * V FP32 pairs),
  * which together give every sweep's voxel->ray messages.  Errors: MRF_ESTATE
  * before mrf_build, MRF_EINVAL for sweeps < 1, MRF_ENOMEM. */
 int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
@@ -177,6 +177,21 @@ int mrf_backward(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
  * dsigma_table are bit-identical to mrf_backward's.  Errors: MRF_ESTATE. */
 int mrf_backward_sensor(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
                         float* dsigma_table, float* dbias_table, void* stream);
+
+/* Generation of the context's last inference: a counter that every
+ * successful mrf_infer / mrf_infer_sensor increments and every mrf_build
+ * increments too (a build discards the inference).  A caller that keeps
+ * results of one inference for a later reverse pass (an autograd node)
+ * records it and passes it to mrf_backward_gen.  Errors: MRF_EINVAL. */
+int mrf_generation(const mrf_ctx* ctx, uint64_t* out);
+
+/* mrf_backward_sensor for the inference of the given generation: returns
+ * MRF_ESTATE, with nothing enqueued, when the context's last inference is not
+ * that one (a later mrf_infer or mrf_build replaced its checkpoints), instead
+ * of differentiating the later inference.  dbias_table may be NULL.
+ * Errors: as mrf_backward_sensor, and MRF_ESTATE on a generation mismatch. */
+int mrf_backward_gen(mrf_ctx* ctx, uint64_t generation, const float* dloss_dlogit, float* dprior_logit,
+                     float* dsigma_table, float* dbias_table, void* stream);
 
 /* The accuracy metric of Sec. III-D for a map: every pixel of the scenes of
  * the last mrf_build with a usable measurement (z_min <= Z <= z_max) whose ray

@@ -152,7 +152,8 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
     if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
     const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
     int32_t cv[IPL];
-    float lo[IPL], eo[IPL], gv[IPL], lt[IPL], et[IPL];
+    float lo[IPL], eo[IPL], gv[IPL];
+    float2 lt[IPL], et[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {   // indices clamped to the ray (m >= 1): loads issued before any wait
         const int64_t at = s + kTile * (int64_t)min(i0 + j, m - 1);
@@ -224,6 +225,7 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
     {
         int32_t vc[NR];
         float vo[NR], vb[NR], vg[NR], vt[NR];
+        float2 pt[NR], pe[NR];
         tile_fetch_i<NT, NR>(col, td.base, nf, vc);
         tile_fetch<NT, NR>(lam.own, td.base, nf, vo);
         tile_fetch<NT, NR>(eb.own, td.base, nf, vb);
@@ -231,13 +233,13 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int cc = max(vc[r], 0);
-            vt[r] = lam.tot[cc];
-            ve[r] = eb.tot[cc];
+            pt[r] = lam.tot[cc];
+            pe[r] = eb.tot[cc];
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            vt[r] = excl_value(vc[r], vt[r], vo[r], lam.has_own);
-            ve[r] = excl_value(vc[r], ve[r], vb[r], eb.has_own);
+            vt[r] = excl_value(vc[r], pt[r], vo[r], lam.has_own);
+            ve[r] = excl_value(vc[r], pe[r], vb[r], eb.has_own);
         }
         tile_to_lds<NT, NR, IPL>(sa, nf, vt);
         tile_to_lds<NT, NR, IPL>(sb, nf, vg);
@@ -364,8 +366,12 @@ constexpr int SG_BLOCKS = 4096;   // blocks of the sigma-table reduction (at mos
 __device__ __forceinline__ void fx_add(unsigned long long* lo, long long* hi, double v)
 {
     // v as a signed 128-bit fixed-point number with 64 fractional bits
-    const double fl = floor(v);
-    const double fr = v - fl;                                   // [0, 1), exact
+    double fl = floor(v);
+    double fr = v - fl;   // in [0, 1] and exact, but it rounds to 1 for -2^-53 < v < 0
+    if (fr >= 1.0) {      // such a v is -0 in 64 fractional bits as well
+        fr = 0.0;
+        fl += 1.0;
+    }
     const unsigned long long l = (unsigned long long)(fr * 18446744073709551616.0);
     const long long h = (long long)fl;
     const unsigned long long old = atomicAdd(lo, l);

@@ -53,7 +53,7 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->fwd_sel[i]);
     const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_col,   &c->b_delta, &c->b_bin,  &c->b_g,    &c->b_lam,
                                  &c->b_ell,    &c->b_vedge, &c->b_vptr,  &c->b_theta, &c->b_L,   &c->b_sigma, &c->b_bias,
-                                 &c->b_ckpt,   &c->b_tsum,  &c->b_tbar,  &c->b_tiles, &c->b_counts};
+                                 &c->b_ckpt,   &c->b_tsum,  &c->b_tbar,  &c->b_tiles, &c->b_counts, &c->b_theta2};
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
     for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
     for (const auto& b : c->b_vox_list) k.push_back((uint64_t)(uintptr_t)b.p);
@@ -103,16 +103,16 @@ static float* ell_slot(const mrf_ctx* c, int K, int k, bool keep)
     return ((K - k) & 1) ? (float*)c->b_lam.p : (float*)c->b_ell.p;
 }
 
-// voxel totals that sweep k (2..K) reads: theta plus the ray messages of sweep k-1
-static float* tot_slot(const mrf_ctx* c, int k, bool keep)
+// voxel total pairs that sweep k (2..K) reads: theta plus the ray messages of sweep k-1
+static float2* tot_slot(const mrf_ctx* c, int k, bool keep)
 {
-    return (float*)c->b_tsum.p + (keep ? (size_t)(k - 2) * (size_t)c->V : 0);
+    return (float2*)c->b_tsum.p + (keep ? (size_t)(k - 2) * (size_t)c->V : 0);
 }
 
 // the voxel->ray messages of sweep k (1..K): lambda_e = tot[col_e] - own_e
 static ExclSrc lam_src(const mrf_ctx* c, int K, int k, bool keep)
 {
-    if (k == 1) return ExclSrc{(const float*)c->b_theta.p, nullptr};   // no incoming message yet
+    if (k == 1) return ExclSrc{(const float2*)c->b_theta2.p, nullptr};   // no incoming message yet
     return ExclSrc{tot_slot(c, k, keep), ell_slot(c, K, k - 1, keep)};
 }
 
@@ -121,16 +121,17 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
 {
     hipError_t e;
     const float* theta = (const float*)c->b_theta.p;
+    if ((e = launch_pair(theta, (float2*)c->b_theta2.p, c->V, s)) != hipSuccess) return e;
     if ((e = launch_potentials(c, s)) != hipSuccess) return e;
     for (int k = 1; k <= K; ++k) {
-        if (k > 1 && (e = launch_voxel_phase(c, theta, ell_slot(c, K, k - 1, keep), tot_slot(c, k, keep), nullptr,
-                                             s)) != hipSuccess)
+        if (k > 1 && (e = launch_voxel_phase(c, ell_slot(c, K, k - 1, keep),
+                                             VoxOut{theta, tot_slot(c, k, keep), nullptr, nullptr}, s)) != hipSuccess)
             return e;
         if ((e = launch_ray_phase(c, lam_src(c, K, k, keep), ell_slot(c, K, k, keep), plain, s)) != hipSuccess)
             return e;
     }
     if ((e = launch_copy((float*)c->b_L.p, theta, c->V, s)) != hipSuccess) return e;
-    return launch_voxel_phase(c, theta, ell_slot(c, K, K, keep), (float*)c->b_L.p, nullptr, s);
+    return launch_voxel_phase(c, ell_slot(c, K, K, keep), VoxOut{theta, nullptr, (float*)c->b_L.p, nullptr}, s);
 }
 
 static const float* final_ell(const mrf_ctx* c) { return c->inferred ? (const float*)c->b_ell.p : nullptr; }
@@ -191,7 +192,8 @@ void mrf_destroy(mrf_ctx* c)
     drop_graph(c);
     DevBuf* all[] = {&c->b_scenes, &c->b_frames, &c->b_counts, &c->b_rowptr, &c->b_col, &c->b_delta,
                      &c->b_bin, &c->b_tin, &c->b_tout, &c->b_g, &c->b_lam, &c->b_ell, &c->b_vedge,
-                     &c->b_vptr, &c->b_theta, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias, &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric, &c->b_bricks,
+                     &c->b_vptr, &c->b_theta, &c->b_theta2, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias,
+                     &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric, &c->b_bricks,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
     for (DevBuf* b : all) free_buf(*b);
@@ -221,6 +223,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_build: hipSetDevice");
     c->built = c->inferred = c->have_ckpt = 0;   // a cached graph is revalidated by mrf_infer
+    ++c->gen;
 
     c->scenes_h.clear();
     c->frames_h.clear();
@@ -363,7 +366,8 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_theta, vb), "mrf_build: alloc theta");
     HCK(ensure(c->b_L, vb), "mrf_build: alloc L");
     HCK(ensure(c->b_thetabar, vb), "mrf_build: alloc thetabar");
-    HCK(ensure(c->b_tbar, 2 * vb), "mrf_build: alloc voxel sums");
+    HCK(ensure(c->b_theta2, 2 * vb), "mrf_build: alloc theta pairs");
+    HCK(ensure(c->b_tbar, 3 * 2 * vb), "mrf_build: alloc voxel sums");
     HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
     HCK(ensure(c->b_bias, sizeof(float) * kBins), "mrf_build: alloc bias");
     HCK(ensure(c->b_sigpart, kSigPartBytes + sizeof(float) * kBins), "mrf_build: alloc table partials");
@@ -433,9 +437,9 @@ int mrf_infer_sensor(mrf_ctx* c, const float* prior_logit, const float* sigma_ta
     HCK(hipSetDevice(c->device), "mrf_infer: hipSetDevice");
     const int keep = keep_checkpoints ? 1 : 0;
     {
-        // checkpoints: ell of sweeps 1..K-1 and the voxel totals of sweeps 2..K
+        // checkpoints: ell of sweeps 1..K-1 and the voxel total pairs of sweeps 2..K
         const size_t need_ell = keep ? sizeof(float) * (size_t)(sweeps - 1) * (size_t)c->S : 0;
-        const size_t need_tot = sizeof(float) * (size_t)(keep && sweeps > 2 ? sweeps - 1 : 1) * (size_t)c->V;
+        const size_t need_tot = sizeof(float2) * (size_t)(keep && sweeps > 2 ? sweeps - 1 : 1) * (size_t)c->V;
         if (c->b_ckpt.cap < need_ell || c->b_tsum.cap < need_tot) {
             drop_graph(c);   // the graph holds the old addresses
             HCK(ensure(c->b_ckpt, need_ell), "mrf_infer: alloc checkpoints");
@@ -476,6 +480,7 @@ int mrf_infer_sensor(mrf_ctx* c, const float* prior_logit, const float* sigma_ta
         HCK(hipStreamWaitEvent(s, c->ev_out, 0), "mrf_infer: wait");
     }
     c->inferred = 1;
+    ++c->gen;
     c->K = sweeps;
     c->have_ckpt = keep;
     c->stats.sweeps_done = sweeps;
@@ -508,24 +513,43 @@ int mrf_backward_sensor(mrf_ctx* c, const float* dlogit, float* dprior, float* d
     const int K = c->K;
     float* gsum = (float*)c->b_gsum.p;
     float* thetabar = (float*)c->b_thetabar.p;
-    float* tbar = (float*)c->b_tbar.p;
+    float2* tbar = (float2*)c->b_tbar.p;
+    float2* seed = tbar + c->V;
     float* lbuf[2] = {(float*)c->b_lambar.p, (float*)c->b_ellbar.p};
     // d loss / d theta starts at d loss / d L; d loss / d ell^(K)_e = d loss / d L_v(e)
     HCK(launch_copy(thetabar, dlogit, c->V, s), "mrf_backward: seed");
-    ExclSrc eb{dlogit, nullptr};
+    HCK(launch_pair(dlogit, seed, c->V, s), "mrf_backward: seed");
+    ExclSrc eb{seed, nullptr};
     hipError_t e = hipSuccess;
     for (int k = K; k >= 1 && e == hipSuccess; --k) {
         // sweep k: d/d lambda^(k) from the ray adjoint, then its per-voxel sums, which
         // give d/d theta and (less the edge's own) d/d ell^(k-1)
         float* lb = lbuf[(K - k) & 1];
         e = launch_ray_adjoint(c, lam_src(c, K, k, true), eb, lb, gsum, k == K, s);
-        if (e == hipSuccess) e = launch_voxel_phase(c, nullptr, lb, k > 1 ? tbar : nullptr, thetabar, s);
+        if (e == hipSuccess) e = launch_voxel_phase(c, lb, VoxOut{nullptr, k > 1 ? tbar : nullptr, nullptr, thetabar}, s);
         eb = ExclSrc{tbar, lb};
     }
     HCK(e, "mrf_backward: sweeps");
     if (dsigma || dbias) HCK(launch_sigma_grad(c, dsigma, dbias, s), "mrf_backward: sensor-table gradients");
     if (dprior) HCK(launch_copy(dprior, thetabar, c->V, s), "mrf_backward: copy");
     return MRF_OK;
+}
+
+int mrf_generation(const mrf_ctx* c, uint64_t* out)
+{
+    if (!c || !out) return fail(MRF_EINVAL, "mrf_generation: null argument");
+    *out = c->gen;
+    return MRF_OK;
+}
+
+int mrf_backward_gen(mrf_ctx* c, uint64_t generation, const float* dlogit, float* dprior, float* dsigma,
+                     float* dbias, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_backward_gen: null context");
+    if (generation != c->gen)
+        return fail(MRF_ESTATE, "mrf_backward_gen: the inference to differentiate was replaced by a later "
+                                "mrf_infer or mrf_build on this context");
+    return mrf_backward_sensor(c, dlogit, dprior, dsigma, dbias, stream);
 }
 
 int mrf_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* ray_code, double* surface_depth,
@@ -662,20 +686,20 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
     // inference state stays untouched
     const float* theta = (const float*)c->b_theta.p;
     const float* ell_in = final_ell(c);
-    float* vt = (float*)c->b_tbar.p;
+    float2* vt = (float2*)c->b_tbar.p;
     float* ell = (float*)c->b_ellbar.p;
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
-        e = launch_voxel_phase(c, theta, ell_in, vt, nullptr, s);
+        e = launch_voxel_phase(c, ell_in, VoxOut{theta, vt, nullptr, nullptr}, s);
         if (e == hipSuccess) e = launch_ray_phase(c, ExclSrc{vt, ell_in}, ell, false, s);
     }
     if (include_backward) {
         float* lambar = (float*)c->b_lambar.p;
         float* gsum = (float*)c->b_gsum.p;
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
-            e = launch_ray_adjoint(c, ExclSrc{vt, ell_in}, ExclSrc{(const float*)c->b_L.p, ell}, lambar, gsum,
-                                   r == 0, s);
+            e = launch_ray_adjoint(c, ExclSrc{vt, ell_in}, ExclSrc{vt, ell}, lambar, gsum, r == 0, s);
             if (e == hipSuccess)
-                e = launch_voxel_phase(c, nullptr, lambar, vt + c->V, (float*)c->b_thetabar.p, s);
+                e = launch_voxel_phase(c, lambar, VoxOut{nullptr, vt + 2 * c->V, nullptr, (float*)c->b_thetabar.p},
+                                       s);
         }
         if (e == hipSuccess)
             e = launch_sigma_grad(c, (float*)((char*)c->b_sigpart.p + kSigPartBytes), nullptr, s);
@@ -756,7 +780,7 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
     // inputs: the last sweep's messages; outputs go to buffers the reverse pass
     // initialises before use, so the inference state stays untouched
     const ExclSrc lam = final_lam(c);
-    const ExclSrc eb{(const float*)c->b_L.p, nullptr};
+    const ExclSrc eb{(const float2*)c->b_theta2.p, nullptr};   // any d/d ell input serves for timing
     float* ell_out = (float*)c->b_ellbar.p;
     float* lambar = (float*)c->b_lambar.p;
     float* gsum = (float*)c->b_gsum.p;

@@ -449,6 +449,63 @@ __device__ __forceinline__ float wave_sum(float x)
     return readlane(x, 63);
 }
 
+// ---------------------------------------------------------------- FP64 sums
+// The voxel totals are accumulated in FP64: every FP32 term is exact in FP64,
+// so a total that nearly cancels against one of its own terms (a voxel whose
+// receiving ray sent a message of 1e9 while the others sum to a few units)
+// keeps the small remainder.  DPP moves a double as its two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double old, double src)
+{
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), s = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)s, CTRL, 0xF, 0xF,
+                                                              false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(s >> 32),
+                                                              CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over each group of G = 16, 32 or 64 consecutive lanes in a fixed order
+// (a suffix scan inside each 16-lane row, then the rows of the group in order),
+// valid at the group's first lane.
+template <int G>
+__device__ __forceinline__ double dgroup_sum_d(double x)
+{
+    static_assert(G == 16 || G == 32 || G == 64, "groups are rows, half-waves or waves");
+    x = x + dpp_d<DPP_ROW_SHL1>(0.0, x);
+    x = x + dpp_d<DPP_ROW_SHL2>(0.0, x);
+    x = x + dpp_d<DPP_ROW_SHL4>(0.0, x);
+    x = x + dpp_d<DPP_ROW_SHL8>(0.0, x);
+    if (G == 32) {
+        const double t1 = readlane_d(x, 16), t3 = readlane_d(x, 48);
+        x = x + ((threadIdx.x & 32) ? t3 : t1);   // meaningful at lanes 0 and 32
+    }
+    if (G == 64) {
+        const double t1 = readlane_d(x, 16), t2 = readlane_d(x, 32), t3 = readlane_d(x, 48);
+        x = x + (t1 + (t2 + t3));   // meaningful at lane 0
+    }
+    return x;
+}
+
+// sum over a wave in FP64, the same value in every lane
+__device__ __forceinline__ double wave_sum_d(double x) { return readlane_d(dgroup_sum_d<64>(x), 0); }
+
+// A double as the unevaluated FP32 pair (hi, lo), hi = fl(x), lo = fl(x - hi):
+// x to about 2^-48 of its magnitude.
+__device__ __forceinline__ float2 split_pair(double x)
+{
+    const float hi = (float)x;
+    return make_float2(hi, (float)(x - (double)hi));
+}
+
 // Block index remapped so that each XCD (blocks are dealt to the 8 XCDs
 // round-robin) works on one contiguous range of logical blocks, keeping
 // neighbouring work items in the same L2.

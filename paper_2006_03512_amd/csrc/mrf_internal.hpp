@@ -162,18 +162,32 @@ struct TileDev {
 
 // Per-edge voxel -> ray messages (forward) or d/d ell (reverse) in the form the
 // ray kernels read them: value_e = tot[col_e] - own_e, tot a per-voxel total
-// (linear voxel id) and own_e the edge's own term in it (own null: 0).
+// (linear voxel id) and own_e the edge's own term in it (own null: 0).  A total
+// is the FP32 pair (hi, lo) of its FP64 sum, and the value is formed as
+// (hi - own) + lo: when own is most of the total, hi - own is exact and the
+// remainder keeps the accuracy of the FP64 sum instead of losing itself in the
+// rounding of a total of magnitude |own|.
 struct ExclSrc {
-    const float* tot;
+    const float2* tot;
     const float* own;
 };
 
 // The kernel-side form: own always points at a readable per-slot array (the
 // potentials g when absent), with has_own telling whether to use it.
 struct ExclDev {
-    const float* tot;
+    const float2* tot;
     const float* own;
     int has_own;
+};
+
+// Outputs of a voxel-phase reduction of sum_v (the FP64 sum of a per-edge
+// array over voxel v's edges), each optional: tot2[v] = pair(base[v] + sum_v),
+// totf[v] = fl(base[v] + sum_v), acc[v] += fl(sum_v); base null reads as 0.
+struct VoxOut {
+    const float* base;
+    float2* tot2;
+    float* totf;
+    float* acc;
 };
 
 // Work item of the voxel kernels: one voxel's edge list vedge[start, start + m)
@@ -244,11 +258,12 @@ struct mrf_ctx {
         b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_bias, b_ckpt,
         b_ellbar, b_lambar, b_gsum, b_tmp64, b_cls, b_sigpart, b_misc;
     mrf::DevBuf b_tiles, b_tbase;
-    mrf::DevBuf b_tsum;   // per-voxel totals of the sweeps (theta + incoming ray messages)
+    mrf::DevBuf b_tsum;   // per-voxel totals of the sweeps (theta + incoming ray messages), float2 pairs
+    mrf::DevBuf b_theta2; // the prior log-odds as total pairs (theta, 0): the first sweep's lambda
     mrf::DevBuf b_metric; // accuracy metric: per-voxel alpha and log alpha (2 V doubles)
     mrf::DevBuf b_bricks; // sparse grid: one byte per 8^3 brick of every scene
     int64_t n_bricks = 0;
-    mrf::DevBuf b_tbar;   // per-voxel sums of d/d lambda in the reverse pass (2 V: one spare)
+    mrf::DevBuf b_tbar;   // reverse pass, float2 pairs: per-voxel sums of d/d lambda, the seed d/d L, a spare
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
     mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
     mrf::DevBuf b_vox_list[mrf::kVoxClasses];     // brick-major keys
@@ -267,6 +282,7 @@ struct mrf_ctx {
 
     // state
     int built = 0, inferred = 0, K = 0, have_ckpt = 0;
+    uint64_t gen = 0;   // bumped by every build and every successful inference
     int schedule = MRF_SCHED_GRAPH;
 
     // graph cache
@@ -336,10 +352,11 @@ inline ExclDev excl_dev(const mrf_ctx* c, ExclSrc x)
 hipError_t launch_potentials(mrf_ctx* c, hipStream_t s);
 hipError_t launch_fill(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
-// voxel phase: per touched voxel v, sum_v = sum of in over its edges;
-// tout[v] = base[v] + sum_v (base null: 0) and / or tacc[v] += sum_v (each may be null)
-hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* tout, float* tacc,
-                              hipStream_t s);
+// voxel phase: per touched voxel v, sum_v = FP64 sum of in over its edges,
+// written as VoxOut describes
+hipError_t launch_voxel_phase(mrf_ctx* c, const float* in, VoxOut out, hipStream_t s);
+// out[v] = (in[v], 0): a per-voxel array as a total pair
+hipError_t launch_pair(const float* in, float2* out, int64_t n, hipStream_t s);
 hipError_t launch_ray_phase(mrf_ctx* c, ExclSrc lam, float* ell, bool plain, hipStream_t s);
 // one class of the ray phase / reverse pass with launch shape `sel` (autotuner)
 hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam, float* ell, hipStream_t s);

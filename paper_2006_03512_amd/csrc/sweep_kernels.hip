@@ -9,11 +9,13 @@
 //   g_e    log nu(d_e) = log N(Z; d_e, sigma(d_e))   (Eq. noise)
 //
 // Voxel phase: per touched voxel the total tot_v = theta_v + sum of every
-// incoming ray message, a fixed-order reduction over its edge list.  Eq.
-// node_to_factor (every incoming message but the receiving ray's own) is then
-// lam_e = tot_v(e) - ell_e, which the ray kernels form as they stage their
-// tiles: no per-edge scatter.  The subtraction adds one rounding at the
-// magnitude of tot_v, the order of the sum's own rounding error.
+// incoming ray message, a fixed-order FP64 reduction over its edge list kept
+// as the FP32 pair (hi, lo).  Eq. node_to_factor (every incoming message but
+// the receiving ray's own) is then lam_e = (hi_v(e) - ell_e) + lo_v(e), which
+// the ray kernels form as they stage their tiles: no per-edge scatter.  When
+// the edge's own message is most of the total (a message of 1e9 against
+// others summing to a few units), hi - ell_e is exact and lam_e keeps the
+// accuracy of the FP64 sum.
 // Ray phase: one group of lanes per ray.  With P_i = sum_{k<i} log mu_k(0),
 //   S_i = LSE_{j<i} (log mu_j(1) + g_j + P_j)
 //   Q_i = LSE(log mu_{i+1}(1) + g_{i+1}, log mu_{i+1}(0) + Q_{i+1})
@@ -46,6 +48,12 @@ __global__ void copy_k(float* __restrict__ d, const float* __restrict__ s, int64
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         d[i] = s[i];
+}
+
+__global__ void pair_k(const float* __restrict__ in, float2* __restrict__ out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = make_float2(in[i], 0.0f);
 }
 
 __global__ void excl_k(const int32_t* __restrict__ col, ExclDev x, float* __restrict__ out, int64_t E)
@@ -145,6 +153,13 @@ hipError_t launch_copy(float* d, const float* src, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_pair(const float* in, float2* out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pair_k, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_excl(const mrf_ctx* c, ExclSrc x, float* out, hipStream_t s)
 {
     if (c->S <= 0) return hipSuccess;
@@ -176,16 +191,17 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 //
 // The voxel phase reduces: for every touched voxel v, sum_v = the sum of its
 // incoming per-edge values (ray messages forward, d/d lambda in reverse), in a
-// fixed order, written as tout[v] = base[v] + sum_v and/or added to tacc[v].
-// The voxel -> ray message of edge e is then tot[v(e)] - own_e, formed by the
-// ray kernels as they stage their tiles (no per-edge scatter here).
+// fixed order and in FP64 (every FP32 term is exact there), written as VoxOut
+// describes.  The voxel -> ray message of edge e is then formed from the total
+// pair and the edge's own term by the ray kernels as they stage their tiles
+// (no per-edge scatter here).
 
-// Sum over items base + 64 k + l (k < N, l the lane) of the edge list
+// FP64 sum over items base + 64 k + l (k < N, l the lane) of the edge list
 // [s, s+m) of one voxel (0 past m).  Branchless, with item indices clamped to
 // m - 1 (m >= 1), so that every load is issued before the first wait.
 template <int N>
-__device__ __forceinline__ float vox_lane_sum(int64_t s, int m, int base, const uint32_t* __restrict__ vedge,
-                                              const float* __restrict__ in)
+__device__ __forceinline__ double vox_lane_sum(int64_t s, int m, int base, const uint32_t* __restrict__ vedge,
+                                               const float* __restrict__ in)
 {
     const int l = threadIdx.x & 63;
     uint32_t e[N];
@@ -194,17 +210,18 @@ __device__ __forceinline__ float vox_lane_sum(int64_t s, int m, int base, const 
     for (int k = 0; k < N; ++k) e[k] = vedge[s + min(base + k * 64 + l, m - 1)];
 #pragma unroll
     for (int k = 0; k < N; ++k) x[k] = in[e[k]];
-    float a = 0.0f;
+    double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) a += base + k * 64 + l < m ? x[k] : 0.0f;
+    for (int k = 0; k < N; ++k) a += base + k * 64 + l < m ? (double)x[k] : 0.0;
     return a;
 }
 
-__device__ __forceinline__ void vox_store(uint32_t v, float sum, const float* __restrict__ base,
-                                          float* __restrict__ tout, float* __restrict__ tacc)
+__device__ __forceinline__ void vox_store(uint32_t v, double sum, const VoxOut& o)
 {
-    if (tout) tout[v] = (base ? base[v] : 0.0f) + sum;
-    if (tacc) tacc[v] += sum;
+    const double t = (o.base ? (double)o.base[v] : 0.0) + sum;
+    if (o.tot2) o.tot2[v] = split_pair(t);
+    if (o.totf) o.totf[v] = (float)t;
+    if (o.acc) o.acc[v] += (float)sum;
 }
 
 // One voxel's edge list [s, s+m) summed by NW waves, each owning 64*IPL
@@ -215,9 +232,9 @@ __device__ __forceinline__ void vox_store(uint32_t v, float sum, const float* __
 // Voxels arrive in brick-major order and blocks are remapped so each XCD
 // takes a contiguous range of them.
 template <int NW, int IPL, int VPW>
-__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
-    const VoxDev* __restrict__ vd, int64_t n, const uint32_t* __restrict__ vedge, const float* __restrict__ base,
-    const float* __restrict__ in, float* __restrict__ tout, float* __restrict__ tacc)
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev* __restrict__ vd, int64_t n,
+                                                                   const uint32_t* __restrict__ vedge,
+                                                                   const float* __restrict__ in, VoxOut out)
 {
     static_assert(NW == 1 || VPW == 1, "several voxels per wave only with one wave per voxel");
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -240,23 +257,25 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
             for (int k = 0; k < IPL; ++k) x[u][k] = in[e[u][k]];
 #pragma unroll
         for (int u = 0; u < VPW; ++u) {
-            float a = 0.0f;
+            double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) a += k * 64 + l < d[u].m ? x[u][k] : 0.0f;
-            a = wave_sum(a);
-            if (l == 0 && v0 + u < n) vox_store(d[u].v, a, base, tout, tacc);
+            for (int k = 0; k < IPL; ++k) a += k * 64 + l < d[u].m ? (double)x[u][k] : 0.0;
+            a = dgroup_sum_d<64>(a);
+            if (l == 0 && v0 + u < n) vox_store(d[u].v, a, out);
         }
     } else {
         const int64_t vi = lb;
         if (vi >= n) return;   // whole block
         const VoxDev d = vd[vi];
-        float tot = wave_sum(vox_lane_sum<IPL>(d.start, d.m, wv * 64 * IPL, vedge, in));
-        __shared__ float wsum[NW];
-        if (l == 0) wsum[wv] = tot;
+        const double a = dgroup_sum_d<64>(vox_lane_sum<IPL>(d.start, d.m, wv * 64 * IPL, vedge, in));
+        __shared__ double wsum[NW];
+        if (l == 0) wsum[wv] = a;
         __syncthreads();
-        tot = 0.0f;
-        for (int q = 0; q < NW; ++q) tot += wsum[q];
-        if (threadIdx.x == 0) vox_store(d.v, tot, base, tout, tacc);
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int q = 0; q < NW; ++q) tot += wsum[q];
+            vox_store(d.v, tot, out);
+        }
     }
 }
 
@@ -265,9 +284,8 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(
 // l holds edge l of each; group reductions), every load issued first.
 template <int G, int VPG>
 __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ vd, int64_t n,
-                                                     const uint32_t* __restrict__ vedge,
-                                                     const float* __restrict__ base, const float* __restrict__ in,
-                                                     float* __restrict__ tout, float* __restrict__ tacc)
+                                                     const uint32_t* __restrict__ vedge, const float* __restrict__ in,
+                                                     VoxOut out)
 {
     constexpr int GPB = 256 / G;   // groups per block
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -285,8 +303,8 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
     for (int u = 0; u < VPG; ++u) x[u] = in[e[u]];
 #pragma unroll
     for (int u = 0; u < VPG; ++u) {
-        const float sum = drscan<G, OpAdd>(l < d[u].m ? x[u] : 0.0f);   // at group lane 0: the voxel's sum
-        if (l == 0 && v0 + u < n) vox_store(d[u].v, sum, base, tout, tacc);
+        const double sum = dgroup_sum_d<G>(l < d[u].m ? (double)x[u] : 0.0);   // at group lane 0
+        if (l == 0 && v0 + u < n) vox_store(d[u].v, sum, out);
     }
 }
 
@@ -295,30 +313,28 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
 // wave sums are added in wave order.
 __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict__ vd, int64_t n,
                                                         const uint32_t* __restrict__ vedge,
-                                                        const float* __restrict__ base, const float* __restrict__ in,
-                                                        float* __restrict__ tout, float* __restrict__ tacc)
+                                                        const float* __restrict__ in, VoxOut out)
 {
-    __shared__ float wsum[16];
+    __shared__ double wsum[16];
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= n) return;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const VoxDev d = vd[b];
     const int nch = (d.m + kVoxChunk - 1) / kVoxChunk;
-    float a = 0.0f;
+    double a = 0.0;
     for (int c = wv; c < nch; c += 16) a += vox_lane_sum<kVoxChunk / 64>(d.start, d.m, c * kVoxChunk, vedge, in);
-    a = wave_sum(a);
+    a = dgroup_sum_d<64>(a);
     if (l == 0) wsum[wv] = a;
     __syncthreads();
     if (threadIdx.x == 0) {
-        float tot = 0.0f;
+        double tot = 0.0;
         for (int q = 0; q < 16; ++q) tot += wsum[q];
-        vox_store(d.v, tot, base, tout, tacc);
+        vox_store(d.v, tot, out);
     }
 }
 
 template <int K>
-static void launch_voxel_class(mrf_ctx* c, const float* base, const float* in, float* tout, float* tacc,
-                               hipStream_t s)
+static void launch_voxel_class(mrf_ctx* c, const float* in, VoxOut out, hipStream_t s)
 {
     const int64_t n = c->vox_cnt[K];
     if (n <= 0) return;
@@ -328,35 +344,31 @@ static void launch_voxel_class(mrf_ctx* c, const float* base, const float* in, f
         constexpr int G = kVoxCap[K];
         constexpr int VPG = kVoxVPW[K];
         hipLaunchKernelGGL((voxel_small_k<G, VPG>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s,
-                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, tout,
-                           tacc);
+                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, in, out);
     } else {
         constexpr int IPL = kVoxCap[K] / (64 * NW);
         constexpr int VPW = kVoxVPW[K];
         const unsigned blocks = NW == 1 ? nblk(n, 4 * VPW) : (unsigned)n;
         hipLaunchKernelGGL((voxel_k<NW, IPL, VPW>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
-                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, base, in, tout,
-                           tacc);
+                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, in, out);
     }
 }
 
 template <int... K>
-static void voxel_classes(std::integer_sequence<int, K...>, mrf_ctx* c, const float* base, const float* in,
-                          float* tout, float* tacc, hipStream_t s)
+static void voxel_classes(std::integer_sequence<int, K...>, mrf_ctx* c, const float* in, VoxOut out, hipStream_t s)
 {
-    (launch_voxel_class<K>(c, base, in, tout, tacc, s), ...);
+    (launch_voxel_class<K>(c, in, out, s), ...);
 }
 
-hipError_t launch_voxel_phase(mrf_ctx* c, const float* base, const float* in, float* tout, float* tacc,
-                              hipStream_t s)
+hipError_t launch_voxel_phase(mrf_ctx* c, const float* in, VoxOut out, hipStream_t s)
 {
-    voxel_classes(std::make_integer_sequence<int, kVoxClasses - 1>{}, c, base, in, tout, tacc, s);
+    voxel_classes(std::make_integer_sequence<int, kVoxClasses - 1>{}, c, in, out, s);
     const int kc = kVoxClasses - 1;
     if (c->vox_cnt[kc] > 0) {
         ProfScope ps(c, KID_VOX0 + kc, s);
         hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, s,
-                           (const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p, base,
-                           in, tout, tacc);
+                           (const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p, in,
+                           out);
     }
     return hipGetLastError();
 }
@@ -426,7 +438,8 @@ __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, 
     if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
     const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
     int32_t cv[IPL];
-    float ov[IPL], gv[IPL], tv[IPL];
+    float ov[IPL], gv[IPL];
+    float2 tv[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int64_t at = s + kTile * (int64_t)min(i0 + j, m - 1);
@@ -473,13 +486,14 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
     {
         int32_t vc[IPL];
         float vo[IPL], vg[IPL], vt[IPL];
+        float2 vp[IPL];
         tile_fetch_i<NT, IPL>(col, td.base, nf, vc);
         tile_fetch<NT, IPL>(lam.own, td.base, nf, vo);
         tile_fetch<NT, IPL>(g, td.base, nf, vg);
 #pragma unroll
-        for (int r = 0; r < IPL; ++r) vt[r] = lam.tot[max(vc[r], 0)];
+        for (int r = 0; r < IPL; ++r) vp[r] = lam.tot[max(vc[r], 0)];
 #pragma unroll
-        for (int r = 0; r < IPL; ++r) vt[r] = excl_value(vc[r], vt[r], vo[r], lam.has_own);
+        for (int r = 0; r < IPL; ++r) vt[r] = excl_value(vc[r], vp[r], vo[r], lam.has_own);
         tile_to_lds<NT, IPL, IPL>(sl, nf, vt);
         tile_to_lds<NT, IPL, IPL>(sg, nf, vg);
     }

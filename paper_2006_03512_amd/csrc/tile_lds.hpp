@@ -107,10 +107,13 @@ __device__ __forceinline__ void tile_store(float* __restrict__ dst, int64_t base
 
 // Per-edge value tot[col] - own (the voxel's total less the edge's own term;
 // own absent when has_own is 0), 0 on padding slots (col < 0).  t is the
-// gathered tot[max(col, 0)]; selects, so stale bits on padding never propagate.
-__device__ __forceinline__ float excl_value(int32_t col, float t, float own, int has_own)
+// gathered total pair (hi, lo) of tot[max(col, 0)]: (hi - own) + lo, where
+// hi - own is exact whenever own is within a factor two of hi (Sterbenz), so
+// a near-total cancellation leaves lo and the FP64 sum's accuracy.  Selects,
+// so stale bits on padding never propagate.
+__device__ __forceinline__ float excl_value(int32_t col, float2 t, float own, int has_own)
 {
-    return col >= 0 ? t - (has_own ? own : 0.0f) : 0.0f;
+    return col >= 0 ? (t.x - (has_own ? own : 0.0f)) + t.y : 0.0f;
 }
 
 // The fetched values into the LDS image of the tile (layout lds_at<IPL>).

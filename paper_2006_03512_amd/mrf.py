@@ -165,12 +165,26 @@ class RayMRF:
         check(self._L.mrf_marginals(self._h, ptr(p), ptr(logit), stream_handle(stream)), "mrf_marginals")
         return p, logit
 
-    def backward(self, dloss_dlogit, want_prior=True, want_sigma=True, stream=None, want_bias=False):
+    def generation(self) -> int:
+        """Generation of the last inference (changes with every infer and build)."""
+        g = C.c_uint64()
+        check(self._L.mrf_generation(self._h, C.byref(g)), "mrf_generation")
+        return g.value
+
+    def backward(self, dloss_dlogit, want_prior=True, want_sigma=True, stream=None, want_bias=False,
+                 generation=None):
         """(d loss/d prior, d loss/d sigma), with want_bias also d loss/d bias
-        appended; an output not wanted is None."""
+        appended; an output not wanted is None.  With `generation` (from
+        generation() right after the inference) the call fails with MRF_ESTATE
+        if a later infer or build replaced that inference."""
         self._vec(dloss_dlogit, self.n_voxels, "dloss_dlogit")
         dp = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device) if want_prior else None
         ds = torch.empty(N_BINS, dtype=torch.float32, device=self.device) if want_sigma else None
+        if generation is not None:
+            db = torch.empty(N_BINS, dtype=torch.float32, device=self.device) if want_bias else None
+            check(self._L.mrf_backward_gen(self._h, C.c_uint64(int(generation)), ptr(dloss_dlogit), ptr(dp),
+                                           ptr(ds), ptr(db), stream_handle(stream)), "mrf_backward_gen")
+            return (dp, ds, db) if want_bias else (dp, ds)
         if not want_bias:
             check(self._L.mrf_backward(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), stream_handle(stream)),
                   "mrf_backward")
@@ -288,6 +302,7 @@ class MRFInfer(torch.autograd.Function):
                   bias_table=None if bias_table is None else bias_table.detach().contiguous())
         _, logit = mrf.marginals()
         ctx.mrf = mrf
+        ctx.generation = mrf.generation()   # a later forward on the same context invalidates this node
         ctx.has_bias = bias_table is not None
         return logit
 
@@ -295,5 +310,6 @@ class MRFInfer(torch.autograd.Function):
     def backward(ctx, g):
         want_bias = ctx.has_bias and ctx.needs_input_grad[4]
         out = ctx.mrf.backward(g.contiguous().float(), want_prior=ctx.needs_input_grad[1],
-                               want_sigma=ctx.needs_input_grad[2], want_bias=want_bias)
+                               want_sigma=ctx.needs_input_grad[2], want_bias=want_bias,
+                               generation=ctx.generation)
         return None, out[0], out[1], None, (out[2] if want_bias else None)

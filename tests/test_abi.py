@@ -40,6 +40,8 @@ def test_null_arguments_are_rejected():
     assert L.mrf_infer_sensor(None, None, None, None, 1, 0, None) == _lib.MRF_EINVAL
     assert L.mrf_backward_sensor(None, None, None, None, None, None) == _lib.MRF_EINVAL
     assert L.mrf_accuracy(None, None, 0.5, None, None, None, None) == _lib.MRF_EINVAL
+    assert L.mrf_generation(None, None) == _lib.MRF_EINVAL
+    assert L.mrf_backward_gen(None, 0, None, None, None, None, None) == _lib.MRF_EINVAL
     st = _lib.Stats()
     assert L.mrf_stats(None, C.byref(st)) == _lib.MRF_EINVAL
     assert L.mrf_set_schedule(None, 0) == _lib.MRF_EINVAL

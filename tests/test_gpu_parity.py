@@ -349,3 +349,39 @@ def test_empty_graph(RayMRF):
     dp, ds = m.backward(torch.ones_like(th))
     np.testing.assert_array_equal(dp.cpu().numpy(), 1.0)
     np.testing.assert_array_equal(ds.cpu().numpy(), 0.0)
+
+
+def test_stale_backward_is_refused(RayMRF):
+    """Two forwards on one context, then the first graph's backward: the
+    library refuses it (its checkpoints belong to the second inference)
+    instead of returning the second inference's gradients.  The second
+    graph's backward still runs, and equals a backward right after its own
+    forward."""
+    from paper_2006_03512_amd import _lib
+    from paper_2006_03512_amd.mrf import MRFInfer
+    sc = S.make_fd()
+    m = _gpu(RayMRF, sc, keep_chords=False)
+    y = torch.from_numpy(sc.occupancy()).cuda()
+    sig = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
+
+    def forward(scale):
+        th = (torch.from_numpy(sc.prior_logit()).cuda() * scale).requires_grad_(True)
+        L = MRFInfer.apply(m, th, sig, 4)
+        return th, torch.nn.functional.binary_cross_entropy_with_logits(L, y)
+
+    th_a, loss_a = forward(1.0)
+    th_b, loss_b = forward(0.5)
+    with pytest.raises(_lib.MRFError) as ei:
+        loss_a.backward()
+    assert ei.value.code == _lib.MRF_ESTATE
+    loss_b.backward()
+    g_late = th_b.grad.cpu().numpy().copy()
+    th_c, loss_c = forward(0.5)
+    loss_c.backward()
+    np.testing.assert_array_equal(g_late, th_c.grad.cpu().numpy())
+    gen = m.generation()
+    m.build(sc)            # a build discards the inference as well
+    assert m.generation() != gen
+    with pytest.raises(_lib.MRFError) as ei:
+        m.backward(torch.zeros(m.n_voxels, device="cuda"), generation=gen)
+    assert ei.value.code == _lib.MRF_ESTATE
