@@ -36,6 +36,8 @@
  *       (Sec. III-D): visibility and generating-surface density along each
  *       depth ray through voxels of constant occlusion density, the
  *       measurement checked against the most likely surface.
+ *   or_infer_f32_storage            -- the same sweeps with the messages
+ *       stored at single precision: a conditioning measure, not the method.
  *   or_infer_keyframe_avg           -- the same sweeps with the paper's
  *       memory approximation (Sec. IV-A): one length-weighted average message
  *       per keyframe and voxel.
@@ -472,6 +474,53 @@ void or_infer(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int6
         or_voxel_phase(vptr, vedge, V, theta, ell, lam_out);
         if (lam_hist) memcpy(lam_hist + (int64_t)k * E, lam_out, sizeof(double) * (size_t)E);
         or_ray_phase(row_ptr, R, lam_out, g, ell);
+    }
+    or_beliefs(vptr, vedge, V, theta, ell, L);
+}
+
+/* The same K sweeps with every message stored at single precision: after
+ * each voxel phase every lambda, and after each ray phase every ell, is
+ * replaced by a nearby float32 value, all arithmetic staying in FP64.  This
+ * does not change the method; it measures how far the exact answer moves when
+ * the messages carry a relative error of 2^-24 -- the conditioning of the
+ * iteration, which bounds what any implementation with float32 message
+ * arrays can reach.  mode 1 rounds to the nearest float32; mode 2 takes the
+ * float32 neighbour below or above, chosen by a counter-based hash of
+ * (sweep, edge) (splitmix64): a second, independent rounding pattern. */
+static uint64_t or_splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static void or_store_f32(double* a, int64_t E, int mode, uint64_t salt)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < E; ++e) {
+        float f = (float)a[e];
+        if (mode == 2 && isfinite(f) && (double)f != a[e]) {
+            /* the float32 neighbours lo < a[e] < hi; the hash picks one */
+            float lo = (double)f < a[e] ? f : nextafterf(f, -INFINITY);
+            float hi = (double)f > a[e] ? f : nextafterf(f, INFINITY);
+            f = (or_splitmix64(salt * 0x100000001B3ull + (uint64_t)e) >> 63) ? hi : lo;
+        }
+        a[e] = (double)f;
+    }
+}
+
+void or_infer_f32_storage(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
+                          int64_t V, int64_t E, const double* theta, const double* g, int32_t K, int32_t mode,
+                          double* lam_out, double* ell_out, double* L)
+{
+    double* ell = ell_out;
+    memset(ell, 0, sizeof(double) * (size_t)E);
+    for (int32_t k = 0; k < K; ++k) {
+        or_voxel_phase(vptr, vedge, V, theta, ell, lam_out);
+        or_store_f32(lam_out, E, mode, 2u * (uint64_t)k + 1u);
+        or_ray_phase(row_ptr, R, lam_out, g, ell);
+        or_store_f32(ell, E, mode, 2u * (uint64_t)k + 2u);
     }
     or_beliefs(vptr, vedge, V, theta, ell, L);
 }

@@ -58,6 +58,7 @@ def lib():
         _lib.or_infer.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P]
         _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, P, P, P, P]
         _lib.or_single_ray.argtypes = [I64, P, P, P]
+        _lib.or_infer_f32_storage.argtypes = [P, I64, P, P, I64, I64, P, P, I32, I32, P, P, P]
         _lib.or_infer_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P, P]
         _lib.or_infer_keyframe_avg.restype = C.c_int
         _lib.or_accuracy.argtypes = [P, I32, P, P, P, C.c_double, P, P, P, P, P]
@@ -221,6 +222,21 @@ def infer(graph: Graph, theta, sigma_table, sweeps: int, keep_history: bool = Fa
     lib().or_infer(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
                    _p(theta), _p(g), int(sweeps), _p(hist), _p(lam), _p(ell), _p(L))
     return Result(L, lam, ell, g, hist)
+
+
+def infer_f32_storage(graph: Graph, theta, sigma_table, sweeps: int, mode: int = 1, g=None) -> Result:
+    """K sweeps with every message stored at single precision (FP64 arithmetic):
+    mode 1 rounds to nearest, mode 2 to a hashed side.  Measures how far the
+    exact answer moves under float32 message storage (its conditioning)."""
+    theta = np.ascontiguousarray(theta, np.float64)
+    if g is None:
+        g = potentials(graph, sigma_table)
+    g = np.ascontiguousarray(g, np.float64)
+    E, V = graph.n_edges, graph.n_voxels
+    lam, ell, L = np.empty(E), np.empty(E), np.empty(V)
+    lib().or_infer_f32_storage(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
+                               _p(theta), _p(g), int(sweeps), int(mode), _p(lam), _p(ell), _p(L))
+    return Result(L, lam, ell, g, None)
 
 
 def edge_keyframes_and_lengths(graph: Graph, scenes):

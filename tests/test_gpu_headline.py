@@ -13,9 +13,19 @@ on the receiving ray's own message, which the sum must not depend on:
   |lam - lam*| <= 1e-4 (1 + |lam*|) + 1e-6 (|theta| + sum over the other
                                             rays' |ell*|)
 
-on every edge whose |lam*| < 10 (an informative message).  Marginals within
-1e-4; prior and sigma-table gradients by the relative 1e-3 rule (norm per
-group, and per entry against |g*| + max |g*|)."""
+on every edge whose |lam*| < 10 (an informative message).  Prior and
+sigma-table gradients by the relative 1e-3 rule (norm per group, and per entry
+against |g*| + max |g*|).
+
+Marginals: within 1e-4 of the oracle, widened on each voxel by ten times how
+far the FP64 oracle's own marginal moves when its messages are stored at
+single precision (FP64 arithmetic, every lambda and ell rounded to float32
+after each phase, two rounding patterns): 1e-4 + 10 * spread_v.  A handful of
+voxels at this geometry receive a message that is an O(1) difference of
+log-likelihoods of magnitude 1e5 (rays whose every likelier voxel is believed
+empty by the other rays' messages of 1e9), so a float32 ulp of the messages
+the difference is taken from already moves the exact answer by more than
+1e-4; everywhere else spread_v is below 1e-6 and the bar is 1e-4 itself."""
 import numpy as np
 import pytest
 
@@ -55,6 +65,9 @@ def two_keyframes(oracle):
     _say(f"[headline] oracle: {G.n_edges} edges, {K} sweeps with history")
     ref = oracle.infer(G, th, sub.sigma_table, K, keep_history=True)
     ref_prev = oracle.infer(G, th, sub.sigma_table, K - 1)   # the ray messages lambda^(K) sums
+    spread = np.zeros(G.n_voxels)
+    for mode in (1, 2):
+        spread = np.maximum(spread, np.abs(oracle.infer_f32_storage(G, th, sub.sigma_table, K, mode).p - ref.p))
     tb_ref, sb_ref, _ = oracle.backward(G, ref, oracle.bce_logit_grad(ref.L, y), sub.sigma_table)
     _say("[headline] oracle done; GPU build, infer, reverse pass")
     from paper_2006_03512_amd.mrf import RayMRF
@@ -71,20 +84,28 @@ def two_keyframes(oracle):
     out = {"p": p.cpu().numpy(), "lam": lam, "ell": ell, "dtheta": dth.cpu().numpy(), "dsigma": dsg.cpu().numpy()}
     torch.cuda.synchronize()
     m.close()
-    yield G, th, ref, ref_prev, tb_ref, sb_ref, out
+    yield G, th, ref, ref_prev, tb_ref, sb_ref, out, spread
 
 
 def test_headline_marginals(two_keyframes):
-    G, th, ref, _, _, _, out = two_keyframes
+    G, th, ref, _, _, _, out, spread = two_keyframes
     err = np.abs(out["p"] - ref.p)
-    _say(f"  marginals: max |p - p*| = {err.max():.2e}")
-    assert np.all(np.isfinite(out["p"])) and err.max() <= TOL_P
+    over = np.where(err > TOL_P)[0]
+    _say(f"  marginals: max |p - p*| = {err.max():.2e}; {over.size} voxels above {TOL_P:g}, "
+         f"{int((spread > TOL_P).sum())} voxels whose oracle spread under float32 storage is above it")
+    for v in over[:10]:
+        _say(f"    voxel {v}: |p - p*| = {err[v]:.3e}, p* = {ref.p[v]:.6f}, oracle spread {spread[v]:.3e}")
+    well = spread < 1e-6
+    _say(f"  voxels with spread < 1e-6: {int(well.sum())}, max |p - p*| there {err[well].max():.2e}")
+    assert np.all(np.isfinite(out["p"]))
+    assert np.all(err <= TOL_P + 10.0 * spread)
+    assert err[well].max() <= TOL_P
 
 
 def test_headline_informative_messages(two_keyframes):
     """Last sweep's voxel -> ray messages on informative edges, bounded on
     |lam*| and the terms they sum, not on the receiving ray's own message."""
-    G, th, ref, ref_prev, _, _, out = two_keyframes
+    G, th, ref, ref_prev, _, _, out, _ = two_keyframes
     lam_star = ref.lam
     own = np.abs(ref_prev.ell)
     mag = np.abs(th).copy()
@@ -109,7 +130,7 @@ def test_headline_ray_messages(two_keyframes):
     |ell*| < 10: within 2e-4 (1 + |ell*|) plus 1e-6 of the largest |g| among
     the voxels up to and including the edge on its ray (the log-likelihoods the
     prefix recurrence of the message has summed)."""
-    G, _, ref, _, _, _, out = two_keyframes
+    G, _, ref, _, _, _, out, _ = two_keyframes
     lens = np.diff(G.row_ptr)
     nz = lens > 0
     ag = np.abs(ref.g)
@@ -131,7 +152,7 @@ def test_headline_ray_messages(two_keyframes):
 
 
 def test_headline_gradients(two_keyframes):
-    _, _, _, _, tb_ref, sb_ref, out = two_keyframes
+    _, _, _, _, tb_ref, sb_ref, out, _ = two_keyframes
     r1, e1 = _grad_check(out["dtheta"], tb_ref)
     r2, e2 = _grad_check(out["dsigma"], sb_ref)
     _say(f"  theta rel {r1:.2e} entry {e1:.2e}; sigma rel {r2:.2e} entry {e2:.2e}")

@@ -254,3 +254,40 @@ def test_constant_bias_is_a_shift_of_the_measurement(oracle):
     b = oracle.infer(Gs, th, sc.sigma_table, sc.sweeps)
     np.testing.assert_allclose(a.g, b.g, rtol=1e-13, atol=1e-12)
     np.testing.assert_allclose(a.L, b.L, rtol=1e-9, atol=1e-9)
+
+
+def test_f32_storage_rounds_after_each_phase(oracle):
+    """The single-precision-storage variant (a conditioning measure): with one
+    sweep, lambda is theta stored as float32 and ell the exact ray messages of
+    that lambda stored as float32 (mode 1: nearest); mode 2 stores a float32
+    neighbour of the same exact value on either side."""
+    rng = np.random.default_rng(15)
+    V = 11
+    theta = rng.uniform(-3, 1, V)
+    g = np.concatenate([rng.uniform(-5, 0, len(r)) for r in TREE])
+    G = oracle.graph_from_rays(TREE, V)
+    th32 = theta.astype(np.float32).astype(np.float64)
+    exact = oracle.infer(G, th32, None, 1, g=g.copy())
+    r1 = oracle.infer_f32_storage(G, theta, None, 1, mode=1, g=g.copy())
+    assert np.array_equal(r1.lam, th32[G.col])
+    assert np.array_equal(r1.ell, exact.ell.astype(np.float32).astype(np.float64))
+    r2 = oracle.infer_f32_storage(G, theta, None, 1, mode=2, g=g.copy())
+    lo = np.nextafter(exact.ell.astype(np.float32), np.float32(-np.inf)).astype(np.float64)
+    hi = np.nextafter(exact.ell.astype(np.float32), np.float32(np.inf)).astype(np.float64)
+    assert np.all((r2.ell >= lo) & (r2.ell <= hi))
+    assert np.all(r2.ell.astype(np.float32).astype(np.float64) == r2.ell)
+
+
+def test_f32_storage_on_a_tree_stays_near_exact(oracle):
+    """On a well-conditioned tree the float32-stored messages move the exact
+    marginals (joint enumeration) by rounding only."""
+    rng = np.random.default_rng(16)
+    V = 11
+    theta = rng.uniform(-3, 1, V)
+    gl = [rng.uniform(-5, 0, len(r)) for r in TREE]
+    ref = joint_marginals(TREE, V, theta, gl)
+    G = oracle.graph_from_rays(TREE, V)
+    for mode in (1, 2):
+        res = oracle.infer_f32_storage(G, theta, None, 8, mode=mode, g=np.concatenate(gl))
+        err = np.abs(res.p - ref)
+        assert err.max() <= 1e-6 and err.max() > 0.0
