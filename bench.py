@@ -77,11 +77,12 @@ def make_scene(name, frames=None, c5_scale=0.4):
     return [scenes.make(name)]
 
 
-def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=2, single_rows=30):
+def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=1, single_rows=20, runs=3):
     """The FP64 oracle on a bounded sample of the same workload: the first nf
     frames of the batch, restricted to a band of their pixel rows (the other
     pixels carry no measurement), on every thread; then on one thread over a
-    band of single_rows rows of frame 0."""
+    band of single_rows rows of frame 0.  Each figure is the median of `runs`
+    timed runs after one untimed run."""
     import numpy as np
 
     from oracle import oracle
@@ -108,21 +109,32 @@ def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=2, single_rows=30):
             oracle.backward(G, res, oracle.bce_logit_grad(res.L, y), sub.sigma_table)
         return G.n_edges, time.perf_counter() - t0
 
+    def median_run(sub):
+        run(sub)   # untimed: pages in the oracle library and the sample's memory
+        ts = []
+        for _ in range(runs):
+            E, dt = run(sub)
+            ts.append(dt)
+        return E, sorted(ts)[len(ts) // 2], ts
+
     what = "build + %d sweeps%s" % (sweeps, " + reverse pass" if backward else "")
     nf = max(1, min(nf, sc.n_frames))
     sub, where = band(nf, int(round(sc.depth.shape[1] * row_frac)))
-    E, dt = run(sub)
+    E, dt, ts = median_run(sub)
     threads = oracle.num_threads()
     sub1, where1 = band(1, single_rows)
     oracle.set_threads(1)
     try:
-        E1, dt1 = run(sub1)
+        E1, dt1, ts1 = median_run(sub1)
     finally:
         oracle.set_threads(threads)
+    spread = lambda t: ", ".join(f"{x:.2f}" for x in t)
     return {"value": E * sweeps / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"{where} of the {sc.n_frames}-frame {name} batch ({E} edges), {what}, FP64, {dt:.1f} s",
+            "sample": f"{where} of the {sc.n_frames}-frame {name} batch ({E} edges), {what}, FP64, "
+                      f"median of {runs} runs: {dt:.2f} s ({spread(ts)} s)",
             "single_thread": {"value": E1 * sweeps / dt1, "unit": UNIT, "cores": 1,
-                              "sample": f"{where1} ({E1} edges), {what}, FP64, {dt1:.1f} s"}}
+                              "sample": f"{where1} ({E1} edges), {what}, FP64, median of {runs} runs: "
+                                        f"{dt1:.2f} s ({spread(ts1)} s)"}}
 
 
 def copy_bandwidth(nbytes: int, reps: int = 5) -> float:
@@ -154,7 +166,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of the sampled frames' rows the oracle runs on")
-    ap.add_argument("--cpu-frames", type=int, default=2, help="frames of the batch the oracle runs on")
+    ap.add_argument("--cpu-frames", type=int, default=1, help="frames of the batch the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
     ap.add_argument("--sparse-bricks", type=int, default=-1,
                     help="brick radius of a sparse grid (bricks around the measured points); -1: dense")
@@ -162,6 +174,9 @@ def main():
                     help="keep the built-in launch shapes instead of timing the candidates after warmup")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="time one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--keyframe-average", action="store_true",
+                    help="time per-keyframe averaged messages (Sec. IV-A) as the step: build + K sweeps + "
+                         "marginals, no reverse pass")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -185,6 +200,11 @@ def main():
         log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
         del src, dst
     desc, K, backward = WORKLOADS[args.workload]
+    kf_step = args.keyframe_average
+    if kf_step:   # the per-keyframe averaged scheme has no reverse pass
+        backward = False
+        desc = desc.replace(" + reverse pass (BCE vs ground truth)", "").replace(" + reverse pass", "")
+        desc += "; per-keyframe averaged messages (one chord-length-weighted average per keyframe and voxel)"
     t = time.perf_counter()
     scs = make_scene(args.workload, args.frames, args.c5_scale)
     sc = scs[0]
@@ -204,6 +224,11 @@ def main():
     y = torch.from_numpy(np.concatenate([x.occupancy() for x in scs])).cuda() if backward else None
 
     def step():
+        if kf_step:
+            m.build_resident(keyframe_average=True)
+            m.infer_keyframe_avg(theta, sigma, K)
+            m.marginals()
+            return
         m.build_resident()
         m.infer(theta, sigma, K, keep_checkpoints=backward)
         p, logit = m.marginals()
@@ -243,6 +268,7 @@ def main():
         return 1e3 * (time.perf_counter() - a) / n
 
     st = m.stats()
+    kf_pairs = st.n_keyframe_pairs
     build_ms = timed(lambda: m.build_resident(), 1)
     m.set_schedule("graph")
     fwd_graph_ms = timed(lambda: m.infer(theta, sigma, K))
@@ -284,8 +310,34 @@ def main():
         acc_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
     log(f"accurate fraction by sweeps: {acc_by_k}")
 
+    # per-keyframe averaged messages (Sec. IV-A) on the same batch: build, K sweeps,
+    # and the accuracy metric after 1..9 sweeps
+    kf_build_ms = timed(lambda: m.build_resident(keyframe_average=True), 1)
+    kf_pairs = m.stats().n_keyframe_pairs
+    kf_fwd_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
+    kf_plain_ms = None
+    m.set_schedule("plain")
+    kf_plain_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
+    m.set_schedule("graph")
+    m.infer_keyframe_avg(theta, sigma, K)
+    kf_acc = m.accuracy()["counts"].cpu().numpy().sum(0).tolist()
+    kf_by_k = {}
+    for k in range(1, 10):
+        m.infer_keyframe_avg(theta, sigma, k)
+        c = m.accuracy()["counts"].cpu().numpy().sum(0)
+        kf_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
+    m.infer_keyframe_avg(theta, sigma, K)
+    kf_prof = m.profile_sweeps(args.profile_reps, include_backward=False)
+    log(f"keyframe average: build {kf_build_ms:.1f} ms ({kf_pairs} pairs), {K} sweeps {kf_fwd_ms:.1f} ms "
+        f"(plain {kf_plain_ms:.1f}), accurate fraction by sweeps {kf_by_k}")
+    if not kf_step:
+        m.build_resident()   # back to the plain graph for the profile below
+
     # ---- roofline of the dominant kernel (HIP events around each launch)
-    m.infer(theta, sigma, K)
+    if kf_step:
+        m.infer_keyframe_avg(theta, sigma, K)
+    else:
+        m.infer(theta, sigma, K)
     prof = m.profile_sweeps(args.profile_reps, include_backward=backward)
     dom = max(prof, key=lambda k: k["avg_ms"] * k["launches"] / args.profile_reps)
     ach = dom["bytes_per_launch"] / (dom["avg_ms"] / 1e3) / 1e9
@@ -295,8 +347,23 @@ def main():
     if (TRAFFIC is not None and TRAFFIC["workload"] == args.workload and TRAFFIC["kernel"] == dom["name"]
             and args.frames is None and TRAFFIC["csrc_sha256"] == csrc_sha256()):
         traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    # the same kernel and the sweeps at the per-edge bytes of the hot-path scope table
+    # (ray phase 12, voxel phase 12, ray adjoint 16; a forward sweep 24, forward +
+    # reverse 68 per edge and sweep), which leave out the builder's extra per-edge arrays
+    nm = dom["name"]
+    survey_b = 16.0 if nm.startswith("ray_adj") else 12.0
+    dom_edges = dom.get("edges_per_launch", 0)
+    ach_survey = survey_b * dom_edges / (dom["avg_ms"] / 1e3) / 1e9
+    fwd_ms_step = kf_fwd_ms if kf_step else fwd_graph_ms
+    survey = {"kernel_bytes_per_edge": survey_b, "kernel_GBs": round(ach_survey, 1),
+              "forward_24B_GBs": round(24.0 * E * K / (fwd_ms_step / 1e3) / 1e9, 1)}
+    survey["forward_frac"] = round(survey["forward_24B_GBs"] / HBM_PEAK_GBS, 4)
+    if backward:
+        survey["fwd_bwd_68B_GBs"] = round(68.0 * E * K / ((fwd_graph_ms + bwd_ms) / 1e3) / 1e9, 1)
+        survey["fwd_bwd_frac"] = round(survey["fwd_bwd_68B_GBs"] / HBM_PEAK_GBS, 4)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
+                "frac": round(ach / HBM_PEAK_GBS, 4), "frac_survey": round(ach_survey / HBM_PEAK_GBS, 4),
+                "survey_bytes": survey, "traffic": traffic, "kernel": dom["name"],
                 "kernel_avg_ms": round(dom["avg_ms"], 4),
                 "bytes_per_launch": dom["bytes_per_launch"],
                 "forward_sweep_ms": round(sweep_ms, 3),
@@ -343,7 +410,20 @@ def main():
                          "fraction": acc_counts[1] / max(acc_counts[0], 1), "vis_min": 0.5,
                          "fraction_by_sweeps": acc_by_k},
         "forward_updates_per_s": {"batched_graph": E * K / (fwd_graph_ms / 1e3),
-                                  "plain_per_frame": E * K / (fwd_plain_ms / 1e3)},
+                                  "plain_per_frame": E * K / (fwd_plain_ms / 1e3),
+                                  "plain_schedule": "eager launches, one per frame and ray class, "
+                                                    "untuned one-wave-per-ray shapes, no graph"},
+        "keyframe_average": {"pairs": kf_pairs, "build_ms": round(kf_build_ms, 2),
+                             "forward_graph_ms": round(kf_fwd_ms, 2),
+                             "forward_plain_per_frame_ms": round(kf_plain_ms, 2),
+                             "updates_per_s": E * K / (kf_fwd_ms / 1e3),
+                             "map_accuracy": {"evaluated_rays": kf_acc[0], "accurate_rays": kf_acc[1],
+                                              "fraction": kf_acc[1] / max(kf_acc[0], 1), "vis_min": 0.5,
+                                              "fraction_by_sweeps": kf_by_k},
+                             "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4),
+                                          "launches": k["launches"],
+                                          "GBs": round(k["bytes_per_launch"] / max(k["avg_ms"], 1e-9) / 1e6, 1)}
+                                         for k in kf_prof]},
         "kernels": kernels,
         "tuning": {k: v for k, v in m.tuning().items() if k in ("cap", "fwd_lanes", "adj_lanes", "adj_rays")},
         "autotuned": not args.no_autotune,

@@ -92,7 +92,13 @@ typedef struct {
  * lies in a grid voxel whose brick is within brick_radius bricks of it on
  * every axis; a ray then keeps only its voxels in allocated bricks (same
  * chords), and min_ray_voxels applies to those.  Voxels of other bricks take
- * part in no ray factor and keep their prior. */
+ * part in no ray factor and keep their prior.
+ * Per-keyframe averaged messages (Sec. IV-A): with keyframe_average != 0 the
+ * build also prepares mrf_infer_keyframe_avg: every frame is a keyframe, and
+ * each (keyframe, voxel) pair crossed by at least one of the keyframe's rays
+ * gets the chord-length weights of its rays and one slot in a per-keyframe
+ * message buffer (4 bytes per voxel of the frame's scene and frame, plus
+ * 4 bytes per edge and 12 per pair). */
 typedef struct {
     double z_min, z_max;
     double trunc_nsigma, trunc_c0, trunc_c2, trunc_min;
@@ -101,6 +107,7 @@ typedef struct {
     int32_t keep_chords;    /* nonzero: keep f64 chord entry/exit per edge for export */
     int32_t sparse_bricks;  /* nonzero: sparse grid (Sec. IV-B), see below; 0: dense */
     int32_t brick_radius;   /* sparse grid: bricks allocated around a point's brick, 0..64 */
+    int32_t keyframe_average;  /* nonzero: prepare per-keyframe averaged messages (Sec. IV-A) */
 } mrf_build_params;
 
 typedef struct {
@@ -112,6 +119,7 @@ typedef struct {
     int32_t sweeps_done, have_checkpoints;
     int64_t n_slots;                /* edge slots in memory: edges plus tile padding */
     int64_t n_tiles;                /* 4x4-pixel ray tiles */
+    int64_t n_keyframe_pairs;       /* (keyframe, voxel) pairs (builds with keyframe_average) */
 } mrf_stats_t;
 
 /* Create an empty context on the current HIP device.  *out receives it. */
@@ -124,7 +132,8 @@ int mrf_create(mrf_ctx** out);
  * voxel depth (chord midpoint) and sigma-table bin.  Depth and pose arrays
  * must stay valid until the call returns.  Errors: MRF_EINVAL (bad shapes,
  * min_ray_voxels < 2, more than 65535 frames), MRF_ERANGE (total edges >= 2^32
- * or a ray longer than 2048 voxels), MRF_ENOMEM, MRF_EHIP. */
+ * or a ray longer than 2048 voxels; with keyframe_average, per-keyframe
+ * message buffers of 2^32 or more entries), MRF_ENOMEM, MRF_EHIP. */
 int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
               const mrf_build_params* params, void* stream);
 
@@ -154,6 +163,26 @@ int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
 int mrf_infer_sensor(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
                      const float* bias_table, int32_t sweeps, int32_t keep_checkpoints,
                      void* stream);
+
+/* Loopy BP with the memory approximation of Sec. IV-A: the rays of one
+ * keyframe that cross a voxel are taken to send it the same message, their
+ * average weighted by the length each ray travels in the voxel (Euclidean
+ * chord length), so a voxel's belief is theta_v plus ONE averaged message per
+ * keyframe, and the voxel -> ray message into a ray of keyframe f is theta_v
+ * plus the averages of the OTHER keyframes (the receiving ray's keyframe is
+ * left out as a whole, as Eq. node_to_factor leaves out the receiving
+ * factor).  Ray -> voxel messages are Eqs. pos and neg as in mrf_infer, and
+ * ray messages start uniform, so the first sweep's voxel -> ray message is
+ * theta.  After K sweeps mrf_marginals returns theta plus every keyframe's
+ * average of the last sweep; mrf_export_edges gives the last sweep's messages.
+ * Averages are FP64 sums of weight * message in a fixed order; each
+ * keyframe's message is one FP32 rounding of its FP64 value.  Tables and
+ * arguments as mrf_infer_sensor (bias_table may be NULL).  No checkpoints are
+ * kept: mrf_backward after this call returns MRF_ESTATE.  Errors: MRF_ESTATE
+ * before mrf_build or when the build did not set keyframe_average,
+ * MRF_EINVAL for sweeps < 1. */
+int mrf_infer_keyframe_avg(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
+                           const float* bias_table, int32_t sweeps, void* stream);
 
 /* Marginals of the last mrf_infer (Sec. III-B: normalised product of all
  * factor messages into the voxel): logit_v = theta_v + sum of ray messages,
@@ -241,8 +270,10 @@ int mrf_export_edges(const mrf_ctx* ctx, float* delta, uint8_t* bin, float* g,
                      float* lam, float* ell, void* stream);
 
 /* Execution schedule of the sweeps:
- *   MRF_SCHED_PLAIN  one kernel launch per phase per ray class, per frame
- *                    for the ray phase, fixed segments, no graph;
+ *   MRF_SCHED_PLAIN  eager launches, no graph: one launch per phase and ray
+ *                    class, per frame for the ray phase, every ray class
+ *                    with the fixed untuned shape of one 64-lane wave per
+ *                    ray (16 lanes for rays of at most 16 voxels);
  *   MRF_SCHED_GRAPH  all sweeps captured once into a hipGraph and replayed
  *                    (default), with tuned launch shapes. */
 enum { MRF_SCHED_PLAIN = 0, MRF_SCHED_GRAPH = 1 };

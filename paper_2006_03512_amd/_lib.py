@@ -19,7 +19,7 @@ SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backwar
            "mrf_export_incidence", "mrf_export_edges", "mrf_set_schedule", "mrf_destroy",
            "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps", "mrf_get_tuning", "mrf_set_tuning",
            "mrf_autotune", "mrf_infer_sensor", "mrf_backward_sensor", "mrf_accuracy", "mrf_generation",
-           "mrf_backward_gen"]
+           "mrf_backward_gen", "mrf_infer_keyframe_avg"]
 MAX_RAY_CLASSES = 32
 
 
@@ -42,7 +42,8 @@ class BuildParams(C.Structure):
     _fields_ = [("z_min", C.c_double), ("z_max", C.c_double), ("trunc_nsigma", C.c_double),
                 ("trunc_c0", C.c_double), ("trunc_c2", C.c_double), ("trunc_min", C.c_double),
                 ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32),
-                ("keep_chords", C.c_int32), ("sparse_bricks", C.c_int32), ("brick_radius", C.c_int32)]
+                ("keep_chords", C.c_int32), ("sparse_bricks", C.c_int32), ("brick_radius", C.c_int32),
+                ("keyframe_average", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -52,7 +53,7 @@ class Stats(C.Structure):
                 ("max_voxel_degree", C.c_int64), ("ray_len_hist", C.c_int64 * 16),
                 ("voxel_degree_hist", C.c_int64 * 24), ("fwd_bytes_per_sweep", C.c_double),
                 ("sweeps_done", C.c_int32), ("have_checkpoints", C.c_int32),
-                ("n_slots", C.c_int64), ("n_tiles", C.c_int64)]
+                ("n_slots", C.c_int64), ("n_tiles", C.c_int64), ("n_keyframe_pairs", C.c_int64)]
 
 
 class KernelTime(C.Structure):
@@ -85,6 +86,7 @@ def lib() -> C.CDLL:
         L.mrf_build.argtypes = [P, C.POINTER(SceneC), I32, C.POINTER(BuildParams), P]
         L.mrf_infer.argtypes = [P, P, P, I32, I32, P]
         L.mrf_infer_sensor.argtypes = [P, P, P, P, I32, I32, P]
+        L.mrf_infer_keyframe_avg.argtypes = [P, P, P, P, I32, P]
         L.mrf_marginals.argtypes = [P, P, P, P]
         L.mrf_backward.argtypes = [P, P, P, P, P]
         L.mrf_backward_sensor.argtypes = [P, P, P, P, P, P]

@@ -53,11 +53,15 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     for (int i = 0; i < mrf::kRayClasses; ++i) k.push_back((uint64_t)c->fwd_sel[i]);
     const mrf::DevBuf* bufs[] = {&c->b_rowptr, &c->b_col,   &c->b_delta, &c->b_bin,  &c->b_g,    &c->b_lam,
                                  &c->b_ell,    &c->b_vedge, &c->b_vptr,  &c->b_theta, &c->b_L,   &c->b_sigma, &c->b_bias,
-                                 &c->b_ckpt,   &c->b_tsum,  &c->b_tbar,  &c->b_tiles, &c->b_counts, &c->b_theta2};
+                                 &c->b_ckpt,   &c->b_tsum,  &c->b_tbar,  &c->b_tiles, &c->b_counts, &c->b_theta2,
+                                 &c->b_kfw,    &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox};
     for (const mrf::DevBuf* b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
     for (const auto& b : c->b_ray_list) k.push_back((uint64_t)(uintptr_t)b.p);
     for (const auto& b : c->b_vox_list) k.push_back((uint64_t)(uintptr_t)b.p);
     for (const auto& b : c->b_vox_desc) k.push_back((uint64_t)(uintptr_t)b.p);
+    for (const auto& b : c->b_pair_desc) k.push_back((uint64_t)(uintptr_t)b.p);
+    for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->pair_cnt[i]);
+    k.push_back((uint64_t)c->n_kf_vox);
     return k;
 }
 
@@ -134,6 +138,38 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
     return launch_voxel_phase(c, ell_slot(c, K, K, keep), VoxOut{theta, nullptr, (float*)c->b_L.p, nullptr}, s);
 }
 
+// Per-keyframe averaged messages (Sec. IV-A): the first sweep's lambda is the
+// prior (no incoming message yet); sweep k > 1 forms every keyframe's average
+// of the previous sweep's ray messages per voxel (pair phase) and from them each
+// keyframe's voxel -> ray message (theta plus the OTHER keyframes' averages);
+// after the last sweep the beliefs L = theta plus every keyframe's average.
+// ell alternates between b_lam and b_ell so that the last sweep's ends in b_ell.
+static hipError_t enqueue_forward_kf(mrf_ctx* c, int K, bool plain, hipStream_t s)
+{
+    hipError_t e;
+    const float* theta = (const float*)c->b_theta.p;
+    const float* w = (const float*)c->b_kfw.p;
+    double* M = (double*)c->b_pair_m.p;
+    float* x = (float*)c->b_kfx.p;
+    const KfSrc kf{x, (const int64_t*)c->b_kfxb.p};
+    if ((e = launch_pair(theta, (float2*)c->b_theta2.p, c->V, s)) != hipSuccess) return e;
+    if ((e = launch_potentials(c, s)) != hipSuccess) return e;
+    for (int k = 1; k <= K; ++k) {
+        float* ell = ell_slot(c, K, k, false);
+        if (k == 1) {
+            e = launch_ray_phase(c, ExclSrc{(const float2*)c->b_theta2.p, nullptr}, ell, plain, s);
+        } else {
+            e = launch_pair_phase(c, ell_slot(c, K, k - 1, false), w, M, s);
+            if (e == hipSuccess) e = launch_kf_voxel(c, theta, x, nullptr, s);
+            if (e == hipSuccess) e = launch_ray_phase_kf(c, kf, ell, plain, s);
+        }
+        if (e != hipSuccess) return e;
+    }
+    if ((e = launch_copy((float*)c->b_L.p, theta, c->V, s)) != hipSuccess) return e;
+    if ((e = launch_pair_phase(c, (const float*)c->b_ell.p, w, M, s)) != hipSuccess) return e;
+    return launch_kf_voxel(c, theta, nullptr, (float*)c->b_L.p, s);
+}
+
 static const float* final_ell(const mrf_ctx* c) { return c->inferred ? (const float*)c->b_ell.p : nullptr; }
 
 // the last sweep's voxel->ray messages
@@ -195,8 +231,10 @@ void mrf_destroy(mrf_ctx* c)
                      &c->b_vptr, &c->b_theta, &c->b_theta2, &c->b_L, &c->b_thetabar, &c->b_sigma, &c->b_bias,
                      &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric, &c->b_bricks,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
-                     &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export};
+                     &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export,
+                     &c->b_kfw, &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox};
     for (DevBuf* b : all) free_buf(*b);
+    for (auto& b : c->b_pair_desc) free_buf(b);
     for (auto& b : c->b_ray_list) free_buf(b);
     for (auto& b : c->b_vox_list) free_buf(b);
     for (auto& b : c->b_vox_desc) free_buf(b);
@@ -222,7 +260,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         return fail(MRF_EINVAL, "mrf_build: bad depth window, truncation or table range");
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_build: hipSetDevice");
-    c->built = c->inferred = c->have_ckpt = 0;   // a cached graph is revalidated by mrf_infer
+    c->built = c->inferred = c->have_ckpt = c->kf_inferred = 0;   // a cached graph is revalidated by mrf_infer
     ++c->gen;
 
     c->scenes_h.clear();
@@ -300,6 +338,9 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->bp.bricks = nullptr;
     c->n_bricks = NB;
     c->keep_chords = p->keep_chords ? 1 : 0;
+    c->kf = p->keyframe_average ? 1 : 0;
+    c->n_pairs = c->n_kfx = c->n_kf_vox = 0;
+    for (int k = 0; k < kVoxClasses; ++k) c->pair_cnt[k] = 0;
 
     HCK(ensure(c->b_scenes, sizeof(SceneDev) * c->scenes_h.size()), "mrf_build: alloc");
     HCK(ensure(c->b_frames, sizeof(FrameDev) * c->frames_h.size()), "mrf_build: alloc");
@@ -351,12 +392,14 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_delta, e4), "mrf_build: alloc delta");
     HCK(ensure(c->b_bin, e1), "mrf_build: alloc bin");
     HCK(ensure(c->b_g, e4), "mrf_build: alloc g");
-    HCK(ensure(c->b_lam, e4), "mrf_build: alloc lam");
-    HCK(ensure(c->b_ell, e4), "mrf_build: alloc ell");
+    // one entry more: the keyframe-pair build keeps an exclusive count of E + 1 entries in each
+    HCK(ensure(c->b_lam, e4 + 16), "mrf_build: alloc lam");
+    HCK(ensure(c->b_ell, e4 + 16), "mrf_build: alloc ell");
     HCK(ensure(c->b_vedge, e4), "mrf_build: alloc vedge");
     HCK(ensure(c->b_ellbar, e4), "mrf_build: alloc ellbar");
     HCK(ensure(c->b_lambar, e4), "mrf_build: alloc lambar");
     HCK(ensure(c->b_gsum, e4), "mrf_build: alloc gsum");
+    if (c->kf) HCK(ensure(c->b_kfw, e4), "mrf_build: alloc chord lengths");
     if (c->keep_chords) {
         HCK(ensure(c->b_tin, 2 * e4), "mrf_build: alloc t_in");
         HCK(ensure(c->b_tout, 2 * e4), "mrf_build: alloc t_out");
@@ -397,6 +440,11 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         if (e == hipErrorInvalidConfiguration) return fail(MRF_ERANGE, "mrf_build: " + g_err);
         HCK(e, "mrf_build: work lists");
     }
+    if (c->kf) {
+        hipError_t e = build_keyframe_pairs(c, s);
+        if (e == hipErrorInvalidConfiguration) return fail(MRF_ERANGE, "mrf_build: " + g_err);
+        HCK(e, "mrf_build: keyframe pairs");
+    }
     HCK(hipStreamSynchronize(s), "mrf_build: sync");
 
     mrf_stats_t& st = c->stats;
@@ -417,6 +465,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
         24.0 * (double)E + 28.0 * (double)st.n_touched_voxels + 4.0 * (double)st.n_kept_rays + 36.0 * (double)c->T;
     st.sweeps_done = 0;
     st.have_checkpoints = 0;
+    st.n_keyframe_pairs = c->n_pairs;
     c->built = 1;
     return MRF_OK;
 }
@@ -480,11 +529,67 @@ int mrf_infer_sensor(mrf_ctx* c, const float* prior_logit, const float* sigma_ta
         HCK(hipStreamWaitEvent(s, c->ev_out, 0), "mrf_infer: wait");
     }
     c->inferred = 1;
+    c->kf_inferred = 0;
     ++c->gen;
     c->K = sweeps;
     c->have_ckpt = keep;
     c->stats.sweeps_done = sweeps;
     c->stats.have_checkpoints = keep;
+    return MRF_OK;
+}
+
+int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* sigma_table, const float* bias_table,
+                           int32_t sweeps, void* stream)
+{
+    if (!c || !prior_logit || !sigma_table) return fail(MRF_EINVAL, "mrf_infer_keyframe_avg: null argument");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_infer_keyframe_avg: call mrf_build first");
+    if (!c->kf)
+        return fail(MRF_ESTATE, "mrf_infer_keyframe_avg: the graph was built without keyframe_average");
+    if (sweeps < 1) return fail(MRF_EINVAL, "mrf_infer_keyframe_avg: sweeps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_infer_keyframe_avg: hipSetDevice");
+    HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer_keyframe_avg: copy prior");
+    HCK(launch_copy((float*)c->b_sigma.p, sigma_table, kBins, s), "mrf_infer_keyframe_avg: copy sigma");
+    if (bias_table)
+        HCK(launch_copy((float*)c->b_bias.p, bias_table, kBins, s), "mrf_infer_keyframe_avg: copy bias");
+    else
+        HCK(launch_fill((float*)c->b_bias.p, 0.0f, kBins, s), "mrf_infer_keyframe_avg: zero bias");
+    if (c->schedule == MRF_SCHED_PLAIN) {
+        HCK(enqueue_forward_kf(c, sweeps, true, s), "mrf_infer_keyframe_avg: sweeps");
+    } else {
+        std::vector<uint64_t> key = graph_key(c, sweeps, 0);
+        key.push_back(0x6b66);   // the keyframe-average schedule
+        if (!c->gexec || key != c->g_key) {
+            drop_graph(c);
+            hipGraph_t g = nullptr;
+            HCK(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal),
+                "mrf_infer_keyframe_avg: begin capture");
+            hipError_t e = enqueue_forward_kf(c, sweeps, false, c->aux);
+            hipError_t e2 = hipStreamEndCapture(c->aux, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            if (g) hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->gexec = nullptr;
+                return hip_fail(e, "mrf_infer_keyframe_avg: graph capture");
+            }
+            c->g_K = sweeps;
+            c->g_ckpt = 0;
+            c->g_key = key;
+        }
+        HCK(hipEventRecord(c->ev_in, s), "mrf_infer_keyframe_avg: event");
+        HCK(hipStreamWaitEvent(c->aux, c->ev_in, 0), "mrf_infer_keyframe_avg: wait");
+        HCK(hipGraphLaunch(c->gexec, c->aux), "mrf_infer_keyframe_avg: graph launch");
+        HCK(hipEventRecord(c->ev_out, c->aux), "mrf_infer_keyframe_avg: event");
+        HCK(hipStreamWaitEvent(s, c->ev_out, 0), "mrf_infer_keyframe_avg: wait");
+    }
+    c->inferred = 1;
+    c->kf_inferred = 1;
+    ++c->gen;
+    c->K = sweeps;
+    c->have_ckpt = 0;
+    c->stats.sweeps_done = sweeps;
+    c->stats.have_checkpoints = 0;
     return MRF_OK;
 }
 
@@ -506,6 +611,9 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
 int mrf_backward_sensor(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, float* dbias, void* stream)
 {
     if (!c || !dlogit) return fail(MRF_EINVAL, "mrf_backward: null argument");
+    if (c->inferred && c->kf_inferred)
+        return fail(MRF_ESTATE, "mrf_backward: the last inference used per-keyframe averaged messages, which have "
+                                "no reverse pass");
     if (!c->inferred || !c->have_ckpt)
         return fail(MRF_ESTATE, "mrf_backward: needs a preceding mrf_infer with keep_checkpoints");
     hipStream_t s = (hipStream_t)stream;
@@ -605,7 +713,12 @@ int mrf_export_edges(const mrf_ctx* c, float* delta, uint8_t* bin, float* g, flo
     if (g) HCK(export_canonical_edges(c, c->b_g.p, g, 4, s), "export");
     if (lam) {   // materialised into a scratch edge array first
         float* tmp = (float*)c->b_ellbar.p;
-        HCK(launch_excl(c, final_lam(c), tmp, s), "export");
+        if (c->kf_inferred && c->K > 1)
+            HCK(launch_excl_kf(c, KfSrc{(const float*)c->b_kfx.p, (const int64_t*)c->b_kfxb.p}, tmp, s), "export");
+        else if (c->kf_inferred)   // one sweep: the prior was every incoming message
+            HCK(launch_excl(c, ExclSrc{(const float2*)c->b_theta2.p, nullptr}, tmp, s), "export");
+        else
+            HCK(launch_excl(c, final_lam(c), tmp, s), "export");
         HCK(export_canonical_edges(c, tmp, lam, 4, s), "export");
     }
     if (ell) HCK(export_canonical_edges(c, final_ell(c), ell, 4, s), "export");
@@ -640,6 +753,8 @@ static std::string kid_name(const mrf_ctx* c, int k)
         const int q = k - KID_ADJ0;
         return ray_name("ray_adj_k", "ray_adj_lds_k", q, kAdjShapes[q][c->adj_sel[q]], true);
     }
+    if (k == KID_PAIR) return "keyframe pair averages";
+    if (k == KID_KFVOX) return "kf_voxel_k";
     if (k == KID_POT) return "potentials_k";
     if (k == KID_SIGMA) return "sigma_grad_k<false>";   // the profile asks for no bias gradient
     return "?";
@@ -658,9 +773,19 @@ static void kid_bytes(const mrf_ctx* c, int k, double* bytes, int64_t* edges)
     } else if (k >= KID_RAY0 && k < KID_RAY0 + kRayClasses) {
         const int q = k - KID_RAY0;
         // per edge: col 4 + own ell 4 + g 4 + ell 4 (voxel totals: counted once per voxel
-        // in the sweep figure); per ray: count 4; per tile: list 4 + descriptor 32
+        // in the sweep figure; with per-keyframe messages no own ell, and the keyframe's
+        // message counted once per pair); per ray: count 4; per tile: list 4 + descriptor 32
         *edges = c->ray_cls_edges[q];
-        *bytes = 16.0 * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] + 36.0 * (double)c->ray_cnt[q];
+        *bytes = (c->kf_inferred ? 12.0 : 16.0) * (double)*edges + 4.0 * (double)c->ray_cls_rays[q] +
+                 36.0 * (double)c->ray_cnt[q];
+    } else if (k == KID_PAIR) {
+        // per edge: vedge 4 + weight 4 + gathered ell 4; per pair: descriptor 16 + average 8
+        *edges = c->E;
+        *bytes = 12.0 * (double)c->E + 24.0 * (double)c->n_pairs;
+    } else if (k == KID_KFVOX) {
+        // per pair: average 8 + message index 4 + message 4; per voxel: descriptor 16 + theta 4
+        *edges = c->E;
+        *bytes = 16.0 * (double)c->n_pairs + 20.0 * (double)c->n_kf_vox;
     } else if (k >= KID_ADJ0 && k < KID_ADJ0 + kRayClasses) {
         const int q = k - KID_ADJ0;
         // per edge: col 4 + own ell 4 + g 4 + own lambar of the later sweep 4 + lambar 4 +
@@ -688,7 +813,21 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
     const float* ell_in = final_ell(c);
     float2* vt = (float2*)c->b_tbar.p;
     float* ell = (float*)c->b_ellbar.p;
-    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    if (c->kf_inferred) {
+        // per-keyframe sweeps from the last sweep's messages: the pair averages are
+        // rewritten with the values the inference left, the keyframe messages go to
+        // scratch (b_export), the ray messages to b_ellbar
+        e = ensure(c->b_export, sizeof(float) * (size_t)(c->n_kfx > 0 ? c->n_kfx : 1));
+        float* xs = (float*)c->b_export.p;
+        const KfSrc kf{xs, (const int64_t*)c->b_kfxb.p};
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            e = launch_pair_phase(c, ell_in, (const float*)c->b_kfw.p, (double*)c->b_pair_m.p, s);
+            if (e == hipSuccess) e = launch_kf_voxel(c, theta, xs, nullptr, s);
+            if (e == hipSuccess) e = launch_ray_phase_kf(c, kf, ell, false, s);
+        }
+        include_backward = 0;
+    }
+    for (int r = 0; r < reps && e == hipSuccess && !c->kf_inferred; ++r) {
         e = launch_voxel_phase(c, ell_in, VoxOut{theta, vt, nullptr, nullptr}, s);
         if (e == hipSuccess) e = launch_ray_phase(c, ExclSrc{vt, ell_in}, ell, false, s);
     }
@@ -787,7 +926,10 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
     hipEvent_t ev[2] = {nullptr, nullptr};
     HCK(hipEventCreate(&ev[0]), "mrf_autotune: event");
     hipError_t e = hipEventCreate(&ev[1]);
-    for (int adj = 0; adj < 2 && e == hipSuccess; ++adj) {
+    // after per-keyframe averaged sweeps: their ray phase only (they have no reverse pass)
+    const bool kf = c->kf_inferred != 0;
+    const KfSrc kfs{(const float*)c->b_kfx.p, (const int64_t*)c->b_kfxb.p};
+    for (int adj = 0; adj < (kf ? 1 : 2) && e == hipSuccess; ++adj) {
         for (int q = 0; q < kRayClasses && e == hipSuccess; ++q) {
             const int ns = ray_shape_count(q, adj == 1);
             if (c->ray_cnt[q] <= 0 || ns < 2) continue;
@@ -795,6 +937,7 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
             float best_ms = 0.0f;
             for (int i = 0; i < ns && e == hipSuccess; ++i) {
                 auto run = [&]() {
+                    if (kf) return launch_ray_class_shape_kf(c, q, i, kfs, ell_out, s);
                     return adj ? launch_adj_class_shape(c, q, i, lam, eb, lambar, gsum, 1, s)
                                : launch_ray_class_shape(c, q, i, lam, ell_out, s);
                 };

@@ -214,10 +214,12 @@ struct EdgeEmit {
     uint8_t* bin;
     double* tin;
     double* tout;
+    float* wlen;          // chord length per edge (per-keyframe averaging), or null
     const SceneDev* sd;
     int64_t base;
     int32_t vbase;
     double Z, dbin;
+    double wn;            // |w| of the ray: chord length = (t_out - t_in) |w|
     __device__ void operator()(int k, int vi, int vj, int vk, double ti, double to) const
     {
         const int64_t e = base + (int64_t)kTile * k;   // step k of this ray's tile lane
@@ -233,6 +235,7 @@ struct EdgeEmit {
             tin[e] = ti;
             tout[e] = to;
         }
+        if (wlen) wlen[e] = (float)((to - ti) * wn);
     }
 };
 
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
                                                     const int64_t* __restrict__ tbase,
                                                     const TileDev* __restrict__ tiles, uint32_t pad_key,
                                                     int32_t* col, uint32_t* key, float* delta, uint8_t* bin,
-                                                    double* tin, double* tout)
+                                                    double* tin, double* tout, float* wlen)
 {
     const FrameDev fr = frames[blockIdx.y];
     const SceneDev& sd = scenes[fr.scene];
@@ -268,7 +271,11 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
         if (m > 0) {
             Ray ray;
             setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, ray);
-            EdgeEmit em{col, key, delta, bin, tin, tout, &sd, slot0, (int32_t)sd.voxel_base, ray.Z, bp.dmax / 64.0};
+            double wn = ray.w[0] * ray.w[0];
+            wn = wn + ray.w[1] * ray.w[1];
+            wn = wn + ray.w[2] * ray.w[2];
+            EdgeEmit em{col,  key,   delta, bin, tin, tout, wlen, &sd, slot0, (int32_t)sd.voxel_base, ray.Z,
+                        bp.dmax / 64.0, sqrt(wn)};
             walk(sd, ray, scene_bricks(bp, sd), em);
         }
     }
@@ -302,7 +309,7 @@ __global__ void tile_init_k(const SceneDev* __restrict__ scenes, const FrameDev*
         for (int b = 0; b < td.nu; ++b) len = max(len, counts[td.ray0 + a * sd.W + b]);
     td.len = len;
     td.base = 0;
-    td.pad = 0;
+    td.frame = (int32_t)blockIdx.y;
     tiles[fr.tile_base + lt] = td;
     slots16[fr.tile_base + lt] = kTile * len;
 }
@@ -374,7 +381,7 @@ hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s)
                        (const int64_t*)c->b_tbase.p, (const TileDev*)c->b_tiles.p, (uint32_t)c->Vk,
                        (int32_t*)c->b_col.p, (uint32_t*)c->b_g.p, (float*)c->b_delta.p, (uint8_t*)c->b_bin.p,
                        c->keep_chords ? (double*)c->b_tin.p : nullptr,
-                       c->keep_chords ? (double*)c->b_tout.p : nullptr);
+                       c->keep_chords ? (double*)c->b_tout.p : nullptr, c->kf ? (float*)c->b_kfw.p : nullptr);
     return hipGetLastError();
 }
 
@@ -434,9 +441,9 @@ __global__ __launch_bounds__(SC_T) void scan_reduce_k(Load ld, int64_t n, int64_
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-template <class Load>
+template <class Load, class Out>
 __global__ __launch_bounds__(SC_T) void scan_apply_k(Load ld, int64_t n, const int64_t* __restrict__ boff,
-                                                     int64_t* __restrict__ out)
+                                                     Out* __restrict__ out)
 {
     const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_IPT;
     int64_t v[SC_IPT];
@@ -452,13 +459,11 @@ __global__ __launch_bounds__(SC_T) void scan_apply_k(Load ld, int64_t n, const i
 #pragma unroll
     for (int k = 0; k < SC_IPT; ++k) {
         const int64_t i = base + k;
-        if (i < n) out[i] = ex;
+        if (i < n) out[i] = (Out)ex;
         ex += v[k];
-        if (i == n - 1) out[n] = ex;
+        if (i == n - 1) out[n] = (Out)ex;
     }
 }
-
-__global__ void zero_i64_k(int64_t* p) { *p = 0; }
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -474,17 +479,22 @@ size_t scan_tmp_bytes(int64_t n)
     return (words + 8) * sizeof(int64_t);
 }
 
-template <class Load>
-static hipError_t scan_rec(Load ld, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s)
+template <class Out>
+__global__ void zero_k(Out* p) { *p = 0; }
+
+// Exclusive scan of ld(0..n-1) into out[0..n] (out[n] = the total), written as
+// Out (the caller guarantees the total fits); tmp holds scan_tmp_bytes(n).
+template <class Load, class Out = int64_t>
+static hipError_t scan_rec(Load ld, int64_t n, Out* out, int64_t* tmp, hipStream_t s)
 {
     if (n == 0) {
-        hipLaunchKernelGGL(zero_i64_k, dim3(1), dim3(1), 0, s, out);
+        hipLaunchKernelGGL(zero_k<Out>, dim3(1), dim3(1), 0, s, out);
         return hipGetLastError();
     }
     const int64_t nb = cdiv(n, SC_TILE);
     if (nb == 1) {
-        hipLaunchKernelGGL(scan_apply_k<Load>, dim3(1), dim3(SC_T), 0, s, ld, n,
-                           (const int64_t*)nullptr, out);
+        hipLaunchKernelGGL((scan_apply_k<Load, Out>), dim3(1), dim3(SC_T), 0, s, ld, n, (const int64_t*)nullptr,
+                           out);
         return hipGetLastError();
     }
     int64_t* bsum = tmp;
@@ -492,8 +502,8 @@ static hipError_t scan_rec(Load ld, int64_t n, int64_t* out, int64_t* tmp, hipSt
     hipLaunchKernelGGL(scan_reduce_k<Load>, dim3((unsigned)nb), dim3(SC_T), 0, s, ld, n, bsum);
     hipError_t e = scan_rec(LoadI64{bsum}, nb, boff, tmp + 2 * nb + 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_apply_k<Load>, dim3((unsigned)nb), dim3(SC_T), 0, s, ld, n,
-                       (const int64_t*)boff, out);
+    hipLaunchKernelGGL((scan_apply_k<Load, Out>), dim3((unsigned)nb), dim3(SC_T), 0, s, ld, n, (const int64_t*)boff,
+                       out);
     return hipGetLastError();
 }
 
@@ -1168,6 +1178,223 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
         c->stats.max_ray_len = (int64_t)hh[40];
         c->stats.max_voxel_degree = (int64_t)hh[41];
     }
+    return hipGetLastError();
+}
+
+// ============================================================== keyframe pairs
+//
+// Per-keyframe averaged messages (Sec. IV-A): the rays of one keyframe that
+// cross a voxel send it one message, the average of theirs weighted by the
+// length each travels in the voxel.  A voxel's edge list (slots ascending) is
+// grouped by keyframe, since slots are frame-major; each run of one keyframe
+// inside one voxel's list is a (keyframe, voxel) pair.
+
+// first slot of every frame (frames occupy consecutive slot ranges in order);
+// fs[nf] = S
+__global__ void frame_slots_k(const FrameDev* __restrict__ frames, int nf, const int64_t* __restrict__ tbase,
+                              int64_t T, int64_t* __restrict__ fs)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nf) fs[f] = tbase[frames[f].tile_base];
+    if (f == nf) fs[nf] = tbase[T];
+}
+
+// frame holding slot x: the last f with fs[f] <= x (frames without edges
+// share their successor's first slot and are skipped)
+__device__ __forceinline__ int slot_frame(const int64_t* __restrict__ fs, int nf, uint32_t x)
+{
+    int lo = 0, hi = nf;   // fs[lo] <= x < fs[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (fs[mid] <= (int64_t)x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// 1 where entry j of the voxel -> ray list starts a (keyframe, voxel) run
+struct LoadPairStart {
+    const uint32_t* vedge;
+    const uint32_t* keys;   // sorted voxel keys, aligned with vedge
+    const int64_t* fs;
+    int nf;
+    __device__ int64_t operator()(int64_t j) const
+    {
+        if (j == 0) return 1;
+        if (keys[j] != keys[j - 1]) return 1;
+        return slot_frame(fs, nf, vedge[j]) != slot_frame(fs, nf, vedge[j - 1]) ? 1 : 0;
+    }
+};
+
+// pair p (starting at entry j): its first entry and the index of its message
+// in the per-keyframe buffers, xb[f] + linear voxel id
+__global__ void pair_init_k(const LoadPairStart ld, int64_t E, const uint32_t* __restrict__ pos,
+                            const SceneDev* __restrict__ scenes, int ns, const int64_t* __restrict__ xb,
+                            uint32_t* __restrict__ pstart, uint32_t* __restrict__ px)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > E) return;
+    if (j == E) {
+        pstart[pos[E]] = (uint32_t)E;
+        return;
+    }
+    if (!ld(j)) return;
+    const uint32_t p = pos[j];
+    pstart[p] = (uint32_t)j;
+    const int f = slot_frame(ld.fs, ld.nf, ld.vedge[j]);
+    px[p] = (uint32_t)(xb[f] + (int64_t)key_to_voxel(scenes, ns, ld.keys[j]));
+}
+
+// edge-count class of every pair (as the voxel classes)
+__global__ void pair_class_k(const uint32_t* __restrict__ pstart, int64_t P, uint8_t* __restrict__ cls)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t m = (int64_t)pstart[p + 1] - pstart[p];
+    uint8_t c = kVoxClasses - 1;
+    for (int k = 0; k < kVoxClasses - 1; ++k)
+        if (m <= kVoxCap[k]) {
+            c = (uint8_t)k;
+            break;
+        }
+    cls[p] = c;
+}
+
+__global__ void pair_desc_k(const uint32_t* __restrict__ list, int64_t n, const uint32_t* __restrict__ pstart,
+                            VoxDev* __restrict__ desc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = list[i];
+    desc[i] = VoxDev{(int64_t)pstart[p], (int32_t)(pstart[p + 1] - pstart[p]), p};
+}
+
+// the pairs of every touched voxel of one class list: [pos[vptr[key]], pos[vptr[key + 1]])
+__global__ void kf_vox_k(const SceneDev* __restrict__ scenes, int ns, const uint32_t* __restrict__ keys, int64_t n,
+                         const int64_t* __restrict__ vptr, const uint32_t* __restrict__ pos,
+                         VoxDev* __restrict__ desc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t key = keys[i];
+    const uint32_t p0 = pos[vptr[key]], p1 = pos[vptr[key + 1]];
+    desc[i] = VoxDev{(int64_t)p0, (int32_t)(p1 - p0), key_to_voxel(scenes, ns, key)};
+}
+
+// weight of entry j = chord length / its pair's summed chord length (equal
+// weights should every chord of the pair have rounded to zero length)
+__global__ void pair_weight_k(const uint32_t* __restrict__ vedge, const uint32_t* __restrict__ pos, int64_t E,
+                              const uint32_t* __restrict__ pstart, const float* __restrict__ wlen,
+                              const double* __restrict__ wsum, float* __restrict__ w)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = pos[j + 1] - 1;   // inclusive count of pair starts, less one
+        const double sw = wsum[p];
+        w[j] = sw > 0.0 ? (float)((double)wlen[vedge[j]] / sw) : (float)(1.0 / (double)(pstart[p + 1] - pstart[p]));
+    }
+}
+
+hipError_t build_keyframe_pairs(mrf_ctx* c, hipStream_t s)
+{
+    hipError_t e;
+    const int64_t E = c->E;
+    const int nf = c->n_frames;
+    // per-keyframe message buffers: frame f's entries follow the frames before it
+    std::vector<int64_t> xb(nf);
+    int64_t nx = 0;
+    for (int f = 0; f < nf; ++f) {
+        const SceneDev& sd = c->scenes_h[c->frames_h[f].scene];
+        xb[f] = nx - sd.voxel_base;
+        nx += (int64_t)sd.n[0] * sd.n[1] * sd.n[2];
+    }
+    if (nx >= (int64_t(1) << 32)) {
+        set_error("per-keyframe message buffers of 2^32 or more entries");
+        return hipErrorInvalidConfiguration;
+    }
+    c->n_kfx = nx;
+    if ((e = ensure(c->b_kfxb, sizeof(int64_t) * (size_t)(nf + 1) * 2)) != hipSuccess) return e;
+    int64_t* d_xb = (int64_t*)c->b_kfxb.p;
+    int64_t* d_fs = d_xb + nf + 1;
+    if ((e = hipMemcpyAsync(d_xb, xb.data(), sizeof(int64_t) * nf, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(frame_slots_k, dim3((unsigned)cdiv(nf + 1, 64)), dim3(64), 0, s,
+                       (const FrameDev*)c->b_frames.p, nf, (const int64_t*)c->b_tbase.p, c->T, d_fs);
+    if ((e = ensure(c->b_kfx, sizeof(float) * (size_t)(nx > 0 ? nx : 1))) != hipSuccess) return e;
+
+    // pair starts: exclusive count over the voxel -> ray list (b_lam, E + 1 entries),
+    // keys sorted in b_lambar from the radix sort
+    const uint32_t* vedge = (const uint32_t*)c->b_vedge.p;
+    const LoadPairStart ld{vedge, (const uint32_t*)c->b_lambar.p, d_fs, nf};
+    uint32_t* pos = (uint32_t*)c->b_lam.p;
+    const size_t sb = scan_tmp_bytes(E);
+    if ((e = ensure(c->b_misc, sb > c->b_misc.cap ? sb : c->b_misc.cap)) != hipSuccess) return e;
+    if ((e = scan_rec(ld, E, pos, (int64_t*)c->b_misc.p, s)) != hipSuccess) return e;
+    uint32_t P32 = 0;
+    if ((e = hipMemcpyAsync(&P32, pos + E, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const int64_t P = P32;
+    c->n_pairs = P;
+    uint32_t* pstart = (uint32_t*)c->b_ell.p;   // P + 1 <= E + 1 entries
+    if ((e = ensure(c->b_pair_x, sizeof(uint32_t) * (size_t)(P > 0 ? P : 1))) != hipSuccess) return e;
+    if ((e = ensure(c->b_pair_m, sizeof(double) * (size_t)(P > 0 ? P : 1))) != hipSuccess) return e;
+    hipLaunchKernelGGL(pair_init_k, dim3((unsigned)cdiv(E + 1, 256)), dim3(256), 0, s, ld, E, (const uint32_t*)pos,
+                       (const SceneDev*)c->b_scenes.p, c->n_scenes, (const int64_t*)d_xb, pstart,
+                       (uint32_t*)c->b_pair_x.p);
+
+    // pairs by edge count, as VoxDev work items of the voxel-phase kernels
+    if ((e = ensure(c->b_cls, (size_t)(P + 1))) != hipSuccess) return e;
+    if ((e = ensure(c->b_tmp64, (size_t)(P + 2) * sizeof(int64_t))) != hipSuccess) return e;
+    const size_t pb = scan_tmp_bytes(P + 1);
+    if ((e = ensure(c->b_misc, pb > c->b_misc.cap ? pb : c->b_misc.cap)) != hipSuccess) return e;
+    uint8_t* cls = (uint8_t*)c->b_cls.p;
+    if (P > 0)
+        hipLaunchKernelGGL(pair_class_k, dim3((unsigned)cdiv(P, 256)), dim3(256), 0, s, (const uint32_t*)pstart, P,
+                           cls);
+    DevBuf list;
+    for (int k = 0; k < kVoxClasses; ++k) {
+        e = partition(cls, P, (uint8_t)k, (int64_t*)c->b_tmp64.p, c->b_misc.p, c->b_misc.cap, list, &c->pair_cnt[k],
+                      s);
+        const int64_t n = c->pair_cnt[k];
+        if (e == hipSuccess) e = ensure(c->b_pair_desc[k], (size_t)(n > 0 ? n : 1) * sizeof(VoxDev));
+        if (e == hipSuccess && n > 0)
+            hipLaunchKernelGGL(pair_desc_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, (const uint32_t*)list.p, n,
+                               (const uint32_t*)pstart, (VoxDev*)c->b_pair_desc[k].p);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // list is rewritten by the next class
+        if (e != hipSuccess) {
+            hipFree(list.p);
+            return e;
+        }
+    }
+    hipFree(list.p);
+
+    // touched voxels with their pair ranges, class by class
+    int64_t nv = 0;
+    for (int k = 0; k < kVoxClasses; ++k) nv += c->vox_cnt[k];
+    c->n_kf_vox = nv;
+    if ((e = ensure(c->b_kf_vox, (size_t)(nv > 0 ? nv : 1) * sizeof(VoxDev))) != hipSuccess) return e;
+    int64_t off = 0;
+    for (int k = 0; k < kVoxClasses; ++k) {
+        const int64_t n = c->vox_cnt[k];
+        if (n > 0)
+            hipLaunchKernelGGL(kf_vox_k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
+                               c->n_scenes, (const uint32_t*)c->b_vox_list[k].p, n, (const int64_t*)c->b_vptr.p,
+                               (const uint32_t*)pos, (VoxDev*)c->b_kf_vox.p + off);
+        off += n;
+    }
+
+    // weights: chord length over the pair's summed chord length, in list order;
+    // the chord lengths (slot order, b_kfw) are summed per pair by the pair phase
+    double* wsum = (double*)c->b_pair_m.p;
+    float* w = (float*)c->b_ellbar.p;
+    if ((e = launch_pair_phase(c, (const float*)c->b_kfw.p, nullptr, wsum, s)) != hipSuccess) return e;
+    if (E > 0) {
+        int64_t b = cdiv(E, 256);
+        if (b > 65536) b = 65536;
+        hipLaunchKernelGGL(pair_weight_k, dim3((unsigned)b), dim3(256), 0, s, vedge, (const uint32_t*)pos, E,
+                           (const uint32_t*)pstart, (const float*)c->b_kfw.p, (const double*)wsum, w);
+    }
+    std::swap(c->b_kfw, c->b_ellbar);   // weights stay in b_kfw; the chord lengths' buffer becomes scratch
     return hipGetLastError();
 }
 

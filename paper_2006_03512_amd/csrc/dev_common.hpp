@@ -528,11 +528,12 @@ constexpr int tile_blocks()
     return 16 * G / 256;
 }
 
-// Slot of step 0 and length of this group's ray; false if the group has none.
+// Slot of step 0 and length of this group's ray (and, when frame is not
+// null, the tile's frame); false if the group has none.
 template <int G, class Tile>
 __device__ __forceinline__ bool tile_ray(const uint32_t* __restrict__ list, int64_t ntiles,
                                          const Tile* __restrict__ tiles, const int32_t* __restrict__ counts,
-                                         int64_t& s0, int& m)
+                                         int64_t& s0, int& m, int* frame = nullptr)
 {
     constexpr int BPT = tile_blocks<G>();
     constexpr int GPB = 256 / G;
@@ -545,6 +546,7 @@ __device__ __forceinline__ bool tile_ray(const uint32_t* __restrict__ list, int6
     if (ux >= td.nu || vy >= td.nv) return false;
     m = counts[td.ray0 + (int64_t)vy * td.W + ux];
     s0 = td.base + i;
+    if (frame) *frame = td.frame;
     return m > 0;
 }
 

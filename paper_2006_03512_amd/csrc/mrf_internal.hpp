@@ -157,7 +157,7 @@ struct TileDev {
     int32_t W;            // image width (ray id stride between tile rows)
     int32_t nu, nv;       // pixels of the tile inside the image
     int32_t len;          // longest ray of the tile (steps)
-    int32_t pad;
+    int32_t frame;        // global frame (keyframe) index
 };
 
 // Per-edge voxel -> ray messages (forward) or d/d ell (reverse) in the form the
@@ -180,6 +180,15 @@ struct ExclDev {
     int has_own;
 };
 
+// Voxel -> ray messages with per-keyframe averaged messages (Sec. IV-A): the
+// message into a ray of keyframe f from voxel v is x[xb[f] + v], one value
+// per (keyframe, voxel) pair (xb[f] = the keyframe's first entry less the
+// first linear voxel id of its scene).
+struct KfSrc {
+    const float* x;
+    const int64_t* xb;
+};
+
 // Outputs of a voxel-phase reduction of sum_v (the FP64 sum of a per-edge
 // array over voxel v's edges), each optional: tot2[v] = pair(base[v] + sum_v),
 // totf[v] = fl(base[v] + sum_v), acc[v] += fl(sum_v); base null reads as 0.
@@ -188,6 +197,7 @@ struct VoxOut {
     float2* tot2;
     float* totf;
     float* acc;
+    double* dsum = nullptr;   // dsum[v] = sum_v (FP64)
 };
 
 // Work item of the voxel kernels: one voxel's edge list vedge[start, start + m)
@@ -214,7 +224,7 @@ struct DevBuf {
 enum KernelId {
     KID_VOX0 = 0,
     KID_RAY0 = KID_VOX0 + kVoxClasses, KID_ADJ0 = KID_RAY0 + kRayClasses,
-    KID_POT = KID_ADJ0 + kRayClasses, KID_SIGMA, KID_COUNT
+    KID_POT = KID_ADJ0 + kRayClasses, KID_SIGMA, KID_PAIR, KID_KFVOX, KID_COUNT
 };
 
 // HIP events recorded around launches on the stream they run on.
@@ -265,6 +275,21 @@ struct mrf_ctx {
     int64_t n_bricks = 0;
     mrf::DevBuf b_tbar;   // reverse pass, float2 pairs: per-voxel sums of d/d lambda, the seed d/d L, a spare
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
+
+    // per-keyframe averaged messages (Sec. IV-A), built when requested
+    int kf = 0;                   // the build made the pair structures
+    int kf_inferred = 0;          // the last inference used them
+    int64_t n_pairs = 0;          // (keyframe, voxel) pairs with at least one edge
+    int64_t n_kfx = 0;            // entries of the per-keyframe message buffers
+    mrf::DevBuf b_kfw;            // per edge slot: chord length (build), then per vedge entry: weight / pair sum
+    mrf::DevBuf b_pair_m;         // per pair: FP64 average message of the keyframe into the voxel
+    mrf::DevBuf b_pair_x;         // per pair: index of its entry in b_kfx
+    mrf::DevBuf b_kfx;            // per-keyframe voxel -> ray messages
+    mrf::DevBuf b_kfxb;           // per frame: b_kfx base less its scene's first voxel id
+    mrf::DevBuf b_kf_vox;         // per touched voxel: VoxDev over its pairs (start, count, voxel id)
+    mrf::DevBuf b_pair_desc[mrf::kVoxClasses];   // pairs by edge-count class: VoxDev (start, m, pair id)
+    int64_t pair_cnt[mrf::kVoxClasses] = {0};
+    int64_t n_kf_vox = 0;
     mrf::DevBuf b_ray_list[mrf::kRayClasses];     // tile ids by tile length class
     mrf::DevBuf b_vox_list[mrf::kVoxClasses];     // brick-major keys
     mrf::DevBuf b_vox_desc[mrf::kVoxClasses];     // matching VoxDev descriptors
@@ -342,6 +367,10 @@ hipError_t export_canonical_edges(const mrf_ctx* c, const void* in_slots, void* 
 hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s);
 hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// per-keyframe averaged messages: (keyframe, voxel) pairs of the built graph,
+// their weights, work classes and message-buffer indices (after build_classes,
+// with the sorted voxel keys still in b_lambar and chord lengths in b_kfw)
+hipError_t build_keyframe_pairs(mrf_ctx* c, hipStream_t s);
 
 inline ExclDev excl_dev(const mrf_ctx* c, ExclSrc x)
 {
@@ -364,6 +393,16 @@ hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam,
                                   float* gsum, int first, hipStream_t s);
 // out_e = tot[col_e] - own_e on every edge slot (0 on padding)
 hipError_t launch_excl(const mrf_ctx* c, ExclSrc x, float* out, hipStream_t s);
+// per-keyframe averaged messages: the ray phase reading x[xb[frame] + col]
+hipError_t launch_ray_phase_kf(mrf_ctx* c, KfSrc lam, float* ell, bool plain, hipStream_t s);
+hipError_t launch_ray_class_shape_kf(const mrf_ctx* c, int q, int sel, KfSrc lam, float* ell, hipStream_t s);
+// M[p] = FP64 sum over pair p's list entries j of w[j] in[vedge[j]] (w null: 1)
+hipError_t launch_pair_phase(mrf_ctx* c, const float* in, const float* w, double* M, hipStream_t s);
+// per touched voxel: T = theta + sum of its pairs' M; x[pair_x[p]] = fl(T - M[p])
+// for every pair when x is not null; L[v] = fl(T) when L is not null
+hipError_t launch_kf_voxel(mrf_ctx* c, const float* theta, float* x, float* L, hipStream_t s);
+// out_e = x[xb[frame of e] + col_e] on every edge slot (0 on padding)
+hipError_t launch_excl_kf(const mrf_ctx* c, KfSrc x, float* out, hipStream_t s);
 hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
 
 // adjoint_kernels.hip

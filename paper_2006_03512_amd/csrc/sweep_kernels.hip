@@ -199,20 +199,39 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 // FP64 sum over items base + 64 k + l (k < N, l the lane) of the edge list
 // [s, s+m) of one voxel (0 past m).  Branchless, with item indices clamped to
 // m - 1 (m >= 1), so that every load is issued before the first wait.
-template <int N>
+// An item's term: in[vedge[j]], times the list-order weight w[j] when the
+// sum is weighted (per-keyframe averages); the product of two FP32 values is
+// exact in FP64.
+template <bool WT>
+__device__ __forceinline__ double vox_term(float x, const float* __restrict__ w, int64_t j)
+{
+    if constexpr (WT)
+        return (double)x * (double)w[j];
+    else
+        return (double)x;
+}
+
+template <int N, bool WT = false>
 __device__ __forceinline__ double vox_lane_sum(int64_t s, int m, int base, const uint32_t* __restrict__ vedge,
-                                               const float* __restrict__ in)
+                                               const float* __restrict__ in, const float* __restrict__ w = nullptr)
 {
     const int l = threadIdx.x & 63;
     uint32_t e[N];
-    float x[N];
+    float x[N], wt[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) e[k] = vedge[s + min(base + k * 64 + l, m - 1)];
+    if constexpr (WT) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) wt[k] = w[s + min(base + k * 64 + l, m - 1)];
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) x[k] = in[e[k]];
     double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) a += base + k * 64 + l < m ? (double)x[k] : 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double t = WT ? (double)x[k] * (double)wt[k] : (double)x[k];
+        a += base + k * 64 + l < m ? t : 0.0;
+    }
     return a;
 }
 
@@ -222,6 +241,7 @@ __device__ __forceinline__ void vox_store(uint32_t v, double sum, const VoxOut& 
     if (o.tot2) o.tot2[v] = split_pair(t);
     if (o.totf) o.totf[v] = (float)t;
     if (o.acc) o.acc[v] += (float)sum;
+    if (o.dsum) o.dsum[v] = sum;
 }
 
 // One voxel's edge list [s, s+m) summed by NW waves, each owning 64*IPL
@@ -231,10 +251,11 @@ __device__ __forceinline__ void vox_store(uint32_t v, double sum, const VoxOut& 
 // before the first wait (more bytes in flight per wave for low degrees).
 // Voxels arrive in brick-major order and blocks are remapped so each XCD
 // takes a contiguous range of them.
-template <int NW, int IPL, int VPW>
+template <int NW, int IPL, int VPW, bool WT = false>
 __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev* __restrict__ vd, int64_t n,
                                                                    const uint32_t* __restrict__ vedge,
-                                                                   const float* __restrict__ in, VoxOut out)
+                                                                   const float* __restrict__ in, VoxOut out,
+                                                                   const float* __restrict__ w)
 {
     static_assert(NW == 1 || VPW == 1, "several voxels per wave only with one wave per voxel");
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -246,11 +267,17 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
 #pragma unroll
         for (int u = 0; u < VPW; ++u) d[u] = vd[min(v0 + u, n - 1)];   // past the list: a repeat, not stored
         uint32_t e[VPW][IPL];
-        float x[VPW][IPL];
+        float x[VPW][IPL], wt[VPW][IPL];
 #pragma unroll
         for (int u = 0; u < VPW; ++u)
 #pragma unroll
             for (int k = 0; k < IPL; ++k) e[u][k] = vedge[d[u].start + min(k * 64 + l, d[u].m - 1)];
+        if constexpr (WT) {
+#pragma unroll
+            for (int u = 0; u < VPW; ++u)
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) wt[u][k] = w[d[u].start + min(k * 64 + l, d[u].m - 1)];
+        }
 #pragma unroll
         for (int u = 0; u < VPW; ++u)
 #pragma unroll
@@ -259,7 +286,10 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
         for (int u = 0; u < VPW; ++u) {
             double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) a += k * 64 + l < d[u].m ? (double)x[u][k] : 0.0;
+            for (int k = 0; k < IPL; ++k) {
+                const double t = WT ? (double)x[u][k] * (double)wt[u][k] : (double)x[u][k];
+                a += k * 64 + l < d[u].m ? t : 0.0;
+            }
             a = dgroup_sum_d<64>(a);
             if (l == 0 && v0 + u < n) vox_store(d[u].v, a, out);
         }
@@ -267,7 +297,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
         const int64_t vi = lb;
         if (vi >= n) return;   // whole block
         const VoxDev d = vd[vi];
-        const double a = dgroup_sum_d<64>(vox_lane_sum<IPL>(d.start, d.m, wv * 64 * IPL, vedge, in));
+        const double a = dgroup_sum_d<64>(vox_lane_sum<IPL, WT>(d.start, d.m, wv * 64 * IPL, vedge, in, w));
         __shared__ double wsum[NW];
         if (l == 0) wsum[wv] = a;
         __syncthreads();
@@ -282,10 +312,10 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
 // Voxels of at most G edges (G = 16 or 32): 64 / G lane groups per wave, 256
 // / G per block, each group summing VPG consecutive voxels of the list (lane
 // l holds edge l of each; group reductions), every load issued first.
-template <int G, int VPG>
+template <int G, int VPG, bool WT = false>
 __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ vd, int64_t n,
                                                      const uint32_t* __restrict__ vedge, const float* __restrict__ in,
-                                                     VoxOut out)
+                                                     VoxOut out, const float* __restrict__ w)
 {
     constexpr int GPB = 256 / G;   // groups per block
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -296,14 +326,19 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
 #pragma unroll
     for (int u = 0; u < VPG; ++u) d[u] = vd[min(v0 + u, n - 1)];   // past the list: a repeat, not stored
     uint32_t e[VPG];
-    float x[VPG];
+    float x[VPG], wt[VPG];
 #pragma unroll
     for (int u = 0; u < VPG; ++u) e[u] = vedge[d[u].start + min(l, d[u].m - 1)];
+    if constexpr (WT) {
+#pragma unroll
+        for (int u = 0; u < VPG; ++u) wt[u] = w[d[u].start + min(l, d[u].m - 1)];
+    }
 #pragma unroll
     for (int u = 0; u < VPG; ++u) x[u] = in[e[u]];
 #pragma unroll
     for (int u = 0; u < VPG; ++u) {
-        const double sum = dgroup_sum_d<G>(l < d[u].m ? (double)x[u] : 0.0);   // at group lane 0
+        const double t = WT ? (double)x[u] * (double)wt[u] : (double)x[u];
+        const double sum = dgroup_sum_d<G>(l < d[u].m ? t : 0.0);   // at group lane 0
         if (l == 0 && v0 + u < n) vox_store(d[u].v, sum, out);
     }
 }
@@ -311,9 +346,11 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
 // One 1024-thread block per voxel of degree above the largest single-pass
 // class: wave w sums pieces w, w + 16, ... of 1024 edges in order, and the 16
 // wave sums are added in wave order.
+template <bool WT = false>
 __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict__ vd, int64_t n,
                                                         const uint32_t* __restrict__ vedge,
-                                                        const float* __restrict__ in, VoxOut out)
+                                                        const float* __restrict__ in, VoxOut out,
+                                                        const float* __restrict__ w)
 {
     __shared__ double wsum[16];
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
@@ -322,7 +359,8 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
     const VoxDev d = vd[b];
     const int nch = (d.m + kVoxChunk - 1) / kVoxChunk;
     double a = 0.0;
-    for (int c = wv; c < nch; c += 16) a += vox_lane_sum<kVoxChunk / 64>(d.start, d.m, c * kVoxChunk, vedge, in);
+    for (int c = wv; c < nch; c += 16)
+        a += vox_lane_sum<kVoxChunk / 64, WT>(d.start, d.m, c * kVoxChunk, vedge, in, w);
     a = dgroup_sum_d<64>(a);
     if (l == 0) wsum[wv] = a;
     __syncthreads();
@@ -333,25 +371,43 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
     }
 }
 
-template <int K>
-static void launch_voxel_class(mrf_ctx* c, const float* in, VoxOut out, hipStream_t s)
+// Class K of a segment list (voxels, or keyframe pairs with weights w) with n
+// work items described by desc.
+template <int K, bool WT>
+static void launch_seg_class(const VoxDev* desc, int64_t n, const uint32_t* vedge, const float* in, VoxOut out,
+                             const float* w, hipStream_t s)
 {
-    const int64_t n = c->vox_cnt[K];
     if (n <= 0) return;
-    ProfScope ps(c, KID_VOX0 + K, s);
     constexpr int NW = kVoxNW[K];
     if constexpr (NW == 0) {
         constexpr int G = kVoxCap[K];
         constexpr int VPG = kVoxVPW[K];
-        hipLaunchKernelGGL((voxel_small_k<G, VPG>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s,
-                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, in, out);
+        hipLaunchKernelGGL((voxel_small_k<G, VPG, WT>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s, desc, n, vedge,
+                           in, out, w);
     } else {
         constexpr int IPL = kVoxCap[K] / (64 * NW);
         constexpr int VPW = kVoxVPW[K];
         const unsigned blocks = NW == 1 ? nblk(n, 4 * VPW) : (unsigned)n;
-        hipLaunchKernelGGL((voxel_k<NW, IPL, VPW>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s,
-                           (const VoxDev*)c->b_vox_desc[K].p, n, (const uint32_t*)c->b_vedge.p, in, out);
+        hipLaunchKernelGGL((voxel_k<NW, IPL, VPW, WT>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s, desc, n,
+                           vedge, in, out, w);
     }
+}
+
+template <bool WT>
+static void launch_seg_chunked(const VoxDev* desc, int64_t n, const uint32_t* vedge, const float* in, VoxOut out,
+                               const float* w, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(voxel_chunked_k<WT>, dim3((unsigned)n), dim3(1024), 0, s, desc, n, vedge, in, out, w);
+}
+
+template <int K>
+static void launch_voxel_class(mrf_ctx* c, const float* in, VoxOut out, hipStream_t s)
+{
+    if (c->vox_cnt[K] <= 0) return;
+    ProfScope ps(c, KID_VOX0 + K, s);
+    launch_seg_class<K, false>((const VoxDev*)c->b_vox_desc[K].p, c->vox_cnt[K], (const uint32_t*)c->b_vedge.p, in,
+                               out, nullptr, s);
 }
 
 template <int... K>
@@ -366,10 +422,73 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* in, VoxOut out, hipStream
     const int kc = kVoxClasses - 1;
     if (c->vox_cnt[kc] > 0) {
         ProfScope ps(c, KID_VOX0 + kc, s);
-        hipLaunchKernelGGL(voxel_chunked_k, dim3((unsigned)c->vox_cnt[kc]), dim3(1024), 0, s,
-                           (const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p, in,
-                           out);
+        launch_seg_chunked<false>((const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p,
+                                  in, out, nullptr, s);
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ keyframe pairs
+//
+// Per-keyframe averaged messages (Sec. IV-A): keyframe f sends voxel v the
+// average M_fv = sum_j w_j ell_j of its rays' messages, w_j the edge's chord
+// length over the pair's summed chord length, and a ray of keyframe f
+// receives theta_v plus the other keyframes' averages.  The pair phase forms
+// every M (FP64, fixed order); the voxel step sums them per voxel and writes,
+// per pair, x = fl(T - M_fv) into keyframe f's message buffer.
+
+template <int... K>
+static void pair_classes(std::integer_sequence<int, K...>, mrf_ctx* c, const float* in, VoxOut out,
+                         const float* w, hipStream_t s)
+{
+    ((w ? launch_seg_class<K, true>((const VoxDev*)c->b_pair_desc[K].p, c->pair_cnt[K],
+                                    (const uint32_t*)c->b_vedge.p, in, out, w, s)
+        : launch_seg_class<K, false>((const VoxDev*)c->b_pair_desc[K].p, c->pair_cnt[K],
+                                     (const uint32_t*)c->b_vedge.p, in, out, nullptr, s)),
+     ...);
+}
+
+hipError_t launch_pair_phase(mrf_ctx* c, const float* in, const float* w, double* M, hipStream_t s)
+{
+    VoxOut out{nullptr, nullptr, nullptr, nullptr, M};
+    ProfScope ps(c, KID_PAIR, s);
+    pair_classes(std::make_integer_sequence<int, kVoxClasses - 1>{}, c, in, out, w, s);
+    const int kc = kVoxClasses - 1;
+    const VoxDev* d = (const VoxDev*)c->b_pair_desc[kc].p;
+    if (w)
+        launch_seg_chunked<true>(d, c->pair_cnt[kc], (const uint32_t*)c->b_vedge.p, in, out, w, s);
+    else
+        launch_seg_chunked<false>(d, c->pair_cnt[kc], (const uint32_t*)c->b_vedge.p, in, out, nullptr, s);
+    return hipGetLastError();
+}
+
+// One 16-lane group per touched voxel: T = theta_v + the sum of the voxel's
+// pair averages (FP64; lane-strided partial sums added in a fixed order), then
+// every pair's message x = fl(T - M) into its keyframe's buffer, and L_v = fl(T).
+__global__ __launch_bounds__(256) void kf_voxel_k(const VoxDev* __restrict__ vd, int64_t n,
+                                                  const double* __restrict__ M, const uint32_t* __restrict__ px,
+                                                  const float* __restrict__ theta, float* __restrict__ x,
+                                                  float* __restrict__ L)
+{
+    const int64_t vi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 16 + (int)(threadIdx.x >> 4);
+    if (vi >= n) return;   // whole group
+    const int l = (int)(threadIdx.x & 15);
+    const VoxDev d = vd[vi];
+    double a = 0.0;
+    for (int q = l; q < d.m; q += 16) a += M[d.start + q];
+    a = dgroup_sum_d<16>(a);
+    const double T = (double)theta[d.v] + __shfl(a, (int)(threadIdx.x & 48), 64);
+    if (x)
+        for (int q = l; q < d.m; q += 16) x[px[d.start + q]] = (float)(T - M[d.start + q]);
+    if (L && l == 0) L[d.v] = (float)T;
+}
+
+hipError_t launch_kf_voxel(mrf_ctx* c, const float* theta, float* x, float* L, hipStream_t s)
+{
+    if (c->n_kf_vox <= 0) return hipSuccess;
+    ProfScope ps(c, KID_KFVOX, s);
+    hipLaunchKernelGGL(kf_voxel_k, dim3(nblk(c->n_kf_vox, 16)), dim3(256), 0, s, (const VoxDev*)c->b_kf_vox.p,
+                       c->n_kf_vox, (const double*)c->b_pair_m.p, (const uint32_t*)c->b_pair_x.p, theta, x, L);
     return hipGetLastError();
 }
 
@@ -426,33 +545,42 @@ __device__ __forceinline__ void ray_body(const float (&al)[IPL], const float (&b
 // 64-byte row per step holds the 16 rays of the tile); lambda_e = tot[col_e] -
 // own_e.  Step indices are clamped to the ray (m >= 1) so that every load is
 // issued before the first wait.
-template <int G, int IPL>
+// With KF (per-keyframe averaged messages, Sec. IV-A) lambda_e is the message
+// of the ray's keyframe, kf.x[kf.xb[frame] + col_e], instead.
+template <int G, int IPL, bool KF>
 __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                              const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
-                                             const int32_t* __restrict__ col, ExclDev lam,
+                                             const int32_t* __restrict__ col, ExclDev lam, KfSrc kf,
                                              const float* __restrict__ g, float* __restrict__ ell)
 {
     static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
     int64_t s;
-    int m;
-    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
+    int m, frame = 0;
+    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m, &frame)) return;
     const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
     int32_t cv[IPL];
-    float ov[IPL], gv[IPL];
+    float ov[IPL], gv[IPL], lv[IPL];
     float2 tv[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const int64_t at = s + kTile * (int64_t)min(i0 + j, m - 1);
         cv[j] = col[at];
-        ov[j] = lam.own[at];
+        if constexpr (!KF) ov[j] = lam.own[at];
         gv[j] = g[at];
     }
+    if constexpr (KF) {
+        const float* xf = kf.x + kf.xb[frame];
 #pragma unroll
-    for (int j = 0; j < IPL; ++j) tv[j] = lam.tot[max(cv[j], 0)];
+        for (int j = 0; j < IPL; ++j) lv[j] = cv[j] >= 0 ? xf[cv[j]] : 0.0f;
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) tv[j] = lam.tot[max(cv[j], 0)];
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) lv[j] = excl_value(cv[j], tv[j], ov[j], lam.has_own);
+    }
     float al[IPL], be[IPL], gg[IPL];
 #pragma unroll
-    for (int j = 0; j < IPL; ++j)
-        load_step(excl_value(cv[j], tv[j], ov[j], lam.has_own), gv[j], i0 + j < m, al[j], be[j], gg[j]);
+    for (int j = 0; j < IPL; ++j) load_step(lv[j], gv[j], i0 + j < m, al[j], be[j], gg[j]);
     ray_body<G, IPL>(al, be, gg, m, i0, [&](int j, bool ok, float v) {
         if (ok) ell[s + kTile * (i0 + j)] = v;
     });
@@ -464,11 +592,11 @@ __global__ __launch_bounds__(256) void ray_k(const uint32_t* __restrict__ list, 
 // = tot[col] - own and g into LDS; every group runs the scans of its own ray
 // on its LDS column and writes ell back into that column (0 past the ray),
 // and the block stores the tile coalesced.
-template <int G, int IPL>
+template <int G, int IPL, bool KF>
 __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                        const TileDev* __restrict__ tiles,
                                                        const int32_t* __restrict__ counts,
-                                                       const int32_t* __restrict__ col, ExclDev lam,
+                                                       const int32_t* __restrict__ col, ExclDev lam, KfSrc kf,
                                                        const float* __restrict__ g, float* __restrict__ ell)
 {
     constexpr int NT = kTile * G;
@@ -488,12 +616,18 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
         float vo[IPL], vg[IPL], vt[IPL];
         float2 vp[IPL];
         tile_fetch_i<NT, IPL>(col, td.base, nf, vc);
-        tile_fetch<NT, IPL>(lam.own, td.base, nf, vo);
+        if constexpr (!KF) tile_fetch<NT, IPL>(lam.own, td.base, nf, vo);
         tile_fetch<NT, IPL>(g, td.base, nf, vg);
+        if constexpr (KF) {
+            const float* xf = kf.x + kf.xb[td.frame];
 #pragma unroll
-        for (int r = 0; r < IPL; ++r) vp[r] = lam.tot[max(vc[r], 0)];
+            for (int r = 0; r < IPL; ++r) vt[r] = vc[r] >= 0 ? xf[vc[r]] : 0.0f;
+        } else {
 #pragma unroll
-        for (int r = 0; r < IPL; ++r) vt[r] = excl_value(vc[r], vp[r], vo[r], lam.has_own);
+            for (int r = 0; r < IPL; ++r) vp[r] = lam.tot[max(vc[r], 0)];
+#pragma unroll
+            for (int r = 0; r < IPL; ++r) vt[r] = excl_value(vc[r], vp[r], vo[r], lam.has_own);
+        }
         tile_to_lds<NT, IPL, IPL>(sl, nf, vt);
         tile_to_lds<NT, IPL, IPL>(sg, nf, vg);
     }
@@ -509,80 +643,115 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
     tile_store<NT, IPL, IPL>(ell, td.base, nf, [&](int, int at) { return sl[at]; });
 }
 
-template <int Q, int I>
-static void launch_ray_shape(const mrf_ctx* c, int64_t off, int64_t n, ExclDev lam, float* ell, hipStream_t s)
+// The voxel -> ray messages one ray-phase launch reads: per-edge exclusion
+// from the voxel totals, or (kf) the per-keyframe message buffers.
+struct RaySrc {
+    ExclDev lam;
+    KfSrc kf;
+    bool is_kf;
+};
+
+template <int Q, int I, bool KF>
+static void launch_ray_shape_t(const mrf_ctx* c, int64_t off, int64_t n, const RaySrc& src, float* ell, hipStream_t s)
 {
     constexpr int G = kFwdShapes[Q][I].g;
     if constexpr (G != 0) {
         constexpr int CAP = kRayCap[Q];
         const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p + off;
         if constexpr (ray_class_lds(Q)) {
-            hipLaunchKernelGGL((ray_lds_k<G, CAP / G>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
+            hipLaunchKernelGGL((ray_lds_k<G, CAP / G, KF>), dim3((unsigned)n), dim3(kTile * G), 0, s, list, n,
                                (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
-                               (const int32_t*)c->b_col.p, lam, (const float*)c->b_g.p, ell);
+                               (const int32_t*)c->b_col.p, src.lam, src.kf, (const float*)c->b_g.p, ell);
         } else {
-            hipLaunchKernelGGL((ray_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s, list,
-                               n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
-                               (const int32_t*)c->b_col.p, lam, (const float*)c->b_g.p, ell);
+            hipLaunchKernelGGL((ray_k<G, CAP / G, KF>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+                               list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
+                               (const int32_t*)c->b_col.p, src.lam, src.kf, (const float*)c->b_g.p, ell);
         }
     }
 }
 
+template <int Q, int I>
+static void launch_ray_shape(const mrf_ctx* c, int64_t off, int64_t n, const RaySrc& src, float* ell, hipStream_t s)
+{
+    if (src.is_kf)
+        launch_ray_shape_t<Q, I, true>(c, off, n, src, ell, s);
+    else
+        launch_ray_shape_t<Q, I, false>(c, off, n, src, ell, s);
+}
+
 template <int Q, int... I>
-static void launch_ray_sel(int sel, const mrf_ctx* c, int64_t off, int64_t n, ExclDev lam, float* ell,
+static void launch_ray_sel(int sel, const mrf_ctx* c, int64_t off, int64_t n, const RaySrc& src, float* ell,
                            hipStream_t s, std::integer_sequence<int, I...>)
 {
-    ((sel == I ? launch_ray_shape<Q, I>(c, off, n, lam, ell, s) : void()), ...);
+    ((sel == I ? launch_ray_shape<Q, I>(c, off, n, src, ell, s) : void()), ...);
 }
 
 // class Q of the ray phase with launch shape sel, over n tiles of its list from off
 template <int Q>
-static void launch_ray_class(const mrf_ctx* c, int sel, int64_t off, int64_t n, ExclDev lam, float* ell,
+static void launch_ray_class(const mrf_ctx* c, int sel, int64_t off, int64_t n, const RaySrc& src, float* ell,
                              hipStream_t s)
 {
     if (n <= 0) return;
     ProfScope ps(c, KID_RAY0 + Q, s);
-    launch_ray_sel<Q>(sel, c, off, n, lam, ell, s, std::make_integer_sequence<int, kNShapes>{});
+    launch_ray_sel<Q>(sel, c, off, n, src, ell, s, std::make_integer_sequence<int, kNShapes>{});
+}
+
+// The untuned shape of the plain schedule: one 64-lane wave per ray where the
+// class has such a shape (the 16-step class holds a ray in 16 lanes).
+constexpr int plain_shape(int q)
+{
+    for (int i = 0; i < ray_shape_count(q, false); ++i)
+        if (kFwdShapes[q][i].g == 64) return i;
+    return 0;
 }
 
 template <int... Q>
 static void ray_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const int64_t* off, const int64_t* cnt,
-                        ExclDev lam, float* ell, hipStream_t s)
+                        const RaySrc& src, float* ell, bool plain, hipStream_t s)
 {
-    (launch_ray_class<Q>(c, c->fwd_sel[Q], off[Q], cnt[Q], lam, ell, s), ...);
+    (launch_ray_class<Q>(c, plain ? plain_shape(Q) : c->fwd_sel[Q], off[Q], cnt[Q], src, ell, s), ...);
 }
 
-static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt, ExclDev lam, float* ell,
-                        hipStream_t s)
+static void ray_classes(const mrf_ctx* c, const int64_t* off, const int64_t* cnt, const RaySrc& src, float* ell,
+                        bool plain, hipStream_t s)
 {
-    ray_classes(std::make_integer_sequence<int, kRayClasses>{}, c, off, cnt, lam, ell, s);
+    ray_classes(std::make_integer_sequence<int, kRayClasses>{}, c, off, cnt, src, ell, plain, s);
 }
 
-using RayClassFn = void (*)(const mrf_ctx*, int, int64_t, int64_t, ExclDev, float*, hipStream_t);
+using RayClassFn = void (*)(const mrf_ctx*, int, int64_t, int64_t, const RaySrc&, float*, hipStream_t);
 template <int... Q>
 static constexpr std::array<RayClassFn, kRayClasses> ray_class_fns(std::integer_sequence<int, Q...>)
 {
     return {&launch_ray_class<Q>...};
 }
 
-hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam, float* ell, hipStream_t s)
+static hipError_t ray_class_shape(const mrf_ctx* c, int q, int sel, const RaySrc& src, float* ell, hipStream_t s)
 {
     static constexpr std::array<RayClassFn, kRayClasses> fns =
         ray_class_fns(std::make_integer_sequence<int, kRayClasses>{});
     if (q < 0 || q >= kRayClasses || sel < 0 || sel >= ray_shape_count(q, false)) return hipErrorInvalidValue;
-    fns[q](c, sel, 0, c->ray_cnt[q], excl_dev(c, lam), ell, s);
+    fns[q](c, sel, 0, c->ray_cnt[q], src, ell, s);
     return hipGetLastError();
 }
 
-hipError_t launch_ray_phase(mrf_ctx* c, ExclSrc lam_src, float* ell, bool plain, hipStream_t s)
+hipError_t launch_ray_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam, float* ell, hipStream_t s)
 {
-    const ExclDev lam = excl_dev(c, lam_src);
+    return ray_class_shape(c, q, sel, RaySrc{excl_dev(c, lam), KfSrc{nullptr, nullptr}, false}, ell, s);
+}
+
+hipError_t launch_ray_class_shape_kf(const mrf_ctx* c, int q, int sel, KfSrc lam, float* ell, hipStream_t s)
+{
+    return ray_class_shape(c, q, sel, RaySrc{excl_dev(c, ExclSrc{nullptr, nullptr}), lam, true}, ell, s);
+}
+
+static hipError_t ray_phase(mrf_ctx* c, const RaySrc& src, float* ell, bool plain, hipStream_t s)
+{
     int64_t off[kRayClasses] = {0}, cnt[kRayClasses];
     if (!plain) {
         for (int k = 0; k < kRayClasses; ++k) cnt[k] = c->ray_cnt[k];
-        ray_classes(c, off, cnt, lam, ell, s);
+        ray_classes(c, off, cnt, src, ell, false, s);
     } else {
-        // one launch per frame (per class): the plain per-frame schedule
+        // the plain per-frame schedule: one launch per frame (per class), untuned shapes
         const int nf = c->n_frames;
         for (int f = 0; f < nf; ++f) {
             for (int k = 0; k < kRayClasses; ++k) {
@@ -590,9 +759,46 @@ hipError_t launch_ray_phase(mrf_ctx* c, ExclSrc lam_src, float* ell, bool plain,
                 off[k] = fo[f];
                 cnt[k] = fo[f + 1] - fo[f];
             }
-            ray_classes(c, off, cnt, lam, ell, s);
+            ray_classes(c, off, cnt, src, ell, true, s);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_phase(mrf_ctx* c, ExclSrc lam_src, float* ell, bool plain, hipStream_t s)
+{
+    return ray_phase(c, RaySrc{excl_dev(c, lam_src), KfSrc{nullptr, nullptr}, false}, ell, plain, s);
+}
+
+hipError_t launch_ray_phase_kf(mrf_ctx* c, KfSrc lam, float* ell, bool plain, hipStream_t s)
+{
+    return ray_phase(c, RaySrc{excl_dev(c, ExclSrc{nullptr, nullptr}), lam, true}, ell, plain, s);
+}
+
+// lambda_e of the per-keyframe messages on every slot (exports)
+__global__ void excl_kf_k(const int32_t* __restrict__ col, const int64_t* __restrict__ fs, int nf, KfSrc x,
+                          float* __restrict__ out, int64_t S)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = col[i];
+        int lo = 0, hi = nf;   // frame of slot i: the last f with fs[f] <= i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (fs[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        out[i] = v >= 0 ? x.x[x.xb[lo] + v] : 0.0f;
+    }
+}
+
+hipError_t launch_excl_kf(const mrf_ctx* c, KfSrc x, float* out, hipStream_t s)
+{
+    if (c->S <= 0) return hipSuccess;
+    const int64_t* fs = (const int64_t*)c->b_kfxb.p + c->n_frames + 1;
+    hipLaunchKernelGGL(excl_kf_k, dim3(grid_for(c->S)), dim3(256), 0, s, (const int32_t*)c->b_col.p, fs, c->n_frames,
+                       x, out, c->S);
     return hipGetLastError();
 }
 

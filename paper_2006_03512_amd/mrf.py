@@ -33,6 +33,7 @@ class GraphStats:
     fwd_bytes_per_sweep: float
     n_slots: int
     n_tiles: int
+    n_keyframe_pairs: int = 0
 
 
 class RayMRF:
@@ -105,12 +106,13 @@ class RayMRF:
         self._params = p0
         self._frames_built = False   # the context still points at the previous upload's frames
 
-    def build_resident(self, keep_chords: bool = False, stream=None):
-        """(Re)build the ray MRF from the uploaded frames."""
+    def build_resident(self, keep_chords: bool = False, stream=None, keyframe_average: bool = False):
+        """(Re)build the ray MRF from the uploaded frames; keyframe_average
+        prepares ``infer_keyframe_avg`` (Sec. IV-A)."""
         p0 = self._params
         bp = _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
                               p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0,
-                              1 if p0.sparse_bricks else 0, int(p0.brick_radius))
+                              1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0)
         with torch.cuda.device(self.device):
             check(self._L.mrf_build(self._h, self._arr, len(self._arr), C.byref(bp),
                                     stream_handle(stream)), "mrf_build")
@@ -120,10 +122,10 @@ class RayMRF:
         self._frames_built = True
         return st
 
-    def build(self, scenes, keep_chords: bool = False, stream=None):
+    def build(self, scenes, keep_chords: bool = False, stream=None, keyframe_average: bool = False):
         """Upload and build the ray MRF of one scene or a list of scenes (batched)."""
         self.upload(scenes)
-        return self.build_resident(keep_chords, stream)
+        return self.build_resident(keep_chords, stream, keyframe_average)
 
     def stats(self) -> GraphStats:
         st = _lib.Stats()
@@ -131,7 +133,7 @@ class RayMRF:
         return GraphStats(st.n_scenes, st.n_rays, st.n_edges, st.n_voxels, st.n_kept_rays,
                           st.n_touched_voxels, st.max_ray_len, st.max_voxel_degree,
                           list(st.ray_len_hist), list(st.voxel_degree_hist), st.fwd_bytes_per_sweep,
-                          st.n_slots, st.n_tiles)
+                          st.n_slots, st.n_tiles, st.n_keyframe_pairs)
 
     def set_schedule(self, schedule: str):
         code = {"plain": _lib.MRF_SCHED_PLAIN, "graph": _lib.MRF_SCHED_GRAPH}[schedule]
@@ -158,6 +160,16 @@ class RayMRF:
             self._vec(bias_table, N_BINS, "bias_table")
             check(self._L.mrf_infer_sensor(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
                                            int(sweeps), keep, stream_handle(stream)), "mrf_infer_sensor")
+
+    def infer_keyframe_avg(self, prior_logit, sigma_table, sweeps: int, stream=None, bias_table=None):
+        """K sweeps with per-keyframe averaged messages (Sec. IV-A); needs a
+        build with keyframe_average=True.  No reverse pass."""
+        self._vec(prior_logit, self.n_voxels, "prior_logit")
+        self._vec(sigma_table, N_BINS, "sigma_table")
+        if bias_table is not None:
+            self._vec(bias_table, N_BINS, "bias_table")
+        check(self._L.mrf_infer_keyframe_avg(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
+                                             int(sweeps), stream_handle(stream)), "mrf_infer_keyframe_avg")
 
     def marginals(self, stream=None):
         p = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device)

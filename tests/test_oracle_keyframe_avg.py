@@ -1,7 +1,7 @@
 """Pins of the oracle's per-keyframe averaged messages (Sec. IV-A: the rays of
 one keyframe crossing a voxel send one message, their average weighted by the
 length each travels in the voxel; a ray's incoming message leaves out its own
-keyframe).  The GPU kernels do not implement this scheme yet."""
+keyframe).  GPU parity against these functions: tests/test_gpu_keyframe.py."""
 import math
 
 import numpy as np
