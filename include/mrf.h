@@ -248,6 +248,20 @@ int mrf_backward_gen(mrf_ctx* ctx, uint64_t generation, const float* dloss_dlogi
 int mrf_accuracy(mrf_ctx* ctx, const float* logit, double vis_min, int8_t* ray_code,
                  double* surface_depth, int64_t* counts, void* stream);
 
+/* mrf_accuracy for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same computation and outputs, bit for bit, but the 16 V bytes of per-voxel
+ * scratch come from a device array inside the library (one per GPU, held
+ * until the process ends) instead of a context allocation; the call makes no
+ * allocation.  Limit: V <= 2^21 = 2,097,152 voxels over the built scenes, else
+ * MRF_ERANGE with nothing enqueued.  Every call on one GPU shares that GPU's
+ * array (every entry read is written first in the same call): calls that
+ * overlap on one GPU (other streams, other threads, other contexts) race.
+ * Errors: as mrf_accuracy, MRF_ERANGE, MRF_EHIP if the array could not be
+ * located on this device. */
+int mrf_accuracy_static(mrf_ctx* ctx, const float* logit, double vis_min, int8_t* ray_code,
+                        double* surface_depth, int64_t* counts, void* stream);
+
 /* Sizes and histograms of the built graph (host struct). */
 int mrf_stats(const mrf_ctx* ctx, mrf_stats_t* out);
 

@@ -203,6 +203,9 @@ int mrf_create(mrf_ctx** out)
     mrf_ctx* c = new (std::nothrow) mrf_ctx();
     if (!c) return fail(MRF_ENOMEM, "mrf_create: host allocation failed");
     hipError_t e = hipGetDevice(&c->device);
+    // the static scratch of mrf_accuracy_static on this device: looked up once per
+    // device with the device current (a failed lookup only disables that call)
+    if (e == hipSuccess) static_scratch_init(c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
@@ -673,7 +676,31 @@ int mrf_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* ray_cod
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_accuracy: hipSetDevice");
     HCK(ensure(c->b_metric, 2 * sizeof(double) * (size_t)c->V), "mrf_accuracy: alloc");
-    HCK(launch_accuracy(c, logit, vis_min, ray_code, surface_depth, counts, s), "mrf_accuracy");
+    HCK(launch_accuracy(c, logit, vis_min, ray_code, surface_depth, counts, (double*)c->b_metric.p, s),
+        "mrf_accuracy");
+    return MRF_OK;
+}
+
+int mrf_accuracy_static(mrf_ctx* c, const float* logit, double vis_min, int8_t* ray_code, double* surface_depth,
+                        int64_t* counts, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_accuracy_static: null context");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_accuracy_static: call mrf_build first");
+    if (!(vis_min > 0.0 && vis_min <= 1.0))
+        return fail(MRF_EINVAL, "mrf_accuracy_static: vis_min must lie in (0, 1]");
+    if (c->V > kStaticMetricVoxels)
+        return fail(MRF_ERANGE, "mrf_accuracy_static: the scenes hold " + std::to_string(c->V) +
+                                    " voxels, more than the static scratch's " +
+                                    std::to_string(kStaticMetricVoxels));
+    if (!logit) {
+        if (!c->inferred) return fail(MRF_ESTATE, "mrf_accuracy_static: no map given and no mrf_infer yet");
+        logit = (const float*)c->b_L.p;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    double* work = nullptr;
+    HCK(static_scratch(c->device, &work), "mrf_accuracy_static: static scratch of this device");
+    HCK(hipSetDevice(c->device), "mrf_accuracy_static: hipSetDevice");
+    HCK(launch_accuracy(c, logit, vis_min, ray_code, surface_depth, counts, work, s), "mrf_accuracy_static");
     return MRF_OK;
 }
 

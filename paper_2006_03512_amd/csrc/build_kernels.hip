@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "dev_common.hpp"
 #include "mrf_internal.hpp"
@@ -1578,9 +1579,9 @@ __global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ s
 }
 
 hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
-                           int64_t* counts, hipStream_t s)
+                           int64_t* counts, double* work, hipStream_t s)
 {
-    double* alpha = (double*)c->b_metric.p;
+    double* alpha = work;
     double* lalpha = alpha + c->V;
     for (const SceneDev& sd : c->scenes_h) {
         const int64_t n = (int64_t)sd.n[0] * sd.n[1] * sd.n[2];
@@ -1598,6 +1599,49 @@ hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_
                        (const FrameDev*)c->b_frames.p, c->bp, (const double*)alpha, (const double*)lalpha,
                        std::log(vis_min), code, surf, (unsigned long long*)counts);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ static scratch
+//
+// The accuracy metric's per-voxel alpha and log alpha for callers that cannot
+// allocate device memory (mrf_accuracy_static): a file-scope device array of
+// kStaticMetricVoxels voxels (two doubles each, 32 MiB), one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): its device
+// address is looked up once per device, with that device current, and kept.
+static __device__ __align__(256) double scratch[2 * kStaticMetricVoxels];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {nullptr};
+hipError_t g_scratch_err[kMaxDevices] = {hipSuccess};
+bool g_scratch_done[kMaxDevices] = {false};
+}  // namespace
+
+hipError_t static_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));   // the current device's copy
+        g_scratch_ptr[device] = e == hipSuccess ? (double*)ptr : nullptr;
+        g_scratch_err[device] = e;
+        g_scratch_done[device] = true;
+        if (e != hipSuccess) hipGetLastError();
+    }
+    return g_scratch_err[device];
+}
+
+hipError_t static_scratch(int device, double** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) return hipErrorNotInitialized;
+    *out = g_scratch_ptr[device];
+    return g_scratch_err[device];
 }
 
 }  // namespace mrf

@@ -420,6 +420,12 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_
 // every measured point (c->bp.bricks, c->bp.radius).
 hipError_t launch_brick_mask(mrf_ctx* c, hipStream_t s);
 hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
-                           int64_t* counts, hipStream_t s);
+                           int64_t* counts, double* work, hipStream_t s);
+// Device-resident scratch of mrf_accuracy_static: 2 kStaticMetricVoxels doubles
+// per GPU.  static_scratch_init looks up the current device's copy (once per
+// device); static_scratch returns it (hipErrorNotInitialized before init).
+constexpr int64_t kStaticMetricVoxels = int64_t(1) << 21;
+hipError_t static_scratch_init(int device);
+hipError_t static_scratch(int device, double** out);
 
 }  // namespace mrf
