@@ -248,6 +248,38 @@ int mrf_backward_gen(mrf_ctx* ctx, uint64_t generation, const float* dloss_dlogi
 int mrf_accuracy(mrf_ctx* ctx, const float* logit, double vis_min, int8_t* ray_code,
                  double* surface_depth, int64_t* counts, void* stream);
 
+/* mrf_accuracy with the paper's evaluation options (Sec. V).  ref_depth: R
+ * floats (device, ray order as in mrf_build), the image each ray is scored
+ * against instead of its measurement, e.g. noise-free depth rendered from the
+ * same poses or a held-out image (0 or NaN: not evaluated); NULL scores
+ * against the measurements.  tol_nsigma > 0: a ray whose map does not leave
+ * it visible is accurate iff the most likely generating surface (the chosen
+ * voxel's entry, z-depth) lies within tol_nsigma sigma(Z) of the depth Z it is
+ * scored against, sigma(Z) = max(trunc_c0 + trunc_c2 Z^2, trunc_min) the
+ * build's sensor noise (the paper uses 1.5); 0 keeps the voxel-chord rule of
+ * mrf_accuracy.  The beyond-the-map rule is unchanged.  Outputs and errors as
+ * mrf_accuracy, and MRF_EINVAL for a negative tol_nsigma. */
+int mrf_accuracy_ex(mrf_ctx* ctx, const float* logit, double vis_min, const float* ref_depth,
+                    double tol_nsigma, int8_t* ray_code, double* surface_depth, int64_t* counts,
+                    void* stream);
+
+/* The ray factors' messages to their depth variables (Eq. depth_message,
+ * Sec. III-C) after the last inference: the measurement of ray r came from
+ * the depth of its i-th voxel with weight nu(d_i) mu(o_i = 1) prod_{k<i}
+ * mu(o_k = 0), mu the voxel -> ray messages of the last sweep (of
+ * mrf_infer, or the keyframe messages of mrf_infer_keyframe_avg), normalised
+ * over the ray's voxels (the all-empty configuration has potential zero).
+ *   prob: E floats in canonical edge order (as mrf_export_edges), the
+ *     probability of each voxel's depth; may be NULL.
+ *   mode_step: R int32, the step (0-based along the ray) of the most probable
+ *     depth, the first on ties, -1 for rays without voxels; may be NULL.
+ *   mean_depth: R floats, the expected z-depth sum_i prob_i d_i (chord
+ *     midpoints), NaN for rays without voxels; may be NULL.
+ * Weights are formed in base-2 logs with the visibility summed in FP64.
+ * Errors: MRF_ESTATE before an inference. */
+int mrf_depth_distribution(mrf_ctx* ctx, float* prob, int32_t* mode_step, float* mean_depth,
+                           void* stream);
+
 /* mrf_accuracy for callers that cannot allocate device memory (code under
  * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
  * same computation and outputs, bit for bit, but the 16 V bytes of per-voxel

@@ -36,6 +36,9 @@
  *       (Sec. III-D): visibility and generating-surface density along each
  *       depth ray through voxels of constant occlusion density, the
  *       measurement checked against the most likely surface.
+ *   or_depth_distribution           -- the ray factor's message to its depth
+ *       variable (Eq. depth_message, Sec. III-C): where along each ray the
+ *       measurement was generated, given the voxel -> ray messages.
  *   or_infer_f32_storage            -- the same sweeps with the messages
  *       stored at single precision: a conditioning measure, not the method.
  *   or_infer_keyframe_avg           -- the same sweeps with the paper's
@@ -792,8 +795,14 @@ static void or_metric_emit(void* p, int64_t k, int32_t id, double tin, double to
  *   lvis   log visibility at the grid exit;
  *   margin distance of the decision from a tie: the smaller of (best - second
  *          best log omega) and |lvis - log vis_min| (+inf when neither exists). */
+/* tol_nsigma > 0 selects the paper's evaluation rule (Sec. V) instead: the ray
+ * is accurate iff the most likely generating surface (the chosen voxel's
+ * entry, z-depth) lies within tol_nsigma sigma(Z) of Z, sigma(Z) =
+ * max(trunc_c0 + trunc_c2 Z^2, trunc_min) the sensor's noise; the beyond rule
+ * is unchanged.  `depth` is the image the rays are scored against (the
+ * measurement, or a reference such as noise-free depth from the same poses). */
 void or_accuracy(const or_cfg* g, int32_t n_frames, const float* depth, const double* T_wc,
-                 const double* L, double vis_min, int8_t* code, double* tin, double* tout,
+                 const double* L, double vis_min, double tol_nsigma, int8_t* code, double* tin, double* tout,
                  double* lvis, double* margin)
 {
     const int64_t HW = (int64_t)g->width * g->height;
@@ -830,11 +839,54 @@ void or_accuracy(const or_cfg* g, int32_t n_frames, const float* depth, const do
             code[r] = ray.Z > texit ? 1 : 0;
             tin[r] = texit;
             tout[r] = INFINITY;
+        } else if (tol_nsigma > 0.0) {
+            double sig = g->trunc_c2 * ray.Z;
+            sig = sig * ray.Z;
+            sig = g->trunc_c0 + sig;
+            if (sig < g->trunc_min) sig = g->trunc_min;
+            code[r] = fabs(m.btin - ray.Z) <= tol_nsigma * sig ? 1 : 0;
+            tin[r] = m.btin;
+            tout[r] = m.btout;
         } else {
             code[r] = (m.btin <= ray.Z && ray.Z < m.btout) ? 1 : 0;
             tin[r] = m.btin;
             tout[r] = m.btout;
         }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* ray depth potential -> depth variable (Eq. depth_message)           */
+/* ------------------------------------------------------------------ */
+
+/* The message of each ray factor to its depth variable (Sec. III-C): the
+ * measurement was generated at voxel i's depth with weight
+ *   nu(d_i) mu(o_i = 1) prod_{k<i} mu(o_k = 0),
+ * the incoming messages being the voxel -> ray messages lam (log-odds) of a
+ * sweep.  Normalised over the ray's voxels (the all-empty configuration has
+ * potential zero), per edge q = the probability of the depth d_i; per ray
+ * mode = the step of the most probable depth (the first on ties), -1 for a
+ * ray without voxels. */
+void or_depth_distribution(const int64_t* row_ptr, int64_t R, const double* lam, const double* g,
+                           double* q, int32_t* mode)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t s = row_ptr[r], n = row_ptr[r + 1] - s;
+        mode[r] = -1;
+        if (n == 0) continue;
+        double P = 0.0, best = -INFINITY, tot = -INFINITY;
+        for (int64_t i = 0; i < n; ++i) {
+            double w = -or_softplus(-lam[s + i]) + g[s + i] + P;   /* log of the weight of depth d_i */
+            q[s + i] = w;
+            tot = or_lse(tot, w);
+            if (w > best) {
+                best = w;
+                mode[r] = (int32_t)i;
+            }
+            P += -or_softplus(lam[s + i]);
+        }
+        for (int64_t i = 0; i < n; ++i) q[s + i] = exp(q[s + i] - tot);
     }
 }
 

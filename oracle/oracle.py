@@ -61,7 +61,8 @@ def lib():
         _lib.or_infer_f32_storage.argtypes = [P, I64, P, P, I64, I64, P, P, I32, I32, P, P, P]
         _lib.or_infer_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P, P]
         _lib.or_infer_keyframe_avg.restype = C.c_int
-        _lib.or_accuracy.argtypes = [P, I32, P, P, P, C.c_double, P, P, P, P, P]
+        _lib.or_accuracy.argtypes = [P, I32, P, P, P, C.c_double, C.c_double, P, P, P, P, P]
+        _lib.or_depth_distribution.argtypes = [P, I64, P, P, P, P]
         _lib.or_single_ray_adjoint.argtypes = [I64, P, P, P, P, P]
         _lib.or_num_threads.restype = C.c_int
         _lib.or_set_threads.argtypes = [C.c_int]
@@ -312,24 +313,41 @@ def single_ray_adjoint(lam, g, ellbar):
     return lb, gb
 
 
-def accuracy(scene, L, vis_min: float = 0.5) -> dict:
+def accuracy(scene, L, vis_min: float = 0.5, ref_depth=None, tol_nsigma: float = 0.0) -> dict:
     """Sec. III-D accuracy of every depth ray of one scene against the map L
     (log-odds of the scene's V voxels): per ray code (1 accurate, 0 not, -1
     not evaluated), the chosen voxel's chord t_in/t_out (z-depth; (exit, inf)
     when the surface is taken to lie beyond the map), log visibility at the
-    grid exit and the decision's margin from a tie."""
+    grid exit and the decision's margin from a tie.  ref_depth (F, H, W):
+    score against this image instead of the measurement (e.g. noise-free
+    depth); tol_nsigma > 0: the Sec. V rule (surface within tol_nsigma sigma(Z)
+    of Z) instead of the voxel-chord rule."""
     cfg = _cfg(scene)
-    depth = np.ascontiguousarray(scene.depth, np.float32)
+    depth = np.ascontiguousarray(scene.depth if ref_depth is None else ref_depth, np.float32)
+    assert depth.shape == scene.depth.shape
     T = np.ascontiguousarray(scene.T_wc, np.float64)
     Lm = np.ascontiguousarray(L, np.float64)
     assert Lm.shape == (scene.grid.n_voxels,)
     R = depth.size
     out = {"code": np.empty(R, np.int8), "t_in": np.empty(R), "t_out": np.empty(R),
            "lvis": np.empty(R), "margin": np.empty(R)}
-    lib().or_accuracy(C.byref(cfg), scene.n_frames, _p(depth), _p(T), _p(Lm), float(vis_min),
+    lib().or_accuracy(C.byref(cfg), scene.n_frames, _p(depth), _p(T), _p(Lm), float(vis_min), float(tol_nsigma),
                       _p(out["code"]), _p(out["t_in"]), _p(out["t_out"]), _p(out["lvis"]),
                       _p(out["margin"]))
     return out
+
+
+def depth_distribution(graph: Graph, lam, g):
+    """The ray factors' messages to their depth variables (Eq. depth_message)
+    from voxel -> ray messages lam: per edge the probability that the
+    measurement came from that voxel's depth, per ray the step of the most
+    probable depth (-1 without voxels)."""
+    lam = np.ascontiguousarray(lam, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    q = np.empty(graph.n_edges)
+    mode = np.empty(graph.n_rays, np.int32)
+    lib().or_depth_distribution(_p(graph.row_ptr), graph.n_rays, _p(lam), _p(g), _p(q), _p(mode))
+    return q, mode
 
 
 def bce_logit_grad(L, y) -> np.ndarray:

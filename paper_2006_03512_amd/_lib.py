@@ -19,7 +19,8 @@ SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backwar
            "mrf_export_incidence", "mrf_export_edges", "mrf_set_schedule", "mrf_destroy",
            "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps", "mrf_get_tuning", "mrf_set_tuning",
            "mrf_autotune", "mrf_infer_sensor", "mrf_backward_sensor", "mrf_accuracy", "mrf_generation",
-           "mrf_backward_gen", "mrf_infer_keyframe_avg", "mrf_accuracy_static"]
+           "mrf_backward_gen", "mrf_infer_keyframe_avg", "mrf_accuracy_static",
+           "mrf_accuracy_ex", "mrf_depth_distribution"]
 MAX_RAY_CLASSES = 32
 
 
@@ -92,6 +93,8 @@ def lib() -> C.CDLL:
         L.mrf_backward_sensor.argtypes = [P, P, P, P, P, P]
         L.mrf_accuracy.argtypes = [P, P, C.c_double, P, P, P, P]
         L.mrf_accuracy_static.argtypes = [P, P, C.c_double, P, P, P, P]
+        L.mrf_accuracy_ex.argtypes = [P, P, C.c_double, P, C.c_double, P, P, P, P]
+        L.mrf_depth_distribution.argtypes = [P, P, P, P, P]
         L.mrf_generation.argtypes = [P, C.POINTER(C.c_uint64)]
         L.mrf_backward_gen.argtypes = [P, C.c_uint64, P, P, P, P, P]
         L.mrf_stats.argtypes = [P, C.POINTER(Stats)]

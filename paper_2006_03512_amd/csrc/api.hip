@@ -676,8 +676,44 @@ int mrf_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* ray_cod
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_accuracy: hipSetDevice");
     HCK(ensure(c->b_metric, 2 * sizeof(double) * (size_t)c->V), "mrf_accuracy: alloc");
-    HCK(launch_accuracy(c, logit, vis_min, ray_code, surface_depth, counts, (double*)c->b_metric.p, s),
+    HCK(launch_accuracy(c, logit, vis_min, nullptr, 0.0, ray_code, surface_depth, counts, (double*)c->b_metric.p, s),
         "mrf_accuracy");
+    return MRF_OK;
+}
+
+int mrf_accuracy_ex(mrf_ctx* c, const float* logit, double vis_min, const float* ref_depth, double tol_nsigma,
+                    int8_t* ray_code, double* surface_depth, int64_t* counts, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_accuracy_ex: null context");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_accuracy_ex: call mrf_build first");
+    if (!(vis_min > 0.0 && vis_min <= 1.0)) return fail(MRF_EINVAL, "mrf_accuracy_ex: vis_min must lie in (0, 1]");
+    if (!(tol_nsigma >= 0.0)) return fail(MRF_EINVAL, "mrf_accuracy_ex: tol_nsigma must be >= 0");
+    if (!logit) {
+        if (!c->inferred) return fail(MRF_ESTATE, "mrf_accuracy_ex: no map given and no mrf_infer yet");
+        logit = (const float*)c->b_L.p;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_accuracy_ex: hipSetDevice");
+    HCK(ensure(c->b_metric, 2 * sizeof(double) * (size_t)c->V), "mrf_accuracy_ex: alloc");
+    HCK(launch_accuracy(c, logit, vis_min, ref_depth, tol_nsigma, ray_code, surface_depth, counts,
+                        (double*)c->b_metric.p, s),
+        "mrf_accuracy_ex");
+    return MRF_OK;
+}
+
+int mrf_depth_distribution(mrf_ctx* c, float* prob, int32_t* mode_step, float* mean_depth, void* stream)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_depth_distribution: null context");
+    if (!c->inferred) return fail(MRF_ESTATE, "mrf_depth_distribution: call mrf_infer first");
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_depth_distribution: hipSetDevice");
+    float* q = prob ? (float*)c->b_ellbar.p : nullptr;   // slot order, then canonical edge order
+    const KfSrc kfs{(const float*)c->b_kfx.p, (const int64_t*)c->b_kfxb.p};
+    ExclSrc lam = final_lam(c);
+    if (c->kf_inferred) lam = ExclSrc{(const float2*)c->b_theta2.p, nullptr};   // one sweep: the prior
+    HCK(launch_depth_distribution(c, lam, c->kf_inferred && c->K > 1 ? &kfs : nullptr, q, mode_step, mean_depth, s),
+        "mrf_depth_distribution");
+    if (prob) HCK(export_canonical_edges(c, q, prob, 4, s), "mrf_depth_distribution: export");
     return MRF_OK;
 }
 
@@ -700,7 +736,8 @@ int mrf_accuracy_static(mrf_ctx* c, const float* logit, double vis_min, int8_t* 
     double* work = nullptr;
     HCK(static_scratch(c->device, &work), "mrf_accuracy_static: static scratch of this device");
     HCK(hipSetDevice(c->device), "mrf_accuracy_static: hipSetDevice");
-    HCK(launch_accuracy(c, logit, vis_min, ray_code, surface_depth, counts, work, s), "mrf_accuracy_static");
+    HCK(launch_accuracy(c, logit, vis_min, nullptr, 0.0, ray_code, surface_depth, counts, work, s),
+        "mrf_accuracy_static");
     return MRF_OK;
 }
 

@@ -1523,7 +1523,11 @@ struct MetricEmit {
 // box and walked to the grid exit.  Exit visibility of at least vis_min (log:
 // lvmin) means the map leaves the ray visible, and the ray is accurate iff its
 // measurement lies beyond the exit; otherwise iff the measurement lies inside
-// the chord [t_in, t_out) of the voxel of the most likely surface.  code: 1
+// the chord [t_in, t_out) of the voxel of the most likely surface, or, with
+// tol > 0 (the paper's evaluation rule), iff that surface (the voxel's entry)
+// lies within tol sigma(Z) of Z, sigma(Z) = max(c0 + c2 Z^2, smin).  The
+// measurement is the built frame's, or ref[global ray] when ref is given
+// (e.g. noise-free depth from the same poses).  code: 1
 // accurate, 0 not, -1 not evaluated; surf: z-depth of the chosen voxel's
 // entry, +inf when the surface is taken to lie beyond the map, NaN when not
 // evaluated.  Per-scene counts (evaluated, accurate) by block counts and one
@@ -1532,6 +1536,7 @@ __global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ s
                                                   const FrameDev* __restrict__ frames, BuildDev bp,
                                                   const double* __restrict__ alpha,
                                                   const double* __restrict__ lalpha, double lvmin,
+                                                  const float* __restrict__ ref, double tol,
                                                   int8_t* __restrict__ code, double* __restrict__ surf,
                                                   unsigned long long* __restrict__ counts)
 {
@@ -1545,7 +1550,8 @@ __global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ s
         double ts, texit;
         int8_t cd = -1;
         double sf = __builtin_nan("");
-        if (clip_ray(sd, bp, fr.T, fr.depth[pix], v, u, r, ts, texit) && ts < texit) {
+        const float zm = ref ? ref[fr.ray_base + pix] : fr.depth[pix];
+        if (clip_ray(sd, bp, fr.T, zm, v, u, r, ts, texit) && ts < texit) {
             r.ts = ts;
             r.te = texit;
             MetricEmit m;
@@ -1559,6 +1565,13 @@ __global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ s
             if (-m.acc >= lvmin) {
                 cd = r.Z > texit ? 1 : 0;
                 sf = __builtin_huge_val();
+            } else if (tol > 0.0) {
+                double sig = bp.c2 * r.Z;
+                sig = sig * r.Z;
+                sig = bp.c0 + sig;
+                if (sig < bp.smin) sig = bp.smin;
+                cd = fabs(m.btin - r.Z) <= tol * sig ? 1 : 0;
+                sf = m.btin;
             } else {
                 cd = (m.btin <= r.Z && r.Z < m.btout) ? 1 : 0;
                 sf = m.btin;
@@ -1578,8 +1591,8 @@ __global__ __launch_bounds__(256) void accuracy_k(const SceneDev* __restrict__ s
     }
 }
 
-hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
-                           int64_t* counts, double* work, hipStream_t s)
+hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, const float* ref, double tol,
+                           int8_t* code, double* surf, int64_t* counts, double* work, hipStream_t s)
 {
     double* alpha = work;
     double* lalpha = alpha + c->V;
@@ -1597,7 +1610,7 @@ hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_
     dim3 grid((c->max_hw + 255) / 256, c->n_frames);
     hipLaunchKernelGGL(accuracy_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
                        (const FrameDev*)c->b_frames.p, c->bp, (const double*)alpha, (const double*)lalpha,
-                       std::log(vis_min), code, surf, (unsigned long long*)counts);
+                       std::log(vis_min), ref, tol, code, surf, (unsigned long long*)counts);
     return hipGetLastError();
 }
 

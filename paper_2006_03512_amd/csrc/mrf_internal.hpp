@@ -419,8 +419,13 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_
 // Sparse grid (Sec. IV-B): zero the allocation mask and mark the bricks around
 // every measured point (c->bp.bricks, c->bp.radius).
 hipError_t launch_brick_mask(mrf_ctx* c, hipStream_t s);
-hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, int8_t* code, double* surf,
-                           int64_t* counts, double* work, hipStream_t s);
+hipError_t launch_accuracy(mrf_ctx* c, const float* logit, double vis_min, const float* ref, double tol,
+                           int8_t* code, double* surf, int64_t* counts, double* work, hipStream_t s);
+// the ray factors' messages to their depth variables (Eq. depth_message) from
+// the last inference's voxel -> ray messages: per slot the probability of the
+// voxel's depth (q, slot order), per ray the most probable step and the mean depth
+hipError_t launch_depth_distribution(const mrf_ctx* c, ExclSrc lam, const KfSrc* kf, float* q, int32_t* mode,
+                                     float* mean, hipStream_t s);
 // Device-resident scratch of mrf_accuracy_static: 2 kStaticMetricVoxels doubles
 // per GPU.  static_scratch_init looks up the current device's copy (once per
 // device); static_scratch returns it (hipErrorNotInitialized before init).

@@ -803,3 +803,89 @@ hipError_t launch_excl_kf(const mrf_ctx* c, KfSrc x, float* out, hipStream_t s)
 }
 
 }  // namespace mrf
+
+namespace mrf {
+
+// ------------------------------------------------------------ depth messages
+//
+// The ray factor's message to its depth variable (Eq. depth_message, Sec.
+// III-C): the measurement came from voxel i's depth with weight
+// nu(d_i) mu_i(1) prod_{k<i} mu_k(0), mu the voxel -> ray messages of the last
+// sweep, normalised over the ray (the all-empty configuration has potential
+// zero).  One thread per ray walks its steps twice: the log2 weights W_i =
+// log2 mu_i(1) + log2 nu_i + P_i, with the visibility P_i summed in FP64, give
+// the running maximum (the mode, first on ties) and the normaliser; then
+// q_i = 2^(W_i - max) / sum and the mean depth sum_i q_i d_i, d_i = Z - delta_i.
+__global__ __launch_bounds__(256) void depth_dist_k(const TileDev* __restrict__ tiles, int64_t T,
+                                                    const FrameDev* __restrict__ frames,
+                                                    const int32_t* __restrict__ counts,
+                                                    const int32_t* __restrict__ col, ExclDev lam, KfSrc kf,
+                                                    int is_kf, const float* __restrict__ g,
+                                                    const float* __restrict__ delta, float* __restrict__ q,
+                                                    int32_t* __restrict__ mode, float* __restrict__ mean)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ti = t / kTile;
+    if (ti >= T) return;
+    const int i = (int)(t % kTile);
+    const TileDev td = tiles[ti];
+    const int ux = i & (kTileW - 1), vy = i / kTileW;
+    if (ux >= td.nu || vy >= td.nv) return;
+    const int64_t r = td.ray0 + (int64_t)vy * td.W + ux;
+    const int m = counts[r];
+    if (m == 0) {
+        if (mode) mode[r] = -1;
+        if (mean) mean[r] = __builtin_nanf("");
+        return;
+    }
+    const int64_t s0 = td.base + i;
+    const float* xf = is_kf ? kf.x + kf.xb[td.frame] : nullptr;
+    auto weight = [&](int k, double& P) {   // W_k (log2), then P += log2 mu_k(0)
+        const int64_t at = s0 + (int64_t)kTile * k;
+        const int32_t v = col[at];
+        const float lm = is_kf ? xf[v] : excl_value(v, lam.tot[v], lam.own[at], lam.has_own);
+        float al, be, gg;
+        load_step(lm, g[at], true, al, be, gg);
+        const double W = ((double)be + (double)gg) + P;
+        P += (double)al;
+        return W;
+    };
+    double P = 0.0, M = -__builtin_huge_val(), S = 0.0;
+    int best = 0;
+    for (int k = 0; k < m; ++k) {
+        const double W = weight(k, P);
+        if (W > M) {
+            S = S * (double)ex2((float)(M - W)) + 1.0;
+            M = W;
+            best = k;
+        } else {
+            S += (double)ex2((float)(W - M));
+        }
+    }
+    if (mode) mode[r] = best;
+    const FrameDev fr = frames[td.frame];
+    const double Z = (double)fr.depth[r - fr.ray_base];
+    double mq = 0.0;
+    P = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double W = weight(k, P);
+        const double qk = (double)ex2((float)(W - M)) / S;
+        if (q) q[s0 + (int64_t)kTile * k] = (float)qk;
+        mq += qk * (Z - (double)delta[s0 + (int64_t)kTile * k]);
+    }
+    if (mean) mean[r] = (float)mq;
+}
+
+hipError_t launch_depth_distribution(const mrf_ctx* c, ExclSrc lam, const KfSrc* kf, float* q, int32_t* mode,
+                                     float* mean, hipStream_t s)
+{
+    if (c->T <= 0) return hipSuccess;
+    const int64_t n = c->T * kTile;
+    hipLaunchKernelGGL(depth_dist_k, dim3(nblk(n, 256)), dim3(256), 0, s, (const TileDev*)c->b_tiles.p, c->T,
+                       (const FrameDev*)c->b_frames.p, (const int32_t*)c->b_counts.p, (const int32_t*)c->b_col.p,
+                       excl_dev(c, lam), kf ? *kf : KfSrc{nullptr, nullptr}, kf ? 1 : 0, (const float*)c->b_g.p,
+                       (const float*)c->b_delta.p, q, mode, mean);
+    return hipGetLastError();
+}
+
+}  // namespace mrf

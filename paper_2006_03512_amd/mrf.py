@@ -206,13 +206,28 @@ class RayMRF:
                                           stream_handle(stream)), "mrf_backward_sensor")
         return dp, ds, db
 
-    def accuracy(self, logit=None, vis_min: float = 0.5, stream=None) -> dict:
+    def depth_distribution(self, stream=None) -> dict:
+        """The ray factors' messages to their depth variables after the last
+        inference (Eq. depth_message): ``prob`` per edge (canonical order),
+        ``mode_step`` and ``mean_depth`` per ray."""
+        prob = torch.empty(self.n_edges, dtype=torch.float32, device=self.device)
+        mode = torch.empty(self.n_rays, dtype=torch.int32, device=self.device)
+        mean = torch.empty(self.n_rays, dtype=torch.float32, device=self.device)
+        check(self._L.mrf_depth_distribution(self._h, ptr(prob), ptr(mode), ptr(mean), stream_handle(stream)),
+              "mrf_depth_distribution")
+        return {"prob": prob, "mode_step": mode, "mean_depth": mean}
+
+    def accuracy(self, logit=None, vis_min: float = 0.5, stream=None, ref_depth=None,
+                 tol_nsigma: float = 0.0) -> dict:
         """Accuracy metric of a map (Sec. III-D) over every pixel of the built
         scenes: per-ray ``code`` (int8: 1 accurate, 0 not, -1 not evaluated),
         ``surface_depth`` (float64 z-depth of the most likely generating
         surface, inf beyond the map), per-scene ``counts`` (evaluated, accurate)
         and ``accuracy`` (accurate / evaluated per scene).  logit: the map's V
-        log-odds; None uses the last inference's marginals."""
+        log-odds; None uses the last inference's marginals.  ref_depth (R
+        float32 on the device): score against this image (e.g. noise-free
+        depth); tol_nsigma > 0: the paper's rule (surface within tol_nsigma
+        sigma(Z) of Z) instead of the voxel-chord rule."""
         if not getattr(self, "_frames_built", False):
             raise RuntimeError("accuracy() needs a build of the uploaded frames")
         if logit is not None:
@@ -220,8 +235,15 @@ class RayMRF:
         code = torch.empty(self.n_rays, dtype=torch.int8, device=self.device)
         surf = torch.empty(self.n_rays, dtype=torch.float64, device=self.device)
         counts = torch.empty((len(self._arr), 2), dtype=torch.int64, device=self.device)
-        check(self._L.mrf_accuracy(self._h, ptr(logit), float(vis_min), ptr(code), ptr(surf), ptr(counts),
-                                   stream_handle(stream)), "mrf_accuracy")
+        if ref_depth is None and tol_nsigma == 0.0:
+            check(self._L.mrf_accuracy(self._h, ptr(logit), float(vis_min), ptr(code), ptr(surf), ptr(counts),
+                                       stream_handle(stream)), "mrf_accuracy")
+        else:   # the paper's evaluation options: a reference image, the tol_nsigma * sigma(Z) rule
+            if ref_depth is not None:
+                self._vec(ref_depth, self.n_rays, "ref_depth")
+            check(self._L.mrf_accuracy_ex(self._h, ptr(logit), float(vis_min), ptr(ref_depth), float(tol_nsigma),
+                                          ptr(code), ptr(surf), ptr(counts), stream_handle(stream)),
+                  "mrf_accuracy_ex")
         c = counts.cpu()
         acc = [float(a) / float(n) if n > 0 else float("nan") for n, a in c.tolist()]
         return {"code": code, "surface_depth": surf, "counts": counts, "accuracy": acc}

@@ -209,6 +209,14 @@ def bias_table(sigma: np.ndarray, seed: int) -> np.ndarray:
 # noise
 # --------------------------------------------------------------------------
 
+def _clean(t_true, z_min, z_max):
+    """Noise-free z-depth of the rendered surfaces (0 where nothing is hit or
+    outside the sensor's window): the reference the paper scores maps against."""
+    hit = np.isfinite(t_true) & (t_true > 0)
+    z = np.where(hit, t_true, 0.0)
+    return np.where(hit & (z >= z_min) & (z <= z_max), z, 0.0).astype(np.float32)
+
+
 def _noisy(rng, t_true, sigma_fn, z_min, z_max, outlier_frac):
     z = np.where(np.isfinite(t_true), t_true, 0.0)
     hit = np.isfinite(t_true) & (t_true > 0)
@@ -278,6 +286,7 @@ def _room_solids(L, rng, n_boxes, path=None, clearance=0.4, thick=0.1,
 def _render_room(rng, intr, poses, solids, faces, sigma_fn, z_min, z_max, outlier_frac):
     bumps = [(_bump_field(rng) if fc is not None else None) for fc in faces]
     depth = np.zeros((len(poses), intr.height, intr.width), np.float32)
+    clean = np.zeros_like(depth)
     for f, T in enumerate(poses):
         c, w = pixel_rays(intr, T)
         t, idx = ray_box_hits(c, w, solids)
@@ -296,8 +305,9 @@ def _render_room(rng, intr, poses, solids, faces, sigma_fn, z_min, z_max, outlie
             with np.errstate(divide="ignore", invalid="ignore"):
                 dt = np.where(nw < -1e-3, b / nw, 0.0)
             t[m] = t[m] + np.clip(dt, -0.05, 0.05)
+        clean[f] = _clean(t, z_min, z_max)
         depth[f] = _noisy(rng, t, sigma_fn, z_min, z_max, outlier_frac)
-    return depth
+    return depth, clean
 
 
 def _room_sigma(d):
@@ -356,7 +366,7 @@ def make_c1(seed: int = 1000) -> Scene:
                     trunc_min=1e-3, table_dmax=3.2, min_ray_voxels=2)
     depth = _noisy(rng, t, lambda d: 0.0025 * d * d, p.z_min, p.z_max, 0.0)[None]
     return Scene("c1", depth, T[None].copy(), intr, grid, solids, p,
-                 sigma_table("quad_c1", p.table_dmax), 0.1, 5)
+                 sigma_table("quad_c1", p.table_dmax), 0.1, 5, {"clean_depth": _clean(t, p.z_min, p.z_max)[None]})
 
 
 def make_c2(seed: int = 2000) -> Scene:
@@ -369,9 +379,9 @@ def make_c2(seed: int = 2000) -> Scene:
     pitch = math.radians(10.0)
     T = look_at(cam, cam + np.array([0.0, math.cos(pitch), -math.sin(pitch)]))
     p = _room_params()
-    depth = _render_room(rng, ROOM_INTR, [T], solids, faces, _room_sigma, p.z_min, p.z_max, 0.01)
+    depth, clean = _render_room(rng, ROOM_INTR, [T], solids, faces, _room_sigma, p.z_min, p.z_max, 0.01)
     return Scene("c2", depth, T[None].copy(), ROOM_INTR, grid, solids, p,
-                 sigma_table("room", p.table_dmax), 0.1, 10)
+                 sigma_table("room", p.table_dmax), 0.1, 10, {"clean_depth": clean})
 
 
 def make_room_batch(name, seed, grid: Grid, n_frames, sweeps, n_boxes=20,
@@ -385,9 +395,9 @@ def make_room_batch(name, seed, grid: Grid, n_frames, sweeps, n_boxes=20,
     solids, faces = _room_solids(L, rng, n_boxes, path=centres, clearance=0.4,
                                  box_h=(0.1, min(1.5, 0.5 * L[2])))
     p = _room_params()
-    depth = _render_room(rng, intr, poses, solids, faces, _room_sigma, p.z_min, p.z_max, 0.01)
+    depth, clean = _render_room(rng, intr, poses, solids, faces, _room_sigma, p.z_min, p.z_max, 0.01)
     return Scene(name, depth, np.array(poses), intr, grid, solids, p,
-                 sigma_table("room", p.table_dmax), 0.1, sweeps)
+                 sigma_table("room", p.table_dmax), 0.1, sweeps, {"clean_depth": clean})
 
 
 def make_c3(seed: int = 3000, n_frames: int = 30) -> Scene:
@@ -422,12 +432,14 @@ def make_fd(seed: int = 4000) -> Scene:
     p = BuildParams(z_min=0.1, z_max=3.0, trunc_nsigma=3.0, trunc_c0=0.0, trunc_c2=0.0025,
                     trunc_min=1e-3, table_dmax=3.2, min_ray_voxels=2)
     depth = np.zeros((3, intr.height, intr.width), np.float32)
+    clean = np.zeros_like(depth)
     for f, T in enumerate(poses):
         c, w = pixel_rays(intr, T)
         t, _ = ray_box_hits(c, w, solids)
+        clean[f] = _clean(t, p.z_min, p.z_max)
         depth[f] = _noisy(rng, t, lambda d: np.maximum(0.0025 * d * d, 2e-3), p.z_min, p.z_max, 0.0)
     return Scene("fd", depth, np.array(poses), intr, grid, solids, p,
-                 sigma_table("quad_c1", p.table_dmax), 0.1, 8)
+                 sigma_table("quad_c1", p.table_dmax), 0.1, 8, {"clean_depth": clean})
 
 
 C5_LAYOUT = [  # (grid, voxel size, frames)

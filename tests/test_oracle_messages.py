@@ -291,3 +291,66 @@ def test_f32_storage_on_a_tree_stays_near_exact(oracle):
         res = oracle.infer_f32_storage(G, theta, None, 8, mode=mode, g=np.concatenate(gl))
         err = np.abs(res.p - ref)
         assert err.max() <= 1e-6 and err.max() > 0.0
+
+
+def _depth_bruteforce(lam, g):
+    """P(D = d_i) from the ray potential and the incoming messages by summing
+    over all 2^N occupancy states: psi(o, d_i) = nu(d_i) iff o_i = 1 and every
+    voxel before i is empty (the depth potential), times prod_j mu_j(o_j)."""
+    n = len(lam)
+    mu1 = 1.0 / (1.0 + np.exp(-np.asarray(lam)))
+    w = np.zeros(n)
+    for o in itertools.product((0, 1), repeat=n):
+        o = np.array(o)
+        pm = np.prod(np.where(o == 1, mu1, 1.0 - mu1))
+        occ = np.flatnonzero(o)
+        if occ.size:
+            i = occ[0]
+            w[i] += math.exp(g[i]) * pm
+    return w / w.sum()
+
+
+@pytest.mark.parametrize("n", [1, 3, 7, 12])
+def test_depth_message_matches_bruteforce(oracle, n):
+    rng = np.random.default_rng(40 + n)
+    lam = rng.uniform(-6, 6, n)
+    g = rng.uniform(-20, 0, n)
+    G = oracle.graph_from_rays([list(range(n))], n)
+    q, mode = oracle.depth_distribution(G, lam, g)
+    ref = _depth_bruteforce(lam, g)
+    np.testing.assert_allclose(q, ref, rtol=1e-10, atol=1e-15)
+    assert mode[0] == int(np.argmax(ref))
+
+
+def test_depth_message_single_ray_with_priors(oracle):
+    """One ray with Bernoulli(gamma) priors: after any number of sweeps its
+    incoming messages are the prior, and the depth distribution is the
+    posterior of the first occupied voxel, gamma nu_i (1 - gamma)^(i-1) / Z_n."""
+    rng = np.random.default_rng(41)
+    n, gamma = 30, 0.1
+    g = rng.uniform(-8, 1, n)
+    terms = gamma * np.exp(g) * (1 - gamma) ** np.arange(n)
+    G = oracle.graph_from_rays([list(range(n))], n)
+    theta = np.full(n, math.log(gamma / (1 - gamma)))
+    res = oracle.infer(G, theta, None, 3, g=g.copy())
+    q, mode = oracle.depth_distribution(G, res.lam, res.g)
+    np.testing.assert_allclose(q, terms / terms.sum(), rtol=1e-12, atol=0)
+    assert mode[0] == int(np.argmax(terms))
+
+
+def test_depth_message_of_several_rays(oracle):
+    """Rays are independent: each ray's distribution sums to one; empty rays
+    report mode -1."""
+    rays = [[0, 1, 2], [], [3, 1], [4]]
+    G = oracle.graph_from_rays(rays, 5)
+    rng = np.random.default_rng(42)
+    lam = rng.uniform(-3, 3, G.n_edges)
+    g = rng.uniform(-5, 0, G.n_edges)
+    q, mode = oracle.depth_distribution(G, lam, g)
+    for r, ray in enumerate(rays):
+        a, b = G.row_ptr[r], G.row_ptr[r + 1]
+        if ray:
+            np.testing.assert_allclose(q[a:b].sum(), 1.0, rtol=1e-14)
+            np.testing.assert_allclose(q[a:b], _depth_bruteforce(lam[a:b], g[a:b]), rtol=1e-10)
+        else:
+            assert mode[r] == -1

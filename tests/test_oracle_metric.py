@@ -167,3 +167,49 @@ def test_dense_sampling_of_the_continuous_model(oracle, seed):
             assert a["code"][r] == (vox(c + Zs[r] * w) == chosen), r
         checked += 1
     assert checked >= 30, checked
+
+
+def _column_scene_c2(Z, c0, c2, n=16, h=0.1):
+    sc = _column_scene(Z, n, h)
+    import dataclasses
+    sc.params = dataclasses.replace(sc.params, trunc_c0=c0, trunc_c2=c2)
+    return sc
+
+
+def test_tolerance_rule_on_the_column(oracle):
+    """The Sec. V rule: the most likely surface (voxel 3's entry, z-depth 0.8,
+    as in the occluder case above) within 1.5 sigma(Z) of Z, sigma(Z) = c0 +
+    c2 Z^2.  It accepts a measurement just before the voxel (outside its
+    chord) and rejects one deep inside the chord, where the chord rule does
+    the opposite."""
+    L = np.full(16, -30.0)
+    L[3:6] = _logit(0.7)
+    L[8] = _logit(0.95)
+    cases = [(0.79, 1, 0), (0.81, 1, 1), (0.8149, 1, 1), (0.8151, 0, 1), (0.85, 0, 1), (0.7849, 0, 0)]
+    for Z, tol_want, chord_want in cases:   # sigma = 0.01: accept |0.8 - Z| <= 0.015
+        sc = _column_scene_c2(Z, 0.01, 0.0)
+        assert oracle.accuracy(sc, L, tol_nsigma=1.5)["code"][0] == tol_want, Z
+        assert oracle.accuracy(sc, L)["code"][0] == chord_want, Z
+    # depth-dependent sigma: 0.01 + 0.01 Z^2 at Z = 0.824 is 0.01679, 1.5 sigma = 0.02518 > 0.024
+    assert oracle.accuracy(_column_scene_c2(0.824, 0.01, 0.01), L, tol_nsigma=1.5)["code"][0] == 1
+    assert oracle.accuracy(_column_scene_c2(0.824, 0.01, 0.0), L, tol_nsigma=1.5)["code"][0] == 0
+    # the map leaves the ray visible: the beyond-the-map rule is unchanged
+    Lv = np.full(16, -30.0)
+    for Z, want in ((2.05, 0), (2.5, 1)):
+        assert oracle.accuracy(_column_scene_c2(Z, 0.01, 0.0), Lv, tol_nsigma=1.5)["code"][0] == want
+
+
+def test_scoring_against_a_reference_image(oracle):
+    """With a reference image the rays are scored against it: the same result
+    as a scene whose measurement is the reference."""
+    L = np.full(16, -30.0)
+    L[3:6] = _logit(0.2)
+    L[8] = _logit(0.95)
+    meas = _column_scene(0.85)
+    for tol, zr, want in ((0.0, 1.35, 1), (1.5, 1.31, 1), (1.5, 1.35, 0)):
+        ref = np.full((1, 1, 1), zr, np.float32)
+        a = oracle.accuracy(meas, L, ref_depth=ref, tol_nsigma=tol)
+        b = oracle.accuracy(_column_scene(zr), L, tol_nsigma=tol)
+        assert a["code"][0] == b["code"][0] == want
+        assert a["t_in"][0] == b["t_in"][0] == pytest.approx(1.3, abs=1e-12)
+    assert oracle.accuracy(meas, L)["code"][0] == 0   # the measurement itself lies before the surface
