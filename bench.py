@@ -174,6 +174,9 @@ def main():
                     help="keep the built-in launch shapes instead of timing the candidates after warmup")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="time one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the sections outside the step and its roofline (bias table, accuracy by sweep "
+                         "count, keyframe averaging, depth messages): for counter runs")
     ap.add_argument("--keyframe-average", action="store_true",
                     help="time per-keyframe averaged messages (Sec. IV-A) as the step: build + K sweeps + "
                          "marginals, no reverse pass")
@@ -283,72 +286,80 @@ def main():
         bwd_ms = timed(lambda: m.backward(gl))
     log(f"build {build_ms:.1f} ms, forward graph {fwd_graph_ms:.1f} ms, plain {fwd_plain_ms:.1f} ms, "
         f"backward {bwd_ms}")
-    # the same sweeps with a learnt depth-bias table in the sensor model, and the
-    # reverse pass that also returns its gradient
-    from paper_2006_03512_amd import scenes as S
-    bias = torch.from_numpy(S.bias_table(sc.sigma_table, 7).astype(np.float32)).cuda()
-    fwd_bias_ms = timed(lambda: m.infer(theta, sigma, K, bias_table=bias))
-    bwd_bias_ms = None
-    if backward:
-        m.infer(theta, sigma, K, keep_checkpoints=True, bias_table=bias)
-        p, _ = m.marginals()
-        gl = (p - y) / p.numel()
-        bwd_bias_ms = timed(lambda: m.backward(gl, want_bias=True))
-    log(f"with a bias table: forward graph {fwd_bias_ms:.1f} ms, backward {bwd_bias_ms}")
-    # the accuracy metric of the inferred map over every pixel of the batch
-    m.infer(theta, sigma, K)
-    acc_ms = timed(lambda: m.accuracy())
-    acc = m.accuracy()
-    acc_counts = acc["counts"].cpu().numpy().sum(0).tolist()
-    log(f"accuracy metric: {acc_ms:.1f} ms, {acc_counts[1]} of {acc_counts[0]} rays accurate")
-    # the paper's evaluation rule (Sec. V): the most likely surface within 1.5 sigma(Z) of
-    # the noise-free depth rendered from the same poses
-    clean = torch.from_numpy(np.concatenate([x.extra["clean_depth"].reshape(-1) for x in scs])).cuda()
+    fwd_bias_ms = bwd_bias_ms = acc_ms = dd_ms = None
+    acc_counts, acc_clean, acc_by_k, clean_by_k = [0, 0], None, {}, {}
+    kf_build_ms = kf_fwd_ms = kf_plain_ms = kf_clean = None
+    kf_acc, kf_by_k, kf_clean_by_k, kf_prof = [0, 0], {}, {}, []
+    if not args.quick:
+        # the same sweeps with a learnt depth-bias table in the sensor model, and the
+        # reverse pass that also returns its gradient
+        from paper_2006_03512_amd import scenes as S
+        bias = torch.from_numpy(S.bias_table(sc.sigma_table, 7).astype(np.float32)).cuda()
+        fwd_bias_ms = timed(lambda: m.infer(theta, sigma, K, bias_table=bias))
+        bwd_bias_ms = None
+        if backward:
+            m.infer(theta, sigma, K, keep_checkpoints=True, bias_table=bias)
+            p, _ = m.marginals()
+            gl = (p - y) / p.numel()
+            bwd_bias_ms = timed(lambda: m.backward(gl, want_bias=True))
+        log(f"with a bias table: forward graph {fwd_bias_ms:.1f} ms, backward {bwd_bias_ms}")
+        # the accuracy metric of the inferred map over every pixel of the batch
+        m.infer(theta, sigma, K)
+        acc_ms = timed(lambda: m.accuracy())
+        acc = m.accuracy()
+        acc_counts = acc["counts"].cpu().numpy().sum(0).tolist()
+        log(f"accuracy metric: {acc_ms:.1f} ms, {acc_counts[1]} of {acc_counts[0]} rays accurate")
+        # the paper's evaluation rule (Sec. V): the most likely surface within 1.5 sigma(Z) of
+        # the noise-free depth rendered from the same poses
+        clean = torch.from_numpy(np.concatenate([x.extra["clean_depth"].reshape(-1) for x in scs])).cuda()
 
-    def frac_clean():
-        c = m.accuracy(ref_depth=clean, tol_nsigma=1.5)["counts"].cpu().numpy().sum(0)
-        return round(float(c[1]) / max(float(c[0]), 1.0), 6)
+        def frac_clean():
+            c = m.accuracy(ref_depth=clean, tol_nsigma=1.5)["counts"].cpu().numpy().sum(0)
+            return round(float(c[1]) / max(float(c[0]), 1.0), 6)
 
-    acc_clean = frac_clean()
-    # the same metrics after 1..9 sweeps: flooding BP can cycle, and the map's quality
-    # then depends on the phase the stated K lands in
-    acc_by_k, clean_by_k = {}, {}
-    for k in range(1, 10):
-        m.infer(theta, sigma, k)
-        c = m.accuracy()["counts"].cpu().numpy().sum(0)
-        acc_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
-        clean_by_k[str(k)] = frac_clean()
-    log(f"accurate fraction by sweeps: {acc_by_k}; 1.5 sigma of noise-free depth: {clean_by_k}")
-    # the ray factors' messages to their depth variables after K sweeps (Eq. depth_message)
-    m.infer(theta, sigma, K)
-    dd_ms = timed(lambda: m.depth_distribution())
+        acc_clean = frac_clean()
+        # the same metrics after 1..9 sweeps: flooding BP can cycle, and the map's quality
+        # then depends on the phase the stated K lands in
+        acc_by_k, clean_by_k = {}, {}
+        for k in range(1, 10):
+            m.infer(theta, sigma, k)
+            c = m.accuracy()["counts"].cpu().numpy().sum(0)
+            acc_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
+            clean_by_k[str(k)] = frac_clean()
+        log(f"accurate fraction by sweeps: {acc_by_k}; 1.5 sigma of noise-free depth: {clean_by_k}")
+        # the ray factors' messages to their depth variables after K sweeps (Eq. depth_message)
+        m.infer(theta, sigma, K)
+        dd_ms = timed(lambda: m.depth_distribution())
 
-    # per-keyframe averaged messages (Sec. IV-A) on the same batch: build, K sweeps,
-    # and the accuracy metric after 1..9 sweeps
-    kf_build_ms = timed(lambda: m.build_resident(keyframe_average=True), 1)
-    kf_pairs = m.stats().n_keyframe_pairs
-    kf_fwd_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
-    kf_plain_ms = None
-    m.set_schedule("plain")
-    kf_plain_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
-    m.set_schedule("graph")
-    m.infer_keyframe_avg(theta, sigma, K)
-    kf_acc = m.accuracy()["counts"].cpu().numpy().sum(0).tolist()
-    kf_clean = frac_clean()
-    kf_by_k, kf_clean_by_k = {}, {}
-    for k in range(1, 10):
-        m.infer_keyframe_avg(theta, sigma, k)
-        c = m.accuracy()["counts"].cpu().numpy().sum(0)
-        kf_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
-        kf_clean_by_k[str(k)] = frac_clean()
-    m.infer_keyframe_avg(theta, sigma, K)
-    kf_prof = m.profile_sweeps(args.profile_reps, include_backward=False)
-    log(f"keyframe average: build {kf_build_ms:.1f} ms ({kf_pairs} pairs), {K} sweeps {kf_fwd_ms:.1f} ms "
-        f"(plain {kf_plain_ms:.1f}), accurate fraction by sweeps {kf_by_k}")
-    if not kf_step:
-        m.build_resident()   # back to the plain graph for the profile below
+        # per-keyframe averaged messages (Sec. IV-A) on the same batch: build, K sweeps,
+        # and the accuracy metric after 1..9 sweeps
+        kf_build_ms = timed(lambda: m.build_resident(keyframe_average=True), 1)
+        kf_pairs = m.stats().n_keyframe_pairs
+        kf_fwd_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
+        kf_plain_ms = None
+        m.set_schedule("plain")
+        kf_plain_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
+        m.set_schedule("graph")
+        m.infer_keyframe_avg(theta, sigma, K)
+        kf_acc = m.accuracy()["counts"].cpu().numpy().sum(0).tolist()
+        kf_clean = frac_clean()
+        kf_by_k, kf_clean_by_k = {}, {}
+        for k in range(1, 10):
+            m.infer_keyframe_avg(theta, sigma, k)
+            c = m.accuracy()["counts"].cpu().numpy().sum(0)
+            kf_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
+            kf_clean_by_k[str(k)] = frac_clean()
+        m.infer_keyframe_avg(theta, sigma, K)
+        kf_prof = m.profile_sweeps(args.profile_reps, include_backward=False)
+        log(f"keyframe average: build {kf_build_ms:.1f} ms ({kf_pairs} pairs), {K} sweeps {kf_fwd_ms:.1f} ms "
+            f"(plain {kf_plain_ms:.1f}), accurate fraction by sweeps {kf_by_k}")
+        if not kf_step:
+            m.build_resident()   # back to the plain graph for the profile below
 
     # ---- roofline of the dominant kernel (HIP events around each launch)
+    if kf_step and kf_fwd_ms is None:   # --quick: the keyframe-average build and sweeps only
+        m.build_resident(keyframe_average=True)
+        kf_fwd_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
     if kf_step:
         m.infer_keyframe_avg(theta, sigma, K)
     else:
@@ -418,9 +429,10 @@ def main():
         "breakdown_ms": {"build": round(build_ms, 2), "forward_graph": round(fwd_graph_ms, 2),
                          "forward_plain_per_frame": round(fwd_plain_ms, 2),
                          "backward": None if bwd_ms is None else round(bwd_ms, 2),
-                         "forward_graph_with_bias": round(fwd_bias_ms, 2),
+                         "forward_graph_with_bias": None if fwd_bias_ms is None else round(fwd_bias_ms, 2),
                          "backward_with_bias_grad": None if bwd_bias_ms is None else round(bwd_bias_ms, 2),
-                         "accuracy_metric": round(acc_ms, 2), "depth_messages": round(dd_ms, 2)},
+                         "accuracy_metric": None if acc_ms is None else round(acc_ms, 2),
+                         "depth_messages": None if dd_ms is None else round(dd_ms, 2)},
         "map_accuracy": {"rule": "measurement inside the chord of the most likely surface's voxel (Sec. III-D)",
                          "evaluated_rays": acc_counts[0], "accurate_rays": acc_counts[1],
                          "fraction": acc_counts[1] / max(acc_counts[0], 1), "vis_min": 0.5,
@@ -432,7 +444,8 @@ def main():
                                   "plain_per_frame": E * K / (fwd_plain_ms / 1e3),
                                   "plain_schedule": "eager launches, one per frame and ray class, "
                                                     "untuned one-wave-per-ray shapes, no graph"},
-        "keyframe_average": {"pairs": kf_pairs, "build_ms": round(kf_build_ms, 2),
+        "keyframe_average": None if kf_fwd_ms is None else {
+                             "pairs": kf_pairs, "build_ms": round(kf_build_ms, 2),
                              "forward_graph_ms": round(kf_fwd_ms, 2),
                              "forward_plain_per_frame_ms": round(kf_plain_ms, 2),
                              "updates_per_s": E * K / (kf_fwd_ms / 1e3),

@@ -44,7 +44,7 @@ class BuildParams(C.Structure):
                 ("trunc_c0", C.c_double), ("trunc_c2", C.c_double), ("trunc_min", C.c_double),
                 ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32),
                 ("keep_chords", C.c_int32), ("sparse_bricks", C.c_int32), ("brick_radius", C.c_int32),
-                ("keyframe_average", C.c_int32)]
+                ("keyframe_average", C.c_int32), ("skip_empty_bricks", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -339,6 +339,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->bp.min_vox = p->min_ray_voxels;
     c->bp.radius = p->sparse_bricks ? p->brick_radius : 0;
     c->bp.bricks = nullptr;
+    c->bp.skip = p->sparse_bricks && p->skip_empty_bricks ? 1 : 0;
     c->n_bricks = NB;
     c->keep_chords = p->keep_chords ? 1 : 0;
     c->kf = p->keyframe_average ? 1 : 0;

@@ -88,11 +88,41 @@ __device__ __forceinline__ double face(const SceneDev& sd, int a, int idx)
     return sd.o[a] + (double)idx * sd.h;
 }
 
+// Boundary time of voxel index i along axis a in the walk's direction (the
+// face the ray leaves voxel i through), +inf when the ray is parallel to it.
+__device__ __forceinline__ double tmax_at(const SceneDev& sd, const Ray& r, int a, int i)
+{
+    if (r.w[a] > 0.0) return (face(sd, a, i + 1) - r.c[a]) / r.w[a];
+    if (r.w[a] < 0.0) return (face(sd, a, i) - r.c[a]) / r.w[a];
+    return __builtin_huge_val();
+}
+
+// The last voxel along axis a inside brick b in the walk's direction (the
+// grid's last voxel for a partial brick); cur when the ray is parallel to a.
+__device__ __forceinline__ int brick_last(const SceneDev& sd, const Ray& r, int a, int b, int cur)
+{
+    if (r.w[a] > 0.0) return min(b * kBrick + kBrick - 1, sd.n[a] - 1);
+    if (r.w[a] < 0.0) return b * kBrick;
+    return cur;
+}
+
 // Walk voxels from ts to te; emit(k, i, j, kz, tin, tout) for each chord of
 // positive length (voxel (i, j, kz)) in an allocated brick (every brick when
 // bricks is null); ties between axes step the lowest axis.  Returns count.
+//
+// Empty-space skip (Sec. IV-B: rays skip unallocated bricks), when skip is
+// set: from a voxel of an unallocated brick the walk steps brick by brick.  The ray leaves a brick
+// along an axis at the boundary time of its last voxel there (the expression
+// the voxel walk evaluates at that voxel), so stepping the axis with the
+// earliest such time (ties: lowest axis) visits the bricks in the voxel walk's
+// order.  On entering an allocated brick across axis a at time t, every other
+// axis has crossed exactly the voxel boundaries earlier than t (and one at t
+// if it is the lower axis); its index is estimated from the entry point and
+// settled by those comparisons.  The state then -- indices, boundary times,
+// entry time -- is bit for bit the one the voxel-by-voxel walk reaches, so the
+// emitted chords are unchanged.
 template <class Emit>
-__device__ int walk(const SceneDev& sd, const Ray& r, const uint8_t* bricks, Emit&& emit)
+__device__ int walk(const SceneDev& sd, const Ray& r, const uint8_t* bricks, Emit&& emit, bool skip = false)
 {
     int idx[3];
     double tmax[3];
@@ -114,12 +144,77 @@ __device__ int walk(const SceneDev& sd, const Ray& r, const uint8_t* bricks, Emi
             tmax[a] = __builtin_huge_val();
     }
     double tin = r.ts;
+    const double inv_h = 1.0 / sd.h;
     int k = 0;
     for (;;) {
+        const bool unalloc = bricks && !bricks[(idx[0] >> 3) + sd.nb[0] * ((idx[1] >> 3) + sd.nb[1] * (idx[2] >> 3))];
+        if (unalloc && skip) {
+            // walk brick by brick until an allocated brick, the ray's end or the grid's exit
+            int bi[3], last[3];
+            double tb[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                bi[a] = idx[a] >> 3;
+                last[a] = brick_last(sd, r, a, bi[a], idx[a]);
+                tb[a] = last[a] == idx[a] ? tmax[a] : tmax_at(sd, r, a, last[a]);
+            }
+            int a;
+            double tm;
+            bool stop = false;
+            for (;;) {
+                a = (tb[0] <= tb[1] && tb[0] <= tb[2]) ? 0 : (tb[1] <= tb[2] ? 1 : 2);
+                tm = tb[a];
+                if (tm >= r.te) {   // the ray ends in unallocated space
+                    stop = true;
+                    break;
+                }
+                bi[a] += r.w[a] > 0.0 ? 1 : -1;
+                if (bi[a] < 0 || bi[a] >= sd.nb[a]) {   // it leaves the grid
+                    stop = true;
+                    break;
+                }
+                if (bricks[bi[0] + sd.nb[0] * (bi[1] + sd.nb[1] * bi[2])]) break;
+                last[a] = brick_last(sd, r, a, bi[a], -1);
+                tb[a] = tmax_at(sd, r, a, last[a]);
+            }
+            if (stop) break;
+            // the voxel walk's state as it enters brick bi across axis a at time tm
+            idx[a] = r.w[a] > 0.0 ? bi[a] * kBrick : min(bi[a] * kBrick + kBrick - 1, sd.n[a] - 1);
+            tmax[a] = tmax_at(sd, r, a, idx[a]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (b == a || r.w[b] == 0.0) continue;
+                const int sg = r.w[b] > 0.0 ? 1 : -1;
+                // b has crossed every boundary earlier than tm, and one at tm if it is the lower axis
+                auto stepped = [&](double t) { return t < tm || (t == tm && b < a); };
+                const int blo = bi[b] * kBrick, bhi = min(blo + kBrick - 1, sd.n[b] - 1);
+                int first = sg > 0 ? blo : bhi;
+                if ((idx[b] >> 3) == bi[b]) first = idx[b];   // still in the brick it started in
+                const int lastb = sg > 0 ? bhi : blo;
+                const double q = floor((r.c[b] + tm * r.w[b] - sd.o[b]) * inv_h);   // estimate only
+                const int lo = min(first, lastb), hi = max(first, lastb);
+                int i = (int)fmin(fmax(q, (double)lo), (double)hi);
+                double ti = tmax_at(sd, r, b, i);
+                while (i != lastb && stepped(ti)) {
+                    i += sg;
+                    ti = tmax_at(sd, r, b, i);
+                }
+                while (i != first) {
+                    const double tp = tmax_at(sd, r, b, i - sg);
+                    if (stepped(tp)) break;
+                    i -= sg;
+                    ti = tp;
+                }
+                idx[b] = i;
+                tmax[b] = ti;   // the first boundary of b not yet crossed
+            }
+            if (tm > tin) tin = tm;
+            continue;
+        }
         const int a = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
         const double tm = tmax[a];
         const double tout = tm < r.te ? tm : r.te;
-        if (tout > tin && (!bricks || bricks[(idx[0] >> 3) + sd.nb[0] * ((idx[1] >> 3) + sd.nb[1] * (idx[2] >> 3))])) {
+        if (tout > tin && !unalloc) {
             emit(k, idx[0], idx[1], idx[2], tin, tout);
             ++k;
         }
@@ -197,7 +292,7 @@ __global__ __launch_bounds__(256) void trace_count_k(const SceneDev* __restrict_
     const int v = pix / sd.W, u = pix - v * sd.W;
     Ray r;
     int m = 0;
-    if (setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, r)) m = walk(sd, r, scene_bricks(bp, sd), NoEmit{});
+    if (setup_ray(sd, bp, fr.T, fr.depth[pix], v, u, r)) m = walk(sd, r, scene_bricks(bp, sd), NoEmit{}, bp.skip);
     counts[fr.ray_base + pix] = m >= bp.min_vox ? m : 0;
 }
 
@@ -277,7 +372,7 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
             wn = wn + ray.w[2] * ray.w[2];
             EdgeEmit em{col,  key,   delta, bin, tin, tout, wlen, &sd, slot0, (int32_t)sd.voxel_base, ray.Z,
                         bp.dmax / 64.0, sqrt(wn)};
-            walk(sd, ray, scene_bricks(bp, sd), em);
+            walk(sd, ray, scene_bricks(bp, sd), em, bp.skip);
         }
     }
     for (int k = m; k < len; ++k) {

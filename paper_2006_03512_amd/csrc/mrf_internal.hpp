@@ -213,6 +213,7 @@ struct BuildDev {
     int32_t min_vox;
     int32_t radius;            // sparse grid: bricks allocated around a measured point's brick
     const uint8_t* bricks;     // sparse grid: allocation mask (SceneDev::brick_off); null: dense
+    int32_t skip;              // sparse grid: step over unallocated bricks brick by brick
 };
 
 struct DevBuf {

@@ -112,7 +112,8 @@ class RayMRF:
         p0 = self._params
         bp = _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
                               p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0,
-                              1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0)
+                              1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0,
+                              1 if getattr(p0, "skip_empty_bricks", 0) else 0)
         with torch.cuda.device(self.device):
             check(self._L.mrf_build(self._h, self._arr, len(self._arr), C.byref(bp),
                                     stream_handle(stream)), "mrf_build")

@@ -76,6 +76,7 @@ class BuildParams:
     min_ray_voxels: int = 2
     sparse_bricks: int = 0      # 1: only 8^3 bricks around the measured points carry voxels
     brick_radius: int = 1       # bricks allocated around each measured point's brick
+    skip_empty_bricks: int = 0  # 1: the traversal steps over unallocated bricks a brick at a time
 
 
 @dataclass

@@ -62,6 +62,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(_lib.BuildParams) == 7 * 8 + 24
     assert _lib.BuildParams.brick_radius.offset == 7 * 8 + 12
     assert _lib.BuildParams.keyframe_average.offset == 7 * 8 + 16
+    assert _lib.BuildParams.skip_empty_bricks.offset == 7 * 8 + 20
     assert _lib.Stats.n_keyframe_pairs.offset == 8 * (8 + 16 + 24) + 8 + 8 + 16
     assert _lib.Stats.fwd_bytes_per_sweep.offset == 8 * (8 + 16 + 24)
     assert C.sizeof(_lib.Tuning) == 4 * (1 + 8 * _lib.MAX_RAY_CLASSES)
