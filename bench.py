@@ -46,20 +46,22 @@ WORKLOADS = {
 # (FETCH_SIZE, then WRITE_SIZE; each run also times one plain copy through
 # --calib-copy-mib, which calibrates the counter: FETCH_SIZE read 0.5 x the bytes
 # the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid only while the
-# kernel sources hash to `csrc_sha256`; otherwise traffic is reported as null.
-TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>", "csrc_sha256": "3bca698af0262b25fe9f23bec48e52f2f93cecc1c72cb67beaf3a87d6977d634",
-           "fetch_bytes": 1.252e+10, "write_bytes": 4.666e+09}
+# sources that kernel is compiled from hash to `src_sha256`; otherwise traffic
+# is reported as null.
+TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>",
+           "sources": ['adjoint_kernels.hip', 'dev_common.hpp', 'tile_lds.hpp'],
+           "src_sha256": "fb0927d45e4349b88443dc4dbc10dd33b027ec80e551940d13b9a7119a60f1ee",
+           "fetch_bytes": 1.2222e+10, "write_bytes": 4.666e+09}
 
 
-def csrc_sha256():
+def src_sha256(files):
     import hashlib
     d = os.path.join(ROOT, "paper_2006_03512_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -371,7 +373,7 @@ def main():
     fwd_bytes = st.fwd_bytes_per_sweep
     traffic = None
     if (TRAFFIC is not None and TRAFFIC["workload"] == args.workload and TRAFFIC["kernel"] == dom["name"]
-            and args.frames is None and TRAFFIC["csrc_sha256"] == csrc_sha256()):
+            and args.frames is None and TRAFFIC["src_sha256"] == src_sha256(TRAFFIC["sources"])):
         traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
     # the same kernel and the sweeps at the per-edge bytes of the hot-path scope table
     # (ray phase 12, voxel phase 12, ray adjoint 16; a forward sweep 24, forward +
