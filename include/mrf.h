@@ -113,6 +113,9 @@ typedef struct {
     int32_t brick_radius;   /* sparse grid: bricks allocated around a point's brick, 0..64 */
     int32_t keyframe_average;  /* nonzero: prepare per-keyframe averaged messages (Sec. IV-A) */
     int32_t skip_empty_bricks; /* sparse grid: nonzero steps over unallocated bricks brick by brick */
+    int32_t reserve_frames;    /* >= 0: buffers sized for this many more frames of the last scene
+                                  (mrf_add_frames), per-edge ones at 1.25 times the batch's mean
+                                  edge slots per frame */
 } mrf_build_params;
 
 typedef struct {
@@ -141,6 +144,19 @@ int mrf_create(mrf_ctx** out);
  * message buffers of 2^32 or more entries), MRF_ENOMEM, MRF_EHIP. */
 int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
               const mrf_build_params* params, void* stream);
+
+/* Add keyframes to the last scene of the built batch (Sec. V: the online use
+ * adds an image, then re-infers every keyframe): the result is the graph
+ * mrf_build makes with these frames appended to that scene, bit for bit
+ * (same ray ids, slots and voxel -> ray lists), but only the new frames are
+ * traversed and sorted; their entries are merged behind each voxel's existing
+ * ones.  depth: n_frames * H * W floats and T_wc: n_frames * 16 doubles
+ * (device), the last scene's camera model; they must stay valid as long as
+ * the scene's others (mrf_accuracy reads them).  The last inference is
+ * discarded.  Errors: MRF_ESTATE before mrf_build, MRF_EINVAL for a sparse grid
+ * (its bricks depend on every frame: rebuild) or more than 65535 frames,
+ * MRF_ERANGE, MRF_ENOMEM, MRF_EHIP. */
+int mrf_add_frames(mrf_ctx* ctx, int32_t n_frames, const float* depth, const double* T_wc, void* stream);
 
 /* Run `sweeps` flooding sweeps of loopy sum-product BP (Sec. III-B/C, IV-A)
  * from uniform ray messages.  One sweep sends every voxel->ray message

@@ -20,7 +20,7 @@ SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backwar
            "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps", "mrf_get_tuning", "mrf_set_tuning",
            "mrf_autotune", "mrf_infer_sensor", "mrf_backward_sensor", "mrf_accuracy", "mrf_generation",
            "mrf_backward_gen", "mrf_infer_keyframe_avg", "mrf_accuracy_static",
-           "mrf_accuracy_ex", "mrf_depth_distribution"]
+           "mrf_accuracy_ex", "mrf_depth_distribution", "mrf_add_frames"]
 MAX_RAY_CLASSES = 32
 
 
@@ -44,7 +44,8 @@ class BuildParams(C.Structure):
                 ("trunc_c0", C.c_double), ("trunc_c2", C.c_double), ("trunc_min", C.c_double),
                 ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32),
                 ("keep_chords", C.c_int32), ("sparse_bricks", C.c_int32), ("brick_radius", C.c_int32),
-                ("keyframe_average", C.c_int32), ("skip_empty_bricks", C.c_int32)]
+                ("keyframe_average", C.c_int32), ("skip_empty_bricks", C.c_int32),
+                ("reserve_frames", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -95,6 +96,7 @@ def lib() -> C.CDLL:
         L.mrf_accuracy_static.argtypes = [P, P, C.c_double, P, P, P, P]
         L.mrf_accuracy_ex.argtypes = [P, P, C.c_double, P, C.c_double, P, P, P, P]
         L.mrf_depth_distribution.argtypes = [P, P, P, P, P]
+        L.mrf_add_frames.argtypes = [P, I32, P, P, P]
         L.mrf_generation.argtypes = [P, C.POINTER(C.c_uint64)]
         L.mrf_backward_gen.argtypes = [P, C.c_uint64, P, P, P, P, P]
         L.mrf_stats.argtypes = [P, C.POINTER(Stats)]

@@ -78,14 +78,29 @@ namespace mrf {
 
 void set_error(const std::string& msg) { g_err = msg; }
 
+// Set while mrf_add_frames runs: a buffer that ensure() has to grow then gets
+// room for four more growths of the same size, so that frames added one at a
+// time reallocate rarely.
+static thread_local int g_grow_room = 0;
+
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (b.p && b.cap >= bytes) return hipSuccess;
+    const size_t old = b.p ? b.cap : 0;
     if (b.p) hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
-    hipError_t e = hipMalloc(&b.p, bytes);
+    const size_t want = g_grow_room && old > 0 ? bytes + 4 * (bytes - old) : bytes;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e == hipSuccess) {
+        b.cap = want;
+        return e;
+    }
+    b.p = nullptr;
+    hipGetLastError();
+    if (want == bytes) return e;
+    e = hipMalloc(&b.p, bytes);   // without the room
     if (e != hipSuccess) {
         b.p = nullptr;
         hipGetLastError();
@@ -235,7 +250,7 @@ void mrf_destroy(mrf_ctx* c)
                      &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric, &c->b_bricks,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export,
-                     &c->b_kfw, &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox};
+                     &c->b_kfw, &c->b_kflen, &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox};
     for (DevBuf* b : all) free_buf(*b);
     for (auto& b : c->b_pair_desc) free_buf(b);
     for (auto& b : c->b_ray_list) free_buf(b);
@@ -254,6 +269,8 @@ int mrf_set_schedule(mrf_ctx* c, int32_t schedule)
     c->schedule = schedule;
     return MRF_OK;
 }
+
+static void update_stats(mrf_ctx* c);
 
 int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p, void* stream)
 {
@@ -354,8 +371,13 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(hipMemcpyAsync(c->b_frames.p, c->frames_h.data(), sizeof(FrameDev) * c->frames_h.size(),
                        hipMemcpyHostToDevice, s),
         "mrf_build: upload");
-    HCK(ensure(c->b_counts, sizeof(int32_t) * (size_t)R), "mrf_build: alloc counts");
-    HCK(ensure(c->b_rowptr, sizeof(int64_t) * (size_t)(R + 1)), "mrf_build: alloc row_ptr");
+    // room for reserve_frames more frames of the last scene (mrf_add_frames)
+    const int64_t reserve = p->reserve_frames > 0 ? p->reserve_frames : 0;
+    const SceneDev& sl = c->scenes_h.back();
+    const int64_t Rcap = R + reserve * (int64_t)sl.W * sl.H;
+    const int64_t Tcap = Tn + reserve * (int64_t)((sl.W + kTileW - 1) / kTileW) * ((sl.H + kTileW - 1) / kTileW);
+    HCK(ensure(c->b_counts, sizeof(int32_t) * (size_t)Rcap), "mrf_build: alloc counts");
+    HCK(ensure(c->b_rowptr, sizeof(int64_t) * (size_t)(Rcap + 1)), "mrf_build: alloc row_ptr");
     const size_t sbytes = scan_tmp_bytes(R + 1);
     HCK(ensure(c->b_misc, sbytes), "mrf_build: alloc scan");
     if (p->sparse_bricks) {
@@ -374,8 +396,8 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
 
     // tiles of 4x4 rays, slot bases = exclusive scan of 16 * longest ray
     const int64_t T = c->T;
-    HCK(ensure(c->b_tiles, sizeof(TileDev) * (size_t)T), "mrf_build: alloc tiles");
-    HCK(ensure(c->b_tbase, sizeof(int64_t) * (size_t)(T + 1)), "mrf_build: alloc tile bases");
+    HCK(ensure(c->b_tiles, sizeof(TileDev) * (size_t)Tcap), "mrf_build: alloc tiles");
+    HCK(ensure(c->b_tbase, sizeof(int64_t) * (size_t)(Tcap + 1)), "mrf_build: alloc tile bases");
     HCK(ensure(c->b_tmp64, sizeof(int32_t) * (size_t)(T + 1)), "mrf_build: alloc");
     const size_t tbytes = scan_tmp_bytes(T + 1);
     HCK(ensure(c->b_misc, tbytes > sbytes ? tbytes : sbytes), "mrf_build: alloc scan");
@@ -390,7 +412,10 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     if (S >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_build: 2^32 or more edge slots");
     c->S = S;
 
-    const size_t e1 = (size_t)(S > 0 ? S : 1);
+    // per-slot arrays, with room for the reserved frames at 1.25 times the batch's mean
+    // slots per frame
+    const int64_t Scap = S + (5 * reserve * S + 4 * c->n_frames - 1) / (4 * c->n_frames);
+    const size_t e1 = (size_t)(Scap > 0 ? Scap : 1);
     const size_t e4 = sizeof(float) * e1;
     HCK(ensure(c->b_col, e4), "mrf_build: alloc col");
     HCK(ensure(c->b_delta, e4), "mrf_build: alloc delta");
@@ -399,11 +424,11 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     // one entry more: the keyframe-pair build keeps an exclusive count of E + 1 entries in each
     HCK(ensure(c->b_lam, e4 + 16), "mrf_build: alloc lam");
     HCK(ensure(c->b_ell, e4 + 16), "mrf_build: alloc ell");
-    HCK(ensure(c->b_vedge, e4), "mrf_build: alloc vedge");
+    HCK(ensure(c->b_vedge, e4 + 16), "mrf_build: alloc vedge");
     HCK(ensure(c->b_ellbar, e4), "mrf_build: alloc ellbar");
     HCK(ensure(c->b_lambar, e4), "mrf_build: alloc lambar");
     HCK(ensure(c->b_gsum, e4), "mrf_build: alloc gsum");
-    if (c->kf) HCK(ensure(c->b_kfw, e4), "mrf_build: alloc chord lengths");
+    if (c->kf) HCK(ensure(c->b_kflen, e4), "mrf_build: alloc chord lengths");
     if (c->keep_chords) {
         HCK(ensure(c->b_tin, 2 * e4), "mrf_build: alloc t_in");
         HCK(ensure(c->b_tout, 2 * e4), "mrf_build: alloc t_out");
@@ -451,15 +476,24 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     }
     HCK(hipStreamSynchronize(s), "mrf_build: sync");
 
+    update_stats(c);
+    c->built = 1;
+    return MRF_OK;
+}
+
+// sizes, histograms (set by build_classes) and bytes per sweep of the built graph
+static void update_stats(mrf_ctx* c)
+{
     mrf_stats_t& st = c->stats;
-    st.n_scenes = n_scenes;
-    st.n_rays = R;
+    const int64_t E = c->E;
+    st.n_scenes = c->n_scenes;
+    st.n_rays = c->R;
     st.n_edges = E;
-    st.n_voxels = V;
+    st.n_voxels = c->V;
     st.n_kept_rays = 0;
     for (int k = 0; k < kRayClasses; ++k) st.n_kept_rays += c->ray_cls_rays[k];
-    st.n_slots = S;
-    st.n_tiles = T;
+    st.n_slots = c->S;
+    st.n_tiles = c->T;
     st.n_touched_voxels = 0;
     for (int k = 0; k < kVoxClasses; ++k) st.n_touched_voxels += c->vox_cnt[k];
     // voxel phase: vedge 4 + gathered ell 4 per edge, descriptor 16 + theta 4 + total 4 per
@@ -470,6 +504,184 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     st.sweeps_done = 0;
     st.have_checkpoints = 0;
     st.n_keyframe_pairs = c->n_pairs;
+}
+
+// Grows b to hold `need` bytes, keeping its first `keep` bytes; a buffer that has
+// to move gets room for four more additions of the same size, so that frames
+// added one at a time reallocate rarely.
+static hipError_t grow_keep(DevBuf& b, size_t need, size_t keep, hipStream_t s)
+{
+    if (need == 0) need = 16;
+    if (b.p && b.cap >= need) return hipSuccess;
+    const size_t grown = need + 4 * (need > keep ? need - keep : 0);
+    void* p = nullptr;
+    size_t got = grown;
+    hipError_t e = hipMalloc(&p, grown);
+    if (e != hipSuccess) {   // without the extra room
+        hipGetLastError();
+        got = need;
+        e = hipMalloc(&p, need);
+    }
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return e;
+    }
+    if (b.p && keep > 0) e = hipMemcpyAsync(p, b.p, keep < b.cap ? keep : b.cap, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hipFree(p);
+        return e;
+    }
+    if (b.p) hipFree(b.p);
+    b.p = p;
+    b.cap = got;
+    return hipSuccess;
+}
+
+int mrf_add_frames(mrf_ctx* c, int32_t n_frames, const float* depth, const double* T_wc, void* stream)
+{
+    if (!c || n_frames < 1 || !depth || !T_wc) return fail(MRF_EINVAL, "mrf_add_frames: null argument or no frames");
+    if (!c->built) return fail(MRF_ESTATE, "mrf_add_frames: call mrf_build first");
+    if (c->bp.bricks)
+        return fail(MRF_EINVAL, "mrf_add_frames: a sparse grid's bricks depend on every frame; rebuild instead");
+    if (c->frames_h.size() + (size_t)n_frames > 65535) return fail(MRF_EINVAL, "mrf_add_frames: more than 65535 frames");
+    struct GrowRoom {
+        GrowRoom() { g_grow_room = 1; }
+        ~GrowRoom() { g_grow_room = 0; }
+    } grow_room;
+    hipStream_t s = (hipStream_t)stream;
+    HCK(hipSetDevice(c->device), "mrf_add_frames: hipSetDevice");
+    drop_graph(c);
+    c->built = c->inferred = c->have_ckpt = c->kf_inferred = 0;
+    ++c->gen;
+
+    const int last = c->n_scenes - 1;
+    const SceneDev& sd = c->scenes_h[last];
+    const int64_t hw = (int64_t)sd.W * sd.H;
+    const int ntx = (sd.W + kTileW - 1) / kTileW, nty = (sd.H + kTileW - 1) / kTileW;
+    const int f0 = c->n_frames;
+    const int64_t R0 = c->R, T0 = c->T, S0 = c->S, E0 = c->E;
+    const int64_t R1 = R0 + hw * n_frames, T1 = T0 + (int64_t)ntx * nty * n_frames;
+    if (R1 >= (int64_t(1) << 31)) return fail(MRF_ERANGE, "mrf_add_frames: too many rays (>= 2^31)");
+    for (int f = 0; f < n_frames; ++f) {
+        FrameDev fr{};
+        fr.depth = depth + (size_t)f * hw;
+        fr.T = T_wc + (size_t)f * 16;
+        fr.scene = last;
+        fr.ntx = ntx;
+        fr.ray_base = R0 + (int64_t)f * hw;
+        fr.tile_base = T0 + (int64_t)f * ntx * nty;
+        c->frames_h.push_back(fr);
+    }
+    c->n_frames = (int)c->frames_h.size();
+    c->R = R1;
+    c->T = T1;
+    HCK(grow_keep(c->b_frames, sizeof(FrameDev) * c->frames_h.size(), 0, s), "mrf_add_frames: alloc frames");
+    HCK(hipMemcpyAsync(c->b_frames.p, c->frames_h.data(), sizeof(FrameDev) * c->frames_h.size(),
+                       hipMemcpyHostToDevice, s),
+        "mrf_add_frames: upload");
+
+    // rays of the new frames: counts, then row_ptr[R0..R1] = E0 + their exclusive scan
+    HCK(grow_keep(c->b_counts, sizeof(int32_t) * (size_t)R1, sizeof(int32_t) * (size_t)R0, s), "mrf_add_frames: alloc");
+    HCK(grow_keep(c->b_rowptr, sizeof(int64_t) * (size_t)(R1 + 1), sizeof(int64_t) * (size_t)(R0 + 1), s),
+        "mrf_add_frames: alloc");
+    size_t sb = scan_tmp_bytes(R1 - R0 + 1);
+    HCK(ensure(c->b_misc, sb > c->b_misc.cap ? sb : c->b_misc.cap), "mrf_add_frames: alloc scan");
+    HCK(launch_trace_count(c, s, f0, n_frames), "mrf_add_frames: trace count");
+    HCK(scan_exclusive_i32((const int32_t*)c->b_counts.p + R0, (int64_t*)c->b_rowptr.p + R0, R1 - R0, c->b_misc.p,
+                           c->b_misc.cap, s),
+        "mrf_add_frames: scan");
+    HCK(launch_add_i64((int64_t*)c->b_rowptr.p + R0, E0, R1 - R0 + 1, s), "mrf_add_frames: scan");
+    int64_t E1 = 0;
+    HCK(hipMemcpyAsync(&E1, (int64_t*)c->b_rowptr.p + R1, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read E");
+    HCK(hipStreamSynchronize(s), "mrf_add_frames: sync");
+    c->E = E1;
+
+    // tiles of the new frames, slot bases after every existing slot
+    HCK(grow_keep(c->b_tiles, sizeof(TileDev) * (size_t)T1, sizeof(TileDev) * (size_t)T0, s), "mrf_add_frames: alloc");
+    HCK(grow_keep(c->b_tbase, sizeof(int64_t) * (size_t)(T1 + 1), sizeof(int64_t) * (size_t)(T0 + 1), s),
+        "mrf_add_frames: alloc");
+    HCK(ensure(c->b_tmp64, sizeof(int32_t) * (size_t)(T1 - T0 + 1)), "mrf_add_frames: alloc");
+    sb = scan_tmp_bytes(T1 - T0 + 1);
+    HCK(ensure(c->b_misc, sb > c->b_misc.cap ? sb : c->b_misc.cap), "mrf_add_frames: alloc scan");
+    HCK(launch_tiles(c, (int32_t*)c->b_tmp64.p, s, f0, n_frames), "mrf_add_frames: tiles");
+    HCK(scan_exclusive_i32((const int32_t*)c->b_tmp64.p, (int64_t*)c->b_tbase.p + T0, T1 - T0, c->b_misc.p,
+                           c->b_misc.cap, s),
+        "mrf_add_frames: tile scan");
+    HCK(launch_add_i64((int64_t*)c->b_tbase.p + T0, S0, T1 - T0 + 1, s), "mrf_add_frames: tile scan");
+    HCK(launch_tile_bases(c, s, T0), "mrf_add_frames: tile bases");
+    int64_t S1 = 0;
+    HCK(hipMemcpyAsync(&S1, (int64_t*)c->b_tbase.p + T1, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read S");
+    HCK(hipStreamSynchronize(s), "mrf_add_frames: sync");
+    if (S1 >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_add_frames: 2^32 or more edge slots");
+    c->S = S1;
+
+    // per-slot arrays: the existing slots are kept, the new ones written by the emit pass
+    const size_t k4 = sizeof(float) * (size_t)S0, e4 = sizeof(float) * (size_t)S1;
+    HCK(grow_keep(c->b_col, e4, k4, s), "mrf_add_frames: alloc col");
+    HCK(grow_keep(c->b_delta, e4, k4, s), "mrf_add_frames: alloc delta");
+    HCK(grow_keep(c->b_bin, (size_t)S1, (size_t)S0, s), "mrf_add_frames: alloc bin");
+    if (c->keep_chords) {
+        HCK(grow_keep(c->b_tin, 2 * e4, 2 * k4, s), "mrf_add_frames: alloc t_in");
+        HCK(grow_keep(c->b_tout, 2 * e4, 2 * k4, s), "mrf_add_frames: alloc t_out");
+    }
+    if (c->kf) HCK(grow_keep(c->b_kflen, e4, k4, s), "mrf_add_frames: alloc chord lengths");
+    HCK(grow_keep(c->b_vedge, e4 + 16, sizeof(uint32_t) * (size_t)E0, s), "mrf_add_frames: alloc vedge");
+    // message and scratch arrays: the old messages are stale once frames are added
+    HCK(ensure(c->b_g, e4), "mrf_add_frames: alloc");
+    HCK(ensure(c->b_lam, e4 + 16), "mrf_add_frames: alloc");
+    HCK(ensure(c->b_ell, e4 + 16), "mrf_add_frames: alloc");
+    HCK(ensure(c->b_ellbar, e4), "mrf_add_frames: alloc");
+    HCK(ensure(c->b_lambar, e4), "mrf_add_frames: alloc");
+    HCK(ensure(c->b_gsum, e4), "mrf_add_frames: alloc");
+    HCK(launch_trace_emit(c, s, f0, n_frames), "mrf_add_frames: trace emit");
+
+    // the new slots sorted by voxel key on their own (keys were left in b_g), then merged
+    // behind each voxel's existing entries
+    const int64_t n1 = S1 - S0;
+    const int64_t nh = (int64_t)radix_hist_entries(n1);
+    HCK(ensure(c->b_tmp64, sizeof(int64_t) * (size_t)(nh + 1) + sizeof(int32_t) * (size_t)nh),
+        "mrf_add_frames: alloc sort tables");
+    int64_t* offs = (int64_t*)c->b_tmp64.p;
+    int32_t* hist = (int32_t*)(offs + nh + 1);
+    sb = radix_tmp_bytes(n1);
+    HCK(ensure(c->b_misc, sb > c->b_misc.cap ? sb : c->b_misc.cap), "mrf_add_frames: alloc sort scan");
+    uint32_t* nkeys = (uint32_t*)c->b_lambar.p;   // sorted new keys
+    uint32_t* nvals = (uint32_t*)c->b_gsum.p;     // their slots less S0
+    // temporaries in b_export: the new keys' vptr (Vk + 1 int64), then the sort's spare values
+    const size_t vpb = sizeof(int64_t) * (size_t)(c->Vk + 1);
+    hipError_t e = ensure(c->b_export, vpb + sizeof(uint32_t) * (size_t)n1 + 64);
+    int64_t* nvptr = (int64_t*)c->b_export.p;
+    uint32_t* vals_b = (uint32_t*)((char*)c->b_export.p + (vpb + 63) / 64 * 64);
+    if (e == hipSuccess)
+        e = radix_sort_pairs((const uint32_t*)c->b_g.p + S0, (uint32_t*)c->b_lam.p, (uint32_t*)c->b_ell.p,
+                             (uint32_t*)c->b_ellbar.p, vals_b, nkeys, nvals, n1, bits_for(c->Vk), hist, offs,
+                             c->b_misc.p, c->b_misc.cap, s);
+    if (e == hipSuccess) e = launch_vptr_from_sorted(nkeys, n1, c->Vk, nvptr, s);
+    uint32_t* okeys = (uint32_t*)c->b_ell.p;      // keys of the existing entries
+    uint32_t* merged = (uint32_t*)c->b_lam.p;
+    if (e == hipSuccess) e = launch_entry_keys(c, (const uint32_t*)c->b_vedge.p, E0, okeys, s);
+    if (e == hipSuccess)
+        e = launch_merge_incidence((const uint32_t*)c->b_vedge.p, okeys, E0, nvals, nkeys, E1 - E0, (uint32_t)S0,
+                                   (int64_t*)c->b_vptr.p, nvptr, c->Vk + 1, merged, s);
+    HCK(e, "mrf_add_frames: sort and merge");
+    std::swap(c->b_vedge, c->b_lam);
+    // padding entries past E (their key is past every voxel) keep the list's tail defined
+    HCK(launch_fill_u32((uint32_t*)c->b_vedge.p + E1, 0u, S1 - E1, s), "mrf_add_frames: fill");
+    {
+        hipError_t e2 = build_classes(c, s);
+        if (e2 == hipErrorInvalidConfiguration) return fail(MRF_ERANGE, "mrf_add_frames: " + g_err);
+        HCK(e2, "mrf_add_frames: work lists");
+    }
+    if (c->kf) {
+        HCK(launch_entry_keys(c, (const uint32_t*)c->b_vedge.p, E1, (uint32_t*)c->b_lambar.p, s),
+            "mrf_add_frames: keys");
+        hipError_t e2 = build_keyframe_pairs(c, s);
+        if (e2 == hipErrorInvalidConfiguration) return fail(MRF_ERANGE, "mrf_add_frames: " + g_err);
+        HCK(e2, "mrf_add_frames: keyframe pairs");
+    }
+    HCK(hipStreamSynchronize(s), "mrf_add_frames: sync");
+    update_stats(c);
     c->built = 1;
     return MRF_OK;
 }

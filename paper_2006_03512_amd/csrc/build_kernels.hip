@@ -385,11 +385,11 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
 }
 
 // One thread per tile: its rays, extent inside the image and longest ray.
-__global__ void tile_init_k(const SceneDev* __restrict__ scenes, const FrameDev* __restrict__ frames,
+__global__ void tile_init_k(const SceneDev* __restrict__ scenes, const FrameDev* __restrict__ frames, int f0,
                             const int32_t* __restrict__ counts, TileDev* __restrict__ tiles,
-                            int32_t* __restrict__ slots16)
+                            int32_t* __restrict__ slots16, int64_t t0)
 {
-    const FrameDev fr = frames[blockIdx.y];
+    const FrameDev fr = frames[f0 + blockIdx.y];
     const SceneDev& sd = scenes[fr.scene];
     const int nty = (sd.H + kTileW - 1) / kTileW;
     const int lt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -405,9 +405,9 @@ __global__ void tile_init_k(const SceneDev* __restrict__ scenes, const FrameDev*
         for (int b = 0; b < td.nu; ++b) len = max(len, counts[td.ray0 + a * sd.W + b]);
     td.len = len;
     td.base = 0;
-    td.frame = (int32_t)blockIdx.y;
+    td.frame = f0 + (int32_t)blockIdx.y;
     tiles[fr.tile_base + lt] = td;
-    slots16[fr.tile_base + lt] = kTile * len;
+    slots16[fr.tile_base + lt - t0] = kTile * len;
 }
 
 __global__ void tile_base_k(TileDev* __restrict__ tiles, const int64_t* __restrict__ tbase, int64_t T)
@@ -432,31 +432,35 @@ hipError_t launch_brick_mask(mrf_ctx* c, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s)
+hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s, int f0, int nf)
 {
-    dim3 grid((c->max_hw + 255) / 256, c->n_frames);
+    if (nf < 0) nf = c->n_frames - f0;
+    if (nf <= 0) return hipSuccess;
+    dim3 grid((c->max_hw + 255) / 256, nf);
     hipLaunchKernelGGL(trace_count_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
-                       (const FrameDev*)c->b_frames.p, c->bp, (int32_t*)c->b_counts.p);
+                       (const FrameDev*)c->b_frames.p + f0, c->bp, (int32_t*)c->b_counts.p);
     return hipGetLastError();
 }
 
-hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s)
+hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s, int f0, int nf)
 {
+    if (nf < 0) nf = c->n_frames - f0;
+    if (nf <= 0) return hipSuccess;
     int max_tiles = 0;
     for (const auto& sd : c->scenes_h)
         max_tiles = std::max(max_tiles, ((sd.W + kTileW - 1) / kTileW) * ((sd.H + kTileW - 1) / kTileW));
-    dim3 grid((max_tiles + 255) / 256, c->n_frames);
+    dim3 grid((max_tiles + 255) / 256, nf);
     hipLaunchKernelGGL(tile_init_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
-                       (const FrameDev*)c->b_frames.p, (const int32_t*)c->b_counts.p, (TileDev*)c->b_tiles.p,
-                       slots16);
+                       (const FrameDev*)c->b_frames.p, f0, (const int32_t*)c->b_counts.p, (TileDev*)c->b_tiles.p,
+                       slots16, c->frames_h[f0].tile_base);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s)
+hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s, int64_t t0)
 {
-    if (c->T > 0)
-        hipLaunchKernelGGL(tile_base_k, dim3((unsigned)((c->T + 255) / 256)), dim3(256), 0, s,
-                           (TileDev*)c->b_tiles.p, (const int64_t*)c->b_tbase.p, c->T);
+    if (c->T > t0)
+        hipLaunchKernelGGL(tile_base_k, dim3((unsigned)((c->T - t0 + 255) / 256)), dim3(256), 0, s,
+                           (TileDev*)c->b_tiles.p + t0, (const int64_t*)c->b_tbase.p + t0, c->T - t0);
     return hipGetLastError();
 }
 
@@ -469,15 +473,17 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s)
+hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s, int f0, int nf)
 {
-    dim3 grid((unsigned)((c->max_tpf + 256 / kTile - 1) / (256 / kTile)), c->n_frames);
+    if (nf < 0) nf = c->n_frames - f0;
+    if (nf <= 0) return hipSuccess;
+    dim3 grid((unsigned)((c->max_tpf + 256 / kTile - 1) / (256 / kTile)), nf);
     hipLaunchKernelGGL(trace_emit_k, grid, dim3(256), 0, s, (const SceneDev*)c->b_scenes.p,
-                       (const FrameDev*)c->b_frames.p, c->bp, (const int32_t*)c->b_counts.p,
+                       (const FrameDev*)c->b_frames.p + f0, c->bp, (const int32_t*)c->b_counts.p,
                        (const int64_t*)c->b_tbase.p, (const TileDev*)c->b_tiles.p, (uint32_t)c->Vk,
                        (int32_t*)c->b_col.p, (uint32_t*)c->b_g.p, (float*)c->b_delta.p, (uint8_t*)c->b_bin.p,
                        c->keep_chords ? (double*)c->b_tin.p : nullptr,
-                       c->keep_chords ? (double*)c->b_tout.p : nullptr, c->kf ? (float*)c->b_kfw.p : nullptr);
+                       c->keep_chords ? (double*)c->b_tout.p : nullptr, c->kf ? (float*)c->b_kflen.p : nullptr);
     return hipGetLastError();
 }
 
@@ -1277,6 +1283,88 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
     return hipGetLastError();
 }
 
+// ============================================================== adding keyframes
+//
+// Frames appended to the last scene add tiles and slots after every existing
+// one, so within a voxel's edge list (slots ascending) the existing entries come
+// first: with the new slots sorted by voxel key on their own, the merged list of
+// key k is the old list of k followed by the new one, at merged offset
+// old_vptr[k] + new_vptr[k].
+
+// brick-major key of the voxel of list entry j (col of its slot)
+__global__ void entry_keys_k(const SceneDev* __restrict__ scenes, int ns, const uint32_t* __restrict__ vedge,
+                             const int32_t* __restrict__ col, int64_t n, uint32_t* __restrict__ keys)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        keys[j] = voxel_to_key(scenes, ns, col[vedge[j]]);
+}
+
+// old entry j of key k moves to j + new_vptr[k]; new entry i (slot s_new0 + vals[i],
+// key keys_new[i] < Vk) to old_vptr[keys_new[i] + 1] + i
+__global__ void merge_old_k(const uint32_t* __restrict__ vedge_old, const uint32_t* __restrict__ keys_old, int64_t n,
+                            const int64_t* __restrict__ new_vptr, uint32_t* __restrict__ out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        out[j + new_vptr[keys_old[j]]] = vedge_old[j];
+}
+
+__global__ void merge_new_k(const uint32_t* __restrict__ vals, const uint32_t* __restrict__ keys_new, int64_t n,
+                            uint32_t s_new0, const int64_t* __restrict__ old_vptr, uint32_t* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[old_vptr[keys_new[i] + 1] + i] = s_new0 + vals[i];
+}
+
+// vptr_old[k] += new_vptr[k] over every key (k <= Vk)
+__global__ void add_vptr_k(int64_t* __restrict__ vptr, const int64_t* __restrict__ add, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        vptr[k] += add[k];
+}
+
+__global__ void add_i64_k(int64_t* __restrict__ p, int64_t v, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] += v;
+}
+
+static unsigned grid_of(int64_t n)
+{
+    int64_t b = cdiv(n, 256);
+    if (b > 65536) b = 65536;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+hipError_t launch_add_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_i64_k, dim3(grid_of(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry_keys(const mrf_ctx* c, const uint32_t* vedge, int64_t n, uint32_t* keys, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(entry_keys_k, dim3(grid_of(n)), dim3(256), 0, s, (const SceneDev*)c->b_scenes.p, c->n_scenes,
+                       vedge, (const int32_t*)c->b_col.p, n, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_incidence(const uint32_t* vedge_old, const uint32_t* keys_old, int64_t n_old,
+                                  const uint32_t* vals_new, const uint32_t* keys_new, int64_t n_new,
+                                  uint32_t s_new0, int64_t* vptr, int64_t* new_vptr, int64_t nkeys, uint32_t* out,
+                                  hipStream_t s)
+{
+    if (n_old > 0)
+        hipLaunchKernelGGL(merge_old_k, dim3(grid_of(n_old)), dim3(256), 0, s, vedge_old, keys_old, n_old,
+                           (const int64_t*)new_vptr, out);
+    if (n_new > 0)
+        hipLaunchKernelGGL(merge_new_k, dim3(grid_of(n_new)), dim3(256), 0, s, vals_new, keys_new, n_new, s_new0,
+                           (const int64_t*)vptr, out);
+    hipLaunchKernelGGL(add_vptr_k, dim3(grid_of(nkeys)), dim3(256), 0, s, vptr, (const int64_t*)new_vptr, nkeys);
+    return hipGetLastError();
+}
+
 // ============================================================== keyframe pairs
 //
 // Per-keyframe averaged messages (Sec. IV-A): the rays of one keyframe that
@@ -1480,17 +1568,17 @@ hipError_t build_keyframe_pairs(mrf_ctx* c, hipStream_t s)
     }
 
     // weights: chord length over the pair's summed chord length, in list order;
-    // the chord lengths (slot order, b_kfw) are summed per pair by the pair phase
+    // the chord lengths (slot order, b_kflen) are summed per pair by the pair phase
     double* wsum = (double*)c->b_pair_m.p;
-    float* w = (float*)c->b_ellbar.p;
-    if ((e = launch_pair_phase(c, (const float*)c->b_kfw.p, nullptr, wsum, s)) != hipSuccess) return e;
+    if ((e = ensure(c->b_kfw, sizeof(float) * (size_t)(E > 0 ? E : 1))) != hipSuccess) return e;
+    float* w = (float*)c->b_kfw.p;
+    if ((e = launch_pair_phase(c, (const float*)c->b_kflen.p, nullptr, wsum, s)) != hipSuccess) return e;
     if (E > 0) {
         int64_t b = cdiv(E, 256);
         if (b > 65536) b = 65536;
         hipLaunchKernelGGL(pair_weight_k, dim3((unsigned)b), dim3(256), 0, s, vedge, (const uint32_t*)pos, E,
-                           (const uint32_t*)pstart, (const float*)c->b_kfw.p, (const double*)wsum, w);
+                           (const uint32_t*)pstart, (const float*)c->b_kflen.p, (const double*)wsum, w);
     }
-    std::swap(c->b_kfw, c->b_ellbar);   // weights stay in b_kfw; the chord lengths' buffer becomes scratch
     return hipGetLastError();
 }
 

@@ -282,7 +282,8 @@ struct mrf_ctx {
     int kf_inferred = 0;          // the last inference used them
     int64_t n_pairs = 0;          // (keyframe, voxel) pairs with at least one edge
     int64_t n_kfx = 0;            // entries of the per-keyframe message buffers
-    mrf::DevBuf b_kfw;            // per edge slot: chord length (build), then per vedge entry: weight / pair sum
+    mrf::DevBuf b_kflen;          // per edge slot: chord length (Euclidean) of the edge
+    mrf::DevBuf b_kfw;            // per vedge entry: chord length / the pair's summed chord length
     mrf::DevBuf b_pair_m;         // per pair: FP64 average message of the keyframe into the voxel
     mrf::DevBuf b_pair_x;         // per pair: index of its entry in b_kfx
     mrf::DevBuf b_kfx;            // per-keyframe voxel -> ray messages
@@ -347,8 +348,9 @@ hipError_t ensure(DevBuf& b, size_t bytes);
 
 // every launcher returns hipSuccess or the first error
 // build_kernels.hip
-hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s);
-hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s);
+// the count and emit passes over frames [f0, f0 + nf) (nf < 0: to the last frame)
+hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s, int f0 = 0, int nf = -1);
+hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s, int f0 = 0, int nf = -1);
 hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t tmp_bytes,
                               hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
@@ -365,8 +367,18 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s);
 hipError_t export_canonical_incidence(const mrf_ctx* c, int64_t* vptr, uint32_t* vedge, hipStream_t s);
 // per-edge array from slot order to canonical edge order
 hipError_t export_canonical_edges(const mrf_ctx* c, const void* in_slots, void* out, int elem_bytes, hipStream_t s);
-hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s);
-hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s);
+// tile descriptors of frames [f0, f0 + nf); slots16[t - first tile of f0] = 16 * longest ray
+hipError_t launch_tiles(mrf_ctx* c, int32_t* slots16, hipStream_t s, int f0 = 0, int nf = -1);
+hipError_t launch_tile_bases(mrf_ctx* c, hipStream_t s, int64_t t0 = 0);
+hipError_t launch_add_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+// keys[j] = brick-major key of the voxel of list entry j
+hipError_t launch_entry_keys(const mrf_ctx* c, const uint32_t* vedge, int64_t n, uint32_t* keys, hipStream_t s);
+// merged voxel -> ray list of the old entries (sorted, keys_old per entry) and the new
+// slots sorted on their own (vals relative to s_new0); vptr += new_vptr
+hipError_t launch_merge_incidence(const uint32_t* vedge_old, const uint32_t* keys_old, int64_t n_old,
+                                  const uint32_t* vals_new, const uint32_t* keys_new, int64_t n_new,
+                                  uint32_t s_new0, int64_t* vptr, int64_t* new_vptr, int64_t nkeys, uint32_t* out,
+                                  hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // per-keyframe averaged messages: (keyframe, voxel) pairs of the built graph,
 // their weights, work classes and message-buffer indices (after build_classes,

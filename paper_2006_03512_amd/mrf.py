@@ -106,14 +106,16 @@ class RayMRF:
         self._params = p0
         self._frames_built = False   # the context still points at the previous upload's frames
 
-    def build_resident(self, keep_chords: bool = False, stream=None, keyframe_average: bool = False):
+    def build_resident(self, keep_chords: bool = False, stream=None, keyframe_average: bool = False,
+                       reserve_frames: int = 0):
         """(Re)build the ray MRF from the uploaded frames; keyframe_average
-        prepares ``infer_keyframe_avg`` (Sec. IV-A)."""
+        prepares ``infer_keyframe_avg`` (Sec. IV-A); reserve_frames sizes the
+        buffers for that many later ``add_frames`` frames of the last scene."""
         p0 = self._params
         bp = _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
                               p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0,
                               1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0,
-                              1 if getattr(p0, "skip_empty_bricks", 0) else 0)
+                              1 if getattr(p0, "skip_empty_bricks", 0) else 0, int(reserve_frames))
         with torch.cuda.device(self.device):
             check(self._L.mrf_build(self._h, self._arr, len(self._arr), C.byref(bp),
                                     stream_handle(stream)), "mrf_build")
@@ -123,10 +125,26 @@ class RayMRF:
         self._frames_built = True
         return st
 
-    def build(self, scenes, keep_chords: bool = False, stream=None, keyframe_average: bool = False):
+    def add_frames(self, depth, T_wc, stream=None):
+        """Append keyframes (depth (F, H, W) z-depth, T_wc (F, 4, 4) camera->world)
+        to the last scene of the built batch without rebuilding the rest."""
+        d = torch.from_numpy(np.ascontiguousarray(depth, np.float32)).to(self.device)
+        T = torch.from_numpy(np.ascontiguousarray(T_wc, np.float64).reshape(-1, 16)).to(self.device)
+        if d.dim() != 3 or T.shape[0] != d.shape[0]:
+            raise ValueError("depth must be (F, H, W) and T_wc (F, 4, 4)")
+        self._keep += [d, T]
+        with torch.cuda.device(self.device):
+            check(self._L.mrf_add_frames(self._h, int(d.shape[0]), ptr(d), ptr(T), stream_handle(stream)),
+                  "mrf_add_frames")
+        st = self.stats()
+        self.n_voxels, self.n_edges, self.n_rays = st.n_voxels, st.n_edges, st.n_rays
+        return st
+
+    def build(self, scenes, keep_chords: bool = False, stream=None, keyframe_average: bool = False,
+              reserve_frames: int = 0):
         """Upload and build the ray MRF of one scene or a list of scenes (batched)."""
         self.upload(scenes)
-        return self.build_resident(keep_chords, stream, keyframe_average)
+        return self.build_resident(keep_chords, stream, keyframe_average, reserve_frames)
 
     def stats(self) -> GraphStats:
         st = _lib.Stats()
