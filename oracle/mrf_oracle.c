@@ -24,7 +24,9 @@
  *       nu(d_i) = N(Z; d_i + b(d_i), sigma(d_i)) (Eq. noise with the learnt
  *       bias of Sec. IV-C: the bias at the traversed depth gives the predicted
  *       mean measurement, the noise its spread), sigma and b from 64-bin
- *       depth-indexed tables (b = 0 when no bias table is given).
+ *       depth-indexed tables (b = 0 when no bias table is given), or from one
+ *       such table per pixel region (Sec. IV-C learns the model per 20 x 20
+ *       pixel neighbourhood): the caller passes each edge's table entry.
  *   or_infer                        -- flooding schedule of K sweeps; each
  *       sweep sends variable->factor messages (Eq. node_to_factor, including
  *       the prior factor, Eq. prior_potential) and then the ray-factor ->
@@ -348,7 +350,9 @@ void or_incidence(const int32_t* col, int64_t E, int64_t V, int64_t* vptr, int64
 }
 
 /* g_e = log N(Z; d_e + mu_b, sigma_b) = -((delta - mu_b)/sigma_b)^2/2 - log sigma_b
- * - log(2 pi)/2 with delta = Z - d_e; bias (mu, 64 entries) may be NULL for mu = 0. */
+ * - log(2 pi)/2 with delta = Z - d_e; bias (mu) may be NULL for mu = 0.  bin[e]
+ * indexes the tables: the depth bin, or, with per-pixel-region tables (Sec. IV-C),
+ * the region's row times 64 plus the depth bin. */
 void or_potentials(const double* delta, const int32_t* bin, int64_t E,
                    const double* sigma, const double* bias, double* g)
 {
@@ -691,14 +695,15 @@ static void or_ray_adjoint(int64_t n, const double* lam, const double* g, const 
 /* Reverse pass over K sweeps.  Inputs: the forward's lambda of every sweep
  * (lam_hist, K*E), g (E), and Lbar = d loss / d L (V).  Outputs:
  * d loss / d theta (V), d loss / d g accumulated over sweeps (gbar, E), and
- * d loss / d sigma_b and d loss / d mu_b (64 each) through
+ * d loss / d sigma_b and d loss / d mu_b (n_tab entries each: 64 depth bins,
+ * or 64 per pixel region; bin[e] indexes them as in or_potentials) through
  * g_e = log N(Z; d_e + mu_b, sigma_b), with r = Z - d_e - mu_b:
  *   d g / d sigma = r^2 / sigma^3 - 1 / sigma,   d g / d mu = r / sigma^2.
  * bias may be NULL (mu = 0); bias_bar may be NULL (not wanted). */
 void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
                  int64_t V, int64_t E, const double* g, int32_t K, const double* lam_hist,
                  const double* Lbar, const double* delta, const int32_t* bin,
-                 const double* sigma, const double* bias, double* theta_bar, double* gbar,
+                 const double* sigma, const double* bias, int32_t n_tab, double* theta_bar, double* gbar,
                  double* sigma_bar, double* bias_bar)
 {
     double* ellbar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
@@ -731,7 +736,7 @@ void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const i
         }
         if (k > 0) or_voxel_phase(vptr, vedge, V, NULL, lambar, ellbar);
     }
-    for (int b = 0; b < 64; ++b) {
+    for (int32_t b = 0; b < n_tab; ++b) {
         sigma_bar[b] = 0.0;
         if (bias_bar) bias_bar[b] = 0.0;
     }

@@ -56,7 +56,7 @@ def lib():
         _lib.or_incidence.argtypes = [P, I64, I64, P, P]
         _lib.or_potentials.argtypes = [P, P, I64, P, P, P]
         _lib.or_infer.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P]
-        _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, P, P, P, P]
+        _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, I32, P, P, P, P]
         _lib.or_single_ray.argtypes = [I64, P, P, P]
         _lib.or_infer_f32_storage.argtypes = [P, I64, P, P, I64, I64, P, P, I32, I32, P, P, P]
         _lib.or_infer_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P, P]
@@ -186,16 +186,42 @@ def build_graph(scenes) -> Graph:
 
 
 def _bias(bias_table):
-    return None if bias_table is None else np.ascontiguousarray(bias_table, np.float64)
+    return None if bias_table is None else np.ascontiguousarray(bias_table, np.float64).reshape(-1)
 
 
-def potentials(graph: Graph, sigma_table, bias_table=None) -> np.ndarray:
+def cell_table_index(graph: Graph, scenes, cell_px: int) -> np.ndarray:
+    """Per-pixel-region sensor tables (Sec. IV-C): the table entry of every edge,
+    64 * cell + bin, where the cell of pixel (u, v) of a W-wide frame is
+    (v // cell_px) * ceil(W / cell_px) + u // cell_px."""
+    if not isinstance(scenes, (list, tuple)):
+        scenes = [scenes]
+    ray = np.repeat(np.arange(graph.n_rays, dtype=np.int64), np.diff(graph.row_ptr))
+    cell_of_ray = np.empty(graph.n_rays, np.int64)
+    for s, rb in zip(scenes, graph.ray_base):
+        F, H, W = s.depth.shape
+        v, u = np.divmod(np.arange(H * W, dtype=np.int64), W)
+        c = (v // cell_px) * (-(-W // cell_px)) + u // cell_px
+        cell_of_ray[rb: rb + F * H * W] = np.tile(c, F)
+    return (64 * cell_of_ray[ray] + graph.bin).astype(np.int32)
+
+
+def n_cells(scenes, cell_px: int) -> int:
+    """Rows of per-region tables for a batch: the most cells of any scene's image."""
+    if not isinstance(scenes, (list, tuple)):
+        scenes = [scenes]
+    return max((-(-s.intr.width // cell_px)) * (-(-s.intr.height // cell_px)) for s in scenes)
+
+
+def potentials(graph: Graph, sigma_table, bias_table=None, table_index=None) -> np.ndarray:
     """g_e = log N(Z; d_e + mu_b, sigma_b) for 64-entry sigma and bias tables
-    (no bias table: mu = 0)."""
-    sig = np.ascontiguousarray(sigma_table, np.float64)
+    (no bias table: mu = 0); with table_index (cell_table_index) the tables hold
+    64 entries per pixel region, (n_cells, 64) or flat."""
+    sig = np.ascontiguousarray(sigma_table, np.float64).reshape(-1)
     mu = _bias(bias_table)
+    idx = graph.bin if table_index is None else np.ascontiguousarray(table_index, np.int32)
+    assert idx.shape[0] == graph.n_edges and (idx.size == 0 or int(idx.max()) < sig.size)
     g = np.empty(graph.n_edges)
-    lib().or_potentials(_p(graph.delta), _p(graph.bin), graph.n_edges, _p(sig), _p(mu), _p(g))
+    lib().or_potentials(_p(graph.delta), _p(idx), graph.n_edges, _p(sig), _p(mu), _p(g))
     return g
 
 
@@ -213,10 +239,10 @@ class Result:
 
 
 def infer(graph: Graph, theta, sigma_table, sweeps: int, keep_history: bool = False,
-          g: np.ndarray | None = None, bias_table=None) -> Result:
+          g: np.ndarray | None = None, bias_table=None, table_index=None) -> Result:
     theta = np.ascontiguousarray(theta, np.float64)
     if g is None:
-        g = potentials(graph, sigma_table, bias_table)
+        g = potentials(graph, sigma_table, bias_table, table_index)
     E, V = graph.n_edges, graph.n_voxels
     lam, ell, L = np.empty(E), np.empty(E), np.empty(V)
     hist = np.empty((sweeps, E)) if keep_history else None
@@ -263,11 +289,11 @@ def edge_keyframes_and_lengths(graph: Graph, scenes):
 
 
 def infer_keyframe_average(graph: Graph, theta, sigma_table, sweeps: int, key, weight,
-                           bias_table=None) -> Result:
+                           bias_table=None, table_index=None) -> Result:
     """K sweeps with one length-weighted average message per keyframe and
     voxel (Sec. IV-A); key and weight per edge (edge_keyframes_and_lengths)."""
     theta = np.ascontiguousarray(theta, np.float64)
-    g = potentials(graph, sigma_table, bias_table)
+    g = potentials(graph, sigma_table, bias_table, table_index)
     E, V = graph.n_edges, graph.n_voxels
     key = np.ascontiguousarray(key, np.int32)
     weight = np.ascontiguousarray(weight, np.float64)
@@ -279,20 +305,24 @@ def infer_keyframe_average(graph: Graph, theta, sigma_table, sweeps: int, key, w
     return Result(L, lam, ell, g, None)
 
 
-def backward(graph: Graph, res: Result, Lbar, sigma_table, bias_table=None, want_bias: bool = False):
-    """(d loss/d theta (V), d loss/d sigma (64), d loss/d g (E)), and with
-    want_bias also d loss/d mu (64) appended.  bias_table must be the one the
-    forward used."""
+def backward(graph: Graph, res: Result, Lbar, sigma_table, bias_table=None, want_bias: bool = False,
+             table_index=None):
+    """(d loss/d theta (V), d loss/d sigma, d loss/d g (E)), and with want_bias
+    also d loss/d mu appended; the table gradients have the tables' size (64,
+    or 64 per pixel region with table_index).  bias_table and table_index must
+    be the ones the forward used."""
     assert res.lam_hist is not None, "forward must keep its history"
     Lbar = np.ascontiguousarray(Lbar, np.float64)
-    sig = np.ascontiguousarray(sigma_table, np.float64)
+    sig = np.ascontiguousarray(sigma_table, np.float64).reshape(-1)
     mu = _bias(bias_table)
+    idx = graph.bin if table_index is None else np.ascontiguousarray(table_index, np.int32)
+    n_tab = sig.size
     E, V = graph.n_edges, graph.n_voxels
-    tb, gb, sb = np.empty(V), np.empty(E), np.empty(64)
-    bb = np.empty(64) if want_bias else None
+    tb, gb, sb = np.empty(V), np.empty(E), np.empty(n_tab)
+    bb = np.empty(n_tab) if want_bias else None
     lib().or_backward(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
                       _p(res.g), res.lam_hist.shape[0], _p(res.lam_hist), _p(Lbar),
-                      _p(graph.delta), _p(graph.bin), _p(sig), _p(mu), _p(tb), _p(gb), _p(sb), _p(bb))
+                      _p(graph.delta), _p(idx), _p(sig), _p(mu), int(n_tab), _p(tb), _p(gb), _p(sb), _p(bb))
     return (tb, sb, gb, bb) if want_bias else (tb, sb, gb)
 
 
