@@ -288,7 +288,7 @@ def main():
         bwd_ms = timed(lambda: m.backward(gl))
     log(f"build {build_ms:.1f} ms, forward graph {fwd_graph_ms:.1f} ms, plain {fwd_plain_ms:.1f} ms, "
         f"backward {bwd_ms}")
-    fwd_bias_ms = bwd_bias_ms = acc_ms = dd_ms = None
+    fwd_bias_ms = bwd_bias_ms = acc_ms = dd_ms = fwd_cell_ms = bwd_cell_ms = None
     acc_counts, acc_clean, acc_by_k, clean_by_k = [0, 0], None, {}, {}
     kf_build_ms = kf_fwd_ms = kf_plain_ms = kf_clean = None
     kf_acc, kf_by_k, kf_clean_by_k, kf_prof = [0, 0], {}, {}, []
@@ -305,6 +305,20 @@ def main():
             gl = (p - y) / p.numel()
             bwd_bias_ms = timed(lambda: m.backward(gl, want_bias=True))
         log(f"with a bias table: forward graph {fwd_bias_ms:.1f} ms, backward {bwd_bias_ms}")
+        # the same with sigma and bias tables per 20x20-pixel region (Sec. IV-C)
+        ncell = m.set_sensor_cells(20)
+        sig_c = sigma.reshape(1, -1).repeat(ncell, 1).contiguous()
+        bias_c = bias.reshape(1, -1).repeat(ncell, 1).contiguous()
+        fwd_cell_ms = timed(lambda: m.infer(theta, sig_c, K, bias_table=bias_c))
+        bwd_cell_ms = None
+        if backward:
+            m.infer(theta, sig_c, K, keep_checkpoints=True, bias_table=bias_c)
+            p, _ = m.marginals()
+            gl = (p - y) / p.numel()
+            bwd_cell_ms = timed(lambda: m.backward(gl, want_bias=True))
+        m.set_sensor_cells(0)
+        log(f"with tables per 20x20-pixel region ({ncell}): forward graph {fwd_cell_ms:.1f} ms, "
+            f"backward {bwd_cell_ms}")
         # the accuracy metric of the inferred map over every pixel of the batch
         m.infer(theta, sigma, K)
         acc_ms = timed(lambda: m.accuracy())
@@ -433,6 +447,10 @@ def main():
                          "backward": None if bwd_ms is None else round(bwd_ms, 2),
                          "forward_graph_with_bias": None if fwd_bias_ms is None else round(fwd_bias_ms, 2),
                          "backward_with_bias_grad": None if bwd_bias_ms is None else round(bwd_bias_ms, 2),
+                         "forward_graph_with_20px_region_tables": (None if fwd_cell_ms is None
+                                                                   else round(fwd_cell_ms, 2)),
+                         "backward_with_20px_region_table_grads": (None if bwd_cell_ms is None
+                                                                   else round(bwd_cell_ms, 2)),
                          "accuracy_metric": None if acc_ms is None else round(acc_ms, 2),
                          "depth_messages": None if dd_ms is None else round(dd_ms, 2)},
         "map_accuracy": {"rule": "measurement inside the chord of the most likely surface's voxel (Sec. III-D)",

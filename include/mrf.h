@@ -166,7 +166,8 @@ int mrf_add_frames(mrf_ctx* ctx, int32_t n_frames, const float* depth, const dou
  * with prefix products of mu(o=0) and the division-free suffix form of
  * Eq. neg).  prior_logit: V floats, log(gamma_v / (1 - gamma_v)) per voxel
  * (copied).  sigma_table: 64 floats > 0, the learnt depth-indexed Gaussian
- * sigma of Eq. noise (copied).  keep_checkpoints != 0 stores, for
+ * sigma of Eq. noise (copied); after mrf_set_sensor_cells with cell_px > 0,
+ * 64 floats per pixel region (n_cells rows).  keep_checkpoints != 0 stores, for
  * mrf_backward, the ray->voxel messages of sweeps 1..K-1 ((sweeps - 1) * E
  * floats) and the voxel totals of sweeps 2..K ((sweeps - 1) * V FP32 pairs),
  * which together give every sweep's voxel->ray messages.  Errors: MRF_ESTATE
@@ -178,7 +179,7 @@ int mrf_infer(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
  * traversed depth d gives the predicted mean measurement d + b(d), so the
  * forward sensor model of Eq. noise becomes nu = N(Z; d + b(d), sigma(d)).
  * bias_table: 64 floats [m] on the same depth bins as sigma_table (device,
- * copied), or NULL for b = 0, which is mrf_infer exactly.  The incidence
+ * copied; one row per pixel region like sigma_table), or NULL for b = 0, which is mrf_infer exactly.  The incidence
  * (truncation of every ray 3 sigma past its measurement) is fixed at build
  * and does not depend on either table.  Errors as mrf_infer. */
 int mrf_infer_sensor(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
@@ -214,13 +215,14 @@ int mrf_marginals(mrf_ctx* ctx, float* p, float* logit, void* stream);
 /* Reverse pass through the K sweeps of the last mrf_infer (which must have
  * kept checkpoints).  dloss_dlogit: V floats, the gradient with respect to
  * the marginal log-odds (for BCE with logits: (p - y) / V).  Outputs
- * dprior_logit (V floats) and dsigma_table (64 floats); either may be NULL.
+ * dprior_logit (V floats) and dsigma_table (the sigma table's size: 64
+ * floats, or 64 per pixel region); either may be NULL.
  * Deterministic: no floating-point atomics.  Errors: MRF_ESTATE. */
 int mrf_backward(mrf_ctx* ctx, const float* dloss_dlogit, float* dprior_logit,
                  float* dsigma_table, void* stream);
 
-/* mrf_backward that also returns dbias_table (64 floats, device; may be
- * NULL), the gradient with respect to the bias table of the last inference
+/* mrf_backward that also returns dbias_table (the bias table's size, device;
+ * may be NULL), the gradient with respect to the bias table of the last inference
  * (zero table after plain mrf_infer).  With r = Z - d - b the residual about
  * the predicted mean, d g / d b = r / sigma^2 and d g / d sigma = r^2 / sigma^3
  * - 1 / sigma, g = log nu.  Deterministic like mrf_backward; dprior_logit and
@@ -345,6 +347,27 @@ int mrf_export_edges(const mrf_ctx* ctx, float* delta, uint8_t* bin, float* g,
  *                    (default), with tuned launch shapes. */
 enum { MRF_SCHED_PLAIN = 0, MRF_SCHED_GRAPH = 1 };
 int mrf_set_schedule(mrf_ctx* ctx, int32_t schedule);
+
+/* Per-pixel-region sensor tables (Sec. IV-C learns bias and noise for every
+ * 20 x 20 pixel neighbourhood and depth).  cell_px = 0 (the default): one
+ * 64-bin sigma table and one bias table serve every pixel.  cell_px > 0, a
+ * multiple of 4 (a 4 x 4 ray tile then lies in one region): the tables of
+ * mrf_infer, mrf_infer_sensor and mrf_infer_keyframe_avg, and the gradients of
+ * mrf_backward*, hold n_cells rows of 64 bins, row-major; pixel (u, v) of a
+ * W-wide image uses row (v / cell_px) * ceil(W / cell_px) + u / cell_px, and
+ * n_cells is the largest ceil(W / cell_px) * ceil(H / cell_px) over the built
+ * scenes (rows past a smaller image's regions are unused).  The setting stays
+ * across rebuilds; changing it discards the last inference.  *n_cells (may be
+ * NULL) receives the rows for the built scenes, 0 before a build.  The
+ * accuracy metric and the traversal's truncation use the build's analytic
+ * sigma and do not read the tables.  Errors: MRF_EINVAL for a negative
+ * cell_px or one that is not a multiple of 4, MRF_ERANGE when the tables
+ * would exceed 2^31 entries. */
+int mrf_set_sensor_cells(mrf_ctx* ctx, int32_t cell_px, int64_t* n_cells);
+
+/* The current region size (0: one table) and table rows (0 before a build);
+ * either pointer may be NULL. */
+int mrf_sensor_cells(const mrf_ctx* ctx, int32_t* cell_px, int64_t* n_cells);
 
 /* Diagnostic timing of the sweep kernels (not part of the method).  Runs
  * `reps` eager forward sweeps (voxel phase, then ray phase) on the messages

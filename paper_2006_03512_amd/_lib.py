@@ -20,7 +20,8 @@ SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backwar
            "mrf_strerror", "mrf_last_error", "mrf_profile_sweeps", "mrf_get_tuning", "mrf_set_tuning",
            "mrf_autotune", "mrf_infer_sensor", "mrf_backward_sensor", "mrf_accuracy", "mrf_generation",
            "mrf_backward_gen", "mrf_infer_keyframe_avg", "mrf_accuracy_static",
-           "mrf_accuracy_ex", "mrf_depth_distribution", "mrf_add_frames"]
+           "mrf_accuracy_ex", "mrf_depth_distribution", "mrf_add_frames", "mrf_set_sensor_cells",
+           "mrf_sensor_cells"]
 MAX_RAY_CLASSES = 32
 
 
@@ -103,6 +104,8 @@ def lib() -> C.CDLL:
         L.mrf_export_incidence.argtypes = [P, P, P, P, P, P, P, P]
         L.mrf_export_edges.argtypes = [P, P, P, P, P, P, P]
         L.mrf_set_schedule.argtypes = [P, I32]
+        L.mrf_set_sensor_cells.argtypes = [P, I32, C.POINTER(C.c_int64)]
+        L.mrf_sensor_cells.argtypes = [P, C.POINTER(I32), C.POINTER(C.c_int64)]
         L.mrf_profile_sweeps.argtypes = [P, I32, I32, C.POINTER(KernelTime), I32, C.POINTER(I32), P]
         L.mrf_get_tuning.argtypes = [P, C.POINTER(Tuning)]
         L.mrf_set_tuning.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]

@@ -460,29 +460,134 @@ __global__ __launch_bounds__(256) void sigma_grad_k(const float* __restrict__ gs
     }
 }
 
-// accumulators of the sigma and bias tables: glo[2 kBins] then ghi[2 kBins]
-__global__ void sigma_zero_k(unsigned long long* glo, long long* ghi)
+// sigma_grad_k with per-region tables: one block per tile (grid-stride).  The
+// tile's 16-slot steps are the same lane partition as sigma_grad_k's, summed
+// the same way into LDS accumulators of the tile's region row, which the block
+// then adds (entries it touched) to the row's global accumulators; integer
+// sums, so the result is bit-reproducible and, when every region holds the
+// same table, the regions' accumulators add up exactly to sigma_grad_k's.
+template <bool BIAS>
+__global__ __launch_bounds__(256) void sigma_grad_cells_k(const TileDev* __restrict__ tiles, int64_t T,
+                                                          const FrameDev* __restrict__ frames, int cp,
+                                                          int64_t n_ent, const float* __restrict__ gsum,
+                                                          const float* __restrict__ delta,
+                                                          const uint8_t* __restrict__ bin,
+                                                          const float* __restrict__ sigma,
+                                                          const float* __restrict__ bias,
+                                                          unsigned long long* __restrict__ glo,
+                                                          long long* __restrict__ ghi)
 {
-    if (threadIdx.x < 2 * kBins) {
-        glo[threadIdx.x] = 0;
-        ghi[threadIdx.x] = 0;
+    constexpr int NT = BIAS ? 2 : 1;
+    __shared__ unsigned long long slo[NT * kBins];
+    __shared__ long long shi[NT * kBins];
+    __shared__ double inv[kBins], inv2[kBins], inv3[kBins], mu[kBins];
+    for (int64_t ti = blockIdx.x; ti < T; ti += gridDim.x) {
+        const TileDev t = tiles[ti];
+        const int64_t row = tile_cell(t, frames, cp) * kBins;
+        __syncthreads();   // the previous tile's flush is done
+        if (threadIdx.x < kBins) {
+            for (int q = 0; q < NT; ++q) {
+                slo[q * kBins + threadIdx.x] = 0;
+                shi[q * kBins + threadIdx.x] = 0;
+            }
+            const double sg = (double)sigma[row + threadIdx.x];
+            inv[threadIdx.x] = 1.0 / sg;
+            inv2[threadIdx.x] = 1.0 / (sg * sg);
+            inv3[threadIdx.x] = 1.0 / (sg * sg * sg);
+            mu[threadIdx.x] = (double)bias[row + threadIdx.x];
+        }
+        __syncthreads();
+        for (int ch = threadIdx.x; ch < t.len; ch += blockDim.x) {
+            const int64_t e0 = t.base + 16 * (int64_t)ch;
+            float4 gv[4], dv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                gv[q] = *(const float4*)(gsum + e0 + 4 * q);
+                dv[q] = *(const float4*)(delta + e0 + 4 * q);
+            }
+            const uint4 bw = *(const uint4*)(bin + e0);
+            const uint32_t bwords[4] = {bw.x, bw.y, bw.z, bw.w};
+            int cur = -1;
+            double acc = 0.0, accb = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int b = (int)((bwords[j >> 2] >> (8 * (j & 3))) & 255u);
+                const float4 g4 = gv[j >> 2], d4 = dv[j >> 2];
+                const float gj = (j & 3) == 0 ? g4.x : (j & 3) == 1 ? g4.y : (j & 3) == 2 ? g4.z : g4.w;
+                const float dj = (j & 3) == 0 ? d4.x : (j & 3) == 1 ? d4.y : (j & 3) == 2 ? d4.z : d4.w;
+                if (b >= kBins) continue;
+                if (b != cur) {
+                    if (cur >= 0) {
+                        fx_add(&slo[cur], &shi[cur], acc);
+                        if (BIAS) fx_add(&slo[kBins + cur], &shi[kBins + cur], accb);
+                    }
+                    cur = b;
+                    acc = 0.0;
+                    accb = 0.0;
+                }
+                const double r = (double)dj - mu[b];
+                acc += (double)gj * (r * r * inv3[b] - inv[b]);
+                if (BIAS) accb += (double)gj * (r * inv2[b]);
+            }
+            if (cur >= 0) {
+                fx_add(&slo[cur], &shi[cur], acc);
+                if (BIAS) fx_add(&slo[kBins + cur], &shi[kBins + cur], accb);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < NT * kBins) {
+            const unsigned long long l = slo[threadIdx.x];
+            const long long h = shi[threadIdx.x];
+            if (l != 0 || h != 0) {
+                const int64_t at = (threadIdx.x / kBins) * n_ent + row + (threadIdx.x % kBins);
+                const unsigned long long old = atomicAdd(&glo[at], l);
+                const long long carry = (old + l < old) ? 1 : 0;
+                atomicAdd((unsigned long long*)&ghi[at], (unsigned long long)(h + carry));
+            }
+        }
     }
 }
 
-__global__ void sigma_final_k(const unsigned long long* glo, const long long* ghi, float* out, float* out_bias)
+// accumulators of the sigma and bias tables (n entries each): glo[2 n] then ghi[2 n]
+__global__ void sigma_zero_k(unsigned long long* glo, long long* ghi, int64_t n)
 {
-    const int i = threadIdx.x;
-    const auto fx = [&](int k) { return (float)((double)ghi[k] + (double)glo[k] * 5.421010862427522e-20); };
-    if (i < kBins && out) out[i] = fx(i);
-    if (i < kBins && out_bias) out_bias[i] = fx(kBins + i);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n; i += (int64_t)gridDim.x * blockDim.x) {
+        glo[i] = 0;
+        ghi[i] = 0;
+    }
+}
+
+__global__ void sigma_final_k(const unsigned long long* glo, const long long* ghi, int64_t n, float* out,
+                              float* out_bias)
+{
+    const auto fx = [&](int64_t k) { return (float)((double)ghi[k] + (double)glo[k] * 5.421010862427522e-20); };
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (out) out[i] = fx(i);
+        if (out_bias) out_bias[i] = fx(n + i);
+    }
 }
 
 hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_t s)
 {
+    const int64_t n = table_entries(c);
     unsigned long long* glo = (unsigned long long*)c->b_sigpart.p;
-    long long* ghi = (long long*)(glo + 2 * kBins);
-    hipLaunchKernelGGL(sigma_zero_k, dim3(1), dim3(2 * kBins), 0, s, glo, ghi);
-    if (c->S > 0) {
+    long long* ghi = (long long*)(glo + 2 * n);
+    const unsigned nb = (unsigned)((2 * n + 255) / 256 < 1024 ? (2 * n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(sigma_zero_k, dim3(nb), dim3(256), 0, s, glo, ghi, n);
+    if (c->S > 0 && c->cell_px > 0) {
+        ProfScope ps(c, KID_SIGMA, s);
+        const int64_t blocks = c->T < 65536 ? c->T : 65536;
+        if (dbias)
+            hipLaunchKernelGGL(sigma_grad_cells_k<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const TileDev*)c->b_tiles.p, c->T, (const FrameDev*)c->b_frames.p, c->cell_px, n,
+                               (const float*)c->b_gsum.p, (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p,
+                               (const float*)c->b_sigma.p, (const float*)c->b_bias.p, glo, ghi);
+        else
+            hipLaunchKernelGGL(sigma_grad_cells_k<false>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const TileDev*)c->b_tiles.p, c->T, (const FrameDev*)c->b_frames.p, c->cell_px, n,
+                               (const float*)c->b_gsum.p, (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p,
+                               (const float*)c->b_sigma.p, (const float*)c->b_bias.p, glo, ghi);
+    } else if (c->S > 0) {
         ProfScope ps(c, KID_SIGMA, s);
         int64_t blocks = (c->S / 16 + 255) / 256;
         if (blocks > SG_BLOCKS) blocks = SG_BLOCKS;
@@ -495,8 +600,8 @@ hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_
                                (const float*)c->b_gsum.p, (const float*)c->b_delta.p, (const uint8_t*)c->b_bin.p,
                                c->S, (const float*)c->b_sigma.p, (const float*)c->b_bias.p, glo, ghi);
     }
-    hipLaunchKernelGGL(sigma_final_k, dim3(1), dim3(64), 0, s, (const unsigned long long*)glo, (const long long*)ghi,
-                       dsigma, dbias);
+    hipLaunchKernelGGL(sigma_final_k, dim3(nb), dim3(256), 0, s, (const unsigned long long*)glo,
+                       (const long long*)ghi, n, dsigma, dbias);
     return hipGetLastError();
 }
 

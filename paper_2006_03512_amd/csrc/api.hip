@@ -62,6 +62,10 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     for (const auto& b : c->b_pair_desc) k.push_back((uint64_t)(uintptr_t)b.p);
     for (int i = 0; i < mrf::kVoxClasses; ++i) k.push_back((uint64_t)c->pair_cnt[i]);
     k.push_back((uint64_t)c->n_kf_vox);
+    k.push_back((uint64_t)c->cell_px);
+    k.push_back((uint64_t)c->n_cells);
+    k.push_back((uint64_t)(uintptr_t)c->b_frames.p);
+    k.push_back((uint64_t)(uintptr_t)c->b_scenes.p);
     return k;
 }
 
@@ -271,6 +275,57 @@ int mrf_set_schedule(mrf_ctx* c, int32_t schedule)
 }
 
 static void update_stats(mrf_ctx* c);
+static int64_t sensor_cells(const std::vector<SceneDev>& scenes, int cp);
+static hipError_t alloc_tables(mrf_ctx* c);
+
+int mrf_set_sensor_cells(mrf_ctx* c, int32_t cell_px, int64_t* n_cells)
+{
+    if (!c || cell_px < 0 || cell_px % kTileW != 0)
+        return fail(MRF_EINVAL, "mrf_set_sensor_cells: cell_px must be 0 or a positive multiple of 4");
+    HCK(hipSetDevice(c->device), "mrf_set_sensor_cells: hipSetDevice");
+    const int64_t n = sensor_cells(c->scenes_h, cell_px);
+    if (n * kBins >= (int64_t(1) << 31)) return fail(MRF_ERANGE, "mrf_set_sensor_cells: too many regions");
+    if (cell_px != c->cell_px) {
+        drop_graph(c);   // the captured potentials launch depends on the table layout
+        c->cell_px = cell_px;
+        c->inferred = c->have_ckpt = c->kf_inferred = 0;   // the next inference reads the new layout
+    }
+    c->n_cells = n;
+    if (!c->scenes_h.empty()) HCK(alloc_tables(c), "mrf_set_sensor_cells: alloc sensor tables");
+    if (n_cells) *n_cells = c->scenes_h.empty() ? 0 : n;
+    return MRF_OK;
+}
+
+int mrf_sensor_cells(const mrf_ctx* c, int32_t* cell_px, int64_t* n_cells)
+{
+    if (!c) return fail(MRF_EINVAL, "mrf_sensor_cells: null context");
+    if (cell_px) *cell_px = c->cell_px;
+    if (n_cells) *n_cells = c->scenes_h.empty() ? 0 : c->n_cells;
+    return MRF_OK;
+}
+
+// Rows of the sensor tables: 1, or with per-region tables the most regions of any
+// scene's image.
+static int64_t sensor_cells(const std::vector<SceneDev>& scenes, int cp)
+{
+    if (cp <= 0) return 1;
+    int64_t n = 1;
+    for (const SceneDev& d : scenes) {
+        const int64_t k = (int64_t)((d.W + cp - 1) / cp) * ((d.H + cp - 1) / cp);
+        if (k > n) n = k;
+    }
+    return n;
+}
+
+// sigma and bias tables, their gradient accumulators and a scratch output table
+static hipError_t alloc_tables(mrf_ctx* c)
+{
+    const size_t n = (size_t)table_entries(c);
+    hipError_t e = ensure(c->b_sigma, sizeof(float) * n);
+    if (e == hipSuccess) e = ensure(c->b_bias, sizeof(float) * n);
+    if (e == hipSuccess) e = ensure(c->b_sigpart, sigpart_bytes(c) + sizeof(float) * n);
+    return e;
+}
 
 int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p, void* stream)
 {
@@ -362,6 +417,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     c->kf = p->keyframe_average ? 1 : 0;
     c->n_pairs = c->n_kfx = c->n_kf_vox = 0;
     for (int k = 0; k < kVoxClasses; ++k) c->pair_cnt[k] = 0;
+    c->n_cells = sensor_cells(c->scenes_h, c->cell_px);
 
     HCK(ensure(c->b_scenes, sizeof(SceneDev) * c->scenes_h.size()), "mrf_build: alloc");
     HCK(ensure(c->b_frames, sizeof(FrameDev) * c->frames_h.size()), "mrf_build: alloc");
@@ -440,9 +496,7 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(ensure(c->b_thetabar, vb), "mrf_build: alloc thetabar");
     HCK(ensure(c->b_theta2, 2 * vb), "mrf_build: alloc theta pairs");
     HCK(ensure(c->b_tbar, 3 * 2 * vb), "mrf_build: alloc voxel sums");
-    HCK(ensure(c->b_sigma, sizeof(float) * kBins), "mrf_build: alloc sigma");
-    HCK(ensure(c->b_bias, sizeof(float) * kBins), "mrf_build: alloc bias");
-    HCK(ensure(c->b_sigpart, kSigPartBytes + sizeof(float) * kBins), "mrf_build: alloc table partials");
+    HCK(alloc_tables(c), "mrf_build: alloc sensor tables");
 
     // every slot is written: edges by the traversal, the rest as padding (no voxel,
     // no bin, sort key past every voxel)
@@ -712,11 +766,11 @@ int mrf_infer_sensor(mrf_ctx* c, const float* prior_logit, const float* sigma_ta
         }
     }
     HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer: copy prior");
-    HCK(launch_copy((float*)c->b_sigma.p, sigma_table, kBins, s), "mrf_infer: copy sigma");
+    HCK(launch_copy((float*)c->b_sigma.p, sigma_table, table_entries(c), s), "mrf_infer: copy sigma");
     if (bias_table)
-        HCK(launch_copy((float*)c->b_bias.p, bias_table, kBins, s), "mrf_infer: copy bias");
+        HCK(launch_copy((float*)c->b_bias.p, bias_table, table_entries(c), s), "mrf_infer: copy bias");
     else
-        HCK(launch_fill((float*)c->b_bias.p, 0.0f, kBins, s), "mrf_infer: zero bias");
+        HCK(launch_fill((float*)c->b_bias.p, 0.0f, table_entries(c), s), "mrf_infer: zero bias");
     if (c->schedule == MRF_SCHED_PLAIN) {
         HCK(enqueue_forward(c, sweeps, keep, true, s), "mrf_infer: sweeps");
     } else {
@@ -765,11 +819,11 @@ int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* si
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_infer_keyframe_avg: hipSetDevice");
     HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer_keyframe_avg: copy prior");
-    HCK(launch_copy((float*)c->b_sigma.p, sigma_table, kBins, s), "mrf_infer_keyframe_avg: copy sigma");
+    HCK(launch_copy((float*)c->b_sigma.p, sigma_table, table_entries(c), s), "mrf_infer_keyframe_avg: copy sigma");
     if (bias_table)
-        HCK(launch_copy((float*)c->b_bias.p, bias_table, kBins, s), "mrf_infer_keyframe_avg: copy bias");
+        HCK(launch_copy((float*)c->b_bias.p, bias_table, table_entries(c), s), "mrf_infer_keyframe_avg: copy bias");
     else
-        HCK(launch_fill((float*)c->b_bias.p, 0.0f, kBins, s), "mrf_infer_keyframe_avg: zero bias");
+        HCK(launch_fill((float*)c->b_bias.p, 0.0f, table_entries(c), s), "mrf_infer_keyframe_avg: zero bias");
     if (c->schedule == MRF_SCHED_PLAIN) {
         HCK(enqueue_forward_kf(c, sweeps, true, s), "mrf_infer_keyframe_avg: sweeps");
     } else {
@@ -1118,7 +1172,7 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
                                        s);
         }
         if (e == hipSuccess)
-            e = launch_sigma_grad(c, (float*)((char*)c->b_sigpart.p + kSigPartBytes), nullptr, s);
+            e = launch_sigma_grad(c, (float*)((char*)c->b_sigpart.p + sigpart_bytes(c)), nullptr, s);
     }
     c->prof = nullptr;
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -264,6 +264,11 @@ struct mrf_ctx {
     mrf::BuildDev bp{};
     int keep_chords = 0;
 
+    // sensor tables (Sec. IV-C): one 64-bin row, or with cell_px > 0 one row per
+    // cell_px x cell_px pixel region of the frame (n_cells rows)
+    int32_t cell_px = 0;
+    int64_t n_cells = 1;
+
     // buffers (raw device pointers into `bufs`)
     mrf::DevBuf b_scenes, b_frames, b_counts, b_rowptr, b_col, b_delta, b_bin, b_tin, b_tout,
         b_g, b_lam, b_ell, b_vedge, b_vptr, b_theta, b_L, b_thetabar, b_sigma, b_bias, b_ckpt,
@@ -421,10 +426,12 @@ hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
 // adjoint_kernels.hip
 hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* lambar, float* gsum, bool first,
                               hipStream_t s);
-// d loss / d sigma (64) and, when dbias is not null, d loss / d bias (64) from
-// the accumulated d loss / d g; b_sigpart holds the 2 x 2 x 64 fixed-point
-// accumulators (kSigPartBytes), scratch past them is free for callers.
-constexpr size_t kSigPartBytes = sizeof(double) * 4 * kBins;
+// d loss / d sigma and, when dbias is not null, d loss / d bias (a table entry
+// each, table_entries(c)) from the accumulated d loss / d g; b_sigpart holds
+// the 2 x 2 x entries fixed-point accumulators (sigpart_bytes), scratch past
+// them is free for callers.
+inline int64_t table_entries(const mrf_ctx* c) { return c->n_cells * kBins; }
+inline size_t sigpart_bytes(const mrf_ctx* c) { return sizeof(double) * 4 * (size_t)table_entries(c); }
 hipError_t launch_sigma_grad(mrf_ctx* c, float* dsigma, float* dbias, hipStream_t s);
 // Accuracy metric (Sec. III-D) of the map `logit` over every pixel of the built
 // scenes; counts: 2 per scene (evaluated, accurate), zeroed here.  Needs

@@ -132,6 +132,55 @@ __global__ __launch_bounds__(256) void potentials_k(const float* __restrict__ de
     }
 }
 
+// potentials_k with per-region tables: one block per tile (grid-stride), the
+// region's row staged in LDS, the tile's 16 len slots in groups of 4 with the
+// same arithmetic as potentials_k.
+__global__ __launch_bounds__(256) void potentials_cells_k(const TileDev* __restrict__ tiles, int64_t T,
+                                                          const FrameDev* __restrict__ frames, int cp,
+                                                          const float* __restrict__ delta,
+                                                          const uint8_t* __restrict__ bin,
+                                                          const float* __restrict__ sigma,
+                                                          const float* __restrict__ bias, float* __restrict__ g)
+{
+    __shared__ float inv[kBins], cst[kBins], mu[kBins];
+    for (int64_t ti = blockIdx.x; ti < T; ti += gridDim.x) {
+        const TileDev t = tiles[ti];
+        const int64_t row = tile_cell(t, frames, cp) * kBins;
+        __syncthreads();   // the previous tile's readers are done
+        if (threadIdx.x < kBins) {
+            const float s = sigma[row + threadIdx.x];
+            inv[threadIdx.x] = 1.0f / s;
+            cst[threadIdx.x] = logf(s) + 0.91893853320467274f;
+            mu[threadIdx.x] = bias[row + threadIdx.x];
+        }
+        __syncthreads();
+        const int64_t g0 = t.base / 4, ng = 4 * (int64_t)t.len;
+        for (int64_t k = threadIdx.x; k < ng; k += blockDim.x) {
+            const int64_t gi = g0 + k;
+            const uint32_t bw = ((const uint32_t*)bin)[gi];
+            const float4 dv = ((const float4*)delta)[gi];
+            float out[4];
+            bool all = true;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int b = (int)((bw >> (8 * j)) & 255u);
+                const float dj = j == 0 ? dv.x : j == 1 ? dv.y : j == 2 ? dv.z : dv.w;
+                const int bb = b < kBins ? b : 0;
+                const float x = (dj - mu[bb]) * inv[bb];
+                out[j] = -0.5f * x * x - cst[bb];
+                all = all && b < kBins;
+            }
+            if (all) {
+                ((float4*)g)[gi] = make_float4(out[0], out[1], out[2], out[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (((bw >> (8 * j)) & 255u) < kBins) g[4 * gi + j] = out[j];
+            }
+        }
+    }
+}
+
 static unsigned grid_for(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -179,6 +228,14 @@ hipError_t launch_potentials(mrf_ctx* c, hipStream_t s)
 {
     if (c->S <= 0) return hipSuccess;
     ProfScope ps(c, KID_POT, s);
+    if (c->cell_px > 0) {
+        const int64_t blocks = c->T < 65536 ? c->T : 65536;
+        hipLaunchKernelGGL(potentials_cells_k, dim3((unsigned)blocks), dim3(256), 0, s, (const TileDev*)c->b_tiles.p,
+                           c->T, (const FrameDev*)c->b_frames.p, c->cell_px, (const float*)c->b_delta.p,
+                           (const uint8_t*)c->b_bin.p, (const float*)c->b_sigma.p, (const float*)c->b_bias.p,
+                           (float*)c->b_g.p);
+        return hipGetLastError();
+    }
     int64_t blocks = nblk(c->S / 4, 256 * kPotGroups);
     if (blocks > 4096) blocks = 4096;   // grid-stride over at most 16 blocks per CU
     hipLaunchKernelGGL(potentials_k, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)c->b_delta.p,

@@ -11,6 +11,16 @@
 
 namespace mrf {
 
+// Per-region sensor tables (Sec. IV-C): the row of a tile's rays is that of
+// their pixel region.  Region sides are multiples of 4 pixels, so a 4x4 tile
+// lies in one region, found from the tile's top-left pixel.
+__device__ __forceinline__ int64_t tile_cell(const TileDev& t, const FrameDev* __restrict__ frames, int cp)
+{
+    const int64_t pix = (int64_t)t.ray0 - frames[t.frame].ray_base;
+    const int v0 = (int)(pix / t.W), u0 = (int)(pix - (int64_t)v0 * t.W);
+    return (int64_t)(v0 / cp) * ((t.W + cp - 1) / cp) + u0 / cp;
+}
+
 // LDS word of (step k, tile lane i) for rays held IPL steps per lane: row k
 // of 16 words, the lane index XOR-ed with (k / IPL) mod 16.  Coalesced
 // staging (16 consecutive threads per step) still fills whole rows, and the

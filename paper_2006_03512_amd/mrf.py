@@ -165,18 +165,36 @@ class RayMRF:
             raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} elements")
         return x
 
+    def set_sensor_cells(self, cell_px: int) -> int:
+        """Per-pixel-region sensor tables (Sec. IV-C): with cell_px > 0 (a
+        multiple of 4) the sigma and bias tables hold 64 bins for every
+        cell_px x cell_px region (0: one table).  Returns the table rows for
+        the built scenes (0 before a build)."""
+        n = C.c_int64(0)
+        check(self._L.mrf_set_sensor_cells(self._h, int(cell_px), C.byref(n)), "mrf_set_sensor_cells")
+        return int(n.value)
+
+    @property
+    def table_entries(self) -> int:
+        """Entries of a sensor table for the built scenes: 64, or 64 per region."""
+        cp, n = C.c_int32(0), C.c_int64(0)
+        check(self._L.mrf_sensor_cells(self._h, C.byref(cp), C.byref(n)), "mrf_sensor_cells")
+        return N_BINS * max(int(n.value), 1)
+
     def infer(self, prior_logit, sigma_table, sweeps: int, keep_checkpoints: bool = False, stream=None,
               bias_table=None):
-        """K sweeps; bias_table (64, metres) is the learnt depth bias of the
-        sensor model (None: zero bias, the plain ``mrf_infer``)."""
+        """K sweeps; bias_table (metres, the sigma table's size) is the learnt
+        depth bias of the sensor model (None: zero bias, the plain
+        ``mrf_infer``)."""
         self._vec(prior_logit, self.n_voxels, "prior_logit")
-        self._vec(sigma_table, N_BINS, "sigma_table")
+        nt = self.table_entries
+        self._vec(sigma_table, nt, "sigma_table")
         keep = 1 if keep_checkpoints else 0
         if bias_table is None:
             check(self._L.mrf_infer(self._h, ptr(prior_logit), ptr(sigma_table), int(sweeps), keep,
                                     stream_handle(stream)), "mrf_infer")
         else:
-            self._vec(bias_table, N_BINS, "bias_table")
+            self._vec(bias_table, nt, "bias_table")
             check(self._L.mrf_infer_sensor(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
                                            int(sweeps), keep, stream_handle(stream)), "mrf_infer_sensor")
 
@@ -184,9 +202,10 @@ class RayMRF:
         """K sweeps with per-keyframe averaged messages (Sec. IV-A); needs a
         build with keyframe_average=True.  No reverse pass."""
         self._vec(prior_logit, self.n_voxels, "prior_logit")
-        self._vec(sigma_table, N_BINS, "sigma_table")
+        nt = self.table_entries
+        self._vec(sigma_table, nt, "sigma_table")
         if bias_table is not None:
-            self._vec(bias_table, N_BINS, "bias_table")
+            self._vec(bias_table, nt, "bias_table")
         check(self._L.mrf_infer_keyframe_avg(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
                                              int(sweeps), stream_handle(stream)), "mrf_infer_keyframe_avg")
 
@@ -210,9 +229,10 @@ class RayMRF:
         if a later infer or build replaced that inference."""
         self._vec(dloss_dlogit, self.n_voxels, "dloss_dlogit")
         dp = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device) if want_prior else None
-        ds = torch.empty(N_BINS, dtype=torch.float32, device=self.device) if want_sigma else None
+        nt = self.table_entries
+        ds = torch.empty(nt, dtype=torch.float32, device=self.device) if want_sigma else None
         if generation is not None:
-            db = torch.empty(N_BINS, dtype=torch.float32, device=self.device) if want_bias else None
+            db = torch.empty(nt, dtype=torch.float32, device=self.device) if want_bias else None
             check(self._L.mrf_backward_gen(self._h, C.c_uint64(int(generation)), ptr(dloss_dlogit), ptr(dp),
                                            ptr(ds), ptr(db), stream_handle(stream)), "mrf_backward_gen")
             return (dp, ds, db) if want_bias else (dp, ds)
@@ -220,7 +240,7 @@ class RayMRF:
             check(self._L.mrf_backward(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), stream_handle(stream)),
                   "mrf_backward")
             return dp, ds
-        db = torch.empty(N_BINS, dtype=torch.float32, device=self.device)
+        db = torch.empty(nt, dtype=torch.float32, device=self.device)
         check(self._L.mrf_backward_sensor(self._h, ptr(dloss_dlogit), ptr(dp), ptr(ds), ptr(db),
                                           stream_handle(stream)), "mrf_backward_sensor")
         return dp, ds, db
@@ -357,6 +377,7 @@ class MRFInfer(torch.autograd.Function):
         ctx.mrf = mrf
         ctx.generation = mrf.generation()   # a later forward on the same context invalidates this node
         ctx.has_bias = bias_table is not None
+        ctx.table_shape = sigma_table.shape
         return logit
 
     @staticmethod
@@ -365,4 +386,6 @@ class MRFInfer(torch.autograd.Function):
         out = ctx.mrf.backward(g.contiguous().float(), want_prior=ctx.needs_input_grad[1],
                                want_sigma=ctx.needs_input_grad[2], want_bias=want_bias,
                                generation=ctx.generation)
-        return None, out[0], out[1], None, (out[2] if want_bias else None)
+        ds = None if out[1] is None else out[1].view(ctx.table_shape)
+        db = out[2].view(ctx.table_shape) if want_bias else None
+        return None, out[0], ds, None, db
