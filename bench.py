@@ -37,8 +37,9 @@ WORKLOADS = {
     "c2": ("one 640x480 frame in a 5x5x3 m room, 100x100x60 grid at 0.05 m, 10 sweeps forward",
            10, False),
     "c1": ("one 64x48 frame, 64^3 grid at 0.05 m, 5 sweeps forward", 5, False),
-    "c5": ("8 independent rooms (grids 64^3 .. 400x400x150 at 0.05 .. 0.0125 m) batched in one "
-           "launch sequence, 10 sweeps forward + reverse pass; frame counts scaled by --c5-scale", 10, True),
+    "c5": ("8 independent rooms (grids 64^3 .. 400x400x150 at 0.05 .. 0.0125 m, 120, 20 and 6 x 10 frames) "
+           "batched in one launch sequence, 10 sweeps forward + reverse pass; the count pass trims frames of "
+           "the rooms with the most edges until the step fits --mem-frac of the GPU's memory", 10, True),
 }
 
 
@@ -69,7 +70,53 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_scene(name, frames=None, c5_scale=0.4):
+def trim_to_memory(m, scs, K, backward, mem_frac):
+    """The count pass decides: with B bytes per edge slot (the ten per-edge arrays of
+    the build and sweeps, 37 bytes, plus K - 1 checkpointed ray messages of 4 bytes
+    for the reverse pass) and the per-voxel and per-ray arrays, drop the last frame
+    of the room holding the most slots until the whole step fits mem_frac of the
+    GPU's memory.  Returns the trimmed scenes and a record of what was done."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+    slots, edges = m.count(scs)
+    per_slot = 37 + (4 * (K - 1) if backward else 0)
+    V = sum(x.grid.n_voxels for x in scs)
+    per_voxel = 4 * 3 + 8 + 24 + 8 + (8 * (K - 1) if backward else 8)
+    total_mem = torch.cuda.get_device_properties(0).total_memory
+    budget = mem_frac * total_mem
+    off = np.cumsum([0] + [x.n_frames for x in scs])
+    F = [x.n_frames for x in scs]
+
+    def need():
+        S = sum(int(slots[off[i]: off[i] + F[i]].sum()) for i in range(len(scs)))
+        R = sum(F[i] * x.depth[0].size for i, x in enumerate(scs))
+        return per_slot * S + per_voxel * V + 12 * R, S
+    while need()[0] > budget:
+        big = max(range(len(scs)), key=lambda i: (int(slots[off[i]: off[i] + F[i]].sum()) if F[i] > 1 else -1))
+        if F[big] <= 1:
+            break
+        F[big] -= 1
+    out = []
+    for x, f in zip(scs, F):
+        if f < x.n_frames:
+            ex = dict(x.extra)
+            if "clean_depth" in ex:
+                ex["clean_depth"] = ex["clean_depth"][:f].copy()
+            x = dataclasses.replace(x, depth=x.depth[:f].copy(), T_wc=x.T_wc[:f].copy(), extra=ex)
+        out.append(x)
+    nb, S = need()
+    rec = {"stated_frames": [int(x.n_frames) for x in scs], "frames": [int(f) for f in F],
+           "stated_slots": int(slots.sum()), "stated_edges": int(edges.sum()),
+           "slots": int(S), "edges": int(sum(int(edges[off[i]: off[i] + F[i]].sum()) for i in range(len(scs)))),
+           "bytes_per_slot": per_slot, "memory_budget_gb": round(budget / 1e9, 1),
+           "estimated_gb": round(nb / 1e9, 1), "stated_estimated_gb": round(
+               (per_slot * int(slots.sum()) + per_voxel * V + 12 * sum(x.depth.size for x in scs)) / 1e9, 1)}
+    return out, rec
+
+
+def make_scene(name, frames=None, c5_scale=1.0):
     """List of scenes of the workload (one scene except c5)."""
     from paper_2006_03512_amd import scenes
     if name in ("c3", "c4"):
@@ -169,7 +216,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of the sampled frames' rows the oracle runs on")
     ap.add_argument("--cpu-frames", type=int, default=1, help="frames of the batch the oracle runs on")
-    ap.add_argument("--c5-scale", type=float, default=0.4, help="frame-count scale of the c5 rooms")
+    ap.add_argument("--c5-scale", type=float, default=1.0,
+                    help="frame-count scale of the c5 rooms before the count pass trims them")
+    ap.add_argument("--mem-frac", type=float, default=0.8,
+                    help="c5: fraction of the GPU's memory the step may use (the count pass trims frames to fit)")
     ap.add_argument("--sparse-bricks", type=int, default=-1,
                     help="brick radius of a sparse grid (bricks around the measured points); -1: dense")
     ap.add_argument("--no-autotune", action="store_true",
@@ -223,6 +273,13 @@ def main():
         f"({time.perf_counter() - t:.1f} s to generate)")
 
     m = RayMRF(0)
+    trim = None
+    if args.workload == "c5":
+        scs, trim = trim_to_memory(m, scs, K, backward, args.mem_frac)
+        n_frames = sum(x.n_frames for x in scs)
+        log(f"count pass: stated frames {trim['stated_frames']} ({trim['stated_slots']} slots, "
+            f"~{trim['stated_estimated_gb']} GB), run with {trim['frames']} ({trim['slots']} slots, "
+            f"~{trim['estimated_gb']} GB of {trim['memory_budget_gb']} GB)")
     m.upload(scs)
     theta = torch.from_numpy(np.concatenate([x.prior_logit() for x in scs])).cuda()
     sigma = torch.from_numpy(sc.sigma_table.astype(np.float32)).cuda()
@@ -438,6 +495,8 @@ def main():
                    "max_voxel_degree": st.max_voxel_degree, "parallelism": "single GPU",
                    "grid_storage": ("dense" if args.sparse_bricks < 0
                                     else f"sparse bricks, radius {args.sparse_bricks}"),
+                   "frames_per_scene": [int(x.n_frames) for x in scs],
+                   "count_pass": trim,
                    "ray_len_log2_hist": st.ray_len_hist[:12],
                    "voxel_degree_log2_hist": st.voxel_degree_hist[:20]},
         "roofline": roofline,

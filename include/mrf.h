@@ -158,6 +158,18 @@ int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
  * MRF_ERANGE, MRF_ENOMEM, MRF_EHIP. */
 int mrf_add_frames(mrf_ctx* ctx, int32_t n_frames, const float* depth, const double* T_wc, void* stream);
 
+/* The count pass of mrf_build alone (the traversal of Sec. IV-A counts each
+ * ray's voxels; no incidence, potentials or message arrays are made): for
+ * every frame of the batch, scenes in order and their frames in order, the
+ * edge slots it would occupy (edges plus the padding of its 4 x 4 tiles:
+ * per-edge memory is proportional to slots) and its edges.  frame_slots and
+ * frame_edges are host arrays of the batch's total frame count (either may be
+ * NULL, not both).  A caller sizes a batch to its memory with it before
+ * building.  Arguments and errors as mrf_build; the context is left without a
+ * graph (mrf_infer needs a new mrf_build). */
+int mrf_count(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* params,
+              int64_t* frame_slots, int64_t* frame_edges, void* stream);
+
 /* Run `sweeps` flooding sweeps of loopy sum-product BP (Sec. III-B/C, IV-A)
  * from uniform ray messages.  One sweep sends every voxel->ray message
  * (Eq. node_to_factor: the prior times every other ray's message, formed as

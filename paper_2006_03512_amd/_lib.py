@@ -21,7 +21,7 @@ SYMBOLS = ["mrf_create", "mrf_build", "mrf_infer", "mrf_marginals", "mrf_backwar
            "mrf_autotune", "mrf_infer_sensor", "mrf_backward_sensor", "mrf_accuracy", "mrf_generation",
            "mrf_backward_gen", "mrf_infer_keyframe_avg", "mrf_accuracy_static",
            "mrf_accuracy_ex", "mrf_depth_distribution", "mrf_add_frames", "mrf_set_sensor_cells",
-           "mrf_sensor_cells"]
+           "mrf_sensor_cells", "mrf_count"]
 MAX_RAY_CLASSES = 32
 
 
@@ -98,6 +98,7 @@ def lib() -> C.CDLL:
         L.mrf_accuracy_ex.argtypes = [P, P, C.c_double, P, C.c_double, P, P, P, P]
         L.mrf_depth_distribution.argtypes = [P, P, P, P, P]
         L.mrf_add_frames.argtypes = [P, I32, P, P, P]
+        L.mrf_count.argtypes = [P, P, I32, C.POINTER(BuildParams), P, P, P]
         L.mrf_generation.argtypes = [P, C.POINTER(C.c_uint64)]
         L.mrf_backward_gen.argtypes = [P, C.c_uint64, P, P, P, P, P]
         L.mrf_stats.argtypes = [P, C.POINTER(Stats)]

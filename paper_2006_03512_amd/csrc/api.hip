@@ -327,7 +327,10 @@ static hipError_t alloc_tables(mrf_ctx* c)
     return e;
 }
 
-int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p, void* stream)
+// mrf_build, or with frame_slots / frame_edges (host, one entry per frame) its
+// count pass alone: the per-frame slot and edge counts, and no graph.
+static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p,
+                      void* stream, int64_t* frame_slots, int64_t* frame_edges)
 {
     if (!c || !scenes || !p || n_scenes < 1) return fail(MRF_EINVAL, "mrf_build: null argument or no scenes");
     if (p->min_ray_voxels < 2) return fail(MRF_EINVAL, "mrf_build: min_ray_voxels must be >= 2");
@@ -465,6 +468,22 @@ int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
     HCK(hipMemcpyAsync(&S, (int64_t*)c->b_tbase.p + T, sizeof(int64_t), hipMemcpyDeviceToHost, s),
         "mrf_build: read S");
     HCK(hipStreamSynchronize(s), "mrf_build: sync");
+    if (frame_slots || frame_edges) {
+        // count only: per-frame slots and edges, and the context keeps no graph
+        c->S = S;
+        const size_t nf = c->frames_h.size();
+        HCK(ensure(c->b_export, 2 * sizeof(int64_t) * nf), "mrf_count: alloc");
+        HCK(launch_frame_counts(c, (int64_t*)c->b_export.p, s), "mrf_count: per-frame counts");
+        std::vector<int64_t> h(2 * nf);
+        HCK(hipMemcpyAsync(h.data(), c->b_export.p, 2 * sizeof(int64_t) * nf, hipMemcpyDeviceToHost, s),
+            "mrf_count: read counts");
+        HCK(hipStreamSynchronize(s), "mrf_count: sync");
+        for (size_t f = 0; f < nf; ++f) {
+            if (frame_slots) frame_slots[f] = h[2 * f];
+            if (frame_edges) frame_edges[f] = h[2 * f + 1];
+        }
+        return MRF_OK;
+    }
     if (S >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_build: 2^32 or more edge slots");
     c->S = S;
 
@@ -558,6 +577,18 @@ static void update_stats(mrf_ctx* c)
     st.sweeps_done = 0;
     st.have_checkpoints = 0;
     st.n_keyframe_pairs = c->n_pairs;
+}
+
+int mrf_build(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p, void* stream)
+{
+    return build_impl(c, scenes, n_scenes, p, stream, nullptr, nullptr);
+}
+
+int mrf_count(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p,
+              int64_t* frame_slots, int64_t* frame_edges, void* stream)
+{
+    if (!frame_slots && !frame_edges) return fail(MRF_EINVAL, "mrf_count: no output");
+    return build_impl(c, scenes, n_scenes, p, stream, frame_slots, frame_edges);
 }
 
 // Grows b to hold `need` bytes, keeping its first `keep` bytes; a buffer that has

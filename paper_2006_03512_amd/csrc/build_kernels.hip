@@ -1656,6 +1656,31 @@ hipError_t export_canonical_edges(const mrf_ctx* c, const void* in_slots, void* 
 }
 
 
+// ============================================================== per-frame counts
+
+__global__ void frame_counts_k(const FrameDev* __restrict__ frames, const SceneDev* __restrict__ scenes, int nf,
+                               const int64_t* __restrict__ tbase, const int64_t* __restrict__ rowptr,
+                               int64_t* __restrict__ out)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const FrameDev fr = frames[f];
+    const SceneDev& sd = scenes[fr.scene];
+    const int64_t nt = (int64_t)fr.ntx * ((sd.H + kTileW - 1) / kTileW);
+    const int64_t hw = (int64_t)sd.W * sd.H;
+    out[2 * f] = tbase[fr.tile_base + nt] - tbase[fr.tile_base];
+    out[2 * f + 1] = rowptr[fr.ray_base + hw] - rowptr[fr.ray_base];
+}
+
+hipError_t launch_frame_counts(const mrf_ctx* c, int64_t* out, hipStream_t s)
+{
+    if (c->n_frames <= 0) return hipSuccess;
+    hipLaunchKernelGGL(frame_counts_k, dim3((unsigned)cdiv(c->n_frames, 256)), dim3(256), 0, s,
+                       (const FrameDev*)c->b_frames.p, (const SceneDev*)c->b_scenes.p, c->n_frames,
+                       (const int64_t*)c->b_tbase.p, (const int64_t*)c->b_rowptr.p, out);
+    return hipGetLastError();
+}
+
 // ============================================================== accuracy metric
 
 // Sec. III-D: a voxel is a region of constant occlusion density alpha, chosen

@@ -356,6 +356,9 @@ hipError_t ensure(DevBuf& b, size_t bytes);
 // the count and emit passes over frames [f0, f0 + nf) (nf < 0: to the last frame)
 hipError_t launch_trace_count(mrf_ctx* c, hipStream_t s, int f0 = 0, int nf = -1);
 hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s, int f0 = 0, int nf = -1);
+// per frame f: out[2 f] = its edge slots, out[2 f + 1] = its edges (after the count
+// pass and the tile bases)
+hipError_t launch_frame_counts(const mrf_ctx* c, int64_t* out, hipStream_t s);
 hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t tmp_bytes,
                               hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);

@@ -106,16 +106,19 @@ class RayMRF:
         self._params = p0
         self._frames_built = False   # the context still points at the previous upload's frames
 
+    def _build_params(self, keep_chords, keyframe_average, reserve_frames):
+        p0 = self._params
+        return _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
+                                p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0,
+                                1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0,
+                                1 if getattr(p0, "skip_empty_bricks", 0) else 0, int(reserve_frames))
+
     def build_resident(self, keep_chords: bool = False, stream=None, keyframe_average: bool = False,
                        reserve_frames: int = 0):
         """(Re)build the ray MRF from the uploaded frames; keyframe_average
         prepares ``infer_keyframe_avg`` (Sec. IV-A); reserve_frames sizes the
         buffers for that many later ``add_frames`` frames of the last scene."""
-        p0 = self._params
-        bp = _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
-                              p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0,
-                              1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0,
-                              1 if getattr(p0, "skip_empty_bricks", 0) else 0, int(reserve_frames))
+        bp = self._build_params(keep_chords, keyframe_average, reserve_frames)
         with torch.cuda.device(self.device):
             check(self._L.mrf_build(self._h, self._arr, len(self._arr), C.byref(bp),
                                     stream_handle(stream)), "mrf_build")
@@ -139,6 +142,20 @@ class RayMRF:
         st = self.stats()
         self.n_voxels, self.n_edges, self.n_rays = st.n_voxels, st.n_edges, st.n_rays
         return st
+
+    def count(self, scenes, stream=None):
+        """The build's count pass alone: per frame of the batch (scenes in
+        order), (edge slots, edges) as two int64 numpy arrays; no graph is
+        kept."""
+        self.upload(scenes)
+        nf = sum(s.n_frames for s in (scenes if isinstance(scenes, (list, tuple)) else [scenes]))
+        slots, edges = np.zeros(nf, np.int64), np.zeros(nf, np.int64)
+        bp = self._build_params(False, False, 0)
+        with torch.cuda.device(self.device):
+            check(self._L.mrf_count(self._h, self._arr, len(self._arr), C.byref(bp),
+                                    slots.ctypes.data_as(C.c_void_p), edges.ctypes.data_as(C.c_void_p),
+                                    stream_handle(stream)), "mrf_count")
+        return slots, edges
 
     def build(self, scenes, keep_chords: bool = False, stream=None, keyframe_average: bool = False,
               reserve_frames: int = 0):
