@@ -70,8 +70,8 @@ typedef struct {
 /* One scene: n_frames depth images of one camera model into one grid. */
 typedef struct {
     int32_t n_frames, reserved;
-    const float* depth;     /* device, n_frames*H*W z-depth [m]; 0 or NaN = no return */
-    const double* T_wc;     /* device, n_frames*16 row-major camera->world (OpenCV axes) */
+    const float* depth;     /* host or device, n_frames*H*W z-depth [m]; 0 or NaN = no return */
+    const double* T_wc;     /* host or device, n_frames*16 row-major camera->world (OpenCV axes) */
     mrf_intrinsics K;
     mrf_grid grid;
 } mrf_scene;
@@ -138,7 +138,11 @@ int mrf_create(mrf_ctx** out);
  * traversal named in Sec. IV-A), ray->voxel CSR in edge order, voxel->ray CSR
  * by a stable device radix sort (edges ascending inside a voxel), per-edge
  * voxel depth (chord midpoint) and sigma-table bin.  Depth and pose arrays
- * must stay valid until the call returns.  Errors: MRF_EINVAL (bad shapes,
+ * may be device memory or host memory (queried with hipPointerGetAttributes):
+ * device arrays and pinned, mapped host arrays are read in place and must stay
+ * valid while the build is in use (mrf_accuracy and rebuilds read them);
+ * pageable host arrays are copied into the context, which keeps the copies
+ * until the next mrf_build, and need only stay valid until the call returns.  Errors: MRF_EINVAL (bad shapes,
  * min_ray_voxels < 2, more than 65535 frames), MRF_ERANGE (total edges >= 2^32
  * or a ray longer than 2048 voxels; with keyframe_average, per-keyframe
  * message buffers of 2^32 or more entries), MRF_ENOMEM, MRF_EHIP. */
@@ -151,8 +155,7 @@ int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
  * (same ray ids, slots and voxel -> ray lists), but only the new frames are
  * traversed and sorted; their entries are merged behind each voxel's existing
  * ones.  depth: n_frames * H * W floats and T_wc: n_frames * 16 doubles
- * (device), the last scene's camera model; they must stay valid as long as
- * the scene's others (mrf_accuracy reads them).  The last inference is
+ * (host or device, as in mrf_build), the last scene's camera model.  The last inference is
  * discarded.  Errors: MRF_ESTATE before mrf_build, MRF_EINVAL for a sparse grid
  * (its bricks depend on every frame: rebuild) or more than 65535 frames,
  * MRF_ERANGE, MRF_ENOMEM, MRF_EHIP. */

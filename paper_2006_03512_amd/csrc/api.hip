@@ -256,6 +256,7 @@ void mrf_destroy(mrf_ctx* c)
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export,
                      &c->b_kfw, &c->b_kflen, &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox};
     for (DevBuf* b : all) free_buf(*b);
+    for (auto& b : c->b_host_in) free_buf(b);
     for (auto& b : c->b_pair_desc) free_buf(b);
     for (auto& b : c->b_ray_list) free_buf(b);
     for (auto& b : c->b_vox_list) free_buf(b);
@@ -327,6 +328,34 @@ static hipError_t alloc_tables(mrf_ctx* c)
     return e;
 }
 
+// Device address of an input array of `bytes` bytes: the array itself when it is
+// device memory (or host memory the device can address), otherwise a copy the
+// context keeps (in b_host_in, until the next mrf_build).
+static hipError_t device_view(mrf_ctx* c, const void* p, size_t bytes, const void** out, hipStream_t s)
+{
+    hipPointerAttribute_t a{};
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e == hipSuccess && a.type == hipMemoryTypeDevice) {
+        *out = p;
+        return hipSuccess;
+    }
+    if (e == hipSuccess && a.type == hipMemoryTypeHost && a.devicePointer) {
+        *out = a.devicePointer;   // pinned and mapped
+        return hipSuccess;
+    }
+    hipGetLastError();   // pageable host memory is not known to HIP
+    DevBuf b;
+    e = ensure(b, bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.p, p, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        free_buf(b);
+        return e;
+    }
+    c->b_host_in.push_back(b);
+    *out = b.p;
+    return hipSuccess;
+}
+
 // mrf_build, or with frame_slots / frame_edges (host, one entry per frame) its
 // count pass alone: the per-frame slot and edge counts, and no graph.
 static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_build_params* p,
@@ -343,6 +372,10 @@ static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, con
 
     c->scenes_h.clear();
     c->frames_h.clear();
+    // copies of host inputs of the previous build, once this one has stopped using them
+    HCK(hipStreamSynchronize(s), "mrf_build: sync");
+    for (auto& b : c->b_host_in) free_buf(b);
+    c->b_host_in.clear();
     c->n_scenes = n_scenes;
     int64_t R = 0, V = 0, Vk = 0, Tn = 0, NB = 0;
     if (p->sparse_bricks && (p->brick_radius < 0 || p->brick_radius > 64))
@@ -376,13 +409,17 @@ static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, con
         NB += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
         const int64_t hw = (int64_t)d.W * d.H;
         if (hw > (int64_t(1) << 30)) return fail(MRF_ERANGE, "mrf_build: image too large");
+        const void* dv = nullptr;
+        const void* tv = nullptr;
+        HCK(device_view(c, sc.depth, sizeof(float) * (size_t)hw * sc.n_frames, &dv, s), "mrf_build: depth input");
+        HCK(device_view(c, sc.T_wc, sizeof(double) * 16 * (size_t)sc.n_frames, &tv, s), "mrf_build: pose input");
         if (hw > max_hw) max_hw = (int)hw;
         const int ntx = (d.W + kTileW - 1) / kTileW, nty = (d.H + kTileW - 1) / kTileW;
         if (ntx * nty > max_tpf) max_tpf = ntx * nty;
         for (int f = 0; f < sc.n_frames; ++f) {
             FrameDev fr{};
-            fr.depth = sc.depth + (size_t)f * hw;
-            fr.T = sc.T_wc + (size_t)f * 16;
+            fr.depth = (const float*)dv + (size_t)f * hw;
+            fr.T = (const double*)tv + (size_t)f * 16;
             fr.scene = i;
             fr.ntx = ntx;
             fr.ray_base = R + (int64_t)f * hw;
@@ -648,10 +685,14 @@ int mrf_add_frames(mrf_ctx* c, int32_t n_frames, const float* depth, const doubl
     const int64_t R0 = c->R, T0 = c->T, S0 = c->S, E0 = c->E;
     const int64_t R1 = R0 + hw * n_frames, T1 = T0 + (int64_t)ntx * nty * n_frames;
     if (R1 >= (int64_t(1) << 31)) return fail(MRF_ERANGE, "mrf_add_frames: too many rays (>= 2^31)");
+    const void* dv = nullptr;
+    const void* tv = nullptr;
+    HCK(device_view(c, depth, sizeof(float) * (size_t)hw * n_frames, &dv, s), "mrf_add_frames: depth input");
+    HCK(device_view(c, T_wc, sizeof(double) * 16 * (size_t)n_frames, &tv, s), "mrf_add_frames: pose input");
     for (int f = 0; f < n_frames; ++f) {
         FrameDev fr{};
-        fr.depth = depth + (size_t)f * hw;
-        fr.T = T_wc + (size_t)f * 16;
+        fr.depth = (const float*)dv + (size_t)f * hw;
+        fr.T = (const double*)tv + (size_t)f * 16;
         fr.scene = last;
         fr.ntx = ntx;
         fr.ray_base = R0 + (int64_t)f * hw;

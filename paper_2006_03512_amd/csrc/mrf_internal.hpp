@@ -281,6 +281,7 @@ struct mrf_ctx {
     int64_t n_bricks = 0;
     mrf::DevBuf b_tbar;   // reverse pass, float2 pairs: per-voxel sums of d/d lambda, the seed d/d L, a spare
     mrf::DevBuf b_export;     // temporaries of the canonical incidence export
+    std::vector<mrf::DevBuf> b_host_in;   // device copies of depth and pose arrays given in host memory
 
     // per-keyframe averaged messages (Sec. IV-A), built when requested
     int kf = 0;                   // the build made the pair structures

@@ -290,7 +290,7 @@ class RayMRF:
             self._vec(logit, self.n_voxels, "logit")
         code = torch.empty(self.n_rays, dtype=torch.int8, device=self.device)
         surf = torch.empty(self.n_rays, dtype=torch.float64, device=self.device)
-        counts = torch.empty((len(self._arr), 2), dtype=torch.int64, device=self.device)
+        counts = torch.empty((self.stats().n_scenes, 2), dtype=torch.int64, device=self.device)
         if ref_depth is None and tol_nsigma == 0.0:
             check(self._L.mrf_accuracy(self._h, ptr(logit), float(vis_min), ptr(code), ptr(surf), ptr(counts),
                                        stream_handle(stream)), "mrf_accuracy")
