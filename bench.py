@@ -72,16 +72,17 @@ def log(msg):
 
 def trim_to_memory(m, scs, K, backward, mem_frac):
     """The count pass decides: with B bytes per edge slot (the ten per-edge arrays of
-    the build and sweeps, 37 bytes, plus K - 1 checkpointed ray messages of 4 bytes
-    for the reverse pass) and the per-voxel and per-ray arrays, drop the last frame
-    of the room holding the most slots until the whole step fits mem_frac of the
-    GPU's memory.  Returns the trimmed scenes and a record of what was done."""
+    the build and sweeps, 37 bytes, the radix sort's tile histograms and offsets,
+    under one byte, plus K - 1 checkpointed ray messages of 4 bytes for the reverse
+    pass) and the per-voxel and per-ray arrays, drop the last frame of the room
+    holding the most slots until the whole step fits mem_frac of the GPU's memory.
+    Returns the trimmed scenes and a record of what was done."""
     import dataclasses
 
     import numpy as np
     import torch
     slots, edges = m.count(scs)
-    per_slot = 37 + (4 * (K - 1) if backward else 0)
+    per_slot = 38 + (4 * (K - 1) if backward else 0)
     V = sum(x.grid.n_voxels for x in scs)
     per_voxel = 4 * 3 + 8 + 24 + 8 + (8 * (K - 1) if backward else 8)
     total_mem = torch.cuda.get_device_properties(0).total_memory
@@ -229,6 +230,8 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="skip the sections outside the step and its roofline (bias table, accuracy by sweep "
                          "count, keyframe averaging, depth messages): for counter runs")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="time build + K sweeps + marginals without checkpoints or the reverse pass")
     ap.add_argument("--keyframe-average", action="store_true",
                     help="time per-keyframe averaged messages (Sec. IV-A) as the step: build + K sweeps + "
                          "marginals, no reverse pass")
@@ -256,6 +259,10 @@ def main():
         del src, dst
     desc, K, backward = WORKLOADS[args.workload]
     kf_step = args.keyframe_average
+    if args.forward_only and backward:
+        backward = False
+        desc = desc.replace(" + reverse pass (BCE vs ground truth)", "").replace(" + reverse pass", "")
+        desc += "; forward sweeps only (no checkpoints, no reverse pass)"
     if kf_step:   # the per-keyframe averaged scheme has no reverse pass
         backward = False
         desc = desc.replace(" + reverse pass (BCE vs ground truth)", "").replace(" + reverse pass", "")
@@ -490,7 +497,7 @@ def main():
                    "grid": [[x.grid.nx, x.grid.ny, x.grid.nz] for x in scs],
                    "voxel_m": [x.grid.voxel for x in scs],
                    "sweeps": K, "rays": st.n_rays, "edges": E, "voxels": st.n_voxels,
-                   "edge_slots": st.n_slots, "tiles": st.n_tiles,
+                   "edge_slots": st.n_slots, "tiles": st.n_tiles, "slot_groups": st.n_slot_groups,
                    "touched_voxels": st.n_touched_voxels, "max_ray_len": st.max_ray_len,
                    "max_voxel_degree": st.max_voxel_degree, "parallelism": "single GPU",
                    "grid_storage": ("dense" if args.sparse_bricks < 0

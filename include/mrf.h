@@ -116,6 +116,8 @@ typedef struct {
     int32_t reserve_frames;    /* >= 0: buffers sized for this many more frames of the last scene
                                   (mrf_add_frames), per-edge ones at 1.25 times the batch's mean
                                   edge slots per frame */
+    int32_t group_slots_log2;  /* 0 (= 32) or 12..32: a group of scenes holds fewer than 2^this
+                                  edge slots (see below); smaller values only for testing */
 } mrf_build_params;
 
 typedef struct {
@@ -128,6 +130,7 @@ typedef struct {
     int64_t n_slots;                /* edge slots in memory: edges plus tile padding */
     int64_t n_tiles;                /* 4x4-pixel ray tiles */
     int64_t n_keyframe_pairs;       /* (keyframe, voxel) pairs (builds with keyframe_average) */
+    int64_t n_slot_groups;          /* groups of scenes under 2^32 edge slots each (see mrf_build) */
 } mrf_stats_t;
 
 /* Create an empty context on the current HIP device.  *out receives it. */
@@ -142,10 +145,16 @@ int mrf_create(mrf_ctx** out);
  * device arrays and pinned, mapped host arrays are read in place and must stay
  * valid while the build is in use (mrf_accuracy and rebuilds read them);
  * pageable host arrays are copied into the context, which keeps the copies
- * until the next mrf_build, and need only stay valid until the call returns.  Errors: MRF_EINVAL (bad shapes,
- * min_ray_voxels < 2, more than 65535 frames), MRF_ERANGE (total edges >= 2^32
- * or a ray longer than 2048 voxels; with keyframe_average, per-keyframe
- * message buffers of 2^32 or more entries), MRF_ENOMEM, MRF_EHIP. */
+ * until the next mrf_build, and need only stay valid until the call returns.
+ * Edge slots (edges plus tile padding) and list positions are 64-bit; the
+ * voxel -> ray lists hold 32-bit slot ids relative to a group of whole
+ * scenes: the scenes in order form groups of fewer than 2^32 slots each (at
+ * most 8 groups), so a batch may hold more than 2^32 slots while every scene
+ * holds fewer (mrf_stats reports the groups).  Errors: MRF_EINVAL (bad shapes,
+ * min_ray_voxels < 2, more than 65535 frames), MRF_ERANGE (a scene of 2^32 or
+ * more edge slots, more than 8 groups, a ray longer than 2048 voxels; with
+ * keyframe_average, 2^32 or more slots in the batch or per-keyframe message
+ * buffers of 2^32 or more entries), MRF_ENOMEM, MRF_EHIP. */
 int mrf_build(mrf_ctx* ctx, const mrf_scene* scenes, int32_t n_scenes,
               const mrf_build_params* params, void* stream);
 

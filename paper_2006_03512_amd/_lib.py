@@ -46,7 +46,7 @@ class BuildParams(C.Structure):
                 ("table_dmax", C.c_double), ("min_ray_voxels", C.c_int32),
                 ("keep_chords", C.c_int32), ("sparse_bricks", C.c_int32), ("brick_radius", C.c_int32),
                 ("keyframe_average", C.c_int32), ("skip_empty_bricks", C.c_int32),
-                ("reserve_frames", C.c_int32)]
+                ("reserve_frames", C.c_int32), ("group_slots_log2", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -56,7 +56,8 @@ class Stats(C.Structure):
                 ("max_voxel_degree", C.c_int64), ("ray_len_hist", C.c_int64 * 16),
                 ("voxel_degree_hist", C.c_int64 * 24), ("fwd_bytes_per_sweep", C.c_double),
                 ("sweeps_done", C.c_int32), ("have_checkpoints", C.c_int32),
-                ("n_slots", C.c_int64), ("n_tiles", C.c_int64), ("n_keyframe_pairs", C.c_int64)]
+                ("n_slots", C.c_int64), ("n_tiles", C.c_int64), ("n_keyframe_pairs", C.c_int64),
+                ("n_slot_groups", C.c_int64)]
 
 
 class KernelTime(C.Structure):

@@ -64,6 +64,11 @@ std::vector<uint64_t> graph_key(const mrf_ctx* c, int K, int keep)
     k.push_back((uint64_t)c->n_kf_vox);
     k.push_back((uint64_t)c->cell_px);
     k.push_back((uint64_t)c->n_cells);
+    k.push_back((uint64_t)c->sg.n);
+    for (int g = 0; g < mrf::kMaxSlotGroups; ++g) {
+        k.push_back((uint64_t)c->sg.slot[g]);
+        k.push_back((uint64_t)c->sg.pos[g]);
+    }
     k.push_back((uint64_t)(uintptr_t)c->b_frames.p);
     k.push_back((uint64_t)(uintptr_t)c->b_scenes.p);
     return k;
@@ -455,6 +460,9 @@ static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, con
     c->n_bricks = NB;
     c->keep_chords = p->keep_chords ? 1 : 0;
     c->kf = p->keyframe_average ? 1 : 0;
+    if (p->group_slots_log2 != 0 && (p->group_slots_log2 < 12 || p->group_slots_log2 > 32))
+        return fail(MRF_EINVAL, "mrf_build: group_slots_log2 must be 0 or lie in [12, 32]");
+    c->group_log2 = p->group_slots_log2 ? p->group_slots_log2 : 32;
     c->n_pairs = c->n_kfx = c->n_kf_vox = 0;
     for (int k = 0; k < kVoxClasses; ++k) c->pair_cnt[k] = 0;
     c->n_cells = sensor_cells(c->scenes_h, c->cell_px);
@@ -521,8 +529,45 @@ static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, con
         }
         return MRF_OK;
     }
-    if (S >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_build: 2^32 or more edge slots");
     c->S = S;
+    {
+        // slot groups: runs of whole scenes with fewer than 2^group_log2 slots each; a
+        // voxel's list entries hold slots relative to their group's first slot
+        const size_t nf = c->frames_h.size();
+        HCK(ensure(c->b_export, 2 * sizeof(int64_t) * nf), "mrf_build: alloc");
+        HCK(launch_frame_counts(c, (int64_t*)c->b_export.p, s), "mrf_build: per-frame counts");
+        std::vector<int64_t> h(2 * nf);
+        HCK(hipMemcpyAsync(h.data(), c->b_export.p, 2 * sizeof(int64_t) * nf, hipMemcpyDeviceToHost, s),
+            "mrf_build: read counts");
+        HCK(hipStreamSynchronize(s), "mrf_build: sync");
+        std::vector<int64_t> scene_slots(c->n_scenes, 0);
+        for (size_t f = 0; f < nf; ++f) scene_slots[c->frames_h[f].scene] += h[2 * f];
+        const int64_t limit = int64_t(1) << c->group_log2;
+        SlotGroups g{};
+        c->group_scene.assign(1, 0);
+        int64_t acc = 0, first = 0;
+        for (int i = 0; i < c->n_scenes; ++i) {
+            if (scene_slots[i] >= limit)
+                return fail(MRF_ERANGE, "mrf_build: a scene with 2^" + std::to_string(c->group_log2) +
+                                            " or more edge slots");
+            if (acc + scene_slots[i] >= limit) {
+                if (g.n == kMaxSlotGroups)
+                    return fail(MRF_ERANGE, "mrf_build: more than " + std::to_string(kMaxSlotGroups) +
+                                                " groups of scenes under 2^" + std::to_string(c->group_log2) +
+                                                " edge slots");
+                g.slot[g.n] = first;
+                c->group_scene.push_back(i);
+                ++g.n;
+                acc = 0;
+            }
+            acc += scene_slots[i];
+            first += scene_slots[i];
+        }
+        if (c->kf && g.n > 1)
+            return fail(MRF_ERANGE, "mrf_build: per-keyframe averages need fewer than 2^" +
+                                        std::to_string(c->group_log2) + " edge slots");
+        c->sg = g;
+    }
 
     // per-slot arrays, with room for the reserved frames at 1.25 times the batch's mean
     // slots per frame
@@ -570,10 +615,17 @@ static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, con
     HCK(ensure(c->b_misc, sb2 > c->b_misc.cap ? sb2 : c->b_misc.cap), "mrf_build: alloc sort scan");
     HCK(radix_sort_pairs((const uint32_t*)c->b_g.p, (uint32_t*)c->b_lam.p, (uint32_t*)c->b_ell.p,
                          (uint32_t*)c->b_ellbar.p, (uint32_t*)c->b_gsum.p, (uint32_t*)c->b_lambar.p,
-                         (uint32_t*)c->b_vedge.p, S, bits_for(Vk), hist, offs, c->b_misc.p, c->b_misc.cap, s),
+                         (uint32_t*)c->b_vedge.p, S, bits_for(Vk), hist, offs, c->b_misc.p, c->b_misc.cap, s, c->sg),
         "mrf_build: radix sort");
     HCK(launch_vptr_from_sorted((const uint32_t*)c->b_lambar.p, S, Vk, (int64_t*)c->b_vptr.p, s),
         "mrf_build: vptr");
+    for (int g = 1; g < c->sg.n; ++g) {   // list position of each group's first key
+        const int64_t k0 = c->scenes_h[c->group_scene[g]].key_base;
+        HCK(hipMemcpyAsync(&c->sg.pos[g], (const int64_t*)c->b_vptr.p + k0, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           s),
+            "mrf_build: group positions");
+    }
+    HCK(hipStreamSynchronize(s), "mrf_build: sync");
     {
         hipError_t e = build_classes(c, s);
         if (e == hipErrorInvalidConfiguration) return fail(MRF_ERANGE, "mrf_build: " + g_err);
@@ -603,6 +655,7 @@ static void update_stats(mrf_ctx* c)
     st.n_kept_rays = 0;
     for (int k = 0; k < kRayClasses; ++k) st.n_kept_rays += c->ray_cls_rays[k];
     st.n_slots = c->S;
+    st.n_slot_groups = c->sg.n;
     st.n_tiles = c->T;
     st.n_touched_voxels = 0;
     for (int k = 0; k < kVoxClasses; ++k) st.n_touched_voxels += c->vox_cnt[k];
@@ -739,7 +792,10 @@ int mrf_add_frames(mrf_ctx* c, int32_t n_frames, const float* depth, const doubl
     int64_t S1 = 0;
     HCK(hipMemcpyAsync(&S1, (int64_t*)c->b_tbase.p + T1, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read S");
     HCK(hipStreamSynchronize(s), "mrf_add_frames: sync");
-    if (S1 >= (int64_t(1) << 32)) return fail(MRF_ERANGE, "mrf_add_frames: 2^32 or more edge slots");
+    const int64_t gb = c->sg.slot[c->sg.n - 1];   // the last scene's group
+    if (S1 - gb >= (int64_t(1) << c->group_log2))
+        return fail(MRF_ERANGE, "mrf_add_frames: the last scene's group would reach 2^" +
+                                    std::to_string(c->group_log2) + " edge slots");
     c->S = S1;
 
     // per-slot arrays: the existing slots are kept, the new ones written by the emit pass
@@ -788,8 +844,8 @@ int mrf_add_frames(mrf_ctx* c, int32_t n_frames, const float* depth, const doubl
     uint32_t* merged = (uint32_t*)c->b_lam.p;
     if (e == hipSuccess) e = launch_entry_keys(c, (const uint32_t*)c->b_vedge.p, E0, okeys, s);
     if (e == hipSuccess)
-        e = launch_merge_incidence((const uint32_t*)c->b_vedge.p, okeys, E0, nvals, nkeys, E1 - E0, (uint32_t)S0,
-                                   (int64_t*)c->b_vptr.p, nvptr, c->Vk + 1, merged, s);
+        e = launch_merge_incidence((const uint32_t*)c->b_vedge.p, okeys, E0, nvals, nkeys, E1 - E0,
+                                   (uint32_t)(S0 - gb), (int64_t*)c->b_vptr.p, nvptr, c->Vk + 1, merged, s);
     HCK(e, "mrf_add_frames: sort and merge");
     std::swap(c->b_vedge, c->b_lam);
     // padding entries past E (their key is past every voxel) keep the list's tail defined

@@ -763,7 +763,7 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
                                                      int shift, const int32_t* __restrict__ hist,
                                                      const int64_t* __restrict__ offs,
                                                      uint32_t* __restrict__ keys_out,
-                                                     uint32_t* __restrict__ vals_out)
+                                                     uint32_t* __restrict__ vals_out, const SlotGroups groups)
 {
     constexpr int NW = RS_T / 64;
     constexpr int WI = RS_IPT * 64;   // items per wave
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
         const int64_t i = wstart + r * 64 + lane;
         const int64_t ic = i < n ? i : n - 1;
         kr[r] = keys_in[ic];
-        vr[r] = vals_in ? vals_in[ic] : (uint32_t)i;
+        vr[r] = vals_in ? vals_in[ic] : (uint32_t)(i - group_slot_base_of_slot(groups, i));
     }
     const int64_t o0 = offs[tile * 256 + tid];
     const int64_t cnt = hist[tile * 256 + tid];
@@ -846,7 +846,7 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
 hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                             uint32_t* vals_b, uint32_t* keys_out, uint32_t* vals_out, int64_t n,
                             int key_bits, int32_t* hist, int64_t* offs, void* tmp, size_t tmp_bytes,
-                            hipStream_t s)
+                            hipStream_t s, const SlotGroups& groups)
 {
     if (n == 0) return hipSuccess;
     const int passes = key_bits <= 8 ? 1 : (key_bits + 7) / 8;
@@ -869,7 +869,7 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t*
         hipLaunchKernelGGL(rs_offsets_k, dim3((unsigned)nch), dim3(256), 0, s, (const int32_t*)hist, nb,
                            (const int64_t*)coff, (const int64_t*)dtot, offs);
         hipLaunchKernelGGL(rs_scatter_k, dim3((unsigned)nb), dim3(RS_T), 0, s, sk, sv, n, 8 * p,
-                           (const int32_t*)hist, (const int64_t*)offs, dk, dv);
+                           (const int32_t*)hist, (const int64_t*)offs, dk, dv, groups);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         sk = dk;
@@ -1293,10 +1293,11 @@ hipError_t build_classes(mrf_ctx* c, hipStream_t s)
 
 // brick-major key of the voxel of list entry j (col of its slot)
 __global__ void entry_keys_k(const SceneDev* __restrict__ scenes, int ns, const uint32_t* __restrict__ vedge,
-                             const int32_t* __restrict__ col, int64_t n, uint32_t* __restrict__ keys)
+                             const int32_t* __restrict__ col, int64_t n, uint32_t* __restrict__ keys,
+                             const SlotGroups sg)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-        keys[j] = voxel_to_key(scenes, ns, col[vedge[j]]);
+        keys[j] = voxel_to_key(scenes, ns, col[group_slot_base(sg, j) + vedge[j]]);
 }
 
 // old entry j of key k moves to j + new_vptr[k]; new entry i (slot s_new0 + vals[i],
@@ -1346,7 +1347,7 @@ hipError_t launch_entry_keys(const mrf_ctx* c, const uint32_t* vedge, int64_t n,
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(entry_keys_k, dim3(grid_of(n)), dim3(256), 0, s, (const SceneDev*)c->b_scenes.p, c->n_scenes,
-                       vedge, (const int32_t*)c->b_col.p, n, keys);
+                       vedge, (const int32_t*)c->b_col.p, n, keys, c->sg);
     return hipGetLastError();
 }
 

@@ -221,6 +221,38 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Edge slots in groups of whole scenes with fewer than 2^32 slots each (one group
+// unless the batch has 2^32 slots or more): a voxel's list entry holds its slot
+// less the first slot of its group, in 32 bits, and the entries of group g take
+// the list positions [pos[g], pos[g + 1]).  slot[0] = pos[0] = 0.
+constexpr int kMaxSlotGroups = 8;
+struct SlotGroups {
+    int32_t n = 1;
+    int64_t slot[kMaxSlotGroups] = {0};
+    int64_t pos[kMaxSlotGroups] = {0};
+};
+
+// First slot of the group of list position j (constant indices only, so the
+// table stays in kernel arguments).
+__host__ __device__ __forceinline__ int64_t group_slot_base(const SlotGroups& g, int64_t j)
+{
+    int64_t b = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxSlotGroups; ++k)
+        if (k < g.n && j >= g.pos[k]) b = g.slot[k];
+    return b;
+}
+
+// First slot of the group holding slot x.
+__host__ __device__ __forceinline__ int64_t group_slot_base_of_slot(const SlotGroups& g, int64_t x)
+{
+    int64_t b = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxSlotGroups; ++k)
+        if (k < g.n && x >= g.slot[k]) b = g.slot[k];
+    return b;
+}
+
 // Kernel launches that the profiler can time individually.
 enum KernelId {
     KID_VOX0 = 0,
@@ -268,6 +300,10 @@ struct mrf_ctx {
     // cell_px x cell_px pixel region of the frame (n_cells rows)
     int32_t cell_px = 0;
     int64_t n_cells = 1;
+
+    mrf::SlotGroups sg{};     // edge-slot groups of the voxel -> ray lists
+    int32_t group_log2 = 32;  // a group holds fewer than 2^group_log2 slots
+    std::vector<int> group_scene;   // first scene of each group
 
     // buffers (raw device pointers into `bufs`)
     mrf::DevBuf b_scenes, b_frames, b_counts, b_rowptr, b_col, b_delta, b_bin, b_tin, b_tout,
@@ -363,10 +399,13 @@ hipError_t launch_frame_counts(const mrf_ctx* c, int64_t* out, hipStream_t s);
 hipError_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t tmp_bytes,
                               hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
+// Stable LSD sort of (key, value) pairs; the values are the items' indices less
+// the first slot of their group under `groups` (one group: the indices).
 hipError_t radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* keys_out,
                             uint32_t* vals_out, int64_t n, int key_bits, int32_t* hist,
-                            int64_t* offs, void* tmp, size_t tmp_bytes, hipStream_t s);
+                            int64_t* offs, void* tmp, size_t tmp_bytes, hipStream_t s,
+                            const SlotGroups& groups = SlotGroups{});
 size_t radix_hist_entries(int64_t n);
 size_t radix_tmp_bytes(int64_t n);   // tmp bytes radix_sort_pairs needs for n items
 hipError_t launch_vptr_from_sorted(const uint32_t* sorted_keys, int64_t n, int64_t V, int64_t* vptr,

@@ -312,7 +312,8 @@ template <int NW, int IPL, int VPW, bool WT = false>
 __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev* __restrict__ vd, int64_t n,
                                                                    const uint32_t* __restrict__ vedge,
                                                                    const float* __restrict__ in, VoxOut out,
-                                                                   const float* __restrict__ w)
+                                                                   const float* __restrict__ w,
+                                                                   const SlotGroups sg)
 {
     static_assert(NW == 1 || VPW == 1, "several voxels per wave only with one wave per voxel");
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -336,9 +337,11 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
                 for (int k = 0; k < IPL; ++k) wt[u][k] = w[d[u].start + min(k * 64 + l, d[u].m - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < VPW; ++u)
+        for (int u = 0; u < VPW; ++u) {
+            const float* ing = in + group_slot_base(sg, d[u].start);
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) x[u][k] = in[e[u][k]];
+            for (int k = 0; k < IPL; ++k) x[u][k] = ing[e[u][k]];
+        }
 #pragma unroll
         for (int u = 0; u < VPW; ++u) {
             double a = 0.0;
@@ -354,7 +357,8 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
         const int64_t vi = lb;
         if (vi >= n) return;   // whole block
         const VoxDev d = vd[vi];
-        const double a = dgroup_sum_d<64>(vox_lane_sum<IPL, WT>(d.start, d.m, wv * 64 * IPL, vedge, in, w));
+        const double a = dgroup_sum_d<64>(
+            vox_lane_sum<IPL, WT>(d.start, d.m, wv * 64 * IPL, vedge, in + group_slot_base(sg, d.start), w));
         __shared__ double wsum[NW];
         if (l == 0) wsum[wv] = a;
         __syncthreads();
@@ -372,7 +376,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
 template <int G, int VPG, bool WT = false>
 __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ vd, int64_t n,
                                                      const uint32_t* __restrict__ vedge, const float* __restrict__ in,
-                                                     VoxOut out, const float* __restrict__ w)
+                                                     VoxOut out, const float* __restrict__ w, const SlotGroups sg)
 {
     constexpr int GPB = 256 / G;   // groups per block
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
         for (int u = 0; u < VPG; ++u) wt[u] = w[d[u].start + min(l, d[u].m - 1)];
     }
 #pragma unroll
-    for (int u = 0; u < VPG; ++u) x[u] = in[e[u]];
+    for (int u = 0; u < VPG; ++u) x[u] = in[group_slot_base(sg, d[u].start) + e[u]];
 #pragma unroll
     for (int u = 0; u < VPG; ++u) {
         const double t = WT ? (double)x[u] * (double)wt[u] : (double)x[u];
@@ -407,7 +411,7 @@ template <bool WT = false>
 __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict__ vd, int64_t n,
                                                         const uint32_t* __restrict__ vedge,
                                                         const float* __restrict__ in, VoxOut out,
-                                                        const float* __restrict__ w)
+                                                        const float* __restrict__ w, const SlotGroups sg)
 {
     __shared__ double wsum[16];
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
@@ -415,9 +419,10 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const VoxDev d = vd[b];
     const int nch = (d.m + kVoxChunk - 1) / kVoxChunk;
+    const float* ing = in + group_slot_base(sg, d.start);
     double a = 0.0;
     for (int c = wv; c < nch; c += 16)
-        a += vox_lane_sum<kVoxChunk / 64, WT>(d.start, d.m, c * kVoxChunk, vedge, in, w);
+        a += vox_lane_sum<kVoxChunk / 64, WT>(d.start, d.m, c * kVoxChunk, vedge, ing, w);
     a = dgroup_sum_d<64>(a);
     if (l == 0) wsum[wv] = a;
     __syncthreads();
@@ -431,8 +436,8 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
 // Class K of a segment list (voxels, or keyframe pairs with weights w) with n
 // work items described by desc.
 template <int K, bool WT>
-static void launch_seg_class(const VoxDev* desc, int64_t n, const uint32_t* vedge, const float* in, VoxOut out,
-                             const float* w, hipStream_t s)
+static void launch_seg_class(const VoxDev* desc, int64_t n, const uint32_t* vedge, const SlotGroups& sg,
+                             const float* in, VoxOut out, const float* w, hipStream_t s)
 {
     if (n <= 0) return;
     constexpr int NW = kVoxNW[K];
@@ -440,22 +445,22 @@ static void launch_seg_class(const VoxDev* desc, int64_t n, const uint32_t* vedg
         constexpr int G = kVoxCap[K];
         constexpr int VPG = kVoxVPW[K];
         hipLaunchKernelGGL((voxel_small_k<G, VPG, WT>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s, desc, n, vedge,
-                           in, out, w);
+                           in, out, w, sg);
     } else {
         constexpr int IPL = kVoxCap[K] / (64 * NW);
         constexpr int VPW = kVoxVPW[K];
         const unsigned blocks = NW == 1 ? nblk(n, 4 * VPW) : (unsigned)n;
         hipLaunchKernelGGL((voxel_k<NW, IPL, VPW, WT>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s, desc, n,
-                           vedge, in, out, w);
+                           vedge, in, out, w, sg);
     }
 }
 
 template <bool WT>
-static void launch_seg_chunked(const VoxDev* desc, int64_t n, const uint32_t* vedge, const float* in, VoxOut out,
-                               const float* w, hipStream_t s)
+static void launch_seg_chunked(const VoxDev* desc, int64_t n, const uint32_t* vedge, const SlotGroups& sg,
+                               const float* in, VoxOut out, const float* w, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(voxel_chunked_k<WT>, dim3((unsigned)n), dim3(1024), 0, s, desc, n, vedge, in, out, w);
+    hipLaunchKernelGGL(voxel_chunked_k<WT>, dim3((unsigned)n), dim3(1024), 0, s, desc, n, vedge, in, out, w, sg);
 }
 
 template <int K>
@@ -463,8 +468,8 @@ static void launch_voxel_class(mrf_ctx* c, const float* in, VoxOut out, hipStrea
 {
     if (c->vox_cnt[K] <= 0) return;
     ProfScope ps(c, KID_VOX0 + K, s);
-    launch_seg_class<K, false>((const VoxDev*)c->b_vox_desc[K].p, c->vox_cnt[K], (const uint32_t*)c->b_vedge.p, in,
-                               out, nullptr, s);
+    launch_seg_class<K, false>((const VoxDev*)c->b_vox_desc[K].p, c->vox_cnt[K], (const uint32_t*)c->b_vedge.p,
+                               c->sg, in, out, nullptr, s);
 }
 
 template <int... K>
@@ -480,7 +485,7 @@ hipError_t launch_voxel_phase(mrf_ctx* c, const float* in, VoxOut out, hipStream
     if (c->vox_cnt[kc] > 0) {
         ProfScope ps(c, KID_VOX0 + kc, s);
         launch_seg_chunked<false>((const VoxDev*)c->b_vox_desc[kc].p, c->vox_cnt[kc], (const uint32_t*)c->b_vedge.p,
-                                  in, out, nullptr, s);
+                                  c->sg, in, out, nullptr, s);
     }
     return hipGetLastError();
 }
@@ -499,9 +504,9 @@ static void pair_classes(std::integer_sequence<int, K...>, mrf_ctx* c, const flo
                          const float* w, hipStream_t s)
 {
     ((w ? launch_seg_class<K, true>((const VoxDev*)c->b_pair_desc[K].p, c->pair_cnt[K],
-                                    (const uint32_t*)c->b_vedge.p, in, out, w, s)
+                                    (const uint32_t*)c->b_vedge.p, c->sg, in, out, w, s)
         : launch_seg_class<K, false>((const VoxDev*)c->b_pair_desc[K].p, c->pair_cnt[K],
-                                     (const uint32_t*)c->b_vedge.p, in, out, nullptr, s)),
+                                     (const uint32_t*)c->b_vedge.p, c->sg, in, out, nullptr, s)),
      ...);
 }
 
@@ -513,9 +518,9 @@ hipError_t launch_pair_phase(mrf_ctx* c, const float* in, const float* w, double
     const int kc = kVoxClasses - 1;
     const VoxDev* d = (const VoxDev*)c->b_pair_desc[kc].p;
     if (w)
-        launch_seg_chunked<true>(d, c->pair_cnt[kc], (const uint32_t*)c->b_vedge.p, in, out, w, s);
+        launch_seg_chunked<true>(d, c->pair_cnt[kc], (const uint32_t*)c->b_vedge.p, c->sg, in, out, w, s);
     else
-        launch_seg_chunked<false>(d, c->pair_cnt[kc], (const uint32_t*)c->b_vedge.p, in, out, nullptr, s);
+        launch_seg_chunked<false>(d, c->pair_cnt[kc], (const uint32_t*)c->b_vedge.p, c->sg, in, out, nullptr, s);
     return hipGetLastError();
 }
 

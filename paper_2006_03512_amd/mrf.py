@@ -34,6 +34,7 @@ class GraphStats:
     n_slots: int
     n_tiles: int
     n_keyframe_pairs: int = 0
+    n_slot_groups: int = 1
 
 
 class RayMRF:
@@ -111,7 +112,8 @@ class RayMRF:
         return _lib.BuildParams(p0.z_min, p0.z_max, p0.trunc_nsigma, p0.trunc_c0, p0.trunc_c2,
                                 p0.trunc_min, p0.table_dmax, p0.min_ray_voxels, 1 if keep_chords else 0,
                                 1 if p0.sparse_bricks else 0, int(p0.brick_radius), 1 if keyframe_average else 0,
-                                1 if getattr(p0, "skip_empty_bricks", 0) else 0, int(reserve_frames))
+                                1 if getattr(p0, "skip_empty_bricks", 0) else 0, int(reserve_frames),
+                                int(getattr(p0, "group_slots_log2", 0)))
 
     def build_resident(self, keep_chords: bool = False, stream=None, keyframe_average: bool = False,
                        reserve_frames: int = 0):
@@ -169,7 +171,7 @@ class RayMRF:
         return GraphStats(st.n_scenes, st.n_rays, st.n_edges, st.n_voxels, st.n_kept_rays,
                           st.n_touched_voxels, st.max_ray_len, st.max_voxel_degree,
                           list(st.ray_len_hist), list(st.voxel_degree_hist), st.fwd_bytes_per_sweep,
-                          st.n_slots, st.n_tiles, st.n_keyframe_pairs)
+                          st.n_slots, st.n_tiles, st.n_keyframe_pairs, st.n_slot_groups)
 
     def set_schedule(self, schedule: str):
         code = {"plain": _lib.MRF_SCHED_PLAIN, "graph": _lib.MRF_SCHED_GRAPH}[schedule]

@@ -77,6 +77,7 @@ class BuildParams:
     sparse_bricks: int = 0      # 1: only 8^3 bricks around the measured points carry voxels
     brick_radius: int = 1       # bricks allocated around each measured point's brick
     skip_empty_bricks: int = 0  # 1: the traversal steps over unallocated bricks a brick at a time
+    group_slots_log2: int = 0   # 0: scenes grouped under 2^32 edge slots; 12..31 force smaller groups (tests)
 
 
 @dataclass

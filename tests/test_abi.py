@@ -61,6 +61,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(_lib.SceneC) == 8 + 16 + 40 + 48
     assert C.sizeof(_lib.BuildParams) == 7 * 8 + 32
     assert _lib.BuildParams.reserve_frames.offset == 7 * 8 + 24
+    assert _lib.BuildParams.group_slots_log2.offset == 7 * 8 + 28
+    assert _lib.Stats.n_slot_groups.offset == 8 * (8 + 16 + 24) + 8 + 8 + 24
     assert _lib.BuildParams.brick_radius.offset == 7 * 8 + 12
     assert _lib.BuildParams.keyframe_average.offset == 7 * 8 + 16
     assert _lib.BuildParams.skip_empty_bricks.offset == 7 * 8 + 20
