@@ -50,9 +50,9 @@ WORKLOADS = {
 # sources that kernel is compiled from hash to `src_sha256`; otherwise traffic
 # is reported as null.
 TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>",
-           "sources": ['adjoint_kernels.hip', 'dev_common.hpp', 'tile_lds.hpp'],
-           "src_sha256": "fb0927d45e4349b88443dc4dbc10dd33b027ec80e551940d13b9a7119a60f1ee",
-           "fetch_bytes": 1.2222e+10, "write_bytes": 4.666e+09}
+           "sources": ['adjoint_kernels.hip', 'dev_common.hpp', 'tile_lds.hpp', 'mrf_internal.hpp'],
+           "src_sha256": "c209f1c648f9903846bc8054433ed822a55e0beb7200682b1542450f9ba740d2",
+           "fetch_bytes": 1.2221e+10, "write_bytes": 4.666e+09}
 
 
 def src_sha256(files):
@@ -127,7 +127,7 @@ def make_scene(name, frames=None, c5_scale=1.0):
     return [scenes.make(name)]
 
 
-def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=1, single_rows=20, runs=3):
+def cpu_baseline(name, sc, sweeps, backward, row_frac, nf=1, single_rows=10, runs=5):
     """The FP64 oracle on a bounded sample of the same workload: the first nf
     frames of the batch, restricted to a band of their pixel rows (the other
     pixels carry no measurement), on every thread; then on one thread over a
@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--frames", type=int, default=None, help="override the batch size (c3/c4)")
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=float, default=1.0, help="fraction of the sampled frames' rows the oracle runs on")
+    ap.add_argument("--cpu-rows", type=float, default=0.4, help="fraction of the sampled frames' rows the oracle runs on")
     ap.add_argument("--cpu-frames", type=int, default=1, help="frames of the batch the oracle runs on")
     ap.add_argument("--c5-scale", type=float, default=1.0,
                     help="frame-count scale of the c5 rooms before the count pass trims them")
