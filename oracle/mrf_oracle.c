@@ -49,6 +49,8 @@
  *   or_backward                     -- reverse-mode derivative of the K
  *       unrolled sweeps (not in the paper: a project extension), written from
  *       the chain rule on the forward steps above.
+ *   or_backward_keyframe_avg        -- the same for the sweeps with per-keyframe
+ *       averaged messages.
  *
  * Messages to a binary variable are carried as log-odds
  *   lambda = log mu(o=1) - log mu(o=0)      (voxel -> ray, per edge)
@@ -595,14 +597,17 @@ static int or_voxel_phase_kf(const int64_t* vptr, const int64_t* vedge, int64_t 
 /* K sweeps of the flooding schedule with per-keyframe averaged messages;
  * ell = 0 initially, so the first sweep's lambda is theta.  Outputs as
  * or_infer: the last sweep's lambda and ell (E) and the beliefs L (V): the
- * prior plus one averaged message per keyframe.  Returns 0 or -1 (key). */
+ * prior plus one averaged message per keyframe; lam_hist (K*E, or NULL)
+ * receives every sweep's lambda.  Returns 0 or -1 (key). */
 int or_infer_keyframe_avg(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
                           int64_t V, int64_t E, const double* theta, const double* g, int32_t K,
-                          const int32_t* key, const double* w, double* lam_out, double* ell_out, double* L)
+                          const int32_t* key, const double* w, double* lam_out, double* ell_out, double* L,
+                          double* lam_hist)
 {
     memset(ell_out, 0, sizeof(double) * (size_t)E);
     for (int32_t k = 0; k < K; ++k) {
         if (or_voxel_phase_kf(vptr, vedge, V, theta, ell_out, key, w, lam_out, NULL)) return -1;
+        if (lam_hist) memcpy(lam_hist + (int64_t)k * E, lam_out, sizeof(double) * (size_t)E);
         or_ray_phase(row_ptr, R, lam_out, g, ell_out);
     }
     double* tmp = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
@@ -735,6 +740,99 @@ void or_backward(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const i
             theta_bar[v] += tot;
         }
         if (k > 0) or_voxel_phase(vptr, vedge, V, NULL, lambar, ellbar);
+    }
+    for (int32_t b = 0; b < n_tab; ++b) {
+        sigma_bar[b] = 0.0;
+        if (bias_bar) bias_bar[b] = 0.0;
+    }
+    for (int64_t e = 0; e < E; ++e) {
+        double s = sigma[bin[e]];
+        double r = delta[e] - (bias ? bias[bin[e]] : 0.0);
+        sigma_bar[bin[e]] += gbar[e] * (r * r / (s * s * s) - 1.0 / s);
+        if (bias_bar) bias_bar[bin[e]] += gbar[e] * (r / (s * s));
+    }
+    free(ellbar);
+    free(lambar);
+}
+
+/* Reverse pass through K sweeps with per-keyframe averaged messages
+ * (or_infer_keyframe_avg, with lam_hist).  The chain rule on its steps:
+ *   L_v = theta_v + sum over runs r of v of A_r(ell of the last sweep),
+ *   A_r = sum_{q in r} w_q ell_q / sum_{q in r} w_q  (the run's average),
+ *   lambda_e = theta_v + sum over the runs of v other than e's own of A_r,
+ * so with s_r = sum_{e in r} d/d lambda_e, the derivative reaching ell_q of
+ * the previous sweep is w_q / sum_r w times the sum of s over the OTHER runs
+ * of q's voxel (taken as before + after, never as a difference), every sweep
+ * adds sum_{e in v} d/d lambda_e to d/d theta_v, and the last sweep's ell_q
+ * receives w_q / sum_r w times d/d L_v.  The ray adjoint and the sensor-table
+ * gradients are those of or_backward (same arguments). */
+void or_backward_keyframe_avg(const int64_t* row_ptr, int64_t R, const int64_t* vptr, const int64_t* vedge,
+                              int64_t V, int64_t E, const double* g, int32_t K, const double* lam_hist,
+                              const double* Lbar, const double* delta, const int32_t* bin, const double* sigma,
+                              const double* bias, int32_t n_tab, const int32_t* key, const double* w,
+                              double* theta_bar, double* gbar, double* sigma_bar, double* bias_bar)
+{
+    double* ellbar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    double* lambar = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    memset(gbar, 0, sizeof(double) * (size_t)E);
+    /* the last sweep's ell reaches L through its run averages */
+    for (int64_t v = 0; v < V; ++v) {
+        theta_bar[v] = Lbar[v];
+        for (int64_t j = vptr[v]; j < vptr[v + 1];) {
+            int32_t f = key[vedge[j]];
+            int64_t q = j;
+            double sw = 0.0;
+            for (; q < vptr[v + 1] && key[vedge[q]] == f; ++q) sw += w[vedge[q]];
+            for (int64_t r = j; r < q; ++r) ellbar[vedge[r]] = w[vedge[r]] / sw * Lbar[v];
+            j = q;
+        }
+    }
+    int64_t mx = or_max_len(row_ptr, R);
+    for (int32_t k = K - 1; k >= 0; --k) {
+        const double* lam = lam_hist + (int64_t)k * E;
+#pragma omp parallel
+        {
+            double* wk = (double*)malloc(sizeof(double) * 12 * (size_t)mx);
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t r = 0; r < R; ++r) {
+                int64_t s = row_ptr[r], n = row_ptr[r + 1] - s;
+                if (n == 0) continue;
+                or_ray_adjoint(n, lam + s, g + s, ellbar + s, lambar + s, gbar + s, wk);
+            }
+            free(wk);
+        }
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t v = 0; v < V; ++v) {
+            int64_t s = vptr[v], e = vptr[v + 1];
+            double tot = 0.0;
+            for (int64_t j = s; j < e; ++j) tot += lambar[vedge[j]];
+            theta_bar[v] += tot;
+            if (k == 0) continue;
+            /* ell of the previous sweep: w_q / sum w times the other runs' sums */
+            double after = 0.0;
+            for (int64_t j = e - 1; j >= s;) {   /* after-sums parked in ellbar */
+                int32_t f = key[vedge[j]];
+                int64_t q = j;
+                double sr = 0.0;
+                for (; q >= s && key[vedge[q]] == f; --q) sr += lambar[vedge[q]];
+                for (int64_t r = j; r > q; --r) ellbar[vedge[r]] = after;
+                after += sr;
+                j = q;
+            }
+            double before = 0.0;
+            for (int64_t j = s; j < e;) {
+                int32_t f = key[vedge[j]];
+                int64_t q = j;
+                double sr = 0.0, sw = 0.0;
+                for (; q < e && key[vedge[q]] == f; ++q) {
+                    sr += lambar[vedge[q]];
+                    sw += w[vedge[q]];
+                }
+                for (int64_t r = j; r < q; ++r) ellbar[vedge[r]] = w[vedge[r]] / sw * (before + ellbar[vedge[r]]);
+                before += sr;
+                j = q;
+            }
+        }
     }
     for (int32_t b = 0; b < n_tab; ++b) {
         sigma_bar[b] = 0.0;

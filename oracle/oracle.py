@@ -59,7 +59,9 @@ def lib():
         _lib.or_backward.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, I32, P, P, P, P]
         _lib.or_single_ray.argtypes = [I64, P, P, P]
         _lib.or_infer_f32_storage.argtypes = [P, I64, P, P, I64, I64, P, P, I32, I32, P, P, P]
-        _lib.or_infer_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P, P]
+        _lib.or_infer_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, P, I32, P, P, P, P, P, P]
+        _lib.or_backward_keyframe_avg.argtypes = [P, I64, P, P, I64, I64, P, I32, P, P, P, P, P, P, I32, P, P,
+                                                  P, P, P, P]
         _lib.or_infer_keyframe_avg.restype = C.c_int
         _lib.or_accuracy.argtypes = [P, I32, P, P, P, C.c_double, C.c_double, P, P, P, P, P]
         _lib.or_depth_distribution.argtypes = [P, I64, P, P, P, P]
@@ -289,7 +291,7 @@ def edge_keyframes_and_lengths(graph: Graph, scenes):
 
 
 def infer_keyframe_average(graph: Graph, theta, sigma_table, sweeps: int, key, weight,
-                           bias_table=None, table_index=None) -> Result:
+                           bias_table=None, table_index=None, keep_history: bool = False) -> Result:
     """K sweeps with one length-weighted average message per keyframe and
     voxel (Sec. IV-A); key and weight per edge (edge_keyframes_and_lengths)."""
     theta = np.ascontiguousarray(theta, np.float64)
@@ -298,11 +300,36 @@ def infer_keyframe_average(graph: Graph, theta, sigma_table, sweeps: int, key, w
     key = np.ascontiguousarray(key, np.int32)
     weight = np.ascontiguousarray(weight, np.float64)
     lam, ell, L = np.empty(E), np.empty(E), np.empty(V)
+    hist = np.empty((sweeps, E)) if keep_history else None
     rc = lib().or_infer_keyframe_avg(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
-                                     _p(theta), _p(g), int(sweeps), _p(key), _p(weight), _p(lam), _p(ell), _p(L))
+                                     _p(theta), _p(g), int(sweeps), _p(key), _p(weight), _p(lam), _p(ell), _p(L),
+                                     _p(hist))
     if rc != 0:
         raise ValueError("keyframes must be grouped along every voxel's edge list")
-    return Result(L, lam, ell, g, None)
+    return Result(L, lam, ell, g, hist)
+
+
+def backward_keyframe_average(graph: Graph, res: Result, Lbar, sigma_table, key, weight, bias_table=None,
+                              want_bias: bool = False, table_index=None):
+    """Reverse pass of infer_keyframe_average(keep_history=True): (d loss/d
+    theta, d loss/d sigma, d loss/d g), and d loss/d mu appended with
+    want_bias; the same tables, key and weights as the forward."""
+    assert res.lam_hist is not None, "forward must keep its history"
+    Lbar = np.ascontiguousarray(Lbar, np.float64)
+    sig = np.ascontiguousarray(sigma_table, np.float64).reshape(-1)
+    mu = _bias(bias_table)
+    idx = graph.bin if table_index is None else np.ascontiguousarray(table_index, np.int32)
+    key = np.ascontiguousarray(key, np.int32)
+    weight = np.ascontiguousarray(weight, np.float64)
+    n_tab = sig.size
+    E, V = graph.n_edges, graph.n_voxels
+    tb, gb, sb = np.empty(V), np.empty(E), np.empty(n_tab)
+    bb = np.empty(n_tab) if want_bias else None
+    lib().or_backward_keyframe_avg(_p(graph.row_ptr), graph.n_rays, _p(graph.vptr), _p(graph.vedge), V, E,
+                                   _p(res.g), res.lam_hist.shape[0], _p(res.lam_hist), _p(Lbar), _p(graph.delta),
+                                   _p(idx), _p(sig), _p(mu), int(n_tab), _p(key), _p(weight), _p(tb), _p(gb),
+                                   _p(sb), _p(bb))
+    return (tb, sb, gb, bb) if want_bias else (tb, sb, gb)
 
 
 def backward(graph: Graph, res: Result, Lbar, sigma_table, bias_table=None, want_bias: bool = False,
