@@ -263,9 +263,7 @@ def main():
         backward = False
         desc = desc.replace(" + reverse pass (BCE vs ground truth)", "").replace(" + reverse pass", "")
         desc += "; forward sweeps only (no checkpoints, no reverse pass)"
-    if kf_step:   # the per-keyframe averaged scheme has no reverse pass
-        backward = False
-        desc = desc.replace(" + reverse pass (BCE vs ground truth)", "").replace(" + reverse pass", "")
+    if kf_step:
         desc += "; per-keyframe averaged messages (one chord-length-weighted average per keyframe and voxel)"
     t = time.perf_counter()
     scs = make_scene(args.workload, args.frames, args.c5_scale)
@@ -295,8 +293,10 @@ def main():
     def step():
         if kf_step:
             m.build_resident(keyframe_average=True)
-            m.infer_keyframe_avg(theta, sigma, K)
-            m.marginals()
+            m.infer_keyframe_avg(theta, sigma, K, keep_checkpoints=backward)
+            p, _ = m.marginals()
+            if backward:
+                m.backward((p - y) / p.numel())
             return
         m.build_resident()
         m.infer(theta, sigma, K, keep_checkpoints=backward)
@@ -354,7 +354,7 @@ def main():
         f"backward {bwd_ms}")
     fwd_bias_ms = bwd_bias_ms = acc_ms = dd_ms = fwd_cell_ms = bwd_cell_ms = None
     acc_counts, acc_clean, acc_by_k, clean_by_k = [0, 0], None, {}, {}
-    kf_build_ms = kf_fwd_ms = kf_plain_ms = kf_clean = None
+    kf_build_ms = kf_fwd_ms = kf_plain_ms = kf_clean = kf_bwd_ms = None
     kf_acc, kf_by_k, kf_clean_by_k, kf_prof = [0, 0], {}, {}, []
     if not args.quick:
         # the same sweeps with a learnt depth-bias table in the sensor model, and the
@@ -429,10 +429,16 @@ def main():
             c = m.accuracy()["counts"].cpu().numpy().sum(0)
             kf_by_k[str(k)] = round(float(c[1]) / max(float(c[0]), 1.0), 6)
             kf_clean_by_k[str(k)] = frac_clean()
+        kf_bwd_ms = None
+        if backward:   # the reverse pass through the keyframe-averaged sweeps
+            m.infer_keyframe_avg(theta, sigma, K, keep_checkpoints=True)
+            p, _ = m.marginals()
+            gl = (p - y) / p.numel()
+            kf_bwd_ms = timed(lambda: m.backward(gl))
         m.infer_keyframe_avg(theta, sigma, K)
         kf_prof = m.profile_sweeps(args.profile_reps, include_backward=False)
         log(f"keyframe average: build {kf_build_ms:.1f} ms ({kf_pairs} pairs), {K} sweeps {kf_fwd_ms:.1f} ms "
-            f"(plain {kf_plain_ms:.1f}), accurate fraction by sweeps {kf_by_k}")
+            f"(plain {kf_plain_ms:.1f}), reverse {kf_bwd_ms}, accurate fraction by sweeps {kf_by_k}")
         if not kf_step:
             m.build_resident()   # back to the plain graph for the profile below
 
@@ -489,6 +495,9 @@ def main():
         cpu = cpu_baseline(args.workload, sc, K, backward, args.cpu_rows, args.cpu_frames)
         log(f"cpu baseline: {cpu['value']:.3e} {UNIT} on {cpu['cores']} threads")
 
+    def r2(x):
+        return None if x is None else round(x, 2)
+
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
@@ -531,9 +540,10 @@ def main():
                                   "plain_schedule": "eager launches, one per frame and ray class, "
                                                     "untuned one-wave-per-ray shapes, no graph"},
         "keyframe_average": None if kf_fwd_ms is None else {
-                             "pairs": kf_pairs, "build_ms": round(kf_build_ms, 2),
-                             "forward_graph_ms": round(kf_fwd_ms, 2),
-                             "forward_plain_per_frame_ms": round(kf_plain_ms, 2),
+                             "pairs": kf_pairs, "build_ms": r2(kf_build_ms),
+                             "forward_graph_ms": r2(kf_fwd_ms),
+                             "forward_plain_per_frame_ms": r2(kf_plain_ms),
+                             "backward_ms": r2(kf_bwd_ms),
                              "updates_per_s": E * K / (kf_fwd_ms / 1e3),
                              "map_accuracy": {"evaluated_rays": kf_acc[0], "accurate_rays": kf_acc[1],
                                               "fraction": kf_acc[1] / max(kf_acc[0], 1), "vis_min": 0.5,

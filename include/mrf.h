@@ -223,12 +223,16 @@ int mrf_infer_sensor(mrf_ctx* ctx, const float* prior_logit, const float* sigma_
  * average of the last sweep; mrf_export_edges gives the last sweep's messages.
  * Averages are FP64 sums of weight * message in a fixed order; each
  * keyframe's message is one FP32 rounding of its FP64 value.  Tables and
- * arguments as mrf_infer_sensor (bias_table may be NULL).  No checkpoints are
- * kept: mrf_backward after this call returns MRF_ESTATE.  Errors: MRF_ESTATE
+ * arguments as mrf_infer_sensor (bias_table may be NULL).  keep_checkpoints
+ * != 0 keeps the pair averages of sweeps 2..K ((sweeps - 1) * n_keyframe_pairs
+ * doubles, instead of the per-edge messages mrf_infer keeps), from which
+ * mrf_backward* rebuild every sweep's keyframe messages: the reverse pass then
+ * differentiates this scheme (the derivative reaching a pair's average is
+ * shared by its edges in proportion to their weights).  Errors: MRF_ESTATE
  * before mrf_build or when the build did not set keyframe_average,
- * MRF_EINVAL for sweeps < 1. */
+ * MRF_EINVAL for sweeps < 1, MRF_ENOMEM. */
 int mrf_infer_keyframe_avg(mrf_ctx* ctx, const float* prior_logit, const float* sigma_table,
-                           const float* bias_table, int32_t sweeps, void* stream);
+                           const float* bias_table, int32_t sweeps, int32_t keep_checkpoints, void* stream);
 
 /* Marginals of the last mrf_infer (Sec. III-B: normalised product of all
  * factor messages into the voxel): logit_v = theta_v + sum of ray messages,
@@ -236,8 +240,8 @@ int mrf_infer_keyframe_avg(mrf_ctx* ctx, const float* prior_logit, const float* 
  * Errors: MRF_ESTATE before mrf_infer. */
 int mrf_marginals(mrf_ctx* ctx, float* p, float* logit, void* stream);
 
-/* Reverse pass through the K sweeps of the last mrf_infer (which must have
- * kept checkpoints).  dloss_dlogit: V floats, the gradient with respect to
+/* Reverse pass through the K sweeps of the last mrf_infer, mrf_infer_sensor or
+ * mrf_infer_keyframe_avg (which must have kept checkpoints).  dloss_dlogit: V floats, the gradient with respect to
  * the marginal log-odds (for BCE with logits: (p - y) / V).  Outputs
  * dprior_logit (V floats) and dsigma_table (the sigma table's size: 64
  * floats, or 64 per pixel region); either may be NULL.

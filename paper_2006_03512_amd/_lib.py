@@ -90,7 +90,7 @@ def lib() -> C.CDLL:
         L.mrf_build.argtypes = [P, C.POINTER(SceneC), I32, C.POINTER(BuildParams), P]
         L.mrf_infer.argtypes = [P, P, P, I32, I32, P]
         L.mrf_infer_sensor.argtypes = [P, P, P, P, I32, I32, P]
-        L.mrf_infer_keyframe_avg.argtypes = [P, P, P, P, I32, P]
+        L.mrf_infer_keyframe_avg.argtypes = [P, P, P, P, I32, I32, P]
         L.mrf_marginals.argtypes = [P, P, P, P]
         L.mrf_backward.argtypes = [P, P, P, P, P]
         L.mrf_backward_sensor.argtypes = [P, P, P, P, P, P]

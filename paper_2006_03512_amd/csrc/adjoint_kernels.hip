@@ -139,41 +139,61 @@ __device__ __forceinline__ void ray_adj_body(const float (&al)[IPL], const float
 // lam.own_e (the forward messages of the sweep) and d/d ell_e = eb.tot[col_e] -
 // eb.own_e (the later sweep's d/d lambda summed over the voxel, less the
 // edge's own: the adjoint of the forward's total-minus-own).
-template <int G, int IPL>
+// With KF (per-keyframe averaged messages) lambda_e and d/d ell_e come from
+// the keyframe buffers of kfa instead (AdjKf).
+template <int G, int IPL, bool KF>
 __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                  const TileDev* __restrict__ tiles, const int32_t* __restrict__ counts,
                                                  const int32_t* __restrict__ col, ExclDev lam,
-                                                 const float* __restrict__ g, ExclDev eb, float* __restrict__ lambar,
-                                                 float* __restrict__ gsum, int first)
+                                                 const float* __restrict__ g, ExclDev eb, AdjKf kfa,
+                                                 float* __restrict__ lambar, float* __restrict__ gsum, int first)
 {
     static_assert(G == 64 || IPL == 1, "16-lane groups hold a whole ray");
     int64_t s;
-    int m;
-    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m)) return;
+    int m, frame = 0;
+    if (!tile_ray<G>(list, ntiles, tiles, counts, s, m, &frame)) return;
     const int i0 = (int)(threadIdx.x & (G - 1)) * IPL;
     int32_t cv[IPL];
-    float lo[IPL], eo[IPL], gv[IPL];
+    float lo[IPL], eo[IPL], gv[IPL], lv[IPL], ev[IPL];
     float2 lt[IPL], et[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {   // indices clamped to the ray (m >= 1): loads issued before any wait
         const int64_t at = s + kTile * (int64_t)min(i0 + j, m - 1);
         cv[j] = col[at];
-        lo[j] = lam.own[at];
-        eo[j] = eb.own[at];
+        if constexpr (KF) {
+            eo[j] = kfa.w[at];
+        } else {
+            lo[j] = lam.own[at];
+            eo[j] = eb.own[at];
+        }
         gv[j] = g[at];
     }
+    if constexpr (KF) {
+        const int64_t xb = kfa.x.xb[frame];
 #pragma unroll
-    for (int j = 0; j < IPL; ++j) {
-        const int cc = max(cv[j], 0);
-        lt[j] = lam.tot[cc];
-        et[j] = eb.tot[cc];
+        for (int j = 0; j < IPL; ++j) {
+            lv[j] = cv[j] >= 0 ? kfa.x.x[xb + cv[j]] : 0.0f;
+            ev[j] = cv[j] >= 0 ? eo[j] * kfa.y[xb + cv[j]] : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            const int cc = max(cv[j], 0);
+            lt[j] = lam.tot[cc];
+            et[j] = eb.tot[cc];
+        }
+#pragma unroll
+        for (int j = 0; j < IPL; ++j) {
+            lv[j] = excl_value(cv[j], lt[j], lo[j], lam.has_own);
+            ev[j] = excl_value(cv[j], et[j], eo[j], eb.has_own);
+        }
     }
     float al[IPL], be[IPL], gg[IPL], ebar[IPL], lamb[IPL], gb[IPL];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
         const bool ok = i0 + j < m;
-        load_step(excl_value(cv[j], lt[j], lo[j], lam.has_own), gv[j], ok, al[j], be[j], gg[j]);
-        ebar[j] = ok ? excl_value(cv[j], et[j], eo[j], eb.has_own) : 0.0f;
+        load_step(lv[j], gv[j], ok, al[j], be[j], gg[j]);
+        ebar[j] = ok ? ev[j] : 0.0f;
     }
     ray_adj_body<G, IPL>(al, be, gg, ebar, m, i0, lamb, gb);
 #pragma unroll
@@ -195,12 +215,12 @@ __global__ __launch_bounds__(256) void ray_adj_k(const uint32_t* __restrict__ li
 // array); each group writes lambda-bar and g-bar into its rays' columns (zeros
 // past the ray), and the block stores lambda-bar and accumulates the g-bar sum
 // coalesced.
-template <int G, int IPL, int RPW>
+template <int G, int IPL, int RPW, bool KF>
 __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t* __restrict__ list, int64_t ntiles,
                                                                  const TileDev* __restrict__ tiles,
                                                                  const int32_t* __restrict__ counts,
                                                                  const int32_t* __restrict__ col, ExclDev lam,
-                                                                 const float* __restrict__ g, ExclDev eb,
+                                                                 const float* __restrict__ g, ExclDev eb, AdjKf kfa,
                                                                  float* __restrict__ lambar, float* __restrict__ gsum,
                                                                  int first)
 {
@@ -227,19 +247,32 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
         float vo[NR], vb[NR], vg[NR], vt[NR];
         float2 pt[NR], pe[NR];
         tile_fetch_i<NT, NR>(col, td.base, nf, vc);
-        tile_fetch<NT, NR>(lam.own, td.base, nf, vo);
-        tile_fetch<NT, NR>(eb.own, td.base, nf, vb);
-        tile_fetch<NT, NR>(g, td.base, nf, vg);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int cc = max(vc[r], 0);
-            pt[r] = lam.tot[cc];
-            pe[r] = eb.tot[cc];
+        if constexpr (KF) {
+            tile_fetch<NT, NR>(kfa.w, td.base, nf, vb);
+        } else {
+            tile_fetch<NT, NR>(lam.own, td.base, nf, vo);
+            tile_fetch<NT, NR>(eb.own, td.base, nf, vb);
         }
+        tile_fetch<NT, NR>(g, td.base, nf, vg);
+        if constexpr (KF) {
+            const int64_t xb = kfa.x.xb[td.frame];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            vt[r] = excl_value(vc[r], pt[r], vo[r], lam.has_own);
-            ve[r] = excl_value(vc[r], pe[r], vb[r], eb.has_own);
+            for (int r = 0; r < NR; ++r) {
+                vt[r] = vc[r] >= 0 ? kfa.x.x[xb + vc[r]] : 0.0f;
+                ve[r] = vc[r] >= 0 ? vb[r] * kfa.y[xb + vc[r]] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int cc = max(vc[r], 0);
+                pt[r] = lam.tot[cc];
+                pe[r] = eb.tot[cc];
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                vt[r] = excl_value(vc[r], pt[r], vo[r], lam.has_own);
+                ve[r] = excl_value(vc[r], pe[r], vb[r], eb.has_own);
+            }
         }
         tile_to_lds<NT, NR, IPL>(sa, nf, vt);
         tile_to_lds<NT, NR, IPL>(sb, nf, vg);
@@ -289,9 +322,17 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
     tile_store<NT, NR, IPL>(gsum, td.base, nf, [&](int r, int at) { return first ? sb[at] : vs[r] + sb[at]; });
 }
 
-template <int Q, int I>
-static void launch_adj_shape(const mrf_ctx* c, ExclDev lam, ExclDev eb, float* lambar, float* gsum, int first,
-                             hipStream_t s)
+// The reverse pass's per-edge inputs: the voxel totals less the own terms, or
+// (is_kf) the keyframe buffers.
+struct AdjSrc {
+    ExclDev lam, eb;
+    AdjKf kf;
+    bool is_kf;
+};
+
+template <int Q, int I, bool KF>
+static void launch_adj_shape_t(const mrf_ctx* c, const AdjSrc& a, float* lambar, float* gsum, int first,
+                               hipStream_t s)
 {
     constexpr int G = kAdjShapes[Q][I].g;
     if constexpr (G != 0) {
@@ -300,49 +341,69 @@ static void launch_adj_shape(const mrf_ctx* c, ExclDev lam, ExclDev eb, float* l
         const uint32_t* list = (const uint32_t*)c->b_ray_list[Q].p;
         if constexpr (ray_class_lds(Q)) {
             constexpr int RPW = kAdjShapes[Q][I].rpw;
-            hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G, RPW>), dim3((unsigned)n), dim3(kTile * G / RPW), 0, s,
+            hipLaunchKernelGGL((ray_adj_lds_k<G, CAP / G, RPW, KF>), dim3((unsigned)n), dim3(kTile * G / RPW), 0, s,
                                list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
-                               (const int32_t*)c->b_col.p, lam, (const float*)c->b_g.p, eb, lambar, gsum, first);
+                               (const int32_t*)c->b_col.p, a.lam, (const float*)c->b_g.p, a.eb, a.kf, lambar, gsum,
+                               first);
         } else {
-            hipLaunchKernelGGL((ray_adj_k<G, CAP / G>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
+            hipLaunchKernelGGL((ray_adj_k<G, CAP / G, KF>), dim3((unsigned)(n * tile_blocks<G>())), dim3(256), 0, s,
                                list, n, (const TileDev*)c->b_tiles.p, (const int32_t*)c->b_counts.p,
-                               (const int32_t*)c->b_col.p, lam, (const float*)c->b_g.p, eb, lambar, gsum, first);
+                               (const int32_t*)c->b_col.p, a.lam, (const float*)c->b_g.p, a.eb, a.kf, lambar, gsum,
+                               first);
         }
     }
 }
 
+template <int Q, int I>
+static void launch_adj_shape(const mrf_ctx* c, const AdjSrc& a, float* lambar, float* gsum, int first, hipStream_t s)
+{
+    if (a.is_kf)
+        launch_adj_shape_t<Q, I, true>(c, a, lambar, gsum, first, s);
+    else
+        launch_adj_shape_t<Q, I, false>(c, a, lambar, gsum, first, s);
+}
+
 template <int Q, int... I>
-static void launch_adj_sel(int sel, const mrf_ctx* c, ExclDev lam, ExclDev eb, float* lambar, float* gsum, int first,
+static void launch_adj_sel(int sel, const mrf_ctx* c, const AdjSrc& a, float* lambar, float* gsum, int first,
                            hipStream_t s, std::integer_sequence<int, I...>)
 {
-    ((sel == I ? launch_adj_shape<Q, I>(c, lam, eb, lambar, gsum, first, s) : void()), ...);
+    ((sel == I ? launch_adj_shape<Q, I>(c, a, lambar, gsum, first, s) : void()), ...);
 }
 
 template <int Q>
-static void launch_adj_class(const mrf_ctx* c, int sel, ExclDev lam, ExclDev eb, float* lambar, float* gsum,
-                             int first, hipStream_t s)
+static void launch_adj_class(const mrf_ctx* c, int sel, const AdjSrc& a, float* lambar, float* gsum, int first,
+                             hipStream_t s)
 {
     if (c->ray_cnt[Q] <= 0) return;
     ProfScope ps(c, KID_ADJ0 + Q, s);
-    launch_adj_sel<Q>(sel, c, lam, eb, lambar, gsum, first, s, std::make_integer_sequence<int, kNShapes>{});
+    launch_adj_sel<Q>(sel, c, a, lambar, gsum, first, s, std::make_integer_sequence<int, kNShapes>{});
 }
 
 template <int... Q>
-static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, ExclDev lam, ExclDev eb, float* lambar,
+static void adj_classes(std::integer_sequence<int, Q...>, const mrf_ctx* c, const AdjSrc& a, float* lambar,
                         float* gsum, int first, hipStream_t s)
 {
-    (launch_adj_class<Q>(c, c->adj_sel[Q], lam, eb, lambar, gsum, first, s), ...);
+    (launch_adj_class<Q>(c, c->adj_sel[Q], a, lambar, gsum, first, s), ...);
 }
 
 hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* lambar, float* gsum, bool first,
                               hipStream_t s)
 {
-    adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, excl_dev(c, lam), excl_dev(c, ellbar), lambar,
-                gsum, first ? 1 : 0, s);
+    const AdjSrc a{excl_dev(c, lam), excl_dev(c, ellbar), AdjKf{KfSrc{nullptr, nullptr}, nullptr, nullptr}, false};
+    adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, a, lambar, gsum, first ? 1 : 0, s);
     return hipGetLastError();
 }
 
-using AdjClassFn = void (*)(const mrf_ctx*, int, ExclDev, ExclDev, float*, float*, int, hipStream_t);
+hipError_t launch_ray_adjoint_kf(mrf_ctx* c, AdjKf kf, float* lambar, float* gsum, bool first, hipStream_t s)
+{
+    // the exact-scheme sources are unused; any readable arrays stand in
+    const ExclDev none{(const float2*)c->b_theta2.p, (const float*)c->b_g.p, 0};
+    const AdjSrc a{none, none, kf, true};
+    adj_classes(std::make_integer_sequence<int, kRayClasses>{}, c, a, lambar, gsum, first ? 1 : 0, s);
+    return hipGetLastError();
+}
+
+using AdjClassFn = void (*)(const mrf_ctx*, int, const AdjSrc&, float*, float*, int, hipStream_t);
 template <int... Q>
 static constexpr std::array<AdjClassFn, kRayClasses> adj_class_fns(std::integer_sequence<int, Q...>)
 {
@@ -355,7 +416,8 @@ hipError_t launch_adj_class_shape(const mrf_ctx* c, int q, int sel, ExclSrc lam,
     static constexpr std::array<AdjClassFn, kRayClasses> fns =
         adj_class_fns(std::make_integer_sequence<int, kRayClasses>{});
     if (q < 0 || q >= kRayClasses || sel < 0 || sel >= ray_shape_count(q, true)) return hipErrorInvalidValue;
-    fns[q](c, sel, excl_dev(c, lam), excl_dev(c, ellbar), lambar, gsum, first, s);
+    const AdjSrc a{excl_dev(c, lam), excl_dev(c, ellbar), AdjKf{KfSrc{nullptr, nullptr}, nullptr, nullptr}, false};
+    fns[q](c, sel, a, lambar, gsum, first, s);
     return hipGetLastError();
 }
 

@@ -168,12 +168,14 @@ static hipError_t enqueue_forward(mrf_ctx* c, int K, int keep, bool plain, hipSt
 // keyframe's voxel -> ray message (theta plus the OTHER keyframes' averages);
 // after the last sweep the beliefs L = theta plus every keyframe's average.
 // ell alternates between b_lam and b_ell so that the last sweep's ends in b_ell.
-static hipError_t enqueue_forward_kf(mrf_ctx* c, int K, bool plain, hipStream_t s)
+// keep: the pair averages of sweeps 2..K go to b_ckpt ((K - 1) * n_pairs doubles),
+// from which the reverse pass rebuilds every sweep's keyframe messages.
+static hipError_t enqueue_forward_kf(mrf_ctx* c, int K, int keep, bool plain, hipStream_t s)
 {
     hipError_t e;
     const float* theta = (const float*)c->b_theta.p;
     const float* w = (const float*)c->b_kfw.p;
-    double* M = (double*)c->b_pair_m.p;
+    double* Mlast = (double*)c->b_pair_m.p;
     float* x = (float*)c->b_kfx.p;
     const KfSrc kf{x, (const int64_t*)c->b_kfxb.p};
     if ((e = launch_pair(theta, (float2*)c->b_theta2.p, c->V, s)) != hipSuccess) return e;
@@ -183,15 +185,16 @@ static hipError_t enqueue_forward_kf(mrf_ctx* c, int K, bool plain, hipStream_t 
         if (k == 1) {
             e = launch_ray_phase(c, ExclSrc{(const float2*)c->b_theta2.p, nullptr}, ell, plain, s);
         } else {
+            double* M = keep ? (double*)c->b_ckpt.p + (size_t)(k - 2) * (size_t)c->n_pairs : Mlast;
             e = launch_pair_phase(c, ell_slot(c, K, k - 1, false), w, M, s);
-            if (e == hipSuccess) e = launch_kf_voxel(c, theta, x, nullptr, s);
+            if (e == hipSuccess) e = launch_kf_voxel(c, M, theta, x, nullptr, s);
             if (e == hipSuccess) e = launch_ray_phase_kf(c, kf, ell, plain, s);
         }
         if (e != hipSuccess) return e;
     }
     if ((e = launch_copy((float*)c->b_L.p, theta, c->V, s)) != hipSuccess) return e;
-    if ((e = launch_pair_phase(c, (const float*)c->b_ell.p, w, M, s)) != hipSuccess) return e;
-    return launch_kf_voxel(c, theta, nullptr, (float*)c->b_L.p, s);
+    if ((e = launch_pair_phase(c, (const float*)c->b_ell.p, w, Mlast, s)) != hipSuccess) return e;
+    return launch_kf_voxel(c, Mlast, theta, nullptr, (float*)c->b_L.p, s);
 }
 
 static const float* final_ell(const mrf_ctx* c) { return c->inferred ? (const float*)c->b_ell.p : nullptr; }
@@ -259,7 +262,8 @@ void mrf_destroy(mrf_ctx* c)
                      &c->b_ckpt, &c->b_tsum, &c->b_tbar, &c->b_metric, &c->b_bricks,
                      &c->b_ellbar, &c->b_lambar, &c->b_gsum, &c->b_tmp64, &c->b_cls, &c->b_sigpart,
                      &c->b_misc, &c->b_frame_list, &c->b_tiles, &c->b_tbase, &c->b_export,
-                     &c->b_kfw, &c->b_kflen, &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox};
+                     &c->b_kfw, &c->b_kflen, &c->b_pair_m, &c->b_pair_x, &c->b_kfx, &c->b_kfxb, &c->b_kf_vox,
+                     &c->b_kfxr, &c->b_kfy, &c->b_kfws};
     for (DevBuf* b : all) free_buf(*b);
     for (auto& b : c->b_host_in) free_buf(b);
     for (auto& b : c->b_pair_desc) free_buf(b);
@@ -460,6 +464,7 @@ static int build_impl(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, con
     c->n_bricks = NB;
     c->keep_chords = p->keep_chords ? 1 : 0;
     c->kf = p->keyframe_average ? 1 : 0;
+    c->kfws_ready = 0;
     if (p->group_slots_log2 != 0 && (p->group_slots_log2 < 12 || p->group_slots_log2 > 32))
         return fail(MRF_EINVAL, "mrf_build: group_slots_log2 must be 0 or lie in [12, 32]");
     c->group_log2 = p->group_slots_log2 ? p->group_slots_log2 : 32;
@@ -728,6 +733,7 @@ int mrf_add_frames(mrf_ctx* c, int32_t n_frames, const float* depth, const doubl
     HCK(hipSetDevice(c->device), "mrf_add_frames: hipSetDevice");
     drop_graph(c);
     c->built = c->inferred = c->have_ckpt = c->kf_inferred = 0;
+    c->kfws_ready = 0;
     ++c->gen;
 
     const int last = c->n_scenes - 1;
@@ -937,7 +943,7 @@ int mrf_infer_sensor(mrf_ctx* c, const float* prior_logit, const float* sigma_ta
 }
 
 int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* sigma_table, const float* bias_table,
-                           int32_t sweeps, void* stream)
+                           int32_t sweeps, int32_t keep_checkpoints, void* stream)
 {
     if (!c || !prior_logit || !sigma_table) return fail(MRF_EINVAL, "mrf_infer_keyframe_avg: null argument");
     if (!c->built) return fail(MRF_ESTATE, "mrf_infer_keyframe_avg: call mrf_build first");
@@ -946,6 +952,14 @@ int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* si
     if (sweeps < 1) return fail(MRF_EINVAL, "mrf_infer_keyframe_avg: sweeps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_infer_keyframe_avg: hipSetDevice");
+    const int keep = keep_checkpoints ? 1 : 0;
+    if (keep) {   // the pair averages of sweeps 2..K
+        const size_t need = sizeof(double) * (size_t)(sweeps > 1 ? sweeps - 1 : 1) * (size_t)c->n_pairs;
+        if (c->b_ckpt.cap < need) {
+            drop_graph(c);   // the graph holds the old address
+            HCK(ensure(c->b_ckpt, need), "mrf_infer_keyframe_avg: alloc checkpoints");
+        }
+    }
     HCK(launch_copy((float*)c->b_theta.p, prior_logit, c->V, s), "mrf_infer_keyframe_avg: copy prior");
     HCK(launch_copy((float*)c->b_sigma.p, sigma_table, table_entries(c), s), "mrf_infer_keyframe_avg: copy sigma");
     if (bias_table)
@@ -953,16 +967,16 @@ int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* si
     else
         HCK(launch_fill((float*)c->b_bias.p, 0.0f, table_entries(c), s), "mrf_infer_keyframe_avg: zero bias");
     if (c->schedule == MRF_SCHED_PLAIN) {
-        HCK(enqueue_forward_kf(c, sweeps, true, s), "mrf_infer_keyframe_avg: sweeps");
+        HCK(enqueue_forward_kf(c, sweeps, keep, true, s), "mrf_infer_keyframe_avg: sweeps");
     } else {
-        std::vector<uint64_t> key = graph_key(c, sweeps, 0);
+        std::vector<uint64_t> key = graph_key(c, sweeps, keep);
         key.push_back(0x6b66);   // the keyframe-average schedule
         if (!c->gexec || key != c->g_key) {
             drop_graph(c);
             hipGraph_t g = nullptr;
             HCK(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal),
                 "mrf_infer_keyframe_avg: begin capture");
-            hipError_t e = enqueue_forward_kf(c, sweeps, false, c->aux);
+            hipError_t e = enqueue_forward_kf(c, sweeps, keep, false, c->aux);
             hipError_t e2 = hipStreamEndCapture(c->aux, &g);
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
@@ -972,7 +986,7 @@ int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* si
                 return hip_fail(e, "mrf_infer_keyframe_avg: graph capture");
             }
             c->g_K = sweeps;
-            c->g_ckpt = 0;
+            c->g_ckpt = keep;
             c->g_key = key;
         }
         HCK(hipEventRecord(c->ev_in, s), "mrf_infer_keyframe_avg: event");
@@ -985,9 +999,9 @@ int mrf_infer_keyframe_avg(mrf_ctx* c, const float* prior_logit, const float* si
     c->kf_inferred = 1;
     ++c->gen;
     c->K = sweeps;
-    c->have_ckpt = 0;
+    c->have_ckpt = keep;
     c->stats.sweeps_done = sweeps;
-    c->stats.have_checkpoints = 0;
+    c->stats.have_checkpoints = keep;
     return MRF_OK;
 }
 
@@ -1001,6 +1015,48 @@ int mrf_marginals(mrf_ctx* c, float* p, float* logit, void* stream)
     return MRF_OK;
 }
 
+// Reverse pass through K sweeps with per-keyframe averaged messages (as in the
+// oracle's or_backward_keyframe_avg): y holds, per (keyframe, voxel) pair, the
+// derivative reaching the pair's average (seed: d/d L_v), an edge's d/d ell is
+// its share of the pair's weight times y, and each sweep rebuilds its keyframe
+// messages from the checkpointed pair averages.  d/d theta accumulates in
+// b_thetabar, d/d g in b_gsum.
+static hipError_t backward_kf(mrf_ctx* c, const float* dlogit, hipStream_t s)
+{
+    const int K = c->K;
+    const size_t nx = (size_t)(c->n_kfx > 0 ? c->n_kfx : 1);
+    hipError_t e = ensure(c->b_kfxr, sizeof(float) * nx);
+    if (e == hipSuccess) e = ensure(c->b_kfy, sizeof(float) * nx);
+    if (e == hipSuccess && !c->kfws_ready) {   // per-slot pair weights, once per build
+        e = ensure(c->b_kfws, sizeof(float) * (size_t)(c->S > 0 ? c->S : 1));
+        if (e == hipSuccess) e = launch_fill((float*)c->b_kfws.p, 0.0f, c->S, s);
+        if (e == hipSuccess)
+            e = launch_scatter_by_slot((const uint32_t*)c->b_vedge.p, (const float*)c->b_kfw.p, c->E,
+                                       (float*)c->b_kfws.p, s);
+        if (e == hipSuccess) c->kfws_ready = 1;
+    }
+    if (e != hipSuccess) return e;
+    float* thetabar = (float*)c->b_thetabar.p;
+    float* xr = (float*)c->b_kfxr.p;
+    float* y = (float*)c->b_kfy.p;
+    double* sp = (double*)c->b_pair_m.p;   // pair sums of d/d lambda (scratch)
+    const int64_t* xb = (const int64_t*)c->b_kfxb.p;
+    const float* theta = (const float*)c->b_theta.p;
+    if ((e = launch_copy(thetabar, dlogit, c->V, s)) != hipSuccess) return e;
+    // seed: the last sweep's messages reach L_v through their pair averages
+    if ((e = launch_kf_voxel(c, nullptr, dlogit, y, nullptr, s)) != hipSuccess) return e;
+    for (int k = K; k >= 1 && e == hipSuccess; --k) {
+        const double* M = k >= 2 ? (const double*)c->b_ckpt.p + (size_t)(k - 2) * (size_t)c->n_pairs : nullptr;
+        e = launch_kf_voxel(c, M, theta, xr, nullptr, s);   // the keyframe messages of sweep k
+        if (e == hipSuccess)
+            e = launch_ray_adjoint_kf(c, AdjKf{KfSrc{xr, xb}, y, (const float*)c->b_kfws.p}, (float*)c->b_lambar.p,
+                                      (float*)c->b_gsum.p, k == K, s);
+        if (e == hipSuccess) e = launch_pair_phase(c, (const float*)c->b_lambar.p, nullptr, sp, s);
+        if (e == hipSuccess) e = launch_kf_voxel_rev(c, sp, thetabar, k > 1 ? y : nullptr, s);
+    }
+    return e;
+}
+
 int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, void* stream)
 {
     return mrf_backward_sensor(c, dlogit, dprior, dsigma, nullptr, stream);
@@ -1009,13 +1065,16 @@ int mrf_backward(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, 
 int mrf_backward_sensor(mrf_ctx* c, const float* dlogit, float* dprior, float* dsigma, float* dbias, void* stream)
 {
     if (!c || !dlogit) return fail(MRF_EINVAL, "mrf_backward: null argument");
-    if (c->inferred && c->kf_inferred)
-        return fail(MRF_ESTATE, "mrf_backward: the last inference used per-keyframe averaged messages, which have "
-                                "no reverse pass");
     if (!c->inferred || !c->have_ckpt)
         return fail(MRF_ESTATE, "mrf_backward: needs a preceding mrf_infer with keep_checkpoints");
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_backward: hipSetDevice");
+    if (c->kf_inferred) {
+        HCK(backward_kf(c, dlogit, s), "mrf_backward: reverse sweeps with keyframe averages");
+        if (dsigma || dbias) HCK(launch_sigma_grad(c, dsigma, dbias, s), "mrf_backward: sensor-table gradients");
+        if (dprior) HCK(launch_copy(dprior, (const float*)c->b_thetabar.p, c->V, s), "mrf_backward: copy");
+        return MRF_OK;
+    }
     const int K = c->K;
     float* gsum = (float*)c->b_gsum.p;
     float* thetabar = (float*)c->b_thetabar.p;
@@ -1281,7 +1340,7 @@ int mrf_profile_sweeps(mrf_ctx* c, int32_t reps, int32_t include_backward, mrf_k
         const KfSrc kf{xs, (const int64_t*)c->b_kfxb.p};
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
             e = launch_pair_phase(c, ell_in, (const float*)c->b_kfw.p, (double*)c->b_pair_m.p, s);
-            if (e == hipSuccess) e = launch_kf_voxel(c, theta, xs, nullptr, s);
+            if (e == hipSuccess) e = launch_kf_voxel(c, (const double*)c->b_pair_m.p, theta, xs, nullptr, s);
             if (e == hipSuccess) e = launch_ray_phase_kf(c, kf, ell, false, s);
         }
         include_backward = 0;

@@ -473,6 +473,22 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void scatter_by_slot_k(const uint32_t* __restrict__ slot, const float* __restrict__ in, int64_t n,
+                                  float* __restrict__ out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        out[slot[j]] = in[j];
+}
+
+hipError_t launch_scatter_by_slot(const uint32_t* slot, const float* in, int64_t n, float* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(scatter_by_slot_k, dim3((unsigned)b), dim3(256), 0, s, slot, in, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_trace_emit(mrf_ctx* c, hipStream_t s, int f0, int nf)
 {
     if (nf < 0) nf = c->n_frames - f0;

@@ -189,6 +189,16 @@ struct KfSrc {
     const int64_t* xb;
 };
 
+// Reverse pass with per-keyframe averaged messages: lambda_e as in KfSrc
+// (x, the sweep's messages), and d/d ell_e = w_e y[xb[f] + col_e], w_e the
+// edge's share of its pair's weight (per slot) and y the derivative reaching
+// the pair's average (same layout as x).
+struct AdjKf {
+    KfSrc x;
+    const float* y;
+    const float* w;
+};
+
 // Outputs of a voxel-phase reduction of sum_v (the FP64 sum of a per-edge
 // array over voxel v's edges), each optional: tot2[v] = pair(base[v] + sum_v),
 // totf[v] = fl(base[v] + sum_v), acc[v] += fl(sum_v); base null reads as 0.
@@ -330,6 +340,9 @@ struct mrf_ctx {
     mrf::DevBuf b_pair_x;         // per pair: index of its entry in b_kfx
     mrf::DevBuf b_kfx;            // per-keyframe voxel -> ray messages
     mrf::DevBuf b_kfxb;           // per frame: b_kfx base less its scene's first voxel id
+    mrf::DevBuf b_kfxr, b_kfy;    // reverse pass: a sweep's rebuilt keyframe messages, the pair derivatives
+    mrf::DevBuf b_kfws;           // reverse pass: per edge slot, the edge's share of its pair's weight
+    int kfws_ready = 0;           // b_kfws holds the current build's weights
     mrf::DevBuf b_kf_vox;         // per touched voxel: VoxDev over its pairs (start, count, voxel id)
     mrf::DevBuf b_pair_desc[mrf::kVoxClasses];   // pairs by edge-count class: VoxDev (start, m, pair id)
     int64_t pair_cnt[mrf::kVoxClasses] = {0};
@@ -428,6 +441,8 @@ hipError_t launch_merge_incidence(const uint32_t* vedge_old, const uint32_t* key
                                   uint32_t s_new0, int64_t* vptr, int64_t* new_vptr, int64_t nkeys, uint32_t* out,
                                   hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// out[slot[j]] = in[j] for j < n (list order to slot order)
+hipError_t launch_scatter_by_slot(const uint32_t* slot, const float* in, int64_t n, float* out, hipStream_t s);
 // per-keyframe averaged messages: (keyframe, voxel) pairs of the built graph,
 // their weights, work classes and message-buffer indices (after build_classes,
 // with the sorted voxel keys still in b_lambar and chord lengths in b_kfw)
@@ -459,14 +474,19 @@ hipError_t launch_ray_phase_kf(mrf_ctx* c, KfSrc lam, float* ell, bool plain, hi
 hipError_t launch_ray_class_shape_kf(const mrf_ctx* c, int q, int sel, KfSrc lam, float* ell, hipStream_t s);
 // M[p] = FP64 sum over pair p's list entries j of w[j] in[vedge[j]] (w null: 1)
 hipError_t launch_pair_phase(mrf_ctx* c, const float* in, const float* w, double* M, hipStream_t s);
-// per touched voxel: T = theta + sum of its pairs' M; x[pair_x[p]] = fl(T - M[p])
-// for every pair when x is not null; L[v] = fl(T) when L is not null
-hipError_t launch_kf_voxel(mrf_ctx* c, const float* theta, float* x, float* L, hipStream_t s);
+// per touched voxel: T = theta + sum of its pairs' M (M null: 0); x[pair_x[p]] =
+// fl(T - M[p]) for every pair when x is not null; L[v] = fl(T) when L is not null
+hipError_t launch_kf_voxel(mrf_ctx* c, const double* M, const float* theta, float* x, float* L, hipStream_t s);
+// reverse: S = sum of the voxel's pair values sp; acc[v] += fl(S); y[pair_x[p]] =
+// fl(S - sp[p]) when y is not null
+hipError_t launch_kf_voxel_rev(mrf_ctx* c, const double* sp, float* acc, float* y, hipStream_t s);
 // out_e = x[xb[frame of e] + col_e] on every edge slot (0 on padding)
 hipError_t launch_excl_kf(const mrf_ctx* c, KfSrc x, float* out, hipStream_t s);
 hipError_t launch_sigmoid(const float* L, float* p, int64_t n, hipStream_t s);
 
 // adjoint_kernels.hip
+// the reverse ray phase with per-keyframe averaged messages
+hipError_t launch_ray_adjoint_kf(mrf_ctx* c, AdjKf kf, float* lambar, float* gsum, bool first, hipStream_t s);
 hipError_t launch_ray_adjoint(mrf_ctx* c, ExclSrc lam, ExclSrc ellbar, float* lambar, float* gsum, bool first,
                               hipStream_t s);
 // d loss / d sigma and, when dbias is not null, d loss / d bias (a table entry

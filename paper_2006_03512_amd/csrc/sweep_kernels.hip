@@ -527,6 +527,7 @@ hipError_t launch_pair_phase(mrf_ctx* c, const float* in, const float* w, double
 // One 16-lane group per touched voxel: T = theta_v + the sum of the voxel's
 // pair averages (FP64; lane-strided partial sums added in a fixed order), then
 // every pair's message x = fl(T - M) into its keyframe's buffer, and L_v = fl(T).
+// M null: every average is 0 (x = theta).
 __global__ __launch_bounds__(256) void kf_voxel_k(const VoxDev* __restrict__ vd, int64_t n,
                                                   const double* __restrict__ M, const uint32_t* __restrict__ px,
                                                   const float* __restrict__ theta, float* __restrict__ x,
@@ -537,20 +538,52 @@ __global__ __launch_bounds__(256) void kf_voxel_k(const VoxDev* __restrict__ vd,
     const int l = (int)(threadIdx.x & 15);
     const VoxDev d = vd[vi];
     double a = 0.0;
-    for (int q = l; q < d.m; q += 16) a += M[d.start + q];
+    if (M)
+        for (int q = l; q < d.m; q += 16) a += M[d.start + q];
     a = dgroup_sum_d<16>(a);
     const double T = (double)theta[d.v] + __shfl(a, (int)(threadIdx.x & 48), 64);
     if (x)
-        for (int q = l; q < d.m; q += 16) x[px[d.start + q]] = (float)(T - M[d.start + q]);
+        for (int q = l; q < d.m; q += 16) x[px[d.start + q]] = (float)(T - (M ? M[d.start + q] : 0.0));
     if (L && l == 0) L[d.v] = (float)T;
 }
 
-hipError_t launch_kf_voxel(mrf_ctx* c, const float* theta, float* x, float* L, hipStream_t s)
+hipError_t launch_kf_voxel(mrf_ctx* c, const double* M, const float* theta, float* x, float* L, hipStream_t s)
 {
     if (c->n_kf_vox <= 0) return hipSuccess;
     ProfScope ps(c, KID_KFVOX, s);
     hipLaunchKernelGGL(kf_voxel_k, dim3(nblk(c->n_kf_vox, 16)), dim3(256), 0, s, (const VoxDev*)c->b_kf_vox.p,
-                       c->n_kf_vox, (const double*)c->b_pair_m.p, (const uint32_t*)c->b_pair_x.p, theta, x, L);
+                       c->n_kf_vox, M, (const uint32_t*)c->b_pair_x.p, theta, x, L);
+    return hipGetLastError();
+}
+
+// Reverse of kf_voxel_k: with s_p the pair sums of d/d lambda (FP64), S_v =
+// their sum over the voxel's pairs (the same fixed order); acc_v += fl(S_v)
+// (d/d theta) and, when y is given, y = fl(S_v - s_p) into the pair's keyframe
+// buffer: the derivative reaching the pair's average through every other
+// keyframe's incoming message.
+__global__ __launch_bounds__(256) void kf_voxel_rev_k(const VoxDev* __restrict__ vd, int64_t n,
+                                                      const double* __restrict__ sp, const uint32_t* __restrict__ px,
+                                                      float* __restrict__ acc, float* __restrict__ y)
+{
+    const int64_t vi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 16 + (int)(threadIdx.x >> 4);
+    if (vi >= n) return;   // whole group
+    const int l = (int)(threadIdx.x & 15);
+    const VoxDev d = vd[vi];
+    double a = 0.0;
+    for (int q = l; q < d.m; q += 16) a += sp[d.start + q];
+    a = dgroup_sum_d<16>(a);
+    const double S = __shfl(a, (int)(threadIdx.x & 48), 64);
+    if (y)
+        for (int q = l; q < d.m; q += 16) y[px[d.start + q]] = (float)(S - sp[d.start + q]);
+    if (l == 0) acc[d.v] += (float)S;
+}
+
+hipError_t launch_kf_voxel_rev(mrf_ctx* c, const double* sp, float* acc, float* y, hipStream_t s)
+{
+    if (c->n_kf_vox <= 0) return hipSuccess;
+    ProfScope ps(c, KID_KFVOX, s);
+    hipLaunchKernelGGL(kf_voxel_rev_k, dim3(nblk(c->n_kf_vox, 16)), dim3(256), 0, s, (const VoxDev*)c->b_kf_vox.p,
+                       c->n_kf_vox, sp, (const uint32_t*)c->b_pair_x.p, acc, y);
     return hipGetLastError();
 }
 

@@ -217,16 +217,19 @@ class RayMRF:
             check(self._L.mrf_infer_sensor(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
                                            int(sweeps), keep, stream_handle(stream)), "mrf_infer_sensor")
 
-    def infer_keyframe_avg(self, prior_logit, sigma_table, sweeps: int, stream=None, bias_table=None):
+    def infer_keyframe_avg(self, prior_logit, sigma_table, sweeps: int, stream=None, bias_table=None,
+                           keep_checkpoints: bool = False):
         """K sweeps with per-keyframe averaged messages (Sec. IV-A); needs a
-        build with keyframe_average=True.  No reverse pass."""
+        build with keyframe_average=True.  keep_checkpoints keeps the pair
+        averages the reverse pass (``backward``) rebuilds the sweeps from."""
         self._vec(prior_logit, self.n_voxels, "prior_logit")
         nt = self.table_entries
         self._vec(sigma_table, nt, "sigma_table")
         if bias_table is not None:
             self._vec(bias_table, nt, "bias_table")
         check(self._L.mrf_infer_keyframe_avg(self._h, ptr(prior_logit), ptr(sigma_table), ptr(bias_table),
-                                             int(sweeps), stream_handle(stream)), "mrf_infer_keyframe_avg")
+                                             int(sweeps), 1 if keep_checkpoints else 0, stream_handle(stream)),
+              "mrf_infer_keyframe_avg")
 
     def marginals(self, stream=None):
         p = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device)
@@ -379,19 +382,26 @@ class RayMRF:
 
 
 class MRFInfer(torch.autograd.Function):
-    """logit = MRFInfer.apply(mrf, prior_logit, sigma_table, sweeps[, bias_table])
+    """logit = MRFInfer.apply(mrf, prior_logit, sigma_table, sweeps[, bias_table[, keyframe_average]])
 
     Forward runs ``sweeps`` BP sweeps keeping per-sweep checkpoints and returns
     the marginal log-odds; backward runs the library's reverse pass and
-    returns gradients for the prior log-odds, the 64-bin sigma table and, when
-    given, the 64-bin depth-bias table of the sensor model.
+    returns gradients for the prior log-odds, the sigma table and, when given,
+    the depth-bias table of the sensor model.  keyframe_average: the sweeps
+    with per-keyframe averaged messages (Sec. IV-A; the build must prepare
+    them).
     """
 
     @staticmethod
-    def forward(ctx, mrf: RayMRF, prior_logit, sigma_table, sweeps: int, bias_table=None):
-        mrf.infer(prior_logit.detach().contiguous(), sigma_table.detach().contiguous(), sweeps,
-                  keep_checkpoints=True,
-                  bias_table=None if bias_table is None else bias_table.detach().contiguous())
+    def forward(ctx, mrf: RayMRF, prior_logit, sigma_table, sweeps: int, bias_table=None,
+                keyframe_average: bool = False):
+        bias = None if bias_table is None else bias_table.detach().contiguous()
+        if keyframe_average:
+            mrf.infer_keyframe_avg(prior_logit.detach().contiguous(), sigma_table.detach().contiguous(), sweeps,
+                                   bias_table=bias, keep_checkpoints=True)
+        else:
+            mrf.infer(prior_logit.detach().contiguous(), sigma_table.detach().contiguous(), sweeps,
+                      keep_checkpoints=True, bias_table=bias)
         _, logit = mrf.marginals()
         ctx.mrf = mrf
         ctx.generation = mrf.generation()   # a later forward on the same context invalidates this node
@@ -407,4 +417,4 @@ class MRFInfer(torch.autograd.Function):
                                generation=ctx.generation)
         ds = None if out[1] is None else out[1].view(ctx.table_shape)
         db = out[2].view(ctx.table_shape) if want_bias else None
-        return None, out[0], ds, None, db
+        return None, out[0], ds, None, db, None

@@ -159,7 +159,7 @@ def test_keyframe_average_single_keyframe_keeps_prior(RayMRF):
     m.close()
 
 
-def test_keyframe_average_needs_the_build_flag_and_has_no_reverse_pass(RayMRF):
+def test_keyframe_average_needs_the_build_flag_and_checkpoints_for_a_reverse_pass(RayMRF):
     from paper_2006_03512_amd._lib import MRF_ESTATE, MRFError
     sc = S.make_fd()
     m = RayMRF()
