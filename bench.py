@@ -70,19 +70,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def trim_to_memory(m, scs, K, backward, mem_frac):
+def trim_to_memory(m, scs, K, backward, mem_frac, keyframe_average=False):
     """The count pass decides: with B bytes per edge slot (the ten per-edge arrays of
     the build and sweeps, 37 bytes, the radix sort's tile histograms and offsets,
     under one byte, plus K - 1 checkpointed ray messages of 4 bytes for the reverse
     pass) and the per-voxel and per-ray arrays, drop the last frame of the room
     holding the most slots until the whole step fits mem_frac of the GPU's memory.
+    With per-keyframe averaged messages the checkpoints are per (keyframe, voxel)
+    pair instead (counted as 2 bytes per slot) and three per-edge arrays are
+    added (chord length, weight share in list and in slot order, 12 bytes), and
+    the batch must stay under 2^32 slots (one group).
     Returns the trimmed scenes and a record of what was done."""
     import dataclasses
 
     import numpy as np
     import torch
     slots, edges = m.count(scs)
-    per_slot = 38 + (4 * (K - 1) if backward else 0)
+    if keyframe_average:
+        per_slot = 38 + 12 + (2 if backward else 0)
+    else:
+        per_slot = 38 + (4 * (K - 1) if backward else 0)
+    max_slots = (1 << 32) - 1 if keyframe_average else None
     V = sum(x.grid.n_voxels for x in scs)
     per_voxel = 4 * 3 + 8 + 24 + 8 + (8 * (K - 1) if backward else 8)
     total_mem = torch.cuda.get_device_properties(0).total_memory
@@ -94,7 +102,7 @@ def trim_to_memory(m, scs, K, backward, mem_frac):
         S = sum(int(slots[off[i]: off[i] + F[i]].sum()) for i in range(len(scs)))
         R = sum(F[i] * x.depth[0].size for i, x in enumerate(scs))
         return per_slot * S + per_voxel * V + 12 * R, S
-    while need()[0] > budget:
+    while need()[0] > budget or (max_slots is not None and need()[1] > max_slots):
         big = max(range(len(scs)), key=lambda i: (int(slots[off[i]: off[i] + F[i]].sum()) if F[i] > 1 else -1))
         if F[big] <= 1:
             break
@@ -280,7 +288,7 @@ def main():
     m = RayMRF(0)
     trim = None
     if args.workload == "c5":
-        scs, trim = trim_to_memory(m, scs, K, backward, args.mem_frac)
+        scs, trim = trim_to_memory(m, scs, K, backward, args.mem_frac, kf_step)
         n_frames = sum(x.n_frames for x in scs)
         log(f"count pass: stated frames {trim['stated_frames']} ({trim['stated_slots']} slots, "
             f"~{trim['stated_estimated_gb']} GB), run with {trim['frames']} ({trim['slots']} slots, "
@@ -338,15 +346,27 @@ def main():
 
     st = m.stats()
     kf_pairs = st.n_keyframe_pairs
-    build_ms = timed(lambda: m.build_resident(), 1)
+    if kf_step:   # the step's own scheme: per-keyframe averaged messages on the kept build
+        def fwd():
+            m.infer_keyframe_avg(theta, sigma, K)
+
+        build_ms = timed(lambda: m.build_resident(keyframe_average=True), 1)
+    else:
+        def fwd():
+            m.infer(theta, sigma, K)
+
+        build_ms = timed(lambda: m.build_resident(), 1)
     m.set_schedule("graph")
-    fwd_graph_ms = timed(lambda: m.infer(theta, sigma, K))
+    fwd_graph_ms = timed(fwd)
     m.set_schedule("plain")
-    fwd_plain_ms = timed(lambda: m.infer(theta, sigma, K))
+    fwd_plain_ms = timed(fwd)
     m.set_schedule("graph")
     bwd_ms = None
     if backward:
-        m.infer(theta, sigma, K, keep_checkpoints=True)
+        if kf_step:
+            m.infer_keyframe_avg(theta, sigma, K, keep_checkpoints=True)
+        else:
+            m.infer(theta, sigma, K, keep_checkpoints=True)
         p, _ = m.marginals()
         gl = (p - y) / p.numel()
         bwd_ms = timed(lambda: m.backward(gl))
@@ -443,9 +463,8 @@ def main():
             m.build_resident()   # back to the plain graph for the profile below
 
     # ---- roofline of the dominant kernel (HIP events around each launch)
-    if kf_step and kf_fwd_ms is None:   # --quick: the keyframe-average build and sweeps only
-        m.build_resident(keyframe_average=True)
-        kf_fwd_ms = timed(lambda: m.infer_keyframe_avg(theta, sigma, K))
+    if kf_step and kf_fwd_ms is None:   # --quick: the breakdown above timed the keyframe-average scheme
+        kf_build_ms, kf_fwd_ms, kf_plain_ms, kf_bwd_ms = build_ms, fwd_graph_ms, fwd_plain_ms, bwd_ms
     if kf_step:
         m.infer_keyframe_avg(theta, sigma, K)
     else:
