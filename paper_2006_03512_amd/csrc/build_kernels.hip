@@ -1415,17 +1415,23 @@ __device__ __forceinline__ int slot_frame(const int64_t* __restrict__ fs, int nf
     return lo;
 }
 
+// the frame (keyframe) of every entry of the voxel -> ray list
+__global__ void entry_frame_k(const uint32_t* __restrict__ vedge, int64_t n, const int64_t* __restrict__ fs, int nf,
+                              uint16_t* __restrict__ fr)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        fr[j] = (uint16_t)slot_frame(fs, nf, vedge[j]);
+}
+
 // 1 where entry j of the voxel -> ray list starts a (keyframe, voxel) run
 struct LoadPairStart {
-    const uint32_t* vedge;
-    const uint32_t* keys;   // sorted voxel keys, aligned with vedge
-    const int64_t* fs;
-    int nf;
+    const uint16_t* fr;     // frame of each entry
+    const uint32_t* keys;   // sorted voxel keys, aligned with the list
     __device__ int64_t operator()(int64_t j) const
     {
         if (j == 0) return 1;
         if (keys[j] != keys[j - 1]) return 1;
-        return slot_frame(fs, nf, vedge[j]) != slot_frame(fs, nf, vedge[j - 1]) ? 1 : 0;
+        return fr[j] != fr[j - 1] ? 1 : 0;
     }
 };
 
@@ -1444,7 +1450,7 @@ __global__ void pair_init_k(const LoadPairStart ld, int64_t E, const uint32_t* _
     if (!ld(j)) return;
     const uint32_t p = pos[j];
     pstart[p] = (uint32_t)j;
-    const int f = slot_frame(ld.fs, ld.nf, ld.vedge[j]);
+    const int f = ld.fr[j];
     px[p] = (uint32_t)(xb[f] + (int64_t)key_to_voxel(scenes, ns, ld.keys[j]));
 }
 
@@ -1524,9 +1530,15 @@ hipError_t build_keyframe_pairs(mrf_ctx* c, hipStream_t s)
     if ((e = ensure(c->b_kfx, sizeof(float) * (size_t)(nx > 0 ? nx : 1))) != hipSuccess) return e;
 
     // pair starts: exclusive count over the voxel -> ray list (b_lam, E + 1 entries),
-    // keys sorted in b_lambar from the radix sort
+    // keys sorted in b_lambar from the radix sort, each entry's frame in b_gsum
     const uint32_t* vedge = (const uint32_t*)c->b_vedge.p;
-    const LoadPairStart ld{vedge, (const uint32_t*)c->b_lambar.p, d_fs, nf};
+    uint16_t* fr = (uint16_t*)c->b_gsum.p;   // 2 E bytes of a per-slot array free during the build
+    if (E > 0) {
+        int64_t b = cdiv(E, 256);
+        if (b > 65536) b = 65536;
+        hipLaunchKernelGGL(entry_frame_k, dim3((unsigned)b), dim3(256), 0, s, vedge, E, (const int64_t*)d_fs, nf, fr);
+    }
+    const LoadPairStart ld{fr, (const uint32_t*)c->b_lambar.p};
     uint32_t* pos = (uint32_t*)c->b_lam.p;
     const size_t sb = scan_tmp_bytes(E);
     if ((e = ensure(c->b_misc, sb > c->b_misc.cap ? sb : c->b_misc.cap)) != hipSuccess) return e;
