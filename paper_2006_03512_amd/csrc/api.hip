@@ -88,9 +88,15 @@ namespace mrf {
 void set_error(const std::string& msg) { g_err = msg; }
 
 // Set while mrf_add_frames runs: a buffer that ensure() has to grow then gets
-// room for four more growths of the same size, so that frames added one at a
-// time reallocate rarely.
+// room for four more growths of the same size (at most doubling it), so that
+// frames added one at a time reallocate rarely.
 static thread_local int g_grow_room = 0;
+
+static size_t with_room(size_t need, size_t prev)
+{
+    const size_t step = need > prev ? need - prev : 0;
+    return step < need / 4 ? need + 4 * step : 2 * need;
+}
 
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
@@ -100,7 +106,7 @@ hipError_t ensure(DevBuf& b, size_t bytes)
     if (b.p) hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
-    const size_t want = g_grow_room && old > 0 ? bytes + 4 * (bytes - old) : bytes;
+    const size_t want = g_grow_room && old > 0 ? with_room(bytes, old) : bytes;
     hipError_t e = hipMalloc(&b.p, want);
     if (e == hipSuccess) {
         b.cap = want;
@@ -687,13 +693,13 @@ int mrf_count(mrf_ctx* c, const mrf_scene* scenes, int32_t n_scenes, const mrf_b
 }
 
 // Grows b to hold `need` bytes, keeping its first `keep` bytes; a buffer that has
-// to move gets room for four more additions of the same size, so that frames
-// added one at a time reallocate rarely.
+// to move gets room for four more additions of the same size (at most doubling
+// it), so that frames added one at a time reallocate rarely.
 static hipError_t grow_keep(DevBuf& b, size_t need, size_t keep, hipStream_t s)
 {
     if (need == 0) need = 16;
     if (b.p && b.cap >= need) return hipSuccess;
-    const size_t grown = need + 4 * (need > keep ? need - keep : 0);
+    const size_t grown = with_room(need, keep);
     void* p = nullptr;
     size_t got = grown;
     hipError_t e = hipMalloc(&p, grown);
