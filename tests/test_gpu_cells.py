@@ -6,7 +6,7 @@ float32-storage spread) and the gradients of the prior and of every region's sig
 (1e-3 relative, by norm and per entry); equal rows in every region reproduce
 the single-table call bit for bit, with region gradients that sum to its
 gradients; a batch of scenes with different image sizes; per-keyframe
-averaged messages with region tables."""
+averaged messages with region tables, their gradients included."""
 import numpy as np
 import pytest
 
@@ -204,13 +204,25 @@ def test_region_tables_with_keyframe_averages(oracle, RayMRF):
     key, w = oracle.edge_keyframes_and_lengths(G, sc)
     th = sc.prior_logit()
     ref = oracle.infer_keyframe_average(G, th.astype(np.float64), sig64, 8, key, w, bias_table=mu64,
-                                        table_index=idx)
+                                        table_index=idx, keep_history=True)
+    y = sc.occupancy().astype(np.float64)
+    tb, sb, _, bb = oracle.backward_keyframe_average(G, ref, oracle.bce_logit_grad(ref.L, y), sig64, key, w,
+                                                     bias_table=mu64, want_bias=True, table_index=idx)
+    from paper_2006_03512_amd.mrf import MRFInfer
     m = RayMRF()
     m.build(sc, keyframe_average=True)
     m.set_sensor_cells(20)
-    m.infer_keyframe_avg(torch.from_numpy(th).cuda(), torch.from_numpy(sig32).cuda(), 8,
-                         bias_table=torch.from_numpy(mu32).cuda())
-    p = m.marginals()[0].cpu().numpy()
+    thd = torch.from_numpy(th).cuda().requires_grad_(True)
+    sgd = torch.from_numpy(sig32).cuda().requires_grad_(True)
+    bsd = torch.from_numpy(mu32).cuda().requires_grad_(True)
+    logit = MRFInfer.apply(m, thd, sgd, 8, bsd, True)
+    p = torch.sigmoid(logit.detach()).cpu().numpy()
     err = np.abs(p - ref.p)
     assert err.max() <= TOL_P, err.max()
+    loss = torch.nn.functional.binary_cross_entropy_with_logits(logit, torch.from_numpy(y.astype(np.float32)).cuda())
+    loss.backward()
+    for what, got, want in (("theta", thd.grad, tb), ("sigma", sgd.grad, sb), ("bias", bsd.grad, bb)):
+        r, e = _grad_check(got.cpu().numpy(), want)
+        _say(f"  keyframe averages, {what} rel {r:.2e} entry {e:.2e}")
+        assert r <= TOL_G and e <= TOL_G, (what, r, e)
     m.close()
