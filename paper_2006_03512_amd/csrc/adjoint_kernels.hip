@@ -274,9 +274,9 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
                 ve[r] = excl_value(vc[r], pe[r], vb[r], eb.has_own);
             }
         }
-        tile_to_lds<NT, NR, IPL>(sa, nf, vt);
-        tile_to_lds<NT, NR, IPL>(sb, nf, vg);
-        if (RPW > 1) tile_to_lds<NT, NR, IPL>(se, nf, ve);
+        tile_to_lds<NT, NR, IPL>(sa, vt);
+        tile_to_lds<NT, NR, IPL>(sb, vg);
+        if constexpr (RPW > 1) tile_to_lds<NT, NR, IPL>(se, ve);
     }
     __syncthreads();
     // g-bar sums of earlier sweeps, fetched before the scans so that their
@@ -293,9 +293,9 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
 #pragma unroll
         for (int j = 0; j < IPL; ++j)   // column rows are inside the LDS tile even past the ray
             load_step(sa[cb + kTile * j], sb[cb + kTile * j], i0 + j < m, al[j], be[j], gg[j]);
-        if (RPW == 1) {
+        if constexpr (RPW == 1) {
             __syncthreads();   // every group has its lambda: reuse sa for ell-bar
-            tile_to_lds<NT, NR, IPL>(sa, nf, ve);
+            tile_to_lds<NT, NR, IPL>(sa, ve);
             __syncthreads();
         }
         const float* sev = RPW > 1 ? se : sa;
@@ -318,8 +318,9 @@ __global__ __launch_bounds__(kTile * G / RPW) void ray_adj_lds_k(const uint32_t*
         }
     }
     __syncthreads();
-    tile_store<NT, NR, IPL>(lambar, td.base, nf, [&](int, int at) { return sa[at]; });
-    tile_store<NT, NR, IPL>(gsum, td.base, nf, [&](int r, int at) { return first ? sb[at] : vs[r] + sb[at]; });
+    tile_store2<NT, NR, IPL>(
+        lambar, [&](int, int at) { return sa[at]; }, gsum,
+        [&](int r, int at) { return first ? sb[at] : vs[r] + sb[at]; }, td.base, nf);
 }
 
 // The reverse pass's per-edge inputs: the voxel totals less the own terms, or

@@ -723,8 +723,8 @@ __global__ __launch_bounds__(kTile * G) void ray_lds_k(const uint32_t* __restric
 #pragma unroll
             for (int r = 0; r < IPL; ++r) vt[r] = excl_value(vc[r], vp[r], vo[r], lam.has_own);
         }
-        tile_to_lds<NT, IPL, IPL>(sl, nf, vt);
-        tile_to_lds<NT, IPL, IPL>(sg, nf, vg);
+        tile_to_lds<NT, IPL, IPL>(sl, vt);
+        tile_to_lds<NT, IPL, IPL>(sg, vg);
     }
     __syncthreads();
     if (__ballot(m > 0)) {   // skip waves whose rays are all empty

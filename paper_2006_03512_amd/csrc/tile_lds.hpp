@@ -41,40 +41,74 @@ __device__ __forceinline__ int lds_col(int i0, int gl, int i)
 }
 
 // A block of NT threads moves a tile's nf = 16 len floats (nf <= NT NR) in NR
-// rounds.  With NR a multiple of 4, thread t handles four consecutive floats per
-// group of rounds, idx = 4 (t + q NT) + b for round r = 4 q + b (16-byte loads
-// and stores); otherwise idx = t + r NT.  Loads go through registers so that
-// every round's load is issued before the first wait; indices past nf are
-// clamped to the tile's last floats and their values dropped.  The tile starts
-// 64-byte aligned (tile bases are multiples of 16 slots).
+// rounds, W = 4, 2 or 1 consecutive floats per access (the widest that
+// divides NR): thread t handles idx = W (t + q NT) + b for round r = W q + b
+// (16- or 8-byte loads and stores).  Loads go through registers so that every
+// round's load is issued before the first wait; indices past nf are clamped to
+// the tile's last floats and their values dropped.  The tile starts 64-byte
+// aligned (tile bases are multiples of 16 slots), and nf is a multiple of 16.
+template <int NR>
+constexpr int tile_vec()
+{
+    return NR % 4 == 0 ? 4 : NR % 2 == 0 ? 2 : 1;
+}
+
 template <int NT, int NR>
 __device__ __forceinline__ int tile_idx(int r)
 {
-    if constexpr (NR % 4 == 0)
-        return 4 * ((int)threadIdx.x + (r >> 2) * NT) + (r & 3);
-    else
-        return (int)threadIdx.x + r * NT;
+    constexpr int W = tile_vec<NR>();
+    return W * ((int)threadIdx.x + (r / W) * NT) + (r % W);
+}
+
+// LDS word (layout lds_at<IPL>) of this thread's item of round r
+template <int NT, int NR, int IPL>
+__device__ __forceinline__ int tile_lds_word(int r)
+{
+    const int idx = tile_idx<NT, NR>(r);
+    return lds_at<IPL>(idx >> 4, idx & (kTile - 1));
+}
+
+template <int W, class T>
+struct VecT;
+template <class T>
+struct VecT<1, T> {
+    T v[1];
+};
+template <class T>
+struct alignas(8) VecT<2, T> {
+    T v[2];
+};
+template <class T>
+struct alignas(16) VecT<4, T> {
+    T v[4];
+};
+
+// Element iw (of W items) after the uniform base p, addressed by a 32-bit
+// lane offset (tiles hold at most 2^15 items), so that the uniform base stays
+// in scalar registers and every array of a round shares one offset.
+template <int W, class T>
+__device__ __forceinline__ const VecT<W, T>& vec_at(const T* p, int iw)
+{
+    return *(const VecT<W, T>*)((const char*)p + (uint32_t)iw * (uint32_t)(W * sizeof(T)));
+}
+template <int W, class T>
+__device__ __forceinline__ VecT<W, T>& vec_at(T* p, int iw)
+{
+    return *(VecT<W, T>*)((char*)p + (uint32_t)iw * (uint32_t)(W * sizeof(T)));
 }
 
 template <int NT, int NR, class T>
 __device__ __forceinline__ void tile_fetch_t(const T* __restrict__ src, int64_t base, int nf, T (&v)[NR])
 {
     static_assert(sizeof(T) == 4, "32-bit items");
-    if constexpr (NR % 4 == 0) {
-        using V4 = typename std::conditional<std::is_same<T, float>::value, float4, int4>::type;
-        const V4* p = (const V4*)(src + base);
-        const int n4 = nf >> 2;
+    constexpr int W = tile_vec<NR>();
+    const T* p = src + base;
+    const int nw = nf / W;
 #pragma unroll
-        for (int q = 0; q < NR / 4; ++q) {
-            const V4 w = p[min((int)threadIdx.x + q * NT, n4 - 1)];
-            v[4 * q] = w.x;
-            v[4 * q + 1] = w.y;
-            v[4 * q + 2] = w.z;
-            v[4 * q + 3] = w.w;
-        }
-    } else {
+    for (int q = 0; q < NR / W; ++q) {
+        const VecT<W, T> w = vec_at<W>(p, min((int)threadIdx.x + q * NT, nw - 1));
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = src[base + min((int)threadIdx.x + r * NT, nf - 1)];
+        for (int b = 0; b < W; ++b) v[W * q + b] = w.v[b];
     }
 }
 
@@ -91,28 +125,44 @@ __device__ __forceinline__ void tile_fetch_i(const int32_t* __restrict__ src, in
 }
 
 // Values of the LDS image (layout lds_at<IPL>) to global memory, in the
-// mapping of tile_idx: 16-byte stores when NR is a multiple of 4.
+// mapping of tile_idx, for one destination or (TWO) two sharing each access
+// group's branch and LDS words: val(r, word) is round r's value from LDS word
+// `word`.
+template <int NT, int NR, int IPL, bool TWO, class F1, class F2>
+__device__ __forceinline__ void tile_store_t(float* __restrict__ d1, F1 v1, float* __restrict__ d2, F2 v2,
+                                             int64_t base, int nf)
+{
+    constexpr int W = tile_vec<NR>();
+    float* p1 = d1 + base;
+    float* p2 = d2 + (TWO ? base : 0);
+#pragma unroll
+    for (int q = 0; q < NR / W; ++q) {
+        const int iw = (int)threadIdx.x + q * NT;
+        if (W * iw < nf) {
+            VecT<W, float> a, b;
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int at = tile_lds_word<NT, NR, IPL>(W * q + e);
+                a.v[e] = v1(W * q + e, at);
+                if constexpr (TWO) b.v[e] = v2(W * q + e, at);
+            }
+            vec_at<W>(p1, iw) = a;
+            if constexpr (TWO) vec_at<W>(p2, iw) = b;
+        }
+    }
+}
+
 template <int NT, int NR, int IPL, class F>
 __device__ __forceinline__ void tile_store(float* __restrict__ dst, int64_t base, int nf, F val)
 {
-    if constexpr (NR % 4 == 0) {
-        float4* p = (float4*)(dst + base);
-#pragma unroll
-        for (int q = 0; q < NR / 4; ++q) {
-            const int i4 = (int)threadIdx.x + q * NT;
-            if (4 * i4 < nf) {
-                const int k = i4 >> 2, l0 = (i4 & 3) << 2;
-                p[i4] = make_float4(val(4 * q, lds_at<IPL>(k, l0)), val(4 * q + 1, lds_at<IPL>(k, l0 + 1)),
-                                    val(4 * q + 2, lds_at<IPL>(k, l0 + 2)), val(4 * q + 3, lds_at<IPL>(k, l0 + 3)));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int idx = (int)threadIdx.x + r * NT;
-            if (idx < nf) dst[base + idx] = val(r, lds_at<IPL>(idx >> 4, idx & (kTile - 1)));
-        }
-    }
+    tile_store_t<NT, NR, IPL, false>(dst, val, dst, val, base, nf);
+}
+
+template <int NT, int NR, int IPL, class F1, class F2>
+__device__ __forceinline__ void tile_store2(float* __restrict__ d1, F1 v1, float* __restrict__ d2, F2 v2,
+                                            int64_t base, int nf)
+{
+    tile_store_t<NT, NR, IPL, true>(d1, v1, d2, v2, base, nf);
 }
 
 // Per-edge value tot[col] - own (the voxel's total less the edge's own term;
@@ -127,14 +177,15 @@ __device__ __forceinline__ float excl_value(int32_t col, float2 t, float own, in
 }
 
 // The fetched values into the LDS image of the tile (layout lds_at<IPL>).
-template <int NT, int NR, int IPL>
-__device__ __forceinline__ void tile_to_lds(float* __restrict__ lds, int nf, const float (&v)[NR])
+// Every round is written, also past nf: the image holds NT NR words, and its
+// words past the tile are never read as data (the rays' steps end inside it).
+// No branch, so the rounds' LDS words are computed once for all arrays.
+template <int NT, int NR, int IPL, int N>
+__device__ __forceinline__ void tile_to_lds(float (&lds)[N], const float (&v)[NR])
 {
+    static_assert(N >= NT * NR, "the LDS image holds every round");
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int idx = tile_idx<NT, NR>(r);
-        if (idx < nf) lds[lds_at<IPL>(idx >> 4, idx & (kTile - 1))] = v[r];
-    }
+    for (int r = 0; r < NR; ++r) lds[tile_lds_word<NT, NR, IPL>(r)] = v[r];
 }
 
 // steps of tile lane i (0 for pixels outside the image)
