@@ -43,16 +43,28 @@ WORKLOADS = {
 }
 
 
-# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script
-# (FETCH_SIZE, then WRITE_SIZE; each run also times one plain copy through
-# --calib-copy-mib, which calibrates the counter: FETCH_SIZE read 0.5 x the bytes
-# the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid only while the
-# sources that kernel is compiled from hash to `src_sha256`; otherwise traffic
-# is reported as null.
-TRAFFIC = {"workload": "c4", "kernel": "ray_adj_lds_k<64,5,2>",
-           "sources": ['adjoint_kernels.hip', 'dev_common.hpp', 'tile_lds.hpp', 'mrf_internal.hpp'],
-           "src_sha256": "c209f1c648f9903846bc8054433ed822a55e0beb7200682b1542450f9ba740d2",
-           "fetch_bytes": 1.2221e+10, "write_bytes": 4.666e+09}
+# HBM traffic per launch (read, written bytes) of the kernels that can be the
+# dominant one on c4 (the top kernels by time per step, and every launch shape
+# the autotuner may pick for their ray classes), from two rocprofv3 --pmc runs
+# of this script (FETCH_SIZE, then WRITE_SIZE; each run also times one plain
+# copy through --calib-copy-mib, which calibrates the counter: FETCH_SIZE read
+# 0.5 x the bytes the copy reads, WRITE_SIZE 1.0 x the bytes it writes).  Valid
+# only while the kernel sources hash to `src_sha256`; otherwise traffic is
+# reported as null.
+TRAFFIC = {"workload": "c4",
+           "sources": ['adjoint_kernels.hip', 'sweep_kernels.hip', 'dev_common.hpp', 'tile_lds.hpp',
+                       'mrf_internal.hpp'],
+           "src_sha256": "71951750018d9736bc25e48395c0627b91ff24567a80f3d7edcd2f3150430a77",
+           "kernels": {
+                       "ray_adj_lds_k<32,10,1>": [1.2762e+10, 4.666e+09],
+                       "ray_adj_lds_k<32,10,2>": [1.2233e+10, 4.666e+09],
+                       "ray_adj_lds_k<32,8,1>": [7.1533e+09, 2.7666e+09],
+                       "ray_adj_lds_k<32,8,2>": [7.3958e+09, 2.7674e+09],
+                       "ray_adj_lds_k<64,4,1>": [7.3928e+09, 2.7666e+09],
+                       "ray_adj_lds_k<64,4,2>": [7.4075e+09, 2.7666e+09],
+                       "ray_adj_lds_k<64,5,1>": [1.2767e+10, 4.666e+09],
+                       "ray_adj_lds_k<64,5,2>": [1.2779e+10, 4.6661e+09],
+                       "voxel_k<4,16,1>": [8.839e+09, 7.9467e+06]}}
 
 
 def src_sha256(files):
@@ -475,9 +487,9 @@ def main():
     sweep_ms = fwd_graph_ms / K   # one forward sweep in the captured graph (potentials and marginals included)
     fwd_bytes = st.fwd_bytes_per_sweep
     traffic = None
-    if (TRAFFIC is not None and TRAFFIC["workload"] == args.workload and TRAFFIC["kernel"] == dom["name"]
-            and args.frames is None and TRAFFIC["src_sha256"] == src_sha256(TRAFFIC["sources"])):
-        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    if (TRAFFIC["workload"] == args.workload and dom["name"] in TRAFFIC["kernels"] and args.frames is None
+            and TRAFFIC["src_sha256"] == src_sha256(TRAFFIC["sources"])):
+        traffic = sum(TRAFFIC["kernels"][dom["name"]])
     # the same kernel and the sweeps at the per-edge bytes of the hot-path scope table
     # (ray phase 12, voxel phase 12, ray adjoint 16; a forward sweep 24, forward +
     # reverse 68 per edge and sweep), which leave out the builder's extra per-edge arrays

@@ -1441,16 +1441,20 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
     hipStream_t s = (hipStream_t)stream;
     HCK(hipSetDevice(c->device), "mrf_autotune: hipSetDevice");
     // inputs: the last sweep's messages; outputs go to buffers the reverse pass
-    // initialises before use, so the inference state stays untouched
+    // initialises before use, so the inference state stays untouched.  The
+    // reverse kernels run in the form of every reverse sweep after the first:
+    // an own term in their d/d ell input (any per-voxel pairs and any slot
+    // array serve for timing) and the running g-bar sum read and accumulated.
     const ExclSrc lam = final_lam(c);
-    const ExclSrc eb{(const float2*)c->b_theta2.p, nullptr};   // any d/d ell input serves for timing
+    const ExclSrc eb{(const float2*)c->b_theta2.p, (const float*)c->b_ellbar.p};
     float* ell_out = (float*)c->b_ellbar.p;
     float* lambar = (float*)c->b_lambar.p;
     float* gsum = (float*)c->b_gsum.p;
     hipEvent_t ev[2] = {nullptr, nullptr};
     HCK(hipEventCreate(&ev[0]), "mrf_autotune: event");
     hipError_t e = hipEventCreate(&ev[1]);
-    // after per-keyframe averaged sweeps: their ray phase only (they have no reverse pass)
+    // after per-keyframe averaged sweeps: their ray phase only (the reverse
+    // shapes are tuned on the exact scheme's sweeps)
     const bool kf = c->kf_inferred != 0;
     const KfSrc kfs{(const float*)c->b_kfx.p, (const int64_t*)c->b_kfxb.p};
     for (int adj = 0; adj < (kf ? 1 : 2) && e == hipSuccess; ++adj) {
@@ -1462,7 +1466,7 @@ int mrf_autotune(mrf_ctx* c, int32_t reps, void* stream)
             for (int i = 0; i < ns && e == hipSuccess; ++i) {
                 auto run = [&]() {
                     if (kf) return launch_ray_class_shape_kf(c, q, i, kfs, ell_out, s);
-                    return adj ? launch_adj_class_shape(c, q, i, lam, eb, lambar, gsum, 1, s)
+                    return adj ? launch_adj_class_shape(c, q, i, lam, eb, lambar, gsum, 0, s)
                                : launch_ray_class_shape(c, q, i, lam, ell_out, s);
                 };
                 e = run();   // warm-up
