@@ -308,7 +308,7 @@ __device__ __forceinline__ void vox_store(uint32_t v, double sum, const VoxOut& 
 // before the first wait (more bytes in flight per wave for low degrees).
 // Voxels arrive in brick-major order and blocks are remapped so each XCD
 // takes a contiguous range of them.
-template <int NW, int IPL, int VPW, bool WT = false>
+template <int NW, int IPL, int VPW, bool WT = false, bool MG = false>
 __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev* __restrict__ vd, int64_t n,
                                                                    const uint32_t* __restrict__ vedge,
                                                                    const float* __restrict__ in, VoxOut out,
@@ -316,7 +316,9 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
                                                                    const SlotGroups sg)
 {
     static_assert(NW == 1 || VPW == 1, "several voxels per wave only with one wave per voxel");
-    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // the wave index is uniform across the wave: said so, the voxel descriptors
+    // below become scalar loads and their address and group arithmetic scalar
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
     if constexpr (NW == 1) {
         const int64_t v0 = (lb * 4 + wv) * VPW;
@@ -338,7 +340,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
         }
 #pragma unroll
         for (int u = 0; u < VPW; ++u) {
-            const float* ing = in + group_slot_base(sg, d[u].start);
+            const float* ing = in + (MG ? group_slot_base(sg, d[u].start) : 0);
 #pragma unroll
             for (int k = 0; k < IPL; ++k) x[u][k] = ing[e[u][k]];
         }
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
         if (vi >= n) return;   // whole block
         const VoxDev d = vd[vi];
         const double a = dgroup_sum_d<64>(
-            vox_lane_sum<IPL, WT>(d.start, d.m, wv * 64 * IPL, vedge, in + group_slot_base(sg, d.start), w));
+            vox_lane_sum<IPL, WT>(d.start, d.m, wv * 64 * IPL, vedge, in + (MG ? group_slot_base(sg, d.start) : 0), w));
         __shared__ double wsum[NW];
         if (l == 0) wsum[wv] = a;
         __syncthreads();
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
 // Voxels of at most G edges (G = 16 or 32): 64 / G lane groups per wave, 256
 // / G per block, each group summing VPG consecutive voxels of the list (lane
 // l holds edge l of each; group reductions), every load issued first.
-template <int G, int VPG, bool WT = false>
+template <int G, int VPG, bool WT = false, bool MG = false>
 __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ vd, int64_t n,
                                                      const uint32_t* __restrict__ vedge, const float* __restrict__ in,
                                                      VoxOut out, const float* __restrict__ w, const SlotGroups sg)
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
         for (int u = 0; u < VPG; ++u) wt[u] = w[d[u].start + min(l, d[u].m - 1)];
     }
 #pragma unroll
-    for (int u = 0; u < VPG; ++u) x[u] = in[group_slot_base(sg, d[u].start) + e[u]];
+    for (int u = 0; u < VPG; ++u) x[u] = in[(MG ? group_slot_base(sg, d[u].start) : 0) + e[u]];
 #pragma unroll
     for (int u = 0; u < VPG; ++u) {
         const double t = WT ? (double)x[u] * (double)wt[u] : (double)x[u];
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(256) void voxel_small_k(const VoxDev* __restrict__ 
 // One 1024-thread block per voxel of degree above the largest single-pass
 // class: wave w sums pieces w, w + 16, ... of 1024 edges in order, and the 16
 // wave sums are added in wave order.
-template <bool WT = false>
+template <bool WT = false, bool MG = false>
 __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict__ vd, int64_t n,
                                                         const uint32_t* __restrict__ vedge,
                                                         const float* __restrict__ in, VoxOut out,
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const VoxDev d = vd[b];
     const int nch = (d.m + kVoxChunk - 1) / kVoxChunk;
-    const float* ing = in + group_slot_base(sg, d.start);
+    const float* ing = in + (MG ? group_slot_base(sg, d.start) : 0);
     double a = 0.0;
     for (int c = wv; c < nch; c += 16)
         a += vox_lane_sum<kVoxChunk / 64, WT>(d.start, d.m, c * kVoxChunk, vedge, ing, w);
@@ -434,25 +436,37 @@ __global__ __launch_bounds__(1024) void voxel_chunked_k(const VoxDev* __restrict
 }
 
 // Class K of a segment list (voxels, or keyframe pairs with weights w) with n
-// work items described by desc.
+// work items described by desc.  MG: several slot groups (each voxel's list
+// entries are relative to its group's first slot); a single group, the common
+// case, skips the group lookup.
+template <int K, bool WT, bool MG>
+static void launch_seg_class_t(const VoxDev* desc, int64_t n, const uint32_t* vedge, const SlotGroups& sg,
+                               const float* in, VoxOut out, const float* w, hipStream_t s)
+{
+    constexpr int NW = kVoxNW[K];
+    if constexpr (NW == 0) {
+        constexpr int G = kVoxCap[K];
+        constexpr int VPG = kVoxVPW[K];
+        hipLaunchKernelGGL((voxel_small_k<G, VPG, WT, MG>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s, desc, n,
+                           vedge, in, out, w, sg);
+    } else {
+        constexpr int IPL = kVoxCap[K] / (64 * NW);
+        constexpr int VPW = kVoxVPW[K];
+        const unsigned blocks = NW == 1 ? nblk(n, 4 * VPW) : (unsigned)n;
+        hipLaunchKernelGGL((voxel_k<NW, IPL, VPW, WT, MG>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s, desc,
+                           n, vedge, in, out, w, sg);
+    }
+}
+
 template <int K, bool WT>
 static void launch_seg_class(const VoxDev* desc, int64_t n, const uint32_t* vedge, const SlotGroups& sg,
                              const float* in, VoxOut out, const float* w, hipStream_t s)
 {
     if (n <= 0) return;
-    constexpr int NW = kVoxNW[K];
-    if constexpr (NW == 0) {
-        constexpr int G = kVoxCap[K];
-        constexpr int VPG = kVoxVPW[K];
-        hipLaunchKernelGGL((voxel_small_k<G, VPG, WT>), dim3(nblk(n, 256 / G * VPG)), dim3(256), 0, s, desc, n, vedge,
-                           in, out, w, sg);
-    } else {
-        constexpr int IPL = kVoxCap[K] / (64 * NW);
-        constexpr int VPW = kVoxVPW[K];
-        const unsigned blocks = NW == 1 ? nblk(n, 4 * VPW) : (unsigned)n;
-        hipLaunchKernelGGL((voxel_k<NW, IPL, VPW, WT>), dim3(blocks), dim3(NW == 1 ? 256 : 64 * NW), 0, s, desc, n,
-                           vedge, in, out, w, sg);
-    }
+    if (sg.n > 1)
+        launch_seg_class_t<K, WT, true>(desc, n, vedge, sg, in, out, w, s);
+    else
+        launch_seg_class_t<K, WT, false>(desc, n, vedge, sg, in, out, w, s);
 }
 
 template <bool WT>
@@ -460,7 +474,12 @@ static void launch_seg_chunked(const VoxDev* desc, int64_t n, const uint32_t* ve
                                const float* in, VoxOut out, const float* w, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(voxel_chunked_k<WT>, dim3((unsigned)n), dim3(1024), 0, s, desc, n, vedge, in, out, w, sg);
+    if (sg.n > 1)
+        hipLaunchKernelGGL((voxel_chunked_k<WT, true>), dim3((unsigned)n), dim3(1024), 0, s, desc, n, vedge, in, out,
+                           w, sg);
+    else
+        hipLaunchKernelGGL((voxel_chunked_k<WT, false>), dim3((unsigned)n), dim3(1024), 0, s, desc, n, vedge, in,
+                           out, w, sg);
 }
 
 template <int K>
