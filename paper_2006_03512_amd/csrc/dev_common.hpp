@@ -473,17 +473,17 @@ __device__ __forceinline__ double readlane_d(double x, int l)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over each group of G = 16, 32 or 64 consecutive lanes in a fixed order
-// (a suffix scan inside each 16-lane row, then the rows of the group in order),
-// valid at the group's first lane.
+// Sum over each group of G = 8, 16, 32 or 64 consecutive lanes in a fixed
+// order (a suffix scan inside each 8- or 16-lane piece of a row, then the rows
+// of the group in order), valid at the group's first lane.
 template <int G>
 __device__ __forceinline__ double dgroup_sum_d(double x)
 {
-    static_assert(G == 16 || G == 32 || G == 64, "groups are rows, half-waves or waves");
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "groups are half-rows, rows, half-waves or waves");
     x = x + dpp_d<DPP_ROW_SHL1>(0.0, x);
     x = x + dpp_d<DPP_ROW_SHL2>(0.0, x);
     x = x + dpp_d<DPP_ROW_SHL4>(0.0, x);
-    x = x + dpp_d<DPP_ROW_SHL8>(0.0, x);
+    if (G >= 16) x = x + dpp_d<DPP_ROW_SHL8>(0.0, x);
     if (G == 32) {
         const double t1 = readlane_d(x, 16), t3 = readlane_d(x, 48);
         x = x + ((threadIdx.x & 32) ? t3 : t1);   // meaningful at lanes 0 and 32

@@ -344,16 +344,40 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void voxel_k(const VoxDev*
 #pragma unroll
             for (int k = 0; k < IPL; ++k) x[u][k] = ing[e[u][k]];
         }
+        double a[VPW];
 #pragma unroll
         for (int u = 0; u < VPW; ++u) {
-            double a = 0.0;
+            a[u] = 0.0;
 #pragma unroll
             for (int k = 0; k < IPL; ++k) {
                 const double t = WT ? (double)x[u][k] * (double)wt[u][k] : (double)x[u][k];
-                a += k * 64 + l < d[u].m ? t : 0.0;
+                a[u] += k * 64 + l < d[u].m ? t : 0.0;
             }
-            a = dgroup_sum_d<64>(a);
-            if (l == 0 && v0 + u < n) vox_store(d[u].v, a, out);
+        }
+        if constexpr (VPW == 1) {
+            const double t = dgroup_sum_d<64>(a[0]);
+            if (l == 0) vox_store(d[0].v, t, out);
+        } else {
+            // the wave's VPW x 64 lane sums transposed through LDS: voxel u
+            // goes to the LG = 64 / VPW lanes [u LG, (u + 1) LG), lane p of
+            // them adding the sums of lanes [p VPW, (p + 1) VPW) in order, then
+            // a group sum over the LG lanes (one reduction for all voxels)
+            constexpr int LG = 64 / VPW;
+            static_assert(LG == 8 || LG == 16, "four or eight voxels per wave");
+            __shared__ double red[4][VPW][64];
+#pragma unroll
+            for (int u = 0; u < VPW; ++u) red[wv][u][l] = a[u];
+            // LDS accesses of one wave complete in order: the fences only keep
+            // the compiler from moving the reads above the writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int u = l / LG, p = l % LG;
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < VPW; ++j) t += red[wv][u][p * VPW + j];
+            t = dgroup_sum_d<LG>(t);   // at the group's first lane
+            if (p == 0 && v0 + u < n) vox_store(vd[v0 + u].v, t, out);
         }
     } else {
         const int64_t vi = lb;
