@@ -60,12 +60,25 @@ __device__ __forceinline__ int tile_idx(int r)
     return W * ((int)threadIdx.x + (r / W) * NT) + (r % W);
 }
 
-// LDS word (layout lds_at<IPL>) of this thread's item of round r
+// LDS word (layout lds_at<IPL>) of the first item of this thread's access
+// group q (rounds W q .. W q + W - 1).  The W items of a group share their row
+// k and start at a lane l0 that is a multiple of W, so item b lies at
+// k 16 + ((l0 + b) ^ x) = (k 16 + (l0 ^ x)) ^ b: one XOR per item instead of
+// the row's division by IPL per item.
+template <int NT, int NR, int IPL>
+__device__ __forceinline__ int tile_lds_group(int q)
+{
+    constexpr int W = tile_vec<NR>();
+    const int idx = W * ((int)threadIdx.x + q * NT);
+    return lds_at<IPL>(idx >> 4, idx & (kTile - 1));
+}
+
+// LDS word of this thread's item of round r
 template <int NT, int NR, int IPL>
 __device__ __forceinline__ int tile_lds_word(int r)
 {
-    const int idx = tile_idx<NT, NR>(r);
-    return lds_at<IPL>(idx >> 4, idx & (kTile - 1));
+    constexpr int W = tile_vec<NR>();
+    return tile_lds_group<NT, NR, IPL>(r / W) ^ (r % W);
 }
 
 template <int W, class T>
@@ -140,9 +153,10 @@ __device__ __forceinline__ void tile_store_t(float* __restrict__ d1, F1 v1, floa
         const int iw = (int)threadIdx.x + q * NT;
         if (W * iw < nf) {
             VecT<W, float> a, b;
+            const int g0 = tile_lds_group<NT, NR, IPL>(q);
 #pragma unroll
             for (int e = 0; e < W; ++e) {
-                const int at = tile_lds_word<NT, NR, IPL>(W * q + e);
+                const int at = g0 ^ e;
                 a.v[e] = v1(W * q + e, at);
                 if constexpr (TWO) b.v[e] = v2(W * q + e, at);
             }
@@ -184,8 +198,13 @@ template <int NT, int NR, int IPL, int N>
 __device__ __forceinline__ void tile_to_lds(float (&lds)[N], const float (&v)[NR])
 {
     static_assert(N >= NT * NR, "the LDS image holds every round");
+    constexpr int W = tile_vec<NR>();
 #pragma unroll
-    for (int r = 0; r < NR; ++r) lds[tile_lds_word<NT, NR, IPL>(r)] = v[r];
+    for (int q = 0; q < NR / W; ++q) {
+        const int g0 = tile_lds_group<NT, NR, IPL>(q);
+#pragma unroll
+        for (int b = 0; b < W; ++b) lds[g0 ^ b] = v[W * q + b];
+    }
 }
 
 // steps of tile lane i (0 for pixels outside the image)
