@@ -651,17 +651,23 @@ size_t radix_tmp_bytes(int64_t n)
     return sizeof(int64_t) * (size_t)(2 * 256 * nch + 256);
 }
 
-// Lanes of a wave holding digit d (of valid items): 8 ballots.
+// Lanes of a wave holding digit d (of valid items): 8 ballots.  Per bit, with
+// s the bit sign-extended (all ones when set, 0 when clear) and m the lanes
+// whose bit is set, the lanes that agree with this lane are ~(m ^ s); each
+// 32-bit half is updated with one three-input bit operation, p & ~(m ^ s)
+// (truth table 0x90 over (p, m, s)), instead of a select of the 64-bit mask.
 __device__ __forceinline__ uint64_t rs_peers(int d, bool valid)
 {
-    uint64_t peers = __ballot(valid);
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t sb = (uint32_t)((int32_t)((uint32_t)d << (31 - b)) >> 31);   // 0 or all ones
+        const uint64_t m = __ballot(sb != 0u);
+        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, sb, 0x90);
+        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), sb, 0x90);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Digit counts of one tile of RS_TILE keys.  Thread t takes RS_IPT
@@ -788,17 +794,33 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
     __shared__ int64_t boff[256];
     __shared__ int32_t dstart[256];
     __shared__ int32_t wcnt[NW][256];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform across the wave
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
     const int64_t start = tile * RS_TILE;
     const int64_t wstart = start + (int64_t)w * WI;
+    // items of this wave below n: item r * 64 + lane is valid iff it is < nvw
+    const int64_t rem = n - wstart;
+    const int nvw = rem <= 0 ? 0 : (rem < WI ? (int)rem : WI);
     uint32_t kr[RS_IPT], vr[RS_IPT];
 #pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
         const int64_t i = wstart + r * 64 + lane;
         const int64_t ic = i < n ? i : n - 1;
         kr[r] = keys_in[ic];
-        vr[r] = vals_in ? vals_in[ic] : (uint32_t)(i - group_slot_base_of_slot(groups, i));
+        if (vals_in) vr[r] = vals_in[ic];
+    }
+    if (!vals_in) {   // first pass: the values are the slots, relative to their group's first slot
+        if (groups.n > 1) {
+#pragma unroll
+            for (int r = 0; r < RS_IPT; ++r) {
+                const int64_t i = wstart + r * 64 + lane;
+                vr[r] = (uint32_t)(i - group_slot_base_of_slot(groups, i));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RS_IPT; ++r) vr[r] = (uint32_t)(wstart + r * 64 + lane);
+        }
     }
     const int64_t o0 = offs[tile * 256 + tid];
     const int64_t cnt = hist[tile * 256 + tid];
@@ -815,7 +837,7 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
     int rc[RS_IPT];
 #pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
-        const bool valid = wstart + r * 64 + lane < n;
+        const bool valid = r * 64 + lane < nvw;
         const int d = (kr[r] >> shift) & 255;
         const uint64_t peers = rs_peers(d, valid);
         const int rank = __popcll(peers & below), num = __popcll(peers);
@@ -838,7 +860,7 @@ __global__ __launch_bounds__(RS_T) void rs_scatter_k(const uint32_t* __restrict_
     // complete in order)
 #pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
-        const bool valid = wstart + r * 64 + lane < n;
+        const bool valid = r * 64 + lane < nvw;
         const int d = (kr[r] >> shift) & 255;
         const int rank = rc[r] & 255;
         const int b = wcnt[w][d];
