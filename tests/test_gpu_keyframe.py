@@ -63,17 +63,23 @@ def _running_max_abs(G, x):
     return out
 
 
+def _pair_code(G, key):
+    """One int64 per edge naming its (voxel, keyframe) pair, and the keyframe
+    count (a 1-D unique over these codes is much faster than one over rows)."""
+    nk = int(key.max()) + 1 if key.size else 1
+    return G.col.astype(np.int64) * nk + key.astype(np.int64), nk
+
+
 def _others(G, key, w, ell, theta):
     """Per edge: |theta| plus the summed |average| of the OTHER keyframes into
     its voxel (from the oracle's last-sweep messages)."""
-    pair = np.stack([G.col.astype(np.int64), key.astype(np.int64)], 1)
-    uniq, inv = np.unique(pair, axis=0, return_inverse=True)
+    code, nk = _pair_code(G, key)
+    uniq, inv = np.unique(code, return_inverse=True)
     inv = inv.reshape(-1)
     sw = np.bincount(inv, weights=w)
     sm = np.bincount(inv, weights=w * ell)
     avg = np.abs(sm / sw)
-    per_voxel = np.abs(theta).copy()
-    np.add.at(per_voxel, uniq[:, 0], avg)
+    per_voxel = np.abs(theta) + np.bincount(uniq // nk, weights=avg, minlength=theta.size)
     return per_voxel[G.col] - avg[inv]
 
 
@@ -113,7 +119,7 @@ def test_keyframe_average_matches_oracle(oracle, RayMRF, name):
     _say(f"[keyframe average] {name}: GPU ({G.n_edges} edges, {K} sweeps)")
     m = RayMRF()
     st = m.build(scs, keyframe_average=True)
-    npairs = np.unique(np.stack([G.col.astype(np.int64), key.astype(np.int64)], 1), axis=0).shape[0]
+    npairs = np.unique(_pair_code(G, key)[0]).size
     assert st.n_keyframe_pairs == npairs
     m.infer_keyframe_avg(torch.from_numpy(th.astype(np.float32)).cuda(),
                          torch.from_numpy(sig.astype(np.float32)).cuda(), K)
