@@ -316,11 +316,25 @@ struct EdgeEmit {
     int32_t vbase;
     double Z, dbin;
     double wn;            // |w| of the ray: chord length = (t_out - t_in) |w|
+    double rbin;          // 1 / dbin, correctly rounded
+    // The bin is floor(d / dbin) with the quotient rounded once, as in the
+    // oracle.  y = d * rbin is within about 2^-51 |d / dbin| of that quotient
+    // (under 4e-10 below 2^20), so wherever y is more than 1e-9 from an integer
+    // the two have the same floor; next to a bin boundary the division decides.
+    // Quotients of 2^20 and more clamp to the last bin either way.
+    __device__ double bin_of(double d) const
+    {
+        const double y = d * rbin;
+        double q = floor(y);
+        const double f = y - q;   // exact
+        if (f < 1e-9 || f > 1.0 - 1e-9) q = floor(d / dbin);
+        return q;
+    }
     __device__ void operator()(int k, int vi, int vj, int vk, double ti, double to) const
     {
         const int64_t e = base + (int64_t)kTile * k;   // step k of this ray's tile lane
         const double d = (ti + to) * 0.5;   // voxel depth: chord midpoint
-        double q = floor(d / dbin);
+        double q = bin_of(d);
         if (q < 0.0) q = 0.0;
         if (q > 63.0) q = 63.0;
         col[e] = vbase + vi + sd->n[0] * (vj + sd->n[1] * vk);
@@ -370,8 +384,9 @@ __global__ __launch_bounds__(256) void trace_emit_k(const SceneDev* __restrict__
             double wn = ray.w[0] * ray.w[0];
             wn = wn + ray.w[1] * ray.w[1];
             wn = wn + ray.w[2] * ray.w[2];
-            EdgeEmit em{col,  key,   delta, bin, tin, tout, wlen, &sd, slot0, (int32_t)sd.voxel_base, ray.Z,
-                        bp.dmax / 64.0, sqrt(wn)};
+            const double dbin = bp.dmax / 64.0;
+            EdgeEmit em{col,   key,   delta, bin, tin, tout, wlen, &sd, slot0, (int32_t)sd.voxel_base, ray.Z,
+                        dbin,  sqrt(wn), 1.0 / dbin};
             walk(sd, ray, scene_bricks(bp, sd), em, bp.skip);
         }
     }
