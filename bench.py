@@ -56,15 +56,15 @@ TRAFFIC = {"workload": "c4",
                        'mrf_internal.hpp'],
            "src_sha256": "db49eb0cdb9d65dec414cea544507680eaa67cd133d7450c7efb25f990c72a25",
            "kernels": {
-                       "ray_adj_lds_k<32,10,1>": [1.276e+10, 4.666e+09],
-                       "ray_adj_lds_k<32,10,2>": [1.2235e+10, 4.666e+09],
-                       "ray_adj_lds_k<32,8,1>": [7.4017e+09, 2.7666e+09],
-                       "ray_adj_lds_k<32,8,2>": [7.1624e+09, 2.7675e+09],
-                       "ray_adj_lds_k<64,4,1>": [7.3949e+09, 2.7666e+09],
-                       "ray_adj_lds_k<64,4,2>": [7.4087e+09, 2.7666e+09],
+                       "ray_adj_lds_k<32,10,1>": [1.2761e+10, 4.666e+09],
+                       "ray_adj_lds_k<32,10,2>": [1.2234e+10, 4.666e+09],
+                       "ray_adj_lds_k<32,8,1>": [7.1532e+09, 2.7667e+09],
+                       "ray_adj_lds_k<32,8,2>": [7.3984e+09, 2.7676e+09],
+                       "ray_adj_lds_k<64,4,1>": [7.3932e+09, 2.7666e+09],
+                       "ray_adj_lds_k<64,4,2>": [7.4075e+09, 2.7666e+09],
                        "ray_adj_lds_k<64,5,1>": [1.2765e+10, 4.666e+09],
-                       "ray_adj_lds_k<64,5,2>": [1.278e+10, 4.6661e+09],
-                       "voxel_k<4,16,1>": [8.8426e+09, 8.0669e+06]}}
+                       "ray_adj_lds_k<64,5,2>": [1.2776e+10, 4.6661e+09],
+                       "voxel_k<4,16,1>": [8.8416e+09, 8.0598e+06]}}
 
 
 def src_sha256(files):
