@@ -326,7 +326,7 @@ struct EdgeEmit {
     {
         const double y = d * rbin;
         double q = floor(y);
-        const double f = y - q;   // exact
+        const double f = y - q;   // exact for y >= 0 (chord midpoints are)
         if (f < 1e-9 || f > 1.0 - 1e-9) q = floor(d / dbin);
         return q;
     }
